@@ -1,0 +1,1 @@
+"""Plain CPU oracle (test infrastructure only; never imported by the product)."""

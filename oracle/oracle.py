@@ -1,0 +1,144 @@
+"""ctypes wrapper around the plain C oracle (``ta_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product package.  It shares no code
+with the HIP path; the only thing both sides see is the seeded input generator.
+The functions mirror the C oracle one to one and return numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ta_oracle.c")
+_LIB = os.path.join(_HERE, "libta_oracle.so")
+
+OK, INVALID_ARG, BAD_TREE, CTX_RANGE, UNSORTED, ITER_OVERFLOW, SIZE_OVERFLOW = range(7)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no FP contraction, OpenMP over ranks)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
+                               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.c_void_p
+        i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
+        _lib.tao_check_tree.argtypes = [i32, P]
+        _lib.tao_attribute.argtypes = [i64, P, P, P, i32, P, P, P]
+        _lib.tao_segment.argtypes = [i64, P, P, P, i32, P, i32, i32, P, i32, P, P, P, P]
+        _lib.tao_imbalance.argtypes = [P, i64, i32, i32, P, i32, f64, P] + [P] * 14
+        _lib.tao_outliers.argtypes = [P, i64, i32, i32, P, i32, i32, f64, P, P, P, P]
+        _lib.tao_topology.argtypes = [P, P, i64, P, P, P, i32, i32, i32] + [P] * 6
+        for f in ("tao_check_tree", "tao_attribute", "tao_segment", "tao_imbalance",
+                  "tao_outliers", "tao_topology"):
+            getattr(_lib, f).restype = C.c_int
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _arr(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+def check_tree(parent) -> int:
+    parent = _arr(parent, np.int32)
+    return lib().tao_check_tree(len(parent), _p(parent))
+
+
+def attribute(offsets, ts, ctx, parent, want_excl=True, want_incl=True):
+    """-> (status, excl[R,N], incl[R,N])"""
+    offsets, ts, ctx, parent = (_arr(offsets, np.int64), _arr(ts, np.int64),
+                                _arr(ctx, np.int32), _arr(parent, np.int32))
+    R, N = len(offsets) - 1, len(parent)
+    excl = np.zeros((R, N), np.int64) if want_excl else None
+    incl = np.zeros((R, N), np.int64) if want_incl else None
+    st = lib().tao_attribute(R, _p(offsets), _p(ts), _p(ctx), N, _p(parent), _p(excl), _p(incl))
+    return st, excl, incl
+
+
+def segment(offsets, ts, ctx, parent, marker, regions, n_iters):
+    """-> (status, tensor[R,I,G], iters_found[R], outside[R], span[R])"""
+    offsets, ts, ctx, parent = (_arr(offsets, np.int64), _arr(ts, np.int64),
+                                _arr(ctx, np.int32), _arr(parent, np.int32))
+    regions = _arr(regions, np.int32)
+    R, N, G, I = len(offsets) - 1, len(parent), len(regions), int(n_iters)
+    T = np.zeros((R, I, G), np.int64)
+    it = np.zeros(R, np.int32)
+    out = np.zeros(R, np.int64)
+    span = np.zeros(R, np.int64)
+    st = lib().tao_segment(R, _p(offsets), _p(ts), _p(ctx), N, _p(parent), int(marker), G,
+                           _p(regions), I, _p(T), _p(it), _p(out), _p(span))
+    return st, T, it, out, span
+
+
+IMBALANCE_CELL = ("mean", "std", "max_minus_mean", "min", "max")
+IMBALANCE_REGION = ("avg_mean", "avg_max", "savings_per_iter", "total_savings",
+                    "balance_ratio", "cv_across", "cv_within", "share")
+
+
+def imbalance(T, iters_found=None, ddof=1, t_app=0.0, span=None):
+    """-> (status, dict of the per-cell [I,G], per-region [G] and scalar stats)"""
+    T = _arr(T, np.int64)
+    R, I, G = T.shape
+    it = _arr(iters_found, np.int32)
+    span = _arr(span, np.int64)
+    o = {k: np.zeros((I, G), np.float64) for k in ("mean", "std", "max_minus_mean")}
+    o["min"] = np.zeros((I, G), np.int64)
+    o["max"] = np.zeros((I, G), np.int64)
+    for k in IMBALANCE_REGION:
+        o[k] = np.zeros(G, np.float64)
+    o["potential_speedup"] = np.zeros(1, np.float64)
+    st = lib().tao_imbalance(_p(T), R, I, G, _p(it), int(ddof), float(t_app), _p(span),
+                             *[_p(o[k]) for k in IMBALANCE_CELL + IMBALANCE_REGION],
+                             _p(o["potential_speedup"]))
+    return st, o
+
+
+def outliers(T, iters_found=None, mode=0, kind=0, tau=3.5, want_region=True):
+    """mode 0 = FULL, 1 = TOTALS; kind 0 = robust (MAD), 1 = plain z.
+    -> (status, rank_score[R], rank_flag[R] (uint8), n_flagged, region_score[R,G])"""
+    T = _arr(T, np.int64)
+    R, I, G = T.shape
+    it = _arr(iters_found, np.int32)
+    score = np.zeros(R, np.float64)
+    flag = np.zeros(R, np.uint8)
+    nf = np.zeros(1, np.int64)
+    reg = np.zeros((R, G), np.float64) if want_region else None
+    st = lib().tao_outliers(_p(T), R, I, G, _p(it), int(mode), int(kind), float(tau),
+                            _p(score), _p(flag), _p(nf), _p(reg))
+    return st, score, flag, int(nf[0]), reg
+
+
+def topology(rank_score, rank_flag, rank_node, node_rack, node_chassis, n_racks, n_chassis):
+    """-> (status, dict flagged/max/mean per rack and per chassis)"""
+    rank_score = _arr(rank_score, np.float64)
+    rank_flag = _arr(rank_flag, np.uint8)
+    rank_node, node_rack, node_chassis = (_arr(rank_node, np.int32), _arr(node_rack, np.int32),
+                                          _arr(node_chassis, np.int32))
+    o = {"flagged_rack": np.zeros(n_racks, np.int64), "max_rack": np.zeros(n_racks),
+         "mean_rack": np.zeros(n_racks), "flagged_chassis": np.zeros(n_chassis, np.int64),
+         "max_chassis": np.zeros(n_chassis), "mean_chassis": np.zeros(n_chassis)}
+    st = lib().tao_topology(_p(rank_score), _p(rank_flag), len(rank_score), _p(rank_node),
+                            _p(node_rack), _p(node_chassis), len(node_rack), n_racks, n_chassis,
+                            *[_p(o[k]) for k in ("flagged_rack", "max_rack", "mean_rack",
+                                                 "flagged_chassis", "max_chassis", "mean_chassis")])
+    return st, o

@@ -1,0 +1,631 @@
+/*
+ * ta_oracle.c -- plain, slow, obviously-correct CPU oracle for the trace ->
+ * rank x iteration x region tensor method and its statistics.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes or
+ * calls this file; only the test-suite, the smoke check and the benchmark's CPU
+ * baseline leg load it.  It shares no code, header or table with the HIP path.
+ *
+ * Paper: "Enhancing Performance Insight at Scale: A Heterogeneous Framework for
+ * Exascale Diagnostics" (arXiv 2605.03561).
+ *
+ * Everything here is the plain definition written out, event by event:
+ *   - durations and exclusive cost:   Sec. II (traces are series of timed
+ *     calling-context-tree node events; HPCToolkit samples the call stack), and
+ *     Sec. VI-B ("inclusive and exclusive costs" per CCT node);
+ *   - inclusive cost:                 an ancestor walk up the parent tree
+ *     (Sec. VI-B, bottom-up call-path traversal from a leaf id);
+ *   - iteration boundaries and the re-materialised per-iteration profile:
+ *     Sec. V and Fig. 2 (scan traces for iterative boundaries, rebuild one
+ *     profile per interval, index node x trace x iteration);
+ *   - per-iteration cross-rank statistics {mean, min, max, std}: the groupby
+ *     listing of Sec. VI-A (pandas semantics, so std uses ddof = 1);
+ *   - global balance ratio (mean over ranks / max over ranks): Sec. VI-A
+ *     (GPU imbalance quantification) and Sec. VI-B;
+ *   - coefficient of variation across / within ranks: Sec. VI-A, Table IV;
+ *   - potential savings = average max - average mean per iteration, times the
+ *     iteration count, divided by application time: Sec. VI-A, Table V;
+ *   - execution share: Table IV, column 2.
+ * The outlier statistic (robust z from median / MAD) is not in the paper; it is
+ * the textbook modified z-score (Iglewicz-Hoaglin), written out per column.
+ *
+ * Readings where the paper is silent are listed in the design notes; the ones
+ * that change arithmetic are restated at the function that uses them.
+ *
+ * Precision: int64 for all times (ns), __int128 for sums of squares, FP64 for
+ * every statistic, long double for FP accumulations of many FP64 terms.
+ * Build: gcc -O2 -ffp-contract=off (no FMA contraction), optional -fopenmp
+ * (only the independent per-rank loop is parallel; results do not depend on it).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Status codes: the numeric values are the library's documented ABI values. */
+enum {
+  TAO_OK = 0,
+  TAO_ERR_INVALID_ARG = 1,
+  TAO_ERR_BAD_TREE = 2,
+  TAO_ERR_CTX_RANGE = 3,
+  TAO_ERR_UNSORTED = 4,
+  TAO_ERR_ITER_OVERFLOW = 5,
+  TAO_ERR_SIZE_OVERFLOW = 6
+};
+
+typedef __int128 i128;
+
+/* ------------------------------------------------------------------------ */
+/* Tree helpers                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* A parent array is a valid forest iff every node reaches a root (-1) in at
+ * most N steps and every parent id is in range. */
+int tao_check_tree(int32_t N, const int32_t *parent) {
+  if (N <= 0 || parent == NULL) return TAO_ERR_INVALID_ARG;
+  for (int32_t v = 0; v < N; v++) {
+    int32_t u = v;
+    int32_t steps = 0;
+    while (u != -1) {
+      if (u < -1 || u >= N) return TAO_ERR_BAD_TREE;
+      if (steps > N) return TAO_ERR_BAD_TREE; /* cycle */
+      u = parent[u];
+      steps++;
+    }
+  }
+  return TAO_OK;
+}
+
+/* Is `a` an ancestor-or-self of `c`?  Plain walk to the root. */
+static int is_anc_or_self(const int32_t *parent, int32_t a, int32_t c) {
+  for (int32_t u = c; u != -1; u = parent[u])
+    if (u == a) return 1;
+  return 0;
+}
+
+/* Region of a node: the region whose root is the NEAREST ancestor-or-self of
+ * c among the region roots; -1 if none.  Plain walk, checking every region at
+ * each step (O(depth * G)). */
+static int32_t region_of_node(const int32_t *parent, int32_t c, int32_t G,
+                              const int32_t *region_nodes) {
+  for (int32_t u = c; u != -1; u = parent[u])
+    for (int32_t g = 0; g < G; g++)
+      if (region_nodes[g] == u) return g;
+  return -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Input checks shared by attribute and segment                              */
+/* ------------------------------------------------------------------------ */
+
+static int check_traces(int64_t R, const int64_t *off, const int64_t *ts,
+                        const int32_t *ctx, int32_t N) {
+  if (R < 0 || off == NULL) return TAO_ERR_INVALID_ARG;
+  if (off[0] != 0) return TAO_ERR_INVALID_ARG;
+  for (int64_t r = 0; r < R; r++)
+    if (off[r + 1] < off[r]) return TAO_ERR_INVALID_ARG;
+  int64_t E = off[R];
+  if (E > 0 && (ts == NULL || ctx == NULL)) return TAO_ERR_INVALID_ARG;
+  for (int64_t k = 0; k < E; k++)
+    if (ctx[k] < 0 || ctx[k] >= N) return TAO_ERR_CTX_RANGE;
+  for (int64_t r = 0; r < R; r++)
+    for (int64_t k = off[r]; k + 1 < off[r + 1]; k++)
+      if (ts[k + 1] < ts[k]) return TAO_ERR_UNSORTED;
+  return TAO_OK;
+}
+
+/* Duration of event k of a rank whose events are [b, e): the time until the
+ * next sample of the same rank; the last sample of a rank gets 0 (sampling
+ * semantics, Sec. II; the interval [t_k, t_k+1) belongs to ctx_k). */
+static int64_t duration(const int64_t *ts, int64_t k, int64_t e) {
+  return (k + 1 < e) ? ts[k + 1] - ts[k] : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Attribution: exclusive and inclusive cost per CCT node per rank           */
+/* ------------------------------------------------------------------------ */
+
+/* excl[r][v] = sum of durations of rank r's events whose context is v.
+ * incl[r][v] = sum of excl[r][u] over every u whose ancestor-or-self set holds
+ *              v (computed by walking from each u to the root).
+ * Either output may be NULL. */
+int tao_attribute(int64_t R, const int64_t *off, const int64_t *ts,
+                  const int32_t *ctx, int32_t N, const int32_t *parent,
+                  int64_t *excl, int64_t *incl) {
+  int st = tao_check_tree(N, parent);
+  if (st) return st;
+  st = check_traces(R, off, ts, ctx, N);
+  if (st) return st;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < R; r++) {
+    int64_t *ex = excl ? excl + r * (int64_t)N : NULL;
+    int64_t *local = NULL;
+    if (!ex) {
+      local = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+      ex = local;
+    }
+    for (int32_t v = 0; v < N; v++) ex[v] = 0;
+    for (int64_t k = off[r]; k < off[r + 1]; k++)
+      ex[ctx[k]] += duration(ts, k, off[r + 1]);
+    if (incl) {
+      int64_t *in = incl + r * (int64_t)N;
+      for (int32_t v = 0; v < N; v++) in[v] = 0;
+      for (int32_t u = 0; u < N; u++)
+        for (int32_t a = u; a != -1; a = parent[a]) in[a] += ex[u];
+    }
+    free(local);
+  }
+  return TAO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Segmentation: iteration boundaries and the rank x iteration x region      */
+/* tensor (Sec. V, Fig. 2)                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Reading of the iteration boundary (the paper gives no rule): an event is a
+ * boundary when its context lies in the marker's subtree and the previous event
+ * of the same rank (if any) does not.  The iteration index of an event is the
+ * number of boundaries at or before it, minus one; events before the first
+ * boundary (index -1) and events outside every region go to `outside`.  The
+ * last iteration runs to the end of the trace.
+ *
+ * tensor[(r*I + i)*G + g] = sum of d_k over rank r's events k with iteration i
+ *                           and region g.
+ * iters_found[r] = number of boundaries; more than I -> TAO_ERR_ITER_OVERFLOW.
+ * span[r] = t_last - t_first (0 for an empty rank), outside[r] = span - sum T.
+ * outside and span may be NULL. */
+int tao_segment(int64_t R, const int64_t *off, const int64_t *ts,
+                const int32_t *ctx, int32_t N, const int32_t *parent,
+                int32_t marker, int32_t G, const int32_t *region_nodes,
+                int32_t I, int64_t *tensor, int32_t *iters_found,
+                int64_t *outside, int64_t *span) {
+  int st = tao_check_tree(N, parent);
+  if (st) return st;
+  if (marker < 0 || marker >= N || G < 0 || I < 0 || tensor == NULL ||
+      iters_found == NULL || (G > 0 && region_nodes == NULL))
+    return TAO_ERR_INVALID_ARG;
+  for (int32_t g = 0; g < G; g++) {
+    if (region_nodes[g] < 0 || region_nodes[g] >= N) return TAO_ERR_INVALID_ARG;
+    for (int32_t h = 0; h < g; h++)
+      if (region_nodes[h] == region_nodes[g]) return TAO_ERR_INVALID_ARG;
+  }
+  st = check_traces(R, off, ts, ctx, N);
+  if (st) return st;
+
+  int overflow = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : overflow)
+  for (int64_t r = 0; r < R; r++) {
+    int64_t *row = tensor + r * (int64_t)I * G;
+    for (int64_t j = 0; j < (int64_t)I * G; j++) row[j] = 0;
+    int64_t b = off[r], e = off[r + 1];
+    int64_t out = 0;
+    int32_t it = -1;   /* iteration index of the current event */
+    int prev_in = 0;   /* was the previous event inside the marker subtree? */
+    for (int64_t k = b; k < e; k++) {
+      int32_t c = ctx[k];
+      int in_m = is_anc_or_self(parent, marker, c);
+      if (in_m && (k == b || !prev_in)) it++;
+      prev_in = in_m;
+      int64_t d = duration(ts, k, e);
+      int32_t g = region_of_node(parent, c, G, region_nodes);
+      if (it < 0 || g < 0) {
+        out += d;
+      } else if (it < I) {
+        row[(int64_t)it * G + g] += d;
+      }
+      /* it >= I: overflow, reported below; the value is not stored. */
+    }
+    iters_found[r] = it + 1;
+    if (it + 1 > I) overflow = 1;
+    int64_t sp = (e > b) ? ts[e - 1] - ts[b] : 0;
+    if (span) span[r] = sp;
+    if (outside) outside[r] = out;
+  }
+  return overflow ? TAO_ERR_ITER_OVERFLOW : TAO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Imbalance statistics (Sec. VI-A, Tables IV and V, groupby listing)        */
+/* ------------------------------------------------------------------------ */
+
+/* int128 -> double, correctly rounded (gcc's conversion is). */
+static double d128(i128 x) { return (double)x; }
+
+/* The valid ranks of iteration i are those that found more than i iterations
+ * (ranks with fewer iterations are left out of that iteration's statistics).
+ * With iters_found == NULL every rank is valid for every iteration. */
+static int valid(const int32_t *iters_found, int64_t r, int32_t i) {
+  return iters_found == NULL || i < iters_found[r];
+}
+
+/* Per (i,g), over the valid ranks, with n = count:
+ *   s1 = sum x (int64), s2 = sum x^2 (int128), mn, mx
+ *   mean           = s1 / n
+ *   std            = sqrt((n*s2 - s1^2) / (n*(n - ddof)))     (NaN if n<=ddof)
+ *   max_minus_mean = (n*mx - s1) / n
+ * computed as one FP64 operation on exact integers each.  Empty columns give
+ * mean = std = max_minus_mean = NaN and min = max = 0.
+ *
+ * Per region g, over I' = {i : n_i > 0}:
+ *   avg_mean         = (1/|I'|) sum_i mean_i
+ *   avg_max          = (1/|I'|) sum_i max_i
+ *   savings_per_iter = (1/|I'|) sum_i (max_i - mean_i)       [= avg_max - avg_mean]
+ *   total_savings    = savings_per_iter * |I'|
+ *   balance_ratio    = (sum_r S[r,g] / R) / max_r S[r,g],   S[r,g] = sum_i x
+ *   cv_across        = mean over {i : n_i > ddof, mean_i > 0} of std_i / mean_i
+ *   cv_within        = mean over {r : n_r > ddof, S[r,g] > 0} of the rank's
+ *                      std over its iterations / its mean over its iterations
+ *   share            = sum of region g's cells / sum of all cells
+ * and potential_speedup = sum_g total_savings_g / t_app (fraction of time).
+ * FP sums of many FP64 terms accumulate in long double, in ascending index.
+ * t_app <= 0: use max_r span[r] if span != NULL, else NaN. */
+int tao_imbalance(const int64_t *T, int64_t R, int32_t I, int32_t G,
+                  const int32_t *iters_found, int32_t ddof, double t_app,
+                  const int64_t *span,
+                  /* [I*G] */ double *mean, double *stdv, double *max_minus_mean,
+                  int64_t *minv, int64_t *maxv,
+                  /* [G] */ double *avg_mean, double *avg_max,
+                  double *savings_per_iter, double *total_savings,
+                  double *balance_ratio, double *cv_across, double *cv_within,
+                  double *share,
+                  /* [1] */ double *potential_speedup) {
+  if (R < 0 || I < 0 || G <= 0 || ddof < 0 || T == NULL) return TAO_ERR_INVALID_ARG;
+  const double nan = NAN;
+  int64_t grand = 0;
+  for (int64_t r = 0; r < R; r++)
+    for (int32_t i = 0; i < I; i++)
+      if (valid(iters_found, r, i))
+        for (int32_t g = 0; g < G; g++) grand += T[((int64_t)r * I + i) * G + g];
+
+  long double sum_total = 0.0L;
+  for (int32_t g = 0; g < G; g++) {
+    long double acc_mean = 0.0L, acc_mm = 0.0L, acc_cv = 0.0L;
+    int64_t acc_max = 0, n_iters = 0, n_cv = 0;
+    for (int32_t i = 0; i < I; i++) {
+      int64_t n = 0, s1 = 0, mn = 0, mx = 0;
+      i128 s2 = 0;
+      for (int64_t r = 0; r < R; r++) {
+        if (!valid(iters_found, r, i)) continue;
+        int64_t x = T[((int64_t)r * I + i) * G + g];
+        if (n == 0 || x < mn) mn = x;
+        if (n == 0 || x > mx) mx = x;
+        n++;
+        s1 += x;
+        s2 += (i128)x * x;
+      }
+      double m = nan, sd = nan, mm = nan;
+      if (n > 0) {
+        m = (double)s1 / (double)n;
+        mm = d128((i128)n * mx - s1) / (double)n;
+        if (n > ddof) {
+          double var = d128((i128)n * s2 - (i128)s1 * s1) /
+                       ((double)n * (double)(n - ddof));
+          sd = sqrt(var);
+        }
+        acc_mean += m;
+        acc_mm += mm;
+        acc_max += mx;
+        n_iters++;
+        if (n > ddof && m > 0.0) {
+          acc_cv += sd / m;
+          n_cv++;
+        }
+      }
+      int64_t j = (int64_t)i * G + g;
+      if (mean) mean[j] = m;
+      if (stdv) stdv[j] = sd;
+      if (max_minus_mean) max_minus_mean[j] = mm;
+      if (minv) minv[j] = mn;
+      if (maxv) maxv[j] = mx;
+    }
+    double spi = n_iters ? (double)(acc_mm / (long double)n_iters) : nan;
+    double tot = n_iters ? spi * (double)n_iters : nan;
+    if (avg_mean) avg_mean[g] = n_iters ? (double)(acc_mean / (long double)n_iters) : nan;
+    if (avg_max) avg_max[g] = n_iters ? (double)acc_max / (double)n_iters : nan;
+    if (savings_per_iter) savings_per_iter[g] = spi;
+    if (total_savings) total_savings[g] = tot;
+    if (n_iters) sum_total += tot;
+    if (cv_across) cv_across[g] = n_cv ? (double)(acc_cv / (long double)n_cv) : nan;
+
+    /* Per-rank totals over the rank's valid iterations. */
+    int64_t ssum = 0, smax = 0, gsum = 0;
+    long double acc_w = 0.0L;
+    int64_t n_w = 0;
+    for (int64_t r = 0; r < R; r++) {
+      int64_t s = 0, nr = 0;
+      i128 q = 0;
+      for (int32_t i = 0; i < I; i++) {
+        if (!valid(iters_found, r, i)) continue;
+        int64_t x = T[((int64_t)r * I + i) * G + g];
+        s += x;
+        q += (i128)x * x;
+        nr++;
+      }
+      ssum += s;
+      if (r == 0 || s > smax) smax = s;
+      gsum += s;
+      if (nr > ddof && s > 0) {
+        double mr = (double)s / (double)nr;
+        double vr = d128((i128)nr * q - (i128)s * s) / ((double)nr * (double)(nr - ddof));
+        acc_w += sqrt(vr) / mr;
+        n_w++;
+      }
+    }
+    if (balance_ratio)
+      balance_ratio[g] = (R > 0 && smax != 0)
+                             ? ((double)ssum / (double)R) / (double)smax
+                             : nan;
+    if (cv_within) cv_within[g] = n_w ? (double)(acc_w / (long double)n_w) : nan;
+    if (share) share[g] = grand ? (double)gsum / (double)grand : nan;
+  }
+  if (potential_speedup) {
+    double tapp = t_app;
+    if (!(tapp > 0.0)) {
+      tapp = nan;
+      if (span && R > 0) {
+        int64_t mx = span[0];
+        for (int64_t r = 1; r < R; r++)
+          if (span[r] > mx) mx = span[r];
+        tapp = (double)mx;
+      }
+    }
+    potential_speedup[0] = (double)sum_total / tapp;
+  }
+  return TAO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Outliers: robust z (median / MAD) and plain z scores                      */
+/* ------------------------------------------------------------------------ */
+
+static int cmp_i64(const void *a, const void *b) {
+  int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+  return (x > y) - (x < y);
+}
+static int cmp_f64(const void *a, const void *b) {
+  double x = *(const double *)a, y = *(const double *)b;
+  return (x > y) - (x < y);
+}
+
+/* Twice the median of n sorted integers: 2*x[n/2] for odd n, the sum of the
+ * two middle values for even n (exact in int64). */
+static int64_t twice_median_sorted(const int64_t *s, int64_t n) {
+  return (n & 1) ? 2 * s[n / 2] : s[n / 2 - 1] + s[n / 2];
+}
+
+/* Robust z of one integer column (n values, already gathered):
+ *   med2 = 2*median,  dev_r = |2x_r - med2| (= 2|x - med|),
+ *   mad4 = 2*median(dev) (= 4*MAD),
+ *   z_r  = (4x_r - 2*med2) / (1.4826 * mad4)            when mad4 > 0,
+ *   z_r  = (2x_r - med2)*n / (1.253314 * sum_r dev_r)   when mad4 == 0 and
+ *                                                       the mean abs dev > 0,
+ *   z_r  = 0                                            otherwise (all equal).
+ * 1.4826 = 1/Phi^-1(3/4) makes MAD consistent with the normal sigma;
+ * 1.253314 = sqrt(pi/2) does the same for the mean absolute deviation. */
+static void robust_z_int(const int64_t *x, int64_t n, double *z, int64_t *work) {
+  memcpy(work, x, sizeof(int64_t) * (size_t)n);
+  qsort(work, (size_t)n, sizeof(int64_t), cmp_i64);
+  int64_t med2 = twice_median_sorted(work, n);
+  int64_t sumdev = 0;
+  for (int64_t r = 0; r < n; r++) {
+    int64_t dv = 2 * x[r] - med2;
+    work[r] = dv < 0 ? -dv : dv;
+    sumdev += work[r];
+  }
+  qsort(work, (size_t)n, sizeof(int64_t), cmp_i64);
+  int64_t mad4 = twice_median_sorted(work, n);
+  for (int64_t r = 0; r < n; r++) {
+    if (mad4 > 0) {
+      z[r] = (double)(4 * x[r] - 2 * med2) / (1.4826 * (double)mad4);
+    } else if (sumdev > 0) {
+      z[r] = ((double)(2 * x[r] - med2) * (double)n) / (1.253314 * (double)sumdev);
+    } else {
+      z[r] = 0.0;
+    }
+  }
+}
+
+/* The same robust z for FP64 values: med = middle value (odd n) or
+ * 0.5*(a + b) (even n); MAD = median of |v - med| by the same rule;
+ * z = (v - med) / (1.4826*MAD); MAD == 0 -> 1.253314 * mean|v - med|
+ * (long double sum); both zero -> 0. */
+static void robust_z_f64(const double *v, int64_t n, double *z, double *work) {
+  memcpy(work, v, sizeof(double) * (size_t)n);
+  qsort(work, (size_t)n, sizeof(double), cmp_f64);
+  double med = (n & 1) ? work[n / 2] : 0.5 * (work[n / 2 - 1] + work[n / 2]);
+  long double sad = 0.0L;
+  for (int64_t r = 0; r < n; r++) {
+    work[r] = fabs(v[r] - med);
+    sad += work[r];
+  }
+  qsort(work, (size_t)n, sizeof(double), cmp_f64);
+  double mad = (n & 1) ? work[n / 2] : 0.5 * (work[n / 2 - 1] + work[n / 2]);
+  double mean_ad = (double)(sad / (long double)n);
+  for (int64_t r = 0; r < n; r++) {
+    if (mad > 0.0)
+      z[r] = (v[r] - med) / (1.4826 * mad);
+    else if (mean_ad > 0.0)
+      z[r] = (v[r] - med) / (1.253314 * mean_ad);
+    else
+      z[r] = 0.0;
+  }
+}
+
+/* Plain z with ddof: (x - mean)/std over the n values; std from exact sums for
+ * integers; std == 0 or n <= ddof -> 0. */
+static void plain_z_int(const int64_t *x, int64_t n, int32_t ddof, double *z) {
+  int64_t s1 = 0;
+  i128 s2 = 0;
+  for (int64_t r = 0; r < n; r++) {
+    s1 += x[r];
+    s2 += (i128)x[r] * x[r];
+  }
+  double sd = 0.0;
+  if (n > ddof)
+    sd = sqrt(d128((i128)n * s2 - (i128)s1 * s1) / ((double)n * (double)(n - ddof)));
+  for (int64_t r = 0; r < n; r++)
+    z[r] = (sd > 0.0) ? d128((i128)n * x[r] - s1) / ((double)n * sd) : 0.0;
+}
+static void plain_z_f64(const double *v, int64_t n, int32_t ddof, double *z) {
+  long double s = 0.0L;
+  for (int64_t r = 0; r < n; r++) s += v[r];
+  double m = (double)(s / (long double)n);
+  long double q = 0.0L;
+  for (int64_t r = 0; r < n; r++) q += (long double)(v[r] - m) * (long double)(v[r] - m);
+  double sd = (n > ddof) ? sqrt((double)(q / (long double)(n - ddof))) : 0.0;
+  for (int64_t r = 0; r < n; r++) z[r] = (sd > 0.0) ? (v[r] - m) / sd : 0.0;
+}
+
+/* Outlier scan over the tensor.  Ranks with iters_found == 0 take no part and
+ * get score 0 / flag 0.  (Not in the paper, which clusters ranks instead; this
+ * is the exact scan that judges the learned pre-screen.)
+ *
+ * mode 0 (FULL):   per column (i,g), a score z(r,i,g) over the ranks valid in
+ *                  iteration i; m(r,g) = mean over the rank's valid iterations
+ *                  of z (FP64 sum in ascending i); then per region a second
+ *                  robust z over ranks of m(r,g).
+ * mode 1 (TOTALS): per region, one score over ranks of S[r,g] (the sum of the
+ *                  rank's valid cells).
+ * kind 0: robust (median/MAD) z;  kind 1: plain z with ddof 1.
+ * rank_score[r] = max_g |z2(r,g)|,  rank_flag[r] = rank_score > tau,
+ * region_score[r*G+g] = z2(r,g) (signed; may be NULL). */
+int tao_outliers(const int64_t *T, int64_t R, int32_t I, int32_t G,
+                 const int32_t *iters_found, int32_t mode, int32_t kind,
+                 double tau, double *rank_score, uint8_t *rank_flag,
+                 int64_t *n_flagged, double *region_score) {
+  if (R < 0 || I < 0 || G <= 0 || T == NULL || rank_score == NULL ||
+      rank_flag == NULL || (mode != 0 && mode != 1) || (kind != 0 && kind != 1))
+    return TAO_ERR_INVALID_ARG;
+  int64_t *col = (int64_t *)malloc(sizeof(int64_t) * (size_t)(R + 1));
+  int64_t *iwork = (int64_t *)malloc(sizeof(int64_t) * (size_t)(R + 1));
+  int64_t *who = (int64_t *)malloc(sizeof(int64_t) * (size_t)(R + 1));
+  double *z = (double *)malloc(sizeof(double) * (size_t)(R + 1));
+  double *fwork = (double *)malloc(sizeof(double) * (size_t)(R + 1));
+  double *fcol = (double *)malloc(sizeof(double) * (size_t)(R + 1));
+  double *m = (double *)calloc((size_t)R * (size_t)G + 1, sizeof(double));
+  double *zr = (double *)malloc(sizeof(double) * ((size_t)R * (size_t)G + 1));
+  if (!col || !iwork || !who || !z || !fwork || !fcol || !m || !zr) return TAO_ERR_SIZE_OVERFLOW;
+
+  /* Active ranks: at least one iteration. */
+  int64_t na = 0;
+  for (int64_t r = 0; r < R; r++)
+    if (iters_found == NULL ? I > 0 : iters_found[r] > 0) who[na++] = r;
+
+  if (mode == 0) {
+    /* Stage 1: per-cell score, summed over i in ascending order per (r,g). */
+    for (int32_t i = 0; i < I; i++) {
+      for (int32_t g = 0; g < G; g++) {
+        int64_t n = 0;
+        for (int64_t a = 0; a < na; a++) {
+          int64_t r = who[a];
+          if (valid(iters_found, r, i)) col[n++] = T[((int64_t)r * I + i) * G + g];
+        }
+        if (n == 0) continue;
+        if (kind == 0) robust_z_int(col, n, z, iwork);
+        else plain_z_int(col, n, 1, z);
+        n = 0;
+        for (int64_t a = 0; a < na; a++) {
+          int64_t r = who[a];
+          if (valid(iters_found, r, i)) m[r * G + g] += z[n++];
+        }
+      }
+    }
+    for (int64_t a = 0; a < na; a++) {
+      int64_t r = who[a];
+      double cnt = (double)(iters_found ? iters_found[r] : I);
+      if (iters_found && iters_found[r] > I) cnt = (double)I;
+      for (int32_t g = 0; g < G; g++) m[r * G + g] = m[r * G + g] / cnt;
+    }
+    /* Stage 2: per region, score of m(r,g) over active ranks. */
+    for (int32_t g = 0; g < G; g++) {
+      for (int64_t a = 0; a < na; a++) fcol[a] = m[who[a] * G + g];
+      if (na > 0) {
+        if (kind == 0) robust_z_f64(fcol, na, z, fwork);
+        else plain_z_f64(fcol, na, 1, z);
+      }
+      for (int64_t a = 0; a < na; a++) zr[who[a] * G + g] = z[a];
+    }
+  } else {
+    for (int32_t g = 0; g < G; g++) {
+      for (int64_t a = 0; a < na; a++) {
+        int64_t r = who[a], s = 0;
+        for (int32_t i = 0; i < I; i++)
+          if (valid(iters_found, r, i)) s += T[((int64_t)r * I + i) * G + g];
+        col[a] = s;
+      }
+      if (na > 0) {
+        if (kind == 0) robust_z_int(col, na, z, iwork);
+        else plain_z_int(col, na, 1, z);
+      }
+      for (int64_t a = 0; a < na; a++) zr[who[a] * G + g] = z[a];
+    }
+  }
+
+  int64_t nf = 0;
+  for (int64_t r = 0; r < R; r++) {
+    rank_score[r] = 0.0;
+    rank_flag[r] = 0;
+    if (region_score)
+      for (int32_t g = 0; g < G; g++) region_score[r * G + g] = 0.0;
+  }
+  for (int64_t a = 0; a < na; a++) {
+    int64_t r = who[a];
+    double best = 0.0;
+    for (int32_t g = 0; g < G; g++) {
+      double v = fabs(zr[r * G + g]);
+      if (v > best) best = v;
+      if (region_score) region_score[r * G + g] = zr[r * G + g];
+    }
+    rank_score[r] = best;
+    rank_flag[r] = best > tau;
+    nf += rank_flag[r];
+  }
+  if (n_flagged) n_flagged[0] = nf;
+  free(col); free(iwork); free(who); free(z); free(fwork); free(fcol); free(m); free(zr);
+  return TAO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Topology aggregation (Sec. VI-B: ranks -> compute nodes -> racks/chassis) */
+/* ------------------------------------------------------------------------ */
+
+/* Per rack and per chassis: number of flagged ranks, max score and mean score
+ * over the ranks placed there (NaN where none). */
+int tao_topology(const double *rank_score, const uint8_t *rank_flag, int64_t R,
+                 const int32_t *rank_node, const int32_t *node_rack,
+                 const int32_t *node_chassis, int32_t n_nodes, int32_t n_racks,
+                 int32_t n_chassis, int64_t *flagged_rack, double *max_rack,
+                 double *mean_rack, int64_t *flagged_chassis,
+                 double *max_chassis, double *mean_chassis) {
+  if (R < 0 || n_racks <= 0 || n_chassis <= 0 || n_nodes <= 0) return TAO_ERR_INVALID_ARG;
+  for (int64_t r = 0; r < R; r++) {
+    int32_t nd = rank_node[r];
+    if (nd < 0 || nd >= n_nodes) return TAO_ERR_INVALID_ARG;
+    if (node_rack[nd] < 0 || node_rack[nd] >= n_racks) return TAO_ERR_INVALID_ARG;
+    if (node_chassis[nd] < 0 || node_chassis[nd] >= n_chassis) return TAO_ERR_INVALID_ARG;
+  }
+  for (int pass = 0; pass < 2; pass++) {
+    int32_t K = pass ? n_chassis : n_racks;
+    const int32_t *key = pass ? node_chassis : node_rack;
+    int64_t *fl = pass ? flagged_chassis : flagged_rack;
+    double *mx = pass ? max_chassis : max_rack;
+    double *mn = pass ? mean_chassis : mean_rack;
+    for (int32_t k = 0; k < K; k++) {
+      int64_t cnt = 0, nfl = 0;
+      long double s = 0.0L;
+      double best = -INFINITY;
+      for (int64_t r = 0; r < R; r++) {
+        if (key[rank_node[r]] != k) continue;
+        cnt++;
+        nfl += rank_flag[r] ? 1 : 0;
+        s += rank_score[r];
+        if (rank_score[r] > best) best = rank_score[r];
+      }
+      if (fl) fl[k] = nfl;
+      if (mx) mx[k] = cnt ? best : NAN;
+      if (mn) mn[k] = cnt ? (double)(s / (long double)cnt) : NAN;
+    }
+  }
+  return TAO_OK;
+}
