@@ -1,0 +1,232 @@
+/*
+ * ta.h -- C ABI of the MI355X (gfx950) trace-analysis library.
+ *
+ * The library reduces a batch of per-rank execution traces (timestamped
+ * calling-context-tree node events) to a rank x iteration x region time tensor
+ * and computes cross-rank imbalance and outlier statistics on it.
+ *
+ * Paper: "Enhancing Performance Insight at Scale: A Heterogeneous Framework for
+ * Exascale Diagnostics" (arXiv 2605.03561).  Sec. II defines an execution
+ * trace as a series of timed CCT-node events per rank; Sec. V re-materialises
+ * per-iteration profiles from traces (iteration boundaries found by a scan)
+ * into a node x trace x iteration model; Sec. VI-A derives per-iteration
+ * groupby statistics, the global balance ratio, coefficients of variation and
+ * the potential savings (Tables IV and V); Sec. VI-B maps ranks to compute
+ * nodes and to physical rack / chassis coordinates.
+ *
+ * Conventions (all calls):
+ *   - Bulk arrays are DEVICE pointers owned by the caller; the library never
+ *     frees or keeps them past the call.  Small descriptors (the parent array,
+ *     the region list, host offsets for planning) are HOST pointers, copied
+ *     during the call.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream).  Outputs are valid once the stream has reached the call.
+ *   - Argument errors are detected on the host before anything is launched
+ *     and returned as a status; nothing is written then.
+ *   - Data errors (context id out of range, decreasing timestamps, more
+ *     iterations than the tensor holds, inconsistent offsets) are detected on
+ *     the device and recorded in a sticky per-handle word; the outputs of the
+ *     call that met them are unspecified.  ta_sync_status() waits for the
+ *     stream, returns the error (or TA_OK) and clears it.
+ *   - Row-major layouts: tensor[(r*I + i)*G + g], excl[r*N + v].
+ *   - Alignment: every device array must be 16-byte aligned (torch's default
+ *     allocations are); otherwise TA_ERR_INVALID_ARG.
+ *   - A handle may be used from one host thread at a time.  Calls on one
+ *     handle share its workspace: calls issued on different streams of the
+ *     same handle must not overlap in time.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef TA_H_
+#define TA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ta_status;
+enum {
+  TA_OK = 0,
+  TA_ERR_INVALID_ARG = 1,    /* bad argument, or (device) inconsistent offsets */
+  TA_ERR_BAD_TREE = 2,       /* parent array has a cycle or an out-of-range id */
+  TA_ERR_CTX_RANGE = 3,      /* (device) a context id outside [0, N)           */
+  TA_ERR_UNSORTED = 4,       /* (device) timestamps decrease within a rank     */
+  TA_ERR_ITER_OVERFLOW = 5,  /* (device) a rank has more than n_iters iterations */
+  TA_ERR_SIZE_OVERFLOW = 6,  /* a size exceeds what a kernel supports          */
+  TA_ERR_OOM = 7,            /* workspace allocation failed                    */
+  TA_ERR_HIP = 8,            /* a HIP runtime call failed                      */
+  TA_ERR_STATE = 9           /* a required earlier call is missing             */
+};
+
+typedef struct ta_handle_s *ta_handle;
+
+/* Handle life cycle.  `device` is the HIP device ordinal the handle's
+ * workspace and kernels use.  The handle owns its workspace, the call-path
+ * tables, batch plans and captured graphs. */
+ta_status ta_create(ta_handle *out, int device);
+ta_status ta_destroy(ta_handle h);
+const char *ta_status_string(ta_status s);
+/* Human-readable detail of the last failure on this handle (never NULL). */
+const char *ta_last_error(ta_handle h);
+/* Blocks until `stream` is idle; returns and clears the sticky device error.
+ * When several kinds were met, the first of CTX_RANGE, UNSORTED,
+ * ITER_OVERFLOW, INVALID_ARG is returned. */
+ta_status ta_sync_status(ta_handle h, void *stream);
+
+/* Calling-context tree (Sec. II; Sec. VI-B walks it bottom-up from a leaf).
+ * parent_host[v] is the parent of node v, -1 for a root; a forest is allowed.
+ * Any numbering is accepted: the library renumbers nodes in depth-first
+ * preorder internally.  A cycle or an id outside [-1, N) -> TA_ERR_BAD_TREE.
+ * N must be at most 8192 for attribution (exclusive/inclusive cost) and at
+ * most 4194304 otherwise.  Resets the regions. */
+ta_status ta_set_tree(ta_handle h, int32_t n_nodes, const int32_t *parent_host);
+
+/* Iteration marker and regions (Sec. V: iterations are found by scanning the
+ * traces; Sec. VI-A: the regions are the kernels under study).  An event opens
+ * a new iteration when its context lies in the marker's subtree and the
+ * previous event of the same rank does not.  An event belongs to region g when
+ * region_nodes_host[g] is the nearest ancestor-or-self of its context among
+ * the region nodes.  1 <= n_regions <= 256, distinct nodes. */
+ta_status ta_set_regions(ta_handle h, int32_t marker_node, int32_t n_regions,
+                         const int32_t *region_nodes_host);
+
+/* A batch of traces in CSR form (device pointers):
+ *   offsets[n_ranks + 1] (int64, offsets[0] = 0, non-decreasing,
+ *   offsets[n_ranks] = n_events), ts[n_events] (int64 ns, non-decreasing within
+ *   a rank), ctx[n_events] (int32 node ids).  The duration of an event is the
+ *   next timestamp of the same rank minus its own; a rank's last event lasts 0. */
+typedef struct {
+  int64_t n_ranks;
+  int64_t n_events;
+  const int64_t *offsets;
+  const int64_t *ts;
+  const int32_t *ctx;
+} ta_traces;
+
+/* Outputs of the segmentation / attribution pass (device pointers; any may be
+ * NULL unless stated):
+ *   tensor[R*I*G]   int64 time per (rank, iteration, region) -- required for
+ *                   segmentation; rows i >= iters_found[r] are zero
+ *   iters_found[R]  int32 number of iterations (boundaries) found -- required
+ *                   for segmentation
+ *   outside[R]      int64 time in no region or before the first boundary
+ *   span[R]         int64 last minus first timestamp
+ *   rank_sum[R*G]   int64 sum over the rank's iterations of its cells
+ *   rank_sumsq[R*G*2] unsigned 128-bit sum of squares of the same cells, as
+ *                   (low, high) uint64 pairs
+ *   excl[R*N], incl[R*N]  int64 exclusive / inclusive time per CCT node, in
+ *                   the caller's node numbering */
+typedef struct {
+  int64_t *tensor;
+  int32_t *iters_found;
+  int64_t *outside;
+  int64_t *span;
+  int64_t *rank_sum;
+  uint64_t *rank_sumsq;
+  int64_t *excl;
+  int64_t *incl;
+} ta_seg_out;
+
+/* Exclusive and inclusive cost per CCT node and rank (Sec. VI-B: profiles
+ * carry inclusive and exclusive costs per calling context; Sec. II: trace
+ * samples are timed CCT-node events).  excl[r][v] = total duration of rank
+ * r's events whose context is v; incl[r][v] = sum of excl[r][u] over the
+ * subtree of v.  Needs ta_set_tree(). */
+ta_status ta_attribute(ta_handle h, const ta_traces *t, int64_t *excl, int64_t *incl,
+                       void *stream);
+
+/* Iteration segmentation into the rank x iteration x region tensor (Sec. V,
+ * Fig. 2: one re-materialised profile per iteration interval, indexed by
+ * trace and iteration).  Events before the first boundary and events in no
+ * region go to `outside`.  Needs ta_set_tree() and ta_set_regions(). */
+ta_status ta_segment(ta_handle h, const ta_traces *t, int32_t n_iters, int64_t *tensor,
+                     int32_t *iters_found, int64_t *outside, void *stream);
+
+/* Fused single pass over the traces producing everything in `out` that is
+ * non-NULL (attribution needs excl and/or incl; segmentation needs tensor and
+ * iters_found).  This is the measured hot path. */
+ta_status ta_attribute_segment(ta_handle h, const ta_traces *t, int32_t n_iters,
+                               const ta_seg_out *out, void *stream);
+
+/* Imbalance statistics (Sec. VI-A: the groupby listing's mean / min / max /
+ * std per iteration across ranks with pandas' ddof; global balance ratio =
+ * mean over ranks / max over ranks of the run totals; coefficients of
+ * variation across and within ranks, Table IV; potential savings = average
+ * max - average mean per iteration, total = savings x iterations, speedup =
+ * total / application time, Table V).
+ * Per cell (i,g) over the ranks valid in iteration i (i < iters_found[r];
+ * all ranks when iters_found is NULL):
+ *   mean = s1/n, std = sqrt((n*s2 - s1^2)/(n*(n-ddof))), max_minus_mean =
+ *   (n*max - s1)/n, min, max   -- from exact int64 / int128 sums.
+ * Per region g over the iterations with at least one valid rank (I'):
+ *   avg_mean, avg_max, savings_per_iter = mean over I' of max_minus_mean,
+ *   total_savings = savings_per_iter * |I'|, balance_ratio = (sum_r S/R) /
+ *   max_r S with S the rank's total, cv_across = mean over I' (mean > 0,
+ *   n > ddof) of std/mean, cv_within = mean over ranks (n_r > ddof, S > 0) of
+ *   the rank's std over its iterations / its mean, share = region total /
+ *   all regions' total.  potential_speedup = sum_g total_savings / t_app_ns;
+ *   t_app_ns <= 0 uses max_r span[r] (NaN if span is NULL).
+ * rank_sum / rank_sumsq (as produced by ta_attribute_segment) may be NULL;
+ * the library then computes them with an extra pass over the tensor.
+ * Every output pointer in `o` is a device pointer and may be NULL. */
+typedef struct {
+  double *mean, *std, *max_minus_mean; /* [I*G] */
+  int64_t *min, *max;                  /* [I*G] */
+  double *avg_mean, *avg_max, *savings_per_iter, *total_savings, *balance_ratio,
+      *cv_across, *cv_within, *share;  /* [G] */
+  double *potential_speedup;           /* [1] */
+} ta_imbalance_out;
+
+ta_status ta_imbalance(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                       int32_t n_regions, const int32_t *iters_found, const int64_t *rank_sum,
+                       const uint64_t *rank_sumsq, const int64_t *span, int32_t ddof,
+                       double t_app_ns, const ta_imbalance_out *o, void *stream);
+
+/* Exact outlier scan (not in the paper, which clusters ranks, Sec. VI-B; this
+ * is the textbook modified z-score).  Ranks with no iteration take no part and
+ * score 0.
+ *   TA_SCAN_FULL: per cell (i,g) a score over the ranks valid in i; m(r,g) =
+ *     mean over the rank's iterations of its cell scores (summed in ascending
+ *     i); then per region a second score over ranks of m(r,g).
+ *   TA_SCAN_TOTALS: per region one score over ranks of the rank totals.
+ *   TA_SCORE_MAD: robust z = (x - median) / (1.4826 * MAD); when MAD is 0,
+ *     1.253314 * mean absolute deviation replaces 1.4826 * MAD; when that is
+ *     0 too, z = 0.  Medians of an even count average the two middle values.
+ *   TA_SCORE_Z: (x - mean) / std with ddof = 1 (0 when std is 0).
+ * rank_score[r] = max_g |z2(r,g)|; rank_flag[r] = rank_score > tau;
+ * n_flagged[0] = number of flags; region_score[r*G+g] = z2(r,g) (signed, may
+ * be NULL).  All outputs are device pointers. */
+enum { TA_SCAN_FULL = 0, TA_SCAN_TOTALS = 1 };
+enum { TA_SCORE_MAD = 0, TA_SCORE_Z = 1 };
+ta_status ta_outliers(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                      int32_t n_regions, const int32_t *iters_found, int32_t mode, int32_t kind,
+                      double tau, double *rank_score, uint8_t *rank_flag, int64_t *n_flagged,
+                      double *region_score, void *stream);
+
+/* Node-level and physical localisation (Sec. VI-B: ranks are joined with their
+ * compute node, nodes are mapped to rack and chassis coordinates).  For each
+ * rack and each chassis: the number of flagged ranks placed there, their max
+ * score and mean score (NaN where no rank is placed).  rank_node[R] indexes
+ * node_rack[n_nodes] and node_chassis[n_nodes] (chassis numbered globally).
+ * Device pointers; any of the six outputs may be NULL. */
+ta_status ta_topology_aggregate(ta_handle h, const double *rank_score, const uint8_t *rank_flag,
+                                int64_t n_ranks, const int32_t *rank_node,
+                                const int32_t *node_rack, const int32_t *node_chassis,
+                                int32_t n_nodes, int32_t n_racks, int32_t n_chassis,
+                                int64_t *flagged_per_rack, double *max_per_rack,
+                                double *mean_per_rack, int64_t *flagged_per_chassis,
+                                double *max_per_chassis, double *mean_per_chassis,
+                                void *stream);
+
+/* Return a call-path: walks from `leaf` to its root over the tree given to
+ * ta_set_tree (Sec. VI-B reconstructs the call chain of a leaf id bottom-up).
+ * Writes up to `cap` node ids (leaf first) into path_host and the full length
+ * into *len.  Host-only, synchronous. */
+ta_status ta_callpath(ta_handle h, int32_t leaf, int32_t *path_host, int32_t cap, int32_t *len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TA_H_ */

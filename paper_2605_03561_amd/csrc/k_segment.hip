@@ -1,0 +1,408 @@
+// k_segment.hip -- fused attribution + iteration segmentation over CSR traces.
+//
+// One workgroup owns one rank at a time (grid-stride over a rank order, so the
+// same kernel serves one-workgroup-per-rank launches and persistent plans).
+// Per rank it streams the rank's events in tiles of NT*EPT, each thread holding
+// EPT consecutive events loaded with 16-byte vector loads from tile-aligned
+// global indices:
+//   duration  d_k = t_{k+1} - t_k (last event 0)                  [Sec. II]
+//   excl      LDS histogram keyed by preorder index (ds_add_u64)  [Sec. VI-B]
+//   boundary  entry into the marker subtree; iteration index by a
+//             workgroup scan of per-thread boundary counts        [Sec. V]
+//   tensor    LDS ring of W iteration rows x G regions; completed rows are
+//             written once, whole and coalesced, then cleared     [Sec. V]
+//   incl      one exclusive scan of the histogram in preorder:
+//             incl[v] = P[tout(v)] - P[tin(v)]
+// Everything is integer, so the result does not depend on the order of the
+// LDS atomics.  No global atomics except the sticky error word (errors only).
+#include "ta_internal.h"
+
+namespace ta {
+namespace {
+
+constexpr int NT = 256;
+constexpr int EPT = 4;
+constexpr int TILE = NT * EPT;
+constexpr int NWAVE = NT / 64;
+
+__device__ inline int wave_incl_scan_i32(int v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ inline int64_t wave_incl_scan_i64(int64_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int64_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ inline int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// 64x64 -> 128-bit unsigned square accumulated into (lo, hi).
+__device__ inline void acc_sq(uint64_t &lo, uint64_t &hi, int64_t v) {
+  unsigned __int128 p = (unsigned __int128)(__int128)v * (unsigned __int128)(__int128)v;
+  unsigned __int128 s = ((unsigned __int128)hi << 64 | lo) + p;
+  lo = (uint64_t)s;
+  hi = (uint64_t)(s >> 64);
+}
+
+template <bool ATTR, bool SEG>
+__global__ __launch_bounds__(NT) void seg_kernel(SegArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = a.N, G = a.G, I = a.I, W = a.W;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+
+  // ---- LDS layout ------------------------------------------------------
+  size_t o = 0;
+  int64_t *hist = reinterpret_cast<int64_t *>(smem + o);            // [N+1]
+  if (ATTR) o += ((size_t)(N + 1) * 8 + 15) & ~(size_t)15;
+  int64_t *ring = reinterpret_cast<int64_t *>(smem + o);            // [W*G]
+  size_t ring_bytes = SEG ? (size_t)W * G * 8 : 0;
+  size_t ring_area = ring_bytes > (size_t)NT * 24 ? ring_bytes : (size_t)NT * 24;
+  o += ring_area;
+  uint32_t *info = reinterpret_cast<uint32_t *>(smem + o);          // [N]
+  o += ((size_t)N * 4 + 15) & ~(size_t)15;
+  int *wsum = reinterpret_cast<int *>(smem + o);                    // [2][NWAVE]
+  int64_t *wsum64 = reinterpret_cast<int64_t *>(smem + o + 2 * NWAVE * sizeof(int));
+  // Rank-end reductions alias the ring area (the ring is cleared after).
+  int64_t *redS = ring;                                             // [NT]
+  uint64_t *redQ = reinterpret_cast<uint64_t *>(ring + NT);         // [NT][2]
+
+  // ---- stage the call-path table, clear histogram and ring -------------
+  for (int v = tid; v < N; v += NT) info[v] = a.info[v];
+  if (ATTR)
+    for (int v = tid; v <= N; v += NT) hist[v] = 0;
+  for (size_t v = tid; v < ring_area / 8; v += NT) ring[v] = 0;
+  __syncthreads();
+
+  // Region-row flush mapping: thread -> (row offset, region) with a fixed
+  // region per thread, so rank totals accumulate in registers.
+  const int rows_pp = SEG ? NT / G : 1;
+  const int gme = SEG ? tid % G : 0;
+  const int rsub = SEG ? tid / G : 0;
+  const bool fl_active = SEG && tid < rows_pp * G;
+
+  int parity = 0;
+  for (int64_t rr = blockIdx.x; rr < a.R; rr += gridDim.x) {
+    const int64_t r = a.order ? (int64_t)a.order[rr] : rr;
+    int64_t b = a.off[r], e = a.off[r + 1];
+    uint32_t errb = 0;
+    if (b < 0 || e < b || e > a.E) {
+      errb |= ERRBIT_OFFSETS;
+      b = e = 0;
+    }
+    int carry = -1;      // iteration index in effect after the processed events
+    int flushed = 0;     // tensor rows [0, flushed) are written
+    int64_t out_acc = 0; // time outside every region / before the first boundary
+    int64_t S = 0;
+    uint64_t Qlo = 0, Qhi = 0;
+    int64_t *trow = SEG ? a.tensor + r * (int64_t)I * G : nullptr;
+
+    auto flush = [&](int row_lo, int row_hi) {  // rows inclusive, all in the ring
+      if (!fl_active) return;
+      for (int row = row_lo + rsub; row <= row_hi; row += rows_pp) {
+        int slot = (row & (W - 1)) * G + gme;
+        int64_t v = ring[slot];
+        ring[slot] = 0;
+        trow[(int64_t)row * G + gme] = v;
+        S += v;
+        acc_sq(Qlo, Qhi, v);
+      }
+    };
+
+    for (int64_t t0 = b & ~(int64_t)(TILE - 1); t0 < e; t0 += TILE) {
+      const int64_t c0 = t0 + (int64_t)tid * EPT;
+      int64_t tsv[EPT];
+      int32_t cv[EPT];
+#pragma unroll
+      for (int j = 0; j < EPT; j++) {
+        tsv[j] = 0;
+        cv[j] = 0;
+      }
+      const bool any_in = (c0 + EPT > b) && (c0 < e);
+      if (any_in) {
+        if (c0 + EPT <= a.E) {
+          const int4 *pt = reinterpret_cast<const int4 *>(a.ts + c0);
+          int4 x0 = pt[0], x1 = pt[1];
+          int4 y = *reinterpret_cast<const int4 *>(a.ctx + c0);
+          tsv[0] = (int64_t)(((uint64_t)(uint32_t)x0.y << 32) | (uint32_t)x0.x);
+          tsv[1] = (int64_t)(((uint64_t)(uint32_t)x0.w << 32) | (uint32_t)x0.z);
+          tsv[2] = (int64_t)(((uint64_t)(uint32_t)x1.y << 32) | (uint32_t)x1.x);
+          tsv[3] = (int64_t)(((uint64_t)(uint32_t)x1.w << 32) | (uint32_t)x1.z);
+          cv[0] = y.x;
+          cv[1] = y.y;
+          cv[2] = y.z;
+          cv[3] = y.w;
+        } else {
+#pragma unroll
+          for (int j = 0; j < EPT; j++)
+            if (c0 + j < a.E) {
+              tsv[j] = a.ts[c0 + j];
+              cv[j] = a.ctx[c0 + j];
+            }
+        }
+      }
+      // Timestamp after my last event (lane + 1's first, or a load at the
+      // wave edge) and context before my first event.
+      int64_t nxt = __shfl_down(tsv[0], 1, 64);
+      if (lane == 63) {
+        int64_t k = c0 + EPT;
+        nxt = (k < e) ? a.ts[k] : 0;
+      }
+      int32_t pc = __shfl_up(cv[EPT - 1], 1, 64);
+      if (lane == 0) {
+        int64_t k = c0 - 1;
+        pc = (k >= b && k < e) ? a.ctx[k] : -1;
+      }
+      int prev_in = 0;
+      if (c0 - 1 >= b && c0 - 1 < e && (uint32_t)pc < (uint32_t)N)
+        prev_in = (info[pc] & INFO_MARKER_BIT) ? 1 : 0;
+
+      int64_t d[EPT];
+      uint32_t inf[EPT];
+      uint32_t inr = 0, bmask = 0;
+      int bcount = 0;
+#pragma unroll
+      for (int j = 0; j < EPT; j++) {
+        const int64_t k = c0 + j;
+        const bool in_r = (k >= b) && (k < e);
+        const int64_t tn = (j < EPT - 1) ? tsv[j + 1] : nxt;
+        int64_t dj = (in_r && k + 1 < e) ? tn - tsv[j] : 0;
+        if (dj < 0) errb |= ERRBIT_UNSORTED;
+        uint32_t w = 0;
+        if (in_r) {
+          if ((uint32_t)cv[j] < (uint32_t)N) w = info[cv[j]];
+          else errb |= ERRBIT_CTX;
+        }
+        const int inm = (w & INFO_MARKER_BIT) ? 1 : 0;
+        const int bnd = inm & (prev_in ^ 1);
+        prev_in = inm;
+        bmask |= (uint32_t)bnd << j;
+        inr |= (uint32_t)in_r << j;
+        bcount += bnd;
+        d[j] = dj;
+        inf[j] = w;
+      }
+
+      // Workgroup scan of boundary counts -> iteration index of each event.
+      const int inc = wave_incl_scan_i32(bcount, lane);
+      int *ws = wsum + parity * NWAVE;
+      parity ^= 1;
+      if (lane == 63) ws[wid] = inc;
+      __syncthreads();
+      int wbase = 0, tot = 0;
+#pragma unroll
+      for (int w = 0; w < NWAVE; w++) {
+        int s = ws[w];
+        wbase += (w < wid) ? s : 0;
+        tot += s;
+      }
+      const int it_first = carry;
+      const int it_last = carry + tot;
+      int itj[EPT];
+      int run = carry + wbase + inc - bcount;
+#pragma unroll
+      for (int j = 0; j < EPT; j++) {
+        run += (bmask >> j) & 1;
+        itj[j] = run;
+      }
+
+      if (ATTR) {
+#pragma unroll
+        for (int j = 0; j < EPT; j++)
+          if (d[j] != 0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&hist[inf[j] >> INFO_TIN_SHIFT]),
+                      (unsigned long long)d[j]);
+      }
+
+      if (SEG) {
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
+          const int gj = (int)(inf[j] & INFO_REGION_MASK) - 1;
+          if (((inr >> j) & 1) && (itj[j] < 0 || gj < 0)) out_acc += d[j];
+          if (((inr >> j) & 1) && itj[j] >= I) errb |= ERRBIT_OVERFLOW;
+        }
+        int lo = it_first > 0 ? it_first : 0;
+        while (true) {
+          const int hi = lo + W - 1;
+          int64_t pend = 0;
+          int pslot = -1;
+#pragma unroll
+          for (int j = 0; j < EPT; j++) {
+            const int gj = (int)(inf[j] & INFO_REGION_MASK) - 1;
+            const int it = itj[j];
+            if (((inr >> j) & 1) && gj >= 0 && it >= lo && it <= hi && it < I) {
+              const int slot = (it & (W - 1)) * G + gj;
+              if (slot == pslot) {
+                pend += d[j];
+              } else {
+                if (pslot >= 0 && pend != 0)
+                  atomicAdd(reinterpret_cast<unsigned long long *>(&ring[pslot]),
+                            (unsigned long long)pend);
+                pslot = slot;
+                pend = d[j];
+              }
+            }
+          }
+          if (pslot >= 0 && pend != 0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&ring[pslot]), (unsigned long long)pend);
+          __syncthreads();
+          int fl_hi = hi < it_last - 1 ? hi : it_last - 1;
+          if (fl_hi > I - 1) fl_hi = I - 1;
+          if (fl_hi >= flushed) {
+            flush(flushed, fl_hi);
+            flushed = fl_hi + 1;
+          }
+          __syncthreads();
+          if (hi >= it_last) break;
+          lo = hi + 1;
+        }
+      }
+      carry = it_last;
+    }
+
+    // ---- rank epilogue --------------------------------------------------
+    if (SEG) {
+      const int last_data = carry < I - 1 ? carry : I - 1;
+      if (fl_active) {
+        for (int row = flushed + rsub; row < I; row += rows_pp) {
+          int64_t v = 0;
+          if (row <= last_data) {
+            int slot = (row & (W - 1)) * G + gme;
+            v = ring[slot];
+            ring[slot] = 0;
+          }
+          trow[(int64_t)row * G + gme] = v;
+          S += v;
+          acc_sq(Qlo, Qhi, v);
+        }
+      }
+      // outside: workgroup sum
+      int64_t os = wave_sum_i64(out_acc);
+      __syncthreads();
+      if (lane == 0) wsum64[wid] = os;
+      redS[tid] = S;
+      redQ[2 * tid] = Qlo;
+      redQ[2 * tid + 1] = Qhi;
+      __syncthreads();
+      if (tid < G) {
+        int64_t s = 0;
+        unsigned __int128 q = 0;
+        for (int k = 0; k < rows_pp; k++) {
+          int idx = k * G + tid;
+          s += redS[idx];
+          q += ((unsigned __int128)redQ[2 * idx + 1] << 64) | redQ[2 * idx];
+        }
+        if (a.rank_sum) a.rank_sum[r * G + tid] = s;
+        if (a.rank_sumsq) {
+          a.rank_sumsq[2 * (r * G + tid)] = (uint64_t)q;
+          a.rank_sumsq[2 * (r * G + tid) + 1] = (uint64_t)(q >> 64);
+        }
+      }
+      if (tid == 0) {
+        int64_t s = 0;
+        for (int w = 0; w < NWAVE; w++) s += wsum64[w];
+        if (a.outside) a.outside[r] = s;
+        if (a.iters_found) a.iters_found[r] = carry + 1;
+      }
+      __syncthreads();
+      for (int v = tid; v < 3 * NT; v += NT) ring[v] = 0;  // redS + redQ area
+    }
+    if (tid == 0 && a.span) a.span[r] = (e > b) ? a.ts[e - 1] - a.ts[b] : 0;
+
+    if (ATTR) {
+      __syncthreads();
+      // Exclusive scan of the histogram in preorder: P[j] = sum_{j' < j} h[j'].
+      const int n1 = N + 1;
+      const int L = (n1 + NT - 1) / NT;
+      const int k0 = tid * L;
+      const int k1 = (k0 + L < n1) ? k0 + L : n1;
+      int64_t s = 0;
+      for (int k = k0; k < k1; k++) s += (k < N) ? hist[k] : 0;
+      const int64_t incs = wave_incl_scan_i64(s, lane);
+      if (lane == 63) wsum64[wid] = incs;
+      __syncthreads();
+      int64_t runp = incs - s;
+      for (int w = 0; w < wid; w++) runp += wsum64[w];
+      for (int k = k0; k < k1; k++) {
+        int64_t h = (k < N) ? hist[k] : 0;
+        hist[k] = runp;
+        runp += h;
+      }
+      __syncthreads();
+      for (int v = tid; v < N; v += NT) {
+        const int2 tt = a.tin_tout[v];
+        const int64_t pa = hist[tt.x];
+        if (a.excl) a.excl[r * N + v] = hist[tt.x + 1] - pa;
+        if (a.incl) a.incl[r * N + v] = hist[tt.y] - pa;
+      }
+      __syncthreads();
+      for (int v = tid; v <= N; v += NT) hist[v] = 0;
+    }
+    if (errb) atomicOr(a.err, errb);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+size_t segment_lds_bytes(int N, int G, bool attr, bool seg, int *W, int *log2W) {
+  size_t fixed = 0;
+  if (attr) fixed += ((size_t)(N + 1) * 8 + 15) & ~(size_t)15;
+  fixed += ((size_t)N * 4 + 15) & ~(size_t)15;
+  fixed += 2 * NWAVE * sizeof(int) + NWAVE * sizeof(int64_t);
+  int w = 2, lw = 1;
+  if (seg) {
+    // Largest power-of-two ring within 16 KiB, and within what leaves room for
+    // two workgroups per CU when the tables allow it.
+    size_t budget = 16384;
+    if (fixed + budget > 80 * 1024 && fixed + 8192 <= 80 * 1024) budget = 8192;
+    while ((size_t)(w * 2) * G * 8 <= budget && w < 1024) {
+      w *= 2;
+      lw++;
+    }
+  }
+  *W = w;
+  *log2W = lw;
+  size_t ring = seg ? (size_t)w * G * 8 : 0;
+  if (ring < (size_t)NT * 24) ring = (size_t)NT * 24;
+  return fixed + ring;
+}
+
+template <bool A, bool S>
+void allow_big_lds() {
+  static bool done = false;
+  if (!done) {
+    hipFuncSetAttribute(reinterpret_cast<const void *>(&seg_kernel<A, S>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    done = true;
+  }
+}
+
+hipError_t launch_segment(const SegArgs &a, bool attr, bool seg, int grid, size_t lds,
+                          hipStream_t s) {
+  allow_big_lds<true, true>();
+  allow_big_lds<true, false>();
+  allow_big_lds<false, true>();
+  if (attr && seg) {
+    hipLaunchKernelGGL((seg_kernel<true, true>), dim3(grid), dim3(NT), lds, s, a);
+  } else if (attr) {
+    hipLaunchKernelGGL((seg_kernel<true, false>), dim3(grid), dim3(NT), lds, s, a);
+  } else {
+    hipLaunchKernelGGL((seg_kernel<false, true>), dim3(grid), dim3(NT), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ta

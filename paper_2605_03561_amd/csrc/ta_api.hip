@@ -1,0 +1,478 @@
+// ta_api.hip -- host side of the C ABI: handle, call-path tables, argument
+// validation, workspace and kernel launches.  No exception crosses the ABI.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "ta_internal.h"
+
+struct ta_handle_s {
+  int device = 0;
+  std::string last_error;
+  // call-path tree (caller numbering) and derived tables
+  int32_t N = 0;
+  std::vector<int32_t> parent, tin, tout;
+  // regions
+  int32_t marker = -1, G = 0;
+  std::vector<int32_t> regions;
+  uint32_t *d_info = nullptr;
+  int2 *d_tin_tout = nullptr;
+  uint32_t *d_err = nullptr;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+namespace {
+
+ta_status fail(ta_handle h, ta_status s, const std::string &msg) {
+  if (h) h->last_error = msg;
+  return s;
+}
+
+ta_status hipfail(ta_handle h, hipError_t e, const char *what) {
+  return fail(h, TA_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define TA_HIP(h, call)                                  \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hipfail((h), e_, #call); \
+  } while (0)
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int d) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != d) hipSetDevice(d);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+ta_status ensure_ws(ta_handle h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return TA_OK;
+  if (h->ws) {
+    // Kernels already queued may still use the old workspace.
+    TA_HIP(h, hipDeviceSynchronize());
+    TA_HIP(h, hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  size_t want = bytes + bytes / 4;
+  if (hipMalloc(&h->ws, want) != hipSuccess) {
+    h->ws = nullptr;
+    return fail(h, TA_ERR_OOM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+  }
+  h->ws_bytes = want;
+  return TA_OK;
+}
+
+// Validate a parent array; fill preorder index and subtree end.
+ta_status build_tree(ta_handle h, int32_t N, const int32_t *parent, std::vector<int32_t> &tin,
+                     std::vector<int32_t> &tout) {
+  std::vector<int32_t> head(N, -1), next(N, -1);
+  std::vector<int32_t> roots;
+  for (int32_t v = N - 1; v >= 0; v--) {  // children lists in increasing id order
+    const int32_t p = parent[v];
+    if (p < -1 || p >= N) return fail(h, TA_ERR_BAD_TREE, "parent id out of range at node " + std::to_string(v));
+    if (p == v) return fail(h, TA_ERR_BAD_TREE, "node is its own parent: " + std::to_string(v));
+    if (p >= 0) {
+      next[v] = head[p];
+      head[p] = v;
+    }
+  }
+  for (int32_t v = 0; v < N; v++)
+    if (parent[v] == -1) roots.push_back(v);
+  tin.assign(N, -1);
+  tout.assign(N, -1);
+  int32_t clock = 0;
+  std::vector<int32_t> stack;
+  for (int32_t root : roots) {
+    stack.push_back(root);
+    tin[root] = clock++;
+    while (!stack.empty()) {
+      const int32_t v = stack.back();
+      const int32_t c = head[v];
+      if (c >= 0) {
+        head[v] = next[c];  // consume the child
+        tin[c] = clock++;
+        stack.push_back(c);
+      } else {
+        tout[v] = clock;
+        stack.pop_back();
+      }
+    }
+  }
+  if (clock != N) return fail(h, TA_ERR_BAD_TREE, "parent array has a cycle");
+  return TA_OK;
+}
+
+ta_status upload_tables(ta_handle h) {
+  const int32_t N = h->N;
+  std::vector<uint32_t> info(N);
+  std::vector<int32_t> reg(N, -1);
+  std::vector<int32_t> is_region(N, -1);
+  for (int32_t g = 0; g < h->G; g++) is_region[h->regions[g]] = g;
+  // Visit in preorder so a parent's region is known before its children's.
+  std::vector<int32_t> order(N);
+  for (int32_t v = 0; v < N; v++) order[h->tin[v]] = v;
+  for (int32_t j = 0; j < N; j++) {
+    const int32_t v = order[j];
+    if (is_region[v] >= 0) reg[v] = is_region[v];
+    else if (h->parent[v] >= 0) reg[v] = reg[h->parent[v]];
+  }
+  const int32_t m = h->marker;
+  for (int32_t v = 0; v < N; v++) {
+    uint32_t w = (uint32_t)h->tin[v] << ta::INFO_TIN_SHIFT;
+    if (m >= 0 && h->tin[v] >= h->tin[m] && h->tin[v] < h->tout[m]) w |= ta::INFO_MARKER_BIT;
+    w |= (uint32_t)(reg[v] + 1);
+    info[v] = w;
+  }
+  std::vector<int2> tt(N);
+  for (int32_t v = 0; v < N; v++) tt[v] = make_int2(h->tin[v], h->tout[v]);
+  if (h->d_info) hipFree(h->d_info);
+  if (h->d_tin_tout) hipFree(h->d_tin_tout);
+  h->d_info = nullptr;
+  h->d_tin_tout = nullptr;
+  TA_HIP(h, hipMalloc(&h->d_info, (size_t)N * sizeof(uint32_t)));
+  TA_HIP(h, hipMalloc(&h->d_tin_tout, (size_t)N * sizeof(int2)));
+  TA_HIP(h, hipMemcpy(h->d_info, info.data(), (size_t)N * sizeof(uint32_t), hipMemcpyHostToDevice));
+  TA_HIP(h, hipMemcpy(h->d_tin_tout, tt.data(), (size_t)N * sizeof(int2), hipMemcpyHostToDevice));
+  return TA_OK;
+}
+
+ta_status check_traces(ta_handle h, const ta_traces *t) {
+  if (!t) return fail(h, TA_ERR_INVALID_ARG, "traces is NULL");
+  if (t->n_ranks < 0 || t->n_events < 0) return fail(h, TA_ERR_INVALID_ARG, "negative size");
+  if (t->n_ranks >= (int64_t)1 << 31) return fail(h, TA_ERR_SIZE_OVERFLOW, "too many ranks");
+  if (!t->offsets || !aligned16(t->offsets)) return fail(h, TA_ERR_INVALID_ARG, "offsets NULL or not 16-byte aligned");
+  if (t->n_events > 0 && (!t->ts || !t->ctx))
+    return fail(h, TA_ERR_INVALID_ARG, "ts/ctx NULL");
+  if ((t->ts && !aligned16(t->ts)) || (t->ctx && !aligned16(t->ctx)))
+    return fail(h, TA_ERR_INVALID_ARG, "ts/ctx not 16-byte aligned");
+  return TA_OK;
+}
+
+ta_status run_segment(ta_handle h, const ta_traces *t, int32_t n_iters, const ta_seg_out *o,
+                      void *stream, bool want_attr, bool want_seg) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  ta_status st = check_traces(h, t);
+  if (st) return st;
+  if (!o) return fail(h, TA_ERR_INVALID_ARG, "outputs NULL");
+  if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  const bool attr = want_attr && (o->excl || o->incl);
+  const bool seg = want_seg && (o->tensor || o->iters_found);
+  if (!attr && !seg) return fail(h, TA_ERR_INVALID_ARG, "no output requested");
+  if (seg) {
+    if (h->G <= 0) return fail(h, TA_ERR_STATE, "ta_set_regions has not been called");
+    if (!o->tensor || !o->iters_found)
+      return fail(h, TA_ERR_INVALID_ARG, "segmentation needs tensor and iters_found");
+    if (n_iters < 1) return fail(h, TA_ERR_INVALID_ARG, "n_iters must be >= 1");
+    const double cells = (double)t->n_ranks * (double)n_iters * (double)h->G;
+    if (cells > 4e18 || (double)n_iters * h->G > 2e9) return fail(h, TA_ERR_SIZE_OVERFLOW, "tensor too large");
+  }
+  if (attr && h->N > ta::MAX_NODES_ATTR)
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "attribution supports at most 8192 CCT nodes");
+  const void *ptrs[] = {o->tensor, o->iters_found, o->outside, o->span, o->rank_sum, o->rank_sumsq,
+                        o->excl, o->incl};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "output not 16-byte aligned");
+  if (t->n_ranks == 0) return TA_OK;
+
+  int W = 2, lw = 1;
+  const size_t lds = ta::segment_lds_bytes(h->N, seg ? h->G : 1, attr, seg, &W, &lw);
+  if (lds > 160 * 1024) return fail(h, TA_ERR_SIZE_OVERFLOW, "call-path tables exceed LDS");
+  ta::SegArgs a{};
+  a.off = t->offsets;
+  a.ts = t->ts;
+  a.ctx = t->ctx;
+  a.R = t->n_ranks;
+  a.E = t->n_events;
+  a.info = h->d_info;
+  a.tin_tout = h->d_tin_tout;
+  a.order = nullptr;
+  a.N = h->N;
+  a.G = seg ? h->G : 1;
+  a.I = seg ? n_iters : 0;
+  a.W = W;
+  a.log2W = lw;
+  a.tensor = seg ? o->tensor : nullptr;
+  a.iters_found = seg ? o->iters_found : nullptr;
+  a.outside = seg ? o->outside : nullptr;
+  a.span = o->span;
+  a.rank_sum = seg ? o->rank_sum : nullptr;
+  a.rank_sumsq = seg ? o->rank_sumsq : nullptr;
+  a.excl = attr ? o->excl : nullptr;
+  a.incl = attr ? o->incl : nullptr;
+  a.err = h->d_err;
+  DeviceGuard dg(h->device);
+  const int grid = (int)std::min<int64_t>(t->n_ranks, (int64_t)1 << 30);
+  hipError_t e = ta::launch_segment(a, attr, seg, grid, lds, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "segment kernel launch");
+  return TA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ta_status_string(ta_status s) {
+  switch (s) {
+    case TA_OK: return "ok";
+    case TA_ERR_INVALID_ARG: return "invalid argument";
+    case TA_ERR_BAD_TREE: return "bad call-path tree";
+    case TA_ERR_CTX_RANGE: return "context id out of range";
+    case TA_ERR_UNSORTED: return "timestamps decrease within a rank";
+    case TA_ERR_ITER_OVERFLOW: return "more iterations than the tensor holds";
+    case TA_ERR_SIZE_OVERFLOW: return "size exceeds a kernel limit";
+    case TA_ERR_OOM: return "out of device memory";
+    case TA_ERR_HIP: return "HIP runtime error";
+    case TA_ERR_STATE: return "missing set-up call";
+    default: return "unknown status";
+  }
+}
+
+ta_status ta_create(ta_handle *out, int device) {
+  if (!out) return TA_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TA_ERR_INVALID_ARG;
+  ta_handle h = new (std::nothrow) ta_handle_s();
+  if (!h) return TA_ERR_OOM;
+  h->device = device;
+  DeviceGuard dg(device);
+  if (hipMalloc(&h->d_err, 256) != hipSuccess || hipMemset(h->d_err, 0, 256) != hipSuccess) {
+    delete h;
+    return TA_ERR_HIP;
+  }
+  *out = h;
+  return TA_OK;
+}
+
+ta_status ta_destroy(ta_handle h) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  DeviceGuard dg(h->device);
+  hipDeviceSynchronize();
+  if (h->d_info) hipFree(h->d_info);
+  if (h->d_tin_tout) hipFree(h->d_tin_tout);
+  if (h->d_err) hipFree(h->d_err);
+  if (h->ws) hipFree(h->ws);
+  delete h;
+  return TA_OK;
+}
+
+const char *ta_last_error(ta_handle h) { return h ? h->last_error.c_str() : "NULL handle"; }
+
+ta_status ta_sync_status(ta_handle h, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  DeviceGuard dg(h->device);
+  TA_HIP(h, hipStreamSynchronize((hipStream_t)stream));
+  uint32_t bits = 0;
+  TA_HIP(h, hipMemcpy(&bits, h->d_err, sizeof(bits), hipMemcpyDeviceToHost));
+  TA_HIP(h, hipMemset(h->d_err, 0, sizeof(bits)));
+  if (bits & ta::ERRBIT_CTX) return fail(h, TA_ERR_CTX_RANGE, "a context id is outside [0, N)");
+  if (bits & ta::ERRBIT_UNSORTED) return fail(h, TA_ERR_UNSORTED, "timestamps decrease within a rank");
+  if (bits & ta::ERRBIT_OVERFLOW) return fail(h, TA_ERR_ITER_OVERFLOW, "a rank has more iterations than n_iters");
+  if (bits & ta::ERRBIT_OFFSETS) return fail(h, TA_ERR_INVALID_ARG, "inconsistent offsets or placement ids");
+  return TA_OK;
+}
+
+ta_status ta_set_tree(ta_handle h, int32_t n_nodes, const int32_t *parent_host) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (n_nodes <= 0 || !parent_host) return fail(h, TA_ERR_INVALID_ARG, "empty tree");
+  if (n_nodes > ta::MAX_NODES) return fail(h, TA_ERR_SIZE_OVERFLOW, "too many CCT nodes");
+  std::vector<int32_t> tin, tout;
+  ta_status st = build_tree(h, n_nodes, parent_host, tin, tout);
+  if (st) return st;
+  DeviceGuard dg(h->device);
+  h->N = n_nodes;
+  h->parent.assign(parent_host, parent_host + n_nodes);
+  h->tin = std::move(tin);
+  h->tout = std::move(tout);
+  h->marker = -1;
+  h->G = 0;
+  h->regions.clear();
+  return upload_tables(h);
+}
+
+ta_status ta_set_regions(ta_handle h, int32_t marker_node, int32_t n_regions,
+                         const int32_t *region_nodes_host) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  if (marker_node < 0 || marker_node >= h->N) return fail(h, TA_ERR_INVALID_ARG, "marker out of range");
+  if (n_regions < 1 || n_regions > ta::MAX_REGIONS || !region_nodes_host)
+    return fail(h, TA_ERR_INVALID_ARG, "n_regions must be in [1, 256]");
+  std::vector<int32_t> regs(region_nodes_host, region_nodes_host + n_regions);
+  std::vector<char> seen(h->N, 0);
+  for (int32_t v : regs) {
+    if (v < 0 || v >= h->N) return fail(h, TA_ERR_INVALID_ARG, "region node out of range");
+    if (seen[v]) return fail(h, TA_ERR_INVALID_ARG, "duplicate region node");
+    seen[v] = 1;
+  }
+  DeviceGuard dg(h->device);
+  h->marker = marker_node;
+  h->G = n_regions;
+  h->regions = std::move(regs);
+  return upload_tables(h);
+}
+
+ta_status ta_callpath(ta_handle h, int32_t leaf, int32_t *path_host, int32_t cap, int32_t *len) {
+  if (!h || !len) return TA_ERR_INVALID_ARG;
+  if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  if (leaf < 0 || leaf >= h->N) return fail(h, TA_ERR_INVALID_ARG, "leaf out of range");
+  if (cap > 0 && !path_host) return fail(h, TA_ERR_INVALID_ARG, "path NULL");
+  int32_t n = 0;
+  for (int32_t v = leaf; v != -1; v = h->parent[v]) {
+    if (n < cap) path_host[n] = v;
+    n++;
+  }
+  *len = n;
+  return TA_OK;
+}
+
+ta_status ta_attribute(ta_handle h, const ta_traces *t, int64_t *excl, int64_t *incl, void *stream) {
+  ta_seg_out o{};
+  o.excl = excl;
+  o.incl = incl;
+  if (!excl && !incl) return fail(h, TA_ERR_INVALID_ARG, "excl and incl are both NULL");
+  return run_segment(h, t, 0, &o, stream, true, false);
+}
+
+ta_status ta_segment(ta_handle h, const ta_traces *t, int32_t n_iters, int64_t *tensor,
+                     int32_t *iters_found, int64_t *outside, void *stream) {
+  ta_seg_out o{};
+  o.tensor = tensor;
+  o.iters_found = iters_found;
+  o.outside = outside;
+  if (!tensor || !iters_found) return fail(h, TA_ERR_INVALID_ARG, "tensor and iters_found are required");
+  return run_segment(h, t, n_iters, &o, stream, false, true);
+}
+
+ta_status ta_attribute_segment(ta_handle h, const ta_traces *t, int32_t n_iters,
+                               const ta_seg_out *out, void *stream) {
+  return run_segment(h, t, n_iters, out, stream, true, true);
+}
+
+ta_status ta_imbalance(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                       int32_t n_regions, const int32_t *iters_found, const int64_t *rank_sum,
+                       const uint64_t *rank_sumsq, const int64_t *span, int32_t ddof,
+                       double t_app_ns, const ta_imbalance_out *o, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!o) return fail(h, TA_ERR_INVALID_ARG, "outputs NULL");
+  if (n_ranks < 0 || n_iters < 1 || n_regions < 1 || ddof < 0)
+    return fail(h, TA_ERR_INVALID_ARG, "bad sizes or ddof");
+  if (n_ranks > 0 && !tensor) return fail(h, TA_ERR_INVALID_ARG, "tensor NULL");
+  if ((double)n_iters * n_regions > 2e9 || (double)n_ranks * n_iters * n_regions > 4e18)
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "tensor too large");
+  const void *ptrs[] = {tensor, iters_found, rank_sum, rank_sumsq, span, o->mean, o->std,
+                        o->max_minus_mean, o->min, o->max, o->avg_mean, o->avg_max,
+                        o->savings_per_iter, o->total_savings, o->balance_ratio, o->cv_across,
+                        o->cv_within, o->share, o->potential_speedup};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  const bool need_rs = !rank_sum || !rank_sumsq;
+  DeviceGuard dg(h->device);
+  ta_status st = ensure_ws(h, ta::imbalance_ws_bytes(n_ranks, n_iters, n_regions, need_rs));
+  if (st) return st;
+  ta::ImbArgs a{};
+  a.T = tensor;
+  a.R = n_ranks;
+  a.I = n_iters;
+  a.G = n_regions;
+  a.it = iters_found;
+  a.rank_sum = need_rs ? nullptr : rank_sum;
+  a.rank_sumsq = need_rs ? nullptr : rank_sumsq;
+  a.span = span;
+  a.ddof = ddof;
+  a.t_app = t_app_ns;
+  a.o = *o;
+  hipError_t e = ta::launch_imbalance(a, h->ws, h->ws_bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "imbalance launch");
+  return TA_OK;
+}
+
+ta_status ta_outliers(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                      int32_t n_regions, const int32_t *iters_found, int32_t mode, int32_t kind,
+                      double tau, double *rank_score, uint8_t *rank_flag, int64_t *n_flagged,
+                      double *region_score, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (n_ranks < 0 || n_iters < 1 || n_regions < 1) return fail(h, TA_ERR_INVALID_ARG, "bad sizes");
+  if ((mode != TA_SCAN_FULL && mode != TA_SCAN_TOTALS) || (kind != TA_SCORE_MAD && kind != TA_SCORE_Z))
+    return fail(h, TA_ERR_INVALID_ARG, "bad mode or kind");
+  if (!(tau >= 0.0)) return fail(h, TA_ERR_INVALID_ARG, "tau must be >= 0");
+  if (n_ranks > 0 && (!tensor || !rank_score || !rank_flag))
+    return fail(h, TA_ERR_INVALID_ARG, "tensor, rank_score and rank_flag are required");
+  if ((double)n_iters * n_regions > 2e9 || (double)n_ranks * n_iters * n_regions > 4e18)
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "tensor too large");
+  const void *ptrs[] = {tensor, iters_found, rank_score, rank_flag, n_flagged, region_score};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  DeviceGuard dg(h->device);
+  ta_status st = ensure_ws(h, ta::outliers_ws_bytes(n_ranks, n_iters, n_regions, mode, kind));
+  if (st) return st;
+  ta::OutArgs a{};
+  a.T = tensor;
+  a.R = n_ranks;
+  a.I = n_iters;
+  a.G = n_regions;
+  a.it = iters_found;
+  a.mode = mode;
+  a.kind = kind;
+  a.tau = tau;
+  a.rank_score = rank_score;
+  a.rank_flag = rank_flag;
+  a.n_flagged = n_flagged;
+  a.region_score = region_score;
+  hipError_t e = ta::launch_outliers(a, h->ws, h->ws_bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "outliers launch");
+  return TA_OK;
+}
+
+ta_status ta_topology_aggregate(ta_handle h, const double *rank_score, const uint8_t *rank_flag,
+                                int64_t n_ranks, const int32_t *rank_node,
+                                const int32_t *node_rack, const int32_t *node_chassis,
+                                int32_t n_nodes, int32_t n_racks, int32_t n_chassis,
+                                int64_t *flagged_per_rack, double *max_per_rack,
+                                double *mean_per_rack, int64_t *flagged_per_chassis,
+                                double *max_per_chassis, double *mean_per_chassis,
+                                void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (n_ranks < 0 || n_nodes < 1 || n_racks < 1 || n_chassis < 1)
+    return fail(h, TA_ERR_INVALID_ARG, "bad sizes");
+  if (n_ranks > 0 && (!rank_score || !rank_flag || !rank_node))
+    return fail(h, TA_ERR_INVALID_ARG, "rank arrays NULL");
+  if (!node_rack || !node_chassis) return fail(h, TA_ERR_INVALID_ARG, "node maps NULL");
+  const void *ptrs[] = {rank_score, rank_flag, rank_node, node_rack, node_chassis,
+                        flagged_per_rack, max_per_rack, mean_per_rack, flagged_per_chassis,
+                        max_per_chassis, mean_per_chassis};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  DeviceGuard dg(h->device);
+  ta::TopoArgs a{};
+  a.score = rank_score;
+  a.flag = rank_flag;
+  a.R = n_ranks;
+  a.rank_node = rank_node;
+  a.node_rack = node_rack;
+  a.node_chassis = node_chassis;
+  a.n_nodes = n_nodes;
+  a.n_racks = n_racks;
+  a.n_chassis = n_chassis;
+  a.fl_rack = flagged_per_rack;
+  a.mx_rack = max_per_rack;
+  a.mn_rack = mean_per_rack;
+  a.fl_ch = flagged_per_chassis;
+  a.mx_ch = max_per_chassis;
+  a.mn_ch = mean_per_chassis;
+  a.err = h->d_err;
+  hipError_t e = ta::launch_topology(a, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "topology launch");
+  return TA_OK;
+}
+
+}  // extern "C"

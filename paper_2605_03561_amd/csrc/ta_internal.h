@@ -1,0 +1,106 @@
+// ta_internal.h -- shared declarations of the HIP trace-analysis library.
+// Device code is written for gfx950 (CDNA4, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ta.h"
+
+namespace ta {
+
+// Sticky device error bits (one per data-error kind).
+enum : uint32_t {
+  ERRBIT_CTX = 1u,
+  ERRBIT_UNSORTED = 2u,
+  ERRBIT_OVERFLOW = 4u,
+  ERRBIT_OFFSETS = 8u,
+};
+
+// Packed per-node word used by the trace kernels (indexed by caller node id):
+//   bits 0..8   region index + 1 (0 = the node is in no region)
+//   bit  9      node lies in the marker's subtree
+//   bits 10..31 preorder index of the node
+constexpr int INFO_REGION_BITS = 9;
+constexpr uint32_t INFO_REGION_MASK = (1u << INFO_REGION_BITS) - 1u;
+constexpr uint32_t INFO_MARKER_BIT = 1u << INFO_REGION_BITS;
+constexpr int INFO_TIN_SHIFT = 10;
+
+constexpr int MAX_NODES_ATTR = 8192;      // LDS histogram limit for attribution
+constexpr int MAX_NODES = 1 << 22;        // preorder index field width
+constexpr int MAX_REGIONS = 256;
+
+struct SegArgs {
+  const int64_t *off;
+  const int64_t *ts;
+  const int32_t *ctx;
+  int64_t R;
+  int64_t E;
+  const uint32_t *info;   // [N]
+  const int2 *tin_tout;   // [N] preorder index and subtree end, by caller id
+  const int32_t *order;   // rank visiting order (NULL = identity)
+  int32_t N, G, I, W, log2W;
+  int64_t *tensor;
+  int32_t *iters_found;
+  int64_t *outside;
+  int64_t *span;
+  int64_t *rank_sum;
+  uint64_t *rank_sumsq;
+  int64_t *excl;
+  int64_t *incl;
+  uint32_t *err;
+};
+
+// Launchers (defined in the kernel translation units).
+hipError_t launch_segment(const SegArgs &a, bool attr, bool seg, int grid, size_t lds_bytes,
+                          hipStream_t s);
+size_t segment_lds_bytes(int N, int G, bool attr, bool seg, int *W, int *log2W);
+
+struct ImbArgs {
+  const int64_t *T;
+  int64_t R;
+  int32_t I, G;
+  const int32_t *it;
+  const int64_t *rank_sum;
+  const uint64_t *rank_sumsq;
+  const int64_t *span;
+  int32_t ddof;
+  double t_app;
+  ta_imbalance_out o;
+};
+hipError_t launch_imbalance(const ImbArgs &a, void *ws, size_t ws_bytes, hipStream_t s);
+size_t imbalance_ws_bytes(int64_t R, int32_t I, int32_t G, bool need_rank_stats);
+
+struct OutArgs {
+  const int64_t *T;
+  int64_t R;
+  int32_t I, G;
+  const int32_t *it;
+  int32_t mode, kind;
+  double tau;
+  double *rank_score;
+  uint8_t *rank_flag;
+  int64_t *n_flagged;
+  double *region_score;
+};
+hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStream_t s);
+size_t outliers_ws_bytes(int64_t R, int32_t I, int32_t G, int32_t mode, int32_t kind);
+
+struct TopoArgs {
+  const double *score;
+  const uint8_t *flag;
+  int64_t R;
+  const int32_t *rank_node, *node_rack, *node_chassis;
+  int32_t n_nodes, n_racks, n_chassis;
+  int64_t *fl_rack;
+  double *mx_rack, *mn_rack;
+  int64_t *fl_ch;
+  double *mx_ch, *mn_ch;
+  uint32_t *err;
+};
+hipError_t launch_topology(const TopoArgs &a, hipStream_t s);
+
+}  // namespace ta

@@ -20,9 +20,11 @@ Two trace layouts:
   ``D = round(f_r * Gamma(4, mu_g/4))`` laid out as [marker][regions in a random
   per-iteration order][unregioned filler].  With ``b = L_r // I`` events per
   iteration, ``b >= G + 2`` gives the *anchored* form (one event at every segment
-  start, the rest at uniform times, so the tensor equals D exactly); otherwise the
-  *sampled* form (the marker plus ``b - 1`` events at uniform times, so the
-  tensor estimates D, as statistical sampling does).  A final root event closes
+  start, the rest at stratified-jittered times, so the tensor equals D exactly);
+  otherwise the *sampled* form (the marker plus ``b - 1`` events at
+  stratified-jittered times -- one uniform draw inside each of ``b - 1`` equal
+  slices of the iteration -- so the tensor estimates D, as periodic sampling
+  with jitter does).  A final root event closes
   the trace.
 """
 from __future__ import annotations
@@ -235,8 +237,11 @@ def timeline_workload(seed: int = 0, n_ranks: int = 10_000, median_len: int = 50
         anchored = b >= G + 2
         n_extra = b - G - 2 if anchored else b - 1
 
-        # Extra events at uniform times inside each iteration.
-        u = np.floor(rng.random((I, n_extra)) * Ti[:, None]).astype(np.int64)
+        # Extra events at stratified-jittered times inside each iteration:
+        # event j of n falls in [j*Ti/n, (j+1)*Ti/n), so they come out sorted.
+        jj = np.arange(n_extra)[None, :]
+        u = np.floor((jj + rng.random((I, n_extra))) * (Ti[:, None] / max(n_extra, 1))).astype(np.int64)
+        u = np.minimum(u, np.maximum(Ti[:, None] - 1, 0))
         ex_t = it_start[:, None] + u
         # Segment holding each extra event: ends are non-decreasing over the
         # whole trace, so one search over the flattened ends finds it.

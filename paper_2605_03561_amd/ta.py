@@ -1,0 +1,265 @@
+"""Python binding of the C ABI in ``include/ta.h`` (argument marshalling only).
+
+Every computation runs in the HIP library ``libta.so``; torch supplies device
+memory and the current stream.  Importing this module fails loudly if the
+library has not been built (``python -m paper_2605_03561_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libta.so")
+
+OK, INVALID_ARG, BAD_TREE, CTX_RANGE, UNSORTED, ITER_OVERFLOW, SIZE_OVERFLOW, OOM, HIP, STATE = range(10)
+SCAN_FULL, SCAN_TOTALS = 0, 1
+SCORE_MAD, SCORE_Z = 0, 1
+
+
+class TAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ta status {status}: {msg}")
+        self.status = status
+
+
+class Traces(C.Structure):
+    _fields_ = [("n_ranks", C.c_int64), ("n_events", C.c_int64), ("offsets", C.c_void_p),
+                ("ts", C.c_void_p), ("ctx", C.c_void_p)]
+
+
+class SegOut(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("tensor", "iters_found", "outside", "span", "rank_sum",
+                                         "rank_sumsq", "excl", "incl")]
+
+
+IMB_FIELDS = ("mean", "std", "max_minus_mean", "min", "max", "avg_mean", "avg_max",
+              "savings_per_iter", "total_savings", "balance_ratio", "cv_across", "cv_within",
+              "share", "potential_speedup")
+
+
+class ImbOut(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in IMB_FIELDS]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2605_03561_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "ta_create": [C.POINTER(P), C.c_int],
+        "ta_destroy": [P],
+        "ta_status_string": [i32],
+        "ta_last_error": [P],
+        "ta_sync_status": [P, P],
+        "ta_set_tree": [P, i32, P],
+        "ta_set_regions": [P, i32, i32, P],
+        "ta_callpath": [P, i32, P, i32, P],
+        "ta_attribute": [P, P, P, P, P],
+        "ta_segment": [P, P, i32, P, P, P, P],
+        "ta_attribute_segment": [P, P, i32, P, P],
+        "ta_imbalance": [P, P, i64, i32, i32, P, P, P, P, i32, f64, P, P],
+        "ta_outliers": [P, P, i64, i32, i32, P, i32, i32, f64, P, P, P, P, P],
+        "ta_topology_aggregate": [P, P, P, i64, P, P, P, i32, i32, i32, P, P, P, P, P, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = i32
+    lib.ta_status_string.restype = C.c_char_p
+    lib.ta_last_error.restype = C.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def to_device(arr, dtype, device):
+    return torch.from_numpy(np.ascontiguousarray(arr, dtype=dtype)).to(device)
+
+
+class DeviceTraces:
+    """CSR traces resident on the GPU (offsets int64, ts int64, ctx int32)."""
+
+    def __init__(self, offsets, ts, ctx, device="cuda:0"):
+        self.device = torch.device(device)
+        self.offsets = offsets if isinstance(offsets, torch.Tensor) else to_device(offsets, np.int64, self.device)
+        self.ts = ts if isinstance(ts, torch.Tensor) else to_device(ts, np.int64, self.device)
+        self.ctx = ctx if isinstance(ctx, torch.Tensor) else to_device(ctx, np.int32, self.device)
+        self.n_ranks = self.offsets.numel() - 1
+        self.n_events = self.ts.numel()
+
+    def struct(self) -> Traces:
+        return Traces(self.n_ranks, self.n_events, _ptr(self.offsets).value,
+                      _ptr(self.ts).value if self.n_events else None,
+                      _ptr(self.ctx).value if self.n_events else None)
+
+
+class Handle:
+    """Owns a library handle (workspace, call-path tables) on one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        torch.cuda.init()
+        h = C.c_void_p()
+        self._check(_lib.ta_create(C.byref(h), device), None)
+        self.h = h
+        self.n_nodes = 0
+        self.n_regions = 0
+
+    def _check(self, st, h=True):
+        if st != OK:
+            msg = _lib.ta_status_string(st).decode()
+            if h is not None and getattr(self, "h", None) is not None:
+                msg += ": " + _lib.ta_last_error(self.h).decode()
+            raise TAError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            _lib.ta_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- set-up ------------------------------------------------------------
+    def set_tree(self, parent):
+        p = np.ascontiguousarray(parent, dtype=np.int32)
+        self._check(_lib.ta_set_tree(self.h, len(p), p.ctypes.data_as(C.c_void_p)))
+        self.n_nodes = len(p)
+        self.n_regions = 0
+
+    def set_regions(self, marker: int, regions):
+        g = np.ascontiguousarray(regions, dtype=np.int32)
+        self._check(_lib.ta_set_regions(self.h, int(marker), len(g), g.ctypes.data_as(C.c_void_p)))
+        self.n_regions = len(g)
+
+    def sync_status(self):
+        """Wait for the stream and raise TAError on a sticky device error."""
+        self._check(_lib.ta_sync_status(self.h, _stream(self.device)))
+
+    def callpath(self, leaf: int):
+        buf = np.zeros(64, np.int32)
+        n = C.c_int32()
+        self._check(_lib.ta_callpath(self.h, int(leaf), buf.ctypes.data_as(C.c_void_p), 64,
+                                     C.byref(n)))
+        if n.value > 64:
+            buf = np.zeros(n.value, np.int32)
+            self._check(_lib.ta_callpath(self.h, int(leaf), buf.ctypes.data_as(C.c_void_p),
+                                         n.value, C.byref(n)))
+        return buf[:n.value].tolist()
+
+    # -- trace passes --------------------------------------------------------
+    def _empty(self, shape, dtype):
+        return torch.empty(shape, dtype=dtype, device=self.device)
+
+    def attribute_segment(self, tr: DeviceTraces, n_iters: int, outputs=("tensor", "iters_found",
+                          "outside", "span", "rank_sum", "rank_sumsq", "excl", "incl"),
+                          out=None):
+        """Fused pass; returns a dict of the requested device tensors.  `out`
+        may hold preallocated tensors (same names) to write into."""
+        R, G, N = tr.n_ranks, max(self.n_regions, 1), self.n_nodes
+        shapes = {"tensor": ((R, n_iters, G), torch.int64), "iters_found": ((R,), torch.int32),
+                  "outside": ((R,), torch.int64), "span": ((R,), torch.int64),
+                  "rank_sum": ((R, G), torch.int64), "rank_sumsq": ((R, G, 2), torch.int64),
+                  "excl": ((R, N), torch.int64), "incl": ((R, N), torch.int64)}
+        res = {}
+        for k in outputs:
+            if out is not None and k in out:
+                res[k] = out[k]
+            else:
+                shp, dt = shapes[k]
+                res[k] = self._empty(shp, dt)
+        so = SegOut(*[(_ptr(res[k]).value if k in res else None) for k in
+                      ("tensor", "iters_found", "outside", "span", "rank_sum", "rank_sumsq",
+                       "excl", "incl")])
+        t = tr.struct()
+        self._check(_lib.ta_attribute_segment(self.h, C.byref(t), int(n_iters), C.byref(so),
+                                              _stream(self.device)))
+        return res
+
+    def attribute(self, tr: DeviceTraces, excl=True, incl=True):
+        R, N = tr.n_ranks, self.n_nodes
+        e = self._empty((R, N), torch.int64) if excl else None
+        i = self._empty((R, N), torch.int64) if incl else None
+        t = tr.struct()
+        self._check(_lib.ta_attribute(self.h, C.byref(t), _ptr(e), _ptr(i), _stream(self.device)))
+        return e, i
+
+    def segment(self, tr: DeviceTraces, n_iters: int):
+        R, G = tr.n_ranks, self.n_regions
+        T = self._empty((R, n_iters, G), torch.int64)
+        it = self._empty((R,), torch.int32)
+        out = self._empty((R,), torch.int64)
+        t = tr.struct()
+        self._check(_lib.ta_segment(self.h, C.byref(t), int(n_iters), _ptr(T), _ptr(it), _ptr(out),
+                                    _stream(self.device)))
+        return T, it, out
+
+    # -- statistics ----------------------------------------------------------
+    def imbalance(self, tensor, iters_found=None, rank_sum=None, rank_sumsq=None, span=None,
+                  ddof=1, t_app=0.0):
+        R, I, G = tensor.shape
+        o = {}
+        for k in ("mean", "std", "max_minus_mean"):
+            o[k] = self._empty((I, G), torch.float64)
+        o["min"] = self._empty((I, G), torch.int64)
+        o["max"] = self._empty((I, G), torch.int64)
+        for k in ("avg_mean", "avg_max", "savings_per_iter", "total_savings", "balance_ratio",
+                  "cv_across", "cv_within", "share"):
+            o[k] = self._empty((G,), torch.float64)
+        o["potential_speedup"] = self._empty((1,), torch.float64)
+        io = ImbOut(*[_ptr(o[k]).value for k in IMB_FIELDS])
+        self._check(_lib.ta_imbalance(self.h, _ptr(tensor), R, I, G, _ptr(iters_found),
+                                      _ptr(rank_sum), _ptr(rank_sumsq), _ptr(span), int(ddof),
+                                      float(t_app), C.byref(io), _stream(self.device)))
+        return o
+
+    def outliers(self, tensor, iters_found=None, mode=SCAN_FULL, kind=SCORE_MAD, tau=3.5,
+                 region=False):
+        R, I, G = tensor.shape
+        score = self._empty((R,), torch.float64)
+        flag = self._empty((R,), torch.uint8)
+        nf = self._empty((1,), torch.int64)
+        reg = self._empty((R, G), torch.float64) if region else None
+        self._check(_lib.ta_outliers(self.h, _ptr(tensor), R, I, G, _ptr(iters_found), int(mode),
+                                     int(kind), float(tau), _ptr(score), _ptr(flag), _ptr(nf),
+                                     _ptr(reg), _stream(self.device)))
+        return {"rank_score": score, "rank_flag": flag, "n_flagged": nf, "region_score": reg}
+
+    def topology(self, rank_score, rank_flag, rank_node, node_rack, node_chassis, n_racks,
+                 n_chassis):
+        o = {"flagged_rack": self._empty((n_racks,), torch.int64),
+             "max_rack": self._empty((n_racks,), torch.float64),
+             "mean_rack": self._empty((n_racks,), torch.float64),
+             "flagged_chassis": self._empty((n_chassis,), torch.int64),
+             "max_chassis": self._empty((n_chassis,), torch.float64),
+             "mean_chassis": self._empty((n_chassis,), torch.float64)}
+        self._check(_lib.ta_topology_aggregate(
+            self.h, _ptr(rank_score), _ptr(rank_flag), rank_score.numel(), _ptr(rank_node),
+            _ptr(node_rack), _ptr(node_chassis), node_rack.numel(), int(n_racks), int(n_chassis),
+            *[_ptr(o[k]) for k in ("flagged_rack", "max_rack", "mean_rack", "flagged_chassis",
+                                   "max_chassis", "mean_chassis")], _stream(self.device)))
+        return o
