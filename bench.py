@@ -1,0 +1,211 @@
+"""Benchmark of the trace -> rank x iteration x region tensor hot path on one GPU.
+
+One step = one pass of the whole path over a resident batch of synthetic
+traces: fused attribution + segmentation (one kernel), imbalance statistics,
+the exact outlier scan, and rack / chassis aggregation of the outlier scores.
+Inputs are generated on the GPU before timing (they stay in HBM); the JSON
+line reports whole-step events/s, the fused kernel against the HBM roofline,
+and the CPU oracle timed on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--workload c3|c2|small]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # 100,000 ranks, lognormal lengths (median 20k, 1k..200k), 5,000-node tree,
+    # 500 iterations, 64 regions, 2% of ranks 1.3x slower in 3 regions.
+    "c3": dict(n_ranks=100_000, median_len=20_000, min_len=1_000, max_len=200_000,
+               n_nodes=5_000, depth_max=12, n_iters=500, n_regions=64, inject_frac=0.02),
+    # 10,000 ranks, median 50k (1k..400k), 1,000 nodes, 300 iterations, 32 regions.
+    "c2": dict(n_ranks=10_000, median_len=50_000, min_len=1_000, max_len=400_000,
+               n_nodes=1_000, depth_max=12, n_iters=300, n_regions=32, inject_frac=0.0),
+    "small": dict(n_ranks=2_000, median_len=5_000, min_len=1_000, max_len=40_000,
+                  n_nodes=1_000, depth_max=12, n_iters=100, n_regions=32, inject_frac=0.02),
+}
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2605_03561_amd", "csrc", "k_segment.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:12]
+
+
+def read_traffic(workload: str, src_hash: str):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"fused_segment_{workload}_pmc.md")
+    if not os.path.exists(p):
+        return None
+    vals = {}
+    for line in open(p):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_12") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-sample-ranks", type=int, default=192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by rank "
+              "across GPUs by design but no multi-GPU run is part of this benchmark.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2605_03561_amd import gpu_synth, synth, ta
+
+    dev = torch.device("cuda:0")
+    cfg = WORKLOADS[args.workload]
+    t_gen = time.time()
+    w = gpu_synth.timeline_on_gpu(seed=args.seed, device=dev, **cfg)
+    t_gen = time.time() - t_gen
+    R, I, G, N, E = cfg["n_ranks"], cfg["n_iters"], cfg["n_regions"], cfg["n_nodes"], w.n_events
+    print(f"[bench] generated {args.workload}: R={R} E={E} in {t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+
+    h = ta.Handle(0)
+    h.set_tree(w.parent)
+    h.set_regions(w.marker, w.regions)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx, dev)
+    seg = h.attribute_segment(tr, I)          # allocates the outputs once
+    h.sync_status()
+    rank_node, node_rack, node_chassis = synth.topology(args.seed, R)
+    dn = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rank_node_d, node_rack_d, node_chassis_d = dn(rank_node), dn(node_rack), dn(node_chassis)
+
+    stream = torch.cuda.current_stream(dev)
+    stages = ["segment", "imbalance", "outliers", "topology"]
+
+    def step(ev=None):
+        rec = (lambda k: ev[k].record(stream)) if ev else (lambda k: None)
+        rec(0)
+        h.attribute_segment(tr, I, out=seg)
+        rec(1)
+        h.imbalance(seg["tensor"], seg["iters_found"], seg["rank_sum"], seg["rank_sumsq"],
+                    seg["span"])
+        rec(2)
+        o = h.outliers(seg["tensor"], seg["iters_found"])
+        rec(3)
+        h.topology(o["rank_score"], o["rank_flag"], rank_node_d, node_rack_d, node_chassis_d,
+                   22, 176)
+        rec(4)
+        return o
+
+    for _ in range(args.warmup):
+        step()
+    h.sync_status()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.sync_status()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    stage_ms = {s: float(np.mean([events[k][j].elapsed_time(events[k][j + 1])
+                                  for k in range(args.steps)])) for j, s in enumerate(stages)}
+
+    # Algorithmic bytes of the fused kernel (what the method must move).
+    alg_bytes = (12 * E + 8 * (R + 1) + 8 * R * I * G + 16 * R * N + 8 * R * G + 16 * R * G
+                 + (4 + 8 + 8) * R + 12 * N)
+    seg_s = stage_ms["segment"] / 1e3
+    achieved = alg_bytes / seg_s / 1e9
+    src_hash = kernel_source_hash()
+    traffic = read_traffic(args.workload, src_hash)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_sample_ranks, I, E / R)
+
+    value = E / (ms_step / 1e3)
+    line = {
+        "metric": "trace events/s into rank x iteration x region tensor (whole step: "
+                  "attribute+segment, imbalance, exact outlier scan, topology)",
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic (GPU-generated, seeded)",
+        "config": {"workload": f"{args.workload}: {R} ranks, {E} events, {N}-node tree, "
+                               f"{I} iterations, {G} regions, lognormal lengths "
+                               f"median {cfg['median_len']} ({cfg['min_len']}..{cfg['max_len']}), "
+                               f"{cfg['inject_frac']:.0%} injected slow ranks",
+                   "n_ranks": R, "n_events": E, "n_iters": I, "n_regions": G, "n_nodes": N},
+        "stage_ms": stage_ms,
+        "fused_segment_events_per_s": E / seg_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "seg_kernel<true,true> (fused attribute+segment)",
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel_source_sha256_12": src_hash},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    h.close()
+
+
+def cpu_baseline(w, n_sample, I, mean_events):
+    """Time the plain oracle (OpenMP over ranks, all host cores) on a stratified
+    sample of ranks copied back from the GPU: attribution, segmentation,
+    imbalance and the exact outlier scan over the sample."""
+    from oracle import oracle
+    from paper_2605_03561_amd import gpu_synth
+
+    R = len(w["offsets_host"]) - 1
+    ranks = np.linspace(0, R - 1, min(n_sample, R)).round().astype(np.int64)
+    s = gpu_synth.sample_ranks_to_host(w, ranks)
+    oracle.lib()
+    t = time.perf_counter()
+    st1, _, _ = oracle.attribute(s.offsets, s.ts, s.ctx, s.parent)
+    st2, T, it, _, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker, s.regions, I)
+    st3, _ = oracle.imbalance(T, it, span=span)
+    st4 = oracle.outliers(T, it)[0]
+    dt = time.perf_counter() - t
+    assert st1 == st2 == st3 == st4 == 0
+    n_ev = len(s.ts)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_ev / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(ranks)} evenly spaced ranks ({n_ev} events, mean "
+                      f"{n_ev / len(ranks):.0f}/rank vs {mean_events:.0f} overall): attribute + "
+                      f"segment + imbalance + full outlier scan, {dt:.1f} s",
+            "seconds": dt}
+
+
+if __name__ == "__main__":
+    main()

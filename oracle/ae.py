@@ -1,0 +1,177 @@
+"""Autoencoder oracle for the learned pre-screen (FP64 numpy).
+
+TEST INFRASTRUCTURE ONLY (never imported by the product package).
+
+The learned pre-screen is not part of the paper; the network and its training
+are a plain reading of a small dense autoencoder:
+  64 -> 128 -> 32 -> 128 -> 64, ReLU after the three hidden layers, linear
+  output, loss = mean over rows and features of (y - x)^2, Adam with bias
+  correction (Kingma & Ba 2015), Xavier-uniform initial weights (Glorot &
+  Bengio 2010), zero biases.
+Inputs are per-rank iteration profiles: x[r, i, :] = (T[r, i, :] - mu) / sigma
+with per-region mean and standard deviation over the training tensors' valid
+cells.  Rank score = max over regions of the mean over the rank's valid
+iterations of the squared reconstruction error.
+
+`bf16=True` rounds every matrix-product operand (activations, weights and the
+back-propagated errors) to bfloat16 (round to nearest even) at the points
+where the GPU kernels do, keeping FP64 accumulation; `bf16=False` is plain
+FP64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+DIMS = (64, 128, 32, 128, 64)
+N_LAYERS = 4
+
+
+# ---------------------------------------------------------------------------
+# bfloat16 rounding (round to nearest, ties to even) of FP32 values
+# ---------------------------------------------------------------------------
+
+def to_bf16(a) -> np.ndarray:
+    """Round to the nearest bfloat16 (ties to even) through FP32; returns FP64."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    nan = np.isnan(f)
+    if nan.any():
+        out[nan] = np.nan
+    return out
+
+
+# ---------------------------------------------------------------------------
+# SplitMix64 counter draws, the same definition the GPU initialiser uses
+# ---------------------------------------------------------------------------
+
+_M = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        z = (z + np.uint64(0x9E3779B97F4A7C15)) & _M
+        z = ((z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)) & _M
+        z = ((z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)) & _M
+        return z ^ (z >> np.uint64(31))
+
+
+def init_params(seed: int) -> dict:
+    """Xavier-uniform weights W_l[out, in] ~ U(-a, a), a = sqrt(6/(in+out)),
+    drawn as u = SplitMix64(seed-mixed counter) -> (u >> 11 + 0.5) / 2^53,
+    w = (2u - 1) * a in FP64, stored as FP32.  Biases are zero."""
+    p = {}
+    s = _mix64(np.array([seed], dtype=np.uint64))[0]
+    for l in range(N_LAYERS):
+        fin, fout = DIMS[l], DIMS[l + 1]
+        idx = np.arange(fout * fin, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            key = (s ^ _mix64(np.array([l + 1], dtype=np.uint64))[0])
+            z = _mix64((key + idx * np.uint64(0x9E3779B97F4A7C15)) & _M)
+        u = ((z >> np.uint64(11)).astype(np.float64) + 0.5) / 9007199254740992.0
+        a = np.sqrt(6.0 / (fin + fout))
+        p[f"W{l + 1}"] = ((2.0 * u - 1.0) * a).astype(np.float32).astype(np.float64).reshape(fout, fin)
+        p[f"b{l + 1}"] = np.zeros(fout)
+    return p
+
+
+# ---------------------------------------------------------------------------
+# Normalisation
+# ---------------------------------------------------------------------------
+
+def fit_norm(tensors, iters_list):
+    """Per-region mean and (population) standard deviation over the valid
+    cells of all training tensors, accumulated in FP64; returned as FP32."""
+    G = tensors[0].shape[2]
+    s = np.zeros(G)
+    q = np.zeros(G)
+    n = 0
+    for T, it in zip(tensors, iters_list):
+        R, I, _ = T.shape
+        valid = np.arange(I)[None, :] < np.asarray(it)[:, None]
+        x = T[valid].astype(np.float64)
+        s += x.sum(0)
+        n += x.shape[0]
+    mu = s / n
+    for T, it in zip(tensors, iters_list):
+        R, I, _ = T.shape
+        valid = np.arange(I)[None, :] < np.asarray(it)[:, None]
+        x = T[valid].astype(np.float64)
+        q += ((x - mu) ** 2).sum(0)
+    sd = np.sqrt(q / n)
+    sd[sd == 0] = 1.0
+    return mu.astype(np.float32), sd.astype(np.float32)
+
+
+def normalize(T, mu, sd):
+    """x = ((float)T - mu) * (1 / sd), in FP32 as the GPU does."""
+    inv = (np.float32(1.0) / np.asarray(sd, np.float32)).astype(np.float32)
+    return ((T.astype(np.float32) - np.asarray(mu, np.float32)) * inv).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Forward / backward
+# ---------------------------------------------------------------------------
+
+def forward(p: dict, X: np.ndarray, bf16: bool = False):
+    """X [B, 64] -> (pre-activations z_l, activations a_l); a_0 = X."""
+    rnd = to_bf16 if bf16 else (lambda v: np.asarray(v, np.float64))
+    a = [np.asarray(X, np.float64)]
+    z = []
+    for l in range(N_LAYERS):
+        W, b = p[f"W{l + 1}"], p[f"b{l + 1}"]
+        zl = rnd(a[-1]) @ rnd(W).T + b
+        if bf16:
+            zl = zl.astype(np.float32).astype(np.float64)
+        z.append(zl)
+        a.append(np.maximum(zl, 0.0) if l < N_LAYERS - 1 else zl)
+    return z, a
+
+
+def loss_and_grads(p: dict, X: np.ndarray, bf16: bool = False):
+    """Mean squared reconstruction error and its gradients."""
+    rnd = to_bf16 if bf16 else (lambda v: np.asarray(v, np.float64))
+    X = np.asarray(X, np.float64)
+    B = X.shape[0]
+    z, a = forward(p, X, bf16)
+    y = a[-1]
+    diff = y - X
+    loss = float((diff ** 2).sum() / (B * DIMS[-1]))
+    g = {}
+    d = 2.0 * diff / (B * DIMS[-1])                  # dL/dz_4
+    for l in range(N_LAYERS - 1, -1, -1):
+        W = p[f"W{l + 1}"]
+        g[f"W{l + 1}"] = rnd(d).T @ rnd(a[l])
+        g[f"b{l + 1}"] = d.sum(0)
+        if l > 0:
+            da = rnd(d) @ rnd(W)
+            d = da * (z[l - 1] > 0)
+    return loss, g
+
+
+def adam_update(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (t counts from 1) on FP64 copies of the parameters."""
+    for k in p:
+        m[k] = b1 * m[k] + (1 - b1) * g[k]
+        v[k] = b2 * v[k] + (1 - b2) * g[k] * g[k]
+        mh = m[k] / (1 - b1 ** t)
+        vh = v[k] / (1 - b2 ** t)
+        p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
+    return p, m, v
+
+
+def rank_scores(p: dict, T: np.ndarray, iters, mu, sd, bf16: bool = False) -> np.ndarray:
+    """score[r] = max_g mean_{i < iters[r]} (y - x)^2 over the rank's profile."""
+    R, I, G = T.shape
+    X = normalize(T, mu, sd)
+    out = np.zeros(R)
+    for r in range(R):
+        n = int(min(iters[r], I))
+        if n == 0:
+            continue
+        _, a = forward(p, X[r, :n], bf16)
+        e = (a[-1] - X[r, :n].astype(np.float64)) ** 2
+        out[r] = e.mean(0).max()
+    return out

@@ -1,0 +1,135 @@
+"""Pins for the autoencoder oracle (CPU): finite differences, closed forms and
+the bfloat16 rounding rule."""
+import numpy as np
+import pytest
+
+from oracle import ae
+
+
+def _rand_params(seed=0, scale=0.3):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for l in range(4):
+        fin, fout = ae.DIMS[l], ae.DIMS[l + 1]
+        p[f"W{l + 1}"] = rng.normal(0, scale, (fout, fin))
+        p[f"b{l + 1}"] = rng.normal(0, 0.1, fout)
+    return p
+
+
+def test_finite_differences_fp64():
+    """Central differences in FP64 agree with the analytic gradients."""
+    rng = np.random.default_rng(1)
+    p = _rand_params(1)
+    X = rng.normal(0, 1, (7, 64))
+    _, g = ae.loss_and_grads(p, X)
+    h = 1e-4   # central differences: truncation O(h^2), roundoff O(eps*L/h)
+    for k in p:
+        flat = p[k].reshape(-1)
+        for idx in rng.choice(flat.size, 6, replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = ae.loss_and_grads(p, X)
+            flat[idx] = old - h
+            lm, _ = ae.loss_and_grads(p, X)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[k].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * abs(an) + 1e-10, (k, idx, fd, an)
+
+
+def test_constant_output_closed_form():
+    """All weights zero: the output is b4, the loss is mean((b4 - x)^2) and
+    dL/db4 = 2 * mean over rows of (b4 - x) / 64."""
+    rng = np.random.default_rng(2)
+    p = {f"W{l + 1}": np.zeros((ae.DIMS[l + 1], ae.DIMS[l])) for l in range(4)}
+    p.update({f"b{l + 1}": np.zeros(ae.DIMS[l + 1]) for l in range(4)})
+    c = rng.normal(0, 1, 64)
+    p["b4"] = c
+    X = rng.normal(0, 1, (5, 64))
+    loss, g = ae.loss_and_grads(p, X)
+    assert loss == pytest.approx(((c - X) ** 2).mean(), rel=1e-14)
+    np.testing.assert_allclose(g["b4"], 2 * (c - X).sum(0) / (5 * 64), rtol=1e-13)
+    for k in ("W1", "W2", "W3", "b1", "b2", "b3"):
+        assert not g[k].any()
+    np.testing.assert_allclose(g["W4"], 0.0)     # hidden activations are zero
+
+
+def test_first_adam_step_is_sign_step():
+    p = {"w": np.array([1.0, -2.0, 3.0])}
+    g = {"w": np.array([0.5, -4.0, 1e-3])}
+    m = {"w": np.zeros(3)}
+    v = {"w": np.zeros(3)}
+    p, m, v = ae.adam_update(p, g, m, v, 1, lr=0.01)
+    np.testing.assert_allclose(p["w"], [1.0 - 0.01, -2.0 + 0.01, 3.0 - 0.01], rtol=1e-6)
+
+
+def test_bf16_rounding_ties_to_even():
+    one = 1.0
+    vals = np.array([one, one + 2 ** -8, one + 3 * 2 ** -8, one + 2 ** -7, -(one + 2 ** -8),
+                     3.140625, 1e-30], np.float64)
+    r = ae.to_bf16(vals)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                       # midpoint -> even mantissa
+    assert r[2] == one + 2 ** -6             # midpoint -> even mantissa
+    assert r[3] == one + 2 ** -7             # representable
+    assert r[4] == -1.0
+    assert r[5] == 3.140625                  # 7 mantissa bits: exact
+    assert abs(r[6] - 1e-30) / 1e-30 < 2 ** -8
+
+
+def test_xavier_init_bounds_and_moments():
+    p = ae.init_params(123)
+    for l in range(4):
+        W = p[f"W{l + 1}"]
+        a = np.sqrt(6.0 / (ae.DIMS[l] + ae.DIMS[l + 1]))
+        assert W.shape == (ae.DIMS[l + 1], ae.DIMS[l])
+        assert np.abs(W).max() <= a
+        assert abs(W.mean()) < 0.05 * a
+        assert abs(W.var() / (a * a / 3) - 1) < 0.1
+    q = ae.init_params(123)
+    assert all(np.array_equal(p[k], q[k]) for k in p)
+    assert not np.array_equal(p["W1"], ae.init_params(124)["W1"])
+
+
+def test_training_reduces_loss():
+    """Adam on low-rank data: the loss falls well below its starting value."""
+    rng = np.random.default_rng(3)
+    basis = rng.normal(0, 1, (4, 64))
+    X = rng.normal(0, 1, (512, 4)) @ basis
+    p = ae.init_params(7)
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(v) for k, v in p.items()}
+    l0, _ = ae.loss_and_grads(p, X)
+    for t in range(1, 301):
+        batch = X[rng.choice(512, 64, replace=False)]
+        _, g = ae.loss_and_grads(p, batch)
+        p, m, v = ae.adam_update(p, g, m, v, t, lr=3e-3)
+    l1, _ = ae.loss_and_grads(p, X)
+    assert l1 < 0.3 * l0
+
+
+def test_bf16_mode_close_to_fp64():
+    rng = np.random.default_rng(4)
+    p = ae.init_params(5)
+    X = rng.normal(0, 1, (64, 64))
+    l64, g64 = ae.loss_and_grads(p, X)
+    l16, g16 = ae.loss_and_grads(p, X, bf16=True)
+    assert abs(l16 - l64) / l64 < 2e-2
+    for k in g64:
+        if k.startswith("W"):
+            rel = np.linalg.norm(g16[k] - g64[k]) / np.linalg.norm(g64[k])
+            assert rel < 5e-2, k
+
+
+def test_fit_norm_and_scores():
+    rng = np.random.default_rng(5)
+    T = rng.integers(0, 1000, (6, 5, 64)).astype(np.int64)
+    it = np.array([5, 5, 3, 0, 5, 1])
+    mu, sd = ae.fit_norm([T], [it])
+    valid = np.arange(5)[None, :] < it[:, None]
+    x = T[valid].astype(np.float64)
+    np.testing.assert_allclose(mu, x.mean(0), rtol=1e-6)
+    np.testing.assert_allclose(sd, x.std(0), rtol=1e-6)
+    p = ae.init_params(1)
+    s = ae.rank_scores(p, T, it, mu, sd)
+    assert s[3] == 0.0 and (s[[0, 1, 2, 4, 5]] > 0).all()

@@ -1,0 +1,161 @@
+"""Parity at the benchmark's sizes, on GPU-generated traces.
+
+* 100,000 ranks (the benchmark workload, same launch configuration): sampled
+  ranks are copied back and checked bit-exact against the oracle (tensor rows,
+  exclusive / inclusive rows, iteration counts, outside time, spans, rank
+  totals); sampled tensor columns are checked against the oracle's
+  per-iteration statistics; statistics that hold at any size are checked on
+  the full outputs.
+* 3,000 ranks with the 10,000-rank workload's shape: everything, including the
+  exact outlier scan, against the oracle on the whole batch.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+
+    from paper_2605_03561_amd import gpu_synth, ta
+    return torch, gpu_synth, ta
+
+
+def test_gpu_generator_invariants(mods, oracle):
+    torch, gpu_synth, ta = mods
+    w = gpu_synth.timeline_on_gpu(seed=11, n_ranks=300, median_len=3000, min_len=200,
+                                  max_len=20000, n_nodes=600, depth_max=10, n_iters=50,
+                                  n_regions=64, inject_frac=0.05)
+    s = gpu_synth.sample_ranks_to_host(w, np.arange(300))
+    assert np.array_equal(s.offsets, w.offsets_host)
+    for r in range(300):
+        t = s.ts[s.offsets[r]:s.offsets[r + 1]]
+        assert (np.diff(t) >= 0).all()
+        assert (s.ctx[s.offsets[r]:s.offsets[r + 1]] == w.marker).sum() == 50
+    assert s.ctx.min() >= 0 and s.ctx.max() < 600
+    st, T, it, out, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker, s.regions, 50)
+    assert st == 0 and (it == 50).all()
+    assert np.array_equal(T.sum((1, 2)) + out, span)
+    # planted mean duration per region (rank factor ~ 1): a loose statistical check
+    mean_rg = T[w.anchored].mean((0, 1))
+    ratio = mean_rg / w.mu
+    assert 0.85 < np.median(ratio) < 1.15
+
+
+@pytest.fixture(scope="module")
+def c3(mods):
+    torch, gpu_synth, ta = mods
+    import bench
+    cfg = bench.WORKLOADS["c3"]
+    print("[fullsize] generating the 100k-rank workload", flush=True)
+    w = gpu_synth.timeline_on_gpu(seed=0, **cfg)
+    h = ta.Handle(0)
+    h.set_tree(w.parent)
+    h.set_regions(w.marker, w.regions)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx)
+    seg = h.attribute_segment(tr, cfg["n_iters"])
+    h.sync_status()
+    yield w, h, seg, cfg
+    h.close()
+    del seg, w
+    torch.cuda.empty_cache()
+
+
+def _sample(w, k=40):
+    R = len(w.offsets_host) - 1
+    lens = np.diff(w.offsets_host)
+    picks = set(np.linspace(0, R - 1, k).round().astype(int).tolist())
+    picks |= {int(lens.argmax()), int(lens.argmin())}
+    picks |= set(np.nonzero(w.injected)[0][:4].tolist())
+    return np.array(sorted(picks))
+
+
+def test_c3_sampled_rank_parity(mods, oracle, c3):
+    torch, gpu_synth, ta = mods
+    w, h, seg, cfg = c3
+    ranks = _sample(w)
+    s = gpu_synth.sample_ranks_to_host(w, ranks)
+    st, ex, inc = oracle.attribute(s.offsets, s.ts, s.ctx, s.parent)
+    st2, T, it, out, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker, s.regions,
+                                           cfg["n_iters"])
+    assert st == st2 == 0
+    idx = torch.from_numpy(ranks).cuda()
+    g = {k: seg[k].index_select(0, idx).cpu().numpy() for k in seg}
+    assert np.array_equal(g["tensor"], T)
+    assert np.array_equal(g["excl"], ex)
+    assert np.array_equal(g["incl"], inc)
+    assert np.array_equal(g["iters_found"], it)
+    assert np.array_equal(g["outside"], out)
+    assert np.array_equal(g["span"], span)
+    assert np.array_equal(g["rank_sum"], T.sum(1))
+
+
+def test_c3_statistics(mods, oracle, c3):
+    torch, gpu_synth, ta = mods
+    w, h, seg, cfg = c3
+    I, G = cfg["n_iters"], cfg["n_regions"]
+    o = h.imbalance(seg["tensor"], seg["iters_found"], seg["rank_sum"], seg["rank_sumsq"],
+                    seg["span"])
+    go = {k: v.cpu().numpy() for k, v in o.items()}
+    it = seg["iters_found"].cpu().numpy()
+    rng = np.random.default_rng(0)
+    for i, gg in zip(rng.integers(0, I, 8), rng.integers(0, G, 8)):
+        col = seg["tensor"][:, int(i), int(gg)].contiguous().cpu().numpy()
+        # the column alone, as a one-iteration one-region tensor
+        st, ref = oracle.imbalance(col.reshape(-1, 1, 1), (it > i).astype(np.int32))
+        assert go["mean"][i, gg] == ref["mean"][0, 0]
+        assert go["max_minus_mean"][i, gg] == ref["max_minus_mean"][0, 0]
+        assert go["min"][i, gg] == ref["min"][0, 0] and go["max"][i, gg] == ref["max"][0, 0]
+        assert go["std"][i, gg] == pytest.approx(ref["std"][0, 0], rel=1e-15)
+    # properties that hold at any size
+    assert (go["savings_per_iter"] >= 0).all()
+    assert abs(go["share"].sum() - 1.0) < 1e-12
+    ratio = go["avg_mean"] / go["avg_max"]
+    assert (go["balance_ratio"] >= ratio - 1e-12).all()
+    S = seg["rank_sum"].cpu().numpy()
+    np.testing.assert_allclose(go["balance_ratio"], S.mean(0) / S.max(0), rtol=1e-12)
+    ol = h.outliers(seg["tensor"], seg["iters_found"], region=True)
+    score = ol["rank_score"].cpu().numpy()
+    reg = ol["region_score"].cpu().numpy()
+    flag = ol["rank_flag"].cpu().numpy()
+    assert np.array_equal(score, np.abs(reg).max(1))
+    assert np.array_equal(flag, (score > 3.5).astype(np.uint8))
+    assert int(ol["n_flagged"].item()) == int(flag.sum())
+    # the scan finds most of the injected slow ranks (sanity, not parity)
+    assert flag[w.injected].mean() > 0.5
+
+
+def test_c2_shape_full_parity(mods, oracle):
+    torch, gpu_synth, ta = mods
+    w = gpu_synth.timeline_on_gpu(seed=4, n_ranks=3000, median_len=6000, min_len=1000,
+                                  max_len=60000, n_nodes=1000, depth_max=12, n_iters=300,
+                                  n_regions=32, inject_frac=0.02)
+    h = ta.Handle(0)
+    h.set_tree(w.parent)
+    h.set_regions(w.marker, w.regions)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx)
+    seg = h.attribute_segment(tr, 300)
+    h.sync_status()
+    s = gpu_synth.sample_ranks_to_host(w, np.arange(3000))
+    st, ex, inc = oracle.attribute(s.offsets, s.ts, s.ctx, s.parent)
+    st2, T, it, out, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker, s.regions,
+                                           300)
+    assert st == st2 == 0
+    assert np.array_equal(seg["tensor"].cpu().numpy(), T)
+    assert np.array_equal(seg["excl"].cpu().numpy(), ex)
+    assert np.array_equal(seg["incl"].cpu().numpy(), inc)
+    o = h.imbalance(seg["tensor"], seg["iters_found"], seg["rank_sum"], seg["rank_sumsq"],
+                    seg["span"])
+    st, ref = oracle.imbalance(T, it, span=span)
+    for k in ref:
+        a, b = o[k].cpu().numpy(), ref[k]
+        assert np.array_equal(np.isnan(a), np.isnan(b))
+        np.testing.assert_allclose(a, b, rtol=1e-12)
+    for mode in (0, 1):
+        ol = h.outliers(seg["tensor"], seg["iters_found"], mode=mode, region=True)
+        st, score, flag, nf, reg = oracle.outliers(T, it, mode=mode)
+        assert np.array_equal(ol["region_score"].cpu().numpy(), reg)
+        assert np.array_equal(ol["rank_flag"].cpu().numpy(), flag)
+    h.close()
