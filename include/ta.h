@@ -226,6 +226,46 @@ ta_status ta_topology_aggregate(ta_handle h, const double *rank_score, const uin
  * into *len.  Host-only, synchronous. */
 ta_status ta_callpath(ta_handle h, int32_t leaf, int32_t *path_host, int32_t cap, int32_t *len);
 
+/* Batch plan: the whole batch in one HIP graph launch.
+ * ta_plan_create orders the ranks longest first (so the longest traces start
+ * first and the tail is short), picks the launch shape of the fused pass
+ * (events per thread per tile, streaming loads, one workgroup per rank or a
+ * persistent grid) and captures the fused pass -- optionally followed by the
+ * imbalance and outlier stages -- into a graph over the buffers given here.
+ *   autotune 0: the default shape; 1: time every candidate shape on this
+ *   batch (each produces identical results) and keep the fastest; 2: as 1, but
+ *   reuse the choice stored in the JSON file named by the TA_AUTOTUNE_CACHE
+ *   environment variable when it holds this batch shape (and store new ones).
+ * offsets_host is a host copy of t->offsets.  The plan keeps its own
+ * workspace; the traces and every output buffer must stay allocated while
+ * the plan is used.  A plan must be destroyed before its handle. */
+typedef struct ta_plan_s *ta_plan;
+typedef struct {
+  int32_t n_iters;
+  ta_seg_out seg;            /* outputs of the fused pass */
+  int32_t with_imbalance;    /* nonzero: add ta_imbalance on seg's outputs */
+  ta_imbalance_out imb;
+  int32_t ddof;
+  double t_app_ns;
+  int32_t with_outliers;     /* nonzero: add ta_outliers on seg's tensor */
+  int32_t outlier_mode, outlier_kind;
+  double tau;
+  double *rank_score;
+  uint8_t *rank_flag;
+  int64_t *n_flagged;
+  double *region_score;
+  int32_t autotune;
+} ta_batch_desc;
+
+ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets_host,
+                         const ta_batch_desc *d, ta_plan *out, void *stream);
+/* Replays the captured graph on `stream`. */
+ta_status ta_plan_launch(ta_plan p, void *stream);
+/* The chosen launch shape and its measured time (ms; 0 when not tuned). */
+ta_status ta_plan_info(ta_plan p, int32_t *events_per_thread, int32_t *nontemporal,
+                       int32_t *wgs_per_cu, float *tuned_ms);
+ta_status ta_plan_destroy(ta_plan p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,7 @@ extern "C" {
 typedef struct {
   int64_t n_ranks;
   int32_t n_iters;
-  int32_t n_regions;        /* G <= 63 */
+  int32_t n_regions;        /* G <= 127 */
   int32_t marker;           /* node id of the iteration marker */
   int32_t root;             /* node id used for the closing event */
   uint64_t seed;

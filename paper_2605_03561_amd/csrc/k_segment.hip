@@ -21,9 +21,87 @@ namespace ta {
 namespace {
 
 constexpr int NT = 256;
-constexpr int EPT = 4;
-constexpr int TILE = NT * EPT;
 constexpr int NWAVE = NT / 64;
+
+// The events of one tile held by one thread, plus the two halo values the
+// wave edges need (the timestamp after lane 63's last event and the context
+// before lane 0's first event).
+template <int EPT>
+struct Tile {
+  int64_t ts[EPT];
+  int32_t cv[EPT];
+  int64_t halo_ts;
+  int32_t halo_ctx;
+};
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+
+template <bool NTMP, class T>
+__device__ inline T ld(const T *p) {
+  if constexpr (NTMP) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <bool NTMP, class T>
+__device__ inline void st(T *p, T v) {
+  if constexpr (NTMP) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+__device__ inline int64_t join64(int lo, int hi) {
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Load the EPT events starting at global index c0 (a multiple of EPT, so the
+// vector loads are aligned) if any of them belongs to the rank [b, e).
+template <int EPT, bool NTMP>
+__device__ inline void load_tile(Tile<EPT> &t, const int64_t *__restrict__ ts,
+                                 const int32_t *__restrict__ ctx, int64_t E, int64_t c0,
+                                 int64_t b, int64_t e, int lane) {
+#pragma unroll
+  for (int j = 0; j < EPT; j++) {
+    t.ts[j] = 0;
+    t.cv[j] = 0;
+  }
+  if ((c0 + EPT > b) && (c0 < e)) {
+    if (c0 + EPT <= E) {
+      const v4i *pt = reinterpret_cast<const v4i *>(ts + c0);
+#pragma unroll
+      for (int q = 0; q < EPT / 2; q++) {
+        const v4i x = ld<NTMP>(pt + q);
+        t.ts[2 * q] = join64(x.x, x.y);
+        t.ts[2 * q + 1] = join64(x.z, x.w);
+      }
+      if constexpr (EPT == 2) {
+        const v2i y = ld<NTMP>(reinterpret_cast<const v2i *>(ctx + c0));
+        t.cv[0] = y.x;
+        t.cv[1] = y.y;
+      } else {
+        const v4i *pc = reinterpret_cast<const v4i *>(ctx + c0);
+#pragma unroll
+        for (int q = 0; q < EPT / 4; q++) {
+          const v4i y = ld<NTMP>(pc + q);
+          t.cv[4 * q] = y.x;
+          t.cv[4 * q + 1] = y.y;
+          t.cv[4 * q + 2] = y.z;
+          t.cv[4 * q + 3] = y.w;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < EPT; j++)
+        if (c0 + j < E) {
+          t.ts[j] = ts[c0 + j];
+          t.cv[j] = ctx[c0 + j];
+        }
+    }
+  }
+  t.halo_ts = 0;
+  t.halo_ctx = -1;
+  if (lane == 63 && c0 + EPT < e) t.halo_ts = ts[c0 + EPT];
+  if (lane == 0 && c0 - 1 >= b && c0 - 1 < e) t.halo_ctx = ctx[c0 - 1];
+}
 
 __device__ inline int wave_incl_scan_i32(int v, int lane) {
 #pragma unroll
@@ -57,8 +135,9 @@ __device__ inline void acc_sq(uint64_t &lo, uint64_t &hi, int64_t v) {
   hi = (uint64_t)(s >> 64);
 }
 
-template <bool ATTR, bool SEG>
+template <bool ATTR, bool SEG, int EPT, bool NTMP>
 __global__ __launch_bounds__(NT) void seg_kernel(SegArgs a) {
+  constexpr int TILE = NT * EPT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = a.N, G = a.G, I = a.I, W = a.W;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -115,56 +194,29 @@ __global__ __launch_bounds__(NT) void seg_kernel(SegArgs a) {
         int slot = (row & (W - 1)) * G + gme;
         int64_t v = ring[slot];
         ring[slot] = 0;
-        trow[(int64_t)row * G + gme] = v;
+        st<NTMP>(&trow[(int64_t)row * G + gme], v);
         S += v;
         acc_sq(Qlo, Qhi, v);
       }
     };
 
-    for (int64_t t0 = b & ~(int64_t)(TILE - 1); t0 < e; t0 += TILE) {
+    Tile<EPT> cur, nxt_tile;
+    int64_t t0 = b & ~(int64_t)(TILE - 1);
+    if (t0 < e) load_tile<EPT, NTMP>(cur, a.ts, a.ctx, a.E, t0 + (int64_t)tid * EPT, b, e, lane);
+    for (; t0 < e; t0 += TILE) {
       const int64_t c0 = t0 + (int64_t)tid * EPT;
-      int64_t tsv[EPT];
-      int32_t cv[EPT];
-#pragma unroll
-      for (int j = 0; j < EPT; j++) {
-        tsv[j] = 0;
-        cv[j] = 0;
-      }
-      const bool any_in = (c0 + EPT > b) && (c0 < e);
-      if (any_in) {
-        if (c0 + EPT <= a.E) {
-          const int4 *pt = reinterpret_cast<const int4 *>(a.ts + c0);
-          int4 x0 = pt[0], x1 = pt[1];
-          int4 y = *reinterpret_cast<const int4 *>(a.ctx + c0);
-          tsv[0] = (int64_t)(((uint64_t)(uint32_t)x0.y << 32) | (uint32_t)x0.x);
-          tsv[1] = (int64_t)(((uint64_t)(uint32_t)x0.w << 32) | (uint32_t)x0.z);
-          tsv[2] = (int64_t)(((uint64_t)(uint32_t)x1.y << 32) | (uint32_t)x1.x);
-          tsv[3] = (int64_t)(((uint64_t)(uint32_t)x1.w << 32) | (uint32_t)x1.z);
-          cv[0] = y.x;
-          cv[1] = y.y;
-          cv[2] = y.z;
-          cv[3] = y.w;
-        } else {
-#pragma unroll
-          for (int j = 0; j < EPT; j++)
-            if (c0 + j < a.E) {
-              tsv[j] = a.ts[c0 + j];
-              cv[j] = a.ctx[c0 + j];
-            }
-        }
-      }
-      // Timestamp after my last event (lane + 1's first, or a load at the
+      // Issue the next tile's loads now; they complete while this tile is
+      // processed (barriers wait only for LDS traffic).
+      if (t0 + TILE < e)
+        load_tile<EPT, NTMP>(nxt_tile, a.ts, a.ctx, a.E, c0 + TILE, b, e, lane);
+      const int64_t *tsv = cur.ts;
+      const int32_t *cv = cur.cv;
+      // Timestamp after my last event (lane + 1's first, or the halo at the
       // wave edge) and context before my first event.
       int64_t nxt = __shfl_down(tsv[0], 1, 64);
-      if (lane == 63) {
-        int64_t k = c0 + EPT;
-        nxt = (k < e) ? a.ts[k] : 0;
-      }
+      if (lane == 63) nxt = cur.halo_ts;
       int32_t pc = __shfl_up(cv[EPT - 1], 1, 64);
-      if (lane == 0) {
-        int64_t k = c0 - 1;
-        pc = (k >= b && k < e) ? a.ctx[k] : -1;
-      }
+      if (lane == 0) pc = cur.halo_ctx;
       int prev_in = 0;
       if (c0 - 1 >= b && c0 - 1 < e && (uint32_t)pc < (uint32_t)N)
         prev_in = (info[pc] & INFO_MARKER_BIT) ? 1 : 0;
@@ -270,6 +322,7 @@ __global__ __launch_bounds__(NT) void seg_kernel(SegArgs a) {
         }
       }
       carry = it_last;
+      cur = nxt_tile;
     }
 
     // ---- rank epilogue --------------------------------------------------
@@ -283,7 +336,7 @@ __global__ __launch_bounds__(NT) void seg_kernel(SegArgs a) {
             v = ring[slot];
             ring[slot] = 0;
           }
-          trow[(int64_t)row * G + gme] = v;
+          st<NTMP>(&trow[(int64_t)row * G + gme], v);
           S += v;
           acc_sq(Qlo, Qhi, v);
         }
@@ -344,8 +397,8 @@ __global__ __launch_bounds__(NT) void seg_kernel(SegArgs a) {
       for (int v = tid; v < N; v += NT) {
         const int2 tt = a.tin_tout[v];
         const int64_t pa = hist[tt.x];
-        if (a.excl) a.excl[r * N + v] = hist[tt.x + 1] - pa;
-        if (a.incl) a.incl[r * N + v] = hist[tt.y] - pa;
+        if (a.excl) st<NTMP>(&a.excl[r * N + v], hist[tt.x + 1] - pa);
+        if (a.incl) st<NTMP>(&a.incl[r * N + v], hist[tt.y] - pa);
       }
       __syncthreads();
       for (int v = tid; v <= N; v += NT) hist[v] = 0;
@@ -380,29 +433,40 @@ size_t segment_lds_bytes(int N, int G, bool attr, bool seg, int *W, int *log2W) 
   return fixed + ring;
 }
 
-template <bool A, bool S>
-void allow_big_lds() {
-  static bool done = false;
-  if (!done) {
-    hipFuncSetAttribute(reinterpret_cast<const void *>(&seg_kernel<A, S>),
+namespace {
+
+template <bool A, bool S, int EPT, bool NTMP>
+hipError_t launch_variant(const SegArgs &a, int grid, size_t lds, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute(reinterpret_cast<const void *>(&seg_kernel<A, S, EPT, NTMP>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    done = true;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((seg_kernel<A, S, EPT, NTMP>), dim3(grid), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <bool A, bool S>
+hipError_t launch_ept(const SegArgs &a, const SegShape &sh, int grid, size_t lds, hipStream_t s) {
+  switch (sh.ept * 2 + (sh.nontemporal ? 1 : 0)) {
+    case 4: return launch_variant<A, S, 2, false>(a, grid, lds, s);
+    case 5: return launch_variant<A, S, 2, true>(a, grid, lds, s);
+    case 8: return launch_variant<A, S, 4, false>(a, grid, lds, s);
+    case 9: return launch_variant<A, S, 4, true>(a, grid, lds, s);
+    case 16: return launch_variant<A, S, 8, false>(a, grid, lds, s);
+    case 17: return launch_variant<A, S, 8, true>(a, grid, lds, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_segment(const SegArgs &a, bool attr, bool seg, int grid, size_t lds,
-                          hipStream_t s) {
-  allow_big_lds<true, true>();
-  allow_big_lds<true, false>();
-  allow_big_lds<false, true>();
-  if (attr && seg) {
-    hipLaunchKernelGGL((seg_kernel<true, true>), dim3(grid), dim3(NT), lds, s, a);
-  } else if (attr) {
-    hipLaunchKernelGGL((seg_kernel<true, false>), dim3(grid), dim3(NT), lds, s, a);
-  } else {
-    hipLaunchKernelGGL((seg_kernel<false, true>), dim3(grid), dim3(NT), lds, s, a);
-  }
-  return hipGetLastError();
+}  // namespace
+
+hipError_t launch_segment(const SegArgs &a, bool attr, bool seg, const SegShape &sh, int grid,
+                          size_t lds, hipStream_t s) {
+  if (attr && seg) return launch_ept<true, true>(a, sh, grid, lds, s);
+  if (attr) return launch_ept<true, false>(a, sh, grid, lds, s);
+  return launch_ept<false, true>(a, sh, grid, lds, s);
 }
 
 }  // namespace ta

@@ -30,14 +30,6 @@ __device__ inline double u01(uint64_t x) {
 
 enum : uint64_t { W_GAMMA = 1, W_PERM = 2, W_FILL = 3, W_EXTRA = 4, W_PICK = 5, W_APICK = 6 };
 
-__device__ inline int64_t wave_incl_scan(int64_t v, int lane) {
-  for (int d = 1; d < 64; d <<= 1) {
-    int64_t t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
-  }
-  return v;
-}
-
 // Stratified-jittered sample time j of n inside an iteration of length Ti.
 __device__ inline int64_t extra_time(uint64_t seed, int64_t r, int i, int j, int n, int64_t Ti) {
   if (Ti <= 0) return 0;
@@ -48,11 +40,13 @@ __device__ inline int64_t extra_time(uint64_t seed, int64_t r, int i, int j, int
   return x;
 }
 
-__global__ __launch_bounds__(64) void gen_kernel(tas_params p) {
-  __shared__ int64_t start[66];
-  __shared__ int kind[64];
-  __shared__ int64_t dur[64];
-  __shared__ uint64_t keys[64];
+constexpr int GT = 128;  // threads per rank; one per segment (G + 1 <= 128)
+
+__global__ __launch_bounds__(GT) void gen_kernel(tas_params p) {
+  __shared__ int64_t start[GT + 2];
+  __shared__ int kind[GT];
+  __shared__ int64_t dur[GT];
+  __shared__ uint64_t keys[GT];
   const int lane = threadIdx.x;
   const int64_t r = blockIdx.x;
   const int G = p.n_regions, I = p.n_iters;
@@ -73,6 +67,8 @@ __global__ __launch_bounds__(64) void gen_kernel(tas_params p) {
       dur[G] = (int64_t)llrint(-p.filler_mean_ns * log(u01(draw(seed, r, i, 0, W_FILL))));
     }
     __syncthreads();
+    // Random order of the regions: each region's position is the number of
+    // smaller keys; the filler segment comes last.
     if (lane < G) {
       const uint64_t k = keys[lane];
       int pos = 0;
@@ -85,19 +81,23 @@ __global__ __launch_bounds__(64) void gen_kernel(tas_params p) {
       kind[G] = G;
     }
     __syncthreads();
-    const int64_t len = lane <= G ? dur[kind[lane]] : 0;
-    const int64_t inc = wave_incl_scan(len, lane);
-    const int64_t Ti = __shfl(inc, G, 64);
-    if (lane <= G) start[lane] = t + inc - len;
-    if (lane == 0) start[G + 1] = t + Ti;
+    if (lane == 0) {
+      int64_t x = t;
+      for (int s = 0; s <= G; s++) {
+        start[s] = x;
+        x += dur[kind[s]];
+      }
+      start[G + 1] = x;
+    }
     __syncthreads();
+    const int64_t Ti = start[G + 1] - t;
 
     const int64_t base = off + (int64_t)i * b;
     if (lane == 0) {
       p.ts[base] = t;
       p.ctx[base] = p.marker;
     }
-    for (int j = lane; j < n_extra; j += 64) {
+    for (int j = lane; j < n_extra; j += GT) {
       const int64_t tj = t + extra_time(seed, r, i, j, n_extra, Ti);
       int lo = 0, hi = G;  // last segment whose start is <= tj
       while (lo < hi) {
@@ -138,11 +138,11 @@ __global__ __launch_bounds__(64) void gen_kernel(tas_params p) {
 }  // namespace
 
 extern "C" int32_t tas_generate(const tas_params *p, void *stream) {
-  if (!p || p->n_ranks < 0 || p->n_iters < 1 || p->n_regions < 1 || p->n_regions > 63) return 1;
+  if (!p || p->n_ranks < 0 || p->n_iters < 1 || p->n_regions < 1 || p->n_regions > 127) return 1;
   if (p->n_ranks == 0) return 0;
   if (!p->offsets || !p->events_per_iter || !p->t0 || !p->scale || !p->mu || !p->pool ||
       !p->pool_off || !p->ts || !p->ctx)
     return 1;
-  hipLaunchKernelGGL(gen_kernel, dim3((unsigned)p->n_ranks), dim3(64), 0, (hipStream_t)stream, *p);
+  hipLaunchKernelGGL(gen_kernel, dim3((unsigned)p->n_ranks), dim3(GT), 0, (hipStream_t)stream, *p);
   return hipGetLastError() == hipSuccess ? 0 : 8;
 }

@@ -1,6 +1,7 @@
 // ta_api.hip -- host side of the C ABI: handle, call-path tables, argument
 // validation, workspace and kernel launches.  No exception crosses the ABI.
 #include <algorithm>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -158,8 +159,15 @@ ta_status check_traces(ta_handle h, const ta_traces *t) {
   return TA_OK;
 }
 
-ta_status run_segment(ta_handle h, const ta_traces *t, int32_t n_iters, const ta_seg_out *o,
-                      void *stream, bool want_attr, bool want_seg) {
+struct SegLaunch {
+  ta::SegArgs a{};
+  size_t lds = 0;
+  bool attr = false, seg = false;
+};
+
+// Validate a fused-pass request and fill the kernel arguments (no launch).
+ta_status prepare_segment(ta_handle h, const ta_traces *t, int32_t n_iters, const ta_seg_out *o,
+                          bool want_attr, bool want_seg, SegLaunch *L) {
   if (!h) return TA_ERR_INVALID_ARG;
   ta_status st = check_traces(h, t);
   if (st) return st;
@@ -182,12 +190,10 @@ ta_status run_segment(ta_handle h, const ta_traces *t, int32_t n_iters, const ta
                         o->excl, o->incl};
   for (const void *p : ptrs)
     if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "output not 16-byte aligned");
-  if (t->n_ranks == 0) return TA_OK;
-
   int W = 2, lw = 1;
-  const size_t lds = ta::segment_lds_bytes(h->N, seg ? h->G : 1, attr, seg, &W, &lw);
-  if (lds > 160 * 1024) return fail(h, TA_ERR_SIZE_OVERFLOW, "call-path tables exceed LDS");
-  ta::SegArgs a{};
+  L->lds = ta::segment_lds_bytes(h->N, seg ? h->G : 1, attr, seg, &W, &lw);
+  if (L->lds > 160 * 1024) return fail(h, TA_ERR_SIZE_OVERFLOW, "call-path tables exceed LDS");
+  ta::SegArgs &a = L->a;
   a.off = t->offsets;
   a.ts = t->ts;
   a.ctx = t->ctx;
@@ -210,10 +216,141 @@ ta_status run_segment(ta_handle h, const ta_traces *t, int32_t n_iters, const ta
   a.excl = attr ? o->excl : nullptr;
   a.incl = attr ? o->incl : nullptr;
   a.err = h->d_err;
+  L->attr = attr;
+  L->seg = seg;
+  return TA_OK;
+}
+
+int device_cus(int device) {
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0)
+    n = 256;
+  return n;
+}
+
+int grid_for(const SegLaunch &L, const ta::SegShape &sh, int cus) {
+  const int64_t R = L.a.R;
+  if (sh.wgs_per_cu <= 0) return (int)std::min<int64_t>(R, (int64_t)1 << 30);
+  return (int)std::min<int64_t>(R, (int64_t)sh.wgs_per_cu * cus);
+}
+
+ta_status run_segment(ta_handle h, const ta_traces *t, int32_t n_iters, const ta_seg_out *o,
+                      void *stream, bool want_attr, bool want_seg) {
+  SegLaunch L;
+  ta_status st = prepare_segment(h, t, n_iters, o, want_attr, want_seg, &L);
+  if (st) return st;
+  if (t->n_ranks == 0) return TA_OK;
   DeviceGuard dg(h->device);
-  const int grid = (int)std::min<int64_t>(t->n_ranks, (int64_t)1 << 30);
-  hipError_t e = ta::launch_segment(a, attr, seg, grid, lds, (hipStream_t)stream);
+  const ta::SegShape sh{};
+  hipError_t e = ta::launch_segment(L.a, L.attr, L.seg, sh, grid_for(L, sh, device_cus(h->device)),
+                                    L.lds, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "segment kernel launch");
+  return TA_OK;
+}
+
+}  // namespace
+
+struct ta_plan_s {
+  ta_handle h = nullptr;
+  int32_t *d_order = nullptr;
+  void *ws = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ta::SegShape shape;
+  float tuned_ms = 0.f;
+};
+
+namespace {
+
+void plan_free(ta_plan p) {
+  if (!p) return;
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap) hipStreamDestroy(p->cap);
+  if (p->d_order) hipFree(p->d_order);
+  if (p->ws) hipFree(p->ws);
+  delete p;
+}
+
+// --- autotune cache: a flat JSON object {"<key>": {"ept": e, "nt": n, "wgs": w, "ms": t}, ...}
+struct CacheEntry {
+  std::string key;
+  int ept, nt, wgs;
+  double ms;
+};
+
+std::vector<CacheEntry> cache_read(const char *path) {
+  std::vector<CacheEntry> out;
+  FILE *f = path ? fopen(path, "r") : nullptr;
+  if (!f) return out;
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+  fclose(f);
+  size_t pos = 0;
+  while (true) {
+    size_t q0 = txt.find('"', pos);
+    if (q0 == std::string::npos) break;
+    size_t q1 = txt.find('"', q0 + 1);
+    size_t br = txt.find('{', q1);
+    size_t be = txt.find('}', br);
+    if (q1 == std::string::npos || br == std::string::npos || be == std::string::npos) break;
+    CacheEntry c{txt.substr(q0 + 1, q1 - q0 - 1), 0, 0, 0, 0.0};
+    std::string body = txt.substr(br, be - br + 1);
+    if (sscanf(body.c_str(), "{\"ept\": %d, \"nt\": %d, \"wgs\": %d, \"ms\": %lf}", &c.ept, &c.nt,
+               &c.wgs, &c.ms) == 4)
+      out.push_back(c);
+    pos = be + 1;
+  }
+  return out;
+}
+
+void cache_write(const char *path, const std::vector<CacheEntry> &es) {
+  if (!path) return;
+  std::string tmp = std::string(path) + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  for (size_t i = 0; i < es.size(); i++)
+    fprintf(f, "  \"%s\": {\"ept\": %d, \"nt\": %d, \"wgs\": %d, \"ms\": %.4f}%s\n", es[i].key.c_str(),
+            es[i].ept, es[i].nt, es[i].wgs, es[i].ms, i + 1 < es.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+  rename(tmp.c_str(), path);
+}
+
+std::string plan_key(ta_handle h, const SegLaunch &L) {
+  hipDeviceProp_t prop{};
+  hipGetDeviceProperties(&prop, h->device);
+  char k[512];
+  snprintf(k, sizeof k, "%s/cu%d/R%lld/E%lld/N%d/G%d/I%d/a%d/s%d", prop.gcnArchName,
+           prop.multiProcessorCount, (long long)L.a.R, (long long)L.a.E, L.a.N, L.a.G, L.a.I,
+           (int)L.attr, (int)L.seg);
+  for (char *c = k; *c; c++)
+    if (*c == '"' || *c == '\\') *c = '_';
+  return k;
+}
+
+ta_status time_shape(ta_handle h, const SegLaunch &L, const ta::SegShape &sh, int cus,
+                     hipStream_t s, float *ms) {
+  const int grid = grid_for(L, sh, cus);
+  hipEvent_t e0, e1;
+  TA_HIP(h, hipEventCreate(&e0));
+  TA_HIP(h, hipEventCreate(&e1));
+  hipError_t e = ta::launch_segment(L.a, L.attr, L.seg, sh, grid, L.lds, s);
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int k = 0; k < 2 && e == hipSuccess; k++)
+    e = ta::launch_segment(L.a, L.attr, L.seg, sh, grid, L.lds, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return hipfail(h, e, "autotune launch");
+  *ms = t / 2.f;
   return TA_OK;
 }
 
@@ -472,6 +609,197 @@ ta_status ta_topology_aggregate(ta_handle h, const double *rank_score, const uin
   a.err = h->d_err;
   hipError_t e = ta::launch_topology(a, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "topology launch");
+  return TA_OK;
+}
+
+ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets_host,
+                         const ta_batch_desc *d, ta_plan *out, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!out || !d || !offsets_host) return fail(h, TA_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  SegLaunch L;
+  ta_status st = prepare_segment(h, t, d->n_iters, &d->seg, true, true, &L);
+  if (st) return st;
+  if (t->n_ranks == 0) return fail(h, TA_ERR_INVALID_ARG, "empty batch");
+  if ((d->with_imbalance || d->with_outliers) && !L.seg)
+    return fail(h, TA_ERR_INVALID_ARG, "statistics stages need the tensor");
+  if (d->with_outliers) {
+    if ((d->outlier_mode != TA_SCAN_FULL && d->outlier_mode != TA_SCAN_TOTALS) ||
+        (d->outlier_kind != TA_SCORE_MAD && d->outlier_kind != TA_SCORE_Z) || !(d->tau >= 0.0))
+      return fail(h, TA_ERR_INVALID_ARG, "bad outlier mode, kind or tau");
+    if (!d->rank_score || !d->rank_flag) return fail(h, TA_ERR_INVALID_ARG, "rank_score/rank_flag NULL");
+    const void *ptrs[] = {d->rank_score, d->rank_flag, d->n_flagged, d->region_score};
+    for (const void *p : ptrs)
+      if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  }
+  if (d->with_imbalance) {
+    if (d->ddof < 0) return fail(h, TA_ERR_INVALID_ARG, "ddof < 0");
+    const void *ptrs[] = {d->imb.mean, d->imb.std, d->imb.max_minus_mean, d->imb.min, d->imb.max,
+                          d->imb.avg_mean, d->imb.avg_max, d->imb.savings_per_iter,
+                          d->imb.total_savings, d->imb.balance_ratio, d->imb.cv_across,
+                          d->imb.cv_within, d->imb.share, d->imb.potential_speedup};
+    for (const void *p : ptrs)
+      if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  }
+  const int64_t R = t->n_ranks;
+  for (int64_t r = 0; r < R; r++)
+    if (offsets_host[r + 1] < offsets_host[r]) return fail(h, TA_ERR_INVALID_ARG, "offsets_host decreasing");
+  DeviceGuard dg(h->device);
+  ta_plan p = new (std::nothrow) ta_plan_s();
+  if (!p) return TA_ERR_OOM;
+  p->h = h;
+  // Longest ranks first; ties by rank id.
+  std::vector<int32_t> order(R);
+  for (int64_t r = 0; r < R; r++) order[r] = (int32_t)r;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return offsets_host[x + 1] - offsets_host[x] > offsets_host[y + 1] - offsets_host[y];
+  });
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMalloc(&p->d_order, (size_t)R * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_order, order.data(), (size_t)R * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return hipfail(h, e, "plan order upload");
+  }
+  L.a.order = p->d_order;
+  const int I = d->n_iters, G = h->G;
+  size_t ws = 0;
+  if (d->with_imbalance)
+    ws = std::max(ws, ta::imbalance_ws_bytes(R, I, G, !d->seg.rank_sum || !d->seg.rank_sumsq));
+  if (d->with_outliers)
+    ws = std::max(ws, ta::outliers_ws_bytes(R, I, G, d->outlier_mode, d->outlier_kind));
+  if (ws && hipMalloc(&p->ws, ws) != hipSuccess) {
+    p->ws = nullptr;
+    plan_free(p);
+    return fail(h, TA_ERR_OOM, "plan workspace allocation failed");
+  }
+
+  // Launch shape: default, cached, or measured on this batch.
+  const int cus = device_cus(h->device);
+  const int occ = std::max(1, (int)((160 * 1024) / std::max<size_t>(L.lds, 1)));
+  ta::SegShape best{};
+  float best_ms = 0.f;
+  const char *cpath = getenv("TA_AUTOTUNE_CACHE");
+  const std::string key = plan_key(h, L);
+  std::vector<CacheEntry> cache = d->autotune == 2 ? cache_read(cpath) : std::vector<CacheEntry>{};
+  bool found = false;
+  for (const CacheEntry &c : cache)
+    if (c.key == key) {
+      best.ept = c.ept;
+      best.nontemporal = c.nt != 0;
+      best.wgs_per_cu = c.wgs;
+      best_ms = (float)c.ms;
+      found = true;
+    }
+  if (d->autotune && !found) {
+    bool have = false;
+    for (int ept : {2, 4, 8})
+      for (int nt : {0, 1})
+        for (int wgs : {0, occ}) {
+          ta::SegShape sh;
+          sh.ept = ept;
+          sh.nontemporal = nt != 0;
+          sh.wgs_per_cu = wgs;
+          float ms = 0.f;
+          st = time_shape(h, L, sh, cus, s, &ms);
+          if (st) {
+            plan_free(p);
+            return st;
+          }
+          if (!have || ms < best_ms) {
+            best = sh;
+            best_ms = ms;
+            have = true;
+          }
+        }
+    if (d->autotune == 2 && cpath) {
+      cache.push_back({key, best.ept, best.nontemporal ? 1 : 0, best.wgs_per_cu, best_ms});
+      cache_write(cpath, cache);
+    }
+  }
+  p->shape = best;
+  p->tuned_ms = best_ms;
+
+  // One eager pass (sets kernel attributes outside capture), then capture.
+  const int grid = grid_for(L, best, cus);
+  e = ta::launch_segment(L.a, L.attr, L.seg, best, grid, L.lds, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return hipfail(h, e, "plan capture start");
+  }
+  hipError_t le = ta::launch_segment(L.a, L.attr, L.seg, best, grid, L.lds, p->cap);
+  if (le == hipSuccess && d->with_imbalance) {
+    ta::ImbArgs ia{};
+    ia.T = d->seg.tensor;
+    ia.R = R;
+    ia.I = I;
+    ia.G = G;
+    ia.it = d->seg.iters_found;
+    ia.rank_sum = (d->seg.rank_sum && d->seg.rank_sumsq) ? d->seg.rank_sum : nullptr;
+    ia.rank_sumsq = (d->seg.rank_sum && d->seg.rank_sumsq) ? d->seg.rank_sumsq : nullptr;
+    ia.span = d->seg.span;
+    ia.ddof = d->ddof;
+    ia.t_app = d->t_app_ns;
+    ia.o = d->imb;
+    le = ta::launch_imbalance(ia, p->ws, ws, p->cap);
+  }
+  if (le == hipSuccess && d->with_outliers) {
+    ta::OutArgs oa{};
+    oa.T = d->seg.tensor;
+    oa.R = R;
+    oa.I = I;
+    oa.G = G;
+    oa.it = d->seg.iters_found;
+    oa.mode = d->outlier_mode;
+    oa.kind = d->outlier_kind;
+    oa.tau = d->tau;
+    oa.rank_score = d->rank_score;
+    oa.rank_flag = d->rank_flag;
+    oa.n_flagged = d->n_flagged;
+    oa.region_score = d->region_score;
+    le = ta::launch_outliers(oa, p->ws, ws, p->cap);
+  }
+  e = hipStreamEndCapture(p->cap, &p->graph);
+  if (le != hipSuccess || e != hipSuccess) {
+    plan_free(p);
+    return hipfail(h, le != hipSuccess ? le : e, "plan capture");
+  }
+  e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return hipfail(h, e, "graph instantiate");
+  }
+  *out = p;
+  return TA_OK;
+}
+
+ta_status ta_plan_launch(ta_plan p, void *stream) {
+  if (!p || !p->exec) return TA_ERR_INVALID_ARG;
+  DeviceGuard dg(p->h->device);
+  hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(p->h, e, "graph launch");
+  return TA_OK;
+}
+
+ta_status ta_plan_info(ta_plan p, int32_t *events_per_thread, int32_t *nontemporal,
+                       int32_t *wgs_per_cu, float *tuned_ms) {
+  if (!p) return TA_ERR_INVALID_ARG;
+  if (events_per_thread) *events_per_thread = p->shape.ept;
+  if (nontemporal) *nontemporal = p->shape.nontemporal ? 1 : 0;
+  if (wgs_per_cu) *wgs_per_cu = p->shape.wgs_per_cu;
+  if (tuned_ms) *tuned_ms = p->tuned_ms;
+  return TA_OK;
+}
+
+ta_status ta_plan_destroy(ta_plan p) {
+  if (!p) return TA_ERR_INVALID_ARG;
+  DeviceGuard dg(p->h->device);
+  hipStreamSynchronize(p->cap);
+  plan_free(p);
   return TA_OK;
 }
 

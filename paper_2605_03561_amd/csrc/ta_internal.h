@@ -54,9 +54,16 @@ struct SegArgs {
   uint32_t *err;
 };
 
+// Launch shape of the fused pass (chosen by the batch autotuner).
+struct SegShape {
+  int ept = 4;              // events per thread per tile: 2, 4 or 8
+  bool nontemporal = false; // streaming loads/stores that bypass cache retention
+  int wgs_per_cu = 0;       // 0: one workgroup per rank; k > 0: persistent, k per CU
+};
+
 // Launchers (defined in the kernel translation units).
-hipError_t launch_segment(const SegArgs &a, bool attr, bool seg, int grid, size_t lds_bytes,
-                          hipStream_t s);
+hipError_t launch_segment(const SegArgs &a, bool attr, bool seg, const SegShape &sh, int grid,
+                          size_t lds_bytes, hipStream_t s);
 size_t segment_lds_bytes(int N, int G, bool attr, bool seg, int *W, int *log2W);
 
 struct ImbArgs {

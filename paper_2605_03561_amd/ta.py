@@ -45,6 +45,15 @@ class ImbOut(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in IMB_FIELDS]
 
 
+class BatchDesc(C.Structure):
+    _fields_ = [("n_iters", C.c_int32), ("seg", SegOut), ("with_imbalance", C.c_int32),
+                ("imb", ImbOut), ("ddof", C.c_int32), ("t_app_ns", C.c_double),
+                ("with_outliers", C.c_int32), ("outlier_mode", C.c_int32),
+                ("outlier_kind", C.c_int32), ("tau", C.c_double), ("rank_score", C.c_void_p),
+                ("rank_flag", C.c_void_p), ("n_flagged", C.c_void_p),
+                ("region_score", C.c_void_p), ("autotune", C.c_int32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
@@ -66,6 +75,10 @@ def _load():
         "ta_imbalance": [P, P, i64, i32, i32, P, P, P, P, i32, f64, P, P],
         "ta_outliers": [P, P, i64, i32, i32, P, i32, i32, f64, P, P, P, P, P],
         "ta_topology_aggregate": [P, P, P, i64, P, P, P, i32, i32, i32, P, P, P, P, P, P, P],
+        "ta_plan_create": [P, P, P, P, P, P],
+        "ta_plan_launch": [P, P],
+        "ta_plan_info": [P, P, P, P, P],
+        "ta_plan_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -263,3 +276,83 @@ class Handle:
             *[_ptr(o[k]) for k in ("flagged_rack", "max_rack", "mean_rack", "flagged_chassis",
                                    "max_chassis", "mean_chassis")], _stream(self.device)))
         return o
+
+    # -- batch plans -----------------------------------------------------------
+    def plan(self, tr: DeviceTraces, n_iters: int, offsets_host, imbalance=True, outliers=True,
+             autotune=1, ddof=1, t_app=0.0, mode=SCAN_FULL, kind=SCORE_MAD, tau=3.5,
+             region=False):
+        """Create a batch plan (fused pass [+ imbalance] [+ outlier scan] in one
+        graph); allocates every output and returns the Plan."""
+        return Plan(self, tr, n_iters, offsets_host, imbalance, outliers, autotune, ddof, t_app,
+                    mode, kind, tau, region)
+
+
+class Plan:
+    def __init__(self, h: Handle, tr: DeviceTraces, n_iters, offsets_host, imbalance, outliers,
+                 autotune, ddof, t_app, mode, kind, tau, region):
+        self.h = h
+        self.tr = tr
+        R, G, N, I = tr.n_ranks, h.n_regions, h.n_nodes, int(n_iters)
+        e = h._empty
+        self.seg = {"tensor": e((R, I, G), torch.int64), "iters_found": e((R,), torch.int32),
+                    "outside": e((R,), torch.int64), "span": e((R,), torch.int64),
+                    "rank_sum": e((R, G), torch.int64), "rank_sumsq": e((R, G, 2), torch.int64),
+                    "excl": e((R, N), torch.int64), "incl": e((R, N), torch.int64)}
+        d = BatchDesc()
+        d.n_iters = I
+        d.seg = SegOut(*[_ptr(self.seg[k]).value for k in ("tensor", "iters_found", "outside",
+                                                          "span", "rank_sum", "rank_sumsq",
+                                                          "excl", "incl")])
+        self.imb = None
+        if imbalance:
+            self.imb = {k: e((I, G), torch.float64) for k in ("mean", "std", "max_minus_mean")}
+            self.imb["min"] = e((I, G), torch.int64)
+            self.imb["max"] = e((I, G), torch.int64)
+            for k in ("avg_mean", "avg_max", "savings_per_iter", "total_savings",
+                      "balance_ratio", "cv_across", "cv_within", "share"):
+                self.imb[k] = e((G,), torch.float64)
+            self.imb["potential_speedup"] = e((1,), torch.float64)
+            d.with_imbalance = 1
+            d.imb = ImbOut(*[_ptr(self.imb[k]).value for k in IMB_FIELDS])
+            d.ddof = int(ddof)
+            d.t_app_ns = float(t_app)
+        self.out = None
+        if outliers:
+            self.out = {"rank_score": e((R,), torch.float64), "rank_flag": e((R,), torch.uint8),
+                        "n_flagged": e((1,), torch.int64),
+                        "region_score": e((R, G), torch.float64) if region else None}
+            d.with_outliers = 1
+            d.outlier_mode, d.outlier_kind, d.tau = int(mode), int(kind), float(tau)
+            d.rank_score = _ptr(self.out["rank_score"]).value
+            d.rank_flag = _ptr(self.out["rank_flag"]).value
+            d.n_flagged = _ptr(self.out["n_flagged"]).value
+            d.region_score = _ptr(self.out["region_score"]).value if region else None
+        d.autotune = int(autotune)
+        self._desc = d
+        off = np.ascontiguousarray(offsets_host, dtype=np.int64)
+        t = tr.struct()
+        p = C.c_void_p()
+        h._check(_lib.ta_plan_create(h.h, C.byref(t), off.ctypes.data_as(C.c_void_p), C.byref(d),
+                                     C.byref(p), _stream(h.device)))
+        self.p = p
+
+    def launch(self):
+        self.h._check(_lib.ta_plan_launch(self.p, _stream(self.h.device)))
+
+    def info(self):
+        ept, nt, wgs, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
+        self.h._check(_lib.ta_plan_info(self.p, C.byref(ept), C.byref(nt), C.byref(wgs),
+                                        C.byref(ms)))
+        return {"events_per_thread": ept.value, "nontemporal": nt.value,
+                "wgs_per_cu": wgs.value, "tuned_ms": ms.value}
+
+    def close(self):
+        if getattr(self, "p", None) is not None:
+            _lib.ta_plan_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
