@@ -266,6 +266,65 @@ ta_status ta_plan_info(ta_plan p, int32_t *events_per_thread, int32_t *nontempor
                        int32_t *wgs_per_cu, float *tuned_ms);
 ta_status ta_plan_destroy(ta_plan p);
 
+/* ---- Learned pre-screen -------------------------------------------------
+ * Not part of the paper's method: a small autoencoder over per-rank iteration
+ * profiles, 64 -> 128 -> 32 -> 128 -> 64 (ReLU on the hidden layers, linear
+ * output, mean squared error, Adam with bias correction), bfloat16 weights and
+ * activations on the matrix cores with FP32 accumulation and FP32 master
+ * weights.  A profile row is x[r,i,g] = (T[r,i,g] - mu_g) / sigma_g over a
+ * rank's valid iterations; mu, sigma are fitted on training tensors.  The rank
+ * score is max_g mean_i (y - x)^2.  All need n_regions == 64.  The state lives
+ * in the handle. */
+
+/* Xavier-uniform weights from SplitMix64 draws of `seed`, zero biases and
+ * optimiser moments, step 0. */
+ta_status ta_ae_init(ta_handle h, uint64_t seed, void *stream);
+/* Adds the valid cells of `tensor` to the running per-region sums (reset != 0
+ * starts over) and refreshes mu and sigma (population standard deviation). */
+ta_status ta_ae_fit_norm(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                         int32_t n_regions, const int32_t *iters_found, int32_t reset,
+                         void *stream);
+/* Writes the normalised profile rows of every valid (rank, iteration), rank by
+ * rank, to rows[n][64] (device; may be NULL to count) and their number to
+ * *n_rows_host.  Synchronises the stream. */
+ta_status ta_ae_rows(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                     int32_t n_regions, const int32_t *iters_found, float *rows,
+                     int64_t *n_rows_host, void *stream);
+/* Gradient (grad[24928], layout W1 W2 W3 W4 b1 b2 b3 b4, row-major [out][in])
+ * and mean loss (loss[1]) over rows[0..n_rows) without updating anything. */
+ta_status ta_ae_grad(ta_handle h, const float *rows, int64_t n_rows, float *grad, float *loss,
+                     void *stream);
+/* `epochs` passes over the rows in batches of `batch` (a fresh permutation of
+ * the rows per epoch, drawn from shuffle_seed), one Adam step (learning rate
+ * lr) per batch; epoch_loss[e] (device, may be NULL) is the row-weighted mean
+ * batch loss of epoch e. */
+ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t epochs, int32_t batch,
+                      float lr, uint64_t shuffle_seed, float *epoch_loss, void *stream);
+/* rank_score[r] (device FP32) for every rank; ranks without iterations score 0. */
+ta_status ta_ae_score(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                      int32_t n_regions, const int32_t *iters_found, float *rank_score,
+                      void *stream);
+/* Sets the fallback threshold to the given quantile of rank_score (device);
+ * synchronises. */
+ta_status ta_ae_calibrate(ta_handle h, const float *rank_score, int64_t n_ranks, double quantile,
+                          void *stream);
+/* Pre-screen: topk_ranks[k] (device) = the k ranks with the largest scores
+ * (ties toward the lower rank id), in ascending rank id.  Fallback to the exact
+ * scan (TA_SCAN_FULL, TA_SCORE_MAD) -- the k ranks with the largest exact
+ * scores -- when the network is not initialised or fitted, or when more than k
+ * ranks exceed the calibrated threshold; *used_fallback_host says which ran.
+ * rank_score (device FP32, may be NULL) receives the network's scores.
+ * Synchronises the stream once (to decide on the fallback). */
+ta_status ta_prescreen(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                       int32_t n_regions, const int32_t *iters_found, int64_t k,
+                       int32_t *topk_ranks, float *rank_score, int32_t *used_fallback_host,
+                       void *stream);
+/* Checkpoint of the network (weights, optimiser moments and step,
+ * normalisation, threshold) to / from a host buffer of ta_ae_state_bytes(). */
+size_t ta_ae_state_bytes(void);
+ta_status ta_ae_get_state(ta_handle h, void *buf_host, size_t bytes);
+ta_status ta_ae_set_state(ta_handle h, const void *buf_host, size_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

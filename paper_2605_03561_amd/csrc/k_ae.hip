@@ -1,0 +1,756 @@
+// k_ae.hip -- learned pre-screen: autoencoder training and scoring kernels.
+//
+// Dense layers run on the matrix cores (v_mfma_f32_16x16x16_bf16): operands
+// are bfloat16 (round to nearest even), accumulation is FP32.  A workgroup
+// (4 waves) processes row tiles of 16 profile rows; every wave owns a fixed set
+// of 16x16 output tiles per layer, so weight-gradient tiles stay in the MFMA
+// accumulators across all row tiles of a training step and are written once
+// per workgroup.  Partials are summed in workgroup order by the Adam kernel, so
+// a step is deterministic.
+#include "ta_ae.h"
+#include "ta_device.h"
+
+namespace ta {
+namespace {
+
+constexpr int AT = 256;       // threads per workgroup
+constexpr int TR = 16;        // rows per tile
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// One 16x16 tile of D += A * B over K (a multiple of 16).  A(m, k) is
+// A[m*sam + k*sak], B(k, n) is B[k*sbk + n*sbn] (bfloat16 in LDS).  Operand
+// lane layout: lane l supplies row/column (l & 15) and k = 4*(l >> 4) + 0..3;
+// the result holds rows 4*(l >> 4) + 0..3 of column (l & 15).
+__device__ inline f4 mma_tile(const uint16_t *A, int sam, int sak, const uint16_t *B, int sbk,
+                              int sbn, int m0, int n0, int K, f4 acc) {
+  const int lane = threadIdx.x & 63;
+  const int mi = m0 + (lane & 15), ni = n0 + (lane & 15), kq = 4 * (lane >> 4);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    s4 a, b;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int k = k0 + kq + j;
+      a[j] = (short)A[mi * sam + k * sak];
+      b[j] = (short)B[k * sbk + ni * sbn];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ inline int out_row(int j) { return 4 * ((threadIdx.x & 63) >> 4) + j; }
+__device__ inline int out_col() { return threadIdx.x & 15; }
+
+// Sum of a value over the four lane groups that hold the same column.
+__device__ inline float col_sum(float v) {
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+struct AeLds {
+  uint16_t W[AE_NW];          // bf16 weights
+  float b[AE_NP - AE_NW];     // biases
+  float X[TR * AE_IN];        // targets (FP32)
+  uint16_t Xb[TR * AE_IN];
+  uint16_t H1[TR * AE_H1], H2[TR * AE_H2], H3[TR * AE_H3];
+  uint16_t D4[TR * AE_IN], D3[TR * AE_H3], D2[TR * AE_H2], D1[TR * AE_H1];
+  float red[AT];
+  double redd[AT];
+  int valid[TR];
+};
+
+__device__ void stage_weights(AeLds &L, const uint16_t *wb, const float *w) {
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(wb);
+  uint32_t *dst = reinterpret_cast<uint32_t *>(L.W);
+  for (int k = threadIdx.x; k < AE_NW / 2; k += AT) dst[k] = src[k];
+  for (int k = threadIdx.x; k < AE_NP - AE_NW; k += AT) L.b[k] = w[AE_NW + k];
+}
+
+// Forward through the four layers for the tile in L.Xb.  Hidden activations
+// are stored as bf16 after ReLU; the output pre-activation tile of wave w
+// (columns 16w..16w+15) is returned in `y` (bias added).
+__device__ inline void forward(AeLds &L, f4 &y) {
+  const int wid = threadIdx.x >> 6;
+  const f4 z0 = {0.f, 0.f, 0.f, 0.f};
+  // L1: [16 x 64] * W1^T -> [16 x 128]
+  for (int t = wid; t < AE_H1 / 16; t += 4) {
+    f4 a = mma_tile(L.Xb, AE_IN, 1, L.W + AE_W1, 1, AE_IN, 0, 16 * t, AE_IN, z0);
+    const int c = 16 * t + out_col();
+#pragma unroll
+    for (int j = 0; j < 4; j++) L.H1[out_row(j) * AE_H1 + c] = f2bf(fmaxf(a[j] + L.b[c], 0.f));
+  }
+  __syncthreads();
+  // L2: [16 x 128] * W2^T -> [16 x 32]
+  for (int t = wid; t < AE_H2 / 16; t += 4) {
+    f4 a = mma_tile(L.H1, AE_H1, 1, L.W + AE_W2, 1, AE_H1, 0, 16 * t, AE_H1, z0);
+    const int c = 16 * t + out_col();
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+      L.H2[out_row(j) * AE_H2 + c] = f2bf(fmaxf(a[j] + L.b[AE_B2 - AE_B1 + c], 0.f));
+  }
+  __syncthreads();
+  // L3: [16 x 32] * W3^T -> [16 x 128]
+  for (int t = wid; t < AE_H3 / 16; t += 4) {
+    f4 a = mma_tile(L.H2, AE_H2, 1, L.W + AE_W3, 1, AE_H2, 0, 16 * t, AE_H2, z0);
+    const int c = 16 * t + out_col();
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+      L.H3[out_row(j) * AE_H3 + c] = f2bf(fmaxf(a[j] + L.b[AE_B3 - AE_B1 + c], 0.f));
+  }
+  __syncthreads();
+  // L4: [16 x 128] * W4^T -> [16 x 64]; wave w owns columns 16w..16w+15
+  y = mma_tile(L.H3, AE_H3, 1, L.W + AE_W4, 1, AE_H3, 0, 16 * wid, AE_H3, z0);
+  const int c = 16 * wid + out_col();
+#pragma unroll
+  for (int j = 0; j < 4; j++) y[j] += L.b[AE_B4 - AE_B1 + c];
+}
+
+__device__ inline uint64_t perm_row(uint64_t k, uint64_t a, uint64_t c, uint64_t n) {
+  return (a * k + c) % n;
+}
+
+// ---------------------------------------------------------------------------
+// Training step: gradient partials of the mean squared error over the rows
+// perm(k), k in [k0, k_end), written per workgroup to part[wg][AE_NP + 1].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(AT) void ae_fwdbwd(const float *__restrict__ rows, int64_t n,
+                                                 int64_t k0, int64_t k_end, uint64_t pa,
+                                                 uint64_t pc, float scale,
+                                                 const uint16_t *__restrict__ wb,
+                                                 const float *__restrict__ w, float *part) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  AeLds &L = *reinterpret_cast<AeLds *>(smem);
+  const int tid = threadIdx.x, wid = tid >> 6;
+  stage_weights(L, wb, w);
+  const int64_t tiles = (k_end - k0 + TR - 1) / TR;
+  const int64_t t_lo = tiles * blockIdx.x / gridDim.x, t_hi = tiles * (blockIdx.x + 1) / gridDim.x;
+
+  const f4 z0 = {0.f, 0.f, 0.f, 0.f};
+  f4 gW1[8], gW4[8], gW2[4], gW3[4];
+#pragma unroll
+  for (int q = 0; q < 8; q++) gW1[q] = gW4[q] = z0;
+#pragma unroll
+  for (int q = 0; q < 4; q++) gW2[q] = gW3[q] = z0;
+  float gb1[2] = {0.f, 0.f}, gb3[2] = {0.f, 0.f}, gb2 = 0.f, gb4 = 0.f, loss = 0.f;
+
+  for (int64_t t = t_lo; t < t_hi; t++) {
+    __syncthreads();
+    {  // load 16 rows (4 floats per thread)
+      const int r = tid >> 4, c4 = (tid & 15) * 4;
+      const int64_t k = k0 + t * TR + r;
+      const bool ok = k < k_end;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (ok) v = *reinterpret_cast<const float4 *>(rows + perm_row((uint64_t)k, pa, pc, (uint64_t)n) * AE_IN + c4);
+      L.X[r * AE_IN + c4 + 0] = v.x;
+      L.X[r * AE_IN + c4 + 1] = v.y;
+      L.X[r * AE_IN + c4 + 2] = v.z;
+      L.X[r * AE_IN + c4 + 3] = v.w;
+      L.Xb[r * AE_IN + c4 + 0] = f2bf(v.x);
+      L.Xb[r * AE_IN + c4 + 1] = f2bf(v.y);
+      L.Xb[r * AE_IN + c4 + 2] = f2bf(v.z);
+      L.Xb[r * AE_IN + c4 + 3] = f2bf(v.w);
+      if ((tid & 15) == 0) L.valid[r] = ok;
+    }
+    __syncthreads();
+    f4 y;
+    forward(L, y);
+    {  // output error -> D4 (dL/dy), loss, db4
+      const int c = 16 * wid + out_col();
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int r = out_row(j);
+        float d = 0.f;
+        if (L.valid[r]) {
+          const float e = y[j] - L.X[r * AE_IN + c];
+          loss += e * e;
+          d = scale * e;
+        }
+        gb4 += d;
+        L.D4[r * AE_IN + c] = f2bf(d);
+      }
+    }
+    __syncthreads();
+    // dW4 [64 x 128] += D4^T H3 ; 32 tiles, 8 per wave
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const int tt = wid * 8 + q, mt = tt >> 3, nt = tt & 7;
+      gW4[q] = mma_tile(L.D4, 1, AE_IN, L.H3, AE_H3, 1, 16 * mt, 16 * nt, TR, gW4[q]);
+    }
+    // dH3 [16 x 128] = D4 W4 ; mask by H3 > 0 -> D3
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int nt = wid + 4 * q;
+      f4 a = mma_tile(L.D4, AE_IN, 1, L.W + AE_W4, AE_H3, 1, 0, 16 * nt, AE_IN, z0);
+      const int c = 16 * nt + out_col();
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int r = out_row(j);
+        const float d = (int16_t)L.H3[r * AE_H3 + c] > 0 ? a[j] : 0.f;  // ReLU was active
+        gb3[q] += d;
+        L.D3[r * AE_H3 + c] = f2bf(d);
+      }
+    }
+    __syncthreads();
+    // dW3 [128 x 32] += D3^T H2 ; 16 tiles, 4 per wave
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int tt = wid * 4 + q, mt = tt >> 1, nt = tt & 1;
+      gW3[q] = mma_tile(L.D3, 1, AE_H3, L.H2, AE_H2, 1, 16 * mt, 16 * nt, TR, gW3[q]);
+    }
+    // dH2 [16 x 32] = D3 W3 -> D2
+    if (wid < 2) {
+      f4 a = mma_tile(L.D3, AE_H3, 1, L.W + AE_W3, AE_H2, 1, 0, 16 * wid, AE_H3, z0);
+      const int c = 16 * wid + out_col();
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int r = out_row(j);
+        const float d = (int16_t)L.H2[r * AE_H2 + c] > 0 ? a[j] : 0.f;
+        gb2 += d;
+        L.D2[r * AE_H2 + c] = f2bf(d);
+      }
+    }
+    __syncthreads();
+    // dW2 [32 x 128] += D2^T H1 ; 16 tiles, 4 per wave
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int tt = wid * 4 + q, mt = tt >> 3, nt = tt & 7;
+      gW2[q] = mma_tile(L.D2, 1, AE_H2, L.H1, AE_H1, 1, 16 * mt, 16 * nt, TR, gW2[q]);
+    }
+    // dH1 [16 x 128] = D2 W2 -> D1
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int nt = wid + 4 * q;
+      f4 a = mma_tile(L.D2, AE_H2, 1, L.W + AE_W2, AE_H1, 1, 0, 16 * nt, AE_H2, z0);
+      const int c = 16 * nt + out_col();
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int r = out_row(j);
+        const float d = (int16_t)L.H1[r * AE_H1 + c] > 0 ? a[j] : 0.f;
+        gb1[q] += d;
+        L.D1[r * AE_H1 + c] = f2bf(d);
+      }
+    }
+    __syncthreads();
+    // dW1 [128 x 64] += D1^T Xb ; 32 tiles, 8 per wave
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const int tt = wid * 8 + q, mt = tt >> 2, nt = tt & 3;
+      gW1[q] = mma_tile(L.D1, 1, AE_H1, L.Xb, AE_IN, 1, 16 * mt, 16 * nt, TR, gW1[q]);
+    }
+  }
+
+  // Write this workgroup's partials (every element exactly once).
+  float *P = part + (int64_t)blockIdx.x * (AE_NP + 1);
+  const int cc = out_col();
+#pragma unroll
+  for (int q = 0; q < 8; q++) {
+    {
+      const int tt = wid * 8 + q, mt = tt >> 2, nt = tt & 3;
+#pragma unroll
+      for (int j = 0; j < 4; j++) P[AE_W1 + (16 * mt + out_row(j)) * AE_IN + 16 * nt + cc] = gW1[q][j];
+    }
+    {
+      const int tt = wid * 8 + q, mt = tt >> 3, nt = tt & 7;
+#pragma unroll
+      for (int j = 0; j < 4; j++) P[AE_W4 + (16 * mt + out_row(j)) * AE_H3 + 16 * nt + cc] = gW4[q][j];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    {
+      const int tt = wid * 4 + q, mt = tt >> 3, nt = tt & 7;
+#pragma unroll
+      for (int j = 0; j < 4; j++) P[AE_W2 + (16 * mt + out_row(j)) * AE_H1 + 16 * nt + cc] = gW2[q][j];
+    }
+    {
+      const int tt = wid * 4 + q, mt = tt >> 1, nt = tt & 1;
+#pragma unroll
+      for (int j = 0; j < 4; j++) P[AE_W3 + (16 * mt + out_row(j)) * AE_H2 + 16 * nt + cc] = gW3[q][j];
+    }
+  }
+  const int lane = tid & 63;
+  const float b4s = col_sum(gb4);
+  const float b3s0 = col_sum(gb3[0]), b3s1 = col_sum(gb3[1]);
+  const float b1s0 = col_sum(gb1[0]), b1s1 = col_sum(gb1[1]);
+  const float b2s = col_sum(gb2);
+  if (lane < 16) {
+    P[AE_B4 + 16 * wid + lane] = b4s;
+    P[AE_B3 + 16 * wid + lane] = b3s0;
+    P[AE_B3 + 16 * (wid + 4) + lane] = b3s1;
+    P[AE_B1 + 16 * wid + lane] = b1s0;
+    P[AE_B1 + 16 * (wid + 4) + lane] = b1s1;
+    if (wid < 2) P[AE_B2 + 16 * wid + lane] = b2s;
+  }
+  const double ls = block_sum_f64<AT>((double)loss, L.redd);
+  if (tid == 0) P[AE_NP] = (float)ls;
+}
+
+// Sum the workgroup partials in workgroup order; optionally take one Adam step.
+__global__ __launch_bounds__(256) void ae_adam(const float *part, int nwg, float *w, uint16_t *wb,
+                                               float *m, float *v, float lr, float bc1, float bc2,
+                                               int update, float *grad_out, float *loss_out,
+                                               float loss_scale) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < AE_NP) {
+    float g = 0.f;
+    for (int k = 0; k < nwg; k++) g += part[(int64_t)k * (AE_NP + 1) + p];
+    if (grad_out) grad_out[p] = g;
+    if (update) {
+      const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+      const float mm = b1 * m[p] + (1.f - b1) * g;
+      const float vv = b2 * v[p] + (1.f - b2) * g * g;
+      m[p] = mm;
+      v[p] = vv;
+      const float wn = w[p] - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+      w[p] = wn;
+      if (p < AE_NW) wb[p] = f2bf(wn);
+    }
+  }
+  if (p == 0 && loss_out) {
+    float s = 0.f;
+    for (int k = 0; k < nwg; k++) s += part[(int64_t)k * (AE_NP + 1) + AE_NP];
+    loss_out[0] = s * loss_scale;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: Xavier-uniform weights from SplitMix64 counter draws.
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void ae_init_kernel(uint64_t seed, float *w, uint16_t *wb, float *m, float *v) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= AE_NP) return;
+  float val = 0.f;
+  if (p < AE_NW) {
+    int l, base, fin, fout;
+    if (p < AE_W2) { l = 0; base = AE_W1; fin = AE_IN; fout = AE_H1; }
+    else if (p < AE_W3) { l = 1; base = AE_W2; fin = AE_H1; fout = AE_H2; }
+    else if (p < AE_W4) { l = 2; base = AE_W3; fin = AE_H2; fout = AE_H3; }
+    else { l = 3; base = AE_W4; fin = AE_H3; fout = AE_IN; }
+    const uint64_t s = mix64(seed);
+    const uint64_t key = s ^ mix64((uint64_t)(l + 1));
+    const uint64_t idx = (uint64_t)(p - base);
+    const uint64_t z = mix64(key + idx * 0x9E3779B97F4A7C15ull);
+    const double u = ((double)(z >> 11) + 0.5) / 9007199254740992.0;
+    const double a = sqrt(6.0 / (double)(fin + fout));
+    val = (float)((2.0 * u - 1.0) * a);
+    wb[p] = f2bf(val);
+  }
+  w[p] = val;
+  m[p] = 0.f;
+  v[p] = 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Normalisation fit: exact per-region sums over the valid cells.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ae_norm_partial(const int64_t *__restrict__ T, int64_t R,
+                                                       int I, const int32_t *it, int64_t rpb,
+                                                       int64_t *ps, uint64_t *pq, int64_t *pc) {
+  const int g = threadIdx.x & 63, rs = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * rpb, r1 = r0 + rpb < R ? r0 + rpb : R;
+  int64_t s = 0, cnt = 0;
+  u128 q = 0;
+  for (int64_t r = r0 + rs; r < r1; r += 4) {
+    int ni = it ? it[r] : I;
+    if (ni > I) ni = I;
+    if (ni < 0) ni = 0;
+    const int64_t *row = T + r * (int64_t)I * AE_IN + g;
+    for (int i = 0; i < ni; i++) {
+      const int64_t x = row[(int64_t)i * AE_IN];
+      s += x;
+      q += (u128)((i128)x * x);
+    }
+    cnt += ni;
+  }
+  __shared__ int64_t ss[256], sc[256];
+  __shared__ uint64_t sl[256], sh[256];
+  ss[threadIdx.x] = s;
+  sc[threadIdx.x] = cnt;
+  sl[threadIdx.x] = (uint64_t)q;
+  sh[threadIdx.x] = (uint64_t)(q >> 64);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    int64_t a = 0, c = 0;
+    u128 b = 0;
+    for (int k = 0; k < 4; k++) {
+      const int t = k * 64 + threadIdx.x;
+      a += ss[t];
+      c += sc[t];
+      b += ((u128)sh[t] << 64) | sl[t];
+    }
+    ps[(int64_t)blockIdx.x * 64 + g] = a;
+    pq[((int64_t)blockIdx.x * 64 + g) * 2] = (uint64_t)b;
+    pq[((int64_t)blockIdx.x * 64 + g) * 2 + 1] = (uint64_t)(b >> 64);
+    if (g == 0) pc[blockIdx.x] = c;
+  }
+}
+
+__global__ void ae_norm_final(int nb, const int64_t *ps, const uint64_t *pq, const int64_t *pc,
+                              int reset, int64_t *nsum, uint64_t *nsq, int64_t *ncnt, float *mu,
+                              float *isd) {
+  const int g = threadIdx.x;
+  if (g >= 64) return;
+  int64_t s = reset ? 0 : nsum[g];
+  u128 q = reset ? 0 : (((u128)nsq[2 * g + 1] << 64) | nsq[2 * g]);
+  int64_t n = reset ? 0 : ncnt[0];
+  int64_t add = 0;
+  for (int b = 0; b < nb; b++) {
+    s += ps[(int64_t)b * 64 + g];
+    q += ((u128)pq[((int64_t)b * 64 + g) * 2 + 1] << 64) | pq[((int64_t)b * 64 + g) * 2];
+    add += pc[b];
+  }
+  n += add;
+  nsum[g] = s;
+  nsq[2 * g] = (uint64_t)q;
+  nsq[2 * g + 1] = (uint64_t)(q >> 64);
+  if (g == 0) ncnt[0] = n;
+  double m = 0.0, sd = 1.0;
+  if (n > 0) {
+    m = i64_to_f64(s) / (double)n;
+    const i128 num = (i128)((u128)n * q) - (i128)s * s;
+    sd = sqrt(i128_to_f64(num) / ((double)n * (double)n));
+    if (!(sd > 0.0)) sd = 1.0;
+  }
+  const float sd32 = (float)sd;
+  mu[g] = (float)m;
+  isd[g] = 1.0f / sd32;
+}
+
+// ---------------------------------------------------------------------------
+// Training rows: normalised profile rows of every valid (rank, iteration).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void ae_rows_scan(const int32_t *it, int64_t R, int I,
+                                                     int64_t *off) {
+  __shared__ int64_t buf[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (R + 1023) / 1024;
+  const int64_t a = t * per, b = a + per < R ? a + per : R;
+  int64_t s = 0;
+  for (int64_t r = a; r < b; r++) {
+    int ni = it ? it[r] : I;
+    s += ni > I ? I : (ni < 0 ? 0 : ni);
+  }
+  buf[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+    const int64_t x = t >= d ? buf[t - d] : 0;
+    __syncthreads();
+    buf[t] += x;
+    __syncthreads();
+  }
+  int64_t run = buf[t] - s;
+  for (int64_t r = a; r < b; r++) {
+    off[r] = run;
+    int ni = it ? it[r] : I;
+    run += ni > I ? I : (ni < 0 ? 0 : ni);
+  }
+  if (t == 1023) off[R] = buf[1023];
+}
+
+__global__ __launch_bounds__(256) void ae_rows_fill(const int64_t *__restrict__ T, int64_t R, int I,
+                                                    const int64_t *off, const float *mu,
+                                                    const float *isd, float *rows) {
+  const int64_t r = blockIdx.x;
+  const int64_t o = off[r], n = off[r + 1] - o;
+  const int g = threadIdx.x & 63;
+  const float m = mu[g], s = isd[g];
+  const int64_t *src = T + r * (int64_t)I * AE_IN;
+  for (int64_t k = threadIdx.x; k < n * AE_IN; k += 256)
+    rows[(o + k / AE_IN) * AE_IN + (k % AE_IN)] = ((float)src[k] - m) * s;
+}
+
+// ---------------------------------------------------------------------------
+// Scoring: score[r] = max_g mean_{i < n_r} (y - x)^2 over the rank's profile.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(AT) void ae_score_kernel(const int64_t *__restrict__ T, int64_t R,
+                                                       int I, const int32_t *it,
+                                                       const uint16_t *__restrict__ wb,
+                                                       const float *__restrict__ w,
+                                                       const float *mu, const float *isd,
+                                                       float *score) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  AeLds &L = *reinterpret_cast<AeLds *>(smem);
+  const int tid = threadIdx.x, wid = tid >> 6;
+  stage_weights(L, wb, w);
+  const int r4 = tid >> 4, c4 = (tid & 15) * 4;
+  float m4[4], s4v[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    m4[q] = mu[c4 + q];
+    s4v[q] = isd[c4 + q];
+  }
+  for (int64_t r = blockIdx.x; r < R; r += gridDim.x) {
+    int ni = it ? it[r] : I;
+    if (ni > I) ni = I;
+    if (ni < 0) ni = 0;
+    float err = 0.f;  // this lane's column (16*wid + l&15), its rows
+    const int64_t *src = T + r * (int64_t)I * AE_IN;
+    for (int i0 = 0; i0 < ni; i0 += TR) {
+      __syncthreads();
+      const int i = i0 + r4;
+      const bool ok = i < ni;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const float x = ok ? ((float)src[(int64_t)i * AE_IN + c4 + q] - m4[q]) * s4v[q] : 0.f;
+        L.X[r4 * AE_IN + c4 + q] = x;
+        L.Xb[r4 * AE_IN + c4 + q] = f2bf(x);
+      }
+      if ((tid & 15) == 0) L.valid[r4] = ok;
+      __syncthreads();
+      f4 y;
+      forward(L, y);
+      const int c = 16 * wid + out_col();
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int rr = out_row(j);
+        if (L.valid[rr]) {
+          const float e = y[j] - L.X[rr * AE_IN + c];
+          err += e * e;
+        }
+      }
+    }
+    const float cs = col_sum(err);
+    __syncthreads();
+    if ((tid & 63) < 16) L.red[16 * wid + (tid & 15)] = cs;
+    __syncthreads();
+    if (tid < 64) {
+      float v = ni > 0 ? L.red[tid] / (float)ni : 0.f;
+      for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+      if (tid == 0) score[r] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Top-k: the k largest scores (ties toward the lower rank id), listed in
+// ascending rank id; also counts scores above a threshold.
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t fkey(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ __launch_bounds__(1024) void topk_kernel(const float *score, int64_t R, int64_t k,
+                                                    int32_t *idx, int32_t *n_above, float thr) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sh[4];
+  __shared__ int64_t sc[1024];
+  const int t = threadIdx.x;
+  // Threshold key K*: the (R-k)-th smallest key (0-based); keys > K* all
+  // selected, keys == K* taken in rank order until k are chosen.
+  uint32_t pref = 0;
+  int64_t want = R - k;  // rank of K* among ascending keys
+  for (int sh_ = 24; sh_ >= 0; sh_ -= 8) {
+    for (int b = t; b < 256; b += 1024) hist[b] = 0;
+    __syncthreads();
+    for (int64_t r = t; r < R; r += 1024) {
+      const uint32_t key = fkey(score[r]);
+      if (sh_ == 24 || (key >> (sh_ + 8)) == pref) atomicAdd(&hist[(key >> sh_) & 255], 1u);
+    }
+    __syncthreads();
+    if (t == 0) {
+      int64_t cum = 0;
+      int b = 0;
+      for (; b < 256; b++) {
+        if (cum + (int64_t)hist[b] > want) break;
+        cum += hist[b];
+      }
+      sh[0] = (pref << 8) | (uint32_t)b;
+      sh[1] = (uint32_t)(want - cum);
+    }
+    __syncthreads();
+    pref = sh[0];
+    want = sh[1];
+    __syncthreads();
+  }
+  const uint32_t kstar = pref;
+  // count keys strictly greater than K*
+  int64_t gt = 0, above = 0;
+  for (int64_t r = t; r < R; r += 1024) {
+    gt += fkey(score[r]) > kstar;
+    above += score[r] > thr;
+  }
+  sc[t] = gt;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (t < s) sc[t] += sc[t + s];
+    __syncthreads();
+  }
+  const int64_t n_gt = sc[0];
+  __syncthreads();
+  sc[t] = above;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (t < s) sc[t] += sc[t + s];
+    __syncthreads();
+  }
+  if (t == 0 && n_above) n_above[0] = (int32_t)sc[0];
+  __syncthreads();
+  const int64_t ties = k - n_gt;  // how many keys equal to K* to take
+  // Ordered compaction in chunks of 1024 ranks.
+  int64_t base_gt = 0, base_tie = 0;
+  for (int64_t c0 = 0; c0 < R; c0 += 1024) {
+    const int64_t r = c0 + t;
+    const uint32_t key = r < R ? fkey(score[r]) : 0u;
+    const int is_gt = r < R && key > kstar;
+    const int is_eq = r < R && key == kstar;
+    sc[t] = ((int64_t)is_eq << 32) | is_gt;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const int64_t x = t >= d ? sc[t - d] : 0;
+      __syncthreads();
+      sc[t] += x;
+      __syncthreads();
+    }
+    const int64_t incl = sc[t];
+    const int64_t gt_before = base_gt + (incl & 0xffffffffll) - is_gt;
+    const int64_t tie_before = base_tie + (incl >> 32) - is_eq;
+    if (is_gt || (is_eq && tie_before < ties))
+      idx[gt_before + (tie_before < ties ? tie_before : ties)] = (int32_t)r;
+    const int64_t tot = sc[1023];
+    __syncthreads();
+    base_gt += tot & 0xffffffffll;
+    base_tie += tot >> 32;
+  }
+}
+
+}  // namespace
+
+hipError_t ae_alloc(AeState &s) {
+  hipError_t e = hipSuccess;
+  auto A = [&](void **p, size_t b) {
+    if (e == hipSuccess) e = hipMalloc(p, b);
+  };
+  A((void **)&s.w, AE_NP * 4);
+  A((void **)&s.wb, AE_NW * 2);
+  A((void **)&s.m, AE_NP * 4);
+  A((void **)&s.v, AE_NP * 4);
+  A((void **)&s.mu, 64 * 4);
+  A((void **)&s.isd, 64 * 4);
+  A((void **)&s.nsum, 64 * 8);
+  A((void **)&s.nsq, 128 * 8);
+  A((void **)&s.ncnt, 8 * 8);
+  A((void **)&s.part, (size_t)AE_WG * (AE_NP + 1) * 4);
+  A((void **)&s.loss, 16);
+  return e;
+}
+
+void ae_free(AeState &s) {
+  void *ps[] = {s.w, s.wb, s.m, s.v, s.mu, s.isd, s.nsum, s.nsq, s.ncnt, s.part, s.loss};
+  for (void *p : ps)
+    if (p) hipFree(p);
+  s = AeState{};
+}
+
+hipError_t launch_ae_init(AeState &s, uint64_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(ae_init_kernel, dim3((AE_NP + 255) / 256), dim3(256), 0, st, seed, s.w, s.wb,
+                     s.m, s.v);
+  s.step = 0;
+  return hipGetLastError();
+}
+
+size_t ae_norm_ws_bytes(int64_t R) {
+  const int64_t nb = (R + 63) / 64 < 1024 ? (R + 63) / 64 + 1 : 1025;
+  return (size_t)nb * (64 * 8 + 128 * 8 + 8) + 1024;
+}
+
+hipError_t launch_ae_norm(AeState &s, const int64_t *T, int64_t R, int I, const int32_t *it,
+                          bool reset, void *ws, size_t ws_bytes, hipStream_t st) {
+  int64_t nb = (R + 63) / 64;
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  const int64_t rpb = (R + nb - 1) / nb;
+  char *p = (char *)ws;
+  int64_t *ps = (int64_t *)p;
+  uint64_t *pq = (uint64_t *)(p + nb * 64 * 8);
+  int64_t *pc = (int64_t *)(p + nb * 64 * 8 + nb * 128 * 8);
+  if ((size_t)(nb * (64 * 8 + 128 * 8 + 8)) > ws_bytes) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ae_norm_partial, dim3((unsigned)nb), dim3(256), 0, st, T, R, I, it, rpb, ps, pq, pc);
+  hipLaunchKernelGGL(ae_norm_final, dim3(1), dim3(64), 0, st, (int)nb, ps, pq, pc, reset ? 1 : 0,
+                     s.nsum, s.nsq, s.ncnt, s.mu, s.isd);
+  return hipGetLastError();
+}
+
+size_t ae_rows_ws_bytes(int64_t R) { return (size_t)(R + 1) * 8 + 256; }
+
+hipError_t launch_ae_rows(const AeState &s, const int64_t *T, int64_t R, int I, const int32_t *it,
+                          float *rows, int64_t *n_rows, void *ws, size_t ws_bytes, hipStream_t st) {
+  if ((size_t)(R + 1) * 8 > ws_bytes) return hipErrorInvalidValue;
+  int64_t *off = (int64_t *)ws;
+  hipLaunchKernelGGL(ae_rows_scan, dim3(1), dim3(1024), 0, st, it, R, I, off);
+  if (rows && R > 0)
+    hipLaunchKernelGGL(ae_rows_fill, dim3((unsigned)R), dim3(256), 0, st, T, R, I, off, s.mu, s.isd, rows);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && n_rows) e = hipMemcpyAsync(n_rows, off + R, 8, hipMemcpyDeviceToHost, st);
+  return e;
+}
+
+template <class K>
+void allow_lds(K k) {
+  static bool done = false;
+  if (!done) {
+    hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)sizeof(AeLds));
+    done = true;
+  }
+}
+
+hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, int batch,
+                          uint64_t a, uint64_t c, float lr, bool update, hipStream_t st,
+                          float *grad_out, float *loss_out) {
+  const int64_t k_end = k0 + batch < n ? k0 + batch : n;
+  const int64_t bv = k_end - k0;
+  if (bv <= 0) return hipErrorInvalidValue;
+  const float scale = 2.0f / (float)(bv * AE_IN);
+  allow_lds(&ae_fwdbwd);
+  hipLaunchKernelGGL(ae_fwdbwd, dim3(AE_WG), dim3(AT), sizeof(AeLds), st, rows, n, k0, k_end, a, c,
+                     scale, s.wb, s.w, s.part);
+  float bc1 = 1.f, bc2 = 1.f;
+  if (update) {
+    s.step++;
+    bc1 = (float)(1.0 - pow(0.9, (double)s.step));
+    bc2 = (float)(1.0 - pow(0.999, (double)s.step));
+  }
+  hipLaunchKernelGGL(ae_adam, dim3((AE_NP + 255) / 256), dim3(256), 0, st, s.part, AE_WG, s.w, s.wb,
+                     s.m, s.v, lr, bc1, bc2, update ? 1 : 0, grad_out, loss_out ? loss_out : s.loss,
+                     1.0f / (float)(bv * AE_IN));
+  return hipGetLastError();
+}
+
+hipError_t launch_ae_score(const AeState &s, const int64_t *T, int64_t R, int I, const int32_t *it,
+                           float *score, hipStream_t st) {
+  allow_lds(&ae_score_kernel);
+  int cus = 256;
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t grid = R < (int64_t)cus * 2 ? R : (int64_t)cus * 2;
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ae_score_kernel, dim3((unsigned)grid), dim3(AT), sizeof(AeLds), st, T, R, I, it,
+                     s.wb, s.w, s.mu, s.isd, score);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk(const float *score, int64_t R, int64_t k, int32_t *idx, int32_t *n_above,
+                       float thr, hipStream_t st) {
+  hipLaunchKernelGGL(topk_kernel, dim3(1), dim3(1024), 0, st, score, R, k, idx, n_above, thr);
+  return hipGetLastError();
+}
+
+}  // namespace ta

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <new>
 
+#include "ta_ae.h"
 #include "ta_internal.h"
 
 struct ta_handle_s {
@@ -23,6 +24,7 @@ struct ta_handle_s {
   uint32_t *d_err = nullptr;
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  ta::AeState ae;
 };
 
 namespace {
@@ -399,6 +401,7 @@ ta_status ta_destroy(ta_handle h) {
   if (h->d_tin_tout) hipFree(h->d_tin_tout);
   if (h->d_err) hipFree(h->d_err);
   if (h->ws) hipFree(h->ws);
+  ta::ae_free(h->ae);
   delete h;
   return TA_OK;
 }
@@ -800,6 +803,323 @@ ta_status ta_plan_destroy(ta_plan p) {
   DeviceGuard dg(p->h->device);
   hipStreamSynchronize(p->cap);
   plan_free(p);
+  return TA_OK;
+}
+
+}  // extern "C"
+
+// ---- learned pre-screen ---------------------------------------------------
+
+namespace {
+
+ta_status ae_check(ta_handle h, const int64_t *tensor, int64_t R, int32_t I, int32_t G) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (G != ta::AE_IN) return fail(h, TA_ERR_INVALID_ARG, "the pre-screen needs n_regions == 64");
+  if (R < 0 || I < 1 || (R > 0 && !tensor) || !aligned16(tensor))
+    return fail(h, TA_ERR_INVALID_ARG, "bad tensor or sizes");
+  if (R >= ((int64_t)1 << 31)) return fail(h, TA_ERR_SIZE_OVERFLOW, "too many ranks");
+  return TA_OK;
+}
+
+ta_status ae_ensure(ta_handle h) {
+  if (h->ae.w) return TA_OK;
+  hipError_t e = ta::ae_alloc(h->ae);
+  if (e != hipSuccess) {
+    ta::ae_free(h->ae);
+    return fail(h, TA_ERR_OOM, "autoencoder state allocation failed");
+  }
+  return TA_OK;
+}
+
+uint64_t splitmix(uint64_t &s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) {
+    const uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+__global__ void fill_f32(float *p, int n, float v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void add_loss(float *dst, const float *src, float w) { dst[0] += src[0] * w; }
+
+__global__ void f64_to_f32(const double *a, float *b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+constexpr uint32_t AE_MAGIC = 0x45414154u;  // "TAAE"
+struct AeHeader {
+  uint32_t magic, version;
+  int64_t step;
+  int32_t ready, normed;
+  float threshold;
+  int32_t pad;
+};
+
+}  // namespace
+
+extern "C" {
+
+ta_status ta_ae_init(ta_handle h, uint64_t seed, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  DeviceGuard dg(h->device);
+  ta_status st = ae_ensure(h);
+  if (st) return st;
+  hipError_t e = ta::launch_ae_init(h->ae, seed, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "ae init");
+  h->ae.ready = true;
+  return TA_OK;
+}
+
+ta_status ta_ae_fit_norm(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                         int32_t n_regions, const int32_t *iters_found, int32_t reset,
+                         void *stream) {
+  ta_status st = ae_check(h, tensor, n_ranks, n_iters, n_regions);
+  if (st) return st;
+  DeviceGuard dg(h->device);
+  st = ae_ensure(h);
+  if (!st) st = ensure_ws(h, ta::ae_norm_ws_bytes(n_ranks));
+  if (st) return st;
+  if (!h->ae.normed) reset = 1;
+  hipError_t e = ta::launch_ae_norm(h->ae, tensor, n_ranks, n_iters, iters_found, reset != 0, h->ws,
+                                    h->ws_bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "ae norm");
+  h->ae.normed = true;
+  return TA_OK;
+}
+
+ta_status ta_ae_rows(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                     int32_t n_regions, const int32_t *iters_found, float *rows,
+                     int64_t *n_rows_host, void *stream) {
+  ta_status st = ae_check(h, tensor, n_ranks, n_iters, n_regions);
+  if (st) return st;
+  if (!n_rows_host) return fail(h, TA_ERR_INVALID_ARG, "n_rows_host NULL");
+  if (rows && !aligned16(rows)) return fail(h, TA_ERR_INVALID_ARG, "rows not 16-byte aligned");
+  if (!h->ae.normed) return fail(h, TA_ERR_STATE, "ta_ae_fit_norm has not been called");
+  DeviceGuard dg(h->device);
+  st = ensure_ws(h, ta::ae_rows_ws_bytes(n_ranks));
+  if (st) return st;
+  int64_t n = 0;
+  hipError_t e = ta::launch_ae_rows(h->ae, tensor, n_ranks, n_iters, iters_found, rows, &n, h->ws,
+                                    h->ws_bytes, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "ae rows");
+  *n_rows_host = n;
+  return TA_OK;
+}
+
+ta_status ta_ae_grad(ta_handle h, const float *rows, int64_t n_rows, float *grad, float *loss,
+                     void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!rows || n_rows < 1 || !grad || !aligned16(rows) || !aligned16(grad) || !aligned16(loss))
+    return fail(h, TA_ERR_INVALID_ARG, "bad rows or outputs");
+  if (!h->ae.ready) return fail(h, TA_ERR_STATE, "ta_ae_init has not been called");
+  if (n_rows > ((int64_t)1 << 31)) return fail(h, TA_ERR_SIZE_OVERFLOW, "too many rows");
+  DeviceGuard dg(h->device);
+  hipError_t e = ta::launch_ae_step(h->ae, rows, n_rows, 0, (int)n_rows, 1, 0, 0.f, false,
+                                    (hipStream_t)stream, grad, loss);
+  if (e != hipSuccess) return hipfail(h, e, "ae grad");
+  return TA_OK;
+}
+
+ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t epochs, int32_t batch,
+                      float lr, uint64_t shuffle_seed, float *epoch_loss, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!rows || n_rows < 1 || epochs < 0 || batch < 1 || !(lr > 0.f) || !aligned16(rows) ||
+      !aligned16(epoch_loss))
+    return fail(h, TA_ERR_INVALID_ARG, "bad training arguments");
+  if (!h->ae.ready) return fail(h, TA_ERR_STATE, "ta_ae_init has not been called");
+  if (n_rows > ((int64_t)1 << 32)) return fail(h, TA_ERR_SIZE_OVERFLOW, "too many rows");
+  DeviceGuard dg(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t rs = shuffle_seed;
+  if (epoch_loss && epochs > 0)
+    hipLaunchKernelGGL(fill_f32, dim3((epochs + 255) / 256), dim3(256), 0, s, epoch_loss, epochs, 0.f);
+  const uint64_t n = (uint64_t)n_rows;
+  for (int32_t ep = 0; ep < epochs; ep++) {
+    // Row order of the epoch: k -> (a*k + c) mod n with gcd(a, n) = 1.
+    uint64_t a = 1, c = 0;
+    if (n > 1) {
+      do {
+        a = 1 + splitmix(rs) % (n - 1);
+      } while (gcd64(a, n) != 1);
+      c = splitmix(rs) % n;
+    }
+    for (int64_t k0 = 0; k0 < n_rows; k0 += batch) {
+      hipError_t e = ta::launch_ae_step(h->ae, rows, n_rows, k0, batch, a, c, lr, true, s, nullptr,
+                                        nullptr);
+      if (e != hipSuccess) return hipfail(h, e, "ae step");
+      if (epoch_loss) {
+        const int64_t bv = std::min<int64_t>(batch, n_rows - k0);
+        hipLaunchKernelGGL(add_loss, dim3(1), dim3(1), 0, s, epoch_loss + ep, h->ae.loss,
+                           (float)((double)bv / (double)n_rows));
+      }
+    }
+  }
+  const hipError_t le = hipGetLastError();
+  return le == hipSuccess ? TA_OK : hipfail(h, le, "ae train");
+}
+
+ta_status ta_ae_score(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                      int32_t n_regions, const int32_t *iters_found, float *rank_score,
+                      void *stream) {
+  ta_status st = ae_check(h, tensor, n_ranks, n_iters, n_regions);
+  if (st) return st;
+  if (!rank_score || !aligned16(rank_score)) return fail(h, TA_ERR_INVALID_ARG, "rank_score");
+  if (!h->ae.ready || !h->ae.normed) return fail(h, TA_ERR_STATE, "network not initialised and fitted");
+  DeviceGuard dg(h->device);
+  hipError_t e = ta::launch_ae_score(h->ae, tensor, n_ranks, n_iters, iters_found, rank_score,
+                                     (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "ae score");
+  return TA_OK;
+}
+
+ta_status ta_ae_calibrate(ta_handle h, const float *rank_score, int64_t n_ranks, double quantile,
+                          void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!rank_score || n_ranks < 1 || !(quantile >= 0.0 && quantile <= 1.0))
+    return fail(h, TA_ERR_INVALID_ARG, "bad calibration arguments");
+  DeviceGuard dg(h->device);
+  std::vector<float> v(n_ranks);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e == hipSuccess) e = hipMemcpy(v.data(), rank_score, (size_t)n_ranks * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hipfail(h, e, "calibrate");
+  std::sort(v.begin(), v.end());
+  const int64_t idx = std::min<int64_t>(n_ranks - 1, (int64_t)(quantile * (double)(n_ranks - 1) + 0.5));
+  h->ae.threshold = v[idx];
+  return TA_OK;
+}
+
+ta_status ta_prescreen(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                       int32_t n_regions, const int32_t *iters_found, int64_t k,
+                       int32_t *topk_ranks, float *rank_score, int32_t *used_fallback_host,
+                       void *stream) {
+  ta_status st = ae_check(h, tensor, n_ranks, n_iters, n_regions);
+  if (st) return st;
+  if (k < 1 || k > n_ranks || !topk_ranks || !used_fallback_host || !aligned16(topk_ranks) ||
+      !aligned16(rank_score))
+    return fail(h, TA_ERR_INVALID_ARG, "bad k or outputs");
+  DeviceGuard dg(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t fl = ((size_t)n_ranks * 4 + 255) & ~(size_t)255;
+  const size_t need = std::max(fl + 256, fl + ta::outliers_ws_bytes(n_ranks, n_iters, n_regions,
+                                                                    TA_SCAN_FULL, TA_SCORE_MAD) +
+                                              ((size_t)n_ranks * 9 + 1024));
+  st = ensure_ws(h, need);
+  if (st) return st;
+  float *score = rank_score ? rank_score : (float *)h->ws;
+  int32_t *above = (int32_t *)((char *)h->ws + fl);
+  bool fallback = !(h->ae.ready && h->ae.normed);
+  hipError_t e = hipSuccess;
+  if (!fallback) {
+    e = ta::launch_ae_score(h->ae, tensor, n_ranks, n_iters, iters_found, score, s);
+    const float thr = h->ae.threshold >= 0.f ? h->ae.threshold : 3.4e38f;
+    if (e == hipSuccess) e = ta::launch_topk(score, n_ranks, k, topk_ranks, above, thr, s);
+    int32_t n_above = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&n_above, above, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hipfail(h, e, "prescreen");
+    fallback = h->ae.threshold >= 0.f && n_above > k;
+  }
+  *used_fallback_host = fallback ? 1 : 0;
+  if (!fallback) return TA_OK;
+  // Exact scan, then the k ranks with the largest exact scores.
+  char *base = (char *)h->ws + fl + 256;
+  double *xs = (double *)base;
+  uint8_t *xf = (uint8_t *)(base + (((size_t)n_ranks * 8 + 255) & ~(size_t)255));
+  char *ows = (char *)xf + (((size_t)n_ranks + 255) & ~(size_t)255);
+  ta::OutArgs oa{};
+  oa.T = tensor;
+  oa.R = n_ranks;
+  oa.I = n_iters;
+  oa.G = n_regions;
+  oa.it = iters_found;
+  oa.mode = TA_SCAN_FULL;
+  oa.kind = TA_SCORE_MAD;
+  oa.tau = 3.5;
+  oa.rank_score = xs;
+  oa.rank_flag = xf;
+  const size_t ows_bytes = h->ws_bytes - (size_t)(ows - (char *)h->ws);
+  e = ta::launch_outliers(oa, ows, ows_bytes, s);
+  float *xs32 = (float *)h->ws;
+  if (e == hipSuccess)
+    hipLaunchKernelGGL(f64_to_f32, dim3((unsigned)((n_ranks + 255) / 256)), dim3(256), 0, s, xs, xs32,
+                       n_ranks);
+  if (e == hipSuccess) e = ta::launch_topk(xs32, n_ranks, k, topk_ranks, above, 3.4e38f, s);
+  if (e != hipSuccess) return hipfail(h, e, "prescreen fallback");
+  return TA_OK;
+}
+
+size_t ta_ae_state_bytes(void) {
+  return sizeof(AeHeader) + (size_t)ta::AE_NP * 4 * 3 + 64 * 4 * 2;
+}
+
+ta_status ta_ae_get_state(ta_handle h, void *buf_host, size_t bytes) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!buf_host || bytes < ta_ae_state_bytes()) return fail(h, TA_ERR_INVALID_ARG, "buffer too small");
+  if (!h->ae.w) return fail(h, TA_ERR_STATE, "no network state");
+  DeviceGuard dg(h->device);
+  TA_HIP(h, hipDeviceSynchronize());
+  char *p = (char *)buf_host;
+  AeHeader hd{AE_MAGIC, 1u, h->ae.step, h->ae.ready, h->ae.normed, h->ae.threshold, 0};
+  memcpy(p, &hd, sizeof hd);
+  p += sizeof hd;
+  TA_HIP(h, hipMemcpy(p, h->ae.w, ta::AE_NP * 4, hipMemcpyDeviceToHost));
+  p += ta::AE_NP * 4;
+  TA_HIP(h, hipMemcpy(p, h->ae.m, ta::AE_NP * 4, hipMemcpyDeviceToHost));
+  p += ta::AE_NP * 4;
+  TA_HIP(h, hipMemcpy(p, h->ae.v, ta::AE_NP * 4, hipMemcpyDeviceToHost));
+  p += ta::AE_NP * 4;
+  TA_HIP(h, hipMemcpy(p, h->ae.mu, 64 * 4, hipMemcpyDeviceToHost));
+  p += 64 * 4;
+  TA_HIP(h, hipMemcpy(p, h->ae.isd, 64 * 4, hipMemcpyDeviceToHost));
+  return TA_OK;
+}
+
+ta_status ta_ae_set_state(ta_handle h, const void *buf_host, size_t bytes) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!buf_host || bytes < ta_ae_state_bytes()) return fail(h, TA_ERR_INVALID_ARG, "buffer too small");
+  AeHeader hd;
+  memcpy(&hd, buf_host, sizeof hd);
+  if (hd.magic != AE_MAGIC || hd.version != 1u) return fail(h, TA_ERR_INVALID_ARG, "not a network state");
+  DeviceGuard dg(h->device);
+  ta_status st = ae_ensure(h);
+  if (st) return st;
+  TA_HIP(h, hipDeviceSynchronize());
+  const char *p = (const char *)buf_host + sizeof hd;
+  std::vector<uint16_t> wb(ta::AE_NW);
+  const float *wf = (const float *)p;
+  for (int i = 0; i < ta::AE_NW; i++) {
+    uint32_t u;
+    memcpy(&u, wf + i, 4);
+    wb[i] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  }
+  TA_HIP(h, hipMemcpy(h->ae.w, p, ta::AE_NP * 4, hipMemcpyHostToDevice));
+  TA_HIP(h, hipMemcpy(h->ae.wb, wb.data(), ta::AE_NW * 2, hipMemcpyHostToDevice));
+  p += ta::AE_NP * 4;
+  TA_HIP(h, hipMemcpy(h->ae.m, p, ta::AE_NP * 4, hipMemcpyHostToDevice));
+  p += ta::AE_NP * 4;
+  TA_HIP(h, hipMemcpy(h->ae.v, p, ta::AE_NP * 4, hipMemcpyHostToDevice));
+  p += ta::AE_NP * 4;
+  TA_HIP(h, hipMemcpy(h->ae.mu, p, 64 * 4, hipMemcpyHostToDevice));
+  p += 64 * 4;
+  TA_HIP(h, hipMemcpy(h->ae.isd, p, 64 * 4, hipMemcpyHostToDevice));
+  h->ae.step = hd.step;
+  h->ae.ready = hd.ready != 0;
+  h->ae.normed = hd.normed != 0;
+  h->ae.threshold = hd.threshold;
   return TA_OK;
 }
 

@@ -79,11 +79,23 @@ def _load():
         "ta_plan_launch": [P, P],
         "ta_plan_info": [P, P, P, P, P],
         "ta_plan_destroy": [P],
+        "ta_ae_init": [P, C.c_uint64, P],
+        "ta_ae_fit_norm": [P, P, i64, i32, i32, P, i32, P],
+        "ta_ae_rows": [P, P, i64, i32, i32, P, P, P, P],
+        "ta_ae_grad": [P, P, i64, P, P, P],
+        "ta_ae_train": [P, P, i64, i32, i32, C.c_float, C.c_uint64, P, P],
+        "ta_ae_score": [P, P, i64, i32, i32, P, P, P],
+        "ta_ae_calibrate": [P, P, i64, f64, P],
+        "ta_prescreen": [P, P, i64, i32, i32, P, i64, P, P, P, P],
+        "ta_ae_get_state": [P, P, C.c_size_t],
+        "ta_ae_set_state": [P, P, C.c_size_t],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = i32
+    lib.ta_ae_state_bytes.argtypes = []
+    lib.ta_ae_state_bytes.restype = C.c_size_t
     lib.ta_status_string.restype = C.c_char_p
     lib.ta_last_error.restype = C.c_char_p
     return lib
@@ -276,6 +288,71 @@ class Handle:
             *[_ptr(o[k]) for k in ("flagged_rack", "max_rack", "mean_rack", "flagged_chassis",
                                    "max_chassis", "mean_chassis")], _stream(self.device)))
         return o
+
+    # -- learned pre-screen ------------------------------------------------------
+    AE_NP = 24928
+
+    def ae_init(self, seed: int):
+        self._check(_lib.ta_ae_init(self.h, C.c_uint64(seed), _stream(self.device)))
+
+    def ae_fit_norm(self, tensor, iters_found=None, reset=True):
+        R, I, G = tensor.shape
+        self._check(_lib.ta_ae_fit_norm(self.h, _ptr(tensor), R, I, G, _ptr(iters_found),
+                                        int(bool(reset)), _stream(self.device)))
+
+    def ae_rows(self, tensor, iters_found=None):
+        R, I, G = tensor.shape
+        n = C.c_int64()
+        self._check(_lib.ta_ae_rows(self.h, _ptr(tensor), R, I, G, _ptr(iters_found), None,
+                                    C.byref(n), _stream(self.device)))
+        rows = self._empty((max(n.value, 1), 64), torch.float32)
+        self._check(_lib.ta_ae_rows(self.h, _ptr(tensor), R, I, G, _ptr(iters_found), _ptr(rows),
+                                    C.byref(n), _stream(self.device)))
+        return rows[:n.value]
+
+    def ae_grad(self, rows):
+        g = self._empty((self.AE_NP,), torch.float32)
+        loss = self._empty((1,), torch.float32)
+        self._check(_lib.ta_ae_grad(self.h, _ptr(rows), rows.shape[0], _ptr(g), _ptr(loss),
+                                    _stream(self.device)))
+        return g, loss
+
+    def ae_train(self, rows, epochs, batch=4096, lr=1e-3, seed=0):
+        el = self._empty((max(epochs, 1),), torch.float32)
+        self._check(_lib.ta_ae_train(self.h, _ptr(rows), rows.shape[0], int(epochs), int(batch),
+                                     C.c_float(lr), C.c_uint64(seed), _ptr(el),
+                                     _stream(self.device)))
+        return el[:epochs]
+
+    def ae_score(self, tensor, iters_found=None):
+        R, I, G = tensor.shape
+        sc = self._empty((R,), torch.float32)
+        self._check(_lib.ta_ae_score(self.h, _ptr(tensor), R, I, G, _ptr(iters_found), _ptr(sc),
+                                     _stream(self.device)))
+        return sc
+
+    def ae_calibrate(self, scores, quantile):
+        self._check(_lib.ta_ae_calibrate(self.h, _ptr(scores), scores.numel(), float(quantile),
+                                         _stream(self.device)))
+
+    def prescreen(self, tensor, iters_found, k):
+        R, I, G = tensor.shape
+        top = self._empty((k,), torch.int32)
+        sc = self._empty((R,), torch.float32)
+        fb = C.c_int32()
+        self._check(_lib.ta_prescreen(self.h, _ptr(tensor), R, I, G, _ptr(iters_found), int(k),
+                                      _ptr(top), _ptr(sc), C.byref(fb), _stream(self.device)))
+        return top, sc, bool(fb.value)
+
+    def ae_get_state(self) -> bytes:
+        n = _lib.ta_ae_state_bytes()
+        buf = C.create_string_buffer(n)
+        self._check(_lib.ta_ae_get_state(self.h, buf, n))
+        return buf.raw
+
+    def ae_set_state(self, state: bytes):
+        buf = C.create_string_buffer(state, len(state))
+        self._check(_lib.ta_ae_set_state(self.h, buf, len(state)))
 
     # -- batch plans -----------------------------------------------------------
     def plan(self, tr: DeviceTraces, n_iters: int, offsets_host, imbalance=True, outliers=True,

@@ -1,0 +1,207 @@
+"""Learned pre-screen on the GPU against the autoencoder oracle (oracle/ae.py).
+
+Tolerances: the GPU rounds matrix-product operands to bfloat16 exactly where the
+oracle's bf16 mode does, but accumulates in FP32 instead of FP64, so results
+agree to about 1e-3 relative (weight-gradient matrices: relative L2 <= 1e-2).
+Initial weights, normalisation constants and normalised rows are exact.
+"""
+import struct
+
+import numpy as np
+import pytest
+
+from oracle import ae
+
+pytestmark = pytest.mark.gpu
+
+NP = 24928
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2605_03561_amd import ta
+    h = ta.Handle(0)
+    yield torch, ta, h
+    h.close()
+
+
+def unpack(state: bytes):
+    hdr = 4 + 4 + 8 + 4 + 4 + 4 + 4
+    a = np.frombuffer(state, dtype=np.float32, offset=hdr)
+    w, m, v = a[:NP], a[NP:2 * NP], a[2 * NP:3 * NP]
+    mu, isd = a[3 * NP:3 * NP + 64], a[3 * NP + 64:3 * NP + 128]
+    return w, m, v, mu, isd
+
+
+def to_params(w):
+    p, o = {}, 0
+    for l in range(4):
+        fin, fout = ae.DIMS[l], ae.DIMS[l + 1]
+        p[f"W{l + 1}"] = w[o:o + fin * fout].astype(np.float64).reshape(fout, fin)
+        o += fin * fout
+    for l in range(4):
+        fout = ae.DIMS[l + 1]
+        p[f"b{l + 1}"] = w[o:o + fout].astype(np.float64)
+        o += fout
+    return p
+
+
+def flat(g):
+    return np.concatenate([g[f"W{l + 1}"].reshape(-1) for l in range(4)] +
+                          [g[f"b{l + 1}"].reshape(-1) for l in range(4)])
+
+
+def fake_tensor(rng, R, I, it=None):
+    base = rng.gamma(4.0, 50_000.0, (1, 1, 64))
+    T = np.rint(rng.gamma(4.0, 1.0, (R, I, 64)) / 4.0 * base * (1 + 0.05 * rng.standard_normal((R, 1, 1))))
+    T = T.astype(np.int64)
+    if it is None:
+        it = np.full(R, I, np.int32)
+    T[np.arange(I)[None, :] >= it[:, None]] = 0
+    return T, it
+
+
+def test_init_matches_oracle(env):
+    torch, ta, h = env
+    h.ae_init(12345)
+    torch.cuda.synchronize()
+    w, m, v, _, _ = unpack(h.ae_get_state())
+    ref = flat(ae.init_params(12345)).astype(np.float32)
+    assert np.array_equal(w, ref)
+    assert not m.any() and not v.any()
+
+
+def test_fit_norm_and_rows_match_oracle(env):
+    torch, ta, h = env
+    rng = np.random.default_rng(1)
+    T1, it1 = fake_tensor(rng, 37, 20, rng.integers(0, 21, 37).astype(np.int32))
+    T2, it2 = fake_tensor(rng, 11, 20)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    h.ae_init(1)
+    h.ae_fit_norm(dev(T1), dev(it1), reset=True)
+    h.ae_fit_norm(dev(T2), dev(it2), reset=False)
+    _, _, _, mu, isd = unpack(h.ae_get_state())
+    rmu, rsd = ae.fit_norm([T1, T2], [it1, it2])
+    np.testing.assert_allclose(mu, rmu, rtol=1e-6)
+    np.testing.assert_allclose(isd, (np.float32(1) / rsd).astype(np.float32), rtol=1e-6)
+    rows = h.ae_rows(dev(T1), dev(it1)).cpu().numpy()
+    X = ae.normalize(T1, mu, 1.0 / isd)
+    ref = np.concatenate([X[r, :it1[r]] for r in range(37)])
+    assert rows.shape == ref.shape
+    np.testing.assert_allclose(rows, ref, rtol=1e-6, atol=1e-6)
+
+
+def test_gradient_matches_oracle(env):
+    torch, ta, h = env
+    rng = np.random.default_rng(2)
+    h.ae_init(77)
+    X = rng.normal(0, 1, (300, 64)).astype(np.float32)
+    g, loss = h.ae_grad(torch.from_numpy(X).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    p = ae.init_params(77)
+    l_ref, g_ref = ae.loss_and_grads(p, X.astype(np.float64), bf16=True)
+    assert abs(loss.item() - l_ref) / l_ref < 1e-3
+    rg = flat(g_ref)
+    o = 0
+    for l in range(4):
+        n = ae.DIMS[l] * ae.DIMS[l + 1]
+        a, b = g[o:o + n], rg[o:o + n]
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-2, f"W{l + 1}"
+        o += n
+    a, b = g[o:], rg[o:]
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-2
+
+
+def test_adam_step_matches_oracle(env):
+    torch, ta, h = env
+    rng = np.random.default_rng(3)
+    X = rng.normal(0, 1, (256, 64)).astype(np.float32)
+    h.ae_init(5)
+    h.ae_train(torch.from_numpy(X).cuda(), epochs=1, batch=256, lr=1e-3, seed=9)
+    torch.cuda.synchronize()
+    w, m, v, _, _ = unpack(h.ae_get_state())
+    p = ae.init_params(5)
+    _, g = ae.loss_and_grads(p, X.astype(np.float64), bf16=True)
+    mm = {k: np.zeros_like(x) for k, x in p.items()}
+    vv = {k: np.zeros_like(x) for k, x in p.items()}
+    p1, _, _ = ae.adam_update(dict(p), g, mm, vv, 1, lr=1e-3)
+    ref = flat(p1)
+    # first Adam step moves every weight by about lr * sign(g): compare the moves
+    w0 = flat(p)
+    gr = flat(g)
+    firm = np.abs(gr) > 1e-2 * np.sqrt((gr ** 2).mean())   # sign well determined
+    assert firm.mean() > 0.5
+    np.testing.assert_allclose(w[firm], ref[firm], atol=2e-4)
+    assert (np.sign(w - w0) == np.sign(ref - w0)).mean() > 0.98
+
+
+def test_training_reduces_loss(env):
+    torch, ta, h = env
+    rng = np.random.default_rng(4)
+    basis = rng.normal(0, 1, (4, 64))
+    X = (rng.normal(0, 1, (8192, 4)) @ basis).astype(np.float32)
+    h.ae_init(3)
+    el = h.ae_train(torch.from_numpy(X).cuda(), epochs=8, batch=512, lr=3e-3, seed=1).cpu().numpy()
+    assert el[-1] < 0.3 * el[0], el
+
+
+def test_scores_match_oracle_and_state_roundtrip(env):
+    torch, ta, h = env
+    rng = np.random.default_rng(5)
+    T, it = fake_tensor(rng, 40, 33, rng.integers(0, 34, 40).astype(np.int32))
+    dT, dit = torch.from_numpy(T).cuda(), torch.from_numpy(it).cuda()
+    h.ae_init(11)
+    h.ae_fit_norm(dT, dit)
+    sc = h.ae_score(dT, dit).cpu().numpy()
+    w, _, _, mu, isd = unpack(h.ae_get_state())
+    ref = ae.rank_scores(to_params(w), T, it, mu, (np.float32(1) / isd), bf16=True)
+    np.testing.assert_allclose(sc, ref, rtol=2e-3, atol=1e-6)
+    assert sc[it == 0].max(initial=0.0) == 0.0
+    state = h.ae_get_state()
+    h2 = ta.Handle(0)
+    h2.ae_set_state(state)
+    sc2 = h2.ae_score(dT, dit).cpu().numpy()
+    h2.close()
+    assert np.array_equal(sc, sc2)
+
+
+def test_prescreen_topk_and_fallback(env, oracle):
+    torch, ta, h = env
+    rng = np.random.default_rng(6)
+    T, it = fake_tensor(rng, 300, 40)
+    T[[7, 150, 299], :, 5] *= 3
+    dT, dit = torch.from_numpy(T).cuda(), torch.from_numpy(it).cuda()
+    h.ae_init(2)
+    h.ae_fit_norm(dT, dit)
+    top, sc, fb = h.prescreen(dT, dit, 25)
+    assert not fb
+    s = sc.cpu().numpy()
+    order = sorted(range(300), key=lambda r: (-s[r], r))[:25]
+    assert top.cpu().numpy().tolist() == sorted(order)
+    # threshold below most scores -> more than k above it -> exact fallback
+    h.ae_calibrate(sc, 0.5)
+    top2, _, fb2 = h.prescreen(dT, dit, 25)
+    assert fb2
+    _, xs, flag, nf, _ = oracle.outliers(T, it, mode=0, kind=0)
+    xs32 = xs.astype(np.float32)
+    order = sorted(range(300), key=lambda r: (-xs32[r], r))[:25]
+    assert top2.cpu().numpy().tolist() == sorted(order)
+    assert {7, 150, 299} <= set(top2.cpu().numpy().tolist())
+    h.ae_calibrate(sc, 1.0)   # back to: fallback only when more than k exceed the max
+
+
+def test_topk_ties_and_edges(env):
+    torch, ta, h = env
+    rng = np.random.default_rng(7)
+    T, it = fake_tensor(rng, 70, 10)
+    T[10:30] = T[10]                          # twenty ranks with equal scores
+    dT, dit = torch.from_numpy(T).cuda(), torch.from_numpy(it).cuda()
+    h.ae_init(4)
+    h.ae_fit_norm(dT, dit)
+    for k in (1, 2, 15, 25, 69, 70):
+        top, sc, fb = h.prescreen(dT, dit, k)
+        s = sc.cpu().numpy()
+        order = sorted(range(70), key=lambda r: (-s[r], r))[:k]
+        assert top.cpu().numpy().tolist() == sorted(order)
