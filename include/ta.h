@@ -197,7 +197,10 @@ ta_status ta_imbalance(ta_handle h, const int64_t *tensor, int64_t n_ranks, int3
  *   TA_SCORE_Z: (x - mean) / std with ddof = 1 (0 when std is 0).
  * rank_score[r] = max_g |z2(r,g)|; rank_flag[r] = rank_score > tau;
  * n_flagged[0] = number of flags; region_score[r*G+g] = z2(r,g) (signed, may
- * be NULL).  All outputs are device pointers. */
+ * be NULL).  All outputs are device pointers.
+ * Cell values must lie in (-2^61, 2^61); n_iters * n_regions <= 4,194,240
+ * (TA_ERR_SIZE_OVERFLOW otherwise).  The FULL scan keeps a column-major copy
+ * of the tensor in the handle's workspace (as large as the tensor). */
 enum { TA_SCAN_FULL = 0, TA_SCAN_TOTALS = 1 };
 enum { TA_SCORE_MAD = 0, TA_SCORE_Z = 1 };
 ta_status ta_outliers(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
@@ -300,6 +303,12 @@ ta_status ta_ae_grad(ta_handle h, const float *rows, int64_t n_rows, float *grad
  * batch loss of epoch e. */
 ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t epochs, int32_t batch,
                       float lr, uint64_t shuffle_seed, float *epoch_loss, void *stream);
+/* Score used by ta_ae_score / ta_prescreen: TA_AE_SCORE_ERROR (default) =
+ * max_g mean_i (y - x)^2, the reconstruction error; TA_AE_SCORE_RESIDUAL =
+ * max_g |mean_i (y - x)|, a region's persistent residual over the rank's
+ * iterations.  Saved with the network state. */
+enum { TA_AE_SCORE_ERROR = 0, TA_AE_SCORE_RESIDUAL = 1 };
+ta_status ta_ae_set_score_kind(ta_handle h, int32_t kind);
 /* rank_score[r] (device FP32) for every rank; ranks without iterations score 0. */
 ta_status ta_ae_score(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
                       int32_t n_regions, const int32_t *iters_found, float *rank_score,

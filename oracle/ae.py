@@ -162,8 +162,11 @@ def adam_update(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return p, m, v
 
 
-def rank_scores(p: dict, T: np.ndarray, iters, mu, sd, bf16: bool = False) -> np.ndarray:
-    """score[r] = max_g mean_{i < iters[r]} (y - x)^2 over the rank's profile."""
+def rank_scores(p: dict, T: np.ndarray, iters, mu, sd, bf16: bool = False,
+                kind: int = 0) -> np.ndarray:
+    """kind 0: score[r] = max_g mean_{i < iters[r]} (y - x)^2 (reconstruction
+    error); kind 1: score[r] = max_g |mean_{i < iters[r]} (y - x)| (persistent
+    residual of a region over the rank's iterations)."""
     R, I, G = T.shape
     X = normalize(T, mu, sd)
     out = np.zeros(R)
@@ -172,6 +175,6 @@ def rank_scores(p: dict, T: np.ndarray, iters, mu, sd, bf16: bool = False) -> np
         if n == 0:
             continue
         _, a = forward(p, X[r, :n], bf16)
-        e = (a[-1] - X[r, :n].astype(np.float64)) ** 2
-        out[r] = e.mean(0).max()
+        res = a[-1] - X[r, :n].astype(np.float64)
+        out[r] = (res ** 2).mean(0).max() if kind == 0 else np.abs(res.mean(0)).max()
     return out

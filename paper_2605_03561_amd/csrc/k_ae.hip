@@ -476,64 +476,191 @@ __global__ __launch_bounds__(256) void ae_rows_fill(const int64_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Scoring: score[r] = max_g mean_{i < n_r} (y - x)^2 over the rank's profile.
+// Scoring.  One wave per rank (8 waves per workgroup share the weights in
+// LDS); the rank's profile rows go through the network in tiles of 16 with
+// v_mfma_f32_16x16x32_bf16, operands read as 16-byte LDS vectors from padded
+// rows.  No workgroup barrier after the weights are staged.
+//   kind 0: score = max_g mean_i (y - x)^2     kind 1: max_g |mean_i (y - x)|
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(AT) void ae_score_kernel(const int64_t *__restrict__ T, int64_t R,
-                                                       int I, const int32_t *it,
-                                                       const uint16_t *__restrict__ wb,
-                                                       const float *__restrict__ w,
-                                                       const float *mu, const float *isd,
-                                                       float *score) {
+constexpr int SW = 8;                  // waves per workgroup
+constexpr int P_W1 = 72, P_W2 = 136, P_W3 = 40, P_W4 = 136;   // padded row strides (bf16)
+constexpr int P_X = 68;                // FP32 row stride of the input tile
+constexpr int P_H = 136, P_H2 = 40;    // bf16 row strides of the hidden tiles
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+
+struct ScoreLds {
+  uint16_t W1[AE_H1 * P_W1], W2[AE_H2 * P_W2], W3[AE_H3 * P_W3], W4[AE_IN * P_W4];
+  float b[AE_NP - AE_NW];
+  float mu[AE_IN], isd[AE_IN];
+  struct Wave {
+    float X[TR * P_X];
+    uint16_t H[TR * P_H];     // first and third hidden layers (one after the other)
+    uint16_t H2[TR * P_H2];
+  } wv[SW];
+};
+
+__device__ inline bf8 ld_bf8(const uint16_t *p) {
+  return __builtin_bit_cast(bf8, *reinterpret_cast<const u4v *>(p));
+}
+
+__device__ inline bf8 ld_bf8_from_f32(const float *p) {
+  const float4 a = *reinterpret_cast<const float4 *>(p);
+  const float4 b = *reinterpret_cast<const float4 *>(p + 4);
+  u4v u;
+  u[0] = (uint32_t)f2bf(a.x) | ((uint32_t)f2bf(a.y) << 16);
+  u[1] = (uint32_t)f2bf(a.z) | ((uint32_t)f2bf(a.w) << 16);
+  u[2] = (uint32_t)f2bf(b.x) | ((uint32_t)f2bf(b.y) << 16);
+  u[3] = (uint32_t)f2bf(b.z) | ((uint32_t)f2bf(b.w) << 16);
+  return __builtin_bit_cast(bf8, u);
+}
+
+__device__ inline void lds_wave_sync() {
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+__device__ inline f4 mfma32(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(SW * 64) void ae_score_kernel(const int64_t *__restrict__ T, int64_t R,
+                                                           int I, const int32_t *it,
+                                                           const uint16_t *__restrict__ wb,
+                                                           const float *__restrict__ w,
+                                                           const float *mu, const float *isd,
+                                                           int kind, float *score) {
   extern __shared__ __align__(16) unsigned char smem[];
-  AeLds &L = *reinterpret_cast<AeLds *>(smem);
-  const int tid = threadIdx.x, wid = tid >> 6;
-  stage_weights(L, wb, w);
-  const int r4 = tid >> 4, c4 = (tid & 15) * 4;
-  float m4[4], s4v[4];
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    m4[q] = mu[c4 + q];
-    s4v[q] = isd[c4 + q];
+  ScoreLds &L = *reinterpret_cast<ScoreLds *>(smem);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int k = tid; k < AE_NW; k += SW * 64) {
+    uint16_t v = wb[k];
+    if (k < AE_W2) L.W1[(k / AE_IN) * P_W1 + k % AE_IN] = v;
+    else if (k < AE_W3) L.W2[((k - AE_W2) / AE_H1) * P_W2 + (k - AE_W2) % AE_H1] = v;
+    else if (k < AE_W4) L.W3[((k - AE_W3) / AE_H2) * P_W3 + (k - AE_W3) % AE_H2] = v;
+    else L.W4[((k - AE_W4) / AE_H3) * P_W4 + (k - AE_W4) % AE_H3] = v;
   }
-  for (int64_t r = blockIdx.x; r < R; r += gridDim.x) {
-    int ni = it ? it[r] : I;
-    if (ni > I) ni = I;
-    if (ni < 0) ni = 0;
-    float err = 0.f;  // this lane's column (16*wid + l&15), its rows
+  for (int k = tid; k < AE_NP - AE_NW; k += SW * 64) L.b[k] = w[AE_NW + k];
+  for (int k = tid; k < AE_IN; k += SW * 64) {
+    L.mu[k] = mu[k];
+    L.isd[k] = isd[k];
+  }
+  __syncthreads();
+  auto &V = L.wv[wid];
+  const int row = lane & 15, kq = 8 * (lane >> 4), col = lane & 15, rq = 4 * (lane >> 4);
+  // row loading: lane -> tile row lane/4, columns 16*(lane%4) .. +15
+  const int lr = lane >> 2, lc = 16 * (lane & 3);
+  const float *bias = L.b;
+  const int64_t nw = (int64_t)gridDim.x * SW;
+  for (int64_t r = (int64_t)blockIdx.x * SW + wid; r < R; r += nw) {
+    int n = it ? it[r] : I;
+    if (n > I) n = I;
+    if (n < 0) n = 0;
     const int64_t *src = T + r * (int64_t)I * AE_IN;
-    for (int i0 = 0; i0 < ni; i0 += TR) {
-      __syncthreads();
-      const int i = i0 + r4;
-      const bool ok = i < ni;
+    float e2[4] = {0.f, 0.f, 0.f, 0.f}, rs[4] = {0.f, 0.f, 0.f, 0.f};
+    int64_t cur[16], nxt[16];
+    auto load = [&](int i0, int64_t *dst) {
+      const int i = i0 + lr;
+      if (i < n) {
+        const u4v *q = reinterpret_cast<const u4v *>(src + (int64_t)i * AE_IN + lc);
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const float x = ok ? ((float)src[(int64_t)i * AE_IN + c4 + q] - m4[q]) * s4v[q] : 0.f;
-        L.X[r4 * AE_IN + c4 + q] = x;
-        L.Xb[r4 * AE_IN + c4 + q] = f2bf(x);
+        for (int h = 0; h < 8; h++) {
+          const u4v x = __builtin_nontemporal_load(q + h);
+          dst[2 * h] = (int64_t)(((uint64_t)x[1] << 32) | x[0]);
+          dst[2 * h + 1] = (int64_t)(((uint64_t)x[3] << 32) | x[2]);
+        }
+      } else {
+#pragma unroll
+        for (int h = 0; h < 16; h++) dst[h] = 0;
       }
-      if ((tid & 15) == 0) L.valid[r4] = ok;
-      __syncthreads();
-      f4 y;
-      forward(L, y);
-      const int c = 16 * wid + out_col();
+    };
+    if (n > 0) load(0, cur);
+    for (int i0 = 0; i0 < n; i0 += TR) {
+      if (i0 + TR < n) load(i0 + TR, nxt);
+      // normalised input tile (FP32) of this wave
+      {
+        const bool ok = i0 + lr < n;
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int rr = out_row(j);
-        if (L.valid[rr]) {
-          const float e = y[j] - L.X[rr * AE_IN + c];
-          err += e * e;
+        for (int h = 0; h < 16; h += 4) {
+          float4 x;
+          x.x = ok ? ((float)cur[h] - L.mu[lc + h]) * L.isd[lc + h] : 0.f;
+          x.y = ok ? ((float)cur[h + 1] - L.mu[lc + h + 1]) * L.isd[lc + h + 1] : 0.f;
+          x.z = ok ? ((float)cur[h + 2] - L.mu[lc + h + 2]) * L.isd[lc + h + 2] : 0.f;
+          x.w = ok ? ((float)cur[h + 3] - L.mu[lc + h + 3]) * L.isd[lc + h + 3] : 0.f;
+          *reinterpret_cast<float4 *>(&V.X[lr * P_X + lc + h]) = x;
         }
       }
+      lds_wave_sync();
+      // L1: [16 x 64] -> [16 x 128]
+#pragma unroll
+      for (int nt = 0; nt < AE_H1 / 16; nt++) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < AE_IN; k0 += 32)
+          acc = mfma32(ld_bf8_from_f32(&V.X[row * P_X + k0 + kq]),
+                       ld_bf8(&L.W1[(16 * nt + row) * P_W1 + k0 + kq]), acc);
+        const int c = 16 * nt + col;
+#pragma unroll
+        for (int j = 0; j < 4; j++) V.H[(rq + j) * P_H + c] = f2bf(fmaxf(acc[j] + bias[c], 0.f));
+      }
+      lds_wave_sync();
+      // L2: [16 x 128] -> [16 x 32]
+#pragma unroll
+      for (int nt = 0; nt < AE_H2 / 16; nt++) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < AE_H1; k0 += 32)
+          acc = mfma32(ld_bf8(&V.H[row * P_H + k0 + kq]), ld_bf8(&L.W2[(16 * nt + row) * P_W2 + k0 + kq]),
+                       acc);
+        const int c = 16 * nt + col;
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+          V.H2[(rq + j) * P_H2 + c] = f2bf(fmaxf(acc[j] + bias[AE_B2 - AE_B1 + c], 0.f));
+      }
+      lds_wave_sync();
+      // L3: [16 x 32] -> [16 x 128]
+#pragma unroll
+      for (int nt = 0; nt < AE_H3 / 16; nt++) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma32(ld_bf8(&V.H2[row * P_H2 + kq]), ld_bf8(&L.W3[(16 * nt + row) * P_W3 + kq]), acc);
+        const int c = 16 * nt + col;
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+          V.H[(rq + j) * P_H + c] = f2bf(fmaxf(acc[j] + bias[AE_B3 - AE_B1 + c], 0.f));
+      }
+      lds_wave_sync();
+      // L4: [16 x 128] -> [16 x 64], residuals of the valid rows
+#pragma unroll
+      for (int nt = 0; nt < AE_IN / 16; nt++) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < AE_H3; k0 += 32)
+          acc = mfma32(ld_bf8(&V.H[row * P_H + k0 + kq]), ld_bf8(&L.W4[(16 * nt + row) * P_W4 + k0 + kq]),
+                       acc);
+        const int c = 16 * nt + col;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          if (i0 + rq + j < n) {
+            const float res = acc[j] + bias[AE_B4 - AE_B1 + c] - V.X[(rq + j) * P_X + c];
+            e2[nt] += res * res;
+            rs[nt] += res;
+          }
+        }
+      }
+      lds_wave_sync();
+#pragma unroll
+      for (int h = 0; h < 16; h++) cur[h] = nxt[h];
     }
-    const float cs = col_sum(err);
-    __syncthreads();
-    if ((tid & 63) < 16) L.red[16 * wid + (tid & 15)] = cs;
-    __syncthreads();
-    if (tid < 64) {
-      float v = ni > 0 ? L.red[tid] / (float)ni : 0.f;
-      for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
-      if (tid == 0) score[r] = v;
+    float best = 0.f;
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) {
+      const float a = col_sum(e2[nt]), b = col_sum(rs[nt]);
+      const float v = n > 0 ? (kind == 0 ? a : fabsf(b)) / (float)n : 0.f;
+      best = fmaxf(best, v);
     }
+    for (int d = 32; d >= 1; d >>= 1) best = fmaxf(best, __shfl_xor(best, d, 64));
+    if (lane == 0) score[r] = best;
   }
 }
 
@@ -735,15 +862,20 @@ hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, 
 
 hipError_t launch_ae_score(const AeState &s, const int64_t *T, int64_t R, int I, const int32_t *it,
                            float *score, hipStream_t st) {
-  allow_lds(&ae_score_kernel);
-  int cus = 256;
-  int dev = 0;
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void *>(&ae_score_kernel),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(ScoreLds));
+    attr = true;
+  }
+  int cus = 256, dev = 0;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int64_t grid = R < (int64_t)cus * 2 ? R : (int64_t)cus * 2;
+  int64_t grid = (R + SW - 1) / SW;
+  if (grid > cus) grid = cus;
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(ae_score_kernel, dim3((unsigned)grid), dim3(AT), sizeof(AeLds), st, T, R, I, it,
-                     s.wb, s.w, s.mu, s.isd, score);
+  hipLaunchKernelGGL(ae_score_kernel, dim3((unsigned)grid), dim3(SW * 64), sizeof(ScoreLds), st, T, R,
+                     I, it, s.wb, s.w, s.mu, s.isd, s.score_kind, score);
   return hipGetLastError();
 }
 

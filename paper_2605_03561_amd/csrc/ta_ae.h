@@ -43,6 +43,7 @@ struct AeState {
   bool ready = false;        // weights initialised
   bool normed = false;       // normalisation fitted
   float threshold = -1.f;    // calibrated score threshold (fallback rule); < 0: none
+  int score_kind = 0;        // 0: max mean squared error, 1: max |mean residual|
 };
 
 constexpr int AE_WG = 32;   // workgroups per training step (gradient partials)

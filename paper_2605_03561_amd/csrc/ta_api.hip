@@ -547,8 +547,8 @@ ta_status ta_outliers(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32
   if (!(tau >= 0.0)) return fail(h, TA_ERR_INVALID_ARG, "tau must be >= 0");
   if (n_ranks > 0 && (!tensor || !rank_score || !rank_flag))
     return fail(h, TA_ERR_INVALID_ARG, "tensor, rank_score and rank_flag are required");
-  if ((double)n_iters * n_regions > 2e9 || (double)n_ranks * n_iters * n_regions > 4e18)
-    return fail(h, TA_ERR_SIZE_OVERFLOW, "tensor too large");
+  if ((double)n_iters * n_regions > 4194240.0 || (double)n_ranks * n_iters * n_regions > 4e18)
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "n_iters * n_regions above 4,194,240 or tensor too large");
   const void *ptrs[] = {tensor, iters_found, rank_score, rank_flag, n_flagged, region_score};
   for (const void *p : ptrs)
     if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
@@ -865,7 +865,7 @@ struct AeHeader {
   int64_t step;
   int32_t ready, normed;
   float threshold;
-  int32_t pad;
+  int32_t pad;  // score kind
 };
 
 }  // namespace
@@ -972,6 +972,14 @@ ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t ep
   return le == hipSuccess ? TA_OK : hipfail(h, le, "ae train");
 }
 
+ta_status ta_ae_set_score_kind(ta_handle h, int32_t kind) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (kind != TA_AE_SCORE_ERROR && kind != TA_AE_SCORE_RESIDUAL)
+    return fail(h, TA_ERR_INVALID_ARG, "unknown score kind");
+  h->ae.score_kind = kind;
+  return TA_OK;
+}
+
 ta_status ta_ae_score(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
                       int32_t n_regions, const int32_t *iters_found, float *rank_score,
                       void *stream) {
@@ -1073,7 +1081,8 @@ ta_status ta_ae_get_state(ta_handle h, void *buf_host, size_t bytes) {
   DeviceGuard dg(h->device);
   TA_HIP(h, hipDeviceSynchronize());
   char *p = (char *)buf_host;
-  AeHeader hd{AE_MAGIC, 1u, h->ae.step, h->ae.ready, h->ae.normed, h->ae.threshold, 0};
+  AeHeader hd{AE_MAGIC, 1u, h->ae.step, h->ae.ready, h->ae.normed, h->ae.threshold,
+              h->ae.score_kind};
   memcpy(p, &hd, sizeof hd);
   p += sizeof hd;
   TA_HIP(h, hipMemcpy(p, h->ae.w, ta::AE_NP * 4, hipMemcpyDeviceToHost));
@@ -1120,6 +1129,7 @@ ta_status ta_ae_set_state(ta_handle h, const void *buf_host, size_t bytes) {
   h->ae.ready = hd.ready != 0;
   h->ae.normed = hd.normed != 0;
   h->ae.threshold = hd.threshold;
+  h->ae.score_kind = hd.pad == TA_AE_SCORE_RESIDUAL ? TA_AE_SCORE_RESIDUAL : TA_AE_SCORE_ERROR;
   return TA_OK;
 }
 

@@ -1,0 +1,181 @@
+"""Training and evaluation of the learned pre-screen (config-4 workload).
+
+The network is trained on rank x iteration x region tensors that the library's
+own fused pass produces from GPU-generated traces without injected anomalies,
+then judged against the exact outlier scan (robust z, FULL mode) on held-out
+seeds with injected slow ranks.  Every step of the analysis runs in the HIP
+library; torch only holds device buffers and provides the stream and timers.
+
+Workload: 10,000 ranks, lognormal trace lengths (median 50,000 events,
+1,000..400,000), a 1,000-node tree, 500 iterations, 64 regions (the network's
+input width).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import gpu_synth, ta
+
+C4 = dict(n_ranks=10_000, median_len=50_000, min_len=1_000, max_len=400_000, n_nodes=1_000,
+          depth_max=12, n_iters=500, n_regions=64)
+TRAIN_SEEDS = (1001, 1002, 1003, 1004, 1005)
+HELD_OUT = ((2001, 0.005), (2002, 0.01), (2003, 0.02), (2004, 0.035), (2005, 0.05))
+
+
+def make_tensor(h: ta.Handle, seed: int, inject_frac: float, cfg=C4, device="cuda:0"):
+    """Generate one batch of traces on the GPU and reduce it to the tensor.
+    Returns (tensor, iters_found, workload metadata); the traces are freed."""
+    w = gpu_synth.timeline_on_gpu(seed=seed, inject_frac=inject_frac, device=device, **cfg)
+    h.set_tree(w.parent)
+    h.set_regions(w.marker, w.regions)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx, device)
+    out = h.attribute_segment(tr, cfg["n_iters"], outputs=("tensor", "iters_found"))
+    h.sync_status()
+    meta = {"injected": w.injected, "n_events": w.n_events}
+    del tr, w
+    torch.cuda.empty_cache()
+    return out["tensor"], out["iters_found"], meta
+
+
+def _recall_at(scores: np.ndarray, flags: np.ndarray, k: int) -> float:
+    order = np.lexsort((np.arange(len(scores)), -scores))[:k]
+    sel = np.zeros(len(scores), bool)
+    sel[order] = True
+    return float((sel & flags).sum() / max(flags.sum(), 1))
+
+
+def train(h: ta.Handle, seeds=TRAIN_SEEDS, epochs=20, batch=4096, lr=1e-3, init_seed=7,
+          cfg=C4, inject_margin=0.075, log=print):
+    """Fit the normalisation on the training tensors (no injected anomalies),
+    train the network on all their profile rows, then -- on the training
+    tensors only -- measure the exact scan's flag rate f, set the screen size
+    k_frac = f + inject_margin, choose the score kind that best recovers the
+    exact flags, and calibrate the fallback threshold at the (1 - k_frac / 2)
+    quantile of the training scores."""
+    t0 = time.time()
+    tensors = []
+    for s in seeds:
+        T, it, _ = make_tensor(h, s, 0.0, cfg)
+        tensors.append((T, it))
+    h.ae_init(init_seed)
+    for i, (T, it) in enumerate(tensors):
+        h.ae_fit_norm(T, it, reset=(i == 0))
+    rows = torch.cat([h.ae_rows(T, it) for T, it in tensors])
+    torch.cuda.synchronize()
+    log(f"[prescreen] {rows.shape[0]} training rows from {len(seeds)} seeds in {time.time() - t0:.1f}s")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    el = h.ae_train(rows, epochs, batch=batch, lr=lr, seed=init_seed)
+    ev[1].record()
+    torch.cuda.synchronize()
+    train_ms = ev[0].elapsed_time(ev[1])
+    log(f"[prescreen] trained {epochs} epochs in {train_ms / 1e3:.1f}s: loss "
+        f"{el[0].item():.4f} -> {el[-1].item():.4f}")
+    del rows
+    torch.cuda.empty_cache()
+    flags = [h.outliers(T, it)["rank_flag"].cpu().numpy().astype(bool) for T, it in tensors]
+    f_train = max(float(f.mean()) for f in flags)
+    k_frac = min(1.0, f_train + inject_margin)
+    R = cfg["n_ranks"]
+    k = int(round(k_frac * R))
+    kind_recall = {}
+    for kind in (ta.AE_SCORE_ERROR, ta.AE_SCORE_RESIDUAL):
+        h.ae_set_score_kind(kind)
+        kind_recall[kind] = float(np.mean([_recall_at(h.ae_score(T, it).cpu().numpy(), f, k)
+                                           for (T, it), f in zip(tensors, flags)]))
+    kind = max(kind_recall, key=lambda q: (kind_recall[q], -q))
+    h.ae_set_score_kind(kind)
+    scores = torch.cat([h.ae_score(T, it) for T, it in tensors])
+    h.ae_calibrate(scores, 1.0 - k_frac / 2)
+    log(f"[prescreen] exact flag rate on training seeds {f_train:.3f} -> k_frac {k_frac:.3f}; "
+        f"recall of training flags by score kind {kind_recall} -> kind {kind}")
+    del tensors
+    torch.cuda.empty_cache()
+    return {"epochs": epochs, "batch": batch, "lr": lr,
+            "train_rows": int(len(seeds) * R * cfg["n_iters"]), "train_s": train_ms / 1e3,
+            "epoch_loss": el.cpu().numpy().tolist(), "train_flag_rate": f_train,
+            "k_frac": k_frac, "score_kind": int(kind),
+            "train_recall_by_kind": {int(q): v for q, v in kind_recall.items()}}
+
+
+def _time(fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        out = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, out
+
+
+def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_seed=99,
+             log=print):
+    """Judge the trained network (and two references) against the exact scan.
+
+    For each held-out seed: exact FULL robust-z scan -> flagged ranks (the
+    truth for recall); the pre-screen's top-k (k = k_frac * R); the same for
+    an untrained network with the same normalisation; and the non-learned
+    TOTALS scan (robust z of rank totals) taking its k highest scores.  Times
+    are GPU times from HIP events on the current stream."""
+    R = cfg["n_ranks"]
+    k = int(round(k_frac * R))
+    ref = ta.Handle(h.device.index or 0)
+    ref.ae_set_state(h.ae_get_state())
+    ref.ae_init(untrained_seed)                    # fresh weights, same normalisation
+    rows = []
+    for seed, rate in held_out:
+        T, it, meta = make_tensor(h, seed, rate, cfg)
+        t_full, full = _time(lambda: h.outliers(T, it, mode=ta.SCAN_FULL, kind=ta.SCORE_MAD))
+        flags = full["rank_flag"].cpu().numpy().astype(bool)
+        t_pre, pre = _time(lambda: h.prescreen(T, it, k))
+        top, _, fb = pre
+        t_tot, tot = _time(lambda: h.outliers(T, it, mode=ta.SCAN_TOTALS, kind=ta.SCORE_MAD))
+        t_score, sc_t = _time(lambda: h.ae_score(T, it))
+        sc_u = ref.ae_score(T, it)
+        top_u = np.lexsort((np.arange(R), -sc_u.cpu().numpy()))[:k]
+        top_direct = np.lexsort((np.arange(R), -sc_t.cpu().numpy()))[:k]
+
+        def recall(sel):
+            s = np.zeros(R, bool)
+            s[sel] = True
+            hit = (s & flags).sum()
+            return (hit / max(flags.sum(), 1), hit / max(len(sel), 1))
+
+        ts = tot["rank_score"].cpu().numpy()
+        top_tot = np.lexsort((np.arange(R), -ts))[:k]
+        r_ae, p_ae = recall(top.cpu().numpy())
+        r_un, p_un = recall(top_u)
+        r_dir, _ = recall(top_direct)
+        r_tt, p_tt = recall(top_tot)
+        inj = meta["injected"]
+        sel = np.zeros(R, bool)
+        sel[top.cpu().numpy()] = True
+        row = {"seed": seed, "inject_rate": rate, "n_flagged_exact": int(flags.sum()),
+               "injected_flagged_by_exact": float(flags[inj].mean()) if inj.any() else None,
+               "k": k, "recall": float(r_ae), "precision": float(p_ae), "used_fallback": bool(fb),
+               "injected_recall": float(sel[inj].mean()) if inj.any() else None,
+               "network_topk_recall": float(r_dir), "untrained_recall": float(r_un),
+               "totals_scan_recall": float(r_tt),
+               "full_scan_ms": t_full, "prescreen_ms": t_pre, "ae_score_ms": t_score,
+               "totals_scan_ms": t_tot, "speedup_vs_full": t_full / t_pre}
+        log(f"[prescreen] seed {seed} rate {rate:.3f}: exact flags {row['n_flagged_exact']}, "
+            f"recall {r_ae:.4f} (untrained {r_un:.4f}, totals {r_tt:.4f}), "
+            f"{t_full:.2f} ms full vs {t_pre:.2f} ms pre-screen ({t_full / t_pre:.1f}x)")
+        rows.append(row)
+        del T, it, full, tot
+        torch.cuda.empty_cache()
+    ref.close()
+    summ = {"k": k, "recall_min": min(r["recall"] for r in rows),
+            "recall_mean": float(np.mean([r["recall"] for r in rows])),
+            "precision_mean": float(np.mean([r["precision"] for r in rows])),
+            "speedup_min": min(r["speedup_vs_full"] for r in rows),
+            "speedup_mean": float(np.mean([r["speedup_vs_full"] for r in rows])),
+            "untrained_recall_mean": float(np.mean([r["untrained_recall"] for r in rows])),
+            "totals_scan_recall_mean": float(np.mean([r["totals_scan_recall"] for r in rows])),
+            "any_fallback": any(r["used_fallback"] for r in rows)}
+    return summ, rows

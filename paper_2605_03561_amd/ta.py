@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libta.so")
 OK, INVALID_ARG, BAD_TREE, CTX_RANGE, UNSORTED, ITER_OVERFLOW, SIZE_OVERFLOW, OOM, HIP, STATE = range(10)
 SCAN_FULL, SCAN_TOTALS = 0, 1
 SCORE_MAD, SCORE_Z = 0, 1
+AE_SCORE_ERROR, AE_SCORE_RESIDUAL = 0, 1
 
 
 class TAError(RuntimeError):
@@ -85,6 +86,7 @@ def _load():
         "ta_ae_grad": [P, P, i64, P, P, P],
         "ta_ae_train": [P, P, i64, i32, i32, C.c_float, C.c_uint64, P, P],
         "ta_ae_score": [P, P, i64, i32, i32, P, P, P],
+        "ta_ae_set_score_kind": [P, i32],
         "ta_ae_calibrate": [P, P, i64, f64, P],
         "ta_prescreen": [P, P, i64, i32, i32, P, i64, P, P, P, P],
         "ta_ae_get_state": [P, P, C.c_size_t],
@@ -323,6 +325,9 @@ class Handle:
                                      C.c_float(lr), C.c_uint64(seed), _ptr(el),
                                      _stream(self.device)))
         return el[:epochs]
+
+    def ae_set_score_kind(self, kind: int):
+        self._check(_lib.ta_ae_set_score_kind(self.h, int(kind)))
 
     def ae_score(self, tensor, iters_found=None):
         R, I, G = tensor.shape

@@ -133,3 +133,15 @@ def test_fit_norm_and_scores():
     p = ae.init_params(1)
     s = ae.rank_scores(p, T, it, mu, sd)
     assert s[3] == 0.0 and (s[[0, 1, 2, 4, 5]] > 0).all()
+    # closed form with a network that outputs a constant c: residual score is
+    # max_g |c_g - mean_i x|, error score max_g mean_i (c_g - x)^2
+    z = {k: np.zeros_like(v) for k, v in p.items()}
+    c = np.linspace(-1, 1, 64)
+    z["b4"] = c
+    X = ae.normalize(T, mu, sd).astype(np.float64)
+    s0 = ae.rank_scores(z, T, it, mu, sd, kind=0)
+    s1 = ae.rank_scores(z, T, it, mu, sd, kind=1)
+    for r in (0, 2, 5):
+        x = X[r, :it[r]]
+        assert s0[r] == pytest.approx(((c - x) ** 2).mean(0).max(), rel=1e-12)
+        assert s1[r] == pytest.approx(np.abs((c - x).mean(0)).max(), rel=1e-12)

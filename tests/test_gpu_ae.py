@@ -158,6 +158,11 @@ def test_scores_match_oracle_and_state_roundtrip(env):
     w, _, _, mu, isd = unpack(h.ae_get_state())
     ref = ae.rank_scores(to_params(w), T, it, mu, (np.float32(1) / isd), bf16=True)
     np.testing.assert_allclose(sc, ref, rtol=2e-3, atol=1e-6)
+    h.ae_set_score_kind(ta.AE_SCORE_RESIDUAL)
+    sc1 = h.ae_score(dT, dit).cpu().numpy()
+    ref1 = ae.rank_scores(to_params(w), T, it, mu, (np.float32(1) / isd), bf16=True, kind=1)
+    np.testing.assert_allclose(sc1, ref1, rtol=5e-3, atol=2e-5)
+    h.ae_set_score_kind(ta.AE_SCORE_ERROR)
     assert sc[it == 0].max(initial=0.0) == 0.0
     state = h.ae_get_state()
     h2 = ta.Handle(0)

@@ -256,6 +256,47 @@ def test_outliers_ties_and_constant_columns(ta, h, oracle):
         assert np.array_equal(o["rank_flag"].cpu().numpy(), flag)
 
 
+@pytest.mark.parametrize("R", [1, 2, 63, 64, 65, 1000, 4099])
+@pytest.mark.parametrize("style", ["narrow", "wide", "signed", "heavy_ties"])
+def test_outliers_column_shapes(ta, h, oracle, R, style):
+    """Ranks counts around the 64-rank tiles of the column-major scan, value
+    ranges that take one to four 11-bit digits, negative cells, mass ties,
+    ranks without iterations and columns with no valid rank."""
+    import torch
+    print(f"[parity] outliers columns R={R} style={style}", flush=True)
+    rng = np.random.default_rng(R * 7 + len(style))
+    I, G = 5, 3
+    if style == "narrow":
+        T = rng.integers(0, 40, (R, I, G))
+    elif style == "wide":
+        T = rng.integers(0, 1 << 44, (R, I, G))
+    elif style == "signed":
+        T = rng.integers(-(1 << 30), 1 << 30, (R, I, G))
+    else:
+        T = np.where(rng.random((R, I, G)) < 0.7, 1000, rng.integers(0, 1 << 20, (R, I, G)))
+    T = T.astype(np.int64)
+    it = rng.integers(0, I, R).astype(np.int32)       # iteration I-1 valid for no rank
+    it[: max(1, R // 2)] = I - 1
+    if R > 3:
+        it[3] = 0
+    dT, dit = torch.from_numpy(T).cuda(), torch.from_numpy(it).cuda()
+    for mode in (0, 1):
+        for kind in (0, 1):
+            o = h.outliers(dT, dit, mode=mode, kind=kind, tau=3.5, region=True)
+            st, score, flag, nf, reg = oracle.outliers(T, it, mode=mode, kind=kind, tau=3.5)
+            assert st == 0
+            go = {k: v.cpu().numpy() for k, v in o.items()}
+            if kind == 0:
+                assert np.array_equal(go["region_score"], reg), (mode, kind)
+                assert np.array_equal(go["rank_score"], score), (mode, kind)
+                assert np.array_equal(go["rank_flag"], flag), (mode, kind)
+                assert int(go["n_flagged"][0]) == nf
+            else:
+                scale = max(1.0, float(np.abs(reg).max()))
+                close(go["region_score"], reg, rtol=1e-9, atol=1e-12 * scale)
+                close(go["rank_score"], score, rtol=1e-9, atol=1e-12 * scale)
+
+
 def test_topology_parity(ta, h, oracle):
     import torch
     rng = np.random.default_rng(3)
