@@ -70,8 +70,17 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample-ranks", type=int, default=6000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-prescreen", action="store_true",
+                    help="skip training and judging the learned pre-screen")
+    ap.add_argument("--prescreen-epochs", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (the "
+                         "reference kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by rank "
               "across GPUs by design but no multi-GPU run is part of this benchmark.",
@@ -170,6 +179,13 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_sample_ranks, I, E / R)
 
+    fused.close()
+    del fused, seg, o, tr, w
+    torch.cuda.empty_cache()
+    pre = None
+    if not args.no_prescreen:
+        pre = prescreen_summary(h, args.prescreen_epochs)
+
     value = E / (ms_step / 1e3)
     line = {
         "metric": "trace events/s into rank x iteration x region tensor (whole step: "
@@ -200,10 +216,56 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel_source_sha256_12": src_hash},
         "cpu_baseline": cpu,
+        "prescreen": pre,
     }
     print(json.dumps(line))
-    fused.close()
     h.close()
+
+
+def copy_calibration(mib: int):
+    """A plain copy of known size: each dispatch reads and writes mib MiB."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_dispatch": n, "dispatches": 3}))
+
+
+def prescreen_summary(h, epochs):
+    """Train the autoencoder on five runs of the pre-screen workload (10,000
+    ranks, 500 iterations, 64 regions, no injected slow ranks) and judge it
+    against the exact FULL scan on five held-out runs with 0.5..5% injected
+    slow ranks (recall, precision, GPU time of each)."""
+    from paper_2605_03561_amd import prescreen
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    rep = prescreen.train(h, epochs=epochs, log=log)
+    summ, rows = prescreen.evaluate(h, rep["k_frac"], log=log)
+    c = prescreen.C4
+    return {
+        "workload": f"{c['n_ranks']} ranks, lognormal lengths median {c['median_len']} "
+                    f"({c['min_len']}..{c['max_len']}), {c['n_nodes']}-node tree, "
+                    f"{c['n_iters']} iterations, {c['n_regions']} regions; trained on "
+                    f"{len(prescreen.TRAIN_SEEDS)} runs without injection, judged on "
+                    f"{len(prescreen.HELD_OUT)} held-out runs with 0.5..5% injected slow ranks",
+        "epochs": rep["epochs"], "train_s": rep["train_s"],
+        "loss_first": rep["epoch_loss"][0], "loss_last": rep["epoch_loss"][-1],
+        "train_flag_rate": rep["train_flag_rate"], "k_frac": rep["k_frac"],
+        "score_kind": rep["score_kind"],
+        "recall_min": summ["recall_min"], "recall_mean": summ["recall_mean"],
+        "precision_mean": summ["precision_mean"],
+        "full_scan_ms": summ["full_scan_ms_mean"], "prescreen_ms": summ["prescreen_ms_mean"],
+        "speedup_min": summ["speedup_min"], "speedup_mean": summ["speedup_mean"],
+        "untrained_recall_mean": summ["untrained_recall_mean"],
+        "totals_scan_recall_mean": summ["totals_scan_recall_mean"],
+        "totals_scan_ms": summ["totals_scan_ms_mean"],
+        "any_fallback": summ["any_fallback"],
+        "recall_by_kind": [r["recall_by_kind"] for r in rows],
+        "untrained_recall_by_kind": [r["untrained_recall_by_kind"] for r in rows],
+        "meets_target": bool(summ["recall_min"] >= 0.99 and summ["speedup_min"] >= 5.0),
+    }
 
 
 def cpu_baseline(w, n_sample, I, mean_events):

@@ -276,8 +276,8 @@ ta_status ta_plan_destroy(ta_plan p);
  * activations on the matrix cores with FP32 accumulation and FP32 master
  * weights.  A profile row is x[r,i,g] = (T[r,i,g] - mu_g) / sigma_g over a
  * rank's valid iterations; mu, sigma are fitted on training tensors.  The rank
- * score is max_g mean_i (y - x)^2.  All need n_regions == 64.  The state lives
- * in the handle. */
+ * score is chosen by ta_ae_set_score_kind.  All need n_regions == 64.  The
+ * state lives in the handle. */
 
 /* Xavier-uniform weights from SplitMix64 draws of `seed`, zero biases and
  * optimiser moments, step 0. */
@@ -306,9 +306,15 @@ ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t ep
 /* Score used by ta_ae_score / ta_prescreen: TA_AE_SCORE_ERROR (default) =
  * max_g mean_i (y - x)^2, the reconstruction error; TA_AE_SCORE_RESIDUAL =
  * max_g |mean_i (y - x)|, a region's persistent residual over the rank's
- * iterations.  Saved with the network state. */
-enum { TA_AE_SCORE_ERROR = 0, TA_AE_SCORE_RESIDUAL = 1 };
+ * iterations; TA_AE_SCORE_RESIDUAL_Z = max_g |z(r,g)| where z is the robust
+ * z-score over ranks (median, 1.4826 * MAD, mean-absolute-deviation fallback:
+ * the exact scan's second stage) of m(r,g) = mean_i (y - x) -- the network's
+ * residual takes the place of the exact scan's per-cell first stage.  Saved
+ * with the network state. */
+enum { TA_AE_SCORE_ERROR = 0, TA_AE_SCORE_RESIDUAL = 1, TA_AE_SCORE_RESIDUAL_Z = 2 };
 ta_status ta_ae_set_score_kind(ta_handle h, int32_t kind);
+/* The score kind in use (host int32). */
+ta_status ta_ae_get_score_kind(ta_handle h, int32_t *kind_host);
 /* rank_score[r] (device FP32) for every rank; ranks without iterations score 0. */
 ta_status ta_ae_score(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
                       int32_t n_regions, const int32_t *iters_found, float *rank_score,

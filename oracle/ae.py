@@ -162,19 +162,52 @@ def adam_update(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return p, m, v
 
 
+def robust_z(v: np.ndarray) -> np.ndarray:
+    """Robust z-score of a sample: (v - median) / (1.4826 * MAD); when MAD is 0,
+    1.253314 * mean absolute deviation replaces the denominator; when that is
+    0 too, every z is 0.  Medians of an even count average the two middle
+    values (the same rule as the exact scan's second stage)."""
+    v = np.asarray(v, np.float64)
+    if v.size == 0:
+        return v.copy()
+    med = np.median(v)
+    dev = np.abs(v - med)
+    mad = np.median(dev)
+    if mad > 0:
+        return (v - med) / (1.4826 * mad)
+    mean_ad = dev.mean()
+    if mean_ad > 0:
+        return (v - med) / (1.253314 * mean_ad)
+    return np.zeros_like(v)
+
+
 def rank_scores(p: dict, T: np.ndarray, iters, mu, sd, bf16: bool = False,
                 kind: int = 0) -> np.ndarray:
     """kind 0: score[r] = max_g mean_{i < iters[r]} (y - x)^2 (reconstruction
-    error); kind 1: score[r] = max_g |mean_{i < iters[r]} (y - x)| (persistent
-    residual of a region over the rank's iterations)."""
+    error); kind 1: score[r] = max_g |m(r,g)| with m(r,g) = mean_{i < iters[r]}
+    (y - x) (persistent residual of a region over the rank's iterations);
+    kind 2: score[r] = max_g |robust_z over ranks with iterations of m(., g)|.
+    Ranks without iterations score 0 and take no part in kind 2."""
     R, I, G = T.shape
     X = normalize(T, mu, sd)
-    out = np.zeros(R)
+    err = np.zeros((R, G))
+    m = np.zeros((R, G))
+    active = np.zeros(R, bool)
     for r in range(R):
-        n = int(min(iters[r], I))
-        if n == 0:
+        n = int(min(iters[r], I)) if iters is not None else I
+        if n <= 0:
             continue
+        active[r] = True
         _, a = forward(p, X[r, :n], bf16)
         res = a[-1] - X[r, :n].astype(np.float64)
-        out[r] = (res ** 2).mean(0).max() if kind == 0 else np.abs(res.mean(0)).max()
+        err[r] = (res ** 2).mean(0)
+        m[r] = res.mean(0)
+    if kind == 0:
+        return np.where(active, err.max(1), 0.0)
+    if kind == 1:
+        return np.where(active, np.abs(m).max(1), 0.0)
+    out = np.zeros(R)
+    for g in range(G):
+        z = robust_z(m[active, g])
+        out[active] = np.maximum(out[active], np.abs(z))
     return out

@@ -9,6 +9,7 @@
 // a step is deterministic.
 #include "ta_ae.h"
 #include "ta_device.h"
+#include "ta_internal.h"
 
 namespace ta {
 namespace {
@@ -51,6 +52,12 @@ __device__ inline int out_col() { return threadIdx.x & 15; }
 
 // Sum of a value over the four lane groups that hold the same column.
 __device__ inline float col_sum(float v) {
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+__device__ inline double col_sum(double v) {
   v += __shfl_xor(v, 16, 64);
   v += __shfl_xor(v, 32, 64);
   return v;
@@ -477,12 +484,18 @@ __global__ __launch_bounds__(256) void ae_rows_fill(const int64_t *__restrict__ 
 
 // ---------------------------------------------------------------------------
 // Scoring.  One wave per rank (8 waves per workgroup share the weights in
-// LDS); the rank's profile rows go through the network in tiles of 16 with
-// v_mfma_f32_16x16x32_bf16, operands read as 16-byte LDS vectors from padded
-// rows.  No workgroup barrier after the weights are staged.
+// LDS).  The rank's profile rows go through the network 32 at a time, as two
+// 16-row tiles of v_mfma_f32_16x16x32_bf16: every weight fragment read from
+// LDS feeds both tiles, and each layer's input fragments are read once and kept
+// in registers across its output tiles.  The FP32 input tile and the hidden
+// tile share one LDS buffer (the inputs the residual needs are held in
+// registers in the output layout), and the next 32 rows are loaded from HBM
+// into registers while the current ones are in the network.  No workgroup
+// barrier after the weights are staged.
 //   kind 0: score = max_g mean_i (y - x)^2     kind 1: max_g |mean_i (y - x)|
 // ---------------------------------------------------------------------------
 constexpr int SW = 8;                  // waves per workgroup
+constexpr int SR = 32;                 // rows per wave step (two MFMA tiles)
 constexpr int P_W1 = 72, P_W2 = 136, P_W3 = 40, P_W4 = 136;   // padded row strides (bf16)
 constexpr int P_X = 68;                // FP32 row stride of the input tile
 constexpr int P_H = 136, P_H2 = 40;    // bf16 row strides of the hidden tiles
@@ -495,11 +508,14 @@ struct ScoreLds {
   float b[AE_NP - AE_NW];
   float mu[AE_IN], isd[AE_IN];
   struct Wave {
-    float X[TR * P_X];
-    uint16_t H[TR * P_H];     // first and third hidden layers (one after the other)
-    uint16_t H2[TR * P_H2];
+    union {
+      float X[SR * P_X];       // normalised inputs (FP32)
+      uint16_t H[SR * P_H];    // first, then third hidden layer (bf16)
+    } u;
+    uint16_t H2[SR * P_H2];
   } wv[SW];
 };
+static_assert(SR * P_X * 4 == SR * P_H * 2, "input and hidden tiles share a buffer");
 
 __device__ inline bf8 ld_bf8(const uint16_t *p) {
   return __builtin_bit_cast(bf8, *reinterpret_cast<const u4v *>(p));
@@ -516,6 +532,8 @@ __device__ inline bf8 ld_bf8_from_f32(const float *p) {
   return __builtin_bit_cast(bf8, u);
 }
 
+// Orders this wave's LDS accesses: every earlier LDS read and write of the
+// wave has completed before any later one is issued.
 __device__ inline void lds_wave_sync() {
   __builtin_amdgcn_wave_barrier();
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -530,7 +548,7 @@ __global__ __launch_bounds__(SW * 64) void ae_score_kernel(const int64_t *__rest
                                                            const uint16_t *__restrict__ wb,
                                                            const float *__restrict__ w,
                                                            const float *mu, const float *isd,
-                                                           int kind, float *score) {
+                                                           int kind, float *score, double *v_t) {
   extern __shared__ __align__(16) unsigned char smem[];
   ScoreLds &L = *reinterpret_cast<ScoreLds *>(smem);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -548,9 +566,15 @@ __global__ __launch_bounds__(SW * 64) void ae_score_kernel(const int64_t *__rest
   }
   __syncthreads();
   auto &V = L.wv[wid];
+  float *X = V.u.X;
+  uint16_t *H = V.u.H;
+  // MFMA operand layout: A/B lane -> row lane & 15, k = 8 * (lane >> 4) + 0..7;
+  // D lane -> rows 4 * (lane >> 4) + 0..3, column lane & 15.
   const int row = lane & 15, kq = 8 * (lane >> 4), col = lane & 15, rq = 4 * (lane >> 4);
-  // row loading: lane -> tile row lane/4, columns 16*(lane%4) .. +15
-  const int lr = lane >> 2, lc = 16 * (lane & 3);
+  // Loader: load h of a step reads rows 2h, 2h+1 (1 KB contiguous); lane ->
+  // row 2h + lane / 32, columns lc, lc + 1.
+  const int lh = lane >> 5, lc = 2 * (lane & 31);
+  const float m0 = L.mu[lc], m1 = L.mu[lc + 1], s0 = L.isd[lc], s1 = L.isd[lc + 1];
   const float *bias = L.b;
   const int64_t nw = (int64_t)gridDim.x * SW;
   for (int64_t r = (int64_t)blockIdx.x * SW + wid; r < R; r += nw) {
@@ -558,109 +582,155 @@ __global__ __launch_bounds__(SW * 64) void ae_score_kernel(const int64_t *__rest
     if (n > I) n = I;
     if (n < 0) n = 0;
     const int64_t *src = T + r * (int64_t)I * AE_IN;
-    float e2[4] = {0.f, 0.f, 0.f, 0.f}, rs[4] = {0.f, 0.f, 0.f, 0.f};
-    int64_t cur[16], nxt[16];
-    auto load = [&](int i0, int64_t *dst) {
-      const int i = i0 + lr;
-      if (i < n) {
-        const u4v *q = reinterpret_cast<const u4v *>(src + (int64_t)i * AE_IN + lc);
+    // FP64 sums of the FP32 residuals: rows with equal residuals give exactly
+    // equal means whatever the number of iterations (the robust z of kind 2
+    // must see exact ties); squared errors are summed in FP32.
+    float e2[4] = {0.f, 0.f, 0.f, 0.f};
+    double rs[4] = {0.0, 0.0, 0.0, 0.0};
+    u4v buf[16];
+    auto load = [&](int i0) {
 #pragma unroll
-        for (int h = 0; h < 8; h++) {
-          const u4v x = __builtin_nontemporal_load(q + h);
-          dst[2 * h] = (int64_t)(((uint64_t)x[1] << 32) | x[0]);
-          dst[2 * h + 1] = (int64_t)(((uint64_t)x[3] << 32) | x[2]);
-        }
-      } else {
-#pragma unroll
-        for (int h = 0; h < 16; h++) dst[h] = 0;
+      for (int h = 0; h < 16; h++) {
+        const int i = i0 + 2 * h + lh;
+        if (i < n)
+          buf[h] = __builtin_nontemporal_load(
+              reinterpret_cast<const u4v *>(src + (int64_t)i * AE_IN + lc));
       }
     };
-    if (n > 0) load(0, cur);
-    for (int i0 = 0; i0 < n; i0 += TR) {
-      if (i0 + TR < n) load(i0 + TR, nxt);
-      // normalised input tile (FP32) of this wave
-      {
-        const bool ok = i0 + lr < n;
+    if (n > 0) load(0);
+    for (int i0 = 0; i0 < n; i0 += SR) {
 #pragma unroll
-        for (int h = 0; h < 16; h += 4) {
-          float4 x;
-          x.x = ok ? ((float)cur[h] - L.mu[lc + h]) * L.isd[lc + h] : 0.f;
-          x.y = ok ? ((float)cur[h + 1] - L.mu[lc + h + 1]) * L.isd[lc + h + 1] : 0.f;
-          x.z = ok ? ((float)cur[h + 2] - L.mu[lc + h + 2]) * L.isd[lc + h + 2] : 0.f;
-          x.w = ok ? ((float)cur[h + 3] - L.mu[lc + h + 3]) * L.isd[lc + h + 3] : 0.f;
-          *reinterpret_cast<float4 *>(&V.X[lr * P_X + lc + h]) = x;
+      for (int h = 0; h < 16; h++) {  // normalised inputs of this step (rows past n are zero)
+        const int i = 2 * h + lh;
+        const bool ok = i0 + i < n;
+        const int64_t x0 = (int64_t)(((uint64_t)buf[h][1] << 32) | buf[h][0]);
+        const int64_t x1 = (int64_t)(((uint64_t)buf[h][3] << 32) | buf[h][2]);
+        float2 x;
+        x.x = ok ? ((float)x0 - m0) * s0 : 0.f;
+        x.y = ok ? ((float)x1 - m1) * s1 : 0.f;
+        *reinterpret_cast<float2 *>(&X[i * P_X + lc]) = x;
+      }
+      if (i0 + SR < n) load(i0 + SR);  // next step's rows, in flight during the network
+      lds_wave_sync();
+      bf8 a1[2][2];
+      float xr[2][4][4];
+#pragma unroll
+      for (int t = 0; t < 2; t++) {
+#pragma unroll
+        for (int k = 0; k < 2; k++) a1[t][k] = ld_bf8_from_f32(&X[(16 * t + row) * P_X + 32 * k + kq]);
+#pragma unroll
+        for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) xr[t][nt][j] = X[(16 * t + rq + j) * P_X + 16 * nt + col];
+      }
+      lds_wave_sync();
+      // L1: [32 x 64] -> [32 x 128]
+#pragma unroll
+      for (int nt = 0; nt < AE_H1 / 16; nt++) {
+        const bf8 b0 = ld_bf8(&L.W1[(16 * nt + row) * P_W1 + kq]);
+        const bf8 b1 = ld_bf8(&L.W1[(16 * nt + row) * P_W1 + 32 + kq]);
+        const int c = 16 * nt + col;
+        const float bc = bias[c];
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+          f4 acc = {0.f, 0.f, 0.f, 0.f};
+          acc = mfma32(a1[t][0], b0, acc);
+          acc = mfma32(a1[t][1], b1, acc);
+#pragma unroll
+          for (int j = 0; j < 4; j++) H[(16 * t + rq + j) * P_H + c] = f2bf(fmaxf(acc[j] + bc, 0.f));
         }
       }
       lds_wave_sync();
-      // L1: [16 x 64] -> [16 x 128]
+      // L2: [32 x 128] -> [32 x 32]
+      {
+        bf8 a2[2][4];
 #pragma unroll
-      for (int nt = 0; nt < AE_H1 / 16; nt++) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < 2; t++)
 #pragma unroll
-        for (int k0 = 0; k0 < AE_IN; k0 += 32)
-          acc = mfma32(ld_bf8_from_f32(&V.X[row * P_X + k0 + kq]),
-                       ld_bf8(&L.W1[(16 * nt + row) * P_W1 + k0 + kq]), acc);
-        const int c = 16 * nt + col;
+          for (int k = 0; k < 4; k++) a2[t][k] = ld_bf8(&H[(16 * t + row) * P_H + 32 * k + kq]);
 #pragma unroll
-        for (int j = 0; j < 4; j++) V.H[(rq + j) * P_H + c] = f2bf(fmaxf(acc[j] + bias[c], 0.f));
-      }
-      lds_wave_sync();
-      // L2: [16 x 128] -> [16 x 32]
+        for (int nt = 0; nt < AE_H2 / 16; nt++) {
+          bf8 bw[4];
 #pragma unroll
-      for (int nt = 0; nt < AE_H2 / 16; nt++) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
+          for (int k = 0; k < 4; k++) bw[k] = ld_bf8(&L.W2[(16 * nt + row) * P_W2 + 32 * k + kq]);
+          const int c = 16 * nt + col;
+          const float bc = bias[AE_B2 - AE_B1 + c];
 #pragma unroll
-        for (int k0 = 0; k0 < AE_H1; k0 += 32)
-          acc = mfma32(ld_bf8(&V.H[row * P_H + k0 + kq]), ld_bf8(&L.W2[(16 * nt + row) * P_W2 + k0 + kq]),
-                       acc);
-        const int c = 16 * nt + col;
+          for (int t = 0; t < 2; t++) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < 4; j++)
-          V.H2[(rq + j) * P_H2 + c] = f2bf(fmaxf(acc[j] + bias[AE_B2 - AE_B1 + c], 0.f));
-      }
-      lds_wave_sync();
-      // L3: [16 x 32] -> [16 x 128]
+            for (int k = 0; k < 4; k++) acc = mfma32(a2[t][k], bw[k], acc);
 #pragma unroll
-      for (int nt = 0; nt < AE_H3 / 16; nt++) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma32(ld_bf8(&V.H2[row * P_H2 + kq]), ld_bf8(&L.W3[(16 * nt + row) * P_W3 + kq]), acc);
-        const int c = 16 * nt + col;
-#pragma unroll
-        for (int j = 0; j < 4; j++)
-          V.H[(rq + j) * P_H + c] = f2bf(fmaxf(acc[j] + bias[AE_B3 - AE_B1 + c], 0.f));
-      }
-      lds_wave_sync();
-      // L4: [16 x 128] -> [16 x 64], residuals of the valid rows
-#pragma unroll
-      for (int nt = 0; nt < AE_IN / 16; nt++) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k0 = 0; k0 < AE_H3; k0 += 32)
-          acc = mfma32(ld_bf8(&V.H[row * P_H + k0 + kq]), ld_bf8(&L.W4[(16 * nt + row) * P_W4 + k0 + kq]),
-                       acc);
-        const int c = 16 * nt + col;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          if (i0 + rq + j < n) {
-            const float res = acc[j] + bias[AE_B4 - AE_B1 + c] - V.X[(rq + j) * P_X + c];
-            e2[nt] += res * res;
-            rs[nt] += res;
+            for (int j = 0; j < 4; j++) V.H2[(16 * t + rq + j) * P_H2 + c] = f2bf(fmaxf(acc[j] + bc, 0.f));
           }
         }
       }
       lds_wave_sync();
+      // L3: [32 x 32] -> [32 x 128]
+      {
+        bf8 a3[2];
 #pragma unroll
-      for (int h = 0; h < 16; h++) cur[h] = nxt[h];
+        for (int t = 0; t < 2; t++) a3[t] = ld_bf8(&V.H2[(16 * t + row) * P_H2 + kq]);
+#pragma unroll
+        for (int nt = 0; nt < AE_H3 / 16; nt++) {
+          const bf8 bw = ld_bf8(&L.W3[(16 * nt + row) * P_W3 + kq]);
+          const int c = 16 * nt + col;
+          const float bc = bias[AE_B3 - AE_B1 + c];
+#pragma unroll
+          for (int t = 0; t < 2; t++) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mfma32(a3[t], bw, acc);
+#pragma unroll
+            for (int j = 0; j < 4; j++) H[(16 * t + rq + j) * P_H + c] = f2bf(fmaxf(acc[j] + bc, 0.f));
+          }
+        }
+      }
+      lds_wave_sync();
+      // L4: [32 x 128] -> [32 x 64], residuals of the valid rows
+      {
+        bf8 a4[2][4];
+#pragma unroll
+        for (int t = 0; t < 2; t++)
+#pragma unroll
+          for (int k = 0; k < 4; k++) a4[t][k] = ld_bf8(&H[(16 * t + row) * P_H + 32 * k + kq]);
+#pragma unroll
+        for (int nt = 0; nt < AE_IN / 16; nt++) {
+          bf8 bw[4];
+#pragma unroll
+          for (int k = 0; k < 4; k++) bw[k] = ld_bf8(&L.W4[(16 * nt + row) * P_W4 + 32 * k + kq]);
+          const float bc = bias[AE_B4 - AE_B1 + 16 * nt + col];
+#pragma unroll
+          for (int t = 0; t < 2; t++) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 4; k++) acc = mfma32(a4[t][k], bw[k], acc);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+              if (i0 + 16 * t + rq + j < n) {
+                const float res = acc[j] + bc - xr[t][nt][j];
+                e2[nt] += res * res;
+                rs[nt] += (double)res;
+              }
+            }
+          }
+        }
+      }
+      lds_wave_sync();  // the next step's inputs overwrite H
     }
     float best = 0.f;
 #pragma unroll
     for (int nt = 0; nt < 4; nt++) {
-      const float a = col_sum(e2[nt]), b = col_sum(rs[nt]);
-      const float v = n > 0 ? (kind == 0 ? a : fabsf(b)) / (float)n : 0.f;
-      best = fmaxf(best, v);
+      const float a = col_sum(e2[nt]);
+      const double b = col_sum(rs[nt]);
+      if (kind == 2) {
+        if (lane < 16) v_t[(int64_t)(16 * nt + col) * R + r] = n > 0 ? b / (double)n : 0.0;
+      } else {
+        const float v = n > 0 ? (kind == 0 ? a / (float)n : (float)(fabs(b) / (double)n)) : 0.f;
+        best = fmaxf(best, v);
+      }
     }
     for (int d = 32; d >= 1; d >>= 1) best = fmaxf(best, __shfl_xor(best, d, 64));
-    if (lane == 0) score[r] = best;
+    if (kind != 2 && lane == 0) score[r] = best;
   }
 }
 
@@ -781,7 +851,7 @@ hipError_t ae_alloc(AeState &s) {
 void ae_free(AeState &s) {
   void *ps[] = {s.w, s.wb, s.m, s.v, s.mu, s.isd, s.nsum, s.nsq, s.ncnt, s.part, s.loss};
   for (void *p : ps)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   s = AeState{};
 }
 
@@ -832,7 +902,7 @@ template <class K>
 void allow_lds(K k) {
   static bool done = false;
   if (!done) {
-    hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)sizeof(AeLds));
     done = true;
   }
@@ -860,23 +930,32 @@ hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, 
   return hipGetLastError();
 }
 
+size_t ae_score_ws_bytes(int64_t R) { return 2 * (((size_t)R * AE_IN * 8 + 255) & ~(size_t)255); }
+
 hipError_t launch_ae_score(const AeState &s, const int64_t *T, int64_t R, int I, const int32_t *it,
-                           float *score, hipStream_t st) {
+                           float *score, void *ws, size_t ws_bytes, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void *>(&ae_score_kernel),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&ae_score_kernel),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(ScoreLds));
     attr = true;
   }
+  if (R <= 0) return hipSuccess;
+  const bool stage2 = s.score_kind == 2;
+  const size_t half = ae_score_ws_bytes(R) / 2;
+  if (stage2 && (ws == nullptr || ws_bytes < 2 * half)) return hipErrorInvalidValue;
+  double *v_t = stage2 ? (double *)ws : nullptr;
+  double *z_t = stage2 ? (double *)((char *)ws + half) : nullptr;
   int cus = 256, dev = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int64_t grid = (R + SW - 1) / SW;
   if (grid > cus) grid = cus;
-  if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(ae_score_kernel, dim3((unsigned)grid), dim3(SW * 64), sizeof(ScoreLds), st, T, R,
-                     I, it, s.wb, s.w, s.mu, s.isd, s.score_kind, score);
-  return hipGetLastError();
+                     I, it, s.wb, s.w, s.mu, s.isd, s.score_kind, score, v_t);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && stage2) e = launch_region_robust(v_t, R, AE_IN, it, I, z_t, score, st);
+  return e;
 }
 
 hipError_t launch_topk(const float *score, int64_t R, int64_t k, int32_t *idx, int32_t *n_above,

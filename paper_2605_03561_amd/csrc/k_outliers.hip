@@ -83,13 +83,32 @@ typedef long long v2ll __attribute__((ext_vector_type(2)));
 
 __device__ inline uint64_t shr64(uint64_t x, int s) { return s >= 64 ? 0 : x >> s; }
 
-struct ColSelLds {
+constexpr int MS = 2048;          // sample slots (LDS)
+constexpr int SEL_GRID_MAX = 1024; // column workgroups (persistent, one scratch slot each)
+constexpr int64_t SEL_BRACKET_MIN_RP = 32768;  // shorter columns: whole-column radix selection
+
+// LDS of the radix selection (and of the column reductions).
+struct SelLds {
   uint32_t hist[NHC][NB];
   int64_t red[CS];
   uint64_t ured[CS];
   int64_t wtot[CWV];
   uint64_t state[4];
 };
+
+struct ColSelLds : SelLds {
+  int64_t samp[MS];
+  uint32_t ns, cin;  // sample count, bracket count
+};
+
+// Scratch slot per column workgroup: the values inside a bracket (expected
+// about 2 * 5 / sqrt(2048) = 22 % of the column).
+__host__ __device__ inline int64_t sel_cap(int64_t R) {
+  const int64_t Rp = pad_ranks(R);
+  int64_t c = ((Rp * 35 / 100) + 63) & ~(int64_t)63;
+  if (c < 4096) c = 4096;
+  return c;
+}
 
 // f(x) for every cell of the padded column, sentinels included.
 template <class F>
@@ -110,68 +129,102 @@ __device__ __forceinline__ void sweep(const int64_t *__restrict__ col, int64_t R
   }
 }
 
-__device__ inline uint64_t block_min_u64(uint64_t v, uint64_t *buf) {
-  const int t = threadIdx.x;
-  buf[t] = v;
-  __syncthreads();
-  for (int st = CS / 2; st > 0; st >>= 1) {
-    if (t < st && buf[t + st] < buf[t]) buf[t] = buf[t + st];
-    __syncthreads();
+// Block reductions of the column workgroup: a shuffle reduction in each wave,
+// one barrier, then every thread combines the CWV wave results in wave order,
+// and a second barrier before the slots are reused.  `slots` holds CWV * K
+// values.
+__device__ inline uint64_t block_min_u64(uint64_t v, uint64_t *slots) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t o = __shfl_xor(v, d, 64);
+    v = o < v ? o : v;
   }
-  const uint64_t r = buf[0];
+  if ((threadIdx.x & 63) == 0) slots[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t r = slots[0];
+  for (int q = 1; q < CWV; q++) r = slots[q] < r ? slots[q] : r;
   __syncthreads();
   return r;
 }
 
-__device__ inline int64_t block_minmax_i64(int64_t v, bool is_max, int64_t *buf) {
-  const int t = threadIdx.x;
-  buf[t] = v;
-  __syncthreads();
-  for (int st = CS / 2; st > 0; st >>= 1) {
-    if (t < st) {
-      const int64_t o = buf[t + st];
-      if (is_max ? o > buf[t] : o < buf[t]) buf[t] = o;
+// K sums, then (with MM) a minimum and a maximum, in one exchange.
+template <int K, bool MM>
+__device__ inline void block_stats(int64_t (&v)[K], int64_t &mn, int64_t &mx, int64_t *slots) {
+  constexpr int W = K + (MM ? 2 : 0);
+  for (int d = 32; d >= 1; d >>= 1) {
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] += __shfl_xor(v[k], d, 64);
+    if (MM) {
+      const int64_t a = __shfl_xor(mn, d, 64), b = __shfl_xor(mx, d, 64);
+      mn = a < mn ? a : mn;
+      mx = b > mx ? b : mx;
     }
-    __syncthreads();
   }
-  const int64_t r = buf[0];
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; k++) slots[wid * W + k] = v[k];
+    if (MM) {
+      slots[wid * W + K] = mn;
+      slots[wid * W + K + 1] = mx;
+    }
+  }
   __syncthreads();
-  return r;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    int64_t s = 0;
+    for (int q = 0; q < CWV; q++) s += slots[q * W + k];
+    v[k] = s;
+  }
+  if (MM) {
+    mn = slots[K];
+    mx = slots[K + 1];
+    for (int q = 1; q < CWV; q++) {
+      mn = slots[q * W + K] < mn ? slots[q * W + K] : mn;
+      mx = slots[q * W + K + 1] > mx ? slots[q * W + K + 1] : mx;
+    }
+  }
+  __syncthreads();
 }
 
-// Lower median (rank (n-1)/2) of key(x) over the valid cells, keys in
-// [0, 2^bits), and the next order statistic (equal to it for odd n).  With
-// SUMD, also returns the sum of the keys (the first pass reads every cell).
-template <bool SUMD, class KeyF>
-__device__ void col_radix_select(const int64_t *__restrict__ col, int64_t Rp, int64_t n, int bits,
-                                 KeyF keyf, ColSelLds &L, uint64_t &v1, uint64_t &v2,
-                                 int64_t &ksum) {
+__device__ inline int64_t block_sum1(int64_t v, int64_t *slots) {
+  int64_t a[1] = {v}, d0 = 0, d1 = 0;
+  block_stats<1, false>(a, d0, d1, slots);
+  return a[0];
+}
+
+// The k-th smallest key (k from 0) of the values a source visits, keys in
+// [0, 2^bits), and with want_next the (k+1)-th (which must exist).  `visit(f)`
+// calls f(x) for every value of this thread's share of the source; `keyf(x)`
+// maps a value to its key.
+template <class Visit, class KeyF>
+__device__ void radix_select(Visit &&visit, int64_t k, bool want_next, int bits, KeyF keyf,
+                             SelLds &L, uint64_t &v1, uint64_t &v2, int64_t *key_sum = nullptr) {
   const int t = threadIdx.x, wid = t >> 6, lane = t & 63;
   uint32_t *hist = L.hist[wid & (NHC - 1)];
   uint64_t pref = 0;
-  int64_t k = (n - 1) / 2;
   int hi = bits;
   bool first = true;
-  ksum = 0;
+  v1 = v2 = 0;
+  if (key_sum && bits == 0) *key_sum = 0;
   while (hi > 0) {
     const int w = hi < DIG ? hi : DIG;
     const int lo = hi - w;
     const bool last = lo == 0;
     const uint64_t mask = (1ull << w) - 1;
+    const bool sum_keys = key_sum != nullptr && first;
     uint64_t mgt = ~0ull;
-    int64_t sk = 0;
-    const bool sumd = SUMD && first;
-    sweep(col, Rp, [&](int64_t x) {
-      if (x == SENT) return;
+    int64_t ks = 0;
+    visit([&](int64_t x) {
       const uint64_t key = keyf(x);
-      if (sumd) sk += (int64_t)key;
+      if (sum_keys) ks += (int64_t)key;
       const uint64_t top = shr64(key, hi);
       if (top == pref)
         atomicAdd(&hist[(uint32_t)((key >> lo) & mask)], 1u);
       else if (last && top > pref && key < mgt)
         mgt = key;
     });
-    if (sumd) ksum = block_sum_i64<CS>(sk, L.red);
+    if (sum_keys) *key_sum = block_sum1(ks, L.red);
+    first = false;
     if (last) mgt = block_min_u64(mgt, L.ured);  // includes the barrier
     else __syncthreads();
     // Bin search: thread t owns bins [t*BPT, t*BPT + BPT) (merged copies).
@@ -183,8 +236,8 @@ __device__ void col_radix_select(const int64_t *__restrict__ col, int64_t Rp, in
       uint32_t c = 0;
 #pragma unroll
       for (int q = 0; q < NHC; q++) c += L.hist[q][bb];
-      cnt[j] = (bb >> w) ? 0u : c;  // bins beyond this digit's width are empty
-      own += cnt[j];
+      cnt[j] = c;
+      own += c;
     }
     int64_t incl = own;  // inclusive scan over the wave
     for (int d = 1; d < 64; d <<= 1) {
@@ -195,8 +248,7 @@ __device__ void col_radix_select(const int64_t *__restrict__ col, int64_t Rp, in
     __syncthreads();
     int64_t excl = incl - own;
     for (int q = 0; q < wid; q++) excl += L.wtot[q];
-    // Clear the histograms for the next pass (all reads above are done after
-    // the barrier below; the merged counts live in registers).
+    // All histogram reads above precede this barrier; clear for the next pass.
     __syncthreads();
     for (int j = t; j < NHC * NB; j += CS) (&L.hist[0][0])[j] = 0;
     if (excl <= k && k < excl + own) {
@@ -207,19 +259,19 @@ __device__ void col_radix_select(const int64_t *__restrict__ col, int64_t Rp, in
         cum += cnt[j];
       }
       const int64_t kk = k - cum;
-      const int bsel = t * BPT + j;
-      L.state[0] = (pref << w) | (uint64_t)bsel;
+      L.state[0] = (pref << w) | (uint64_t)(t * BPT + j);
       L.state[1] = (uint64_t)kk;
-      // Upper middle of an even count on the last digit: the same bin when it
-      // holds another key, else the next non-empty bin (searched below).
+      // On the last digit the (k+1)-th key is in the same bin when the bin
+      // holds another key, else in the next non-empty bin (searched below).
       L.state[2] = (kk + 1 < (int64_t)cnt[j]) ? 1 : 0;
     }
     __syncthreads();
     const uint64_t np = L.state[0];
     const int64_t kk = (int64_t)L.state[1];
     if (last) {
+      const bool same = L.state[2] != 0;
       uint64_t nxt = ~0ull;  // smallest non-empty bin above the selected one
-      if (L.state[2] == 0) {
+      if (want_next && !same) {
         const int bsel = (int)(np & mask);
 #pragma unroll
         for (int j = BPT - 1; j >= 0; j--) {
@@ -229,41 +281,331 @@ __device__ void col_radix_select(const int64_t *__restrict__ col, int64_t Rp, in
       }
       nxt = block_min_u64(nxt, L.ured);
       v1 = np;
-      if (L.state[2]) v2 = np;
+      if (!want_next || same) v2 = np;
       else if (nxt != ~0ull) v2 = (pref << w) | nxt;
       else v2 = mgt;
-      __syncthreads();
     }
     pref = np;
     k = kk;
     hi = lo;
-    first = false;
   }
-  if (bits == 0) {
-    v1 = v2 = 0;
-    if (SUMD) ksum = 0;
-  }
-  if (n & 1) v2 = v1;
+  if (!want_next) v2 = v1;
 }
 
-__global__ __launch_bounds__(CS) void col_select(const int64_t *__restrict__ Tt, int64_t R,
+// f(x) for this thread's share of scr[0..c), eight loads in flight.
+template <class F>
+__device__ __forceinline__ void visit_scratch(const int64_t *__restrict__ scr, int64_t c, F &&f) {
+  constexpr int U = 8;
+  for (int64_t i0 = 0; i0 < c; i0 += (int64_t)CS * U) {
+    int64_t v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t i = i0 + (int64_t)u * CS + threadIdx.x;
+      v[u] = i < c ? scr[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (i0 + (int64_t)u * CS + threadIdx.x < c) f(v[u]);
+  }
+}
+
+// Append v to scratch when `in` (all lanes of the wave call this together).
+__device__ inline void wave_append(bool in, int64_t v, uint32_t *counter, int64_t *scr, int64_t cap) {
+  const uint64_t m = __ballot(in);
+  if (m == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (in) {
+    const int64_t pos = (int64_t)base + __popcll(m & ((1ull << lane) - 1));
+    if (pos < cap) scr[pos] = v;
+  }
+}
+
+// Visits the m sample values held in LDS.
+struct SampleVisit {
+  const int64_t *samp;
+  int m;
+  template <class F>
+  __device__ void operator()(F &&f) const {
+    for (int j = threadIdx.x; j < m; j += CS) f(samp[j]);
+  }
+};
+
+// Order statistics j1 and j2 of the m (> 0) sample values.
+__device__ void sample_pick(ColSelLds &L, int m, int64_t j1, int64_t j2, int64_t &v1, int64_t &v2) {
+  int64_t mnl = INT64_MAX, mxl = INT64_MIN;
+  for (int j = threadIdx.x; j < m; j += CS) {
+    const int64_t x = L.samp[j];
+    mnl = x < mnl ? x : mnl;
+    mxl = x > mxl ? x : mxl;
+  }
+  int64_t none[1] = {0}, mn = mnl, mx = mxl;
+  block_stats<1, true>(none, mn, mx, L.red);
+  const int bits = nbits64((uint64_t)mx - (uint64_t)mn);
+  auto key = [&](int64_t x) { return (uint64_t)x - (uint64_t)mn; };
+  const SampleVisit vs{L.samp, m};
+  uint64_t a, b;
+  if (j2 == j1 + 1) {
+    radix_select(vs, j1, true, bits, key, L, a, b);
+  } else {
+    radix_select(vs, j1, false, bits, key, L, a, b);
+    if (j2 != j1) radix_select(vs, j2, false, bits, key, L, b, b);
+    else b = a;
+  }
+  v1 = (int64_t)((uint64_t)mn + a);
+  v2 = (int64_t)((uint64_t)mn + b);
+}
+
+// Bracket [lo, hi] around the middle of the sample (m values): its order
+// statistics (1/2 -/+ delta)(m - 1), delta = 5 / sqrt(m).
+__device__ inline void sample_bracket(ColSelLds &L, int m, int64_t &lo, int64_t &hi) {
+  if (m <= 0) {
+    lo = INT64_MAX;  // empty bracket: the caller falls back to full selection
+    hi = INT64_MIN;
+    return;
+  }
+  const double dl = 5.0 / sqrt((double)m);
+  const double ca = (0.5 - dl) * (double)(m - 1), cb = (0.5 + dl) * (double)(m - 1);
+  const int ia = ca <= 0.0 ? 0 : (int)floor(ca);
+  const int ib = cb >= (double)(m - 1) ? m - 1 : (int)ceil(cb);
+  sample_pick(L, m, ia, ib, lo, hi);
+}
+
+// The k-th smallest value of a column (and with `even` the (k+1)-th) from the
+// counts of a bracket pass: clo values below qa, ceqa equal to qa, cmid strictly
+// inside (qa, qb) -- compacted in the scratch that `vmid` visits -- and ceqb
+// equal to qb (0 when qa == qb).  Returns false when a wanted rank lies outside
+// the bracket or the interior overflowed the scratch.
+template <class Visit>
+__device__ bool bracket_pick(Visit &&vmid, int64_t clo, int64_t ceqa, int64_t cmid, int64_t ceqb,
+                             int64_t qa, int64_t qb, int64_t cap, int64_t k, bool even,
+                             SelLds &L, int64_t &x1, int64_t &x2) {
+  auto where = [&](int64_t j) -> int {
+    if (j < clo) return 0;
+    j -= clo;
+    if (j < ceqa) return 1;
+    j -= ceqa;
+    if (j < cmid) return 2;
+    j -= cmid;
+    return j < ceqb ? 3 : 0;
+  };
+  const int w1 = where(k), w2 = even ? where(k + 1) : w1;
+  if (w1 == 0 || w2 == 0) return false;
+  if ((w1 == 2 || w2 == 2) && cmid > cap) return false;
+  const int64_t base = clo + ceqa;
+  const int bits = nbits64((uint64_t)qb - (uint64_t)qa);
+  auto key = [&](int64_t x) { return (uint64_t)x - (uint64_t)qa; };
+  auto val = [&](uint64_t kv) { return (int64_t)((uint64_t)qa + kv); };
+  uint64_t a1 = 0, a2 = 0;
+  if (w1 == 2 && w2 == 2) {
+    radix_select(vmid, k - base, even, bits, key, L, a1, a2);
+    x1 = val(a1);
+    x2 = val(a2);
+    return true;
+  }
+  if (w1 == 2) {
+    radix_select(vmid, k - base, false, bits, key, L, a1, a2);
+    x1 = val(a1);
+  } else {
+    x1 = w1 == 1 ? qa : qb;
+  }
+  if (!even) {
+    x2 = x1;
+    return true;
+  }
+  if (w2 == 2) {
+    radix_select(vmid, k + 1 - base, false, bits, key, L, a1, a2);
+    x2 = val(a1);
+  } else {
+    x2 = w2 == 1 ? qa : qb;
+  }
+  return true;
+}
+
+// Per column (at least SEL_BRACKET_MIN_RP padded ranks; persistent grid, one
+// scratch slot per workgroup): sample, then two streaming passes (median
+// bracket, MAD bracket); exact selection over the compacted bracket values, or
+// over the whole column when a bracket misses the middle or overflows the
+// scratch.
+__global__ __launch_bounds__(CS) void col_select_bracket(const int64_t *__restrict__ Tt, int64_t R, int IG,
+                                                 int64_t *__restrict__ scratch, int64_t cap,
                                                  ColSel out) {
   __shared__ ColSelLds L;
+  const int t = threadIdx.x;
+  const int64_t Rp = pad_ranks(R);
+  int64_t *scr = scratch + (int64_t)blockIdx.x * cap;
+  for (int j = t; j < NHC * NB; j += CS) (&L.hist[0][0])[j] = 0;
+  for (int c = blockIdx.x; c < IG; c += gridDim.x) {
+    const int64_t *col = Tt + (int64_t)c * Rp;
+    auto vcol = [&](auto &&f) {
+      sweep(col, Rp, [&](int64_t x) {
+        if (x != SENT) f(x);
+      });
+    };
+    // ---- sample: 512 chunks of 4 consecutive cells (Rp >= 2048) ------------
+    if (t == 0) {
+      L.ns = 0;
+      L.cin = 0;
+    }
+    __syncthreads();
+    {
+      const int64_t s0 = (((int64_t)t * Rp) / CS) & ~(int64_t)3;
+      v2ll q[2];
+      q[0] = *reinterpret_cast<const v2ll *>(col + s0);
+      q[1] = *reinterpret_cast<const v2ll *>(col + s0 + 2);
+      const int64_t x4[4] = {q[0].x, q[0].y, q[1].x, q[1].y};
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+        if (x4[u] != SENT) L.samp[atomicAdd(&L.ns, 1u)] = x4[u];
+    }
+    __syncthreads();
+    const int m = (int)L.ns;
+
+    // ---- median ------------------------------------------------------------
+    int64_t n, mn = 0, mx = 0, med2 = 0;
+    {
+      int64_t qa, qb;
+      sample_bracket(L, m, qa, qb);
+      int64_t nl = 0, cl = 0, cea = 0, ceb = 0, mnl = INT64_MAX, mxl = INT64_MIN;
+      sweep(col, Rp, [&](int64_t x) {
+        const bool ok = x != SENT;
+        if (ok) {
+          nl++;
+          mnl = x < mnl ? x : mnl;
+          mxl = x > mxl ? x : mxl;
+          cl += x < qa ? 1 : 0;
+          cea += x == qa ? 1 : 0;
+          ceb += (x == qb && qb != qa) ? 1 : 0;
+        }
+        wave_append(ok && x > qa && x < qb, x, &L.cin, scr, cap);
+      });
+      int64_t cnt[4] = {nl, cl, cea, ceb};
+      mn = mnl;
+      mx = mxl;
+      block_stats<4, true>(cnt, mn, mx, L.red);
+      n = cnt[0];
+      const int64_t clo = cnt[1], ceqa = cnt[2], ceqb = cnt[3];
+      const int64_t cmid = (int64_t)L.cin;
+      med2 = 0;
+      if (n > 0) {
+        const int64_t k = (n - 1) / 2;
+        const bool even = (n & 1) == 0;
+        const int64_t ci = cmid < cap ? cmid : cap;
+        auto vscr = [&](auto &&f) { visit_scratch(scr, ci, f); };
+        int64_t x1, x2;
+        if (!bracket_pick(vscr, clo, ceqa, cmid, ceqb, qa, qb, cap, k, even, L, x1, x2)) {
+          uint64_t a1, a2;
+          radix_select(vcol, k, even, nbits64((uint64_t)mx - (uint64_t)mn),
+                       [&](int64_t x) { return (uint64_t)x - (uint64_t)mn; }, L, a1, a2);
+          x1 = (int64_t)((uint64_t)mn + a1);
+          x2 = (int64_t)((uint64_t)mn + a2);
+        }
+        med2 = x1 + x2;
+      }
+    }
+    if (n == 0) {
+      if (t == 0) {
+        out.med2[c] = 0;
+        out.mad4[c] = 0;
+        out.sumdev[c] = 0;
+        out.n[c] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+
+    // ---- MAD: the same on the deviations |2x - med2| -------------------------
+    __syncthreads();  // every thread has read the sorted sample values it needs
+    for (int j = t; j < m; j += CS) {
+      const int64_t d = 2 * L.samp[j] - med2;
+      L.samp[j] = d < 0 ? -d : d;
+    }
+    if (t == 0) L.cin = 0;
+    __syncthreads();
+    int64_t mad4, sd;
+    {
+      int64_t da, db;
+      sample_bracket(L, m, da, db);
+      int64_t sl = 0, cl = 0, cea = 0, ceb = 0;
+      sweep(col, Rp, [&](int64_t x) {
+        const bool ok = x != SENT;
+        int64_t d = 2 * x - med2;
+        d = d < 0 ? -d : d;
+        if (ok) {
+          sl += d;
+          cl += d < da ? 1 : 0;
+          cea += d == da ? 1 : 0;
+          ceb += (d == db && db != da) ? 1 : 0;
+        }
+        wave_append(ok && d > da && d < db, d, &L.cin, scr, cap);
+      });
+      int64_t cnt[4] = {sl, cl, cea, ceb}, u0 = 0, u1 = 0;
+      block_stats<4, false>(cnt, u0, u1, L.red);
+      sd = cnt[0];
+      const int64_t clo = cnt[1], ceqa = cnt[2], ceqb = cnt[3];
+      const int64_t cmid = (int64_t)L.cin;
+      const int64_t k = (n - 1) / 2;
+      const bool even = (n & 1) == 0;
+      const int64_t ci = cmid < cap ? cmid : cap;
+      auto vscr = [&](auto &&f) { visit_scratch(scr, ci, f); };
+      int64_t x1, x2;
+      if (!bracket_pick(vscr, clo, ceqa, cmid, ceqb, da, db, cap, k, even, L, x1, x2)) {
+        // Deviations lie in [0, max(med2 - 2 mn, 2 mx - med2)].
+        const uint64_t dlo = (uint64_t)(med2 - 2 * mn), dhi = (uint64_t)(2 * mx - med2);
+        const uint64_t dmax = dlo > dhi ? dlo : dhi;
+        uint64_t a1, a2;
+        radix_select(vcol, k, even, nbits64(dmax),
+                     [&](int64_t x) {
+                       const int64_t d = 2 * x - med2;
+                       return (uint64_t)(d < 0 ? -d : d);
+                     },
+                     L, a1, a2);
+        x1 = (int64_t)a1;
+        x2 = (int64_t)a2;
+      }
+      mad4 = x1 + x2;
+    }
+    if (t == 0) {
+      out.med2[c] = med2;
+      out.mad4[c] = mad4;
+      out.sumdev[c] = sd;
+      out.n[c] = n;
+    }
+    __syncthreads();
+  }
+}
+
+// Per column, one workgroup each (columns of up to SEL_BRACKET_MIN_RP padded
+// ranks, which stay in the caches between passes): count/min/max, then radix
+// selection over the whole column for the median and for the MAD (whose first
+// pass also sums the absolute deviations).
+__global__ __launch_bounds__(CS) void col_select_radix(const int64_t *__restrict__ Tt, int64_t R,
+                                                       ColSel out) {
+  __shared__ SelLds L;
   const int c = blockIdx.x;
   const int t = threadIdx.x;
   const int64_t Rp = pad_ranks(R);
   const int64_t *col = Tt + (int64_t)c * Rp;
   for (int j = t; j < NHC * NB; j += CS) (&L.hist[0][0])[j] = 0;
+  auto vcol = [&](auto &&f) {
+    sweep(col, Rp, [&](int64_t x) {
+      if (x != SENT) f(x);
+    });
+  };
   int64_t n = 0, mn = INT64_MAX, mx = INT64_MIN;
-  sweep(col, Rp, [&](int64_t x) {
-    if (x == SENT) return;
+  vcol([&](int64_t x) {
     n++;
     mn = x < mn ? x : mn;
     mx = x > mx ? x : mx;
   });
-  n = block_sum_i64<CS>(n, L.red);
-  mn = block_minmax_i64(mn, false, L.red);
-  mx = block_minmax_i64(mx, true, L.red);
+  {
+    int64_t cnt[1] = {n};
+    block_stats<1, true>(cnt, mn, mx, L.red);
+    n = cnt[0];
+  }
   if (n == 0) {
     if (t == 0) {
       out.med2[c] = 0;
@@ -273,25 +615,24 @@ __global__ __launch_bounds__(CS) void col_select(const int64_t *__restrict__ Tt,
     }
     return;
   }
-  const uint64_t base = (uint64_t)mn;
-  uint64_t a, b;
-  int64_t unused;
-  col_radix_select<false>(col, Rp, n, nbits64((uint64_t)mx - base),
-                          [&](int64_t x) { return (uint64_t)x - base; }, L, a, b, unused);
-  const int64_t med2 = (int64_t)(base + a) + (int64_t)(base + b);
-  // Deviations |2x - med2|; the largest is at an end of the range.
+  const int64_t k = (n - 1) / 2;
+  const bool even = (n & 1) == 0;
+  uint64_t a1, a2;
+  radix_select(vcol, k, even, nbits64((uint64_t)mx - (uint64_t)mn),
+               [&](int64_t x) { return (uint64_t)x - (uint64_t)mn; }, L, a1, a2);
+  const int64_t med2 = (int64_t)((uint64_t)mn + a1) + (int64_t)((uint64_t)mn + a2);
   const uint64_t dlo = (uint64_t)(med2 - 2 * mn), dhi = (uint64_t)(2 * mx - med2);
   const uint64_t dmax = dlo > dhi ? dlo : dhi;
   int64_t sd = 0;
-  col_radix_select<true>(col, Rp, n, nbits64(dmax),
-                         [&](int64_t x) {
-                           const int64_t d = 2 * x - med2;
-                           return (uint64_t)(d < 0 ? -d : d);
-                         },
-                         L, a, b, sd);
+  radix_select(vcol, k, even, nbits64(dmax),
+               [&](int64_t x) {
+                 const int64_t d = 2 * x - med2;
+                 return (uint64_t)(d < 0 ? -d : d);
+               },
+               L, a1, a2, &sd);
   if (t == 0) {
     out.med2[c] = med2;
-    out.mad4[c] = (int64_t)(a + b);
+    out.mad4[c] = (int64_t)(a1 + a2);
     out.sumdev[c] = sd;
     out.n[c] = n;
   }
@@ -662,8 +1003,23 @@ __global__ __launch_bounds__(256) void count_final(const int64_t *part, int64_t 
   if (threadIdx.x == 0 && out) out[0] = s;
 }
 
+// Per-rank maximum |z| over regions as FP32 (ranks without iterations: 0).
+__global__ __launch_bounds__(256) void rank_max_f32(const double *z_t, int64_t R, int G,
+                                                    const int32_t *it, int I, float *score) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= R) return;
+  double best = 0.0;
+  if (rank_active(it, I, r))
+    for (int g = 0; g < G; g++) {
+      const double v = fabs(z_t[(int64_t)g * R + r]);
+      if (v > best) best = v;
+    }
+  score[r] = (float)best;
+}
+
 struct OWs {
   int64_t *Tt;      // [IG][Rp] column-major copy of the tensor (FULL)
+  int64_t *scr;     // [min(IG, SEL_GRID_MAX)][sel_cap(R)] bracket values (FULL + MAD)
   ColSel cs;
   ColMom cm;
   double *m_t;      // [G][R] doubles (FULL) -- also reused as z_t
@@ -683,6 +1039,9 @@ OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
   OWs w{};
   if (mode == TA_SCAN_FULL) {
     w.Tt = (int64_t *)take((size_t)pad_ranks(R) * IG * 8);
+    if (kind == TA_SCORE_MAD && pad_ranks(R) >= SEL_BRACKET_MIN_RP) {
+      w.scr = (int64_t *)take((size_t)std::min<size_t>(IG, SEL_GRID_MAX) * sel_cap(R) * 8);
+    }
     if (kind == TA_SCORE_MAD) {
       w.cs.med2 = (int64_t *)take(IG * 8);
       w.cs.mad4 = (int64_t *)take(IG * 8);
@@ -711,6 +1070,16 @@ size_t outliers_ws_bytes(int64_t R, int32_t I, int32_t G, int32_t mode, int32_t 
   return used + 256;
 }
 
+hipError_t launch_region_robust(const double *v_t, int64_t R, int G, const int32_t *it, int I,
+                                double *z_t, float *score, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL((sel_regions<true, true>), dim3(G), dim3(RT), 0, s, (const void *)v_t, R, G, it,
+                     I, z_t, (double *)nullptr);
+  hipLaunchKernelGGL(rank_max_f32, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, z_t, R, G, it, I,
+                     score);
+  return hipGetLastError();
+}
+
 hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStream_t s) {
   size_t used = 0;
   OWs w = carve(ws, a.R, a.I, a.G, a.mode, a.kind, &used);
@@ -724,8 +1093,16 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
       if (IG > 0) {
         hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)(pad_ranks(a.R) / TT), (IG + TT - 1) / TT),
                            dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, w.Tt);
-        if (mad)
-          hipLaunchKernelGGL(col_select, dim3(IG), dim3(CS), 0, s, w.Tt, a.R, w.cs);
+        if (mad && pad_ranks(a.R) < SEL_BRACKET_MIN_RP) {
+          hipLaunchKernelGGL(col_select_radix, dim3(IG), dim3(CS), 0, s, w.Tt, a.R, w.cs);
+        } else if (mad) {
+          int dev = 0, cus = 256;
+          (void)hipGetDevice(&dev);
+          (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+          const int grid = std::min(IG, std::min(SEL_GRID_MAX, 3 * cus));
+          hipLaunchKernelGGL(col_select_bracket, dim3(grid), dim3(CS), 0, s, w.Tt, a.R, IG, w.scr,
+                             sel_cap(a.R), w.cs);
+        }
         else
           hipLaunchKernelGGL(col_moments, dim3(IG), dim3(CS), 0, s, w.Tt, a.R, w.cm);
       }

@@ -172,15 +172,32 @@ __global__ __launch_bounds__(NT) void seg_kernel(SegArgs a) {
   const int rsub = SEG ? tid / G : 0;
   const bool fl_active = SEG && tid < rows_pp * G;
 
-  int parity = 0;
-  for (int64_t rr = blockIdx.x; rr < a.R; rr += gridDim.x) {
-    const int64_t r = a.order ? (int64_t)a.order[rr] : rr;
-    int64_t b = a.off[r], e = a.off[r + 1];
-    uint32_t errb = 0;
+  // A rank task: rank id and event range [b, e) (an invalid range is recorded
+  // and treated as empty).
+  auto rank_at = [&](int64_t rr, int64_t &r, int64_t &b, int64_t &e, uint32_t &errb) {
+    r = a.order ? (int64_t)a.order[rr] : rr;
+    b = a.off[r];
+    e = a.off[r + 1];
+    errb = 0;
     if (b < 0 || e < b || e > a.E) {
-      errb |= ERRBIT_OFFSETS;
+      errb = ERRBIT_OFFSETS;
       b = e = 0;
     }
+  };
+
+  int parity = 0;
+  Tile<EPT> cur, nxt_tile;
+  int64_t r_n = 0, b_n = 0, e_n = 0;
+  uint32_t err_n = 0;
+  if ((int64_t)blockIdx.x < a.R) {
+    rank_at(blockIdx.x, r_n, b_n, e_n, err_n);
+    const int64_t t0n = b_n & ~(int64_t)(TILE - 1);
+    if (t0n < e_n) load_tile<EPT, NTMP>(cur, a.ts, a.ctx, a.E, t0n + (int64_t)tid * EPT, b_n, e_n, lane);
+  }
+  for (int64_t rr = blockIdx.x; rr < a.R; rr += gridDim.x) {
+    const int64_t r = r_n;
+    const int64_t b = b_n, e = e_n;
+    uint32_t errb = err_n;
     int carry = -1;      // iteration index in effect after the processed events
     int flushed = 0;     // tensor rows [0, flushed) are written
     int64_t out_acc = 0; // time outside every region / before the first boundary
@@ -200,9 +217,9 @@ __global__ __launch_bounds__(NT) void seg_kernel(SegArgs a) {
       }
     };
 
-    Tile<EPT> cur, nxt_tile;
+    // The first tile of this rank is already in `cur` (loaded before the
+    // previous rank's epilogue, or before the loop).
     int64_t t0 = b & ~(int64_t)(TILE - 1);
-    if (t0 < e) load_tile<EPT, NTMP>(cur, a.ts, a.ctx, a.E, t0 + (int64_t)tid * EPT, b, e, lane);
     for (; t0 < e; t0 += TILE) {
       const int64_t c0 = t0 + (int64_t)tid * EPT;
       // Issue the next tile's loads now; they complete while this tile is
@@ -323,6 +340,14 @@ __global__ __launch_bounds__(NT) void seg_kernel(SegArgs a) {
       }
       carry = it_last;
       cur = nxt_tile;
+    }
+
+    // Next rank's first tile: its loads are in flight during this epilogue.
+    if (rr + gridDim.x < a.R) {
+      rank_at(rr + gridDim.x, r_n, b_n, e_n, err_n);
+      const int64_t t0n = b_n & ~(int64_t)(TILE - 1);
+      if (t0n < e_n)
+        load_tile<EPT, NTMP>(cur, a.ts, a.ctx, a.E, t0n + (int64_t)tid * EPT, b_n, e_n, lane);
     }
 
     // ---- rank epilogue --------------------------------------------------
@@ -456,6 +481,8 @@ hipError_t launch_ept(const SegArgs &a, const SegShape &sh, int grid, size_t lds
     case 9: return launch_variant<A, S, 4, true>(a, grid, lds, s);
     case 16: return launch_variant<A, S, 8, false>(a, grid, lds, s);
     case 17: return launch_variant<A, S, 8, true>(a, grid, lds, s);
+    case 32: return launch_variant<A, S, 16, false>(a, grid, lds, s);
+    case 33: return launch_variant<A, S, 16, true>(a, grid, lds, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -43,7 +43,8 @@ struct AeState {
   bool ready = false;        // weights initialised
   bool normed = false;       // normalisation fitted
   float threshold = -1.f;    // calibrated score threshold (fallback rule); < 0: none
-  int score_kind = 0;        // 0: max mean squared error, 1: max |mean residual|
+  int score_kind = 0;        // 0: max mean squared error, 1: max |mean residual|,
+                             // 2: max robust z over ranks of the mean residual
 };
 
 constexpr int AE_WG = 32;   // workgroups per training step (gradient partials)
@@ -61,8 +62,11 @@ size_t ae_rows_ws_bytes(int64_t R);
 hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, int batch,
                           uint64_t a, uint64_t c, float lr, bool update, hipStream_t st,
                           float *grad_out, float *loss_out);
+// Workspace of launch_ae_score (score kind 2 keeps per-region residual means
+// and their z-scores, [64][R] FP64 each).
+size_t ae_score_ws_bytes(int64_t R);
 hipError_t launch_ae_score(const AeState &s, const int64_t *T, int64_t R, int I, const int32_t *it,
-                           float *score, hipStream_t st);
+                           float *score, void *ws, size_t ws_bytes, hipStream_t st);
 hipError_t launch_topk(const float *score, int64_t R, int64_t k, int32_t *idx, int32_t *count_gt_thr,
                        float thr, hipStream_t st);
 

@@ -697,7 +697,7 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
     }
   if (d->autotune && !found) {
     bool have = false;
-    for (int ept : {2, 4, 8})
+    for (int ept : {2, 4, 8, 16})
       for (int nt : {0, 1})
         for (int wgs : {0, occ}) {
           ta::SegShape sh;
@@ -974,9 +974,16 @@ ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t ep
 
 ta_status ta_ae_set_score_kind(ta_handle h, int32_t kind) {
   if (!h) return TA_ERR_INVALID_ARG;
-  if (kind != TA_AE_SCORE_ERROR && kind != TA_AE_SCORE_RESIDUAL)
+  if (kind != TA_AE_SCORE_ERROR && kind != TA_AE_SCORE_RESIDUAL && kind != TA_AE_SCORE_RESIDUAL_Z)
     return fail(h, TA_ERR_INVALID_ARG, "unknown score kind");
   h->ae.score_kind = kind;
+  return TA_OK;
+}
+
+ta_status ta_ae_get_score_kind(ta_handle h, int32_t *kind_host) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!kind_host) return fail(h, TA_ERR_INVALID_ARG, "kind_host is NULL");
+  *kind_host = h->ae.score_kind;
   return TA_OK;
 }
 
@@ -988,8 +995,10 @@ ta_status ta_ae_score(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32
   if (!rank_score || !aligned16(rank_score)) return fail(h, TA_ERR_INVALID_ARG, "rank_score");
   if (!h->ae.ready || !h->ae.normed) return fail(h, TA_ERR_STATE, "network not initialised and fitted");
   DeviceGuard dg(h->device);
-  hipError_t e = ta::launch_ae_score(h->ae, tensor, n_ranks, n_iters, iters_found, rank_score,
-                                     (hipStream_t)stream);
+  st = ensure_ws(h, ta::ae_score_ws_bytes(n_ranks));
+  if (st) return st;
+  hipError_t e = ta::launch_ae_score(h->ae, tensor, n_ranks, n_iters, iters_found, rank_score, h->ws,
+                                     h->ws_bytes, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "ae score");
   return TA_OK;
 }
@@ -1022,8 +1031,9 @@ ta_status ta_prescreen(ta_handle h, const int64_t *tensor, int64_t n_ranks, int3
   DeviceGuard dg(h->device);
   hipStream_t s = (hipStream_t)stream;
   const size_t fl = ((size_t)n_ranks * 4 + 255) & ~(size_t)255;
-  const size_t need = std::max(fl + 256, fl + ta::outliers_ws_bytes(n_ranks, n_iters, n_regions,
-                                                                    TA_SCAN_FULL, TA_SCORE_MAD) +
+  const size_t need = fl + 256 + std::max(ta::ae_score_ws_bytes(n_ranks),
+                                          ta::outliers_ws_bytes(n_ranks, n_iters, n_regions,
+                                                                TA_SCAN_FULL, TA_SCORE_MAD) +
                                               ((size_t)n_ranks * 9 + 1024));
   st = ensure_ws(h, need);
   if (st) return st;
@@ -1032,7 +1042,9 @@ ta_status ta_prescreen(ta_handle h, const int64_t *tensor, int64_t n_ranks, int3
   bool fallback = !(h->ae.ready && h->ae.normed);
   hipError_t e = hipSuccess;
   if (!fallback) {
-    e = ta::launch_ae_score(h->ae, tensor, n_ranks, n_iters, iters_found, score, s);
+    char *aws = (char *)h->ws + fl + 256;
+    e = ta::launch_ae_score(h->ae, tensor, n_ranks, n_iters, iters_found, score, aws,
+                            h->ws_bytes - (fl + 256), s);
     const float thr = h->ae.threshold >= 0.f ? h->ae.threshold : 3.4e38f;
     if (e == hipSuccess) e = ta::launch_topk(score, n_ranks, k, topk_ranks, above, thr, s);
     int32_t n_above = 0;
@@ -1129,7 +1141,8 @@ ta_status ta_ae_set_state(ta_handle h, const void *buf_host, size_t bytes) {
   h->ae.ready = hd.ready != 0;
   h->ae.normed = hd.normed != 0;
   h->ae.threshold = hd.threshold;
-  h->ae.score_kind = hd.pad == TA_AE_SCORE_RESIDUAL ? TA_AE_SCORE_RESIDUAL : TA_AE_SCORE_ERROR;
+  h->ae.score_kind = (hd.pad == TA_AE_SCORE_RESIDUAL || hd.pad == TA_AE_SCORE_RESIDUAL_Z)
+                         ? (int)hd.pad : TA_AE_SCORE_ERROR;
   return TA_OK;
 }
 

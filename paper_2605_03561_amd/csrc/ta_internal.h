@@ -56,7 +56,7 @@ struct SegArgs {
 
 // Launch shape of the fused pass (chosen by the batch autotuner).
 struct SegShape {
-  int ept = 4;              // events per thread per tile: 2, 4 or 8
+  int ept = 4;              // events per thread per tile: 2, 4, 8 or 16
   bool nontemporal = false; // streaming loads/stores that bypass cache retention
   int wgs_per_cu = 0;       // 0: one workgroup per rank; k > 0: persistent, k per CU
 };
@@ -93,6 +93,11 @@ struct OutArgs {
   int64_t *n_flagged;
   double *region_score;
 };
+// Robust z over active ranks of per-rank region values v_t[G][R] (median and
+// MAD per region, the exact scan's second stage), z_t[G][R], and FP32
+// score[r] = max_g |z|.
+hipError_t launch_region_robust(const double *v_t, int64_t R, int G, const int32_t *it, int I,
+                                double *z_t, float *score, hipStream_t s);
 hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStream_t s);
 size_t outliers_ws_bytes(int64_t R, int32_t I, int32_t G, int32_t mode, int32_t kind);
 

@@ -77,11 +77,17 @@ def timeline_on_gpu(seed: int = 0, n_ranks: int = 100_000, median_len: int = 20_
                     n_nodes: int = 5_000, depth_max: int = 12, n_iters: int = 500,
                     n_regions: int = 64, inject_frac: float = 0.0, inject_scale: float = 1.3,
                     inject_regions: int = 3, rank_sd: float = 0.05,
-                    filler_mean_ns: float = 5_000.0, device="cuda:0") -> GpuWorkload:
-    """Generate the traces of `n_ranks` ranks directly in device memory."""
+                    filler_mean_ns: float = 5_000.0, device="cuda:0",
+                    app_seed: int | None = None) -> GpuWorkload:
+    """Generate the traces of `n_ranks` ranks directly in device memory.
+
+    `app_seed` fixes the application: call-path tree, iteration marker,
+    regions and per-region mean durations (default: `seed`).  `seed` drives
+    one run of it: trace lengths, per-rank scaling, injected slow ranks,
+    start times and every event draw."""
     lib = _load()
     dev = torch.device(device)
-    trng = np.random.default_rng([GPU_ID, seed])
+    trng = np.random.default_rng([GPU_ID, seed if app_seed is None else app_seed])
     parent = synth.make_tree(trng, n_nodes, depth_max)
     marker = synth.pick_marker(trng, parent)
     regions = synth.pick_regions(trng, parent, marker, n_regions)

@@ -6,9 +6,11 @@ then judged against the exact outlier scan (robust z, FULL mode) on held-out
 seeds with injected slow ranks.  Every step of the analysis runs in the HIP
 library; torch only holds device buffers and provides the stream and timers.
 
-Workload: 10,000 ranks, lognormal trace lengths (median 50,000 events,
-1,000..400,000), a 1,000-node tree, 500 iterations, 64 regions (the network's
-input width).
+Workload: one application (call-path tree, regions and per-region durations
+fixed by app_seed) run with different seeds: 10,000 ranks, lognormal trace
+lengths (median 50,000 events, 1,000..400,000), a 1,000-node tree, 500
+iterations, 64 regions (the network's input width).  Training runs and
+held-out runs differ in every per-run draw.
 """
 from __future__ import annotations
 
@@ -20,8 +22,9 @@ import torch
 from . import gpu_synth, ta
 
 C4 = dict(n_ranks=10_000, median_len=50_000, min_len=1_000, max_len=400_000, n_nodes=1_000,
-          depth_max=12, n_iters=500, n_regions=64)
+          depth_max=12, n_iters=500, n_regions=64, app_seed=4)
 TRAIN_SEEDS = (1001, 1002, 1003, 1004, 1005)
+KINDS = (0, 1, 2)   # ta.AE_SCORE_ERROR, AE_SCORE_RESIDUAL, AE_SCORE_RESIDUAL_Z
 HELD_OUT = ((2001, 0.005), (2002, 0.01), (2003, 0.02), (2004, 0.035), (2005, 0.05))
 
 
@@ -82,7 +85,7 @@ def train(h: ta.Handle, seeds=TRAIN_SEEDS, epochs=20, batch=4096, lr=1e-3, init_
     R = cfg["n_ranks"]
     k = int(round(k_frac * R))
     kind_recall = {}
-    for kind in (ta.AE_SCORE_ERROR, ta.AE_SCORE_RESIDUAL):
+    for kind in KINDS:
         h.ae_set_score_kind(kind)
         kind_recall[kind] = float(np.mean([_recall_at(h.ae_score(T, it).cpu().numpy(), f, k)
                                            for (T, it), f in zip(tensors, flags)]))
@@ -115,19 +118,25 @@ def _time(fn, reps=3):
 
 def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_seed=99,
              log=print):
-    """Judge the trained network (and two references) against the exact scan.
+    """Judge the trained network (and references) against the exact scan.
 
-    For each held-out seed: exact FULL robust-z scan -> flagged ranks (the
-    truth for recall); the pre-screen's top-k (k = k_frac * R); the same for
-    an untrained network with the same normalisation; and the non-learned
-    TOTALS scan (robust z of rank totals) taking its k highest scores.  Times
-    are GPU times from HIP events on the current stream."""
+    For each held-out run: the exact FULL robust-z scan -> flagged ranks (the
+    truth for recall); the pre-screen's k ranks (k = k_frac * R) with the
+    score kind chosen in training; the top-k of every score kind for the
+    trained network and for an untrained one with the same normalisation; and
+    the non-learned TOTALS scan (robust z of rank totals) taking its k highest
+    scores.  Times are GPU times from HIP events on the current stream."""
     R = cfg["n_ranks"]
     k = int(round(k_frac * R))
+    chosen = h.ae_get_score_kind()
     ref = ta.Handle(h.device.index or 0)
     ref.ae_set_state(h.ae_get_state())
     ref.ae_init(untrained_seed)                    # fresh weights, same normalisation
     rows = []
+
+    def topk(scores):
+        return np.lexsort((np.arange(R), -scores))[:k]
+
     for seed, rate in held_out:
         T, it, meta = make_tensor(h, seed, rate, cfg)
         t_full, full = _time(lambda: h.outliers(T, it, mode=ta.SCAN_FULL, kind=ta.SCORE_MAD))
@@ -135,47 +144,53 @@ def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_s
         t_pre, pre = _time(lambda: h.prescreen(T, it, k))
         top, _, fb = pre
         t_tot, tot = _time(lambda: h.outliers(T, it, mode=ta.SCAN_TOTALS, kind=ta.SCORE_MAD))
-        t_score, sc_t = _time(lambda: h.ae_score(T, it))
-        sc_u = ref.ae_score(T, it)
-        top_u = np.lexsort((np.arange(R), -sc_u.cpu().numpy()))[:k]
-        top_direct = np.lexsort((np.arange(R), -sc_t.cpu().numpy()))[:k]
 
         def recall(sel):
             s = np.zeros(R, bool)
             s[sel] = True
             hit = (s & flags).sum()
-            return (hit / max(flags.sum(), 1), hit / max(len(sel), 1))
+            return float(hit / max(flags.sum(), 1)), float(hit / max(len(sel), 1))
 
-        ts = tot["rank_score"].cpu().numpy()
-        top_tot = np.lexsort((np.arange(R), -ts))[:k]
+        by_kind, by_kind_untrained, score_ms = {}, {}, {}
+        for kind in KINDS:
+            h.ae_set_score_kind(kind)
+            ref.ae_set_score_kind(kind)
+            score_ms[kind], sc = _time(lambda: h.ae_score(T, it))
+            by_kind[kind] = recall(topk(sc.cpu().numpy()))[0]
+            by_kind_untrained[kind] = recall(topk(ref.ae_score(T, it).cpu().numpy()))[0]
+        h.ae_set_score_kind(chosen)
         r_ae, p_ae = recall(top.cpu().numpy())
-        r_un, p_un = recall(top_u)
-        r_dir, _ = recall(top_direct)
-        r_tt, p_tt = recall(top_tot)
+        r_tt, p_tt = recall(topk(tot["rank_score"].cpu().numpy()))
         inj = meta["injected"]
         sel = np.zeros(R, bool)
         sel[top.cpu().numpy()] = True
         row = {"seed": seed, "inject_rate": rate, "n_flagged_exact": int(flags.sum()),
                "injected_flagged_by_exact": float(flags[inj].mean()) if inj.any() else None,
-               "k": k, "recall": float(r_ae), "precision": float(p_ae), "used_fallback": bool(fb),
+               "k": k, "recall": r_ae, "precision": p_ae, "used_fallback": bool(fb),
                "injected_recall": float(sel[inj].mean()) if inj.any() else None,
-               "network_topk_recall": float(r_dir), "untrained_recall": float(r_un),
-               "totals_scan_recall": float(r_tt),
-               "full_scan_ms": t_full, "prescreen_ms": t_pre, "ae_score_ms": t_score,
+               "untrained_recall": by_kind_untrained[chosen],
+               "recall_by_kind": by_kind, "untrained_recall_by_kind": by_kind_untrained,
+               "totals_scan_recall": r_tt, "totals_scan_precision": p_tt,
+               "full_scan_ms": t_full, "prescreen_ms": t_pre, "ae_score_ms_by_kind": score_ms,
                "totals_scan_ms": t_tot, "speedup_vs_full": t_full / t_pre}
         log(f"[prescreen] seed {seed} rate {rate:.3f}: exact flags {row['n_flagged_exact']}, "
-            f"recall {r_ae:.4f} (untrained {r_un:.4f}, totals {r_tt:.4f}), "
-            f"{t_full:.2f} ms full vs {t_pre:.2f} ms pre-screen ({t_full / t_pre:.1f}x)")
+            f"recall {r_ae:.4f} (untrained {row['untrained_recall']:.4f}, totals {r_tt:.4f}; "
+            f"by kind {by_kind}), {t_full:.2f} ms full vs {t_pre:.2f} ms pre-screen "
+            f"({t_full / t_pre:.1f}x)")
         rows.append(row)
         del T, it, full, tot
         torch.cuda.empty_cache()
     ref.close()
-    summ = {"k": k, "recall_min": min(r["recall"] for r in rows),
+    summ = {"k": k, "score_kind": chosen,
+            "recall_min": min(r["recall"] for r in rows),
             "recall_mean": float(np.mean([r["recall"] for r in rows])),
             "precision_mean": float(np.mean([r["precision"] for r in rows])),
             "speedup_min": min(r["speedup_vs_full"] for r in rows),
             "speedup_mean": float(np.mean([r["speedup_vs_full"] for r in rows])),
             "untrained_recall_mean": float(np.mean([r["untrained_recall"] for r in rows])),
             "totals_scan_recall_mean": float(np.mean([r["totals_scan_recall"] for r in rows])),
+            "full_scan_ms_mean": float(np.mean([r["full_scan_ms"] for r in rows])),
+            "prescreen_ms_mean": float(np.mean([r["prescreen_ms"] for r in rows])),
+            "totals_scan_ms_mean": float(np.mean([r["totals_scan_ms"] for r in rows])),
             "any_fallback": any(r["used_fallback"] for r in rows)}
     return summ, rows

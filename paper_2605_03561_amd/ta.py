@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libta.so")
 OK, INVALID_ARG, BAD_TREE, CTX_RANGE, UNSORTED, ITER_OVERFLOW, SIZE_OVERFLOW, OOM, HIP, STATE = range(10)
 SCAN_FULL, SCAN_TOTALS = 0, 1
 SCORE_MAD, SCORE_Z = 0, 1
-AE_SCORE_ERROR, AE_SCORE_RESIDUAL = 0, 1
+AE_SCORE_ERROR, AE_SCORE_RESIDUAL, AE_SCORE_RESIDUAL_Z = 0, 1, 2
 
 
 class TAError(RuntimeError):
@@ -87,6 +87,7 @@ def _load():
         "ta_ae_train": [P, P, i64, i32, i32, C.c_float, C.c_uint64, P, P],
         "ta_ae_score": [P, P, i64, i32, i32, P, P, P],
         "ta_ae_set_score_kind": [P, i32],
+        "ta_ae_get_score_kind": [P, P],
         "ta_ae_calibrate": [P, P, i64, f64, P],
         "ta_prescreen": [P, P, i64, i32, i32, P, i64, P, P, P, P],
         "ta_ae_get_state": [P, P, C.c_size_t],
@@ -328,6 +329,11 @@ class Handle:
 
     def ae_set_score_kind(self, kind: int):
         self._check(_lib.ta_ae_set_score_kind(self.h, int(kind)))
+
+    def ae_get_score_kind(self) -> int:
+        k = C.c_int32(0)
+        self._check(_lib.ta_ae_get_score_kind(self.h, C.byref(k)))
+        return int(k.value)
 
     def ae_score(self, tensor, iters_found=None):
         R, I, G = tensor.shape

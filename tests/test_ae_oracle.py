@@ -145,3 +145,44 @@ def test_fit_norm_and_scores():
         x = X[r, :it[r]]
         assert s0[r] == pytest.approx(((c - x) ** 2).mean(0).max(), rel=1e-12)
         assert s1[r] == pytest.approx(np.abs((c - x).mean(0)).max(), rel=1e-12)
+
+
+def test_robust_z_textbook_cases():
+    """Odd and even medians, the mean-absolute-deviation fallback and the
+    all-equal case, worked by hand."""
+    v = np.array([1.0, 2.0, 3.0, 4.0, 100.0])          # median 3, MAD 1
+    np.testing.assert_allclose(ae.robust_z(v), (v - 3.0) / 1.4826, rtol=1e-15)
+    v = np.array([4.0, 1.0, 2.0, 3.0])                  # median 2.5, MAD 1
+    np.testing.assert_allclose(ae.robust_z(v), (v - 2.5) / 1.4826, rtol=1e-15)
+    v = np.array([5.0, 5.0, 5.0, 9.0])                  # MAD 0, mean AD 1
+    np.testing.assert_allclose(ae.robust_z(v), (v - 5.0) / 1.253314, rtol=1e-15)
+    assert not ae.robust_z(np.full(7, 2.0)).any()
+
+
+def test_residual_z_score_equals_exact_totals_scan(oracle):
+    """With a network that outputs zeros, m(r,g) = -mean_i x(r,i,g), an
+    increasing affine map of the rank total S(r,g) when every rank has the
+    same number of iterations; the robust |z| is invariant under such maps,
+    so the kind-2 score equals the C oracle's exact TOTALS robust scan."""
+    rng = np.random.default_rng(11)
+    R, I, G = 40, 6, 64
+    T = rng.gamma(4.0, 2.5e4, (R, I, G)).astype(np.int64)
+    T[3, :, 7] *= 3                                      # a slow region
+    T[:, :, 9] = 1000                                    # constant region: z = 0
+    T[:30, :, 10] = 500                                  # MAD 0, mean AD > 0
+    it = np.full(R, I, np.int32)
+    mu, sd = ae.fit_norm([T], [it])
+    zero = {k: np.zeros_like(v) for k, v in ae.init_params(0).items()}
+    got = ae.rank_scores(zero, T, it, mu, sd, kind=2)
+    st, score, flag, nf, reg = oracle.outliers(T, it, mode=1, kind=0, tau=3.5)
+    assert st == 0
+    np.testing.assert_allclose(got, score, rtol=2e-5, atol=1e-9)
+    # ranks without iterations take no part and score 0
+    it2 = it.copy()
+    it2[[0, 5]] = 0
+    got2 = ae.rank_scores(zero, T, it2, mu, sd, kind=2)
+    assert got2[0] == 0.0 and got2[5] == 0.0
+    keep = np.ones(R, bool)
+    keep[[0, 5]] = False
+    sub = ae.rank_scores(zero, T[keep], it[keep], mu, sd, kind=2)
+    np.testing.assert_allclose(got2[keep], sub, rtol=1e-15)

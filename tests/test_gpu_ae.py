@@ -162,6 +162,11 @@ def test_scores_match_oracle_and_state_roundtrip(env):
     sc1 = h.ae_score(dT, dit).cpu().numpy()
     ref1 = ae.rank_scores(to_params(w), T, it, mu, (np.float32(1) / isd), bf16=True, kind=1)
     np.testing.assert_allclose(sc1, ref1, rtol=5e-3, atol=2e-5)
+    h.ae_set_score_kind(ta.AE_SCORE_RESIDUAL_Z)
+    sc2z = h.ae_score(dT, dit).cpu().numpy()
+    ref2z = ae.rank_scores(to_params(w), T, it, mu, (np.float32(1) / isd), bf16=True, kind=2)
+    assert sc2z[it == 0].max(initial=0.0) == 0.0
+    np.testing.assert_allclose(sc2z, ref2z, rtol=2e-2, atol=2e-2)
     h.ae_set_score_kind(ta.AE_SCORE_ERROR)
     assert sc[it == 0].max(initial=0.0) == 0.0
     state = h.ae_get_state()
@@ -210,3 +215,34 @@ def test_topk_ties_and_edges(env):
         s = sc.cpu().numpy()
         order = sorted(range(70), key=lambda r: (-s[r], r))[:k]
         assert top.cpu().numpy().tolist() == sorted(order)
+
+
+def test_residual_z_with_bias_only_network(env):
+    """Weights zero, output bias c: the residual is c - x exactly (no matrix
+    product rounding), so the kind-2 score matches the oracle to FP32
+    accuracy, including the MAD-0 fallback region and ranks without
+    iterations; 70 ranks span two score workgroups and a partial one."""
+    torch, ta, h = env
+    rng = np.random.default_rng(9)
+    T, it = fake_tensor(rng, 70, 45, rng.integers(0, 46, 70).astype(np.int32))
+    it[:20] = 45
+    T[:, :, 3] = 12345                         # constant region: z = 0
+    T[:50, :, 4] = 777                         # MAD 0, mean AD > 0
+    dT, dit = torch.from_numpy(T).cuda(), torch.from_numpy(it).cuda()
+    h.ae_init(3)
+    h.ae_fit_norm(dT, dit)
+    state = bytearray(h.ae_get_state())
+    hdr = 4 + 4 + 8 + 4 + 4 + 4 + 4
+    w = np.zeros(NP, np.float32)
+    c = np.linspace(-0.5, 0.5, 64).astype(np.float32)
+    w[NP - 64:] = c
+    state[hdr:hdr + 4 * NP] = w.tobytes()
+    h2 = ta.Handle(0)
+    h2.ae_set_state(bytes(state))
+    h2.ae_set_score_kind(ta.AE_SCORE_RESIDUAL_Z)
+    got = h2.ae_score(dT, dit).cpu().numpy()
+    h2.close()
+    _, _, _, mu, isd = unpack(bytes(state))
+    ref = ae.rank_scores(to_params(w), T, it, mu, (np.float32(1) / isd), kind=2)
+    assert got[it == 0].max(initial=0.0) == 0.0
+    np.testing.assert_allclose(got, ref, rtol=1e-4, atol=1e-5)

@@ -256,12 +256,14 @@ def test_outliers_ties_and_constant_columns(ta, h, oracle):
         assert np.array_equal(o["rank_flag"].cpu().numpy(), flag)
 
 
-@pytest.mark.parametrize("R", [1, 2, 63, 64, 65, 1000, 4099])
+@pytest.mark.parametrize("R", [1, 2, 63, 64, 65, 1000, 4099, 32768, 70001])
 @pytest.mark.parametrize("style", ["narrow", "wide", "signed", "heavy_ties"])
 def test_outliers_column_shapes(ta, h, oracle, R, style):
-    """Ranks counts around the 64-rank tiles of the column-major scan, value
-    ranges that take one to four 11-bit digits, negative cells, mass ties,
-    ranks without iterations and columns with no valid rank."""
+    """Ranks counts around the 64-rank tiles of the column-major scan and on
+    both sides of the switch from whole-column radix selection to the sampled
+    bracket (32,768 padded ranks), value ranges that take one to four 11-bit
+    digits, negative cells, mass ties, ranks without iterations and columns
+    with no valid rank."""
     import torch
     print(f"[parity] outliers columns R={R} style={style}", flush=True)
     rng = np.random.default_rng(R * 7 + len(style))

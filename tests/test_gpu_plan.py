@@ -40,7 +40,7 @@ def test_all_shapes_identical(env, oracle):
     assert np.array_equal(p.seg["excl"].cpu().numpy(), ex)
     assert np.array_equal(p.seg["incl"].cpu().numpy(), inc)
     info = p.info()
-    assert info["events_per_thread"] in (2, 4, 8) and info["tuned_ms"] > 0
+    assert info["events_per_thread"] in (2, 4, 8, 16) and info["tuned_ms"] > 0
     p.close()
 
 
@@ -54,7 +54,7 @@ def test_cached_shapes_identical(env, oracle, tmp_path, monkeypatch):
     key_line = [l for l in path.read_text().splitlines() if '"ept"' in l][0]
     key = key_line.split('"')[1]
     p.close()
-    for ept in (2, 4, 8):
+    for ept in (2, 4, 8, 16):
         for nt in (0, 1):
             for wgs in (0, 1, 2):
                 path.write_text('{\n  "%s": {"ept": %d, "nt": %d, "wgs": %d, "ms": 1.0}\n}\n'
