@@ -232,9 +232,10 @@ ta_status ta_callpath(ta_handle h, int32_t leaf, int32_t *path_host, int32_t cap
 /* Batch plan: the whole batch in one HIP graph launch.
  * ta_plan_create orders the ranks longest first (so the longest traces start
  * first and the tail is short), picks the launch shape of the fused pass
- * (events per thread per tile, streaming loads, one workgroup per rank or a
- * persistent grid) and captures the fused pass -- optionally followed by the
- * imbalance and outlier stages -- into a graph over the buffers given here.
+ * (threads per workgroup, events per thread per tile, streaming loads, one
+ * workgroup per rank or a persistent grid) and captures the fused pass --
+ * optionally followed by the imbalance and outlier stages -- into a graph
+ * over the buffers given here.
  *   autotune 0: the default shape; 1: time every candidate shape on this
  *   batch (each produces identical results) and keep the fastest; 2: as 1, but
  *   reuse the choice stored in the JSON file named by the TA_AUTOTUNE_CACHE
@@ -264,9 +265,11 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
                          const ta_batch_desc *d, ta_plan *out, void *stream);
 /* Replays the captured graph on `stream`. */
 ta_status ta_plan_launch(ta_plan p, void *stream);
-/* The chosen launch shape and its measured time (ms; 0 when not tuned). */
-ta_status ta_plan_info(ta_plan p, int32_t *events_per_thread, int32_t *nontemporal,
-                       int32_t *wgs_per_cu, float *tuned_ms);
+/* The chosen launch shape (threads per workgroup, events per thread per tile,
+ * streaming loads, workgroups per CU of a persistent grid or 0) and its
+ * measured time (ms; 0 when not tuned).  Any pointer may be NULL. */
+ta_status ta_plan_info(ta_plan p, int32_t *threads, int32_t *events_per_thread,
+                       int32_t *nontemporal, int32_t *wgs_per_cu, float *tuned_ms);
 ta_status ta_plan_destroy(ta_plan p);
 
 /* ---- Learned pre-screen -------------------------------------------------
@@ -294,15 +297,24 @@ ta_status ta_ae_rows(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_
                      int32_t n_regions, const int32_t *iters_found, float *rows,
                      int64_t *n_rows_host, void *stream);
 /* Gradient (grad[24928], layout W1 W2 W3 W4 b1 b2 b3 b4, row-major [out][in])
- * and mean loss (loss[1]) over rows[0..n_rows) without updating anything. */
-ta_status ta_ae_grad(ta_handle h, const float *rows, int64_t n_rows, float *grad, float *loss,
-                     void *stream);
+ * and mean loss (loss[1]) over rows[0..n_rows) without updating anything.
+ * input_noise > 0 gives the denoising gradient: the network sees
+ * x[j][c] + input_noise * N_key(j, c) and is scored against x[j][c], where
+ * N_key(j, c) is the standard normal draw for row j and feature c under
+ * noise_key: base = M(key ^ M(64 j + c)), z1 = M(base),
+ * z2 = M(base ^ 0xD1B54A32D192ED03), u1 = ((z1 >> 40) + 1/2) / 2^24,
+ * u2 = (z2 >> 40) / 2^24, N = sqrt(-2 ln u1) cos(2 pi u2) (FP32), with M the
+ * SplitMix64 finaliser of the initialiser. */
+ta_status ta_ae_grad(ta_handle h, const float *rows, int64_t n_rows, float input_noise,
+                     uint64_t noise_key, float *grad, float *loss, void *stream);
 /* `epochs` passes over the rows in batches of `batch` (a fresh permutation of
  * the rows per epoch, drawn from shuffle_seed), one Adam step (learning rate
- * lr) per batch; epoch_loss[e] (device, may be NULL) is the row-weighted mean
- * batch loss of epoch e. */
+ * lr) per batch; with input_noise > 0 every step is a denoising step with its
+ * own noise key (drawn from shuffle_seed); epoch_loss[e] (device, may be NULL)
+ * is the row-weighted mean batch loss of epoch e. */
 ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t epochs, int32_t batch,
-                      float lr, uint64_t shuffle_seed, float *epoch_loss, void *stream);
+                      float lr, float input_noise, uint64_t shuffle_seed, float *epoch_loss,
+                      void *stream);
 /* Score used by ta_ae_score / ta_prescreen: TA_AE_SCORE_ERROR (default) =
  * max_g mean_i (y - x)^2, the reconstruction error; TA_AE_SCORE_RESIDUAL =
  * max_g |mean_i (y - x)|, a region's persistent residual over the rank's

@@ -77,6 +77,24 @@ def init_params(seed: int) -> dict:
     return p
 
 
+def gaussian_noise(key: int, rows, n_features: int = 64) -> np.ndarray:
+    """Standard normal draws N_key(j, c) for row ids `rows` and features
+    c < n_features: base = M(key ^ M(64 j + c)), z1 = M(base),
+    z2 = M(base ^ 0xD1B54A32D192ED03), u1 = ((z1 >> 40) + 1/2) / 2^24,
+    u2 = (z2 >> 40) / 2^24, N = sqrt(-2 ln u1) cos(2 pi u2) (Box & Muller
+    1958), M the SplitMix64 finaliser; in FP64."""
+    j = np.asarray(rows, dtype=np.uint64)[:, None]
+    c = np.arange(n_features, dtype=np.uint64)[None, :]
+    with np.errstate(over="ignore"):
+        ctr = (j * np.uint64(n_features) + c) & _M
+        base = _mix64(np.uint64(key) ^ _mix64(ctr))
+        z1 = _mix64(base)
+        z2 = _mix64(base ^ np.uint64(0xD1B54A32D192ED03))
+    u1 = ((z1 >> np.uint64(40)).astype(np.float64) + 0.5) / 16777216.0
+    u2 = (z2 >> np.uint64(40)).astype(np.float64) / 16777216.0
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
 # ---------------------------------------------------------------------------
 # Normalisation
 # ---------------------------------------------------------------------------
@@ -130,12 +148,14 @@ def forward(p: dict, X: np.ndarray, bf16: bool = False):
     return z, a
 
 
-def loss_and_grads(p: dict, X: np.ndarray, bf16: bool = False):
-    """Mean squared reconstruction error and its gradients."""
+def loss_and_grads(p: dict, X: np.ndarray, bf16: bool = False, X_in=None):
+    """Mean squared reconstruction error and its gradients.  X_in (default X)
+    is what the network sees; the error is taken against X (a denoising step
+    when X_in is a corrupted copy of X)."""
     rnd = to_bf16 if bf16 else (lambda v: np.asarray(v, np.float64))
     X = np.asarray(X, np.float64)
     B = X.shape[0]
-    z, a = forward(p, X, bf16)
+    z, a = forward(p, X if X_in is None else np.asarray(X_in, np.float64), bf16)
     y = a[-1]
     diff = y - X
     loss = float((diff ** 2).sum() / (B * DIMS[-1]))

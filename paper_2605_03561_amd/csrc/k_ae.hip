@@ -121,6 +121,26 @@ __device__ inline void forward(AeLds &L, f4 &y) {
   for (int j = 0; j < 4; j++) y[j] += L.b[AE_B4 - AE_B1 + c];
 }
 
+// SplitMix64 finaliser (Steele, Lea & Flood 2014), used as a counter-based
+// generator: draw = mix64(key + counter * golden gamma).
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Standard normal draw for (key, row, feature): two 24-bit uniforms from
+// SplitMix64 counter draws, then Box-Muller (Box & Muller 1958),
+// sqrt(-2 ln u1) cos(2 pi u2), with u1 in (0, 1).
+__device__ inline float gauss_draw(uint64_t key, uint64_t row, int c) {
+  const uint64_t base = mix64(key ^ mix64(row * (uint64_t)AE_IN + (uint64_t)c));
+  const uint64_t z1 = mix64(base), z2 = mix64(base ^ 0xD1B54A32D192ED03ull);
+  const float u1 = ((float)(z1 >> 40) + 0.5f) * (1.0f / 16777216.0f);
+  const float u2 = (float)(z2 >> 40) * (1.0f / 16777216.0f);
+  return sqrtf(-2.0f * logf(u1)) * cosf(6.2831853071795864f * u2);
+}
+
 __device__ inline uint64_t perm_row(uint64_t k, uint64_t a, uint64_t c, uint64_t n) {
   return (a * k + c) % n;
 }
@@ -128,10 +148,14 @@ __device__ inline uint64_t perm_row(uint64_t k, uint64_t a, uint64_t c, uint64_t
 // ---------------------------------------------------------------------------
 // Training step: gradient partials of the mean squared error over the rows
 // perm(k), k in [k0, k_end), written per workgroup to part[wg][AE_NP + 1].
+// With noise_sd > 0 the network sees x + noise_sd * N(0, 1) (drawn for the
+// row's index and the feature under noise_key) and is scored against x
+// (denoising training).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(AT) void ae_fwdbwd(const float *__restrict__ rows, int64_t n,
                                                  int64_t k0, int64_t k_end, uint64_t pa,
-                                                 uint64_t pc, float scale,
+                                                 uint64_t pc, float scale, float noise_sd,
+                                                 uint64_t noise_key,
                                                  const uint16_t *__restrict__ wb,
                                                  const float *__restrict__ w, float *part) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -156,15 +180,23 @@ __global__ __launch_bounds__(AT) void ae_fwdbwd(const float *__restrict__ rows, 
       const int64_t k = k0 + t * TR + r;
       const bool ok = k < k_end;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (ok) v = *reinterpret_cast<const float4 *>(rows + perm_row((uint64_t)k, pa, pc, (uint64_t)n) * AE_IN + c4);
+      const uint64_t row = ok ? perm_row((uint64_t)k, pa, pc, (uint64_t)n) : 0;
+      if (ok) v = *reinterpret_cast<const float4 *>(rows + row * AE_IN + c4);
       L.X[r * AE_IN + c4 + 0] = v.x;
       L.X[r * AE_IN + c4 + 1] = v.y;
       L.X[r * AE_IN + c4 + 2] = v.z;
       L.X[r * AE_IN + c4 + 3] = v.w;
-      L.Xb[r * AE_IN + c4 + 0] = f2bf(v.x);
-      L.Xb[r * AE_IN + c4 + 1] = f2bf(v.y);
-      L.Xb[r * AE_IN + c4 + 2] = f2bf(v.z);
-      L.Xb[r * AE_IN + c4 + 3] = f2bf(v.w);
+      float4 xin = v;
+      if (ok && noise_sd > 0.f) {
+        xin.x += noise_sd * gauss_draw(noise_key, row, c4 + 0);
+        xin.y += noise_sd * gauss_draw(noise_key, row, c4 + 1);
+        xin.z += noise_sd * gauss_draw(noise_key, row, c4 + 2);
+        xin.w += noise_sd * gauss_draw(noise_key, row, c4 + 3);
+      }
+      L.Xb[r * AE_IN + c4 + 0] = f2bf(xin.x);
+      L.Xb[r * AE_IN + c4 + 1] = f2bf(xin.y);
+      L.Xb[r * AE_IN + c4 + 2] = f2bf(xin.z);
+      L.Xb[r * AE_IN + c4 + 3] = f2bf(xin.w);
       if ((tid & 15) == 0) L.valid[r] = ok;
     }
     __syncthreads();
@@ -332,12 +364,6 @@ __global__ __launch_bounds__(256) void ae_adam(const float *part, int nwg, float
 // ---------------------------------------------------------------------------
 // Initialisation: Xavier-uniform weights from SplitMix64 counter draws.
 // ---------------------------------------------------------------------------
-__device__ inline uint64_t mix64(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
 
 __global__ void ae_init_kernel(uint64_t seed, float *w, uint16_t *wb, float *m, float *v) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -909,15 +935,15 @@ void allow_lds(K k) {
 }
 
 hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, int batch,
-                          uint64_t a, uint64_t c, float lr, bool update, hipStream_t st,
-                          float *grad_out, float *loss_out) {
+                          uint64_t a, uint64_t c, float lr, bool update, float noise_sd,
+                          uint64_t noise_key, hipStream_t st, float *grad_out, float *loss_out) {
   const int64_t k_end = k0 + batch < n ? k0 + batch : n;
   const int64_t bv = k_end - k0;
   if (bv <= 0) return hipErrorInvalidValue;
   const float scale = 2.0f / (float)(bv * AE_IN);
   allow_lds(&ae_fwdbwd);
   hipLaunchKernelGGL(ae_fwdbwd, dim3(AE_WG), dim3(AT), sizeof(AeLds), st, rows, n, k0, k_end, a, c,
-                     scale, s.wb, s.w, s.part);
+                     scale, noise_sd, noise_key, s.wb, s.w, s.part);
   float bc1 = 1.f, bc2 = 1.f;
   if (update) {
     s.step++;

@@ -45,10 +45,14 @@ __device__ inline int nbits64(uint64_t v) { return v ? 64 - __clzll((long long)v
 //                     parameters are uniform across the wave
 // ----------------------------------------------------------------------------
 constexpr int TT = 64;
+typedef long long v2ll __attribute__((ext_vector_type(2)));
 constexpr int64_t SENT = INT64_MIN;
 
 __host__ __device__ inline int64_t pad_ranks(int64_t R) { return (R + 63) & ~(int64_t)63; }
 
+// 64 ranks x 64 columns per workgroup.  Reads: lane pairs of adjacent
+// columns of one row (16-byte loads when rows are 16-byte aligned, i.e. I*G
+// even); writes: lane pairs of adjacent ranks of one column (16-byte stores).
 __global__ __launch_bounds__(256) void transpose_kernel(const int64_t *__restrict__ T, int64_t R,
                                                         int IG, int G, const int32_t *it,
                                                         int64_t *__restrict__ Tt) {
@@ -56,18 +60,35 @@ __global__ __launch_bounds__(256) void transpose_kernel(const int64_t *__restric
   const int64_t r0 = (int64_t)blockIdx.x * TT;
   const int c0 = blockIdx.y * TT;
   const int64_t Rp = pad_ranks(R);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int k = ty; k < TT; k += 4) {
+  const int p2 = 2 * (threadIdx.x & 31), k0 = threadIdx.x >> 5;
+  const int ca = c0 + p2;  // this thread's columns ca, ca + 1 (read phase)
+  const int ia = ca / G, ib = (ca + 1) / G;
+  const bool vec = (IG & 1) == 0;
+  for (int k = k0; k < TT; k += 8) {
     const int64_t r = r0 + k;
-    const int c = c0 + tx;
-    int64_t v = SENT;
-    if (r < R && c < IG && (it == nullptr || c / G < it[r])) v = __builtin_nontemporal_load(&T[r * IG + c]);
-    tile[k][tx] = v;
+    int64_t v0 = SENT, v1 = SENT;
+    if (r < R) {
+      const int nit = it ? it[r] : 0x7fffffff;
+      const int64_t *row = T + r * IG;
+      if (vec && ca + 1 < IG) {
+        const v2ll q = __builtin_nontemporal_load(reinterpret_cast<const v2ll *>(row + ca));
+        v0 = ia < nit ? (int64_t)q.x : SENT;
+        v1 = ib < nit ? (int64_t)q.y : SENT;
+      } else {
+        if (ca < IG && ia < nit) v0 = __builtin_nontemporal_load(row + ca);
+        if (ca + 1 < IG && ib < nit) v1 = __builtin_nontemporal_load(row + ca + 1);
+      }
+    }
+    tile[k][p2] = v0;
+    tile[k][p2 + 1] = v1;
   }
   __syncthreads();
-  for (int k = ty; k < TT; k += 4) {
+  for (int k = k0; k < TT; k += 8) {
     const int c = c0 + k;
-    if (c < IG) Tt[(int64_t)c * Rp + r0 + tx] = tile[tx][k];
+    if (c < IG) {
+      const v2ll q = {tile[p2][k], tile[p2 + 1][k]};
+      *reinterpret_cast<v2ll *>(Tt + (int64_t)c * Rp + r0 + p2) = q;
+    }
   }
 }
 
@@ -78,8 +99,6 @@ constexpr int DIG = 11;           // bits per digit
 constexpr int NB = 1 << DIG;
 constexpr int NHC = 2;            // histogram copies (waves alternate)
 constexpr int BPT = NB / CS;      // bins per thread in the bin search
-
-typedef long long v2ll __attribute__((ext_vector_type(2)));
 
 __device__ inline uint64_t shr64(uint64_t x, int s) { return s >= 64 ? 0 : x >> s; }
 

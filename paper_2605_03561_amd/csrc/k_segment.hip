@@ -20,8 +20,7 @@
 namespace ta {
 namespace {
 
-constexpr int NT = 256;
-constexpr int NWAVE = NT / 64;
+constexpr int NT_MAX = 512;  // largest workgroup (LDS reductions are sized for it)
 
 // The events of one tile held by one thread, plus the two halo values the
 // wave edges need (the timestamp after lane 63's last event and the context
@@ -135,8 +134,11 @@ __device__ inline void acc_sq(uint64_t &lo, uint64_t &hi, int64_t v) {
   hi = (uint64_t)(s >> 64);
 }
 
-template <bool ATTR, bool SEG, int EPT, bool NTMP>
-__global__ __launch_bounds__(NT) void seg_kernel(SegArgs a) {
+// NT threads per workgroup (256 or 512); a 512-thread workgroup is limited to
+// 128 VGPRs so that two fit on a CU beside each other (the LDS allows two).
+template <bool ATTR, bool SEG, int EPT, bool NTMP, int NT>
+__global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void seg_kernel(SegArgs a) {
+  constexpr int NWAVE = NT / 64;
   constexpr int TILE = NT * EPT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = a.N, G = a.G, I = a.I, W = a.W;
@@ -439,7 +441,7 @@ size_t segment_lds_bytes(int N, int G, bool attr, bool seg, int *W, int *log2W) 
   size_t fixed = 0;
   if (attr) fixed += ((size_t)(N + 1) * 8 + 15) & ~(size_t)15;
   fixed += ((size_t)N * 4 + 15) & ~(size_t)15;
-  fixed += 2 * NWAVE * sizeof(int) + NWAVE * sizeof(int64_t);
+  fixed += 2 * (NT_MAX / 64) * sizeof(int) + (NT_MAX / 64) * sizeof(int64_t);
   int w = 2, lw = 1;
   if (seg) {
     // Largest power-of-two ring within 16 KiB, and within what leaves room for
@@ -454,35 +456,49 @@ size_t segment_lds_bytes(int N, int G, bool attr, bool seg, int *W, int *log2W) 
   *W = w;
   *log2W = lw;
   size_t ring = seg ? (size_t)w * G * 8 : 0;
-  if (ring < (size_t)NT * 24) ring = (size_t)NT * 24;
+  if (ring < (size_t)NT_MAX * 24) ring = (size_t)NT_MAX * 24;
   return fixed + ring;
 }
 
 namespace {
 
-template <bool A, bool S, int EPT, bool NTMP>
+template <bool A, bool S, int EPT, bool NTMP, int NT>
 hipError_t launch_variant(const SegArgs &a, int grid, size_t lds, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute(reinterpret_cast<const void *>(&seg_kernel<A, S, EPT, NTMP>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&seg_kernel<A, S, EPT, NTMP, NT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL((seg_kernel<A, S, EPT, NTMP>), dim3(grid), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((seg_kernel<A, S, EPT, NTMP, NT>), dim3(grid), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
 template <bool A, bool S>
 hipError_t launch_ept(const SegArgs &a, const SegShape &sh, int grid, size_t lds, hipStream_t s) {
+  if (sh.threads == 512) {
+    // 512-thread workgroups: the fused pass only, 2 or 4 events per thread.
+    if constexpr (A && S) {
+      switch (sh.ept * 2 + (sh.nontemporal ? 1 : 0)) {
+        case 4: return launch_variant<A, S, 2, false, 512>(a, grid, lds, s);
+        case 5: return launch_variant<A, S, 2, true, 512>(a, grid, lds, s);
+        case 8: return launch_variant<A, S, 4, false, 512>(a, grid, lds, s);
+        case 9: return launch_variant<A, S, 4, true, 512>(a, grid, lds, s);
+        default: return hipErrorInvalidValue;
+      }
+    }
+    return hipErrorInvalidValue;
+  }
+  if (sh.threads != 256) return hipErrorInvalidValue;
   switch (sh.ept * 2 + (sh.nontemporal ? 1 : 0)) {
-    case 4: return launch_variant<A, S, 2, false>(a, grid, lds, s);
-    case 5: return launch_variant<A, S, 2, true>(a, grid, lds, s);
-    case 8: return launch_variant<A, S, 4, false>(a, grid, lds, s);
-    case 9: return launch_variant<A, S, 4, true>(a, grid, lds, s);
-    case 16: return launch_variant<A, S, 8, false>(a, grid, lds, s);
-    case 17: return launch_variant<A, S, 8, true>(a, grid, lds, s);
-    case 32: return launch_variant<A, S, 16, false>(a, grid, lds, s);
-    case 33: return launch_variant<A, S, 16, true>(a, grid, lds, s);
+    case 4: return launch_variant<A, S, 2, false, 256>(a, grid, lds, s);
+    case 5: return launch_variant<A, S, 2, true, 256>(a, grid, lds, s);
+    case 8: return launch_variant<A, S, 4, false, 256>(a, grid, lds, s);
+    case 9: return launch_variant<A, S, 4, true, 256>(a, grid, lds, s);
+    case 16: return launch_variant<A, S, 8, false, 256>(a, grid, lds, s);
+    case 17: return launch_variant<A, S, 8, true, 256>(a, grid, lds, s);
+    case 32: return launch_variant<A, S, 16, false, 256>(a, grid, lds, s);
+    case 33: return launch_variant<A, S, 16, true, 256>(a, grid, lds, s);
     default: return hipErrorInvalidValue;
   }
 }

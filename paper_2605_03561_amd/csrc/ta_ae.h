@@ -58,10 +58,11 @@ size_t ae_norm_ws_bytes(int64_t R);
 hipError_t launch_ae_rows(const AeState &s, const int64_t *T, int64_t R, int I, const int32_t *it,
                           float *rows, int64_t *n_rows, void *ws, size_t ws_bytes, hipStream_t st);
 size_t ae_rows_ws_bytes(int64_t R);
-// One optimiser step on rows perm(k), k in [k0, k0 + batch), perm(k) = (a*k + c) mod n.
+// One optimiser step on rows perm(k), k in [k0, k0 + batch), perm(k) = (a*k + c) mod n;
+// noise_sd > 0: denoising step (inputs x + noise_sd * N(0,1) drawn under noise_key).
 hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, int batch,
-                          uint64_t a, uint64_t c, float lr, bool update, hipStream_t st,
-                          float *grad_out, float *loss_out);
+                          uint64_t a, uint64_t c, float lr, bool update, float noise_sd,
+                          uint64_t noise_key, hipStream_t st, float *grad_out, float *loss_out);
 // Workspace of launch_ae_score (score kind 2 keeps per-region residual means
 // and their z-scores, [64][R] FP64 each).
 size_t ae_score_ws_bytes(int64_t R);

@@ -275,11 +275,14 @@ void plan_free(ta_plan p) {
   delete p;
 }
 
-// --- autotune cache: a flat JSON object {"<key>": {"ept": e, "nt": n, "wgs": w, "ms": t}, ...}
+// --- autotune cache: a flat JSON object
+// {"<key>": {"threads": t, "ept": e, "nt": n, "wgs": w, "ms": m}, ...}
+// (entries without "threads" are read as 256-thread shapes).
 struct CacheEntry {
   std::string key;
   int ept, nt, wgs;
   double ms;
+  int threads;
 };
 
 std::vector<CacheEntry> cache_read(const char *path) {
@@ -299,9 +302,11 @@ std::vector<CacheEntry> cache_read(const char *path) {
     size_t br = txt.find('{', q1);
     size_t be = txt.find('}', br);
     if (q1 == std::string::npos || br == std::string::npos || be == std::string::npos) break;
-    CacheEntry c{txt.substr(q0 + 1, q1 - q0 - 1), 0, 0, 0, 0.0};
+    CacheEntry c{txt.substr(q0 + 1, q1 - q0 - 1), 0, 0, 0, 0.0, 256};
     std::string body = txt.substr(br, be - br + 1);
-    if (sscanf(body.c_str(), "{\"ept\": %d, \"nt\": %d, \"wgs\": %d, \"ms\": %lf}", &c.ept, &c.nt,
+    if (sscanf(body.c_str(), "{\"threads\": %d, \"ept\": %d, \"nt\": %d, \"wgs\": %d, \"ms\": %lf}",
+               &c.threads, &c.ept, &c.nt, &c.wgs, &c.ms) == 5 ||
+        sscanf(body.c_str(), "{\"ept\": %d, \"nt\": %d, \"wgs\": %d, \"ms\": %lf}", &c.ept, &c.nt,
                &c.wgs, &c.ms) == 4)
       out.push_back(c);
     pos = be + 1;
@@ -316,8 +321,9 @@ void cache_write(const char *path, const std::vector<CacheEntry> &es) {
   if (!f) return;
   fprintf(f, "{\n");
   for (size_t i = 0; i < es.size(); i++)
-    fprintf(f, "  \"%s\": {\"ept\": %d, \"nt\": %d, \"wgs\": %d, \"ms\": %.4f}%s\n", es[i].key.c_str(),
-            es[i].ept, es[i].nt, es[i].wgs, es[i].ms, i + 1 < es.size() ? "," : "");
+    fprintf(f, "  \"%s\": {\"threads\": %d, \"ept\": %d, \"nt\": %d, \"wgs\": %d, \"ms\": %.4f}%s\n",
+            es[i].key.c_str(), es[i].threads, es[i].ept, es[i].nt, es[i].wgs, es[i].ms,
+            i + 1 < es.size() ? "," : "");
   fprintf(f, "}\n");
   fclose(f);
   rename(tmp.c_str(), path);
@@ -689,6 +695,7 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
   bool found = false;
   for (const CacheEntry &c : cache)
     if (c.key == key) {
+      best.threads = c.threads;
       best.ept = c.ept;
       best.nontemporal = c.nt != 0;
       best.wgs_per_cu = c.wgs;
@@ -697,11 +704,20 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
     }
   if (d->autotune && !found) {
     bool have = false;
-    for (int ept : {2, 4, 8, 16})
+    struct TE {
+      int threads, ept;
+    };
+    std::vector<TE> tes = {{256, 2}, {256, 4}, {256, 8}, {256, 16}};
+    if (L.attr && L.seg) {
+      tes.push_back({512, 2});
+      tes.push_back({512, 4});
+    }
+    for (const TE &te : tes)
       for (int nt : {0, 1})
         for (int wgs : {0, occ}) {
           ta::SegShape sh;
-          sh.ept = ept;
+          sh.threads = te.threads;
+          sh.ept = te.ept;
           sh.nontemporal = nt != 0;
           sh.wgs_per_cu = wgs;
           float ms = 0.f;
@@ -717,7 +733,7 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
           }
         }
     if (d->autotune == 2 && cpath) {
-      cache.push_back({key, best.ept, best.nontemporal ? 1 : 0, best.wgs_per_cu, best_ms});
+      cache.push_back({key, best.ept, best.nontemporal ? 1 : 0, best.wgs_per_cu, best_ms, best.threads});
       cache_write(cpath, cache);
     }
   }
@@ -788,9 +804,10 @@ ta_status ta_plan_launch(ta_plan p, void *stream) {
   return TA_OK;
 }
 
-ta_status ta_plan_info(ta_plan p, int32_t *events_per_thread, int32_t *nontemporal,
-                       int32_t *wgs_per_cu, float *tuned_ms) {
+ta_status ta_plan_info(ta_plan p, int32_t *threads, int32_t *events_per_thread,
+                       int32_t *nontemporal, int32_t *wgs_per_cu, float *tuned_ms) {
   if (!p) return TA_ERR_INVALID_ARG;
+  if (threads) *threads = p->shape.threads;
   if (events_per_thread) *events_per_thread = p->shape.ept;
   if (nontemporal) *nontemporal = p->shape.nontemporal ? 1 : 0;
   if (wgs_per_cu) *wgs_per_cu = p->shape.wgs_per_cu;
@@ -920,31 +937,35 @@ ta_status ta_ae_rows(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_
   return TA_OK;
 }
 
-ta_status ta_ae_grad(ta_handle h, const float *rows, int64_t n_rows, float *grad, float *loss,
-                     void *stream) {
+ta_status ta_ae_grad(ta_handle h, const float *rows, int64_t n_rows, float input_noise,
+                     uint64_t noise_key, float *grad, float *loss, void *stream) {
   if (!h) return TA_ERR_INVALID_ARG;
   if (!rows || n_rows < 1 || !grad || !aligned16(rows) || !aligned16(grad) || !aligned16(loss))
     return fail(h, TA_ERR_INVALID_ARG, "bad rows or outputs");
+  if (!(input_noise >= 0.f) || input_noise > 1e6f)
+    return fail(h, TA_ERR_INVALID_ARG, "input_noise must be in [0, 1e6]");
   if (!h->ae.ready) return fail(h, TA_ERR_STATE, "ta_ae_init has not been called");
   if (n_rows > ((int64_t)1 << 31)) return fail(h, TA_ERR_SIZE_OVERFLOW, "too many rows");
   DeviceGuard dg(h->device);
   hipError_t e = ta::launch_ae_step(h->ae, rows, n_rows, 0, (int)n_rows, 1, 0, 0.f, false,
-                                    (hipStream_t)stream, grad, loss);
+                                    input_noise, noise_key, (hipStream_t)stream, grad, loss);
   if (e != hipSuccess) return hipfail(h, e, "ae grad");
   return TA_OK;
 }
 
 ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t epochs, int32_t batch,
-                      float lr, uint64_t shuffle_seed, float *epoch_loss, void *stream) {
+                      float lr, float input_noise, uint64_t shuffle_seed, float *epoch_loss,
+                      void *stream) {
   if (!h) return TA_ERR_INVALID_ARG;
   if (!rows || n_rows < 1 || epochs < 0 || batch < 1 || !(lr > 0.f) || !aligned16(rows) ||
-      !aligned16(epoch_loss))
+      !aligned16(epoch_loss) || !(input_noise >= 0.f) || input_noise > 1e6f)
     return fail(h, TA_ERR_INVALID_ARG, "bad training arguments");
   if (!h->ae.ready) return fail(h, TA_ERR_STATE, "ta_ae_init has not been called");
   if (n_rows > ((int64_t)1 << 32)) return fail(h, TA_ERR_SIZE_OVERFLOW, "too many rows");
   DeviceGuard dg(h->device);
   hipStream_t s = (hipStream_t)stream;
   uint64_t rs = shuffle_seed;
+  uint64_t ns = shuffle_seed ^ 0x5851F42D4C957F2Dull;  // noise keys: a stream of their own
   if (epoch_loss && epochs > 0)
     hipLaunchKernelGGL(fill_f32, dim3((epochs + 255) / 256), dim3(256), 0, s, epoch_loss, epochs, 0.f);
   const uint64_t n = (uint64_t)n_rows;
@@ -958,8 +979,9 @@ ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t ep
       c = splitmix(rs) % n;
     }
     for (int64_t k0 = 0; k0 < n_rows; k0 += batch) {
-      hipError_t e = ta::launch_ae_step(h->ae, rows, n_rows, k0, batch, a, c, lr, true, s, nullptr,
-                                        nullptr);
+      const uint64_t nkey = splitmix(ns);
+      hipError_t e = ta::launch_ae_step(h->ae, rows, n_rows, k0, batch, a, c, lr, true, input_noise,
+                                        nkey, s, nullptr, nullptr);
       if (e != hipSuccess) return hipfail(h, e, "ae step");
       if (epoch_loss) {
         const int64_t bv = std::min<int64_t>(batch, n_rows - k0);

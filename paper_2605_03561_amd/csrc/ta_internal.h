@@ -56,6 +56,7 @@ struct SegArgs {
 
 // Launch shape of the fused pass (chosen by the batch autotuner).
 struct SegShape {
+  int threads = 256;        // workgroup size: 256, or 512 (fused pass, ept 2 or 4)
   int ept = 4;              // events per thread per tile: 2, 4, 8 or 16
   bool nontemporal = false; // streaming loads/stores that bypass cache retention
   int wgs_per_cu = 0;       // 0: one workgroup per rank; k > 0: persistent, k per CU

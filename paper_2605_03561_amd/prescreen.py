@@ -25,6 +25,7 @@ C4 = dict(n_ranks=10_000, median_len=50_000, min_len=1_000, max_len=400_000, n_n
           depth_max=12, n_iters=500, n_regions=64, app_seed=4)
 TRAIN_SEEDS = (1001, 1002, 1003, 1004, 1005)
 KINDS = (0, 1, 2)   # ta.AE_SCORE_ERROR, AE_SCORE_RESIDUAL, AE_SCORE_RESIDUAL_Z
+INPUT_NOISE = 0.5   # denoising training: standard deviation of the input noise (normalised units)
 HELD_OUT = ((2001, 0.005), (2002, 0.01), (2003, 0.02), (2004, 0.035), (2005, 0.05))
 
 
@@ -51,9 +52,12 @@ def _recall_at(scores: np.ndarray, flags: np.ndarray, k: int) -> float:
 
 
 def train(h: ta.Handle, seeds=TRAIN_SEEDS, epochs=20, batch=4096, lr=1e-3, init_seed=7,
-          cfg=C4, inject_margin=0.075, log=print):
+          cfg=C4, inject_margin=0.075, noise=INPUT_NOISE, log=print):
     """Fit the normalisation on the training tensors (no injected anomalies),
-    train the network on all their profile rows, then -- on the training
+    train the network on all their profile rows as a denoising autoencoder
+    (inputs corrupted with N(0, noise^2) per feature, scored against the clean
+    rows, so it learns each region from the others instead of copying it),
+    then -- on the training
     tensors only -- measure the exact scan's flag rate f, set the screen size
     k_frac = f + inject_margin, choose the score kind that best recovers the
     exact flags, and calibrate the fallback threshold at the (1 - k_frac / 2)
@@ -71,7 +75,7 @@ def train(h: ta.Handle, seeds=TRAIN_SEEDS, epochs=20, batch=4096, lr=1e-3, init_
     log(f"[prescreen] {rows.shape[0]} training rows from {len(seeds)} seeds in {time.time() - t0:.1f}s")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record()
-    el = h.ae_train(rows, epochs, batch=batch, lr=lr, seed=init_seed)
+    el = h.ae_train(rows, epochs, batch=batch, lr=lr, seed=init_seed, noise=noise)
     ev[1].record()
     torch.cuda.synchronize()
     train_ms = ev[0].elapsed_time(ev[1])
@@ -97,7 +101,7 @@ def train(h: ta.Handle, seeds=TRAIN_SEEDS, epochs=20, batch=4096, lr=1e-3, init_
         f"recall of training flags by score kind {kind_recall} -> kind {kind}")
     del tensors
     torch.cuda.empty_cache()
-    return {"epochs": epochs, "batch": batch, "lr": lr,
+    return {"epochs": epochs, "batch": batch, "lr": lr, "input_noise": noise,
             "train_rows": int(len(seeds) * R * cfg["n_iters"]), "train_s": train_ms / 1e3,
             "epoch_loss": el.cpu().numpy().tolist(), "train_flag_rate": f_train,
             "k_frac": k_frac, "score_kind": int(kind),

@@ -78,13 +78,13 @@ def _load():
         "ta_topology_aggregate": [P, P, P, i64, P, P, P, i32, i32, i32, P, P, P, P, P, P, P],
         "ta_plan_create": [P, P, P, P, P, P],
         "ta_plan_launch": [P, P],
-        "ta_plan_info": [P, P, P, P, P],
+        "ta_plan_info": [P, P, P, P, P, P],
         "ta_plan_destroy": [P],
         "ta_ae_init": [P, C.c_uint64, P],
         "ta_ae_fit_norm": [P, P, i64, i32, i32, P, i32, P],
         "ta_ae_rows": [P, P, i64, i32, i32, P, P, P, P],
-        "ta_ae_grad": [P, P, i64, P, P, P],
-        "ta_ae_train": [P, P, i64, i32, i32, C.c_float, C.c_uint64, P, P],
+        "ta_ae_grad": [P, P, i64, C.c_float, C.c_uint64, P, P, P],
+        "ta_ae_train": [P, P, i64, i32, i32, C.c_float, C.c_float, C.c_uint64, P, P],
         "ta_ae_score": [P, P, i64, i32, i32, P, P, P],
         "ta_ae_set_score_kind": [P, i32],
         "ta_ae_get_score_kind": [P, P],
@@ -313,17 +313,18 @@ class Handle:
                                     C.byref(n), _stream(self.device)))
         return rows[:n.value]
 
-    def ae_grad(self, rows):
+    def ae_grad(self, rows, noise=0.0, noise_key=0):
         g = self._empty((self.AE_NP,), torch.float32)
         loss = self._empty((1,), torch.float32)
-        self._check(_lib.ta_ae_grad(self.h, _ptr(rows), rows.shape[0], _ptr(g), _ptr(loss),
+        self._check(_lib.ta_ae_grad(self.h, _ptr(rows), rows.shape[0], C.c_float(noise),
+                                    C.c_uint64(noise_key), _ptr(g), _ptr(loss),
                                     _stream(self.device)))
         return g, loss
 
-    def ae_train(self, rows, epochs, batch=4096, lr=1e-3, seed=0):
+    def ae_train(self, rows, epochs, batch=4096, lr=1e-3, seed=0, noise=0.0):
         el = self._empty((max(epochs, 1),), torch.float32)
         self._check(_lib.ta_ae_train(self.h, _ptr(rows), rows.shape[0], int(epochs), int(batch),
-                                     C.c_float(lr), C.c_uint64(seed), _ptr(el),
+                                     C.c_float(lr), C.c_float(noise), C.c_uint64(seed), _ptr(el),
                                      _stream(self.device)))
         return el[:epochs]
 
@@ -428,10 +429,10 @@ class Plan:
         self.h._check(_lib.ta_plan_launch(self.p, _stream(self.h.device)))
 
     def info(self):
-        ept, nt, wgs, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
-        self.h._check(_lib.ta_plan_info(self.p, C.byref(ept), C.byref(nt), C.byref(wgs),
-                                        C.byref(ms)))
-        return {"events_per_thread": ept.value, "nontemporal": nt.value,
+        th, ept, nt, wgs, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
+        self.h._check(_lib.ta_plan_info(self.p, C.byref(th), C.byref(ept), C.byref(nt),
+                                        C.byref(wgs), C.byref(ms)))
+        return {"threads": th.value, "events_per_thread": ept.value, "nontemporal": nt.value,
                 "wgs_per_cu": wgs.value, "tuned_ms": ms.value}
 
     def close(self):

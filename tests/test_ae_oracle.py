@@ -186,3 +186,52 @@ def test_residual_z_score_equals_exact_totals_scan(oracle):
     keep[[0, 5]] = False
     sub = ae.rank_scores(zero, T[keep], it[keep], mu, sd, kind=2)
     np.testing.assert_allclose(got2[keep], sub, rtol=1e-15)
+
+
+def test_gaussian_noise_moments_and_determinism():
+    """The counter-based normal draws: deterministic per (key, row, feature),
+    different keys give uncorrelated draws, and over 64k draws the sample
+    moments are those of N(0, 1) within a few standard errors (mean, variance,
+    skewness 0, kurtosis 3, P(|z| > 1.96) = 0.05)."""
+    a = ae.gaussian_noise(12345, np.arange(1000))
+    assert a.shape == (1000, 64)
+    assert np.array_equal(a, ae.gaussian_noise(12345, np.arange(1000)))
+    assert np.array_equal(a[[7, 3]], ae.gaussian_noise(12345, [7, 3]))
+    z = a.reshape(-1)
+    n = z.size
+    assert abs(z.mean()) < 4 / np.sqrt(n)
+    assert abs(z.var() - 1) < 4 * np.sqrt(2 / n)
+    assert abs((z ** 3).mean()) < 4 * np.sqrt(15 / n)
+    assert abs((z ** 4).mean() - 3) < 4 * np.sqrt(96 / n)
+    tail = (np.abs(z) > 1.959963984540054).mean()
+    assert abs(tail - 0.05) < 4 * np.sqrt(0.05 * 0.95 / n)
+    b = ae.gaussian_noise(54321, np.arange(1000)).reshape(-1)
+    assert abs(np.corrcoef(z, b)[0, 1]) < 4 / np.sqrt(n)
+    # neighbouring features and rows are uncorrelated too
+    assert abs(np.corrcoef(a[:, :-1].reshape(-1), a[:, 1:].reshape(-1))[0, 1]) < 4 / np.sqrt(n)
+    assert abs(np.corrcoef(a[:-1].reshape(-1), a[1:].reshape(-1))[0, 1]) < 4 / np.sqrt(n)
+
+
+def test_denoising_gradient_finite_differences():
+    """With a corrupted input the gradient is still that of the loss against
+    the clean rows (central differences), and it differs from the plain one."""
+    rng = np.random.default_rng(4)
+    p = _rand_params(4)
+    X = rng.normal(0, 1, (6, 64))
+    Xn = X + 0.5 * ae.gaussian_noise(99, np.arange(6))
+    l0, g = ae.loss_and_grads(p, X, X_in=Xn)
+    _, g_plain = ae.loss_and_grads(p, X)
+    assert not np.allclose(g["W1"], g_plain["W1"])
+    h = 1e-4
+    for k in ("W1", "b2", "W4"):
+        flat = p[k].reshape(-1)
+        for idx in rng.choice(flat.size, 4, replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = ae.loss_and_grads(p, X, X_in=Xn)
+            flat[idx] = old - h
+            lm, _ = ae.loss_and_grads(p, X, X_in=Xn)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[k].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * abs(an) + 1e-10, (k, idx, fd, an)

@@ -114,6 +114,28 @@ def test_gradient_matches_oracle(env):
     assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-2
 
 
+def test_denoising_gradient_matches_oracle(env):
+    """Denoising gradient: the GPU draws the input noise itself (counter-based
+    normal draws per row and feature); the oracle draws the same values from
+    their definition.  The GPU's FP32 log/cos differ from FP64 by rounding
+    only, far inside the bfloat16 operand rounding."""
+    torch, ta, h = env
+    rng = np.random.default_rng(12)
+    h.ae_init(78)
+    X = rng.normal(0, 1, (300, 64)).astype(np.float32)
+    key, sd = 0x1234ABCD5678, 0.7
+    g, loss = h.ae_grad(torch.from_numpy(X).cuda(), noise=sd, noise_key=key)
+    g = g.cpu().numpy().astype(np.float64)
+    p = ae.init_params(78)
+    Xn = (X + np.float32(sd) * ae.gaussian_noise(key, np.arange(300)).astype(np.float32)).astype(np.float32)
+    l_ref, g_ref = ae.loss_and_grads(p, X.astype(np.float64), bf16=True, X_in=Xn.astype(np.float64))
+    l_plain, _ = ae.loss_and_grads(p, X.astype(np.float64), bf16=True)
+    assert abs(loss.item() - l_ref) / l_ref < 1e-3
+    assert abs(l_plain - l_ref) / l_ref > 1e-2          # the noise did change the step
+    rg = flat(g_ref)
+    assert np.linalg.norm(g - rg) / np.linalg.norm(rg) < 1e-2
+
+
 def test_adam_step_matches_oracle(env):
     torch, ta, h = env
     rng = np.random.default_rng(3)

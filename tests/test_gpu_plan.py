@@ -41,6 +41,7 @@ def test_all_shapes_identical(env, oracle):
     assert np.array_equal(p.seg["incl"].cpu().numpy(), inc)
     info = p.info()
     assert info["events_per_thread"] in (2, 4, 8, 16) and info["tuned_ms"] > 0
+    assert info["threads"] in (256, 512)
     p.close()
 
 
@@ -54,19 +55,26 @@ def test_cached_shapes_identical(env, oracle, tmp_path, monkeypatch):
     key_line = [l for l in path.read_text().splitlines() if '"ept"' in l][0]
     key = key_line.split('"')[1]
     p.close()
-    for ept in (2, 4, 8, 16):
+    shapes = [(256, e) for e in (2, 4, 8, 16)] + [(512, 2), (512, 4)]
+    for threads, ept in shapes:
         for nt in (0, 1):
             for wgs in (0, 1, 2):
-                path.write_text('{\n  "%s": {"ept": %d, "nt": %d, "wgs": %d, "ms": 1.0}\n}\n'
-                                % (key, ept, nt, wgs))
+                path.write_text('{\n  "%s": {"threads": %d, "ept": %d, "nt": %d, "wgs": %d, "ms": 1.0}\n}\n'
+                                % (key, threads, ept, nt, wgs))
                 p = h.plan(tr, w.n_iters, w.offsets, imbalance=False, outliers=False, autotune=2)
-                assert p.info() == {"events_per_thread": ept, "nontemporal": nt,
+                assert p.info() == {"threads": threads, "events_per_thread": ept, "nontemporal": nt,
                                     "wgs_per_cu": wgs, "tuned_ms": 1.0}
                 p.launch()
                 h.sync_status()
-                assert np.array_equal(p.seg["tensor"].cpu().numpy(), T), (ept, nt, wgs)
+                assert np.array_equal(p.seg["tensor"].cpu().numpy(), T), (threads, ept, nt, wgs)
                 assert np.array_equal(p.seg["iters_found"].cpu().numpy(), it)
                 p.close()
+    # a cache entry of the older form (no "threads") is a 256-thread shape
+    path.write_text('{\n  "%s": {"ept": 4, "nt": 0, "wgs": 1, "ms": 2.0}\n}\n' % key)
+    p = h.plan(tr, w.n_iters, w.offsets, imbalance=False, outliers=False, autotune=2)
+    assert p.info() == {"threads": 256, "events_per_thread": 4, "nontemporal": 0, "wgs_per_cu": 1,
+                        "tuned_ms": 2.0}
+    p.close()
 
 
 def test_graph_replays_match_eager(env):
