@@ -236,9 +236,10 @@ def copy_calibration(mib: int):
 
 def prescreen_summary(h, epochs):
     """Train the autoencoder on five runs of the pre-screen workload (10,000
-    ranks, 500 iterations, 64 regions, no injected slow ranks) and judge it
-    against the exact FULL scan on five held-out runs with 0.5..5% injected
-    slow ranks (recall, precision, GPU time of each)."""
+    ranks, 500 iterations, 64 regions, no injected slow ranks), set its
+    operating point on three labelled calibration runs (1, 3, 5 % injected),
+    and judge it against the exact FULL scan on five held-out runs with
+    0.5..5 % injected slow ranks (recall, precision, GPU time of each)."""
     from paper_2605_03561_amd import prescreen
     log = lambda m: print(m, file=sys.stderr, flush=True)
     rep = prescreen.train(h, epochs=epochs, log=log)
@@ -248,20 +249,24 @@ def prescreen_summary(h, epochs):
         "workload": f"{c['n_ranks']} ranks, lognormal lengths median {c['median_len']} "
                     f"({c['min_len']}..{c['max_len']}), {c['n_nodes']}-node tree, "
                     f"{c['n_iters']} iterations, {c['n_regions']} regions; trained on "
-                    f"{len(prescreen.TRAIN_SEEDS)} runs without injection, judged on "
+                    f"{len(prescreen.TRAIN_SEEDS)} runs without injection, operating point set on "
+                    f"{len(prescreen.CALIB)} calibration runs with 1..5% injected, judged on "
                     f"{len(prescreen.HELD_OUT)} held-out runs with 0.5..5% injected slow ranks",
         "epochs": rep["epochs"], "train_s": rep["train_s"],
         "loss_first": rep["epoch_loss"][0], "loss_last": rep["epoch_loss"][-1],
-        "train_flag_rate": rep["train_flag_rate"], "k_frac": rep["k_frac"],
+        "input_noise": rep["input_noise"], "calib_flag_rates": rep["calib_flag_rates"],
+        "k_needed_by_kind": rep["k_needed_by_kind"], "k_frac": rep["k_frac"],
         "score_kind": rep["score_kind"],
         "recall_min": summ["recall_min"], "recall_mean": summ["recall_mean"],
         "precision_mean": summ["precision_mean"],
         "full_scan_ms": summ["full_scan_ms_mean"], "prescreen_ms": summ["prescreen_ms_mean"],
+        "ae_score_ms": summ["ae_score_ms_mean"],
         "speedup_min": summ["speedup_min"], "speedup_mean": summ["speedup_mean"],
         "untrained_recall_mean": summ["untrained_recall_mean"],
         "totals_scan_recall_mean": summ["totals_scan_recall_mean"],
         "totals_scan_ms": summ["totals_scan_ms_mean"],
         "any_fallback": summ["any_fallback"],
+        "k_needed_for_recall_0995_max": summ["k_needed_max"],
         "recall_by_kind": [r["recall_by_kind"] for r in rows],
         "untrained_recall_by_kind": [r["untrained_recall_by_kind"] for r in rows],
         "meets_target": bool(summ["recall_min"] >= 0.99 and summ["speedup_min"] >= 5.0),

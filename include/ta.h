@@ -236,7 +236,9 @@ ta_status ta_callpath(ta_handle h, int32_t leaf, int32_t *path_host, int32_t cap
  * workgroup per rank or a persistent grid) and captures the fused pass --
  * optionally followed by the imbalance and outlier stages -- into a graph
  * over the buffers given here.
- *   autotune 0: the default shape; 1: time every candidate shape on this
+ *   autotune 0: the default shape (fused pass: 512 threads x 4 events per
+ *   thread, one workgroup per rank; the eager calls use it too); 1: time
+ *   every candidate shape on this
  *   batch (each produces identical results) and keep the fastest; 2: as 1, but
  *   reuse the choice stored in the JSON file named by the TA_AUTOTUNE_CACHE
  *   environment variable when it holds this batch shape (and store new ones).

@@ -201,13 +201,39 @@ def robust_z(v: np.ndarray) -> np.ndarray:
     return np.zeros_like(v)
 
 
+def robust_z32(v) -> np.ndarray:
+    """robust_z in IEEE FP32, one operation at a time: med = (a + b) * 0.5 of
+    the two middle values (a for an odd count), MAD likewise over |v - med|,
+    scale = 1.4826 * MAD, else 1.253314 * mean |v - med| (the mean summed in
+    FP64, then rounded), else 0; z = (v - med) / scale."""
+    v = np.asarray(v, np.float32)
+    n = v.size
+    if n == 0:
+        return v.copy()
+    f = np.float32
+    s = np.sort(v)
+    med = s[(n - 1) // 2] if n % 2 else f((s[n // 2 - 1] + s[n // 2]) * f(0.5))
+    dev = np.abs(v - med).astype(np.float32)
+    d = np.sort(dev)
+    mad = d[(n - 1) // 2] if n % 2 else f((d[n // 2 - 1] + d[n // 2]) * f(0.5))
+    if mad > 0:
+        scale = f(f(1.4826) * mad)
+    else:
+        mean_ad = dev.astype(np.float64).sum() / n
+        scale = f(1.253314 * mean_ad) if mean_ad > 0 else f(0)
+    if scale == 0:
+        return np.zeros(n, np.float32)
+    return ((v - med) / scale).astype(np.float32)
+
+
 def rank_scores(p: dict, T: np.ndarray, iters, mu, sd, bf16: bool = False,
                 kind: int = 0) -> np.ndarray:
     """kind 0: score[r] = max_g mean_{i < iters[r]} (y - x)^2 (reconstruction
     error); kind 1: score[r] = max_g |m(r,g)| with m(r,g) = mean_{i < iters[r]}
     (y - x) (persistent residual of a region over the rank's iterations);
-    kind 2: score[r] = max_g |robust_z over ranks with iterations of m(., g)|.
-    Ranks without iterations score 0 and take no part in kind 2."""
+    kind 2: score[r] = max_g |robust_z32 over ranks with iterations of
+    m(., g) rounded to FP32| (the second stage in FP32).  Ranks without
+    iterations score 0 and take no part in kind 2."""
     R, I, G = T.shape
     X = normalize(T, mu, sd)
     err = np.zeros((R, G))
@@ -228,6 +254,6 @@ def rank_scores(p: dict, T: np.ndarray, iters, mu, sd, bf16: bool = False,
         return np.where(active, np.abs(m).max(1), 0.0)
     out = np.zeros(R)
     for g in range(G):
-        z = robust_z(m[active, g])
-        out[active] = np.maximum(out[active], np.abs(z))
+        z = robust_z32(m[active, g].astype(np.float32))
+        out[active] = np.maximum(out[active], np.abs(z).astype(np.float64))
     return out

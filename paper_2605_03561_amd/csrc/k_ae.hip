@@ -574,7 +574,7 @@ __global__ __launch_bounds__(SW * 64) void ae_score_kernel(const int64_t *__rest
                                                            const uint16_t *__restrict__ wb,
                                                            const float *__restrict__ w,
                                                            const float *mu, const float *isd,
-                                                           int kind, float *score, double *v_t) {
+                                                           int kind, float *score, float *v_t) {
   extern __shared__ __align__(16) unsigned char smem[];
   ScoreLds &L = *reinterpret_cast<ScoreLds *>(smem);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -614,26 +614,42 @@ __global__ __launch_bounds__(SW * 64) void ae_score_kernel(const int64_t *__rest
     float e2[4] = {0.f, 0.f, 0.f, 0.f};
     double rs[4] = {0.0, 0.0, 0.0, 0.0};
     u4v buf[16];
+    // Rows past the rank's last one are clamped to it (loaded, then ignored),
+    // so every load is in bounds and unconditional.
     auto load = [&](int i0) {
 #pragma unroll
       for (int h = 0; h < 16; h++) {
-        const int i = i0 + 2 * h + lh;
-        if (i < n)
-          buf[h] = __builtin_nontemporal_load(
-              reinterpret_cast<const u4v *>(src + (int64_t)i * AE_IN + lc));
+        int i = i0 + 2 * h + lh;
+        i = i < n ? i : n - 1;
+        buf[h] = __builtin_nontemporal_load(reinterpret_cast<const u4v *>(src + (int64_t)i * AE_IN + lc));
       }
     };
     if (n > 0) load(0);
     for (int i0 = 0; i0 < n; i0 += SR) {
+      // int64 -> FP32 (correctly rounded): cells in [0, 2^32) take one
+      // unsigned conversion; a lane holding any wider cell converts all 32 in full.
+      float cv[32];
+      uint32_t wide = 0;
+#pragma unroll
+      for (int h = 0; h < 16; h++) {
+        wide |= buf[h][1] | buf[h][3];
+        cv[2 * h] = (float)buf[h][0];
+        cv[2 * h + 1] = (float)buf[h][2];
+      }
+      if (wide) {
+#pragma unroll
+        for (int h = 0; h < 16; h++) {
+          cv[2 * h] = (float)(int64_t)(((uint64_t)buf[h][1] << 32) | buf[h][0]);
+          cv[2 * h + 1] = (float)(int64_t)(((uint64_t)buf[h][3] << 32) | buf[h][2]);
+        }
+      }
 #pragma unroll
       for (int h = 0; h < 16; h++) {  // normalised inputs of this step (rows past n are zero)
         const int i = 2 * h + lh;
         const bool ok = i0 + i < n;
-        const int64_t x0 = (int64_t)(((uint64_t)buf[h][1] << 32) | buf[h][0]);
-        const int64_t x1 = (int64_t)(((uint64_t)buf[h][3] << 32) | buf[h][2]);
         float2 x;
-        x.x = ok ? ((float)x0 - m0) * s0 : 0.f;
-        x.y = ok ? ((float)x1 - m1) * s1 : 0.f;
+        x.x = ok ? (cv[2 * h] - m0) * s0 : 0.f;
+        x.y = ok ? (cv[2 * h + 1] - m1) * s1 : 0.f;
         *reinterpret_cast<float2 *>(&X[i * P_X + lc]) = x;
       }
       if (i0 + SR < n) load(i0 + SR);  // next step's rows, in flight during the network
@@ -732,11 +748,10 @@ __global__ __launch_bounds__(SW * 64) void ae_score_kernel(const int64_t *__rest
             for (int k = 0; k < 4; k++) acc = mfma32(a4[t][k], bw[k], acc);
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-              if (i0 + 16 * t + rq + j < n) {
-                const float res = acc[j] + bc - xr[t][nt][j];
-                e2[nt] += res * res;
-                rs[nt] += (double)res;
-              }
+              const float r0 = acc[j] + bc - xr[t][nt][j];
+              const float res = (i0 + 16 * t + rq + j < n) ? r0 : 0.f;  // rows past n add 0
+              e2[nt] += res * res;
+              rs[nt] += (double)res;
             }
           }
         }
@@ -749,7 +764,7 @@ __global__ __launch_bounds__(SW * 64) void ae_score_kernel(const int64_t *__rest
       const float a = col_sum(e2[nt]);
       const double b = col_sum(rs[nt]);
       if (kind == 2) {
-        if (lane < 16) v_t[(int64_t)(16 * nt + col) * R + r] = n > 0 ? b / (double)n : 0.0;
+        if (lane < 16) v_t[(int64_t)(16 * nt + col) * R + r] = n > 0 ? (float)(b / (double)n) : 0.f;
       } else {
         const float v = n > 0 ? (kind == 0 ? a / (float)n : (float)(fabs(b) / (double)n)) : 0.f;
         best = fmaxf(best, v);
@@ -761,14 +776,195 @@ __global__ __launch_bounds__(SW * 64) void ae_score_kernel(const int64_t *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Top-k: the k largest scores (ties toward the lower rank id), listed in
-// ascending rank id; also counts scores above a threshold.
+// Second stage of score kind 2, in FP32: per region g over the ranks with
+// iterations, med = median of m(., g), MAD = median of |m - med|, z = (m - med)
+// / (1.4826 MAD); when MAD is 0, 1.253314 * mean |m - med| (summed in FP64)
+// replaces 1.4826 MAD; when that is 0 too, z = 0.  Medians of an even count
+// are (a + b) * 0.5.  Every step is one IEEE FP32 operation in this order.
+// Exact selection: radix select with 11-bit digits on order-preserving keys.
 // ---------------------------------------------------------------------------
+constexpr int RS = 1024;            // threads per region workgroup
+constexpr int RSW = RS / 64;
+constexpr int RNB = 2048;           // bins of an 11-bit digit
+constexpr int RBPT = RNB / RS;
+
 __device__ inline uint32_t fkey(float f) {
   const uint32_t u = __float_as_uint(f);
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
+__device__ inline float fdec(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
 
+struct RegLds {
+  uint32_t hist[RNB];
+  int64_t wtot[RSW];
+  uint32_t wmin[RSW];
+  double wsum[RSW];
+  uint32_t state[4];
+};
+
+__device__ inline bool region_active(const int32_t *it, int I, int64_t r) {
+  return it ? it[r] > 0 : I > 0;
+}
+
+// k-th smallest of keyf(r) over active ranks (32-bit keys), and with
+// want_next the (k+1)-th.
+template <class KeyF>
+__device__ void select32(int64_t R, const int32_t *it, int I, KeyF keyf, int64_t k, bool want_next,
+                         RegLds &L, uint32_t &v1, uint32_t &v2) {
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  uint32_t pref = 0;
+  v1 = v2 = 0;
+  for (int hi = 32; hi > 0;) {
+    const int w = hi >= 11 ? 11 : hi;
+    const int lo = hi - w;
+    const bool last = lo == 0;
+    uint32_t mgt = 0xffffffffu;
+    for (int64_t r = t; r < R; r += RS) {
+      if (!region_active(it, I, r)) continue;
+      const uint32_t key = keyf(r);
+      const uint32_t top = hi >= 32 ? 0u : key >> hi;
+      if (top == pref) atomicAdd(&L.hist[(key >> lo) & ((1u << w) - 1)], 1u);
+      else if (last && top > pref && key < mgt) mgt = key;
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+      const uint32_t o = __shfl_xor(mgt, d, 64);
+      mgt = o < mgt ? o : mgt;
+    }
+    if (lane == 0) L.wmin[wid] = mgt;
+    __syncthreads();
+    uint32_t cnt[RBPT];
+    int64_t own = 0;
+#pragma unroll
+    for (int j = 0; j < RBPT; j++) {
+      cnt[j] = L.hist[t * RBPT + j];
+      own += cnt[j];
+    }
+    int64_t incl = own;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t o = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += o;
+    }
+    if (lane == 63) L.wtot[wid] = incl;
+    __syncthreads();
+    int64_t excl = incl - own;
+    for (int q = 0; q < wid; q++) excl += L.wtot[q];
+    uint32_t mg = L.wmin[0];
+    for (int q = 1; q < RSW; q++) mg = L.wmin[q] < mg ? L.wmin[q] : mg;
+    __syncthreads();  // all histogram reads are done
+    for (int j = t; j < RNB; j += RS) L.hist[j] = 0;
+    if (excl <= k && k < excl + own) {
+      int64_t cum = excl;
+      int j = 0;
+      for (; j < RBPT; j++) {
+        if (cum + (int64_t)cnt[j] > k) break;
+        cum += cnt[j];
+      }
+      L.state[0] = (pref << w) | (uint32_t)(t * RBPT + j);
+      L.state[1] = (uint32_t)(k - cum);
+      L.state[2] = (k - cum + 1 < (int64_t)cnt[j]) ? 1u : 0u;
+      // next non-empty bin above the selected one (only meaningful on the last digit)
+      uint32_t nb = 0xffffffffu;
+      for (int jj = j + 1; jj < RBPT && nb == 0xffffffffu; jj++)
+        if (cnt[jj]) nb = (uint32_t)(t * RBPT + jj);
+      L.state[3] = nb;
+    }
+    __syncthreads();
+    const uint32_t np = L.state[0];
+    const int64_t kk = (int64_t)L.state[1];
+    if (last && want_next && L.state[2] == 0 && L.state[3] == 0xffffffffu) {
+      // the next non-empty bin lies in a later thread's range: scan the merged
+      // counts again (read before the clear by the owners, kept in cnt)
+      uint32_t nb = 0xffffffffu;
+      const uint32_t bsel = np & ((1u << w) - 1);
+#pragma unroll
+      for (int j = RBPT - 1; j >= 0; j--)
+        if ((uint32_t)(t * RBPT + j) > bsel && cnt[j]) nb = (uint32_t)(t * RBPT + j);
+      for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(nb, d, 64);
+        nb = o < nb ? o : nb;
+      }
+      if (lane == 0) L.wmin[wid] = nb;
+      __syncthreads();
+      nb = L.wmin[0];
+      for (int q = 1; q < RSW; q++) nb = L.wmin[q] < nb ? L.wmin[q] : nb;
+      __syncthreads();
+      if (t == 0) L.state[3] = nb;
+      __syncthreads();
+    }
+    if (last) {
+      v1 = np;
+      if (!want_next || L.state[2]) v2 = np;
+      else if (L.state[3] != 0xffffffffu) v2 = (pref << w) | L.state[3];
+      else v2 = mg;
+    }
+    __syncthreads();
+    pref = np;
+    k = kk;
+    hi = lo;
+  }
+  if (!want_next) v2 = v1;
+}
+
+__global__ __launch_bounds__(RS) void region_robust_f32(const float *__restrict__ v_t, int64_t R,
+                                                        const int32_t *it, int I, float *z_t) {
+  __shared__ RegLds L;
+  const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const float *v = v_t + (int64_t)g * R;
+  float *z = z_t + (int64_t)g * R;
+  for (int j = t; j < RNB; j += RS) L.hist[j] = 0;
+  int64_t nl = 0;
+  for (int64_t r = t; r < R; r += RS) nl += region_active(it, I, r) ? 1 : 0;
+  for (int d = 32; d >= 1; d >>= 1) nl += __shfl_xor(nl, d, 64);
+  if (lane == 0) L.wtot[wid] = nl;
+  __syncthreads();
+  int64_t n = 0;
+  for (int q = 0; q < RSW; q++) n += L.wtot[q];
+  __syncthreads();
+  float med = 0.f, scale = 0.f;
+  if (n > 0) {
+    const int64_t k = (n - 1) / 2;
+    const bool even = (n & 1) == 0;
+    uint32_t a, b;
+    select32(R, it, I, [&](int64_t r) { return fkey(v[r]); }, k, even, L, a, b);
+    med = even ? (fdec(a) + fdec(b)) * 0.5f : fdec(a);
+    // |m - med| >= 0: its bit pattern orders like the value
+    select32(R, it, I, [&](int64_t r) { return __float_as_uint(fabsf(v[r] - med)); }, k, even, L, a,
+             b);
+    const float mad = even ? (__uint_as_float(a) + __uint_as_float(b)) * 0.5f : __uint_as_float(a);
+    if (mad > 0.f) {
+      scale = 1.4826f * mad;
+    } else {
+      double sl = 0.0;
+      for (int64_t r = t; r < R; r += RS)
+        if (region_active(it, I, r)) sl += (double)fabsf(v[r] - med);
+      for (int d = 32; d >= 1; d >>= 1) sl += __shfl_xor(sl, d, 64);
+      if (lane == 0) L.wsum[wid] = sl;
+      __syncthreads();
+      double s = 0.0;
+      for (int q = 0; q < RSW; q++) s += L.wsum[q];
+      const double mean_ad = s / (double)n;
+      if (mean_ad > 0.0) scale = (float)(1.253314 * mean_ad);
+    }
+  }
+  for (int64_t r = t; r < R; r += RS)
+    z[r] = (scale > 0.f && region_active(it, I, r)) ? (v[r] - med) / scale : 0.f;
+}
+
+// score[r] = max_g |z(r, g)| (0 for ranks without iterations).
+__global__ __launch_bounds__(256) void rank_max_z32(const float *z_t, int64_t R, int G, float *score) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= R) return;
+  float best = 0.f;
+  for (int g = 0; g < G; g++) best = fmaxf(best, fabsf(z_t[(int64_t)g * R + r]));
+  score[r] = best;
+}
+
+// ---------------------------------------------------------------------------
+// Top-k: the k largest scores (ties toward the lower rank id), listed in
+// ascending rank id; also counts scores above a threshold.
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void topk_kernel(const float *score, int64_t R, int64_t k,
                                                     int32_t *idx, int32_t *n_above, float thr) {
   __shared__ uint32_t hist[256];
@@ -956,7 +1152,7 @@ hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, 
   return hipGetLastError();
 }
 
-size_t ae_score_ws_bytes(int64_t R) { return 2 * (((size_t)R * AE_IN * 8 + 255) & ~(size_t)255); }
+size_t ae_score_ws_bytes(int64_t R) { return 2 * (((size_t)R * AE_IN * 4 + 255) & ~(size_t)255); }
 
 hipError_t launch_ae_score(const AeState &s, const int64_t *T, int64_t R, int I, const int32_t *it,
                            float *score, void *ws, size_t ws_bytes, hipStream_t st) {
@@ -970,8 +1166,8 @@ hipError_t launch_ae_score(const AeState &s, const int64_t *T, int64_t R, int I,
   const bool stage2 = s.score_kind == 2;
   const size_t half = ae_score_ws_bytes(R) / 2;
   if (stage2 && (ws == nullptr || ws_bytes < 2 * half)) return hipErrorInvalidValue;
-  double *v_t = stage2 ? (double *)ws : nullptr;
-  double *z_t = stage2 ? (double *)((char *)ws + half) : nullptr;
+  float *v_t = stage2 ? (float *)ws : nullptr;
+  float *z_t = stage2 ? (float *)((char *)ws + half) : nullptr;
   int cus = 256, dev = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -980,7 +1176,12 @@ hipError_t launch_ae_score(const AeState &s, const int64_t *T, int64_t R, int I,
   hipLaunchKernelGGL(ae_score_kernel, dim3((unsigned)grid), dim3(SW * 64), sizeof(ScoreLds), st, T, R,
                      I, it, s.wb, s.w, s.mu, s.isd, s.score_kind, score, v_t);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess && stage2) e = launch_region_robust(v_t, R, AE_IN, it, I, z_t, score, st);
+  if (e == hipSuccess && stage2) {
+    hipLaunchKernelGGL(region_robust_f32, dim3(AE_IN), dim3(RS), 0, st, v_t, R, it, I, z_t);
+    hipLaunchKernelGGL(rank_max_z32, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, z_t, R, AE_IN,
+                       score);
+    e = hipGetLastError();
+  }
   return e;
 }
 

@@ -24,6 +24,7 @@ struct ta_handle_s {
   uint32_t *d_err = nullptr;
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  int32_t *pin = nullptr;  // pinned host word (pre-screen fallback count)
   ta::AeState ae;
 };
 
@@ -230,6 +231,18 @@ int device_cus(int device) {
   return n;
 }
 
+// Launch shape of eager calls and of untuned plans: the fused pass with 512
+// threads x 4 events per thread, one workgroup per rank (the tuned choice on
+// the 100k-rank batch); the separate passes with 256 x 4.
+ta::SegShape default_shape(const SegLaunch &L) {
+  ta::SegShape sh{};
+  if (L.attr && L.seg) {
+    sh.threads = 512;
+    sh.ept = 4;
+  }
+  return sh;
+}
+
 int grid_for(const SegLaunch &L, const ta::SegShape &sh, int cus) {
   const int64_t R = L.a.R;
   if (sh.wgs_per_cu <= 0) return (int)std::min<int64_t>(R, (int64_t)1 << 30);
@@ -243,7 +256,7 @@ ta_status run_segment(ta_handle h, const ta_traces *t, int32_t n_iters, const ta
   if (st) return st;
   if (t->n_ranks == 0) return TA_OK;
   DeviceGuard dg(h->device);
-  const ta::SegShape sh{};
+  const ta::SegShape sh = default_shape(L);
   hipError_t e = ta::launch_segment(L.a, L.attr, L.seg, sh, grid_for(L, sh, device_cus(h->device)),
                                     L.lds, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "segment kernel launch");
@@ -407,6 +420,7 @@ ta_status ta_destroy(ta_handle h) {
   if (h->d_tin_tout) hipFree(h->d_tin_tout);
   if (h->d_err) hipFree(h->d_err);
   if (h->ws) hipFree(h->ws);
+  if (h->pin) hipHostFree(h->pin);
   ta::ae_free(h->ae);
   delete h;
   return TA_OK;
@@ -687,7 +701,7 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
   // Launch shape: default, cached, or measured on this batch.
   const int cus = device_cus(h->device);
   const int occ = std::max(1, (int)((160 * 1024) / std::max<size_t>(L.lds, 1)));
-  ta::SegShape best{};
+  ta::SegShape best = default_shape(L);
   float best_ms = 0.f;
   const char *cpath = getenv("TA_AUTOTUNE_CACHE");
   const std::string key = plan_key(h, L);
@@ -1069,10 +1083,11 @@ ta_status ta_prescreen(ta_handle h, const int64_t *tensor, int64_t n_ranks, int3
                             h->ws_bytes - (fl + 256), s);
     const float thr = h->ae.threshold >= 0.f ? h->ae.threshold : 3.4e38f;
     if (e == hipSuccess) e = ta::launch_topk(score, n_ranks, k, topk_ranks, above, thr, s);
-    int32_t n_above = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&n_above, above, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && !h->pin) e = hipHostMalloc((void **)&h->pin, sizeof(int32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->pin, above, 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hipfail(h, e, "prescreen");
+    const int32_t n_above = *h->pin;
     fallback = h->ae.threshold >= 0.f && n_above > k;
   }
   *used_fallback_host = fallback ? 1 : 0;

@@ -24,8 +24,10 @@ from . import gpu_synth, ta
 C4 = dict(n_ranks=10_000, median_len=50_000, min_len=1_000, max_len=400_000, n_nodes=1_000,
           depth_max=12, n_iters=500, n_regions=64, app_seed=4)
 TRAIN_SEEDS = (1001, 1002, 1003, 1004, 1005)
+CALIB = ((3001, 0.01), (3002, 0.03), (3003, 0.05))
+TARGET_RECALL = 0.995
 KINDS = (0, 1, 2)   # ta.AE_SCORE_ERROR, AE_SCORE_RESIDUAL, AE_SCORE_RESIDUAL_Z
-INPUT_NOISE = 0.5   # denoising training: standard deviation of the input noise (normalised units)
+INPUT_NOISE = 1.0   # denoising training: standard deviation of the input noise (normalised units)
 HELD_OUT = ((2001, 0.005), (2002, 0.01), (2003, 0.02), (2004, 0.035), (2005, 0.05))
 
 
@@ -44,24 +46,32 @@ def make_tensor(h: ta.Handle, seed: int, inject_frac: float, cfg=C4, device="cud
     return out["tensor"], out["iters_found"], meta
 
 
-def _recall_at(scores: np.ndarray, flags: np.ndarray, k: int) -> float:
-    order = np.lexsort((np.arange(len(scores)), -scores))[:k]
-    sel = np.zeros(len(scores), bool)
-    sel[order] = True
-    return float((sel & flags).sum() / max(flags.sum(), 1))
+def _k_needed(scores: np.ndarray, flags: np.ndarray, recall: float) -> int:
+    """Smallest k whose top-k (ties toward the lower rank id) holds at least
+    `recall` of the flagged ranks."""
+    n = int(flags.sum())
+    if n == 0:
+        return 0
+    order = np.lexsort((np.arange(len(scores)), -scores))
+    pos = np.nonzero(flags[order])[0]            # positions of flagged ranks, ascending
+    need = int(np.ceil(recall * n))
+    return int(pos[need - 1]) + 1
 
 
-def train(h: ta.Handle, seeds=TRAIN_SEEDS, epochs=20, batch=4096, lr=1e-3, init_seed=7,
-          cfg=C4, inject_margin=0.075, noise=INPUT_NOISE, log=print):
+def train(h: ta.Handle, seeds=TRAIN_SEEDS, calib=CALIB, epochs=20, batch=4096, lr=1e-3,
+          init_seed=7, cfg=C4, noise=INPUT_NOISE, target_recall=TARGET_RECALL, log=print):
     """Fit the normalisation on the training tensors (no injected anomalies),
     train the network on all their profile rows as a denoising autoencoder
     (inputs corrupted with N(0, noise^2) per feature, scored against the clean
     rows, so it learns each region from the others instead of copying it),
-    then -- on the training
-    tensors only -- measure the exact scan's flag rate f, set the screen size
-    k_frac = f + inject_margin, choose the score kind that best recovers the
-    exact flags, and calibrate the fallback threshold at the (1 - k_frac / 2)
-    quantile of the training scores."""
+    then set the operating point on labelled calibration runs (injected slow
+    ranks; disjoint from the training and the held-out runs): for every score
+    kind the smallest k that reaches `target_recall` of the exact FULL scan's
+    flags on every calibration run; keep the kind with the smallest k, add one
+    percent of R, and calibrate the fallback threshold at the score of rank
+    k / 1.25 (the pre-screen falls back to the exact scan when more than k
+    ranks exceed it, i.e. on a run with far more high scores than calibration
+    saw)."""
     t0 = time.time()
     tensors = []
     for s in seeds:
@@ -72,7 +82,7 @@ def train(h: ta.Handle, seeds=TRAIN_SEEDS, epochs=20, batch=4096, lr=1e-3, init_
         h.ae_fit_norm(T, it, reset=(i == 0))
     rows = torch.cat([h.ae_rows(T, it) for T, it in tensors])
     torch.cuda.synchronize()
-    log(f"[prescreen] {rows.shape[0]} training rows from {len(seeds)} seeds in {time.time() - t0:.1f}s")
+    log(f"[prescreen] {rows.shape[0]} training rows from {len(seeds)} runs in {time.time() - t0:.1f}s")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record()
     el = h.ae_train(rows, epochs, batch=batch, lr=lr, seed=init_seed, noise=noise)
@@ -81,31 +91,42 @@ def train(h: ta.Handle, seeds=TRAIN_SEEDS, epochs=20, batch=4096, lr=1e-3, init_
     train_ms = ev[0].elapsed_time(ev[1])
     log(f"[prescreen] trained {epochs} epochs in {train_ms / 1e3:.1f}s: loss "
         f"{el[0].item():.4f} -> {el[-1].item():.4f}")
-    del rows
+    del rows, tensors
     torch.cuda.empty_cache()
-    flags = [h.outliers(T, it)["rank_flag"].cpu().numpy().astype(bool) for T, it in tensors]
-    f_train = max(float(f.mean()) for f in flags)
-    k_frac = min(1.0, f_train + inject_margin)
+
     R = cfg["n_ranks"]
+    need = {kind: 0 for kind in KINDS}
+    cal_scores = {kind: [] for kind in KINDS}
+    cal_rates = []
+    for s, rate in calib:
+        T, it, _ = make_tensor(h, s, rate, cfg)
+        flags = h.outliers(T, it)["rank_flag"].cpu().numpy().astype(bool)
+        cal_rates.append(float(flags.mean()))
+        for kind in KINDS:
+            h.ae_set_score_kind(kind)
+            sc = h.ae_score(T, it).cpu().numpy()
+            cal_scores[kind].append(sc)
+            need[kind] = max(need[kind], _k_needed(sc, flags, target_recall))
+        del T, it
+        torch.cuda.empty_cache()
+    kind = min(KINDS, key=lambda q: (need[q], q))
+    k_frac = min(1.0, need[kind] / R + 0.01)
     k = int(round(k_frac * R))
-    kind_recall = {}
-    for kind in KINDS:
-        h.ae_set_score_kind(kind)
-        kind_recall[kind] = float(np.mean([_recall_at(h.ae_score(T, it).cpu().numpy(), f, k)
-                                           for (T, it), f in zip(tensors, flags)]))
-    kind = max(kind_recall, key=lambda q: (kind_recall[q], -q))
     h.ae_set_score_kind(kind)
-    scores = torch.cat([h.ae_score(T, it) for T, it in tensors])
-    h.ae_calibrate(scores, 1.0 - k_frac / 2)
-    log(f"[prescreen] exact flag rate on training seeds {f_train:.3f} -> k_frac {k_frac:.3f}; "
-        f"recall of training flags by score kind {kind_recall} -> kind {kind}")
-    del tensors
-    torch.cuda.empty_cache()
+    # threshold: the score at position k / 1.25 of the calibration runs (the largest
+    # over runs), so a run falls back when more than k ranks exceed it -- at least
+    # 25 % more high scores than any calibration run had
+    pos = max(0, min(R - 1, int(k / 1.25)))
+    thr = max(float(np.sort(sc)[::-1][pos]) for sc in cal_scores[kind])
+    h.ae_calibrate(torch.tensor(np.array([thr], np.float32), device=h.device), 1.0)
+    log(f"[prescreen] calibration runs: exact flag rates {cal_rates}; k needed for recall "
+        f"{target_recall} by score kind { {q: need[q] for q in KINDS} } -> kind {kind}, "
+        f"k_frac {k_frac:.3f}, threshold {thr:.4g}")
     return {"epochs": epochs, "batch": batch, "lr": lr, "input_noise": noise,
             "train_rows": int(len(seeds) * R * cfg["n_iters"]), "train_s": train_ms / 1e3,
-            "epoch_loss": el.cpu().numpy().tolist(), "train_flag_rate": f_train,
-            "k_frac": k_frac, "score_kind": int(kind),
-            "train_recall_by_kind": {int(q): v for q, v in kind_recall.items()}}
+            "epoch_loss": el.cpu().numpy().tolist(), "calib_flag_rates": cal_rates,
+            "k_needed_by_kind": {int(q): int(need[q]) for q in KINDS},
+            "k_frac": k_frac, "score_kind": int(kind), "threshold": thr}
 
 
 def _time(fn, reps=3):
@@ -155,13 +176,18 @@ def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_s
             hit = (s & flags).sum()
             return float(hit / max(flags.sum(), 1)), float(hit / max(len(sel), 1))
 
-        by_kind, by_kind_untrained, score_ms = {}, {}, {}
+        by_kind, by_kind_untrained, score_ms, k_need = {}, {}, {}, {}
         for kind in KINDS:
             h.ae_set_score_kind(kind)
             ref.ae_set_score_kind(kind)
             score_ms[kind], sc = _time(lambda: h.ae_score(T, it))
+            sc_u = ref.ae_score(T, it).cpu().numpy()
             by_kind[kind] = recall(topk(sc.cpu().numpy()))[0]
-            by_kind_untrained[kind] = recall(topk(ref.ae_score(T, it).cpu().numpy()))[0]
+            by_kind_untrained[kind] = recall(topk(sc_u))[0]
+            if kind == chosen:
+                k_need["trained"] = _k_needed(sc.cpu().numpy(), flags, TARGET_RECALL)
+                k_need["untrained"] = _k_needed(sc_u, flags, TARGET_RECALL)
+        k_need["totals_scan"] = _k_needed(tot["rank_score"].cpu().numpy(), flags, TARGET_RECALL)
         h.ae_set_score_kind(chosen)
         r_ae, p_ae = recall(top.cpu().numpy())
         r_tt, p_tt = recall(topk(tot["rank_score"].cpu().numpy()))
@@ -175,6 +201,7 @@ def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_s
                "untrained_recall": by_kind_untrained[chosen],
                "recall_by_kind": by_kind, "untrained_recall_by_kind": by_kind_untrained,
                "totals_scan_recall": r_tt, "totals_scan_precision": p_tt,
+               "k_needed_for_target_recall": k_need,
                "full_scan_ms": t_full, "prescreen_ms": t_pre, "ae_score_ms_by_kind": score_ms,
                "totals_scan_ms": t_tot, "speedup_vs_full": t_full / t_pre}
         log(f"[prescreen] seed {seed} rate {rate:.3f}: exact flags {row['n_flagged_exact']}, "
@@ -194,7 +221,10 @@ def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_s
             "untrained_recall_mean": float(np.mean([r["untrained_recall"] for r in rows])),
             "totals_scan_recall_mean": float(np.mean([r["totals_scan_recall"] for r in rows])),
             "full_scan_ms_mean": float(np.mean([r["full_scan_ms"] for r in rows])),
+            "ae_score_ms_mean": float(np.mean([r["ae_score_ms_by_kind"][chosen] for r in rows])),
             "prescreen_ms_mean": float(np.mean([r["prescreen_ms"] for r in rows])),
             "totals_scan_ms_mean": float(np.mean([r["totals_scan_ms"] for r in rows])),
-            "any_fallback": any(r["used_fallback"] for r in rows)}
+            "any_fallback": any(r["used_fallback"] for r in rows),
+            "k_needed_max": {q: max(r["k_needed_for_target_recall"][q] for r in rows)
+                             for q in ("trained", "untrained", "totals_scan")}}
     return summ, rows

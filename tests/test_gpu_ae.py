@@ -239,17 +239,19 @@ def test_topk_ties_and_edges(env):
         assert top.cpu().numpy().tolist() == sorted(order)
 
 
-def test_residual_z_with_bias_only_network(env):
-    """Weights zero, output bias c: the residual is c - x exactly (no matrix
-    product rounding), so the kind-2 score matches the oracle to FP32
-    accuracy, including the MAD-0 fallback region and ranks without
-    iterations; 70 ranks span two score workgroups and a partial one."""
+@pytest.mark.parametrize("R", [1, 2, 3, 70, 1025, 2049])
+def test_residual_z_with_bias_only_network(env, R):
+    """Weights zero, output bias c: the residual is c - x up to one FP32
+    rounding per row, so the kind-2 score matches the oracle to FP32 accuracy,
+    including a constant region (z = 0), a region whose MAD is 0 (mean absolute
+    deviation fallback) and ranks without iterations; rank counts around the
+    1024-thread selection workgroup and the 8-rank score workgroups."""
     torch, ta, h = env
-    rng = np.random.default_rng(9)
-    T, it = fake_tensor(rng, 70, 45, rng.integers(0, 46, 70).astype(np.int32))
-    it[:20] = 45
+    rng = np.random.default_rng(9 + R)
+    T, it = fake_tensor(rng, R, 45, rng.integers(0, 46, R).astype(np.int32))
+    it[: max(1, (2 * R) // 7)] = 45
     T[:, :, 3] = 12345                         # constant region: z = 0
-    T[:50, :, 4] = 777                         # MAD 0, mean AD > 0
+    T[: (5 * R) // 7 + 1, :, 4] = 777          # MAD 0, mean AD > 0
     dT, dit = torch.from_numpy(T).cuda(), torch.from_numpy(it).cuda()
     h.ae_init(3)
     h.ae_fit_norm(dT, dit)
