@@ -337,6 +337,8 @@ ta_status ta_ae_score(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32
  * synchronises. */
 ta_status ta_ae_calibrate(ta_handle h, const float *rank_score, int64_t n_ranks, double quantile,
                           void *stream);
+/* The fallback threshold in use (host float; negative when none is set). */
+ta_status ta_ae_get_threshold(ta_handle h, float *threshold_host);
 /* Pre-screen: topk_ranks[k] (device) = the k ranks with the largest scores
  * (ties toward the lower rank id), in ascending rank id.  Fallback to the exact
  * scan (TA_SCAN_FULL, TA_SCORE_MAD) -- the k ranks with the largest exact

@@ -1055,6 +1055,13 @@ ta_status ta_ae_calibrate(ta_handle h, const float *rank_score, int64_t n_ranks,
   return TA_OK;
 }
 
+ta_status ta_ae_get_threshold(ta_handle h, float *threshold_host) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!threshold_host) return fail(h, TA_ERR_INVALID_ARG, "threshold_host is NULL");
+  *threshold_host = h->ae.threshold;
+  return TA_OK;
+}
+
 ta_status ta_prescreen(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
                        int32_t n_regions, const int32_t *iters_found, int64_t k,
                        int32_t *topk_ranks, float *rank_score, int32_t *used_fallback_host,

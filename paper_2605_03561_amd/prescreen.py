@@ -69,9 +69,9 @@ def train(h: ta.Handle, seeds=TRAIN_SEEDS, calib=CALIB, epochs=20, batch=4096, l
     kind the smallest k that reaches `target_recall` of the exact FULL scan's
     flags on every calibration run; keep the kind with the smallest k, add one
     percent of R, and calibrate the fallback threshold at the score of rank
-    k / 1.25 (the pre-screen falls back to the exact scan when more than k
-    ranks exceed it, i.e. on a run with far more high scores than calibration
-    saw)."""
+    0.9 k on the calibration runs (the largest over runs): the pre-screen falls
+    back to the exact scan when more than k ranks exceed it, i.e. on a run with
+    more high-scoring ranks than the top k can hold."""
     t0 = time.time()
     tensors = []
     for s in seeds:
@@ -97,11 +97,12 @@ def train(h: ta.Handle, seeds=TRAIN_SEEDS, calib=CALIB, epochs=20, batch=4096, l
     R = cfg["n_ranks"]
     need = {kind: 0 for kind in KINDS}
     cal_scores = {kind: [] for kind in KINDS}
-    cal_rates = []
+    cal_rates, cal_nflags = [], []
     for s, rate in calib:
         T, it, _ = make_tensor(h, s, rate, cfg)
         flags = h.outliers(T, it)["rank_flag"].cpu().numpy().astype(bool)
         cal_rates.append(float(flags.mean()))
+        cal_nflags.append(int(flags.sum()))
         for kind in KINDS:
             h.ae_set_score_kind(kind)
             sc = h.ae_score(T, it).cpu().numpy()
@@ -113,10 +114,11 @@ def train(h: ta.Handle, seeds=TRAIN_SEEDS, calib=CALIB, epochs=20, batch=4096, l
     k_frac = min(1.0, need[kind] / R + 0.01)
     k = int(round(k_frac * R))
     h.ae_set_score_kind(kind)
-    # threshold: the score at position k / 1.25 of the calibration runs (the largest
-    # over runs), so a run falls back when more than k ranks exceed it -- at least
-    # 25 % more high scores than any calibration run had
-    pos = max(0, min(R - 1, int(k / 1.25)))
+    # threshold: the score at position 0.9 k on the calibration runs (the largest
+    # over runs), so about 0.9 k ranks of a run like them exceed it; a run with more
+    # than k ranks above it -- more high-scoring ranks than the top k can hold --
+    # falls back to the exact scan.
+    pos = max(0, min(R - 1, int(0.9 * k)))
     thr = max(float(np.sort(sc)[::-1][pos]) for sc in cal_scores[kind])
     h.ae_calibrate(torch.tensor(np.array([thr], np.float32), device=h.device), 1.0)
     log(f"[prescreen] calibration runs: exact flag rates {cal_rates}; k needed for recall "
@@ -167,7 +169,9 @@ def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_s
         t_full, full = _time(lambda: h.outliers(T, it, mode=ta.SCAN_FULL, kind=ta.SCORE_MAD))
         flags = full["rank_flag"].cpu().numpy().astype(bool)
         t_pre, pre = _time(lambda: h.prescreen(T, it, k))
-        top, _, fb = pre
+        top, pre_score, fb = pre
+        thr = h.ae_threshold()
+        n_above = int((pre_score.cpu().numpy() > thr).sum()) if thr >= 0 else None
         t_tot, tot = _time(lambda: h.outliers(T, it, mode=ta.SCAN_TOTALS, kind=ta.SCORE_MAD))
 
         def recall(sel):
@@ -197,6 +201,7 @@ def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_s
         row = {"seed": seed, "inject_rate": rate, "n_flagged_exact": int(flags.sum()),
                "injected_flagged_by_exact": float(flags[inj].mean()) if inj.any() else None,
                "k": k, "recall": r_ae, "precision": p_ae, "used_fallback": bool(fb),
+               "n_above_threshold": n_above,
                "injected_recall": float(sel[inj].mean()) if inj.any() else None,
                "untrained_recall": by_kind_untrained[chosen],
                "recall_by_kind": by_kind, "untrained_recall_by_kind": by_kind_untrained,

@@ -89,6 +89,7 @@ def _load():
         "ta_ae_set_score_kind": [P, i32],
         "ta_ae_get_score_kind": [P, P],
         "ta_ae_calibrate": [P, P, i64, f64, P],
+        "ta_ae_get_threshold": [P, P],
         "ta_prescreen": [P, P, i64, i32, i32, P, i64, P, P, P, P],
         "ta_ae_get_state": [P, P, C.c_size_t],
         "ta_ae_set_state": [P, P, C.c_size_t],
@@ -342,6 +343,11 @@ class Handle:
         self._check(_lib.ta_ae_score(self.h, _ptr(tensor), R, I, G, _ptr(iters_found), _ptr(sc),
                                      _stream(self.device)))
         return sc
+
+    def ae_threshold(self) -> float:
+        t = C.c_float(0.0)
+        self._check(_lib.ta_ae_get_threshold(self.h, C.byref(t)))
+        return float(t.value)
 
     def ae_calibrate(self, scores, quantile):
         self._check(_lib.ta_ae_calibrate(self.h, _ptr(scores), scores.numel(), float(quantile),
