@@ -92,18 +92,18 @@ __global__ __launch_bounds__(256) void transpose_kernel(const int64_t *__restric
   }
 }
 
-constexpr int CS = 512;           // threads per column workgroup
+constexpr int CS = 256;           // threads per column workgroup
 constexpr int CWV = CS / 64;      // waves
 constexpr int CU = 4;             // 16-byte loads in flight per thread
 constexpr int DIG = 11;           // bits per digit
 constexpr int NB = 1 << DIG;
-constexpr int NHC = 2;            // histogram copies (waves alternate)
+constexpr int NHC = 1;            // histogram copies
 constexpr int BPT = NB / CS;      // bins per thread in the bin search
 
 __device__ inline uint64_t shr64(uint64_t x, int s) { return s >= 64 ? 0 : x >> s; }
 
-constexpr int MS = 2048;          // sample slots (LDS)
-constexpr int SEL_GRID_MAX = 1024; // column workgroups (persistent, one scratch slot each)
+constexpr int MS = 1024;          // sample slots (LDS)
+constexpr int SEL_GRID_MAX = 2048; // column workgroups (persistent, one scratch slot each)
 constexpr int64_t SEL_BRACKET_MIN_RP = 32768;  // shorter columns: whole-column radix selection
 
 // LDS of the radix selection (and of the column reductions).
@@ -121,10 +121,10 @@ struct ColSelLds : SelLds {
 };
 
 // Scratch slot per column workgroup: the values inside a bracket (expected
-// about 2 * 5 / sqrt(2048) = 22 % of the column).
+// about 2 * 5 / sqrt(1024) = 31 % of the column).
 __host__ __device__ inline int64_t sel_cap(int64_t R) {
   const int64_t Rp = pad_ranks(R);
-  int64_t c = ((Rp * 35 / 100) + 63) & ~(int64_t)63;
+  int64_t c = ((Rp * 45 / 100) + 63) & ~(int64_t)63;
   if (c < 4096) c = 4096;
   return c;
 }
@@ -314,7 +314,7 @@ __device__ void radix_select(Visit &&visit, int64_t k, bool want_next, int bits,
 // f(x) for this thread's share of scr[0..c), eight loads in flight.
 template <class F>
 __device__ __forceinline__ void visit_scratch(const int64_t *__restrict__ scr, int64_t c, F &&f) {
-  constexpr int U = 8;
+  constexpr int U = 4;
   for (int64_t i0 = 0; i0 < c; i0 += (int64_t)CS * U) {
     int64_t v[U];
 #pragma unroll
@@ -449,7 +449,9 @@ __device__ bool bracket_pick(Visit &&vmid, int64_t clo, int64_t ceqa, int64_t cm
 // bracket, MAD bracket); exact selection over the compacted bracket values, or
 // over the whole column when a bracket misses the middle or overflows the
 // scratch.
-__global__ __launch_bounds__(CS) void col_select_bracket(const int64_t *__restrict__ Tt, int64_t R, int IG,
+constexpr int SEL_WGS_PER_CU = 4;  // column workgroups per CU (LDS 20 KB, at most 128 VGPRs each)
+
+__global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void col_select_bracket(const int64_t *__restrict__ Tt, int64_t R, int IG,
                                                  int64_t *__restrict__ scratch, int64_t cap,
                                                  ColSel out) {
   __shared__ ColSelLds L;
@@ -464,18 +466,18 @@ __global__ __launch_bounds__(CS) void col_select_bracket(const int64_t *__restri
         if (x != SENT) f(x);
       });
     };
-    // ---- sample: 512 chunks of 4 consecutive cells (Rp >= 2048) ------------
+    // ---- sample: 2 * CS chunks of 2 consecutive cells (Rp >= 4 * CS) -------
     if (t == 0) {
       L.ns = 0;
       L.cin = 0;
     }
     __syncthreads();
     {
-      const int64_t s0 = (((int64_t)t * Rp) / CS) & ~(int64_t)3;
-      v2ll q[2];
-      q[0] = *reinterpret_cast<const v2ll *>(col + s0);
-      q[1] = *reinterpret_cast<const v2ll *>(col + s0 + 2);
-      const int64_t x4[4] = {q[0].x, q[0].y, q[1].x, q[1].y};
+      const int64_t sa = (((int64_t)(2 * t) * Rp) / (2 * CS)) & ~(int64_t)1;
+      const int64_t sb = (((int64_t)(2 * t + 1) * Rp) / (2 * CS)) & ~(int64_t)1;
+      const v2ll qa = *reinterpret_cast<const v2ll *>(col + sa);
+      const v2ll qb = *reinterpret_cast<const v2ll *>(col + sb);
+      const int64_t x4[4] = {qa.x, qa.y, qb.x, qb.y};
 #pragma unroll
       for (int u = 0; u < 4; u++)
         if (x4[u] != SENT) L.samp[atomicAdd(&L.ns, 1u)] = x4[u];
@@ -1118,7 +1120,7 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
           int dev = 0, cus = 256;
           (void)hipGetDevice(&dev);
           (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-          const int grid = std::min(IG, std::min(SEL_GRID_MAX, 3 * cus));
+          const int grid = std::min(IG, std::min(SEL_GRID_MAX, SEL_WGS_PER_CU * cus));
           hipLaunchKernelGGL(col_select_bracket, dim3(grid), dim3(CS), 0, s, w.Tt, a.R, IG, w.scr,
                              sel_cap(a.R), w.cs);
         }
