@@ -274,6 +274,30 @@ ta_status ta_plan_info(ta_plan p, int32_t *threads, int32_t *events_per_thread,
                        int32_t *nontemporal, int32_t *wgs_per_cu, float *tuned_ms);
 ta_status ta_plan_destroy(ta_plan p);
 
+/* Mixed batch: many trace-analysis requests over one call-path tree and one
+ * region list (the handle's), each with its own ranks, events and iteration
+ * count, reduced by ONE persistent fused pass (a task per rank of every
+ * request, longest first) followed by each request's exact FULL robust outlier
+ * scan (modified z, Sec. VI-B stand-in as for ta_outliers), all captured in one
+ * graph.  Per request: traces and a host copy of its offsets; seg.tensor and
+ * seg.iters_found are required, the other seg outputs may be NULL; rank_score
+ * and rank_flag (both or neither) ask for the outlier scan of that request
+ * (n_flagged may be NULL).  Device data errors of any request set the handle's
+ * sticky error word.  Launch, query and destroy with ta_plan_launch /
+ * ta_plan_info / ta_plan_destroy; autotune as for ta_plan_create. */
+typedef struct {
+  ta_traces traces;
+  const int64_t *offsets_host;
+  int32_t n_iters;
+  ta_seg_out seg;
+  double *rank_score;
+  uint8_t *rank_flag;
+  int64_t *n_flagged;
+} ta_request;
+
+ta_status ta_batch_create(ta_handle h, int32_t n_requests, const ta_request *requests, double tau,
+                          int32_t autotune, ta_plan *out, void *stream);
+
 /* ---- Learned pre-screen -------------------------------------------------
  * Not part of the paper's method: a small autoencoder over per-rank iteration
  * profiles, 64 -> 128 -> 32 -> 128 -> 64 (ReLU on the hidden layers, linear

@@ -466,21 +466,22 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void col_select_bracket(const i
         if (x != SENT) f(x);
       });
     };
-    // ---- sample: 2 * CS chunks of 2 consecutive cells (Rp >= 4 * CS) -------
+    // ---- sample: MS / 2 chunks of 2 consecutive cells (Rp >= 2 * MS) -------
     if (t == 0) {
       L.ns = 0;
       L.cin = 0;
     }
     __syncthreads();
     {
-      const int64_t sa = (((int64_t)(2 * t) * Rp) / (2 * CS)) & ~(int64_t)1;
-      const int64_t sb = (((int64_t)(2 * t + 1) * Rp) / (2 * CS)) & ~(int64_t)1;
-      const v2ll qa = *reinterpret_cast<const v2ll *>(col + sa);
-      const v2ll qb = *reinterpret_cast<const v2ll *>(col + sb);
-      const int64_t x4[4] = {qa.x, qa.y, qb.x, qb.y};
+      constexpr int NCH = MS / 2;  // chunks of 2 consecutive cells, NCH / CS per thread
 #pragma unroll
-      for (int u = 0; u < 4; u++)
-        if (x4[u] != SENT) L.samp[atomicAdd(&L.ns, 1u)] = x4[u];
+      for (int u = 0; u < NCH / CS; u++) {
+        const int64_t j = (int64_t)t * (NCH / CS) + u;
+        const int64_t s0 = ((j * Rp) / NCH) & ~(int64_t)1;
+        const v2ll q = *reinterpret_cast<const v2ll *>(col + s0);
+        if (q.x != SENT) L.samp[atomicAdd(&L.ns, 1u)] = q.x;
+        if (q.y != SENT) L.samp[atomicAdd(&L.ns, 1u)] = q.y;
+      }
     }
     __syncthreads();
     const int m = (int)L.ns;

@@ -136,12 +136,12 @@ __device__ inline void acc_sq(uint64_t &lo, uint64_t &hi, int64_t v) {
 
 // NT threads per workgroup (256 or 512); a 512-thread workgroup is limited to
 // 128 VGPRs so that two fit on a CU beside each other (the LDS allows two).
-template <bool ATTR, bool SEG, int EPT, bool NTMP, int NT>
+template <bool ATTR, bool SEG, int EPT, bool NTMP, int NT, bool MULTI>
 __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void seg_kernel(SegArgs a) {
   constexpr int NWAVE = NT / 64;
   constexpr int TILE = NT * EPT;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int N = a.N, G = a.G, I = a.I, W = a.W;
+  const int N = a.N, G = a.G, W = a.W;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
   // ---- LDS layout ------------------------------------------------------
@@ -174,38 +174,73 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void seg_kernel(SegArgs a) {
   const int rsub = SEG ? tid / G : 0;
   const bool fl_active = SEG && tid < rows_pp * G;
 
-  // A rank task: rank id and event range [b, e) (an invalid range is recorded
-  // and treated as empty).
-  auto rank_at = [&](int64_t rr, int64_t &r, int64_t &b, int64_t &e, uint32_t &errb) {
-    r = a.order ? (int64_t)a.order[rr] : rr;
-    b = a.off[r];
-    e = a.off[r + 1];
-    errb = 0;
-    if (b < 0 || e < b || e > a.E) {
-      errb = ERRBIT_OFFSETS;
-      b = e = 0;
+  // A rank task: the rank id, its event range [b, e) (an invalid range is
+  // recorded and treated as empty) and its request's traces.  Outputs are read
+  // from the request (mixed batch) or the arguments where they are written.
+  struct Task {
+    int64_t r, b, e;
+    uint32_t err;
+    const int64_t *ts;
+    const int32_t *ctx;
+    int64_t E;
+    int I;
+    const SegReq *q;  // MULTI only
+  };
+  auto task_at = [&](int64_t rr) {
+    Task k;
+    const int64_t *off;
+    if constexpr (MULTI) {
+      const int64_t tv = a.tasks[rr];
+      k.q = a.reqs + (tv >> 32);
+      k.r = tv & 0xffffffffll;
+      off = k.q->off;
+      k.ts = k.q->ts;
+      k.ctx = k.q->ctx;
+      k.E = k.q->E;
+      k.I = k.q->I;
+    } else {
+      k.q = nullptr;
+      k.r = a.order ? (int64_t)a.order[rr] : rr;
+      off = a.off;
+      k.ts = a.ts;
+      k.ctx = a.ctx;
+      k.E = a.E;
+      k.I = a.I;
     }
+    k.b = off[k.r];
+    k.e = off[k.r + 1];
+    k.err = 0;
+    if (k.b < 0 || k.e < k.b || k.e > k.E) {
+      k.err = ERRBIT_OFFSETS;
+      k.b = k.e = 0;
+    }
+    return k;
+  };
+#define TA_OUT(f) (MULTI ? T.q->f : a.f)
+
+  // First tile of task rr into `dst` (the task's context is only needed to
+  // issue the loads).
+  auto prefetch_first = [&](int64_t rr, Tile<EPT> &dst) {
+    const Task n = task_at(rr);
+    const int64_t t0n = n.b & ~(int64_t)(TILE - 1);
+    if (t0n < n.e) load_tile<EPT, NTMP>(dst, n.ts, n.ctx, n.E, t0n + (int64_t)tid * EPT, n.b, n.e, lane);
   };
 
   int parity = 0;
   Tile<EPT> cur, nxt_tile;
-  int64_t r_n = 0, b_n = 0, e_n = 0;
-  uint32_t err_n = 0;
-  if ((int64_t)blockIdx.x < a.R) {
-    rank_at(blockIdx.x, r_n, b_n, e_n, err_n);
-    const int64_t t0n = b_n & ~(int64_t)(TILE - 1);
-    if (t0n < e_n) load_tile<EPT, NTMP>(cur, a.ts, a.ctx, a.E, t0n + (int64_t)tid * EPT, b_n, e_n, lane);
-  }
+  if ((int64_t)blockIdx.x < a.R) prefetch_first(blockIdx.x, cur);
   for (int64_t rr = blockIdx.x; rr < a.R; rr += gridDim.x) {
-    const int64_t r = r_n;
-    const int64_t b = b_n, e = e_n;
-    uint32_t errb = err_n;
+    const Task T = task_at(rr);
+    const int64_t r = T.r;
+    const int64_t b = T.b, e = T.e;
+    const int I = T.I;
+    uint32_t errb = T.err;
     int carry = -1;      // iteration index in effect after the processed events
     int flushed = 0;     // tensor rows [0, flushed) are written
     int64_t out_acc = 0; // time outside every region / before the first boundary
     int64_t S = 0;
     uint64_t Qlo = 0, Qhi = 0;
-    int64_t *trow = SEG ? a.tensor + r * (int64_t)I * G : nullptr;
+    int64_t *trow = SEG ? TA_OUT(tensor) + r * (int64_t)I * G : nullptr;
 
     auto flush = [&](int row_lo, int row_hi) {  // rows inclusive, all in the ring
       if (!fl_active) return;
@@ -227,7 +262,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void seg_kernel(SegArgs a) {
       // Issue the next tile's loads now; they complete while this tile is
       // processed (barriers wait only for LDS traffic).
       if (t0 + TILE < e)
-        load_tile<EPT, NTMP>(nxt_tile, a.ts, a.ctx, a.E, c0 + TILE, b, e, lane);
+        load_tile<EPT, NTMP>(nxt_tile, T.ts, T.ctx, T.E, c0 + TILE, b, e, lane);
       const int64_t *tsv = cur.ts;
       const int32_t *cv = cur.cv;
       // Timestamp after my last event (lane + 1's first, or the halo at the
@@ -345,12 +380,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void seg_kernel(SegArgs a) {
     }
 
     // Next rank's first tile: its loads are in flight during this epilogue.
-    if (rr + gridDim.x < a.R) {
-      rank_at(rr + gridDim.x, r_n, b_n, e_n, err_n);
-      const int64_t t0n = b_n & ~(int64_t)(TILE - 1);
-      if (t0n < e_n)
-        load_tile<EPT, NTMP>(cur, a.ts, a.ctx, a.E, t0n + (int64_t)tid * EPT, b_n, e_n, lane);
-    }
+    if (rr + gridDim.x < a.R) prefetch_first(rr + gridDim.x, cur);
 
     // ---- rank epilogue --------------------------------------------------
     if (SEG) {
@@ -384,22 +414,22 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void seg_kernel(SegArgs a) {
           s += redS[idx];
           q += ((unsigned __int128)redQ[2 * idx + 1] << 64) | redQ[2 * idx];
         }
-        if (a.rank_sum) a.rank_sum[r * G + tid] = s;
-        if (a.rank_sumsq) {
-          a.rank_sumsq[2 * (r * G + tid)] = (uint64_t)q;
-          a.rank_sumsq[2 * (r * G + tid) + 1] = (uint64_t)(q >> 64);
+        if (TA_OUT(rank_sum)) TA_OUT(rank_sum)[r * G + tid] = s;
+        if (TA_OUT(rank_sumsq)) {
+          TA_OUT(rank_sumsq)[2 * (r * G + tid)] = (uint64_t)q;
+          TA_OUT(rank_sumsq)[2 * (r * G + tid) + 1] = (uint64_t)(q >> 64);
         }
       }
       if (tid == 0) {
         int64_t s = 0;
         for (int w = 0; w < NWAVE; w++) s += wsum64[w];
-        if (a.outside) a.outside[r] = s;
-        if (a.iters_found) a.iters_found[r] = carry + 1;
+        if (TA_OUT(outside)) TA_OUT(outside)[r] = s;
+        if (TA_OUT(iters_found)) TA_OUT(iters_found)[r] = carry + 1;
       }
       __syncthreads();
       for (int v = tid; v < 3 * NT; v += NT) ring[v] = 0;  // redS + redQ area
     }
-    if (tid == 0 && a.span) a.span[r] = (e > b) ? a.ts[e - 1] - a.ts[b] : 0;
+    if (tid == 0 && TA_OUT(span)) TA_OUT(span)[r] = (e > b) ? T.ts[e - 1] - T.ts[b] : 0;
 
     if (ATTR) {
       __syncthreads();
@@ -424,8 +454,8 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void seg_kernel(SegArgs a) {
       for (int v = tid; v < N; v += NT) {
         const int2 tt = a.tin_tout[v];
         const int64_t pa = hist[tt.x];
-        if (a.excl) st<NTMP>(&a.excl[r * N + v], hist[tt.x + 1] - pa);
-        if (a.incl) st<NTMP>(&a.incl[r * N + v], hist[tt.y] - pa);
+        if (TA_OUT(excl)) st<NTMP>(&TA_OUT(excl)[r * N + v], hist[tt.x + 1] - pa);
+        if (TA_OUT(incl)) st<NTMP>(&TA_OUT(incl)[r * N + v], hist[tt.y] - pa);
       }
       __syncthreads();
       for (int v = tid; v <= N; v += NT) hist[v] = 0;
@@ -433,6 +463,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void seg_kernel(SegArgs a) {
     if (errb) atomicOr(a.err, errb);
     __syncthreads();
   }
+#undef TA_OUT
 }
 
 }  // namespace
@@ -462,16 +493,26 @@ size_t segment_lds_bytes(int N, int G, bool attr, bool seg, int *W, int *log2W) 
 
 namespace {
 
-template <bool A, bool S, int EPT, bool NTMP, int NT>
-hipError_t launch_variant(const SegArgs &a, int grid, size_t lds, hipStream_t s) {
+template <bool A, bool S, int EPT, bool NTMP, int NT, bool MULTI>
+hipError_t launch_one(const SegArgs &a, int grid, size_t lds, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&seg_kernel<A, S, EPT, NTMP, NT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&seg_kernel<A, S, EPT, NTMP, NT, MULTI>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL((seg_kernel<A, S, EPT, NTMP, NT>), dim3(grid), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((seg_kernel<A, S, EPT, NTMP, NT, MULTI>), dim3(grid), dim3(NT), lds, s, a);
   return hipGetLastError();
+}
+
+// Mixed batches use the fused pass only.
+template <bool A, bool S, int EPT, bool NTMP, int NT>
+hipError_t launch_variant(const SegArgs &a, int grid, size_t lds, hipStream_t s) {
+  if (a.reqs) {
+    if constexpr (A && S) return launch_one<A, S, EPT, NTMP, NT, true>(a, grid, lds, s);
+    return hipErrorInvalidValue;
+  }
+  return launch_one<A, S, EPT, NTMP, NT, false>(a, grid, lds, s);
 }
 
 template <bool A, bool S>

@@ -268,6 +268,8 @@ ta_status run_segment(ta_handle h, const ta_traces *t, int32_t n_iters, const ta
 struct ta_plan_s {
   ta_handle h = nullptr;
   int32_t *d_order = nullptr;
+  ta::SegReq *d_reqs = nullptr;  // mixed batch: request descriptors
+  int64_t *d_tasks = nullptr;    // mixed batch: (request << 32) | rank, longest first
   void *ws = nullptr;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -284,6 +286,8 @@ void plan_free(ta_plan p) {
   if (p->graph) hipGraphDestroy(p->graph);
   if (p->cap) hipStreamDestroy(p->cap);
   if (p->d_order) hipFree(p->d_order);
+  if (p->d_reqs) hipFree(p->d_reqs);
+  if (p->d_tasks) hipFree(p->d_tasks);
   if (p->ws) hipFree(p->ws);
   delete p;
 }
@@ -372,6 +376,65 @@ ta_status time_shape(ta_handle h, const SegLaunch &L, const ta::SegShape &sh, in
   hipEventDestroy(e1);
   if (e != hipSuccess) return hipfail(h, e, "autotune launch");
   *ms = t / 2.f;
+  return TA_OK;
+}
+
+// Launch shape of a fused pass: the default, a cached choice (autotune 2) or
+// the fastest candidate measured on this batch (every candidate produces
+// identical outputs).
+ta_status choose_shape(ta_handle h, const SegLaunch &L, int autotune, hipStream_t s,
+                       ta::SegShape *best_out, float *best_ms_out) {
+  const int cus = device_cus(h->device);
+  const int occ = std::max(1, (int)((160 * 1024) / std::max<size_t>(L.lds, 1)));
+  ta::SegShape best = default_shape(L);
+  float best_ms = 0.f;
+  const char *cpath = getenv("TA_AUTOTUNE_CACHE");
+  const std::string key = plan_key(h, L);
+  std::vector<CacheEntry> cache = autotune == 2 ? cache_read(cpath) : std::vector<CacheEntry>{};
+  bool found = false;
+  for (const CacheEntry &c : cache)
+    if (c.key == key) {
+      best.threads = c.threads;
+      best.ept = c.ept;
+      best.nontemporal = c.nt != 0;
+      best.wgs_per_cu = c.wgs;
+      best_ms = (float)c.ms;
+      found = true;
+    }
+  if (autotune && !found) {
+    bool have = false;
+    struct TE {
+      int threads, ept;
+    };
+    std::vector<TE> tes = {{256, 2}, {256, 4}, {256, 8}, {256, 16}};
+    if (L.attr && L.seg) {
+      tes.push_back({512, 2});
+      tes.push_back({512, 4});
+    }
+    for (const TE &te : tes)
+      for (int nt : {0, 1})
+        for (int wgs : {0, occ}) {
+          ta::SegShape sh;
+          sh.threads = te.threads;
+          sh.ept = te.ept;
+          sh.nontemporal = nt != 0;
+          sh.wgs_per_cu = wgs;
+          float ms = 0.f;
+          ta_status st = time_shape(h, L, sh, cus, s, &ms);
+          if (st) return st;
+          if (!have || ms < best_ms) {
+            best = sh;
+            best_ms = ms;
+            have = true;
+          }
+        }
+    if (autotune == 2 && cpath) {
+      cache.push_back({key, best.ept, best.nontemporal ? 1 : 0, best.wgs_per_cu, best_ms, best.threads});
+      cache_write(cpath, cache);
+    }
+  }
+  *best_out = best;
+  *best_ms_out = best_ms;
   return TA_OK;
 }
 
@@ -700,56 +763,12 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
 
   // Launch shape: default, cached, or measured on this batch.
   const int cus = device_cus(h->device);
-  const int occ = std::max(1, (int)((160 * 1024) / std::max<size_t>(L.lds, 1)));
-  ta::SegShape best = default_shape(L);
+  ta::SegShape best;
   float best_ms = 0.f;
-  const char *cpath = getenv("TA_AUTOTUNE_CACHE");
-  const std::string key = plan_key(h, L);
-  std::vector<CacheEntry> cache = d->autotune == 2 ? cache_read(cpath) : std::vector<CacheEntry>{};
-  bool found = false;
-  for (const CacheEntry &c : cache)
-    if (c.key == key) {
-      best.threads = c.threads;
-      best.ept = c.ept;
-      best.nontemporal = c.nt != 0;
-      best.wgs_per_cu = c.wgs;
-      best_ms = (float)c.ms;
-      found = true;
-    }
-  if (d->autotune && !found) {
-    bool have = false;
-    struct TE {
-      int threads, ept;
-    };
-    std::vector<TE> tes = {{256, 2}, {256, 4}, {256, 8}, {256, 16}};
-    if (L.attr && L.seg) {
-      tes.push_back({512, 2});
-      tes.push_back({512, 4});
-    }
-    for (const TE &te : tes)
-      for (int nt : {0, 1})
-        for (int wgs : {0, occ}) {
-          ta::SegShape sh;
-          sh.threads = te.threads;
-          sh.ept = te.ept;
-          sh.nontemporal = nt != 0;
-          sh.wgs_per_cu = wgs;
-          float ms = 0.f;
-          st = time_shape(h, L, sh, cus, s, &ms);
-          if (st) {
-            plan_free(p);
-            return st;
-          }
-          if (!have || ms < best_ms) {
-            best = sh;
-            best_ms = ms;
-            have = true;
-          }
-        }
-    if (d->autotune == 2 && cpath) {
-      cache.push_back({key, best.ept, best.nontemporal ? 1 : 0, best.wgs_per_cu, best_ms, best.threads});
-      cache_write(cpath, cache);
-    }
+  st = choose_shape(h, L, d->autotune, s, &best, &best_ms);
+  if (st) {
+    plan_free(p);
+    return st;
   }
   p->shape = best;
   p->tuned_ms = best_ms;
@@ -800,6 +819,156 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
   if (le != hipSuccess || e != hipSuccess) {
     plan_free(p);
     return hipfail(h, le != hipSuccess ? le : e, "plan capture");
+  }
+  e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return hipfail(h, e, "graph instantiate");
+  }
+  *out = p;
+  return TA_OK;
+}
+
+ta_status ta_batch_create(ta_handle h, int32_t n_requests, const ta_request *requests, double tau,
+                          int32_t autotune, ta_plan *out, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!out || !requests || n_requests < 1) return fail(h, TA_ERR_INVALID_ARG, "no requests");
+  *out = nullptr;
+  if (n_requests > (1 << 20)) return fail(h, TA_ERR_SIZE_OVERFLOW, "too many requests");
+  if (!(tau >= 0.0)) return fail(h, TA_ERR_INVALID_ARG, "tau must be >= 0");
+  if (autotune < 0 || autotune > 2) return fail(h, TA_ERR_INVALID_ARG, "autotune must be 0, 1 or 2");
+  if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  if (h->G <= 0) return fail(h, TA_ERR_STATE, "ta_set_regions has not been called");
+  if (h->N > ta::MAX_NODES_ATTR)
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "attribution supports at most 8192 CCT nodes");
+  const int G = h->G;
+  std::vector<ta::SegReq> qs(n_requests);
+  std::vector<int64_t> tasks, lens;
+  int64_t E_total = 0;
+  size_t ws = 0;
+  for (int32_t q = 0; q < n_requests; q++) {
+    const ta_request &rq = requests[q];
+    ta_status st = check_traces(h, &rq.traces);
+    if (st) return st;
+    const int64_t R = rq.traces.n_ranks;
+    if (R > 0 && !rq.offsets_host) return fail(h, TA_ERR_INVALID_ARG, "offsets_host NULL");
+    if (rq.n_iters < 1) return fail(h, TA_ERR_INVALID_ARG, "n_iters must be >= 1");
+    if ((double)R * rq.n_iters * G > 4e18 || (double)rq.n_iters * G > 4194240.0)
+      return fail(h, TA_ERR_SIZE_OVERFLOW, "tensor too large");
+    if (!rq.seg.tensor || !rq.seg.iters_found)
+      return fail(h, TA_ERR_INVALID_ARG, "each request needs tensor and iters_found");
+    const ta_seg_out &o = rq.seg;
+    const void *ptrs[] = {o.tensor, o.iters_found, o.outside, o.span, o.rank_sum, o.rank_sumsq,
+                          o.excl, o.incl, rq.rank_score, rq.rank_flag, rq.n_flagged};
+    for (const void *ptr : ptrs)
+      if (ptr && !aligned16(ptr)) return fail(h, TA_ERR_INVALID_ARG, "output not 16-byte aligned");
+    if ((rq.rank_score == nullptr) != (rq.rank_flag == nullptr))
+      return fail(h, TA_ERR_INVALID_ARG, "rank_score and rank_flag go together");
+    for (int64_t r = 0; r < R; r++)
+      if (rq.offsets_host[r + 1] < rq.offsets_host[r])
+        return fail(h, TA_ERR_INVALID_ARG, "offsets_host decreasing");
+    qs[q] = ta::SegReq{rq.traces.offsets, rq.traces.ts, rq.traces.ctx, rq.traces.n_events,
+                       rq.n_iters, o.tensor, o.iters_found, o.outside, o.span, o.rank_sum,
+                       o.rank_sumsq, o.excl, o.incl};
+    for (int64_t r = 0; r < R; r++) {
+      tasks.push_back(((int64_t)q << 32) | r);
+      lens.push_back(rq.offsets_host[r + 1] - rq.offsets_host[r]);
+    }
+    E_total += rq.traces.n_events;
+    if (rq.rank_score)
+      ws = std::max(ws, ta::outliers_ws_bytes(R, rq.n_iters, G, TA_SCAN_FULL, TA_SCORE_MAD));
+  }
+  // Longest ranks of every request first; ties in request, then rank order.
+  std::vector<int64_t> idx(tasks.size());
+  for (size_t k = 0; k < idx.size(); k++) idx[k] = (int64_t)k;
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return lens[x] > lens[y]; });
+  std::vector<int64_t> sorted(tasks.size());
+  for (size_t k = 0; k < idx.size(); k++) sorted[k] = tasks[idx[k]];
+
+  DeviceGuard dg(h->device);
+  ta_plan p = new (std::nothrow) ta_plan_s();
+  if (!p) return TA_ERR_OOM;
+  p->h = h;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMalloc(&p->d_reqs, qs.size() * sizeof(ta::SegReq));
+  if (e == hipSuccess && !sorted.empty()) e = hipMalloc(&p->d_tasks, sorted.size() * sizeof(int64_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_reqs, qs.data(), qs.size() * sizeof(ta::SegReq), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !sorted.empty())
+    e = hipMemcpy(p->d_tasks, sorted.data(), sorted.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && ws) e = hipMalloc(&p->ws, ws);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return hipfail(h, e, "batch upload");
+  }
+  SegLaunch L;
+  int W = 2, lw = 1;
+  L.lds = ta::segment_lds_bytes(h->N, G, true, true, &W, &lw);
+  if (L.lds > 160 * 1024) {
+    plan_free(p);
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "call-path tables exceed LDS");
+  }
+  ta::SegArgs &a = L.a;
+  a.R = (int64_t)sorted.size();
+  a.E = E_total;
+  a.info = h->d_info;
+  a.tin_tout = h->d_tin_tout;
+  a.N = h->N;
+  a.G = G;
+  a.I = -n_requests;  // distinguishes mixed batches in the autotune cache key
+  a.W = W;
+  a.log2W = lw;
+  a.err = h->d_err;
+  a.reqs = p->d_reqs;
+  a.tasks = p->d_tasks;
+  L.attr = L.seg = true;
+
+  ta::SegShape best = default_shape(L);
+  float best_ms = 0.f;
+  if (a.R > 0) {
+    ta_status st = choose_shape(h, L, autotune, s, &best, &best_ms);
+    if (st) {
+      plan_free(p);
+      return st;
+    }
+  }
+  p->shape = best;
+  p->tuned_ms = best_ms;
+  const int cus = device_cus(h->device);
+  const int grid = grid_for(L, best, cus);
+  e = hipSuccess;
+  if (a.R > 0) e = ta::launch_segment(a, true, true, best, grid, L.lds, s);  // kernel attributes
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return hipfail(h, e, "batch capture start");
+  }
+  hipError_t le = hipSuccess;
+  if (a.R > 0) le = ta::launch_segment(a, true, true, best, grid, L.lds, p->cap);
+  for (int32_t q = 0; q < n_requests && le == hipSuccess; q++) {
+    const ta_request &rq = requests[q];
+    if (!rq.rank_score) continue;
+    ta::OutArgs oa{};
+    oa.T = rq.seg.tensor;
+    oa.R = rq.traces.n_ranks;
+    oa.I = rq.n_iters;
+    oa.G = G;
+    oa.it = rq.seg.iters_found;
+    oa.mode = TA_SCAN_FULL;
+    oa.kind = TA_SCORE_MAD;
+    oa.tau = tau;
+    oa.rank_score = rq.rank_score;
+    oa.rank_flag = rq.rank_flag;
+    oa.n_flagged = rq.n_flagged;
+    oa.region_score = nullptr;
+    le = ta::launch_outliers(oa, p->ws, ws, p->cap);
+  }
+  e = hipStreamEndCapture(p->cap, &p->graph);
+  if (le != hipSuccess || e != hipSuccess) {
+    plan_free(p);
+    return hipfail(h, le != hipSuccess ? le : e, "batch capture");
   }
   e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {

@@ -33,6 +33,23 @@ constexpr int MAX_NODES_ATTR = 8192;      // LDS histogram limit for attribution
 constexpr int MAX_NODES = 1 << 22;        // preorder index field width
 constexpr int MAX_REGIONS = 256;
 
+// One request of a mixed batch: its traces, iteration count and outputs.
+struct SegReq {
+  const int64_t *off;
+  const int64_t *ts;
+  const int32_t *ctx;
+  int64_t E;
+  int32_t I;
+  int64_t *tensor;
+  int32_t *iters_found;
+  int64_t *outside;
+  int64_t *span;
+  int64_t *rank_sum;
+  uint64_t *rank_sumsq;
+  int64_t *excl;
+  int64_t *incl;
+};
+
 struct SegArgs {
   const int64_t *off;
   const int64_t *ts;
@@ -52,6 +69,10 @@ struct SegArgs {
   int64_t *excl;
   int64_t *incl;
   uint32_t *err;
+  // Mixed batch (reqs != NULL): R tasks; tasks[k] = (request << 32) | rank, and the
+  // per-request fields come from reqs[request] instead of the ones above.
+  const SegReq *reqs;
+  const int64_t *tasks;
 };
 
 // Launch shape of the fused pass (chosen by the batch autotuner).

@@ -46,6 +46,12 @@ class ImbOut(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in IMB_FIELDS]
 
 
+class Request(C.Structure):
+    _fields_ = [("traces", Traces), ("offsets_host", C.c_void_p), ("n_iters", C.c_int32),
+                ("seg", SegOut), ("rank_score", C.c_void_p), ("rank_flag", C.c_void_p),
+                ("n_flagged", C.c_void_p)]
+
+
 class BatchDesc(C.Structure):
     _fields_ = [("n_iters", C.c_int32), ("seg", SegOut), ("with_imbalance", C.c_int32),
                 ("imb", ImbOut), ("ddof", C.c_int32), ("t_app_ns", C.c_double),
@@ -79,6 +85,7 @@ def _load():
         "ta_plan_create": [P, P, P, P, P, P],
         "ta_plan_launch": [P, P],
         "ta_plan_info": [P, P, P, P, P, P],
+        "ta_batch_create": [P, i32, P, f64, i32, P, P],
         "ta_plan_destroy": [P],
         "ta_ae_init": [P, C.c_uint64, P],
         "ta_ae_fit_norm": [P, P, i64, i32, i32, P, i32, P],
@@ -381,8 +388,85 @@ class Handle:
         return Plan(self, tr, n_iters, offsets_host, imbalance, outliers, autotune, ddof, t_app,
                     mode, kind, tau, region)
 
+    def mixed_batch(self, requests, outliers=True, attribution=False, tau=3.5, autotune=2):
+        """Create a mixed batch (see MixedBatch)."""
+        return MixedBatch(self, requests, outliers, attribution, tau, autotune)
 
-class Plan:
+
+class _PlanBase:
+    """A captured graph owned by the library (ta_plan)."""
+
+    def launch(self):
+        self.h._check(_lib.ta_plan_launch(self.p, _stream(self.h.device)))
+
+    def info(self):
+        th, ept, nt, wgs, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
+        self.h._check(_lib.ta_plan_info(self.p, C.byref(th), C.byref(ept), C.byref(nt),
+                                        C.byref(wgs), C.byref(ms)))
+        return {"threads": th.value, "events_per_thread": ept.value, "nontemporal": nt.value,
+                "wgs_per_cu": wgs.value, "tuned_ms": ms.value}
+
+    def close(self):
+        if getattr(self, "p", None) is not None:
+            _lib.ta_plan_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MixedBatch(_PlanBase):
+    """Many requests (traces of their own, one tree and region list) in one
+    persistent fused pass plus each request's exact outlier scan, one graph.
+    `requests` = [(DeviceTraces, offsets_host, n_iters), ...]; outputs per
+    request in .outs[q] (tensor, iters_found, outside, span, rank_sum,
+    rank_sumsq, [excl, incl], [rank_score, rank_flag, n_flagged])."""
+
+    def __init__(self, h: Handle, requests, outliers=True, attribution=False, tau=3.5, autotune=2):
+        self.h = h
+        self.requests = requests
+        G, N = h.n_regions, h.n_nodes
+        e = h._empty
+        self.outs = []
+        arr = (Request * len(requests))()
+        self._hold = []
+        for q, (tr, off_host, n_iters) in enumerate(requests):
+            R, I = tr.n_ranks, int(n_iters)
+            o = {"tensor": e((R, I, G), torch.int64), "iters_found": e((R,), torch.int32),
+                 "outside": e((R,), torch.int64), "span": e((R,), torch.int64),
+                 "rank_sum": e((R, G), torch.int64), "rank_sumsq": e((R, G, 2), torch.int64)}
+            if attribution:
+                o["excl"] = e((R, N), torch.int64)
+                o["incl"] = e((R, N), torch.int64)
+            if outliers:
+                o["rank_score"] = e((R,), torch.float64)
+                o["rank_flag"] = e((R,), torch.uint8)
+                o["n_flagged"] = e((1,), torch.int64)
+            off = np.ascontiguousarray(off_host, dtype=np.int64)
+            self._hold.append(off)
+            rq = arr[q]
+            rq.traces = tr.struct()
+            rq.offsets_host = off.ctypes.data
+            rq.n_iters = I
+            rq.seg = SegOut(*[_ptr(o[k]).value if k in o else None
+                              for k in ("tensor", "iters_found", "outside", "span", "rank_sum",
+                                        "rank_sumsq", "excl", "incl")])
+            rq.rank_score = _ptr(o["rank_score"]).value if outliers else None
+            rq.rank_flag = _ptr(o["rank_flag"]).value if outliers else None
+            rq.n_flagged = _ptr(o["n_flagged"]).value if outliers else None
+            self.outs.append(o)
+        self._arr = arr
+        p = C.c_void_p()
+        h._check(_lib.ta_batch_create(h.h, len(requests), arr, float(tau), int(autotune),
+                                      C.byref(p), _stream(h.device)))
+        self.p = p
+
+
+
+class Plan(_PlanBase):
     def __init__(self, h: Handle, tr: DeviceTraces, n_iters, offsets_host, imbalance, outliers,
                  autotune, ddof, t_app, mode, kind, tau, region):
         self.h = h
@@ -430,24 +514,3 @@ class Plan:
         h._check(_lib.ta_plan_create(h.h, C.byref(t), off.ctypes.data_as(C.c_void_p), C.byref(d),
                                      C.byref(p), _stream(h.device)))
         self.p = p
-
-    def launch(self):
-        self.h._check(_lib.ta_plan_launch(self.p, _stream(self.h.device)))
-
-    def info(self):
-        th, ept, nt, wgs, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
-        self.h._check(_lib.ta_plan_info(self.p, C.byref(th), C.byref(ept), C.byref(nt),
-                                        C.byref(wgs), C.byref(ms)))
-        return {"threads": th.value, "events_per_thread": ept.value, "nontemporal": nt.value,
-                "wgs_per_cu": wgs.value, "tuned_ms": ms.value}
-
-    def close(self):
-        if getattr(self, "p", None) is not None:
-            _lib.ta_plan_destroy(self.p)
-            self.p = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
