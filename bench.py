@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--no-prescreen", action="store_true",
                     help="skip training and judging the learned pre-screen")
     ap.add_argument("--prescreen-epochs", type=int, default=20)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-size batch of 256 requests (run in memory-bounded waves)")
+    ap.add_argument("--mixed-requests", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
@@ -185,6 +188,11 @@ def main():
     pre = None
     if not args.no_prescreen:
         pre = prescreen_summary(h, args.prescreen_epochs)
+    h.close()
+    torch.cuda.empty_cache()
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_batch_summary(args.mixed_requests, args.seed)
 
     value = E / (ms_step / 1e3)
     line = {
@@ -217,9 +225,99 @@ def main():
                      "kernel_source_sha256_12": src_hash},
         "cpu_baseline": cpu,
         "prescreen": pre,
+        "mixed_batch": mixed,
     }
     print(json.dumps(line))
+
+
+def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9):
+    """Mixed-size batch: n_req requests with rank counts log-uniform in
+    1,000..100,000 and 100..500 iterations each, lengths lognormal around 40
+    events per iteration (2..400 per iteration), one application (5,000-node
+    tree, 64 regions), 2 % injected slow ranks.  The whole set does not fit in
+    HBM, so requests run in waves of about `wave_bytes` of traces and tensors:
+    each wave is generated on the GPU (not timed), then reduced by one mixed
+    batch graph (persistent fused pass over every rank of the wave + each
+    request's exact FULL outlier scan), timed with HIP events over 2 launches;
+    rack/chassis aggregation of each request's scores is timed after it."""
+    import torch
+
+    from paper_2605_03561_amd import gpu_synth, synth, ta
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    rng = np.random.default_rng([seed, 5])
+    Rq = np.round(np.exp(rng.uniform(np.log(1e3), np.log(1e5), n_req))).astype(np.int64)
+    Iq = rng.integers(100, 501, n_req)
+    est = Rq * Iq * (66 * 12 + 64 * 8)          # mean events x 12 B + tensor
+    waves, cur, acc = [], [], 0.0
+    for q in range(n_req):
+        if cur and acc + est[q] > wave_bytes:
+            waves.append(cur)
+            cur, acc = [], 0.0
+        cur.append(q)
+        acc += est[q]
+    if cur:
+        waves.append(cur)
+    h = ta.Handle(0)
+    app = dict(n_nodes=5_000, depth_max=12, n_regions=64, app_seed=seed + 77)
+    stream = torch.cuda.current_stream()
+    tot_ms = topo_ms = 0.0
+    tot_E = tot_R = flagged = 0
+    shape = None
+    for wv, qs in enumerate(waves):
+        reqs, keep = [], []
+        for q in qs:
+            I = int(Iq[q])
+            w = gpu_synth.timeline_on_gpu(seed=seed * 1000 + q, n_ranks=int(Rq[q]), n_iters=I,
+                                          median_len=40 * I, min_len=2 * I, max_len=400 * I,
+                                          inject_frac=0.02, **app)
+            if not keep:
+                h.set_tree(w.parent)
+                h.set_regions(w.marker, w.regions)
+            reqs.append((ta.DeviceTraces(w.offsets, w.ts, w.ctx), w.offsets_host, I))
+            keep.append(w)
+            tot_E += w.n_events
+            tot_R += int(Rq[q])
+        mb = h.mixed_batch(reqs, outliers=True, attribution=False, autotune=0)
+        shape = mb.info()
+        mb.launch()
+        h.sync_status()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        for _ in range(2):
+            mb.launch()
+        ev_g = torch.cuda.Event(enable_timing=True)
+        ev_g.record(stream)
+        d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        topo_in = [tuple(d(a) for a in synth.topology(seed * 1000 + q, tr.n_ranks))
+                   for q, (tr, _, _) in zip(qs, reqs)]
+        ev[1].record(stream)
+        for j, (rank_node, node_rack, node_chassis) in enumerate(topo_in):
+            o = mb.outs[j]
+            h.topology(o["rank_score"], o["rank_flag"], rank_node, node_rack, node_chassis, 22, 176)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        h.sync_status()
+        ms = ev[0].elapsed_time(ev_g) / 2
+        tot_ms += ms
+        topo_ms += ev[1].elapsed_time(ev[2])
+        flagged += sum(int(o["n_flagged"][0]) for o in mb.outs)
+        log(f"[mixed] wave {wv + 1}/{len(waves)}: {len(qs)} requests, "
+            f"{sum(t.n_ranks for t, _, _ in reqs)} ranks, {sum(w.n_events for w in keep)} events, "
+            f"{ms:.1f} ms")
+        mb.close()
+        del mb, reqs, keep, topo_in
+        w = None
+        torch.cuda.empty_cache()
     h.close()
+    return {"workload": f"{n_req} requests, rank counts log-uniform 1,000..100,000 (sum {tot_R}), "
+                        f"100..500 iterations, 5,000-node tree, 64 regions, lognormal lengths "
+                        f"around 40 events per iteration, 2% injected slow ranks",
+            "waves": len(waves), "n_ranks": tot_R, "n_events": int(tot_E),
+            "graph_ms": tot_ms, "topology_ms": topo_ms,
+            "events_per_s": tot_E / ((tot_ms + topo_ms) / 1e3), "n_flagged": flagged,
+            "shape": shape, "timed": "per wave: one graph (fused pass over every rank of the wave + "
+                                      "each request's exact FULL outlier scan), then rack/chassis "
+                                      "aggregation of each request; waves summed"}
 
 
 def copy_calibration(mib: int):
