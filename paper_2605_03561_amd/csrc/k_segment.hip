@@ -218,19 +218,21 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void seg_kernel(SegArgs a) {
   };
 #define TA_OUT(f) (MULTI ? T.q->f : a.f)
 
-  // First tile of task rr into `dst` (the task's context is only needed to
-  // issue the loads).
-  auto prefetch_first = [&](int64_t rr, Tile<EPT> &dst) {
-    const Task n = task_at(rr);
+  // First tile of task n into `dst`.
+  auto prefetch_first = [&](const Task &n, Tile<EPT> &dst) {
     const int64_t t0n = n.b & ~(int64_t)(TILE - 1);
     if (t0n < n.e) load_tile<EPT, NTMP>(dst, n.ts, n.ctx, n.E, t0n + (int64_t)tid * EPT, n.b, n.e, lane);
   };
 
   int parity = 0;
   Tile<EPT> cur, nxt_tile;
-  if ((int64_t)blockIdx.x < a.R) prefetch_first(blockIdx.x, cur);
+  Task nt{};
+  if ((int64_t)blockIdx.x < a.R) {
+    nt = task_at(blockIdx.x);
+    prefetch_first(nt, cur);
+  }
   for (int64_t rr = blockIdx.x; rr < a.R; rr += gridDim.x) {
-    const Task T = task_at(rr);
+    const Task T = nt;
     const int64_t r = T.r;
     const int64_t b = T.b, e = T.e;
     const int I = T.I;
@@ -380,7 +382,10 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void seg_kernel(SegArgs a) {
     }
 
     // Next rank's first tile: its loads are in flight during this epilogue.
-    if (rr + gridDim.x < a.R) prefetch_first(rr + gridDim.x, cur);
+    if (rr + gridDim.x < a.R) {
+      nt = task_at(rr + gridDim.x);
+      prefetch_first(nt, cur);
+    }
 
     // ---- rank epilogue --------------------------------------------------
     if (SEG) {
