@@ -45,6 +45,12 @@ def lib():
         _lib.tao_imbalance.argtypes = [P, i64, i32, i32, P, i32, f64, P] + [P] * 14
         _lib.tao_outliers.argtypes = [P, i64, i32, i32, P, i32, i32, f64, P, P, P, P]
         _lib.tao_topology.argtypes = [P, P, i64, P, P, P, i32, i32, i32] + [P] * 6
+        _lib.tao_summary.argtypes = [i64, i32, P, P, P, P]
+        _lib.tao_prune.argtypes = [i32, P, P, f64, P, P]
+        _lib.tao_pruned.argtypes = [i64, i32, P, P, i32, P, P, P]
+        _lib.tao_tensor_inclusive.argtypes = [P, i64, i32, i32, i32, P, P, P]
+        for f in ("tao_summary", "tao_prune", "tao_pruned", "tao_tensor_inclusive"):
+            getattr(_lib, f).restype = C.c_int
         for f in ("tao_check_tree", "tao_attribute", "tao_segment", "tao_imbalance",
                   "tao_outliers", "tao_topology"):
             getattr(_lib, f).restype = C.c_int
@@ -142,3 +148,40 @@ def topology(rank_score, rank_flag, rank_node, node_rack, node_chassis, n_racks,
                             *[_p(o[k]) for k in ("flagged_rack", "max_rack", "mean_rack",
                                                  "flagged_chassis", "max_chassis", "mean_chassis")])
     return st, o
+
+
+def summary(excl, incl):
+    """-> (status, sum_excl[N], sum_incl[N]) over ranks"""
+    excl, incl = _arr(excl, np.int64), _arr(incl, np.int64)
+    R, N = excl.shape
+    se, si = np.zeros(N, np.int64), np.zeros(N, np.int64)
+    st = lib().tao_summary(R, N, _p(excl), _p(incl), _p(se), _p(si))
+    return st, se, si
+
+
+def prune(sum_excl, sum_incl, fraction):
+    """-> (status, kept node ids ascending)"""
+    se, si = _arr(sum_excl, np.int64), _arr(sum_incl, np.int64)
+    kept = np.zeros(len(se), np.int32)
+    n = C.c_int32(0)
+    st = lib().tao_prune(len(se), _p(se), _p(si), float(fraction), _p(kept), C.byref(n))
+    return st, kept[:n.value].copy()
+
+
+def pruned(excl, parent, kept):
+    """-> (status, p_excl[R,K], p_incl[R,K])"""
+    excl, parent, kept = _arr(excl, np.int64), _arr(parent, np.int32), _arr(kept, np.int32)
+    R, N = excl.shape
+    K = len(kept)
+    pe, pi = np.zeros((R, K), np.int64), np.zeros((R, K), np.int64)
+    st = lib().tao_pruned(R, N, _p(parent), _p(excl), K, _p(kept), _p(pe), _p(pi))
+    return st, pe, pi
+
+
+def tensor_inclusive(T, parent, regions):
+    """-> (status, inclusive tensor[R,I,G]) for nested regions"""
+    T, parent, regions = _arr(T, np.int64), _arr(parent, np.int32), _arr(regions, np.int32)
+    R, I, G = T.shape
+    out = np.zeros_like(T)
+    st = lib().tao_tensor_inclusive(_p(T), R, I, G, len(parent), _p(parent), _p(regions), _p(out))
+    return st, out

@@ -629,3 +629,112 @@ int tao_topology(const double *rank_score, const uint8_t *rank_flag, int64_t R,
   }
   return TAO_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Pruning (Sec. III: pruning strategies are evaluated once on the summary    */
+/* profile -- the aggregate of all parallel profiles -- and propagated to     */
+/* every profile; Sec. VI: negligible code regions, less than 1 % of the      */
+/* total runtime, are removed).                                               */
+/* ------------------------------------------------------------------------- */
+
+/* Summary profile: sums over ranks of excl[R][N] and incl[R][N] (either input
+ * may be NULL, then its output is left alone). */
+int tao_summary(int64_t R, int32_t N, const int64_t *excl, const int64_t *incl,
+                int64_t *sum_excl, int64_t *sum_incl) {
+  if (R < 0 || N <= 0) return TAO_ERR_INVALID_ARG;
+  for (int32_t v = 0; v < N; v++) {
+    int64_t se = 0, si = 0;
+    for (int64_t r = 0; r < R; r++) {
+      if (excl) se += excl[r * N + v];
+      if (incl) si += incl[r * N + v];
+    }
+    if (excl && sum_excl) sum_excl[v] = se;
+    if (incl && sum_incl) sum_incl[v] = si;
+  }
+  return TAO_OK;
+}
+
+/* Kept nodes: v with (double)sum_incl[v] >= fraction * (double)total, total =
+ * sum over v of sum_excl[v]; listed in ascending node id. */
+int tao_prune(int32_t N, const int64_t *sum_excl, const int64_t *sum_incl, double fraction,
+              int32_t *kept, int32_t *n_kept) {
+  if (N <= 0 || !sum_excl || !sum_incl || !kept || !n_kept || !(fraction >= 0.0))
+    return TAO_ERR_INVALID_ARG;
+  int64_t total = 0;
+  for (int32_t v = 0; v < N; v++) total += sum_excl[v];
+  const double cut = fraction * (double)total;
+  int32_t k = 0;
+  for (int32_t v = 0; v < N; v++)
+    if ((double)sum_incl[v] >= cut) kept[k++] = v;
+  *n_kept = k;
+  return TAO_OK;
+}
+
+/* Nearest ancestor-or-self of u that is kept (is_kept[] = index in kept or
+ * -1), or -1.  Plain walk. */
+static int32_t nearest_kept(const int32_t *parent, const int32_t *is_kept, int32_t u) {
+  for (; u != -1; u = parent[u])
+    if (is_kept[u] >= 0) return is_kept[u];
+  return -1;
+}
+
+/* Profiles on the pruned tree, per rank: p_excl[r][k] = sum of excl[r][u] over
+ * the nodes u whose nearest kept ancestor-or-self is kept[k] (the cost of pruned
+ * descendants folds into the nearest kept ancestor); p_incl[r][k] = sum of
+ * excl[r][u] over the subtree of kept[k]. */
+int tao_pruned(int64_t R, int32_t N, const int32_t *parent, const int64_t *excl, int32_t K,
+               const int32_t *kept, int64_t *p_excl, int64_t *p_incl) {
+  if (R < 0 || N <= 0 || K <= 0 || !parent || !excl || !kept) return TAO_ERR_INVALID_ARG;
+  int32_t *is_kept = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  if (!is_kept) return TAO_ERR_INVALID_ARG;
+  for (int32_t v = 0; v < N; v++) is_kept[v] = -1;
+  for (int32_t k = 0; k < K; k++) {
+    if (kept[k] < 0 || kept[k] >= N || is_kept[kept[k]] >= 0) {
+      free(is_kept);
+      return TAO_ERR_INVALID_ARG;
+    }
+    is_kept[kept[k]] = k;
+  }
+  for (int64_t r = 0; r < R; r++) {
+    int64_t *pe = p_excl ? p_excl + r * K : NULL;
+    int64_t *pi = p_incl ? p_incl + r * K : NULL;
+    for (int32_t k = 0; k < K; k++) {
+      if (pe) pe[k] = 0;
+      if (pi) pi[k] = 0;
+    }
+    for (int32_t u = 0; u < N; u++) {
+      const int64_t x = excl[r * N + u];
+      if (x == 0) continue;
+      const int32_t k = nearest_kept(parent, is_kept, u);
+      if (pe && k >= 0) pe[k] += x;
+      if (pi)
+        for (int32_t w = u; w != -1; w = parent[w])
+          if (is_kept[w] >= 0) pi[is_kept[w]] += x;
+    }
+  }
+  free(is_kept);
+  return TAO_OK;
+}
+
+/* Inclusive version of a rank x iteration x region tensor whose regions are
+ * nested (e.g. the kept nodes of a pruned tree): out[r][i][g] = sum of T[r][i][h]
+ * over the regions h whose node lies in the subtree of region g's node. */
+int tao_tensor_inclusive(const int64_t *T, int64_t R, int32_t I, int32_t G, int32_t N,
+                         const int32_t *parent, const int32_t *region_nodes, int64_t *out) {
+  if (!T || !out || R < 0 || I < 0 || G <= 0 || N <= 0 || !parent || !region_nodes)
+    return TAO_ERR_INVALID_ARG;
+  int32_t *is_reg = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  if (!is_reg) return TAO_ERR_INVALID_ARG;
+  for (int32_t v = 0; v < N; v++) is_reg[v] = -1;
+  for (int32_t g = 0; g < G; g++) is_reg[region_nodes[g]] = g;
+  for (int64_t c = 0; c < R * I; c++) {
+    const int64_t *row = T + c * G;
+    int64_t *o = out + c * G;
+    for (int32_t g = 0; g < G; g++) o[g] = 0;
+    for (int32_t h = 0; h < G; h++)
+      for (int32_t w = region_nodes[h]; w != -1; w = parent[w])
+        if (is_reg[w] >= 0) o[is_reg[w]] += row[h];
+  }
+  free(is_reg);
+  return TAO_OK;
+}
