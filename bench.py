@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-size batch of 256 requests (run in memory-bounded waves)")
     ap.add_argument("--mixed-requests", type=int, default=256)
+    ap.add_argument("--no-pruned", action="store_true",
+                    help="skip the pruned-tree model leg (summary, pruning at 1%%, pruned "
+                         "profiles, kept-node tensor and its inclusive form)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
@@ -182,8 +185,13 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_sample_ranks, I, E / R)
 
+    pruned = None
+    if not args.no_pruned:
+        del o
+        pruned = pruned_model_summary(h, tr, seg, w, I, args.steps)
+
     fused.close()
-    del fused, seg, o, tr, w
+    del fused, seg, tr, w
     torch.cuda.empty_cache()
     pre = None
     if not args.no_prescreen:
@@ -226,8 +234,57 @@ def main():
         "cpu_baseline": cpu,
         "prescreen": pre,
         "mixed_batch": mixed,
+        "pruned_model": pruned,
     }
     print(json.dumps(line))
+
+
+def pruned_model_summary(h, tr, seg, w, I, steps, fraction=0.01):
+    """The pruned-tree model on the benchmark batch: summary profile of the
+    per-rank exclusive costs, pruning at `fraction` of the total, per-rank
+    profiles on the kept nodes, the rank x iteration x kept-node tensor (the
+    fused pass with the kept nodes as regions) and its inclusive form.  Each
+    stage is timed with HIP events on the launch stream over `steps` calls."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    R, N = seg["excl"].shape
+    E = int(w["offsets_host"][-1])
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(stream)
+        res = None
+        for k in range(steps):
+            res = fn()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])), res
+
+    ms, bytes_ = {}, {}
+    ms["summary"], (se, si) = timed(lambda: h.summary(seg["excl"]))
+    bytes_["summary"] = 8 * R * N + 16 * N
+    ms["prune"], kept = timed(lambda: h.prune(se, si, fraction))
+    K = len(kept)
+    h.set_pruned(kept)
+    ms["pruned_profiles"], _ = timed(lambda: h.pruned_profiles(seg["excl"]))
+    bytes_["pruned_profiles"] = 8 * R * N + 16 * R * K
+    h.set_regions(w["marker"], kept.cpu().numpy())
+    ms["segment_kept_nodes"], (T, it, out) = timed(lambda: h.segment(tr, I))
+    h.sync_status()
+    bytes_["segment_kept_nodes"] = 12 * E + 8 * (R + 1) + 8 * R * I * K + 12 * R + 12 * N
+    ms["tensor_inclusive"], Ti = timed(lambda: h.tensor_inclusive(T))
+    bytes_["tensor_inclusive"] = 16 * R * I * K
+    del T, it, out, Ti
+    h.set_regions(w["marker"], w["regions"])
+    torch.cuda.empty_cache()
+    gbs = {k: bytes_[k] / (ms[k] / 1e3) / 1e9 for k in bytes_}
+    print(f"[bench] pruned model: {K} of {N} nodes kept; ms {ms}", file=sys.stderr, flush=True)
+    return {"fraction": fraction, "n_nodes": N, "n_kept": K, "ms": ms,
+            "algorithmic_bytes": bytes_, "achieved_gbs": gbs,
+            "hbm_frac": {k: v / HBM_PEAK_GBS for k, v in gbs.items()}}
 
 
 def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9):

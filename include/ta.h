@@ -229,6 +229,57 @@ ta_status ta_topology_aggregate(ta_handle h, const double *rank_score, const uin
  * into *len.  Host-only, synchronous. */
 ta_status ta_callpath(ta_handle h, int32_t leaf, int32_t *path_host, int32_t cap, int32_t *len);
 
+/* Summary profile (Sec. II-A: the aggregate of all per-rank profiles).
+ * excl[n_ranks][N] holds per-rank exclusive costs in the caller's node
+ * numbering (as written by ta_attribute).  sum_excl[v] = sum over ranks of
+ * excl[r][v] (required); sum_incl[v] = sum of sum_excl over the subtree of v
+ * in the tree given to ta_set_tree (optional, NULL to skip), which equals
+ * the sum over ranks of the inclusive costs.  Exact int64 sums.  N at most
+ * 8192.  Device pointers. */
+ta_status ta_summary(ta_handle h, const int64_t *excl, int64_t n_ranks, int64_t *sum_excl,
+                     int64_t *sum_incl, void *stream);
+
+/* Pruning (Sec. II-A: a strategy evaluated once on the summary profile and
+ * applied to every rank; Sec. VI-B drops the nodes below 1% of the total
+ * runtime).  Keeps node v iff (double)sum_incl[v] >= fraction * (double)total,
+ * total = sum over v of sum_excl[v] (FP64, round to nearest).  Writes the kept
+ * ids in ascending order to kept[0 .. *n_kept) (kept has room for N entries)
+ * and their count to *n_kept (a DEVICE int32).  With non-negative costs the
+ * inclusive cost never grows from a node to its child, so the kept set holds
+ * the parent of each kept non-root node.  fraction >= 0 (NaN ->
+ * TA_ERR_INVALID_ARG); fraction 0 keeps every node. */
+ta_status ta_prune(ta_handle h, const int64_t *sum_excl, const int64_t *sum_incl, double fraction,
+                   int32_t *kept, int32_t *n_kept, void *stream);
+
+/* Installs a pruned tree: the kept node ids (HOST array, any order, distinct,
+ * in [0, N)), copied during the call.  Needs ta_set_tree(); ta_set_tree()
+ * drops it.  Waits for the device to go idle before replacing the previous
+ * kept set. */
+ta_status ta_set_pruned(ta_handle h, int32_t n_kept, const int32_t *kept_host);
+
+/* Per-rank profiles on the pruned tree (Sec. II-A: the kept set is propagated
+ * across the per-rank profiles).  For rank r and kept index k (the order given
+ * to ta_set_pruned):
+ *   p_excl[r][k] = sum of excl[r][u] over the nodes u whose nearest kept
+ *                  ancestor-or-self is kept[k] (pruned descendants fold into
+ *                  their nearest kept ancestor; nodes with no kept ancestor are
+ *                  dropped),
+ *   p_incl[r][k] = sum of excl[r][u] over the subtree of kept[k].
+ * Either output may be NULL (not both, unless n_ranks is 0).  N at most 8192.
+ * Device pointers. */
+ta_status ta_pruned_profiles(ta_handle h, const int64_t *excl, int64_t n_ranks, int64_t *p_excl,
+                             int64_t *p_incl, void *stream);
+
+/* Inclusive form of a rank x iteration x region tensor (Sec. V: the node x
+ * trace x iteration model; with the regions set to the kept nodes of a pruned
+ * tree, ta_segment gives its exclusive form).  out[r][i][g] = sum of
+ * tensor[r][i][h] over the regions h whose node lies in the subtree of region
+ * g's node (region g included), for the regions of the last ta_set_regions().
+ * tensor and out are [n_ranks][n_iters][G] device arrays; out must not alias
+ * tensor. */
+ta_status ta_tensor_inclusive(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                              int64_t *out, void *stream);
+
 /* Batch plan: the whole batch in one HIP graph launch.
  * ta_plan_create orders the ranks longest first (so the longest traces start
  * first and the tail is short), picks the launch shape of the fused pass

@@ -21,6 +21,11 @@ struct ta_handle_s {
   std::vector<int32_t> regions;
   uint32_t *d_info = nullptr;
   int2 *d_tin_tout = nullptr;
+  int4 *d_rt = nullptr;  // regions in preorder: see region_table()
+  // pruned tree (ta_set_pruned): kept nodes' preorder ranges, kept-children CSR
+  int32_t K = 0;
+  int2 *d_kq = nullptr;
+  int32_t *d_koff = nullptr, *d_kchild = nullptr;
   uint32_t *d_err = nullptr;
   void *ws = nullptr;
   size_t ws_bytes = 0;
@@ -116,6 +121,37 @@ ta_status build_tree(ta_handle h, int32_t N, const int32_t *parent, std::vector<
   return TA_OK;
 }
 
+// Regions in preorder of their nodes: the regions inside region g's subtree
+// then occupy consecutive positions [pos(g), end(g)).  Entry i holds
+// (pos(i), end(i)) of region i and (region at position i, end of that region).
+std::vector<int4> region_table(ta_handle h) {
+  const int32_t G = h->G;
+  std::vector<int32_t> perm(G), pos(G), end(G);
+  for (int32_t g = 0; g < G; g++) perm[g] = g;
+  std::sort(perm.begin(), perm.end(),
+            [&](int32_t a, int32_t b) { return h->tin[h->regions[a]] < h->tin[h->regions[b]]; });
+  for (int32_t j = 0; j < G; j++) pos[perm[j]] = j;
+  for (int32_t g = 0; g < G; g++) {
+    const int32_t tout = h->tout[h->regions[g]];
+    int32_t e = pos[g] + 1;
+    while (e < G && h->tin[h->regions[perm[e]]] < tout) e++;
+    end[g] = e;
+  }
+  std::vector<int4> rt(G);
+  for (int32_t i = 0; i < G; i++) rt[i] = make_int4(pos[i], end[i], perm[i], end[perm[i]]);
+  return rt;
+}
+
+void free_pruned(ta_handle h) {
+  if (h->d_kq) hipFree(h->d_kq);
+  if (h->d_koff) hipFree(h->d_koff);
+  if (h->d_kchild) hipFree(h->d_kchild);
+  h->d_kq = nullptr;
+  h->d_koff = nullptr;
+  h->d_kchild = nullptr;
+  h->K = 0;
+}
+
 ta_status upload_tables(ta_handle h) {
   const int32_t N = h->N;
   std::vector<uint32_t> info(N);
@@ -141,12 +177,56 @@ ta_status upload_tables(ta_handle h) {
   for (int32_t v = 0; v < N; v++) tt[v] = make_int2(h->tin[v], h->tout[v]);
   if (h->d_info) hipFree(h->d_info);
   if (h->d_tin_tout) hipFree(h->d_tin_tout);
+  if (h->d_rt) hipFree(h->d_rt);
   h->d_info = nullptr;
   h->d_tin_tout = nullptr;
+  h->d_rt = nullptr;
   TA_HIP(h, hipMalloc(&h->d_info, (size_t)N * sizeof(uint32_t)));
   TA_HIP(h, hipMalloc(&h->d_tin_tout, (size_t)N * sizeof(int2)));
   TA_HIP(h, hipMemcpy(h->d_info, info.data(), (size_t)N * sizeof(uint32_t), hipMemcpyHostToDevice));
   TA_HIP(h, hipMemcpy(h->d_tin_tout, tt.data(), (size_t)N * sizeof(int2), hipMemcpyHostToDevice));
+  if (h->G > 0) {
+    const std::vector<int4> rt = region_table(h);
+    TA_HIP(h, hipMalloc(&h->d_rt, rt.size() * sizeof(int4)));
+    TA_HIP(h, hipMemcpy(h->d_rt, rt.data(), rt.size() * sizeof(int4), hipMemcpyHostToDevice));
+  }
+  return TA_OK;
+}
+
+// Kept nodes of a pruned tree: preorder range of each, and for each the kept
+// nodes whose nearest kept strict ancestor it is (its children in the pruned
+// tree), as CSR over kept indices.
+ta_status upload_pruned(ta_handle h, const std::vector<int32_t> &kept) {
+  const int32_t K = (int32_t)kept.size();
+  std::vector<int32_t> by_tin(K);
+  for (int32_t k = 0; k < K; k++) by_tin[k] = k;
+  std::sort(by_tin.begin(), by_tin.end(),
+            [&](int32_t a, int32_t b) { return h->tin[kept[a]] < h->tin[kept[b]]; });
+  std::vector<int32_t> up(K, -1), stack;
+  for (int32_t k : by_tin) {
+    const int32_t t = h->tin[kept[k]];
+    while (!stack.empty() && h->tout[kept[stack.back()]] <= t) stack.pop_back();
+    up[k] = stack.empty() ? -1 : stack.back();
+    stack.push_back(k);
+  }
+  std::vector<int32_t> off(K + 1, 0), child;
+  for (int32_t k = 0; k < K; k++)
+    if (up[k] >= 0) off[up[k] + 1]++;
+  for (int32_t k = 0; k < K; k++) off[k + 1] += off[k];
+  child.assign(off[K] > 0 ? off[K] : 1, 0);
+  std::vector<int32_t> fillp(off.begin(), off.end() - 1);
+  for (int32_t k = 0; k < K; k++)
+    if (up[k] >= 0) child[fillp[up[k]]++] = k;
+  std::vector<int2> kq(K);
+  for (int32_t k = 0; k < K; k++) kq[k] = make_int2(h->tin[kept[k]], h->tout[kept[k]]);
+  free_pruned(h);
+  TA_HIP(h, hipMalloc(&h->d_kq, (size_t)K * sizeof(int2)));
+  TA_HIP(h, hipMalloc(&h->d_koff, (size_t)(K + 1) * sizeof(int32_t)));
+  TA_HIP(h, hipMalloc(&h->d_kchild, child.size() * sizeof(int32_t)));
+  TA_HIP(h, hipMemcpy(h->d_kq, kq.data(), (size_t)K * sizeof(int2), hipMemcpyHostToDevice));
+  TA_HIP(h, hipMemcpy(h->d_koff, off.data(), (size_t)(K + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+  TA_HIP(h, hipMemcpy(h->d_kchild, child.data(), child.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  h->K = K;
   return TA_OK;
 }
 
@@ -481,6 +561,8 @@ ta_status ta_destroy(ta_handle h) {
   hipDeviceSynchronize();
   if (h->d_info) hipFree(h->d_info);
   if (h->d_tin_tout) hipFree(h->d_tin_tout);
+  if (h->d_rt) hipFree(h->d_rt);
+  free_pruned(h);
   if (h->d_err) hipFree(h->d_err);
   if (h->ws) hipFree(h->ws);
   if (h->pin) hipHostFree(h->pin);
@@ -520,6 +602,7 @@ ta_status ta_set_tree(ta_handle h, int32_t n_nodes, const int32_t *parent_host) 
   h->marker = -1;
   h->G = 0;
   h->regions.clear();
+  free_pruned(h);
   return upload_tables(h);
 }
 
@@ -695,6 +778,100 @@ ta_status ta_topology_aggregate(ta_handle h, const double *rank_score, const uin
   a.err = h->d_err;
   hipError_t e = ta::launch_topology(a, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "topology launch");
+  return TA_OK;
+}
+
+ta_status ta_summary(ta_handle h, const int64_t *excl, int64_t n_ranks, int64_t *sum_excl,
+                     int64_t *sum_incl, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  if (h->N > ta::MAX_NODES_ATTR)
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "summary profiles support at most 8192 CCT nodes");
+  if (n_ranks < 0) return fail(h, TA_ERR_INVALID_ARG, "negative n_ranks");
+  if (!sum_excl) return fail(h, TA_ERR_INVALID_ARG, "sum_excl is required");
+  if (n_ranks > 0 && !excl) return fail(h, TA_ERR_INVALID_ARG, "excl NULL");
+  if ((double)n_ranks * h->N > 4e18) return fail(h, TA_ERR_SIZE_OVERFLOW, "profiles too large");
+  const void *ptrs[] = {excl, sum_excl, sum_incl};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  DeviceGuard dg(h->device);
+  hipError_t e = ta::launch_summary(excl, n_ranks, h->N, h->d_tin_tout, sum_excl, sum_incl,
+                                    device_cus(h->device), (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "summary launch");
+  return TA_OK;
+}
+
+ta_status ta_prune(ta_handle h, const int64_t *sum_excl, const int64_t *sum_incl, double fraction,
+                   int32_t *kept, int32_t *n_kept, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  if (!sum_excl || !sum_incl || !kept || !n_kept)
+    return fail(h, TA_ERR_INVALID_ARG, "sum_excl, sum_incl, kept and n_kept are required");
+  if (!(fraction >= 0.0)) return fail(h, TA_ERR_INVALID_ARG, "fraction must be >= 0");
+  const void *ptrs[] = {sum_excl, sum_incl, kept, n_kept};
+  for (const void *p : ptrs)
+    if (!aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  DeviceGuard dg(h->device);
+  hipError_t e = ta::launch_prune(sum_excl, sum_incl, h->N, fraction, kept, n_kept,
+                                  (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "prune launch");
+  return TA_OK;
+}
+
+ta_status ta_set_pruned(ta_handle h, int32_t n_kept, const int32_t *kept_host) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  if (n_kept < 1 || n_kept > h->N || !kept_host)
+    return fail(h, TA_ERR_INVALID_ARG, "n_kept must be in [1, N]");
+  std::vector<int32_t> kept(kept_host, kept_host + n_kept);
+  std::vector<char> seen(h->N, 0);
+  for (int32_t v : kept) {
+    if (v < 0 || v >= h->N) return fail(h, TA_ERR_INVALID_ARG, "kept node out of range");
+    if (seen[v]) return fail(h, TA_ERR_INVALID_ARG, "duplicate kept node");
+    seen[v] = 1;
+  }
+  DeviceGuard dg(h->device);
+  // Kernels still queued may read the previous tables.
+  TA_HIP(h, hipDeviceSynchronize());
+  return upload_pruned(h, kept);
+}
+
+ta_status ta_pruned_profiles(ta_handle h, const int64_t *excl, int64_t n_ranks, int64_t *p_excl,
+                             int64_t *p_incl, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (h->K <= 0) return fail(h, TA_ERR_STATE, "ta_set_pruned has not been called");
+  if (h->N > ta::MAX_NODES_ATTR)
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "pruned profiles support at most 8192 CCT nodes");
+  if (n_ranks < 0) return fail(h, TA_ERR_INVALID_ARG, "negative n_ranks");
+  if (n_ranks > 0 && !p_excl && !p_incl) return fail(h, TA_ERR_INVALID_ARG, "no output requested");
+  if (n_ranks > 0 && !excl) return fail(h, TA_ERR_INVALID_ARG, "excl NULL");
+  if ((double)n_ranks * h->N > 4e18) return fail(h, TA_ERR_SIZE_OVERFLOW, "profiles too large");
+  const void *ptrs[] = {excl, p_excl, p_incl};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  DeviceGuard dg(h->device);
+  hipError_t e = ta::launch_pruned_profiles(excl, n_ranks, h->N, h->d_tin_tout, h->d_kq, h->K,
+                                            h->d_koff, h->d_kchild, p_excl, p_incl,
+                                            device_cus(h->device), (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "pruned profiles launch");
+  return TA_OK;
+}
+
+ta_status ta_tensor_inclusive(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                              int64_t *out, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (h->G <= 0 || !h->d_rt) return fail(h, TA_ERR_STATE, "ta_set_regions has not been called");
+  if (n_ranks < 0 || n_iters < 1) return fail(h, TA_ERR_INVALID_ARG, "bad sizes");
+  if ((double)n_ranks * n_iters * h->G > 4e18)
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "tensor too large");
+  if (n_ranks > 0 && (!tensor || !out)) return fail(h, TA_ERR_INVALID_ARG, "tensor and out are required");
+  if ((tensor && !aligned16(tensor)) || (out && !aligned16(out)))
+    return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  if (n_ranks > 0 && tensor == out) return fail(h, TA_ERR_INVALID_ARG, "out must not alias tensor");
+  DeviceGuard dg(h->device);
+  hipError_t e = ta::launch_tensor_inclusive(tensor, n_ranks * n_iters, h->G, h->d_rt, out,
+                                             device_cus(h->device), (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "tensor inclusive launch");
   return TA_OK;
 }
 

@@ -123,6 +123,20 @@ hipError_t launch_region_robust(const double *v_t, int64_t R, int G, const int32
 hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStream_t s);
 size_t outliers_ws_bytes(int64_t R, int32_t I, int32_t G, int32_t mode, int32_t kind);
 
+// Summary profile, pruning, pruned per-rank profiles and the inclusive
+// tensor (k_prune.hip).  tin_tout[v] = (preorder index, subtree end).
+size_t subtree_rows_lds_bytes(int N, int K, bool excl);
+hipError_t launch_summary(const int64_t *excl, int64_t R, int N, const int2 *tin_tout,
+                          int64_t *sum_excl, int64_t *sum_incl, int cus, hipStream_t s);
+hipError_t launch_prune(const int64_t *sum_excl, const int64_t *sum_incl, int N, double fraction,
+                        int32_t *kept, int32_t *n_kept, hipStream_t s);
+hipError_t launch_pruned_profiles(const int64_t *excl, int64_t R, int N, const int2 *tin_tout,
+                                  const int2 *kq, int K, const int32_t *koff,
+                                  const int32_t *kchild, int64_t *p_excl, int64_t *p_incl,
+                                  int cus, hipStream_t s);
+hipError_t launch_tensor_inclusive(const int64_t *T, int64_t n_rows, int G, const int4 *rt,
+                                   int64_t *out, int cus, hipStream_t s);
+
 struct TopoArgs {
   const double *score;
   const uint8_t *flag;

@@ -82,6 +82,11 @@ def _load():
         "ta_imbalance": [P, P, i64, i32, i32, P, P, P, P, i32, f64, P, P],
         "ta_outliers": [P, P, i64, i32, i32, P, i32, i32, f64, P, P, P, P, P],
         "ta_topology_aggregate": [P, P, P, i64, P, P, P, i32, i32, i32, P, P, P, P, P, P, P],
+        "ta_summary": [P, P, i64, P, P, P],
+        "ta_prune": [P, P, P, f64, P, P, P],
+        "ta_set_pruned": [P, i32, P],
+        "ta_pruned_profiles": [P, P, i64, P, P, P],
+        "ta_tensor_inclusive": [P, P, i64, i32, P, P],
         "ta_plan_create": [P, P, P, P, P, P],
         "ta_plan_launch": [P, P],
         "ta_plan_info": [P, P, P, P, P, P],
@@ -161,6 +166,7 @@ class Handle:
         self.h = h
         self.n_nodes = 0
         self.n_regions = 0
+        self.n_kept = 0
 
     def _check(self, st, h=True):
         if st != OK:
@@ -186,6 +192,7 @@ class Handle:
         self._check(_lib.ta_set_tree(self.h, len(p), p.ctypes.data_as(C.c_void_p)))
         self.n_nodes = len(p)
         self.n_regions = 0
+        self.n_kept = 0
 
     def set_regions(self, marker: int, regions):
         g = np.ascontiguousarray(regions, dtype=np.int32)
@@ -253,6 +260,52 @@ class Handle:
         self._check(_lib.ta_segment(self.h, C.byref(t), int(n_iters), _ptr(T), _ptr(it), _ptr(out),
                                     _stream(self.device)))
         return T, it, out
+
+    # -- pruning and the pruned-tree model ------------------------------------
+    def summary(self, excl, incl=True):
+        """Summary profile: per-node sums over ranks of `excl` [R, N] and, if
+        `incl`, of the inclusive costs (device int64 tensors of length N)."""
+        R, N = excl.shape
+        if N != self.n_nodes:
+            raise ValueError("excl must have one column per tree node")
+        se = self._empty((N,), torch.int64)
+        si = self._empty((N,), torch.int64) if incl else None
+        self._check(_lib.ta_summary(self.h, _ptr(excl), R, _ptr(se), _ptr(si),
+                                    _stream(self.device)))
+        return se, si
+
+    def prune(self, sum_excl, sum_incl, fraction):
+        """Kept node ids (ascending, device int32); waits for the count."""
+        kept = self._empty((self.n_nodes,), torch.int32)
+        n = self._empty((4,), torch.int32)
+        self._check(_lib.ta_prune(self.h, _ptr(sum_excl), _ptr(sum_incl), float(fraction),
+                                  _ptr(kept), _ptr(n), _stream(self.device)))
+        return kept[:int(n[0].item())]
+
+    def set_pruned(self, kept):
+        k = kept.cpu().numpy() if torch.is_tensor(kept) else kept
+        k = np.ascontiguousarray(k, dtype=np.int32)
+        self._check(_lib.ta_set_pruned(self.h, len(k), k.ctypes.data_as(C.c_void_p)))
+        self.n_kept = len(k)
+
+    def pruned_profiles(self, excl, want_excl=True, want_incl=True):
+        R, N = excl.shape
+        if N != self.n_nodes:
+            raise ValueError("excl must have one column per tree node")
+        pe = self._empty((R, self.n_kept), torch.int64) if want_excl else None
+        pi = self._empty((R, self.n_kept), torch.int64) if want_incl else None
+        self._check(_lib.ta_pruned_profiles(self.h, _ptr(excl), R, _ptr(pe), _ptr(pi),
+                                            _stream(self.device)))
+        return pe, pi
+
+    def tensor_inclusive(self, tensor):
+        R, I, G = tensor.shape
+        if G != self.n_regions:
+            raise ValueError("tensor must have one column per region")
+        out = self._empty((R, I, G), torch.int64)
+        self._check(_lib.ta_tensor_inclusive(self.h, _ptr(tensor), R, I, _ptr(out),
+                                             _stream(self.device)))
+        return out
 
     # -- statistics ----------------------------------------------------------
     def imbalance(self, tensor, iters_found=None, rank_sum=None, rank_sumsq=None, span=None,

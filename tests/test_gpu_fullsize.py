@@ -127,6 +127,64 @@ def test_c3_statistics(mods, oracle, c3):
     assert flag[w.injected].mean() > 0.5
 
 
+def test_c3_pruned_model(mods, oracle, c3):
+    """Pruning at 1% on the 100k-rank batch: the summary checked by its total
+    (sum of spans) and on sampled columns; the pruning decision re-taken by the
+    oracle on the summary; pruned profiles, the kept-node tensor and its
+    inclusive form checked bit-exact on sampled ranks."""
+    torch, gpu_synth, ta = mods
+    w, h, seg, cfg = c3
+    I = cfg["n_iters"]
+    print("[fullsize] summary + prune", flush=True)
+    se, si = h.summary(seg["excl"])
+    se_h, si_h = se.cpu().numpy(), si.cpu().numpy()
+    assert int(se_h.sum()) == int(seg["span"].sum().item())
+    roots = np.flatnonzero(np.asarray(w.parent) == -1)
+    assert int(si_h[roots].sum()) == int(se_h.sum())
+    rng = np.random.default_rng(3)
+    cols = rng.choice(len(se_h), 12, replace=False)
+    for v in cols:
+        ce = seg["excl"][:, int(v)].contiguous().cpu().numpy().reshape(-1, 1)
+        ci = seg["incl"][:, int(v)].contiguous().cpu().numpy().reshape(-1, 1)
+        st, a, b = oracle.summary(ce, ci)
+        assert a[0] == se_h[v] and b[0] == si_h[v]
+    kept = h.prune(se, si, 0.01)
+    st, kept_o = oracle.prune(se_h, si_h, 0.01)
+    assert np.array_equal(kept.cpu().numpy(), kept_o)
+    assert 1 < len(kept_o) <= 256
+    h.set_pruned(kept)
+    print(f"[fullsize] pruned profiles, {len(kept_o)} kept", flush=True)
+    pe, pi = h.pruned_profiles(seg["excl"])
+    ranks = _sample(w)
+    idx = torch.from_numpy(ranks).cuda()
+    ex_rows = seg["excl"].index_select(0, idx).cpu().numpy()
+    st, pe_o, pi_o = oracle.pruned(ex_rows, w.parent, kept_o)
+    assert np.array_equal(pe.index_select(0, idx).cpu().numpy(), pe_o)
+    assert np.array_equal(pi.index_select(0, idx).cpu().numpy(), pi_o)
+    assert torch.equal(pe.sum(1), seg["span"])
+    del pi
+    print("[fullsize] kept-node tensor + inclusive", flush=True)
+    try:
+        h.set_regions(w.marker, kept_o)
+        T, it, out = h.segment(ta.DeviceTraces(w.offsets, w.ts, w.ctx), I)
+        h.sync_status()
+        Ti = h.tensor_inclusive(T)
+        s = gpu_synth.sample_ranks_to_host(w, ranks)
+        st, To, ito, outo, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker,
+                                                 kept_o, I)
+        assert st == 0
+        assert np.array_equal(T.index_select(0, idx).cpu().numpy(), To)
+        assert np.array_equal(it.index_select(0, idx).cpu().numpy(), ito)
+        st, Tio = oracle.tensor_inclusive(To, w.parent, kept_o)
+        assert np.array_equal(Ti.index_select(0, idx).cpu().numpy(), Tio)
+        # whole batch: the pruned exclusive profile = iterations + prologue
+        assert torch.equal(T.sum((1, 2)) + out, pe.sum(1))
+        del T, Ti, it, out
+    finally:
+        h.set_regions(w.marker, w.regions)
+        torch.cuda.empty_cache()
+
+
 def test_c2_shape_full_parity(mods, oracle):
     torch, gpu_synth, ta = mods
     w = gpu_synth.timeline_on_gpu(seed=4, n_ranks=3000, median_len=6000, min_len=1000,

@@ -1,0 +1,228 @@
+"""GPU parity of the summary profile, pruning, pruned per-rank profiles and the
+inclusive rank x iteration x node tensor (through the C ABI) against the CPU
+oracle.  All outputs are integers or integer decisions: bit-exact.  Inputs are
+seeded and synthetic: random trees relabelled so caller ids differ from
+preorder, forests, arbitrary kept subsets in arbitrary order, ties at the cut.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_03561_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ta():
+    from paper_2605_03561_amd import ta as T
+    return T
+
+
+@pytest.fixture(scope="module")
+def h(ta):
+    hh = ta.Handle(0)
+    yield hh
+    hh.close()
+
+
+def random_tree(rng, N, roots=1, chain=0.3):
+    """Random recursive tree (a node hangs under its predecessor with
+    probability `chain`, else under a uniform earlier node), relabelled by a
+    random permutation; the first `roots` nodes are roots."""
+    par = np.full(N, -1, np.int64)
+    for v in range(min(roots, N), N):
+        par[v] = v - 1 if rng.random() < chain else rng.integers(0, v)
+    perm = rng.permutation(N)
+    parent = np.full(N, -1, np.int32)
+    for v in range(N):
+        parent[perm[v]] = -1 if par[v] < 0 else perm[par[v]]
+    return parent
+
+
+def random_excl(rng, R, N):
+    x = rng.integers(0, 1 << 40, size=(R, N), dtype=np.int64)
+    x[rng.random((R, N)) < 0.3] = 0
+    return x
+
+
+def dev(a, dtype=torch.int64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to("cuda:0")
+
+
+def oracle_incl(oracle, excl, parent):
+    st, _, pi = oracle.pruned(excl, parent, np.arange(len(parent), dtype=np.int32))
+    assert st == 0
+    return pi
+
+
+@pytest.mark.parametrize("R,N,roots", [(0, 50, 1), (1, 1, 1), (3, 257, 1), (2500, 1000, 3),
+                                       (150, 8192, 2)])
+def test_summary_matches_oracle(ta, h, oracle, R, N, roots):
+    print(f"summary R={R} N={N} roots={roots}", flush=True)
+    rng = np.random.default_rng([11, R, N])
+    parent = random_tree(rng, N, roots)
+    excl = random_excl(rng, R, N)
+    st, se, si = oracle.summary(excl, oracle_incl(oracle, excl, parent))
+    assert st == 0
+    h.set_tree(parent)
+    gse, gsi = h.summary(dev(excl).reshape(R, N))
+    assert np.array_equal(gse.cpu().numpy(), se)
+    assert np.array_equal(gsi.cpu().numpy(), si)
+
+
+def test_prune_matches_oracle(ta, h, oracle):
+    rng = np.random.default_rng(12)
+    N = 3000
+    parent = random_tree(rng, N, roots=2)
+    excl = random_excl(rng, 40, N)
+    st, se, si = oracle.summary(excl, oracle_incl(oracle, excl, parent))
+    h.set_tree(parent)
+    gse, gsi = h.summary(dev(excl))
+    for frac in (0.0, 1e-4, 0.001, 0.01, 0.05, 0.3, 0.5, 1.0, 3.0):
+        print(f"prune fraction={frac}", flush=True)
+        st, kept = oracle.prune(se, si, frac)
+        assert st == 0
+        g = h.prune(gse, gsi, frac).cpu().numpy()
+        assert np.array_equal(g, kept), frac
+    assert len(h.prune(gse, gsi, 0.0)) == N
+    assert len(h.prune(gse, gsi, 3.0)) == 0
+
+
+def test_prune_ties_and_errors(ta, h, oracle):
+    """The cut is inclusive: a node whose summary inclusive cost equals
+    fraction x total is kept (decided in FP64 on both sides)."""
+    parent = np.array([-1, 0, 0, 1, 1, 2], np.int32)
+    se = np.array([100, 150, 250, 200, 250, 50], np.int64)       # total 1000
+    si = np.array([1000, 600, 300, 200, 250, 50], np.int64)
+    h.set_tree(parent)
+    for frac in (0.25, 0.2, 0.3, 0.6, 0.05, 0.050000000000000003, 1.0):
+        st, kept = oracle.prune(se, si, frac)
+        g = h.prune(dev(se), dev(si), frac).cpu().numpy()
+        assert np.array_equal(g, kept), frac
+    assert h.prune(dev(se), dev(si), 0.25).cpu().tolist() == [0, 1, 2, 4]
+    with pytest.raises(ta.TAError):
+        h.prune(dev(se), dev(si), float("nan"))
+    with pytest.raises(ta.TAError):
+        h.prune(dev(se), dev(si), -0.1)
+
+
+@pytest.mark.parametrize("R,N,how", [(0, 30, "prune"), (1, 1, "prune"), (5, 300, "random"),
+                                     (1000, 700, "prune"), (333, 2049, "random"),
+                                     (64, 8192, "prune"), (64, 8192, "all")])
+def test_pruned_profiles_match_oracle(ta, h, oracle, R, N, how):
+    print(f"pruned R={R} N={N} kept={how}", flush=True)
+    rng = np.random.default_rng([13, R, N])
+    parent = random_tree(rng, N, roots=1 + N // 1000)
+    excl = random_excl(rng, R, N)
+    h.set_tree(parent)
+    if how == "prune":
+        st, se, si = oracle.summary(excl, oracle_incl(oracle, excl, parent))
+        st, kept = oracle.prune(se, si, 0.01)
+        if len(kept) == 0:
+            kept = np.array([int(np.flatnonzero(parent == -1)[0])], np.int32)
+    elif how == "all":
+        kept = rng.permutation(N).astype(np.int32)
+    else:  # any subset in any order: roots may be missing, nodes then dropped
+        kept = rng.choice(N, size=max(1, N // 7), replace=False).astype(np.int32)
+    st, pe, pi = oracle.pruned(excl, parent, kept)
+    assert st == 0
+    h.set_pruned(kept)
+    gpe, gpi = h.pruned_profiles(dev(excl).reshape(R, N))
+    assert np.array_equal(gpe.cpu().numpy(), pe)
+    assert np.array_equal(gpi.cpu().numpy(), pi)
+    only_e, none_i = h.pruned_profiles(dev(excl).reshape(R, N), want_incl=False)
+    assert none_i is None and np.array_equal(only_e.cpu().numpy(), pe)
+
+
+def test_pruned_state_errors(ta, h):
+    h.set_tree(np.array([-1, 0, 0], np.int32))
+    with pytest.raises(ta.TAError):
+        h.pruned_profiles(dev(np.zeros((2, 3), np.int64)))      # no kept set yet
+    with pytest.raises(ta.TAError):
+        h.set_pruned(np.array([0, 0], np.int32))                 # duplicate
+    with pytest.raises(ta.TAError):
+        h.set_pruned(np.array([3], np.int32))                    # out of range
+    h.set_pruned(np.array([0], np.int32))
+    h.set_tree(np.array([-1, 0], np.int32))                      # drops the kept set
+    with pytest.raises(ta.TAError):
+        h.pruned_profiles(dev(np.zeros((2, 2), np.int64)))
+
+
+def nested_regions(rng, parent, G):
+    """G distinct nodes chosen so that many regions nest: half along
+    root-to-leaf paths, the rest uniform."""
+    N = len(parent)
+    chosen = []
+    seen = set()
+    while len(chosen) < G // 2:
+        v = int(rng.integers(0, N))
+        while v != -1 and len(chosen) < G // 2:
+            if v not in seen:
+                seen.add(v)
+                chosen.append(v)
+            v = int(parent[v])
+    for v in rng.permutation(N):
+        if len(chosen) == G:
+            break
+        if int(v) not in seen:
+            seen.add(int(v))
+            chosen.append(int(v))
+    return np.array(rng.permutation(chosen), np.int32)
+
+
+@pytest.mark.parametrize("G", [1, 2, 5, 17, 32, 33, 64, 65, 100, 130, 255, 256])
+def test_tensor_inclusive_matches_oracle(ta, h, oracle, G):
+    print(f"tensor_inclusive G={G}", flush=True)
+    rng = np.random.default_rng([14, G])
+    N = 600
+    parent = random_tree(rng, N, roots=2, chain=0.5)
+    regions = nested_regions(rng, parent, G)
+    R, I = 37, 23   # 851 rows: ragged against every rows-per-wave packing
+    T = rng.integers(0, 1 << 40, size=(R, I, G), dtype=np.int64)
+    st, ref = oracle.tensor_inclusive(T, parent, regions)
+    assert st == 0
+    h.set_tree(parent)
+    h.set_regions(int(regions[0]), regions)
+    out = h.tensor_inclusive(dev(T)).cpu().numpy()
+    assert np.array_equal(out, ref)
+    empty = h.tensor_inclusive(dev(np.zeros((0, I, G), np.int64)).reshape(0, I, G))
+    assert empty.shape == (0, I, G)
+
+
+def test_pruned_tree_model_end_to_end(ta, h, oracle):
+    """Attribution -> summary -> prune at 1% -> regions = kept nodes ->
+    segmentation (exclusive node x rank x iteration model) -> inclusive model,
+    each stage against the oracle."""
+    w = synth.timeline_workload(seed=21, n_ranks=24, median_len=6000, min_len=300, max_len=20000,
+                                n_nodes=400, depth_max=10, n_iters=60, n_regions=8)
+    I = 60
+    h.set_tree(w.parent)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx)
+    ge, gi = h.attribute(tr)
+    st, ex, inc = oracle.attribute(w.offsets, w.ts, w.ctx, w.parent)
+    assert np.array_equal(ge.cpu().numpy(), ex)
+    gse, gsi = h.summary(ge)
+    st, se, si = oracle.summary(ex, inc)
+    assert np.array_equal(gse.cpu().numpy(), se) and np.array_equal(gsi.cpu().numpy(), si)
+    kept_g = h.prune(gse, gsi, 0.01)
+    st, kept = oracle.prune(se, si, 0.01)
+    assert np.array_equal(kept_g.cpu().numpy(), kept)
+    assert 1 < len(kept) <= 256
+    h.set_pruned(kept_g)
+    gpe, gpi = h.pruned_profiles(ge)
+    st, pe, pi = oracle.pruned(ex, w.parent, kept)
+    assert np.array_equal(gpe.cpu().numpy(), pe) and np.array_equal(gpi.cpu().numpy(), pi)
+    h.set_regions(w.marker, kept)
+    T, it, out = h.segment(tr, I)
+    h.sync_status()
+    st, To, ito, outo, span = oracle.segment(w.offsets, w.ts, w.ctx, w.parent, w.marker, kept, I)
+    assert st == 0
+    assert np.array_equal(T.cpu().numpy(), To) and np.array_equal(it.cpu().numpy(), ito)
+    assert np.array_equal(out.cpu().numpy(), outo)
+    Ti = h.tensor_inclusive(T).cpu().numpy()
+    st, Tio = oracle.tensor_inclusive(To, w.parent, kept)
+    assert np.array_equal(Ti, Tio)
+    # every event lies under a kept root: the pruned exclusive profile splits
+    # into the iterations plus the time before the first iteration
+    assert np.array_equal(To.sum(1).sum(1) + outo, pe.sum(1))
