@@ -185,18 +185,24 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_sample_ranks, I, E / R)
 
+    # Release the batch outputs and the handle's workspace (the exact scan's
+    # column-major copy) before the pruned-tree leg, which needs the traces,
+    # the exclusive profiles and two rank x iteration x kept-node tensors.
+    excl = seg["excl"]
+    fused.close()
+    del fused, seg, o
+    h.close()
+    torch.cuda.empty_cache()
     pruned = None
     if not args.no_pruned:
-        del o
-        pruned = pruned_model_summary(h, tr, seg, w, I, args.steps)
-
-    fused.close()
-    del fused, seg, tr, w
+        pruned = pruned_model_summary(tr, excl, w, I, args.steps)
+    del excl, tr, w
     torch.cuda.empty_cache()
     pre = None
     if not args.no_prescreen:
+        h = ta.Handle(0)
         pre = prescreen_summary(h, args.prescreen_epochs)
-    h.close()
+        h.close()
     torch.cuda.empty_cache()
     mixed = None
     if not args.no_mixed:
@@ -239,7 +245,7 @@ def main():
     print(json.dumps(line))
 
 
-def pruned_model_summary(h, tr, seg, w, I, steps, fraction=0.01):
+def pruned_model_summary(tr, excl, w, I, steps, fraction=0.01):
     """The pruned-tree model on the benchmark batch: summary profile of the
     per-rank exclusive costs, pruning at `fraction` of the total, per-rank
     profiles on the kept nodes, the rank x iteration x kept-node tensor (the
@@ -247,9 +253,13 @@ def pruned_model_summary(h, tr, seg, w, I, steps, fraction=0.01):
     stage is timed with HIP events on the launch stream over `steps` calls."""
     import torch
 
+    from paper_2605_03561_amd import ta
+
     stream = torch.cuda.current_stream()
-    R, N = seg["excl"].shape
+    R, N = excl.shape
     E = int(w["offsets_host"][-1])
+    h = ta.Handle(0)
+    h.set_tree(w["parent"])
 
     def timed(fn):
         fn()
@@ -264,21 +274,27 @@ def pruned_model_summary(h, tr, seg, w, I, steps, fraction=0.01):
         return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])), res
 
     ms, bytes_ = {}, {}
-    ms["summary"], (se, si) = timed(lambda: h.summary(seg["excl"]))
+    ms["summary"], (se, si) = timed(lambda: h.summary(excl))
     bytes_["summary"] = 8 * R * N + 16 * N
     ms["prune"], kept = timed(lambda: h.prune(se, si, fraction))
     K = len(kept)
     h.set_pruned(kept)
-    ms["pruned_profiles"], _ = timed(lambda: h.pruned_profiles(seg["excl"]))
+    ms["pruned_profiles"], _ = timed(lambda: h.pruned_profiles(excl))
     bytes_["pruned_profiles"] = 8 * R * N + 16 * R * K
     h.set_regions(w["marker"], kept.cpu().numpy())
-    ms["segment_kept_nodes"], (T, it, out) = timed(lambda: h.segment(tr, I))
+    # preallocated outputs, reused by every timed call
+    seg = {"tensor": torch.empty((R, I, K), dtype=torch.int64, device=excl.device),
+           "iters_found": torch.empty((R,), dtype=torch.int32, device=excl.device),
+           "outside": torch.empty((R,), dtype=torch.int64, device=excl.device)}
+    ms["segment_kept_nodes"], _ = timed(
+        lambda: h.attribute_segment(tr, I, outputs=tuple(seg), out=seg))
     h.sync_status()
     bytes_["segment_kept_nodes"] = 12 * E + 8 * (R + 1) + 8 * R * I * K + 12 * R + 12 * N
-    ms["tensor_inclusive"], Ti = timed(lambda: h.tensor_inclusive(T))
+    Ti = torch.empty_like(seg["tensor"])
+    ms["tensor_inclusive"], _ = timed(lambda: h.tensor_inclusive(seg["tensor"], out=Ti))
     bytes_["tensor_inclusive"] = 16 * R * I * K
-    del T, it, out, Ti
-    h.set_regions(w["marker"], w["regions"])
+    del seg, Ti
+    h.close()
     torch.cuda.empty_cache()
     gbs = {k: bytes_[k] / (ms[k] / 1e3) / 1e9 for k in bytes_}
     print(f"[bench] pruned model: {K} of {N} nodes kept; ms {ms}", file=sys.stderr, flush=True)

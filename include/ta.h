@@ -275,8 +275,9 @@ ta_status ta_pruned_profiles(ta_handle h, const int64_t *excl, int64_t n_ranks, 
  * tree, ta_segment gives its exclusive form).  out[r][i][g] = sum of
  * tensor[r][i][h] over the regions h whose node lies in the subtree of region
  * g's node (region g included), for the regions of the last ta_set_regions().
- * tensor and out are [n_ranks][n_iters][G] device arrays; out must not alias
- * tensor. */
+ * tensor and out are [n_ranks][n_iters][G] device arrays; out may be tensor
+ * itself (in place: each row is read whole before it is written) but must not
+ * otherwise overlap it. */
 ta_status ta_tensor_inclusive(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
                               int64_t *out, void *stream);
 

@@ -16,7 +16,8 @@
 namespace ta {
 namespace {
 
-constexpr int ST = 256;   // threads of the row-scan and column-sum kernels
+constexpr int ST = 256;   // threads of the column-sum and tensor kernels
+constexpr int SR = 512;   // threads of the row-scan kernel
 constexpr int PT = 1024;  // threads of the single-workgroup pruning kernel
 
 // Exclusive scan over the workgroup (NT a multiple of 64); `wsum` holds NT/64
@@ -44,23 +45,64 @@ __device__ inline T block_excl_scan(T v, T *wsum, T *total) {
   return base + x - v;
 }
 
-// In-place exclusive prefix of P[0..n) in LDS, P[n] = total.  Each thread owns
-// a contiguous chunk.
-template <int NT>
-__device__ inline void lds_scan(uint64_t *P, int n, uint64_t *wsum) {
-  const int per = (n + NT - 1) / NT;
-  const int j0 = min(n, (int)threadIdx.x * per), j1 = min(n, j0 + per);
-  uint64_t s = 0;
-  for (int j = j0; j < j1; j++) s += P[j];
-  uint64_t total;
-  uint64_t acc = block_excl_scan<NT>(s, wsum, &total);
-  for (int j = j0; j < j1; j++) {
-    const uint64_t x = P[j];
-    P[j] = acc;
-    acc += x;
+// x from the lane selected by a DPP control word; lanes with no source (or
+// outside `ROWS`) get 0.  64-bit values move as two 32-bit halves.
+template <int CTRL, int ROWS>
+__device__ inline uint64_t dpp_u64(uint64_t x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROWS, 0xf, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Inclusive scan over the 64 lanes of a wave, on the VALU: shifts by 1, 2, 4
+// and 8 within each 16-lane row, then the last lane of row 0 (2) is added to
+// row 1 (3), and lane 31 to rows 2 and 3.
+__device__ inline uint64_t wave_incl_scan(uint64_t x) {
+  x += dpp_u64<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_u64<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_u64<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_u64<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_u64<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_u64<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ inline uint64_t lane63(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+// Exclusive prefix of P[0..n) in LDS, by wave segments: wave w scans positions
+// [w*L, (w+1)*L) (L a multiple of 256; P is zero from n up to NW*L) in tiles of
+// 256, lane l taking 4 consecutive positions (two 16-byte reads), and leaves
+// the prefix within its segment at the positions below n; seg[w] gets the
+// segment's total.  The full prefix of position x < n is then
+// P[x] + (sum of seg[w'] for w' < x / L).
+__device__ inline void lds_scan_segments(uint64_t *P, int n, int L, uint64_t *seg) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = w * L, e = min(n, b + L);
+  uint64_t carry = 0;
+  for (int t = b; t < e; t += 256) {
+    const int j = t + 4 * lane;
+    const u64x2 p0 = *reinterpret_cast<const u64x2 *>(&P[j]);
+    const u64x2 p1 = *reinterpret_cast<const u64x2 *>(&P[j + 2]);
+    const uint64_t a0 = p0.x, a1 = p0.y, a2 = p1.x, a3 = p1.y;
+    const uint64_t sum = (a0 + a1) + (a2 + a3);
+    const uint64_t inc = wave_incl_scan(sum);
+    uint64_t acc = carry + inc - sum;
+    if (j < e) P[j] = acc;
+    acc += a0;
+    if (j + 1 < e) P[j + 1] = acc;
+    acc += a1;
+    if (j + 2 < e) P[j + 2] = acc;
+    acc += a2;
+    if (j + 3 < e) P[j + 3] = acc;
+    carry += lane63(inc);
   }
-  if (threadIdx.x == 0) P[n] = total;
-  __syncthreads();
+  if (lane == 0) seg[w] = carry;
 }
 
 __global__ void fill_u64(uint64_t *p, int64_t n) {
@@ -90,44 +132,117 @@ __global__ __launch_bounds__(ST) void colsum_kernel(const int64_t *__restrict__ 
   if (s != 0) atomicAdd((unsigned long long *)&out[c], (unsigned long long)s);
 }
 
+// Positions per wave segment of the row scan: a multiple of 256 with
+// (SR / 64) segments covering N.
+__host__ __device__ inline int seg_len(int N) {
+  const int per = (N + SR / 64 - 1) / (SR / 64);
+  return ((per + 255) / 256) * 256 > 0 ? ((per + 255) / 256) * 256 : 256;
+}
+
 // Row pass: for each row of rows[n_rows][N] (caller node order) and each query
 // k with preorder range q[k] = (tin, tout): incl = sum of the row over the
-// range.  With a child list (the kept children of query k in the pruned tree,
-// kchild[koff[k] .. koff[k+1])), excl = incl minus the children's incl: the
-// row's cost on the nodes whose nearest query ancestor-or-self is k.
-__global__ __launch_bounds__(ST) void subtree_rows(const int64_t *__restrict__ rows, int64_t n_rows,
+// range.  With kpar (kpar[k] = the query that is k's nearest query strict
+// ancestor, or -1), excl[k] = incl[k] minus the incl of every query whose kpar
+// is k: the row's cost on the nodes whose nearest query ancestor-or-self is k
+// (exact: 64-bit LDS atomics on integers).
+//
+// Thread t owns nodes t + SR*u (u < B, B*SR >= N): their preorder positions
+// stay in registers, a row arrives in one batch of loads, and the next row's
+// loads are issued before the current row is scanned.  With KB > 0 (K <=
+// KB*SR) the queries' ranges and parents also stay in registers, so nothing
+// waits on the prefetch until the next row is scattered (vector memory
+// counters retire in order).
+template <int B, int KB>
+__global__ __launch_bounds__(SR) void subtree_rows(const int64_t *__restrict__ rows, int64_t n_rows,
                                                   int N, const int2 *__restrict__ tin_tout,
                                                   const int2 *__restrict__ q, int K,
-                                                  const int32_t *__restrict__ koff,
-                                                  const int32_t *__restrict__ kchild,
+                                                  const int32_t *__restrict__ kpar,
                                                   int64_t *__restrict__ out_excl,
                                                   int64_t *__restrict__ out_incl) {
+  constexpr int NW = SR / 64;
+  constexpr int KR = KB > 0 ? KB : 1;
   extern __shared__ uint64_t lds[];
-  __shared__ uint64_t wsum[ST / 64];
-  uint64_t *P = lds;          // [N + 1]
-  uint64_t *Q = lds + N + 1;  // [K] when out_excl
-  for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
+  __shared__ uint64_t seg[NW];
+  const int L = seg_len(N);
+  uint64_t *P = lds;           // [NW * L], zero from N on
+  uint64_t *E = lds + NW * L;  // [K] when out_excl
+  for (int j = N + threadIdx.x; j < NW * L; j += SR) P[j] = 0;
+  int pos[B];
+  uint64_t x[B];
+#pragma unroll
+  for (int u = 0; u < B; u++) {
+    const int v = threadIdx.x + SR * u;
+    pos[u] = v < N ? tin_tout[v].x : -1;
+  }
+  int2 qk[KR];
+  int pk[KR];
+#pragma unroll
+  for (int i = 0; i < KR; i++) {
+    const int k = threadIdx.x + SR * i;
+    const bool on = KB > 0 && k < K;
+    qk[i] = on ? q[k] : make_int2(0, 0);
+    pk[i] = on && out_excl ? kpar[k] : -1;
+  }
+  auto load_row = [&](int64_t r) {
     const int64_t *row = rows + r * N;
-    for (int v = threadIdx.x; v < N; v += ST) P[tin_tout[v].x] = (uint64_t)row[v];
+#pragma unroll
+    for (int u = 0; u < B; u++) x[u] = pos[u] >= 0 ? (uint64_t)row[threadIdx.x + SR * u] : 0;
+  };
+  int64_t r = blockIdx.x;
+  if (r < n_rows) load_row(r);
+  for (; r < n_rows; r += gridDim.x) {
+#pragma unroll
+    for (int u = 0; u < B; u++)
+      if (pos[u] >= 0) P[pos[u]] = x[u];
     __syncthreads();
-    lds_scan<ST>(P, N, wsum);
-    if (out_excl) {
-      for (int k = threadIdx.x; k < K; k += ST) {
-        const int2 t = q[k];
-        Q[k] = P[t.y] - P[t.x];
+    if (r + gridDim.x < n_rows) load_row(r + gridDim.x);  // in flight during the scan
+    lds_scan_segments(P, N, L, seg);
+    __syncthreads();
+    uint64_t off[NW + 1];
+    off[0] = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) off[w + 1] = off[w] + seg[w];
+    // full exclusive prefix at position p in [0, N]
+    auto pref = [&](int p) -> uint64_t { return p >= N ? off[NW] : P[p] + off[p / L]; };
+    if (KB > 0) {
+      uint64_t inc[KR];
+#pragma unroll
+      for (int i = 0; i < KR; i++) {
+        const int k = threadIdx.x + SR * i;
+        inc[i] = k < K ? pref(qk[i].y) - pref(qk[i].x) : 0;
+        if (out_excl && k < K) E[k] = inc[i];
       }
-      __syncthreads();
-      for (int k = threadIdx.x; k < K; k += ST) {
-        const uint64_t inc = Q[k];
-        uint64_t ex = inc;
-        for (int j = koff[k]; j < koff[k + 1]; j++) ex -= Q[kchild[j]];
-        out_excl[r * K + k] = (int64_t)ex;
-        if (out_incl) out_incl[r * K + k] = (int64_t)inc;
+      if (out_excl) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < KR; i++)
+          if (pk[i] >= 0) atomicAdd((unsigned long long *)&E[pk[i]], (unsigned long long)(0 - inc[i]));
+        __syncthreads();
+      }
+#pragma unroll
+      for (int i = 0; i < KR; i++) {
+        const int k = threadIdx.x + SR * i;
+        if (k < K) {
+          if (out_excl) out_excl[r * K + k] = (int64_t)E[k];
+          if (out_incl) out_incl[r * K + k] = (int64_t)inc[i];
+        }
       }
     } else {
-      for (int k = threadIdx.x; k < K; k += ST) {
+      for (int k = threadIdx.x; k < K; k += SR) {
         const int2 t = q[k];
-        out_incl[r * K + k] = (int64_t)(P[t.y] - P[t.x]);
+        const uint64_t inc = pref(t.y) - pref(t.x);
+        if (out_excl) E[k] = inc;
+        if (out_incl) out_incl[r * K + k] = (int64_t)inc;
+      }
+      if (out_excl) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < K; k += SR) {
+          const int2 t = q[k];
+          const int p = kpar[k];
+          if (p >= 0) atomicAdd((unsigned long long *)&E[p], (unsigned long long)(0 - (pref(t.y) - pref(t.x))));
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < K; k += SR) out_excl[r * K + k] = (int64_t)E[k];
       }
     }
     __syncthreads();
@@ -159,85 +274,106 @@ __global__ __launch_bounds__(PT) void prune_kernel(const int64_t *__restrict__ s
   if (threadIdx.x == 0) *n_kept = base;
 }
 
+// The inclusive-tensor kernels may run in place (out == T): a row is read
+// whole by one wave before that wave writes it, and no other wave touches it.
+//
 // Inclusive tensor, G <= 64: segments of GP lanes (GP = power of two >= G),
 // 64 / GP rows per wave.  Lane j of a segment holds the value of the region at
 // region-preorder position j; a segmented inclusive scan S gives the range sum
 // over [j, end_j) as S[end_j - 1] - S[j] + v_j.
 template <int GP>
-__global__ __launch_bounds__(ST) void incl_tensor_narrow(const int64_t *__restrict__ T,
-                                                        int64_t n_rows, int G,
+__global__ __launch_bounds__(ST) void incl_tensor_narrow(const int64_t *T, int64_t n_rows, int G,
                                                         const int4 *__restrict__ rt,
-                                                        int64_t *__restrict__ out) {
-  constexpr int RPW = 64 / GP;
+                                                        int64_t *out) {
+  constexpr int RPW = 64 / GP;  // rows per wave-step
+  constexpr int RB = 4;         // wave-steps whose loads are issued together
   const int lane = threadIdx.x & 63;
   const int seg = lane / GP, j = lane % GP;
   const int64_t wave = ((int64_t)blockIdx.x * ST + threadIdx.x) >> 6;
   const int64_t n_waves = ((int64_t)gridDim.x * ST) >> 6;
   const int4 t = (j < G) ? rt[j] : make_int4(0, 0, 0, 1);
   const int g = t.z, last = t.w - 1;  // region at position j; last position of its range
-  for (int64_t r0 = wave * RPW; r0 < n_rows; r0 += n_waves * RPW) {
-    const int64_t r = r0 + seg;
-    const bool on = (j < G) && (r < n_rows);
-    const uint64_t v = on ? (uint64_t)T[r * G + g] : 0;
-    uint64_t x = v;
+  for (int64_t r0 = wave * RPW * RB; r0 < n_rows; r0 += n_waves * RPW * RB) {
+    uint64_t v[RB];
 #pragma unroll
-    for (int d = 1; d < GP; d <<= 1) {
-      const uint64_t y = __shfl_up(x, d, GP);
-      if (j >= d) x += y;
+    for (int b = 0; b < RB; b++) {
+      const int64_t r = r0 + b * RPW + seg;
+      v[b] = (j < G && r < n_rows) ? (uint64_t)T[r * G + g] : 0;
     }
-    const uint64_t e = __shfl(x, last, GP);
-    if (on) out[r * G + g] = (int64_t)(e - x + v);
+#pragma unroll
+    for (int b = 0; b < RB; b++) {
+      const int64_t r = r0 + b * RPW + seg;
+      uint64_t x = v[b];
+#pragma unroll
+      for (int d = 1; d < GP; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d, GP);
+        if (j >= d) x += y;
+      }
+      const uint64_t e = __shfl(x, last, GP);
+      if (j < G && r < n_rows) out[r * G + g] = (int64_t)(e - x + v[b]);
+    }
   }
 }
 
-// Inclusive tensor, 64 < G <= 256: one row per wave; each lane owns up to four
-// consecutive region-preorder positions; the wave's prefix goes to LDS.
-__global__ __launch_bounds__(ST) void incl_tensor_wide(const int64_t *__restrict__ T,
-                                                      int64_t n_rows, int G,
+// Inclusive tensor, 64 < G <= 256: one row per wave, RB rows whose loads are
+// issued together.  Lane l loads and stores regions l + 64c (coalesced); the
+// values go to LDS at their region-preorder positions, lane l scans positions
+// 4l .. 4l+3 locally, one wave scan joins the lanes, and the exclusive prefix
+// E (E[G] = row total) goes back to LDS: out[g] = E[end(g)] - E[pos(g)].
+__global__ __launch_bounds__(ST) void incl_tensor_wide(const int64_t *T, int64_t n_rows, int G,
                                                       const int4 *__restrict__ rt,
-                                                      int64_t *__restrict__ out) {
-  __shared__ uint64_t S[ST / 64][MAX_REGIONS + 1];
+                                                      int64_t *out) {
+  constexpr int RB = 4;
+  __shared__ uint64_t S[ST / 64][MAX_REGIONS + 4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint64_t *P = S[w];
   const int64_t wave = ((int64_t)blockIdx.x * ST + threadIdx.x) >> 6;
   const int64_t n_waves = ((int64_t)gridDim.x * ST) >> 6;
-  for (int64_t r = wave; r < n_rows; r += n_waves) {
-    const int64_t *row = T + r * G;
-    // region g = lane + 64c goes to its preorder position rt[g].x
-    for (int g = lane; g < G; g += 64) P[rt[g].x] = (uint64_t)row[g];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int j0 = lane * 4;
-    uint64_t a[4], s = 0;
+  int ps[4], pe[4];
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-      a[u] = (j0 + u < G) ? P[j0 + u] : 0;
-      s += a[u];
-    }
-    uint64_t x = s;
+  for (int c = 0; c < 4; c++) {
+    const int g = lane + 64 * c;
+    const int4 t = g < G ? rt[g] : make_int4(0, 0, 0, 0);
+    ps[c] = t.x;
+    pe[c] = t.y;
+  }
+  for (int64_t r0 = wave * RB; r0 < n_rows; r0 += n_waves * RB) {
+    uint64_t v[RB][4];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint64_t y = __shfl_up(x, d, 64);
-      if (lane >= d) x += y;
-    }
-    uint64_t acc = x - s;  // exclusive prefix of position j0
+    for (int b = 0; b < RB; b++)
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-      if (j0 + u <= G) P[j0 + u] = acc;  // P[G] = total (lane owning position G)
-      acc += a[u];
+      for (int c = 0; c < 4; c++) {
+        const int g = lane + 64 * c;
+        v[b][c] = (g < G && r0 + b < n_rows) ? (uint64_t)T[(r0 + b) * G + g] : 0;
+      }
+#pragma unroll
+    for (int b = 0; b < RB; b++) {
+      if (r0 + b >= n_rows) break;
+#pragma unroll
+      for (int c = 0; c < 4; c++)
+        if (lane + 64 * c < G) P[ps[c]] = v[b][c];
+      __builtin_amdgcn_wave_barrier();
+      uint64_t a[4], s = 0;
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        a[u] = 4 * lane + u < G ? P[4 * lane + u] : 0;
+        s += a[u];
+      }
+      uint64_t acc = wave_incl_scan(s) - s;
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        P[4 * lane + u] = acc;  // exclusive prefix; positions >= G hold the total
+        acc += a[u];
+      }
+      if (lane == 63) P[4 * 64] = acc;  // the total, for G = 256
+      __builtin_amdgcn_wave_barrier();
+      int64_t *o = out + (r0 + b) * G;
+#pragma unroll
+      for (int c = 0; c < 4; c++)
+        if (lane + 64 * c < G) o[lane + 64 * c] = (int64_t)(P[pe[c]] - P[ps[c]]);
+      __builtin_amdgcn_wave_barrier();
     }
-    if (j0 + 4 == G) P[G] = acc;  // G = 256: no lane owns position G
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int g = lane; g < G; g += 64) {
-      const int4 t = rt[g];
-      out[r * G + g] = (int64_t)(P[t.y] - P[t.x]);
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -248,19 +384,57 @@ int grid_for(int64_t waves_of_work, int device_cus_hint) {
   return g < 1 ? 1 : (int)g;
 }
 
+template <int B>
+void allow_big_lds_b() {
+  const void *fns[] = {reinterpret_cast<const void *>(&subtree_rows<B, 0>),
+                       reinterpret_cast<const void *>(&subtree_rows<B, 1>),
+                       reinterpret_cast<const void *>(&subtree_rows<B, 2>)};
+  for (const void *f : fns)
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+}
+
+void allow_big_lds() {
+  static bool done = false;
+  if (!done) {
+    allow_big_lds_b<2>();
+    allow_big_lds_b<4>();
+    allow_big_lds_b<8>();
+    allow_big_lds_b<12>();
+    allow_big_lds_b<16>();
+    done = true;
+  }
+}
+
+// Registers per thread: B >= ceil(N / SR) row values, KB >= ceil(K / SR)
+// queries (0: queries read from memory, any K).
+template <int B>
+void launch_rows_b(int grid, size_t lds, hipStream_t s, const int64_t *rows, int64_t n_rows,
+                          int N, const int2 *tin_tout, const int2 *q, int K, const int32_t *kpar,
+                          int64_t *out_excl, int64_t *out_incl) {
+  const int kq = (K + SR - 1) / SR;
+  if (kq <= 1)
+    subtree_rows<B, 1><<<grid, SR, lds, s>>>(rows, n_rows, N, tin_tout, q, K, kpar, out_excl, out_incl);
+  else if (kq <= 2)
+    subtree_rows<B, 2><<<grid, SR, lds, s>>>(rows, n_rows, N, tin_tout, q, K, kpar, out_excl, out_incl);
+  else
+    subtree_rows<B, 0><<<grid, SR, lds, s>>>(rows, n_rows, N, tin_tout, q, K, kpar, out_excl, out_incl);
+}
+
+void launch_rows(int grid, size_t lds, hipStream_t s, const int64_t *rows, int64_t n_rows,
+                        int N, const int2 *tin_tout, const int2 *q, int K, const int32_t *kpar,
+                        int64_t *out_excl, int64_t *out_incl) {
+  const int per = (N + SR - 1) / SR;
+  if (per <= 2) launch_rows_b<2>(grid, lds, s, rows, n_rows, N, tin_tout, q, K, kpar, out_excl, out_incl);
+  else if (per <= 4) launch_rows_b<4>(grid, lds, s, rows, n_rows, N, tin_tout, q, K, kpar, out_excl, out_incl);
+  else if (per <= 8) launch_rows_b<8>(grid, lds, s, rows, n_rows, N, tin_tout, q, K, kpar, out_excl, out_incl);
+  else if (per <= 12) launch_rows_b<12>(grid, lds, s, rows, n_rows, N, tin_tout, q, K, kpar, out_excl, out_incl);
+  else launch_rows_b<16>(grid, lds, s, rows, n_rows, N, tin_tout, q, K, kpar, out_excl, out_incl);
+}
+
 }  // namespace
 
 size_t subtree_rows_lds_bytes(int N, int K, bool excl) {
-  return ((size_t)N + 1 + (excl ? (size_t)K : 0)) * sizeof(uint64_t);
-}
-
-static void allow_big_lds() {
-  static bool done = false;
-  if (!done) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&subtree_rows),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    done = true;
-  }
+  return ((size_t)(SR / 64) * seg_len(N) + (excl ? (size_t)K : 0)) * sizeof(uint64_t);
 }
 
 hipError_t launch_summary(const int64_t *excl, int64_t R, int N, const int2 *tin_tout,
@@ -278,8 +452,7 @@ hipError_t launch_summary(const int64_t *excl, int64_t R, int N, const int2 *tin
   if (sum_incl) {
     allow_big_lds();
     const size_t lds = subtree_rows_lds_bytes(N, N, false);
-    subtree_rows<<<1, ST, lds, s>>>(sum_excl, 1, N, tin_tout, tin_tout, N, nullptr, nullptr,
-                                    nullptr, sum_incl);
+    launch_rows(1, lds, s, sum_excl, 1, N, tin_tout, tin_tout, N, nullptr, nullptr, sum_incl);
   }
   return hipGetLastError();
 }
@@ -291,9 +464,8 @@ hipError_t launch_prune(const int64_t *sum_excl, const int64_t *sum_incl, int N,
 }
 
 hipError_t launch_pruned_profiles(const int64_t *excl, int64_t R, int N, const int2 *tin_tout,
-                                  const int2 *kq, int K, const int32_t *koff,
-                                  const int32_t *kchild, int64_t *p_excl, int64_t *p_incl,
-                                  int cus, hipStream_t s) {
+                                  const int2 *kq, int K, const int32_t *kpar, int64_t *p_excl,
+                                  int64_t *p_incl, int cus, hipStream_t s) {
   if (R <= 0) return hipSuccess;
   const bool ex = p_excl != nullptr;
   const size_t lds = subtree_rows_lds_bytes(N, K, ex);
@@ -303,8 +475,8 @@ hipError_t launch_pruned_profiles(const int64_t *excl, int64_t R, int N, const i
   per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
   int64_t grid = (int64_t)cus * per_cu;
   if (grid > R) grid = R;
-  subtree_rows<<<(unsigned)grid, ST, lds, s>>>(excl, R, N, tin_tout, kq, K, ex ? koff : nullptr,
-                                               ex ? kchild : nullptr, p_excl, p_incl);
+  launch_rows((int)grid, lds, s, excl, R, N, tin_tout, kq, K, ex ? kpar : nullptr, p_excl,
+              p_incl);
   return hipGetLastError();
 }
 
@@ -312,12 +484,13 @@ hipError_t launch_tensor_inclusive(const int64_t *T, int64_t n_rows, int G, cons
                                    int64_t *out, int cus, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   if (G > 64) {
-    incl_tensor_wide<<<grid_for(n_rows, cus), ST, 0, s>>>(T, n_rows, G, rt, out);
+    incl_tensor_wide<<<grid_for((n_rows + 3) / 4, cus), ST, 0, s>>>(T, n_rows, G, rt, out);
     return hipGetLastError();
   }
   int gp = 1;
   while (gp < G) gp <<= 1;
-  const int64_t waves = (n_rows + (64 / gp) - 1) / (64 / gp);
+  const int64_t per_wave = 4 * (64 / gp);  // rows per wave per iteration
+  const int64_t waves = (n_rows + per_wave - 1) / per_wave;
   const int grid = grid_for(waves, cus);
   switch (gp) {
     case 1: incl_tensor_narrow<1><<<grid, ST, 0, s>>>(T, n_rows, G, rt, out); break;

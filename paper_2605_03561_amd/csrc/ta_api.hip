@@ -22,10 +22,11 @@ struct ta_handle_s {
   uint32_t *d_info = nullptr;
   int2 *d_tin_tout = nullptr;
   int4 *d_rt = nullptr;  // regions in preorder: see region_table()
-  // pruned tree (ta_set_pruned): kept nodes' preorder ranges, kept-children CSR
+  // pruned tree (ta_set_pruned): kept nodes' preorder ranges and, for each, the
+  // index of its nearest kept strict ancestor (-1 if none)
   int32_t K = 0;
   int2 *d_kq = nullptr;
-  int32_t *d_koff = nullptr, *d_kchild = nullptr;
+  int32_t *d_kpar = nullptr;
   uint32_t *d_err = nullptr;
   void *ws = nullptr;
   size_t ws_bytes = 0;
@@ -144,11 +145,9 @@ std::vector<int4> region_table(ta_handle h) {
 
 void free_pruned(ta_handle h) {
   if (h->d_kq) hipFree(h->d_kq);
-  if (h->d_koff) hipFree(h->d_koff);
-  if (h->d_kchild) hipFree(h->d_kchild);
+  if (h->d_kpar) hipFree(h->d_kpar);
   h->d_kq = nullptr;
-  h->d_koff = nullptr;
-  h->d_kchild = nullptr;
+  h->d_kpar = nullptr;
   h->K = 0;
 }
 
@@ -193,9 +192,9 @@ ta_status upload_tables(ta_handle h) {
   return TA_OK;
 }
 
-// Kept nodes of a pruned tree: preorder range of each, and for each the kept
-// nodes whose nearest kept strict ancestor it is (its children in the pruned
-// tree), as CSR over kept indices.
+// Kept nodes of a pruned tree: preorder range of each and the index of its
+// nearest kept strict ancestor (its parent in the pruned tree), found with a
+// stack over the kept nodes in preorder.
 ta_status upload_pruned(ta_handle h, const std::vector<int32_t> &kept) {
   const int32_t K = (int32_t)kept.size();
   std::vector<int32_t> by_tin(K);
@@ -209,23 +208,13 @@ ta_status upload_pruned(ta_handle h, const std::vector<int32_t> &kept) {
     up[k] = stack.empty() ? -1 : stack.back();
     stack.push_back(k);
   }
-  std::vector<int32_t> off(K + 1, 0), child;
-  for (int32_t k = 0; k < K; k++)
-    if (up[k] >= 0) off[up[k] + 1]++;
-  for (int32_t k = 0; k < K; k++) off[k + 1] += off[k];
-  child.assign(off[K] > 0 ? off[K] : 1, 0);
-  std::vector<int32_t> fillp(off.begin(), off.end() - 1);
-  for (int32_t k = 0; k < K; k++)
-    if (up[k] >= 0) child[fillp[up[k]]++] = k;
   std::vector<int2> kq(K);
   for (int32_t k = 0; k < K; k++) kq[k] = make_int2(h->tin[kept[k]], h->tout[kept[k]]);
   free_pruned(h);
   TA_HIP(h, hipMalloc(&h->d_kq, (size_t)K * sizeof(int2)));
-  TA_HIP(h, hipMalloc(&h->d_koff, (size_t)(K + 1) * sizeof(int32_t)));
-  TA_HIP(h, hipMalloc(&h->d_kchild, child.size() * sizeof(int32_t)));
+  TA_HIP(h, hipMalloc(&h->d_kpar, (size_t)K * sizeof(int32_t)));
   TA_HIP(h, hipMemcpy(h->d_kq, kq.data(), (size_t)K * sizeof(int2), hipMemcpyHostToDevice));
-  TA_HIP(h, hipMemcpy(h->d_koff, off.data(), (size_t)(K + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
-  TA_HIP(h, hipMemcpy(h->d_kchild, child.data(), child.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  TA_HIP(h, hipMemcpy(h->d_kpar, up.data(), (size_t)K * sizeof(int32_t), hipMemcpyHostToDevice));
   h->K = K;
   return TA_OK;
 }
@@ -851,8 +840,8 @@ ta_status ta_pruned_profiles(ta_handle h, const int64_t *excl, int64_t n_ranks, 
     if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
   DeviceGuard dg(h->device);
   hipError_t e = ta::launch_pruned_profiles(excl, n_ranks, h->N, h->d_tin_tout, h->d_kq, h->K,
-                                            h->d_koff, h->d_kchild, p_excl, p_incl,
-                                            device_cus(h->device), (hipStream_t)stream);
+                                            h->d_kpar, p_excl, p_incl, device_cus(h->device),
+                                            (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "pruned profiles launch");
   return TA_OK;
 }
@@ -867,7 +856,12 @@ ta_status ta_tensor_inclusive(ta_handle h, const int64_t *tensor, int64_t n_rank
   if (n_ranks > 0 && (!tensor || !out)) return fail(h, TA_ERR_INVALID_ARG, "tensor and out are required");
   if ((tensor && !aligned16(tensor)) || (out && !aligned16(out)))
     return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
-  if (n_ranks > 0 && tensor == out) return fail(h, TA_ERR_INVALID_ARG, "out must not alias tensor");
+  if (n_ranks > 0 && tensor != out) {
+    const uint64_t bytes = (uint64_t)n_ranks * (uint64_t)n_iters * (uint64_t)h->G * 8u;
+    const uintptr_t a = (uintptr_t)tensor, b = (uintptr_t)out;
+    if (a < b + bytes && b < a + bytes)
+      return fail(h, TA_ERR_INVALID_ARG, "out overlaps tensor without being equal to it");
+  }
   DeviceGuard dg(h->device);
   hipError_t e = ta::launch_tensor_inclusive(tensor, n_ranks * n_iters, h->G, h->d_rt, out,
                                              device_cus(h->device), (hipStream_t)stream);

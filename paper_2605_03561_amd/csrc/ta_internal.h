@@ -131,9 +131,8 @@ hipError_t launch_summary(const int64_t *excl, int64_t R, int N, const int2 *tin
 hipError_t launch_prune(const int64_t *sum_excl, const int64_t *sum_incl, int N, double fraction,
                         int32_t *kept, int32_t *n_kept, hipStream_t s);
 hipError_t launch_pruned_profiles(const int64_t *excl, int64_t R, int N, const int2 *tin_tout,
-                                  const int2 *kq, int K, const int32_t *koff,
-                                  const int32_t *kchild, int64_t *p_excl, int64_t *p_incl,
-                                  int cus, hipStream_t s);
+                                  const int2 *kq, int K, const int32_t *kpar, int64_t *p_excl,
+                                  int64_t *p_incl, int cus, hipStream_t s);
 hipError_t launch_tensor_inclusive(const int64_t *T, int64_t n_rows, int G, const int4 *rt,
                                    int64_t *out, int cus, hipStream_t s);
 

@@ -298,11 +298,16 @@ class Handle:
                                             _stream(self.device)))
         return pe, pi
 
-    def tensor_inclusive(self, tensor):
+    def tensor_inclusive(self, tensor, out=None):
+        """Inclusive form of `tensor`; `out` may be preallocated, or `tensor`
+        itself for an in-place update."""
         R, I, G = tensor.shape
         if G != self.n_regions:
             raise ValueError("tensor must have one column per region")
-        out = self._empty((R, I, G), torch.int64)
+        if out is None:
+            out = self._empty((R, I, G), torch.int64)
+        elif tuple(out.shape) != (R, I, G) or out.dtype != torch.int64:
+            raise ValueError("out must be an int64 tensor of the same shape")
         self._check(_lib.ta_tensor_inclusive(self.h, _ptr(tensor), R, I, _ptr(out),
                                              _stream(self.device)))
         return out

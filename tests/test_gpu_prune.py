@@ -188,6 +188,13 @@ def test_tensor_inclusive_matches_oracle(ta, h, oracle, G):
     assert np.array_equal(out, ref)
     empty = h.tensor_inclusive(dev(np.zeros((0, I, G), np.int64)).reshape(0, I, G))
     assert empty.shape == (0, I, G)
+    Td = dev(T)
+    h.tensor_inclusive(Td, out=Td)            # in place
+    assert np.array_equal(Td.cpu().numpy(), ref)
+    if G > 1:
+        flat = dev(np.zeros(R * I * G + 2, np.int64))
+        with pytest.raises(ta.TAError, match="overlaps"):   # shifted overlap is refused
+            h.tensor_inclusive(flat[:-2].view(R, I, G), out=flat[2:].view(R, I, G))
 
 
 def test_pruned_tree_model_end_to_end(ta, h, oracle):
