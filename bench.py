@@ -62,6 +62,27 @@ def read_traffic(workload: str, src_hash: str):
         return None
 
 
+def read_pruned_traffic():
+    """HBM bytes per launch of the pruned-model kernels from the committed
+    rocprofv3 counter summary, if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "pruned_model_c3.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    want = {f: hashlib.sha256(open(os.path.join(ROOT, "paper_2605_03561_amd", "csrc", f),
+                                   "rb").read()).hexdigest()[:12]
+            for f in ("k_prune.hip", "k_segment.hip")}
+    for f, hsh in want.items():
+        if f"- {f} sha256_12: {hsh}" not in txt:
+            return None
+    out = {}
+    for line in txt.splitlines():
+        if line.startswith("- hbm_bytes_per_launch "):
+            k, v = line[len("- hbm_bytes_per_launch "):].split(": ")
+            out[k] = float(v)
+    return out or None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,7 +297,10 @@ def pruned_model_summary(tr, excl, w, I, steps, fraction=0.01):
     ms, bytes_ = {}, {}
     ms["summary"], (se, si) = timed(lambda: h.summary(excl))
     bytes_["summary"] = 8 * R * N + 16 * N
-    ms["prune"], kept = timed(lambda: h.prune(se, si, fraction))
+    kept_buf = torch.empty((N,), dtype=torch.int32, device=excl.device)
+    n_buf = torch.empty((4,), dtype=torch.int32, device=excl.device)
+    ms["prune"], _ = timed(lambda: h.prune(se, si, fraction, out=(kept_buf, n_buf)))
+    kept = kept_buf[:int(n_buf[0].item())]
     K = len(kept)
     h.set_pruned(kept)
     ms["pruned_profiles"], _ = timed(lambda: h.pruned_profiles(excl))
@@ -300,7 +324,8 @@ def pruned_model_summary(tr, excl, w, I, steps, fraction=0.01):
     print(f"[bench] pruned model: {K} of {N} nodes kept; ms {ms}", file=sys.stderr, flush=True)
     return {"fraction": fraction, "n_nodes": N, "n_kept": K, "ms": ms,
             "algorithmic_bytes": bytes_, "achieved_gbs": gbs,
-            "hbm_frac": {k: v / HBM_PEAK_GBS for k, v in gbs.items()}}
+            "hbm_frac": {k: v / HBM_PEAK_GBS for k, v in gbs.items()},
+            "traffic": read_pruned_traffic()}
 
 
 def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9):

@@ -274,12 +274,22 @@ class Handle:
                                     _stream(self.device)))
         return se, si
 
-    def prune(self, sum_excl, sum_incl, fraction):
-        """Kept node ids (ascending, device int32); waits for the count."""
-        kept = self._empty((self.n_nodes,), torch.int32)
-        n = self._empty((4,), torch.int32)
+    def prune(self, sum_excl, sum_incl, fraction, out=None):
+        """Kept node ids (ascending, device int32); waits for the count.  With
+        out=(kept, n) (device int32 tensors of N and >= 1 entries) nothing is
+        waited for: the ids go to kept and their count stays in n[0]."""
+        if out is None:
+            kept = self._empty((self.n_nodes,), torch.int32)
+            n = self._empty((4,), torch.int32)
+        else:
+            kept, n = out
+            if kept.numel() < self.n_nodes or n.numel() < 1 or kept.dtype != torch.int32 \
+                    or n.dtype != torch.int32:
+                raise ValueError("out must be int32 tensors of N and >= 1 entries")
         self._check(_lib.ta_prune(self.h, _ptr(sum_excl), _ptr(sum_incl), float(fraction),
                                   _ptr(kept), _ptr(n), _stream(self.device)))
+        if out is not None:
+            return out
         return kept[:int(n[0].item())]
 
     def set_pruned(self, kept):
