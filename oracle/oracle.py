@@ -49,7 +49,11 @@ def lib():
         _lib.tao_prune.argtypes = [i32, P, P, f64, P, P]
         _lib.tao_pruned.argtypes = [i64, i32, P, P, i32, P, P, P]
         _lib.tao_tensor_inclusive.argtypes = [P, i64, i32, i32, i32, P, P, P]
-        for f in ("tao_summary", "tao_prune", "tao_pruned", "tao_tensor_inclusive"):
+        _lib.tao_kmeans.argtypes = [P, i64, i32, i32, P, i32, P, P, P, P]
+        _lib.tao_dbscan1d.argtypes = [P, i64, i64, i64, P, P, P]
+        _lib.tao_node_intersections.argtypes = [P, P, i64, i32, i32, P, P]
+        for f in ("tao_summary", "tao_prune", "tao_pruned", "tao_tensor_inclusive", "tao_kmeans",
+                  "tao_dbscan1d", "tao_node_intersections"):
             getattr(_lib, f).restype = C.c_int
         for f in ("tao_check_tree", "tao_attribute", "tao_segment", "tao_imbalance",
                   "tao_outliers", "tao_topology"):
@@ -185,3 +189,39 @@ def tensor_inclusive(T, parent, regions):
     out = np.zeros_like(T)
     st = lib().tao_tensor_inclusive(_p(T), R, I, G, len(parent), _p(parent), _p(regions), _p(out))
     return st, out
+
+
+def kmeans(X, C0, max_iter):
+    """-> (status, labels[R], centroids[K,D], counts[K], iterations run)"""
+    X = _arr(X, np.int64)
+    C0 = _arr(C0, np.float64)
+    R, D = X.shape
+    K = C0.shape[0]
+    labels = np.zeros(R, np.int32)
+    Cout = np.zeros((K, D), np.float64)
+    counts = np.zeros(K, np.int64)
+    n = C.c_int32(0)
+    st = lib().tao_kmeans(_p(X), R, D, K, _p(C0), int(max_iter), _p(labels), _p(Cout), _p(counts),
+                          C.byref(n))
+    return st, labels, Cout, counts, n.value
+
+
+def dbscan1d(x, eps, min_pts):
+    """-> (status, labels[R] (-1 noise), n_clusters, core[R])"""
+    x = _arr(x, np.int64)
+    R = len(x)
+    labels = np.zeros(R, np.int32)
+    core = np.zeros(R, np.uint8)
+    n = C.c_int32(0)
+    st = lib().tao_dbscan1d(_p(x), R, int(eps), int(min_pts), _p(labels), C.byref(n), _p(core))
+    return st, labels, n.value, core
+
+
+def node_intersections(labels, rank_node, n_nodes, K):
+    """-> (status, pair[K,K], node_clusters[n_nodes])"""
+    labels, rank_node = _arr(labels, np.int32), _arr(rank_node, np.int32)
+    pair = np.zeros((K, K), np.int64)
+    nc = np.zeros(n_nodes, np.int32)
+    st = lib().tao_node_intersections(_p(labels), _p(rank_node), len(labels), int(n_nodes), int(K),
+                                      _p(pair), _p(nc))
+    return st, pair, nc

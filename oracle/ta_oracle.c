@@ -738,3 +738,199 @@ int tao_tensor_inclusive(const int64_t *T, int64_t R, int32_t I, int32_t G, int3
   free(is_reg);
   return TAO_OK;
 }
+
+/* ---- Clustering of ranks (Sec. VI-B: DBSCAN over the ranks, K-Means with
+ * 2..5 groups, and the compute nodes whose ranks fall in two groups). ---- */
+
+/* K-Means (Lloyd) on integer feature rows X[R][D], K clusters from the given
+ * centroids C0[K][D].  An iteration assigns every row to the centroid with the
+ * smallest squared distance, summed over d in ascending order of
+ * ((double)x_d - c_d)^2 with every product and sum rounded (no fused
+ * multiply-add), ties to the smaller k; then each centroid becomes the mean of
+ * its rows, (double)(exact int64 sum) / count, and keeps its value when no row
+ * chose it.  Iterations stop after the first one in which no row changes
+ * cluster, or after max_iter.  Outputs: labels[R], C[K][D], counts[K],
+ * *n_iter (iterations run). */
+int tao_kmeans(const int64_t *X, int64_t R, int32_t D, int32_t K, const double *C0,
+               int32_t max_iter, int32_t *labels, double *C, int64_t *counts, int32_t *n_iter) {
+  if (R < 0 || D < 1 || K < 1 || max_iter < 1 || !C0 || !C || !n_iter || (R > 0 && (!X || !labels)))
+    return TAO_ERR_INVALID_ARG;
+  memcpy(C, C0, sizeof(double) * (size_t)K * (size_t)D);
+  int64_t *sum = (int64_t *)malloc(sizeof(int64_t) * (size_t)K * (size_t)D);
+  int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
+  if (!sum || !cnt) {
+    free(sum);
+    free(cnt);
+    return TAO_ERR_INVALID_ARG;
+  }
+  for (int64_t r = 0; r < R; r++) labels[r] = -1;
+  int32_t it = 0;
+  for (;;) {
+    it++;
+    int64_t changed = 0;
+    for (int64_t r = 0; r < R; r++) {
+      const int64_t *x = X + r * D;
+      int32_t best = 0;
+      double bestd = 0.0;
+      for (int32_t k = 0; k < K; k++) {
+        double dist = 0.0;
+        for (int32_t d = 0; d < D; d++) {
+          const double t = (double)x[d] - C[(size_t)k * D + d];
+          const double sq = t * t;
+          dist = dist + sq;
+        }
+        if (k == 0 || dist < bestd) {
+          best = k;
+          bestd = dist;
+        }
+      }
+      if (labels[r] != best) changed++;
+      labels[r] = best;
+    }
+    memset(sum, 0, sizeof(int64_t) * (size_t)K * (size_t)D);
+    memset(cnt, 0, sizeof(int64_t) * (size_t)K);
+    for (int64_t r = 0; r < R; r++) {
+      cnt[labels[r]]++;
+      for (int32_t d = 0; d < D; d++)
+        sum[(size_t)labels[r] * D + d] = (int64_t)((uint64_t)sum[(size_t)labels[r] * D + d] + (uint64_t)X[r * D + d]);
+    }
+    for (int32_t k = 0; k < K; k++)
+      if (cnt[k] > 0)
+        for (int32_t d = 0; d < D; d++)
+          C[(size_t)k * D + d] = (double)sum[(size_t)k * D + d] / (double)cnt[k];
+    if (changed == 0 || it >= max_iter) break;
+  }
+  if (counts)
+    for (int32_t k = 0; k < K; k++) counts[k] = cnt[k];
+  *n_iter = it;
+  free(sum);
+  free(cnt);
+  return TAO_OK;
+}
+
+typedef struct {
+  int64_t x;
+  int64_t i;
+} tao_xi;
+
+static int cmp_xi(const void *a, const void *b) {
+  const tao_xi *p = (const tao_xi *)a, *q = (const tao_xi *)b;
+  if (p->x != q->x) return p->x < q->x ? -1 : 1;
+  return p->i < q->i ? -1 : (p->i > q->i);
+}
+
+/* DBSCAN on one integer feature per row.  The neighbours of row i are the rows
+ * j with |x_j - x_i| <= eps (i itself included); i is a core row when it has
+ * at least min_pts neighbours.  Clusters are the connected components of the
+ * core rows under the neighbour relation, numbered 0, 1, ... by increasing
+ * value.  A non-core row with a core neighbour (a border row) joins the cluster
+ * of its nearest core neighbour, the smaller cluster number on a tie; any
+ * other row is noise (-1).  Works on the rows sorted by (value, index). */
+int tao_dbscan1d(const int64_t *x, int64_t R, int64_t eps, int64_t min_pts, int32_t *labels,
+                 int32_t *n_clusters, uint8_t *core) {
+  if (R < 0 || eps < 0 || min_pts < 1 || !n_clusters || (R > 0 && (!x || !labels)))
+    return TAO_ERR_INVALID_ARG;
+  *n_clusters = 0;
+  if (R == 0) return TAO_OK;
+  tao_xi *s = (tao_xi *)malloc(sizeof(tao_xi) * (size_t)R);
+  uint8_t *is_core = (uint8_t *)malloc((size_t)R);
+  int32_t *cl = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+  if (!s || !is_core || !cl) {
+    free(s);
+    free(is_core);
+    free(cl);
+    return TAO_ERR_INVALID_ARG;
+  }
+  for (int64_t i = 0; i < R; i++) {
+    s[i].x = x[i];
+    s[i].i = i;
+  }
+  qsort(s, (size_t)R, sizeof(tao_xi), cmp_xi);
+  /* neighbour counts by two pointers over the sorted values */
+  int64_t lo = 0, hi = 0;
+  for (int64_t j = 0; j < R; j++) {
+    while (s[lo].x < s[j].x - eps) lo++;
+    while (hi + 1 < R && s[hi + 1].x <= s[j].x + eps) hi++;
+    if (hi < j) hi = j;
+    is_core[j] = (hi - lo + 1) >= min_pts;
+  }
+  /* core rows: a new cluster starts where the previous core row is more than
+   * eps below */
+  int32_t c = -1;
+  int64_t prev = -1;
+  for (int64_t j = 0; j < R; j++) {
+    cl[j] = -1;
+    if (!is_core[j]) continue;
+    if (prev < 0 || s[j].x - s[prev].x > eps) c++;
+    cl[j] = c;
+    prev = j;
+  }
+  *n_clusters = c + 1;
+  /* border rows: nearest core on either side in sorted order (next_core[j] =
+   * the first core row after j, found by one backward pass) */
+  int64_t *next_core = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+  if (!next_core) {
+    free(s);
+    free(is_core);
+    free(cl);
+    return TAO_ERR_INVALID_ARG;
+  }
+  int64_t nc = -1;
+  for (int64_t j = R - 1; j >= 0; j--) {
+    next_core[j] = nc;
+    if (is_core[j]) nc = j;
+  }
+  int64_t left = -1;
+  for (int64_t j = 0; j < R; j++) {
+    if (is_core[j]) {
+      left = j;
+      continue;
+    }
+    const int64_t right = next_core[j];
+    const int64_t dl = left >= 0 ? s[j].x - s[left].x : INT64_MAX;
+    const int64_t dr = right >= 0 ? s[right].x - s[j].x : INT64_MAX;
+    if (dl <= eps && dl <= dr) cl[j] = cl[left];
+    else if (dr <= eps) cl[j] = cl[right];
+  }
+  for (int64_t j = 0; j < R; j++) {
+    labels[s[j].i] = cl[j];
+    if (core) core[s[j].i] = is_core[j];
+  }
+  free(next_core);
+  free(s);
+  free(is_core);
+  free(cl);
+  return TAO_OK;
+}
+
+/* Compute nodes shared by clusters: pair[a][b] (K x K, symmetric, zero
+ * diagonal) = number of compute nodes holding ranks of both cluster a and
+ * cluster b; node_clusters[n] = number of distinct clusters among node n's
+ * ranks.  Ranks labelled -1 are ignored. */
+int tao_node_intersections(const int32_t *labels, const int32_t *rank_node, int64_t R, int32_t n_nodes,
+                           int32_t K, int64_t *pair, int32_t *node_clusters) {
+  if (R < 0 || n_nodes < 1 || K < 1 || !pair || (R > 0 && (!labels || !rank_node)))
+    return TAO_ERR_INVALID_ARG;
+  uint8_t *has = (uint8_t *)calloc((size_t)n_nodes * (size_t)K, 1);
+  if (!has) return TAO_ERR_INVALID_ARG;
+  for (int64_t r = 0; r < R; r++) {
+    if (rank_node[r] < 0 || rank_node[r] >= n_nodes || labels[r] >= K) {
+      free(has);
+      return TAO_ERR_INVALID_ARG;
+    }
+    if (labels[r] >= 0) has[(size_t)rank_node[r] * K + labels[r]] = 1;
+  }
+  memset(pair, 0, sizeof(int64_t) * (size_t)K * (size_t)K);
+  for (int32_t n = 0; n < n_nodes; n++) {
+    int32_t c = 0;
+    for (int32_t a = 0; a < K; a++) {
+      if (!has[(size_t)n * K + a]) continue;
+      c++;
+      for (int32_t b = 0; b < K; b++)
+        if (b != a && has[(size_t)n * K + b]) pair[(size_t)a * K + b]++;
+    }
+    if (node_clusters) node_clusters[n] = c;
+  }
+  free(has);
+  return TAO_OK;
+}
