@@ -281,6 +281,49 @@ ta_status ta_pruned_profiles(ta_handle h, const int64_t *excl, int64_t n_ranks, 
 ta_status ta_tensor_inclusive(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
                               int64_t *out, void *stream);
 
+/* Clustering of ranks (Sec. VI-B: the ranks of one metric are clustered with
+ * DBSCAN and the groups mapped to compute nodes; K-Means with 2..5 groups is
+ * tested by the compute nodes whose ranks fall in two groups).
+ *
+ * K-Means (Lloyd) on integer feature rows X[n_rows][n_features] (e.g. the
+ * per-rank region totals), from the centroids init[k][n_features] (FP64,
+ * chosen by the caller).  An iteration assigns each row to the centroid with
+ * the smallest squared distance, summed over the features in ascending order
+ * with each product and sum rounded to FP64 (no fused multiply-add), ties to
+ * the smaller index; each centroid then becomes (double)(exact int64 sum of
+ * its rows) / count, and keeps its value when no row chose it.  Iterations stop
+ * after the first one in which no row changes cluster, or after max_iter.
+ * Outputs: labels[n_rows], centroids[k][n_features], counts[k] (optional),
+ * *n_iter (optional, device int32: iterations run).  Feature sums must fit in
+ * int64.  k <= 32, n_features <= 256, k * n_features <= 8192.  Device pointers;
+ * the host queues max_iter iterations without waiting (the ones after the stop
+ * return at once). */
+ta_status ta_kmeans(ta_handle h, const int64_t *X, int64_t n_rows, int32_t n_features, int32_t k,
+                    const double *init, int32_t max_iter, int32_t *labels, double *centroids,
+                    int64_t *counts, int32_t *n_iter, void *stream);
+
+/* DBSCAN on one integer feature per row (the metric's value per rank).  The
+ * neighbours of row i are the rows j with |x[j] - x[i]| <= eps (i included); i
+ * is a core row with at least min_pts neighbours.  Clusters are the connected
+ * components of the core rows under the neighbour relation, numbered 0, 1, ...
+ * by increasing value; a non-core row with a core neighbour joins the cluster
+ * of its nearest core neighbour (the smaller number on a tie); other rows are
+ * noise (-1).  Outputs labels[n_rows], *n_clusters (device int32), core[n_rows]
+ * (optional, 1 for core rows).  Values and eps must keep x +- eps and the
+ * differences of values inside int64.  Device pointers. */
+ta_status ta_dbscan1d(ta_handle h, const int64_t *x, int64_t n_rows, int64_t eps, int64_t min_pts,
+                      int32_t *labels, int32_t *n_clusters, uint8_t *core, void *stream);
+
+/* Compute nodes shared by clusters: pair[a][b] (k x k, symmetric, zero
+ * diagonal) = the number of compute nodes holding ranks of both cluster a and
+ * cluster b; node_clusters[n] (optional) = the number of distinct clusters
+ * among node n's ranks.  labels[n_ranks] in [-1, k) (-1 ignored),
+ * rank_node[n_ranks] in [0, n_nodes); other values are a sticky device error
+ * (TA_ERR_INVALID_ARG from ta_sync_status).  k <= 64.  Device pointers. */
+ta_status ta_node_intersections(ta_handle h, const int32_t *labels, const int32_t *rank_node,
+                                int64_t n_ranks, int32_t n_nodes, int32_t k, int64_t *pair,
+                                int32_t *node_clusters, void *stream);
+
 /* Batch plan: the whole batch in one HIP graph launch.
  * ta_plan_create orders the ranks longest first (so the longest traces start
  * first and the tail is short), picks the launch shape of the fused pass

@@ -869,6 +869,70 @@ ta_status ta_tensor_inclusive(ta_handle h, const int64_t *tensor, int64_t n_rank
   return TA_OK;
 }
 
+ta_status ta_kmeans(ta_handle h, const int64_t *X, int64_t n_rows, int32_t n_features, int32_t k,
+                    const double *init, int32_t max_iter, int32_t *labels, double *centroids,
+                    int64_t *counts, int32_t *n_iter, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (n_rows < 0 || n_features < 1 || k < 1 || max_iter < 1)
+    return fail(h, TA_ERR_INVALID_ARG, "bad sizes or max_iter");
+  if (k > 32 || n_features > 256 || k * n_features > 8192 || n_rows >= ((int64_t)1 << 31))
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "k <= 32, n_features <= 256, k * n_features <= 8192 and "
+                                         "n_rows < 2^31 are supported");
+  if (!init || !centroids || (n_rows > 0 && (!X || !labels)))
+    return fail(h, TA_ERR_INVALID_ARG, "X, init, labels and centroids are required");
+  const void *ptrs[] = {X, init, labels, centroids, counts, n_iter};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  DeviceGuard dg(h->device);
+  ta_status st = ensure_ws(h, ta::kmeans_ws_bytes(k, n_features));
+  if (st) return st;
+  hipError_t e = ta::launch_kmeans(X, n_rows, n_features, k, init, max_iter, labels, centroids,
+                                   counts, n_iter, h->ws, device_cus(h->device), (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "kmeans launch");
+  return TA_OK;
+}
+
+ta_status ta_dbscan1d(ta_handle h, const int64_t *x, int64_t n_rows, int64_t eps, int64_t min_pts,
+                      int32_t *labels, int32_t *n_clusters, uint8_t *core, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (n_rows < 0 || eps < 0 || min_pts < 1)
+    return fail(h, TA_ERR_INVALID_ARG, "n_rows >= 0, eps >= 0 and min_pts >= 1 are required");
+  if (n_rows >= ((int64_t)1 << 31)) return fail(h, TA_ERR_SIZE_OVERFLOW, "n_rows < 2^31 is supported");
+  if (!n_clusters || (n_rows > 0 && (!x || !labels)))
+    return fail(h, TA_ERR_INVALID_ARG, "x, labels and n_clusters are required");
+  const void *ptrs[] = {x, labels, n_clusters, core};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  DeviceGuard dg(h->device);
+  ta_status st = ensure_ws(h, ta::dbscan_ws_bytes(n_rows));
+  if (st) return st;
+  hipError_t e = ta::launch_dbscan1d(x, n_rows, eps, min_pts, labels, n_clusters, core, h->ws,
+                                     device_cus(h->device), (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "dbscan launch");
+  return TA_OK;
+}
+
+ta_status ta_node_intersections(ta_handle h, const int32_t *labels, const int32_t *rank_node,
+                                int64_t n_ranks, int32_t n_nodes, int32_t k, int64_t *pair,
+                                int32_t *node_clusters, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (n_ranks < 0 || n_nodes < 1 || k < 1) return fail(h, TA_ERR_INVALID_ARG, "bad sizes");
+  if (k > 64) return fail(h, TA_ERR_SIZE_OVERFLOW, "at most 64 clusters are supported");
+  if (!pair || (n_ranks > 0 && (!labels || !rank_node)))
+    return fail(h, TA_ERR_INVALID_ARG, "labels, rank_node and pair are required");
+  const void *ptrs[] = {labels, rank_node, pair, node_clusters};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  DeviceGuard dg(h->device);
+  ta_status st = ensure_ws(h, ta::node_intersections_ws_bytes(n_nodes));
+  if (st) return st;
+  hipError_t e = ta::launch_node_intersections(labels, rank_node, n_ranks, n_nodes, k, pair,
+                                               node_clusters, h->ws, h->d_err, device_cus(h->device),
+                                               (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "node intersections launch");
+  return TA_OK;
+}
+
 ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets_host,
                          const ta_batch_desc *d, ta_plan *out, void *stream) {
   if (!h) return TA_ERR_INVALID_ARG;

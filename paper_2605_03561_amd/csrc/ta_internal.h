@@ -136,6 +136,20 @@ hipError_t launch_pruned_profiles(const int64_t *excl, int64_t R, int N, const i
 hipError_t launch_tensor_inclusive(const int64_t *T, int64_t n_rows, int G, const int4 *rt,
                                    int64_t *out, int cus, hipStream_t s);
 
+// Clustering of ranks (k_cluster.hip).
+size_t kmeans_ws_bytes(int K, int D);
+hipError_t launch_kmeans(const int64_t *X, int64_t R, int D, int K, const double *C0, int max_iter,
+                         int32_t *labels, double *C, int64_t *counts, int32_t *n_iter, void *ws,
+                         int cus, hipStream_t s);
+size_t dbscan_ws_bytes(int64_t R);
+hipError_t launch_dbscan1d(const int64_t *x, int64_t R, int64_t eps, int64_t min_pts,
+                           int32_t *labels, int32_t *n_clusters, uint8_t *core, void *ws, int cus,
+                           hipStream_t s);
+size_t node_intersections_ws_bytes(int32_t n_nodes);
+hipError_t launch_node_intersections(const int32_t *labels, const int32_t *rank_node, int64_t R,
+                                     int32_t n_nodes, int K, int64_t *pair, int32_t *node_clusters,
+                                     void *ws, uint32_t *err, int cus, hipStream_t s);
+
 struct TopoArgs {
   const double *score;
   const uint8_t *flag;

@@ -87,6 +87,9 @@ def _load():
         "ta_set_pruned": [P, i32, P],
         "ta_pruned_profiles": [P, P, i64, P, P, P],
         "ta_tensor_inclusive": [P, P, i64, i32, P, P],
+        "ta_kmeans": [P, P, i64, i32, i32, P, i32, P, P, P, P, P],
+        "ta_dbscan1d": [P, P, i64, i64, i64, P, P, P, P],
+        "ta_node_intersections": [P, P, P, i64, i32, i32, P, P, P],
         "ta_plan_create": [P, P, P, P, P, P],
         "ta_plan_launch": [P, P],
         "ta_plan_info": [P, P, P, P, P, P],
@@ -321,6 +324,45 @@ class Handle:
         self._check(_lib.ta_tensor_inclusive(self.h, _ptr(tensor), R, I, _ptr(out),
                                              _stream(self.device)))
         return out
+
+    # -- clustering of ranks ---------------------------------------------------
+    def kmeans(self, X, init, max_iter=100):
+        """Lloyd K-Means on int64 rows X [R, D] from FP64 centroids init [K, D];
+        returns device (labels, centroids, counts, n_iter[1])."""
+        R, D = X.shape
+        K = init.shape[0]
+        if X.dtype != torch.int64 or init.dtype != torch.float64 or init.shape[1] != D:
+            raise ValueError("X must be int64 [R, D] and init float64 [K, D]")
+        labels = self._empty((R,), torch.int32)
+        Cc = self._empty((K, D), torch.float64)
+        counts = self._empty((K,), torch.int64)
+        n = self._empty((4,), torch.int32)
+        self._check(_lib.ta_kmeans(self.h, _ptr(X), R, D, K, _ptr(init), int(max_iter), _ptr(labels),
+                                   _ptr(Cc), _ptr(counts), _ptr(n), _stream(self.device)))
+        return labels, Cc, counts, n[:1]
+
+    def dbscan1d(self, x, eps, min_pts):
+        """DBSCAN on int64 values x [R]; returns device (labels, n_clusters[1], core)."""
+        R = x.shape[0]
+        if x.dtype != torch.int64 or x.dim() != 1:
+            raise ValueError("x must be a 1-D int64 tensor")
+        labels = self._empty((R,), torch.int32)
+        core = self._empty((R,), torch.uint8)
+        n = self._empty((4,), torch.int32)
+        self._check(_lib.ta_dbscan1d(self.h, _ptr(x), R, int(eps), int(min_pts), _ptr(labels),
+                                     _ptr(n), _ptr(core), _stream(self.device)))
+        return labels, n[:1], core
+
+    def node_intersections(self, labels, rank_node, n_nodes, k):
+        """Per pair of clusters, the compute nodes holding ranks of both;
+        returns device (pair [k, k] int64, node_clusters [n_nodes] int32)."""
+        R = labels.shape[0]
+        pair = self._empty((k, k), torch.int64)
+        nc = self._empty((n_nodes,), torch.int32)
+        self._check(_lib.ta_node_intersections(self.h, _ptr(labels), _ptr(rank_node), R,
+                                               int(n_nodes), int(k), _ptr(pair), _ptr(nc),
+                                               _stream(self.device)))
+        return pair, nc
 
     # -- statistics ----------------------------------------------------------
     def imbalance(self, tensor, iters_found=None, rank_sum=None, rank_sumsq=None, span=None,

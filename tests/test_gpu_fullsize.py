@@ -185,6 +185,43 @@ def test_c3_pruned_model(mods, oracle, c3):
         torch.cuda.empty_cache()
 
 
+def test_c3_clustering(mods, oracle, c3):
+    """Clustering of the 100k ranks against the oracle on the whole batch:
+    K-Means (K = 6) on the per-rank region totals, DBSCAN on each rank's total
+    time over the regions, and the compute nodes shared by the clusters."""
+    torch, gpu_synth, ta = mods
+    from paper_2605_03561_amd import synth
+    w, h, seg, cfg = c3
+    S = seg["rank_sum"].cpu().numpy()
+    R = S.shape[0]
+    rng = np.random.default_rng(9)
+    C0 = S[rng.choice(R, 6, replace=False)].astype(np.float64)
+    print("[fullsize] kmeans", flush=True)
+    gl, gc, gn, gi = h.kmeans(seg["rank_sum"], torch.from_numpy(C0).cuda(), 50)
+    st, lab, Cc, cnt, it = oracle.kmeans(S, C0, 50)
+    assert st == 0 and int(gi.item()) == it
+    assert np.array_equal(gl.cpu().numpy(), lab)
+    assert np.array_equal(gc.cpu().numpy(), Cc)
+    assert np.array_equal(gn.cpu().numpy(), cnt)
+    print("[fullsize] dbscan", flush=True)
+    tot = seg["rank_sum"].sum(1)
+    t = tot.cpu().numpy()
+    eps = int(np.median(t) // 2000)
+    dl, dn, dc = h.dbscan1d(tot, eps, 100)
+    st, dlab, n, core = oracle.dbscan1d(t, eps, 100)
+    assert st == 0 and int(dn.item()) == n
+    assert np.array_equal(dl.cpu().numpy(), dlab)
+    assert np.array_equal(dc.cpu().numpy(), core)
+    rank_node, _, _ = synth.topology(0, R)
+    n_nodes = int(rank_node.max()) + 1
+    rn = torch.from_numpy(rank_node).cuda()
+    for labels_d, labels_h, k in ((gl, lab, 6), (dl, dlab, max(n, 1))):
+        gp, gnc = h.node_intersections(labels_d, rn, n_nodes, k)
+        st, pair, nc = oracle.node_intersections(labels_h, rank_node, n_nodes, k)
+        assert np.array_equal(gp.cpu().numpy(), pair) and np.array_equal(gnc.cpu().numpy(), nc)
+    h.sync_status()
+
+
 def test_c2_shape_full_parity(mods, oracle):
     torch, gpu_synth, ta = mods
     w = gpu_synth.timeline_on_gpu(seed=4, n_ranks=3000, median_len=6000, min_len=1000,
