@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the pruned-tree model leg (summary, pruning at 1%%, pruned "
                          "profiles, kept-node tensor and its inclusive form)")
+    ap.add_argument("--no-clustering", action="store_true",
+                    help="skip the clustering leg (K-Means on the per-rank region totals, DBSCAN "
+                         "on the per-rank totals, compute nodes shared by the clusters)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
@@ -210,6 +213,9 @@ def main():
     # column-major copy) before the pruned-tree leg, which needs the traces,
     # the exclusive profiles and two rank x iteration x kept-node tensors.
     excl = seg["excl"]
+    clus = None
+    if not args.no_clustering:
+        clus = clustering_summary(h, seg["rank_sum"], rank_node_d, args.steps, args.seed)
     fused.close()
     del fused, seg, o
     h.close()
@@ -262,8 +268,70 @@ def main():
         "prescreen": pre,
         "mixed_batch": mixed,
         "pruned_model": pruned,
+        "clustering": clus,
     }
     print(json.dumps(line))
+
+
+def clustering_summary(h, rank_sum, rank_node, steps, seed, k=6, max_iter=50, min_pts=100):
+    """Clustering of the batch's ranks (Sec. VI-B's six groups): K-Means with k
+    clusters on the per-rank region totals S[r, :] from k seeded rows, DBSCAN
+    on each rank's total over the regions (eps = median / 2000, min_pts = one
+    compute node's ranks), and the compute nodes shared by the clusters.  Each
+    stage is timed with HIP events on the launch stream over `steps` calls."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    R, D = rank_sum.shape
+    rng = np.random.default_rng([11, seed])
+    init = rank_sum[torch.from_numpy(np.sort(rng.choice(R, k, replace=False))).to(rank_sum.device)]
+    init = init.to(torch.float64).contiguous()
+    tot = rank_sum.sum(1).contiguous()
+    eps = int(tot.median().item()) // 2000
+    n_nodes = int(rank_node.max().item()) + 1
+
+    def timed(fn):
+        res = fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(stream)
+        for j in range(steps):
+            res = fn()
+            ev[j + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[j].elapsed_time(ev[j + 1]) for j in range(steps)])), res
+
+    ms = {}
+    ms["kmeans"], (lab, cent, cnt, n_it) = timed(lambda: h.kmeans(rank_sum, init, max_iter))
+    ms["dbscan"], (dl, dn, dc) = timed(lambda: h.dbscan1d(tot, eps, min_pts))
+    n_db = int(dn.item())
+    ms["node_intersections"], (pair, nc) = timed(
+        lambda: h.node_intersections(lab, rank_node, n_nodes, k))
+    h.sync_status()
+    it = int(n_it.item())
+    # algorithmic bytes: per K-Means iteration the rows and labels; DBSCAN the
+    # values in and labels + core flags out; intersections labels + placement
+    b_km_iter = 8 * R * D + 8 * R
+    b_db = 8 * R + 5 * R
+    b_ni = 8 * R + 8 * n_nodes + 8 * k * k
+    per_iter = ms["kmeans"] / it
+    shared = int((nc > 1).sum().item())
+    out = {"workload": f"{R} ranks x {D} region totals; k = {k}, max_iter = {max_iter}; DBSCAN on "
+                       f"the per-rank totals, eps = {eps} ns, min_pts = {min_pts}; {n_nodes} "
+                       f"placement ids",
+           "ms": ms, "kmeans_iterations": it, "kmeans_ms_per_iteration": per_iter,
+           "kmeans_counts": cnt.cpu().tolist(), "dbscan_clusters": n_db,
+           "dbscan_noise": int((dl < 0).sum().item()),
+           "kmeans_nodes_in_two_or_more_clusters": shared,
+           "algorithmic_bytes": {"kmeans_per_iteration": b_km_iter, "dbscan": b_db,
+                                 "node_intersections": b_ni},
+           "achieved_gbs": {"kmeans_per_iteration": b_km_iter / (per_iter / 1e3) / 1e9,
+                            "dbscan": b_db / (ms["dbscan"] / 1e3) / 1e9,
+                            "node_intersections": b_ni / (ms["node_intersections"] / 1e3) / 1e9}}
+    out["hbm_frac"] = {kk: v / HBM_PEAK_GBS for kk, v in out["achieved_gbs"].items()}
+    print(f"[bench] clustering: {out['ms']}, {it} K-Means iterations, {n_db} DBSCAN clusters",
+          file=sys.stderr, flush=True)
+    return out
 
 
 def pruned_model_summary(tr, excl, w, I, steps, fraction=0.01):

@@ -295,7 +295,7 @@ ta_status ta_tensor_inclusive(ta_handle h, const int64_t *tensor, int64_t n_rank
  * after the first one in which no row changes cluster, or after max_iter.
  * Outputs: labels[n_rows], centroids[k][n_features], counts[k] (optional),
  * *n_iter (optional, device int32: iterations run).  Feature sums must fit in
- * int64.  k <= 32, n_features <= 256, k * n_features <= 8192.  Device pointers;
+ * int64.  k <= 32, n_features <= 256, k * n_features <= 5632.  Device pointers;
  * the host queues max_iter iterations without waiting (the ones after the stop
  * return at once). */
 ta_status ta_kmeans(ta_handle h, const int64_t *X, int64_t n_rows, int32_t n_features, int32_t k,

@@ -19,63 +19,120 @@ constexpr uint64_t SIGN = 0x8000000000000000ull;
 struct KmState {
   int32_t done;
   int32_t it;
-  uint64_t changed;
 };
 
+// Workgroup partials go to one of KS slots (workgroup b to slot b mod KS):
+// the integer sums do not depend on the order, and spreading them keeps the
+// device-scope atomics on one address few.
+constexpr int KS = 32;
+
+// sum[KS][K*D], cnt[KS][K], chg[KS]
 __global__ void km_init(const double *C0, double *C, int KD, int32_t *labels, int64_t R,
-                        int64_t *sum, int64_t *cnt, int K, KmState *st) {
+                        int64_t *sum, int64_t *cnt, uint64_t *chg, int K, KmState *st) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = tid; i < KD; i += n) {
-    C[i] = C0[i];
-    sum[i] = 0;
-  }
-  for (int64_t i = tid; i < K; i += n) cnt[i] = 0;
+  for (int64_t i = tid; i < KD; i += n) C[i] = C0[i];
+  for (int64_t i = tid; i < (int64_t)KS * KD; i += n) sum[i] = 0;
+  for (int64_t i = tid; i < (int64_t)KS * K; i += n) cnt[i] = 0;
+  for (int64_t i = tid; i < KS; i += n) chg[i] = 0;
   for (int64_t r = tid; r < R; r += n) labels[r] = -1;
   if (tid == 0) {
     st->done = 0;
     st->it = 0;
-    st->changed = 0;
   }
 }
 
-// Assignment: thread = row (grid-stride); the distances to all centroids are
-// accumulated in registers, feature by feature in ascending order, so each is
-// the same FP64 sum as the definition's.  Rows then add their features to the
-// workgroup's exact int64 cluster sums in LDS, flushed once per workgroup.
-template <int KMAX>
-__global__ __launch_bounds__(KT) void km_assign(const int64_t *__restrict__ X, int64_t R, int D,
+constexpr int KW = 256;  // threads of the K-Means assignment
+constexpr int FB = 16;   // features loaded per batch
+constexpr int DREG = 64; // features a row keeps in registers
+
+// Xt[d][r] = X[r][d], once per call (64 x 64 tiles through LDS, both sides
+// coalesced), so that the iterations read a feature of 64 consecutive rows
+// with one contiguous 512-byte access.
+__global__ __launch_bounds__(KT) void km_transpose(const int64_t *__restrict__ X, int64_t R, int D,
+                                                  int64_t *__restrict__ Xt) {
+  __shared__ int64_t tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int d0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  for (int i = ty; i < 64; i += KT / 64) {
+    const int64_t r = r0 + i;
+    const int d = d0 + tx;
+    tile[i][tx] = (r < R && d < D) ? X[r * D + d] : 0;
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += KT / 64) {
+    const int d = d0 + i;
+    const int64_t r = r0 + tx;
+    if (d < D && r < R) Xt[(int64_t)d * R + r] = tile[tx][i];
+  }
+}
+
+// Assignment: thread = row (grid-stride) over the transposed rows: feature d
+// of 64 consecutive rows is one contiguous access.  With exactly DREG features
+// (REG, a compile-time width) the whole row is loaded in one batch (one memory
+// round trip: a batch of 100k rows is only a few waves per SIMD, so latency,
+// not bandwidth, bounds this kernel) and stays in registers; otherwise it
+// arrives FB features at a time and is read again for the sums.  The features are added, in ascending
+// order, to the row's distances to all centroids, kept in registers: the same
+// FP64 sums as the definition's; then to the workgroup's exact int64 cluster
+// sums in LDS, flushed once per workgroup.
+template <int KMAX, bool REG>
+__global__ __launch_bounds__(KW) void km_assign(const int64_t *__restrict__ Xt, int64_t R, int D_,
                                                int K, const double *__restrict__ C,
                                                int32_t *__restrict__ labels, int64_t *sum,
-                                               int64_t *cnt, KmState *st) {
+                                               int64_t *cnt, uint64_t *chg, KmState *st) {
   if (st->done) return;
+  const int D = REG ? DREG : D_;
   extern __shared__ uint64_t lds[];
-  double *Cs = reinterpret_cast<double *>(lds);        // [K][D]
-  uint64_t *Ss = lds + (size_t)K * D;                  // [K][D]
-  uint64_t *Ns = Ss + (size_t)K * D;                   // [K]
+  // centroids as [D][KMAX], so that feature d, centroid k sits at a fixed
+  // offset from d's row (an immediate when d is unrolled)
+  double *Cs = reinterpret_cast<double *>(lds);  // [D][KMAX]
+  uint64_t *Ss = lds + (size_t)D * KMAX;         // [K][D]
+  uint64_t *Ns = Ss + (size_t)K * D;             // [K]
   __shared__ uint32_t nchg;
-  for (int i = threadIdx.x; i < K * D; i += KT) {
-    Cs[i] = C[i];
-    Ss[i] = 0;
+  for (int i = threadIdx.x; i < D * KMAX; i += KW) {
+    const int d = i / KMAX, k = i % KMAX;
+    Cs[i] = k < K ? C[k * D + d] : 0.0;
   }
-  for (int i = threadIdx.x; i < K; i += KT) Ns[i] = 0;
+  for (int i = threadIdx.x; i < K * D; i += KW) Ss[i] = 0;
+  for (int i = threadIdx.x; i < K; i += KW) Ns[i] = 0;
   if (threadIdx.x == 0) nchg = 0;
   __syncthreads();
   uint32_t my_chg = 0;
-  for (int64_t r = (int64_t)blockIdx.x * KT + threadIdx.x; r < R; r += (int64_t)gridDim.x * KT) {
-    const int64_t *x = X + r * D;
+  for (int64_t r = (int64_t)blockIdx.x * KW + threadIdx.x; r < R; r += (int64_t)gridDim.x * KW) {
     double dist[KMAX];
 #pragma unroll
     for (int k = 0; k < KMAX; k++) dist[k] = 0.0;
-    for (int d = 0; d < D; d++) {
-      const double xd = (double)x[d];
+    // all KMAX slots, without a branch per centroid (slots k >= K hold zeros
+    // and never enter the choice below)
+    auto add_feature = [&](int d, int64_t xv) {
+      const double xd = (double)xv;
 #pragma unroll
-      for (int k = 0; k < KMAX; k++)
-        if (k < K) {
-          const double t = xd - Cs[k * D + d];
-          const double sq = t * t;
-          dist[k] = dist[k] + sq;
-        }
+      for (int k = 0; k < KMAX; k++) {
+        const double t = xd - Cs[d * KMAX + k];
+        const double sq = t * t;
+        dist[k] = dist[k] + sq;
+      }
+    };
+    int64_t v[REG ? DREG : FB];
+    if (REG) {
+      const int64_t *p = Xt + r;
+#pragma unroll
+      for (int d = 0; d < DREG; d++) {
+        v[d] = *p;
+        p += R;
+      }
+#pragma unroll
+      for (int d = 0; d < DREG; d++) add_feature(d, v[d]);
+    } else {
+      for (int d0 = 0; d0 < D; d0 += FB) {
+#pragma unroll
+        for (int u = 0; u < FB; u++) v[u] = d0 + u < D ? Xt[(int64_t)(d0 + u) * R + r] : 0;
+#pragma unroll
+        for (int u = 0; u < FB; u++)
+          if (d0 + u < D) add_feature(d0 + u, v[u]);
+      }
     }
     int best = 0;
     double bd = dist[0];
@@ -87,41 +144,75 @@ __global__ __launch_bounds__(KT) void km_assign(const int64_t *__restrict__ X, i
       }
     if (labels[r] != best) my_chg++;
     labels[r] = best;
-    for (int d = 0; d < D; d++)
-      atomicAdd((unsigned long long *)&Ss[best * D + d], (unsigned long long)x[d]);
     atomicAdd((unsigned long long *)&Ns[best], 1ull);
+    if (REG) {
+#pragma unroll
+      for (int d = 0; d < DREG; d++)
+        atomicAdd((unsigned long long *)&Ss[best * DREG + d], (unsigned long long)v[d]);
+    } else {
+      for (int d0 = 0; d0 < D; d0 += FB) {
+#pragma unroll
+        for (int u = 0; u < FB; u++) v[u] = d0 + u < D ? Xt[(int64_t)(d0 + u) * R + r] : 0;
+#pragma unroll
+        for (int u = 0; u < FB; u++)
+          if (d0 + u < D) atomicAdd((unsigned long long *)&Ss[best * D + d0 + u], (unsigned long long)v[u]);
+      }
+    }
   }
   if (my_chg) atomicAdd(&nchg, my_chg);
   __syncthreads();
-  for (int i = threadIdx.x; i < K * D; i += KT)
-    if (Ss[i]) atomicAdd((unsigned long long *)&sum[i], (unsigned long long)Ss[i]);
-  for (int i = threadIdx.x; i < K; i += KT)
-    if (Ns[i]) atomicAdd((unsigned long long *)&cnt[i], (unsigned long long)Ns[i]);
-  if (threadIdx.x == 0 && nchg) atomicAdd((unsigned long long *)&st->changed, (unsigned long long)nchg);
+  const int slot = blockIdx.x % KS;
+  int64_t *sum_s = sum + (size_t)slot * K * D;
+  int64_t *cnt_s = cnt + (size_t)slot * K;
+  for (int i = threadIdx.x; i < K * D; i += KW)
+    if (Ss[i]) atomicAdd((unsigned long long *)&sum_s[i], (unsigned long long)Ss[i]);
+  for (int i = threadIdx.x; i < K; i += KW)
+    if (Ns[i]) atomicAdd((unsigned long long *)&cnt_s[i], (unsigned long long)Ns[i]);
+  if (threadIdx.x == 0 && nchg) atomicAdd((unsigned long long *)&chg[slot], (unsigned long long)nchg);
 }
 
-// Update: centroid = (double)(exact sum) / count, unchanged when the cluster
-// is empty; clears the sums for the next iteration and decides whether to stop.
+// Update (one workgroup, after the assignment kernel: the kernel boundary
+// makes the sums visible): centroid = (double)(exact sum) / count, unchanged
+// when the cluster is empty; clear the sums; stop after an iteration without
+// change or after max_iter.
 __global__ __launch_bounds__(KT) void km_update(int K, int D, int max_iter, double *C, int64_t *sum,
-                                               int64_t *cnt, int64_t *counts, int32_t *n_iter,
-                                               KmState *st) {
+                                               int64_t *cnt, uint64_t *chg, int64_t *counts,
+                                               int32_t *n_iter, KmState *st) {
   if (st->done) return;
-  for (int i = threadIdx.x; i < K * D; i += KT) {
-    const int64_t n = cnt[i / D];
-    if (n > 0) C[i] = (double)sum[i] / (double)n;
-    sum[i] = 0;
+  __shared__ int64_t n_k[32];
+  __shared__ uint64_t changed;
+  for (int k = threadIdx.x; k < K; k += KT) {
+    int64_t n = 0;
+    for (int s = 0; s < KS; s++) {
+      n += cnt[(size_t)s * K + k];
+      cnt[(size_t)s * K + k] = 0;
+    }
+    n_k[k] = n;
+    if (counts) counts[k] = n;
+  }
+  if (threadIdx.x == 0) {
+    uint64_t c = 0;
+    for (int s = 0; s < KS; s++) {
+      c += chg[s];
+      chg[s] = 0;
+    }
+    changed = c;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < K; i += KT) {
-    if (counts) counts[i] = cnt[i];
-    cnt[i] = 0;
+  for (int i = threadIdx.x; i < K * D; i += KT) {
+    uint64_t sm = 0;
+    for (int s = 0; s < KS; s++) {
+      sm += (uint64_t)sum[(size_t)s * K * D + i];
+      sum[(size_t)s * K * D + i] = 0;
+    }
+    const int64_t n = n_k[i / D];
+    if (n > 0) C[i] = (double)(int64_t)sm / (double)n;
   }
   if (threadIdx.x == 0) {
     const int it = st->it + 1;
     st->it = it;
     if (n_iter) *n_iter = it;
-    if (st->changed == 0 || it >= max_iter) st->done = 1;
-    st->changed = 0;
+    if (changed == 0 || it >= max_iter) st->done = 1;
   }
 }
 
@@ -435,33 +526,49 @@ int grid_of(int64_t n, int cus) {
 
 }  // namespace
 
-size_t kmeans_ws_bytes(int K, int D) {
-  return ((size_t)K * D + K) * sizeof(int64_t) + 64;
+static size_t km_state_bytes(int K, int D) {
+  return (((size_t)KS * K * D + (size_t)KS * K + KS) * sizeof(int64_t) + 64 + 255) / 256 * 256;
+}
+
+size_t kmeans_ws_bytes(int K, int D, int64_t R) {
+  return km_state_bytes(K, D) + (size_t)R * D * sizeof(int64_t);
 }
 
 hipError_t launch_kmeans(const int64_t *X, int64_t R, int D, int K, const double *C0, int max_iter,
                          int32_t *labels, double *C, int64_t *counts, int32_t *n_iter, void *ws,
                          int cus, hipStream_t s) {
   int64_t *sum = (int64_t *)ws;
-  int64_t *cnt = sum + (size_t)K * D;
-  KmState *st = (KmState *)(cnt + K);
-  km_init<<<grid_of(R > K * D ? R : K * D, cus), KT, 0, s>>>(C0, C, K * D, labels, R, sum, cnt, K, st);
-  const size_t lds = ((size_t)2 * K * D + K) * sizeof(uint64_t);
+  int64_t *cnt = sum + (size_t)KS * K * D;
+  uint64_t *chg = (uint64_t *)(cnt + (size_t)KS * K);
+  KmState *st = (KmState *)(chg + KS);
+  int64_t *Xt = (int64_t *)((char *)ws + km_state_bytes(K, D));
+  km_init<<<grid_of(R > KS * K * D ? R : KS * K * D, cus), KT, 0, s>>>(C0, C, K * D, labels, R, sum,
+                                                                       cnt, chg, K, st);
+  if (R > 0) km_transpose<<<dim3((unsigned)((R + 63) / 64), (unsigned)((D + 63) / 64)), KT, 0, s>>>(X, R, D, Xt);
+  const size_t lds = ((size_t)D * (K <= 8 ? 8 : 32) + (size_t)K * D + K) * sizeof(uint64_t);
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&km_assign<8>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&km_assign<32>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    const void *fns[] = {reinterpret_cast<const void *>(&km_assign<8, true>),
+                         reinterpret_cast<const void *>(&km_assign<8, false>),
+                         reinterpret_cast<const void *>(&km_assign<32, false>)};
+    for (const void *f : fns)
+      (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     attr = true;
   }
-  const int grid = grid_of(R, cus);
+  // a row per thread; at most 8 workgroups per CU
+  int64_t grid = (R + KW - 1) / KW;
+  if (grid > (int64_t)cus * 8) grid = (int64_t)cus * 8;
+  if (grid < 1) grid = 1;
+  // the register-resident row for the usual width (64 region totals, K <= 8)
+  const bool reg = D == DREG && K <= 8;
   for (int it = 0; it < max_iter; it++) {
-    if (K <= 8)
-      km_assign<8><<<grid, KT, lds, s>>>(X, R, D, K, C, labels, sum, cnt, st);
+    if (reg)
+      km_assign<8, true><<<(int)grid, KW, lds, s>>>(Xt, R, D, K, C, labels, sum, cnt, chg, st);
+    else if (K <= 8)
+      km_assign<8, false><<<(int)grid, KW, lds, s>>>(Xt, R, D, K, C, labels, sum, cnt, chg, st);
     else
-      km_assign<32><<<grid, KT, lds, s>>>(X, R, D, K, C, labels, sum, cnt, st);
-    km_update<<<1, KT, 0, s>>>(K, D, max_iter, C, sum, cnt, counts, n_iter, st);
+      km_assign<32, false><<<(int)grid, KW, lds, s>>>(Xt, R, D, K, C, labels, sum, cnt, chg, st);
+    km_update<<<1, KT, 0, s>>>(K, D, max_iter, C, sum, cnt, chg, counts, n_iter, st);
   }
   return hipGetLastError();
 }

@@ -875,8 +875,8 @@ ta_status ta_kmeans(ta_handle h, const int64_t *X, int64_t n_rows, int32_t n_fea
   if (!h) return TA_ERR_INVALID_ARG;
   if (n_rows < 0 || n_features < 1 || k < 1 || max_iter < 1)
     return fail(h, TA_ERR_INVALID_ARG, "bad sizes or max_iter");
-  if (k > 32 || n_features > 256 || k * n_features > 8192 || n_rows >= ((int64_t)1 << 31))
-    return fail(h, TA_ERR_SIZE_OVERFLOW, "k <= 32, n_features <= 256, k * n_features <= 8192 and "
+  if (k > 32 || n_features > 256 || k * n_features > 5632 || n_rows >= ((int64_t)1 << 31))
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "k <= 32, n_features <= 256, k * n_features <= 5632 and "
                                          "n_rows < 2^31 are supported");
   if (!init || !centroids || (n_rows > 0 && (!X || !labels)))
     return fail(h, TA_ERR_INVALID_ARG, "X, init, labels and centroids are required");
@@ -884,7 +884,7 @@ ta_status ta_kmeans(ta_handle h, const int64_t *X, int64_t n_rows, int32_t n_fea
   for (const void *p : ptrs)
     if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
   DeviceGuard dg(h->device);
-  ta_status st = ensure_ws(h, ta::kmeans_ws_bytes(k, n_features));
+  ta_status st = ensure_ws(h, ta::kmeans_ws_bytes(k, n_features, n_rows));
   if (st) return st;
   hipError_t e = ta::launch_kmeans(X, n_rows, n_features, k, init, max_iter, labels, centroids,
                                    counts, n_iter, h->ws, device_cus(h->device), (hipStream_t)stream);

@@ -137,7 +137,7 @@ hipError_t launch_tensor_inclusive(const int64_t *T, int64_t n_rows, int G, cons
                                    int64_t *out, int cus, hipStream_t s);
 
 // Clustering of ranks (k_cluster.hip).
-size_t kmeans_ws_bytes(int K, int D);
+size_t kmeans_ws_bytes(int K, int D, int64_t R);
 hipError_t launch_kmeans(const int64_t *X, int64_t R, int D, int K, const double *C0, int max_iter,
                          int32_t *labels, double *C, int64_t *counts, int32_t *n_iter, void *ws,
                          int cus, hipStream_t s);
