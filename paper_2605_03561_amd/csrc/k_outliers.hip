@@ -102,7 +102,7 @@ constexpr int BPT = NB / CS;      // bins per thread in the bin search
 
 __device__ inline uint64_t shr64(uint64_t x, int s) { return s >= 64 ? 0 : x >> s; }
 
-constexpr int MS = 1024;          // sample slots (LDS)
+constexpr int MS = 2048;          // sample slots (LDS)
 constexpr int SEL_GRID_MAX = 2048; // column workgroups (persistent, one scratch slot each)
 constexpr int64_t SEL_BRACKET_MIN_RP = 32768;  // shorter columns: whole-column radix selection
 
@@ -121,7 +121,8 @@ struct ColSelLds : SelLds {
 };
 
 // Scratch slot per column workgroup: the values inside a bracket (expected
-// about 2 * 5 / sqrt(1024) = 31 % of the column).
+// about 2 * 2.25 / sqrt(2048) = 10 % of the column; the cap leaves room for
+// skewed or tied columns).
 __host__ __device__ inline int64_t sel_cap(int64_t R) {
   const int64_t Rp = pad_ranks(R);
   int64_t c = ((Rp * 45 / 100) + 63) & ~(int64_t)63;
@@ -379,14 +380,17 @@ __device__ void sample_pick(ColSelLds &L, int m, int64_t j1, int64_t j2, int64_t
 }
 
 // Bracket [lo, hi] around the middle of the sample (m values): its order
-// statistics (1/2 -/+ delta)(m - 1), delta = 5 / sqrt(m).
+// statistics (1/2 -/+ delta)(m - 1), delta = 2.25 / sqrt(m).
 __device__ inline void sample_bracket(ColSelLds &L, int m, int64_t &lo, int64_t &hi) {
   if (m <= 0) {
     lo = INT64_MAX;  // empty bracket: the caller falls back to full selection
     hi = INT64_MIN;
     return;
   }
-  const double dl = 5.0 / sqrt((double)m);
+  // the sample median's standard error in quantile units is 0.5 / sqrt(m): a
+  // bracket of +-4.5 of them misses the median with probability ~7e-6 (then
+  // the caller selects over the whole column)
+  const double dl = 2.25 / sqrt((double)m);
   const double ca = (0.5 - dl) * (double)(m - 1), cb = (0.5 + dl) * (double)(m - 1);
   const int ia = ca <= 0.0 ? 0 : (int)floor(ca);
   const int ib = cb >= (double)(m - 1) ? m - 1 : (int)ceil(cb);
