@@ -49,11 +49,12 @@ def lib():
         _lib.tao_prune.argtypes = [i32, P, P, f64, P, P]
         _lib.tao_pruned.argtypes = [i64, i32, P, P, i32, P, P, P]
         _lib.tao_tensor_inclusive.argtypes = [P, i64, i32, i32, i32, P, P, P]
+        _lib.tao_window_profile.argtypes = [i64, P, P, P, i32, P, P, i64, i64, i64, P, P]
         _lib.tao_kmeans.argtypes = [P, i64, i32, i32, P, i32, P, P, P, P]
         _lib.tao_dbscan1d.argtypes = [P, i64, i64, i64, P, P, P]
         _lib.tao_node_intersections.argtypes = [P, P, i64, i32, i32, P, P]
         for f in ("tao_summary", "tao_prune", "tao_pruned", "tao_tensor_inclusive", "tao_kmeans",
-                  "tao_dbscan1d", "tao_node_intersections"):
+                  "tao_dbscan1d", "tao_node_intersections", "tao_window_profile"):
             getattr(_lib, f).restype = C.c_int
         for f in ("tao_check_tree", "tao_attribute", "tao_segment", "tao_imbalance",
                   "tao_outliers", "tao_topology"):
@@ -225,3 +226,17 @@ def node_intersections(labels, rank_node, n_nodes, K):
     st = lib().tao_node_intersections(_p(labels), _p(rank_node), len(labels), int(n_nodes), int(K),
                                       _p(pair), _p(nc))
     return st, pair, nc
+
+
+def window_profile(offsets, ts, ctx, parent, t0, t1, ranks=None):
+    """-> (status, excl[N], incl[N]) summed over the selected ranks (all when
+    ranks is None) for the time window [t0, t1)"""
+    offsets, ts, ctx = _arr(offsets, np.int64), _arr(ts, np.int64), _arr(ctx, np.int32)
+    parent = _arr(parent, np.int32)
+    sel = None if ranks is None else _arr(ranks, np.int32)
+    N = len(parent)
+    excl, incl = np.zeros(N, np.int64), np.zeros(N, np.int64)
+    st = lib().tao_window_profile(len(offsets) - 1, _p(offsets), _p(ts), _p(ctx), N, _p(parent),
+                                  _p(sel), 0 if sel is None else len(sel), int(t0), int(t1),
+                                  _p(excl), _p(incl))
+    return st, excl, incl

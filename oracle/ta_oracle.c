@@ -934,3 +934,42 @@ int tao_node_intersections(const int32_t *labels, const int32_t *rank_node, int6
   free(has);
   return TAO_OK;
 }
+
+/* ---- Time-window profile (Sec. II: a calling context tree for a trace
+ * interval of any subset of ranks). ---- */
+
+/* For the ranks rank_ids[0 .. n_sel) (all R ranks, in order, when rank_ids is
+ * NULL; a rank listed twice counts twice), the interval of every event,
+ * [t_k, t_{k+1}) (a rank's last event lasts 0), clipped to the window [t0, t1),
+ * is summed per context node: excl[v]; incl[v] = the sum of excl over the
+ * subtree of v (ancestor walks). */
+int tao_window_profile(int64_t R, const int64_t *off, const int64_t *ts, const int32_t *ctx,
+                       int32_t N, const int32_t *parent, const int32_t *rank_ids, int64_t n_sel,
+                       int64_t t0, int64_t t1, int64_t *excl, int64_t *incl) {
+  if (N <= 0 || !parent || !excl || t1 < t0 || n_sel < 0) return TAO_ERR_INVALID_ARG;
+  int st = tao_check_tree(N, parent);
+  if (st) return st;
+  st = check_traces(R, off, ts, ctx, N);
+  if (st) return st;
+  for (int32_t v = 0; v < N; v++) excl[v] = 0;
+  const int64_t n = rank_ids ? n_sel : R;
+  for (int64_t i = 0; i < n; i++) {
+    const int64_t r = rank_ids ? rank_ids[i] : i;
+    if (r < 0 || r >= R) return TAO_ERR_INVALID_ARG;
+    const int64_t b = off[r], e = off[r + 1];
+    for (int64_t k = b; k < e; k++) {
+      const int64_t s = ts[k];
+      const int64_t f = s + duration(ts, k, e);
+      const int64_t lo = s > t0 ? s : t0;
+      const int64_t hi = f < t1 ? f : t1;
+      if (hi > lo) excl[ctx[k]] += hi - lo;
+    }
+  }
+  if (incl) {
+    for (int32_t v = 0; v < N; v++) incl[v] = 0;
+    for (int32_t v = 0; v < N; v++)
+      if (excl[v] != 0)
+        for (int32_t w = v; w != -1; w = parent[w]) incl[w] += excl[v];
+  }
+  return TAO_OK;
+}
