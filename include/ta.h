@@ -234,8 +234,8 @@ ta_status ta_callpath(ta_handle h, int32_t leaf, int32_t *path_host, int32_t cap
  * numbering (as written by ta_attribute).  sum_excl[v] = sum over ranks of
  * excl[r][v] (required); sum_incl[v] = sum of sum_excl over the subtree of v
  * in the tree given to ta_set_tree (optional, NULL to skip), which equals
- * the sum over ranks of the inclusive costs.  Exact int64 sums.  N at most
- * 8192.  Device pointers. */
+ * the sum over ranks of the inclusive costs.  Exact int64 sums.  Any tree
+ * size (N up to 4,194,304).  Device pointers. */
 ta_status ta_summary(ta_handle h, const int64_t *excl, int64_t n_ranks, int64_t *sum_excl,
                      int64_t *sum_incl, void *stream);
 
@@ -280,6 +280,21 @@ ta_status ta_pruned_profiles(ta_handle h, const int64_t *excl, int64_t n_ranks, 
  * otherwise overlap it. */
 ta_status ta_tensor_inclusive(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
                               int64_t *out, void *stream);
+
+/* Profile of a time window for any subset of ranks (Sec. II: a calling context
+ * tree for a trace interval).  For the ranks rank_ids[0 .. n_sel) (DEVICE
+ * int32; NULL = all t->n_ranks ranks in order; a rank listed twice counts
+ * twice), every event's interval [t_k, t_{k+1}) (a rank's last event lasts 0)
+ * is clipped to [t0, t1) and added to its context node: excl[N] (required);
+ * incl[N] (optional) = the sum of excl over the subtree of each node.  The
+ * nodes with a non-zero inclusive cost form the calling context tree of the
+ * window.  Binary searches on each rank's timestamps bound the events read,
+ * so a narrow window costs little.  Any tree size (N up to 4,194,304).  Data
+ * errors (rank id out of range, decreasing timestamps, context out of range)
+ * are detected for the events the window touches and reported by
+ * ta_sync_status.  Needs ta_set_tree().  t1 >= t0.  Device pointers. */
+ta_status ta_window_profile(ta_handle h, const ta_traces *t, const int32_t *rank_ids, int64_t n_sel,
+                            int64_t t0, int64_t t1, int64_t *excl, int64_t *incl, void *stream);
 
 /* Clustering of ranks (Sec. VI-B: the ranks of one metric are clustered with
  * DBSCAN and the groups mapped to compute nodes; K-Means with 2..5 groups is

@@ -437,8 +437,76 @@ size_t subtree_rows_lds_bytes(int N, int K, bool excl) {
   return ((size_t)(SR / 64) * seg_len(N) + (excl ? (size_t)K : 0)) * sizeof(uint64_t);
 }
 
+// ---- subtree sums of one node vector, any tree size --------------------------
+// N <= 8192: one workgroup scans the vector in LDS (subtree_rows).  Larger: the
+// vector is scattered to preorder positions, scanned in blocks of SB positions
+// (block-local prefixes + block totals), the block totals are scanned by one
+// workgroup, and out[v] = P[tout(v)] - P[tin(v)] with P[x] = local[x] +
+// total of the blocks before x.
+constexpr int SBT = 1024;          // threads of the block-scan kernels
+constexpr int SBE = 4;             // positions per thread
+constexpr int SB = SBT * SBE;      // positions per block
+
+__global__ void pre_scatter(const int64_t *__restrict__ vec, int N, const int2 *__restrict__ tin_tout,
+                            uint64_t *__restrict__ P) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N;
+       v += (int64_t)gridDim.x * blockDim.x)
+    P[tin_tout[v].x] = (uint64_t)vec[v];
+}
+
+__global__ __launch_bounds__(SBT) void block_scan_local(uint64_t *__restrict__ P, int N,
+                                                       uint64_t *__restrict__ bt) {
+  __shared__ uint64_t wsum[SBT / 64];
+  const int64_t base = (int64_t)blockIdx.x * SB + (int64_t)threadIdx.x * SBE;
+  uint64_t a[SBE], s = 0;
+#pragma unroll
+  for (int u = 0; u < SBE; u++) {
+    a[u] = base + u < N ? P[base + u] : 0;
+    s += a[u];
+  }
+  uint64_t total;
+  uint64_t acc = block_excl_scan<SBT>(s, wsum, &total);
+#pragma unroll
+  for (int u = 0; u < SBE; u++) {
+    if (base + u < N) P[base + u] = acc;
+    acc += a[u];
+  }
+  if (threadIdx.x == 0) bt[blockIdx.x] = total;
+}
+
+// Exclusive scan of the nb block totals in place (nb <= SBT * SBE); bt[nb] = total.
+__global__ __launch_bounds__(SBT) void block_scan_totals(uint64_t *__restrict__ bt, int nb) {
+  __shared__ uint64_t wsum[SBT / 64];
+  const int base = threadIdx.x * SBE;
+  uint64_t a[SBE], s = 0;
+#pragma unroll
+  for (int u = 0; u < SBE; u++) {
+    a[u] = base + u < nb ? bt[base + u] : 0;
+    s += a[u];
+  }
+  uint64_t total;
+  uint64_t acc = block_excl_scan<SBT>(s, wsum, &total);
+#pragma unroll
+  for (int u = 0; u < SBE; u++) {
+    if (base + u < nb) bt[base + u] = acc;
+    acc += a[u];
+  }
+  if (threadIdx.x == 0) bt[nb] = total;
+}
+
+__global__ void subtree_from_prefix(const uint64_t *__restrict__ P, const uint64_t *__restrict__ bt,
+                                    int N, int nb, const int2 *__restrict__ tin_tout,
+                                    int64_t *__restrict__ out) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int2 t = tin_tout[v];
+    auto pref = [&](int x) -> uint64_t { return x >= N ? bt[nb] : P[x] + bt[x / SB]; };
+    out[v] = (int64_t)(pref(t.y) - pref(t.x));
+  }
+}
+
 hipError_t launch_summary(const int64_t *excl, int64_t R, int N, const int2 *tin_tout,
-                          int64_t *sum_excl, int64_t *sum_incl, int cus, hipStream_t s) {
+                          int64_t *sum_excl, int64_t *sum_incl, void *ws, int cus, hipStream_t s) {
   fill_u64<<<(N + ST - 1) / ST, ST, 0, s>>>((uint64_t *)sum_excl, N);
   if (R > 0) {
     const int gx = (N + ST - 1) / ST;
@@ -449,12 +517,9 @@ hipError_t launch_summary(const int64_t *excl, int64_t R, int N, const int2 *tin
     if (gy > 65535) gy = 65535;
     colsum_kernel<<<dim3(gx, (unsigned)gy), ST, 0, s>>>(excl, R, N, (uint64_t *)sum_excl);
   }
-  if (sum_incl) {
-    allow_big_lds();
-    const size_t lds = subtree_rows_lds_bytes(N, N, false);
-    launch_rows(1, lds, s, sum_excl, 1, N, tin_tout, tin_tout, N, nullptr, nullptr, sum_incl);
-  }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !sum_incl) return e;
+  return launch_subtree_sums(sum_excl, N, tin_tout, sum_incl, ws, cus, s);
 }
 
 hipError_t launch_prune(const int64_t *sum_excl, const int64_t *sum_incl, int N, double fraction,
@@ -501,6 +566,33 @@ hipError_t launch_tensor_inclusive(const int64_t *T, int64_t n_rows, int G, cons
     case 32: incl_tensor_narrow<32><<<grid, ST, 0, s>>>(T, n_rows, G, rt, out); break;
     default: incl_tensor_narrow<64><<<grid, ST, 0, s>>>(T, n_rows, G, rt, out); break;
   }
+  return hipGetLastError();
+}
+
+size_t subtree_sums_ws_bytes(int N) {
+  if (N <= MAX_NODES_ATTR) return 0;
+  const int64_t nb = ((int64_t)N + SB - 1) / SB;
+  return ((size_t)N + (size_t)nb + 1) * sizeof(uint64_t);
+}
+
+hipError_t launch_subtree_sums(const int64_t *vec, int N, const int2 *tin_tout, int64_t *out, void *ws,
+                               int cus, hipStream_t s) {
+  if (N <= MAX_NODES_ATTR) {
+    allow_big_lds();
+    const size_t lds = subtree_rows_lds_bytes(N, N, false);
+    launch_rows(1, lds, s, vec, 1, N, tin_tout, tin_tout, N, nullptr, nullptr, out);
+    return hipGetLastError();
+  }
+  const int nb = (int)(((int64_t)N + SB - 1) / SB);
+  if (nb > SBT * SBE) return hipErrorInvalidValue;
+  uint64_t *P = (uint64_t *)ws;
+  uint64_t *bt = P + N;
+  int g = (N + 255) / 256;
+  if (g > cus * 8) g = cus * 8;
+  pre_scatter<<<g, 256, 0, s>>>(vec, N, tin_tout, P);
+  block_scan_local<<<nb, SBT, 0, s>>>(P, N, bt);
+  block_scan_totals<<<1, SBT, 0, s>>>(bt, nb);
+  subtree_from_prefix<<<g, 256, 0, s>>>(P, bt, N, nb, tin_tout, out);
   return hipGetLastError();
 }
 

@@ -774,8 +774,6 @@ ta_status ta_summary(ta_handle h, const int64_t *excl, int64_t n_ranks, int64_t 
                      int64_t *sum_incl, void *stream) {
   if (!h) return TA_ERR_INVALID_ARG;
   if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
-  if (h->N > ta::MAX_NODES_ATTR)
-    return fail(h, TA_ERR_SIZE_OVERFLOW, "summary profiles support at most 8192 CCT nodes");
   if (n_ranks < 0) return fail(h, TA_ERR_INVALID_ARG, "negative n_ranks");
   if (!sum_excl) return fail(h, TA_ERR_INVALID_ARG, "sum_excl is required");
   if (n_ranks > 0 && !excl) return fail(h, TA_ERR_INVALID_ARG, "excl NULL");
@@ -784,7 +782,9 @@ ta_status ta_summary(ta_handle h, const int64_t *excl, int64_t n_ranks, int64_t 
   for (const void *p : ptrs)
     if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
   DeviceGuard dg(h->device);
-  hipError_t e = ta::launch_summary(excl, n_ranks, h->N, h->d_tin_tout, sum_excl, sum_incl,
+  ta_status st = ensure_ws(h, ta::subtree_sums_ws_bytes(h->N));
+  if (st) return st;
+  hipError_t e = ta::launch_summary(excl, n_ranks, h->N, h->d_tin_tout, sum_excl, sum_incl, h->ws,
                                     device_cus(h->device), (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "summary launch");
   return TA_OK;
@@ -866,6 +866,29 @@ ta_status ta_tensor_inclusive(ta_handle h, const int64_t *tensor, int64_t n_rank
   hipError_t e = ta::launch_tensor_inclusive(tensor, n_ranks * n_iters, h->G, h->d_rt, out,
                                              device_cus(h->device), (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "tensor inclusive launch");
+  return TA_OK;
+}
+
+ta_status ta_window_profile(ta_handle h, const ta_traces *t, const int32_t *rank_ids, int64_t n_sel,
+                            int64_t t0, int64_t t1, int64_t *excl, int64_t *incl, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  ta_status st = check_traces(h, t);
+  if (st) return st;
+  if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  if (t1 < t0) return fail(h, TA_ERR_INVALID_ARG, "t1 must be >= t0");
+  if (!excl) return fail(h, TA_ERR_INVALID_ARG, "excl is required");
+  if (rank_ids && n_sel < 0) return fail(h, TA_ERR_INVALID_ARG, "negative n_sel");
+  const void *ptrs[] = {rank_ids, excl, incl};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  const int64_t n = rank_ids ? n_sel : t->n_ranks;
+  DeviceGuard dg(h->device);
+  st = ensure_ws(h, ta::window_ws_bytes(h->N));
+  if (st) return st;
+  hipError_t e = ta::launch_window_profile(t->offsets, t->ts, t->ctx, t->n_ranks, rank_ids, n, h->N,
+                                           h->d_tin_tout, t0, t1, excl, incl, h->ws, h->d_err,
+                                           device_cus(h->device), (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "window profile launch");
   return TA_OK;
 }
 

@@ -127,7 +127,18 @@ size_t outliers_ws_bytes(int64_t R, int32_t I, int32_t G, int32_t mode, int32_t 
 // tensor (k_prune.hip).  tin_tout[v] = (preorder index, subtree end).
 size_t subtree_rows_lds_bytes(int N, int K, bool excl);
 hipError_t launch_summary(const int64_t *excl, int64_t R, int N, const int2 *tin_tout,
-                          int64_t *sum_excl, int64_t *sum_incl, int cus, hipStream_t s);
+                          int64_t *sum_excl, int64_t *sum_incl, void *ws, int cus, hipStream_t s);
+// out[v] = sum of vec over the subtree of v, any N up to MAX_NODES (workspace
+// subtree_sums_ws_bytes(N), none for N <= 8192).
+size_t subtree_sums_ws_bytes(int N);
+hipError_t launch_subtree_sums(const int64_t *vec, int N, const int2 *tin_tout, int64_t *out, void *ws,
+                               int cus, hipStream_t s);
+// Time-window profile (k_window.hip).
+size_t window_ws_bytes(int N);
+hipError_t launch_window_profile(const int64_t *off, const int64_t *ts, const int32_t *ctx, int64_t R,
+                                 const int32_t *ids, int64_t n_sel, int N, const int2 *tin_tout,
+                                 int64_t t0, int64_t t1, int64_t *excl, int64_t *incl, void *ws,
+                                 uint32_t *err, int cus, hipStream_t s);
 hipError_t launch_prune(const int64_t *sum_excl, const int64_t *sum_incl, int N, double fraction,
                         int32_t *kept, int32_t *n_kept, hipStream_t s);
 hipError_t launch_pruned_profiles(const int64_t *excl, int64_t R, int N, const int2 *tin_tout,

@@ -87,6 +87,7 @@ def _load():
         "ta_set_pruned": [P, i32, P],
         "ta_pruned_profiles": [P, P, i64, P, P, P],
         "ta_tensor_inclusive": [P, P, i64, i32, P, P],
+        "ta_window_profile": [P, P, P, i64, i64, i64, P, P, P],
         "ta_kmeans": [P, P, i64, i32, i32, P, i32, P, P, P, P, P],
         "ta_dbscan1d": [P, P, i64, i64, i64, P, P, P, P],
         "ta_node_intersections": [P, P, P, i64, i32, i32, P, P, P],
@@ -324,6 +325,20 @@ class Handle:
         self._check(_lib.ta_tensor_inclusive(self.h, _ptr(tensor), R, I, _ptr(out),
                                              _stream(self.device)))
         return out
+
+    def window_profile(self, tr: DeviceTraces, t0, t1, ranks=None, incl=True):
+        """Exclusive (and inclusive) cost per node of the time window [t0, t1),
+        summed over `ranks` (device int32 tensor; None = all ranks)."""
+        N = self.n_nodes
+        e = self._empty((N,), torch.int64)
+        i = self._empty((N,), torch.int64) if incl else None
+        t = tr.struct()
+        n = 0 if ranks is None else ranks.numel()
+        if ranks is not None and n == 0:   # an empty selection, not "all ranks"
+            ranks = self._empty((4,), torch.int32)
+        self._check(_lib.ta_window_profile(self.h, C.byref(t), _ptr(ranks), n, int(t0), int(t1),
+                                           _ptr(e), _ptr(i), _stream(self.device)))
+        return e, i
 
     # -- clustering of ranks ---------------------------------------------------
     def kmeans(self, X, init, max_iter=100):

@@ -222,6 +222,43 @@ def test_c3_clustering(mods, oracle, c3):
     h.sync_status()
 
 
+def test_c3_window_profile(mods, oracle, c3):
+    """A window over the 100k ranks: sampled ranks against the oracle, and over
+    the whole batch additivity of adjacent windows and the total time (each
+    rank contributes the overlap of its span with the window)."""
+    torch, gpu_synth, ta = mods
+    w, h, seg, cfg = c3
+    h.set_tree(w.parent)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx)
+    first = w.ts[torch.from_numpy(w.offsets_host[:-1]).cuda().clamp(max=len(w.ts) - 1)]
+    lo, hi = int(first.min().item()), int(w.ts.max().item())
+    a = lo + (hi - lo) * 2 // 5
+    b = lo + (hi - lo) // 2
+    c = lo + (hi - lo) * 3 // 5
+    print("[fullsize] window profile", flush=True)
+    e_ab, i_ab = h.window_profile(tr, a, b)
+    e_bc, i_bc = h.window_profile(tr, b, c)
+    e_ac, i_ac = h.window_profile(tr, a, c)
+    h.sync_status()
+    assert torch.equal(e_ab + e_bc, e_ac) and torch.equal(i_ab + i_bc, i_ac)
+    # total time: sum over ranks of |[a, c) & [first, last)|
+    offs = torch.from_numpy(w.offsets_host).cuda()
+    nonempty = offs[1:] > offs[:-1]
+    f = w.ts[offs[:-1].clamp(max=len(w.ts) - 1)]
+    l = w.ts[(offs[1:] - 1).clamp(min=0)]
+    ov = (torch.minimum(l, torch.tensor(c, device=l.device)) -
+          torch.maximum(f, torch.tensor(a, device=f.device))).clamp(min=0)
+    assert int(e_ac.sum().item()) == int(ov[nonempty].sum().item())
+    ranks = _sample(w)
+    s = gpu_synth.sample_ranks_to_host(w, ranks)
+    st, ex, inc = oracle.window_profile(s.offsets, s.ts, s.ctx, s.parent, a, c)
+    ge, gi = h.window_profile(tr, a, c, ranks=torch.from_numpy(ranks.astype(np.int32)).cuda())
+    assert st == 0
+    assert np.array_equal(ge.cpu().numpy(), ex) and np.array_equal(gi.cpu().numpy(), inc)
+    h.set_tree(w.parent)
+    h.set_regions(w.marker, w.regions)
+
+
 def test_c2_shape_full_parity(mods, oracle):
     torch, gpu_synth, ta = mods
     w = gpu_synth.timeline_on_gpu(seed=4, n_ranks=3000, median_len=6000, min_len=1000,

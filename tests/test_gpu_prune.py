@@ -57,7 +57,7 @@ def oracle_incl(oracle, excl, parent):
 
 
 @pytest.mark.parametrize("R,N,roots", [(0, 50, 1), (1, 1, 1), (3, 257, 1), (2500, 1000, 3),
-                                       (150, 8192, 2)])
+                                       (150, 8192, 2), (4, 8193, 1), (3, 20000, 4), (2, 100003, 2)])
 def test_summary_matches_oracle(ta, h, oracle, R, N, roots):
     print(f"summary R={R} N={N} roots={roots}", flush=True)
     rng = np.random.default_rng([11, R, N])
