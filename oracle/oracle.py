@@ -50,11 +50,12 @@ def lib():
         _lib.tao_pruned.argtypes = [i64, i32, P, P, i32, P, P, P]
         _lib.tao_tensor_inclusive.argtypes = [P, i64, i32, i32, i32, P, P, P]
         _lib.tao_window_profile.argtypes = [i64, P, P, P, i32, P, P, i64, i64, i64, P, P]
+        _lib.tao_sparse_profiles.argtypes = [i64, P, P, P, i32, P, P, P]
         _lib.tao_kmeans.argtypes = [P, i64, i32, i32, P, i32, P, P, P, P]
         _lib.tao_dbscan1d.argtypes = [P, i64, i64, i64, P, P, P]
         _lib.tao_node_intersections.argtypes = [P, P, i64, i32, i32, P, P]
         for f in ("tao_summary", "tao_prune", "tao_pruned", "tao_tensor_inclusive", "tao_kmeans",
-                  "tao_dbscan1d", "tao_node_intersections", "tao_window_profile"):
+                  "tao_dbscan1d", "tao_node_intersections", "tao_window_profile", "tao_sparse_profiles"):
             getattr(_lib, f).restype = C.c_int
         for f in ("tao_check_tree", "tao_attribute", "tao_segment", "tao_imbalance",
                   "tao_outliers", "tao_topology"):
@@ -240,3 +241,16 @@ def window_profile(offsets, ts, ctx, parent, t0, t1, ranks=None):
                                   _p(sel), 0 if sel is None else len(sel), int(t0), int(t1),
                                   _p(excl), _p(incl))
     return st, excl, incl
+
+
+def sparse_profiles(offsets, ts, ctx, n_nodes):
+    """-> (status, counts[R], node_ids[E], excl[E]): rank r's non-zero exclusive
+    costs in ascending node id at [offsets[r], offsets[r] + counts[r])"""
+    offsets, ts, ctx = _arr(offsets, np.int64), _arr(ts, np.int64), _arr(ctx, np.int32)
+    R, E = len(offsets) - 1, len(ts)
+    counts = np.zeros(R, np.int64)
+    ids = np.full(E, -1, np.int32)
+    ex = np.zeros(E, np.int64)
+    st = lib().tao_sparse_profiles(R, _p(offsets), _p(ts), _p(ctx), int(n_nodes), _p(counts), _p(ids),
+                                   _p(ex))
+    return st, counts, ids, ex

@@ -61,3 +61,26 @@ def test_adjacent_windows_add_up(oracle):
         # the window's total time is at most (window length) x (ranks)
         roots = np.flatnonzero(np.asarray(w.parent) == -1)
         assert i3[roots].sum() <= (c - a) * 7
+
+
+def test_sparse_profiles_hand_example(oracle):
+    w = synth.hand_example()
+    st, cnt, ids, ex = oracle.sparse_profiles(w.offsets, w.ts, w.ctx, len(w.parent))
+    assert st == 0 and cnt.tolist() == [5, 4]
+    b0, b1 = int(w.offsets[0]), int(w.offsets[1])
+    # rank 0: excl [0, 20, 5, 20, 70, 35]; rank 1: excl [0, 0, 2, 8, 80, 40]
+    assert ids[b0:b0 + 5].tolist() == [1, 2, 3, 4, 5] and ex[b0:b0 + 5].tolist() == [20, 5, 20, 70, 35]
+    assert ids[b1:b1 + 4].tolist() == [2, 3, 4, 5] and ex[b1:b1 + 4].tolist() == [2, 8, 80, 40]
+
+
+def test_sparse_profiles_are_the_dense_rows(oracle):
+    w = synth.timeline_workload(seed=8, n_ranks=11, median_len=2500, min_len=1, max_len=9000,
+                                n_nodes=700, depth_max=10, n_iters=25, n_regions=5)
+    st, ex, _ = oracle.attribute(w.offsets, w.ts, w.ctx, w.parent)
+    st, cnt, ids, sv = oracle.sparse_profiles(w.offsets, w.ts, w.ctx, len(w.parent))
+    assert st == 0
+    for r in range(11):
+        b = int(w.offsets[r])
+        nz = np.flatnonzero(ex[r])
+        assert cnt[r] == len(nz) <= int(w.offsets[r + 1]) - b
+        assert np.array_equal(ids[b:b + cnt[r]], nz) and np.array_equal(sv[b:b + cnt[r]], ex[r][nz])
