@@ -296,6 +296,19 @@ ta_status ta_tensor_inclusive(ta_handle h, const int64_t *tensor, int64_t n_rank
 ta_status ta_window_profile(ta_handle h, const ta_traces *t, const int32_t *rank_ids, int64_t n_sel,
                             int64_t t0, int64_t t1, int64_t *excl, int64_t *incl, void *stream);
 
+/* Sparse per-rank profiles (Sec. I: stored densely, GPU profiles can be over
+ * 1000x larger than sparsely; Sec. VI-B: 97,833 calling contexts).  For each
+ * rank r, the nodes with a non-zero exclusive time (the sum of the durations
+ * of r's events in that context) in ascending node id, at node_ids[off[r] + j]
+ * and excl[off[r] + j] for j < counts[r]; counts[r] <= the rank's event count,
+ * so each rank's entries fit in its own event range (entries after them are
+ * left unwritten).  Any tree size (N up to 4,194,304): node ids are taken in
+ * chunks of 8,192 (an LDS histogram each), one pass over a rank's events per
+ * chunk its events reach.  counts[n_ranks], node_ids[n_events],
+ * excl[n_events]: device pointers.  Needs ta_set_tree(). */
+ta_status ta_sparse_profiles(ta_handle h, const ta_traces *t, int64_t *counts, int32_t *node_ids,
+                             int64_t *excl, void *stream);
+
 /* Clustering of ranks (Sec. VI-B: the ranks of one metric are clustered with
  * DBSCAN and the groups mapped to compute nodes; K-Means with 2..5 groups is
  * tested by the compute nodes whose ranks fall in two groups).

@@ -26,7 +26,8 @@ template <bool LDSH>
 __global__ __launch_bounds__(WT) void window_excl(const int64_t *__restrict__ off,
                                                  const int64_t *__restrict__ ts,
                                                  const int32_t *__restrict__ ctx, int64_t R,
-                                                 const int32_t *__restrict__ ids, int64_t n_sel,
+                                                 int64_t E, const int32_t *__restrict__ ids,
+                                                 int64_t n_sel,
                                                  int N, int64_t t0, int64_t t1,
                                                  int64_t *__restrict__ excl, uint32_t *err) {
   extern __shared__ uint64_t hist[];  // [N] when LDSH
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(WT) void window_excl(const int64_t *__restrict__ of
     if (threadIdx.x == 0) {
       const int64_t r = ids ? (int64_t)ids[i] : i;
       int64_t lo = 0, hi = 0, e = 0;
-      if (r < 0 || r >= R || off[r + 1] < off[r]) {
+      if (r < 0 || r >= R || off[r] < 0 || off[r + 1] < off[r] || off[r + 1] > E) {
         atomicOr(err, ERRBIT_OFFSETS);
       } else {
         const int64_t b = off[r];
@@ -91,6 +92,111 @@ __global__ __launch_bounds__(WT) void window_excl(const int64_t *__restrict__ of
   }
 }
 
+// ---- sparse per-rank profiles --------------------------------------------------
+
+constexpr int SPT = 1024;               // threads per rank workgroup
+constexpr int SPC = 8192;               // node ids per chunk (64 KB LDS histogram)
+constexpr int SPE = SPC / SPT;          // bins per thread in the compaction
+constexpr int SPW = MAX_NODES / SPC / 32;  // words of the touched-chunk mask
+
+// Exclusive scan of per-thread counts over the workgroup; *total = the sum.
+__device__ inline int block_excl_scan_i32(int v, int *wsum, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int base = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < SPT / 64; i++) {
+    const int s = wsum[i];
+    base += i < w ? s : 0;
+    all += s;
+  }
+  __syncthreads();
+  *total = all;
+  return base + x - v;
+}
+
+// One workgroup per rank (grid-stride).  For each chunk of SPC node ids that
+// the rank's events reach with a positive duration: an LDS histogram of the
+// chunk (exact 64-bit atomics), then its non-zero bins in ascending id,
+// compacted by a workgroup scan and appended after the previous chunks' in the
+// rank's own event range.  With more than one chunk a first pass over the
+// events marks the chunks they reach.
+__global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__restrict__ off,
+                                                             const int64_t *__restrict__ ts,
+                                                             const int32_t *__restrict__ ctx,
+                                                             int64_t R, int64_t E, int N,
+                                                             int64_t *__restrict__ counts,
+                                                             int32_t *__restrict__ ids,
+                                                             int64_t *__restrict__ vals,
+                                                             uint32_t *err) {
+  __shared__ uint64_t hist[SPC];
+  __shared__ uint32_t touched[SPW];
+  __shared__ int wsum[SPT / 64];
+  const int n_chunks = (N + SPC - 1) / SPC;
+  for (int64_t r = blockIdx.x; r < R; r += gridDim.x) {
+    // a rank's range, clamped to [0, E] (inconsistent offsets are an error)
+    const int64_t o0 = off[r], o1 = off[r + 1];
+    const bool bad = o0 < 0 || o1 < o0 || o1 > E;
+    const int64_t b = bad ? 0 : o0, e = bad ? 0 : o1;
+    if (bad && threadIdx.x == 0) atomicOr(err, ERRBIT_OFFSETS);
+    auto dur = [&](int64_t k) -> int64_t { return k + 1 < e ? ts[k + 1] - ts[k] : 0; };
+    if (n_chunks > 1) {
+      for (int i = threadIdx.x; i < SPW; i += SPT) touched[i] = 0;
+      __syncthreads();
+      for (int64_t k = b + threadIdx.x; k < e; k += SPT) {
+        const int32_t c = ctx[k];
+        if (c >= 0 && c < N && dur(k) > 0) atomicOr(&touched[(c / SPC) >> 5], 1u << ((c / SPC) & 31));
+      }
+      __syncthreads();
+    }
+    int64_t base = 0;
+    for (int ch = 0; ch < n_chunks; ch++) {
+      if (n_chunks > 1 && !((touched[ch >> 5] >> (ch & 31)) & 1u)) continue;  // uniform
+      const int lo = ch * SPC;
+      for (int i = threadIdx.x; i < SPC; i += SPT) hist[i] = 0;
+      __syncthreads();
+      for (int64_t k = b + threadIdx.x; k < e; k += SPT) {
+        const int32_t c = ctx[k];
+        const int64_t d = dur(k);
+        if (d < 0) atomicOr(err, ERRBIT_UNSORTED);
+        if (c < 0 || c >= N) {
+          if (ch == 0) atomicOr(err, ERRBIT_CTX);
+        } else if (c >= lo && c < lo + SPC && d != 0) {
+          atomicAdd((unsigned long long *)&hist[c - lo], (unsigned long long)d);
+        }
+      }
+      __syncthreads();
+      uint64_t v[SPE];
+      int nz = 0;
+#pragma unroll
+      for (int u = 0; u < SPE; u++) {
+        v[u] = hist[threadIdx.x * SPE + u];
+        nz += v[u] != 0 ? 1 : 0;
+      }
+      int total;
+      int pos = block_excl_scan_i32(nz, wsum, &total);
+#pragma unroll
+      for (int u = 0; u < SPE; u++)
+        if (v[u] != 0) {
+          const int64_t o = b + base + pos++;
+          ids[o] = lo + threadIdx.x * SPE + u;
+          vals[o] = (int64_t)v[u];
+        }
+      base += total;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[r] = base;
+    __syncthreads();
+  }
+}
+
 int grid_w(int64_t n, int cus, int per_cu) {
   int64_t g = n < (int64_t)cus * per_cu ? n : (int64_t)cus * per_cu;
   return g < 1 ? 1 : (int)g;
@@ -101,7 +207,7 @@ int grid_w(int64_t n, int cus, int per_cu) {
 size_t window_ws_bytes(int N) { return subtree_sums_ws_bytes(N); }
 
 hipError_t launch_window_profile(const int64_t *off, const int64_t *ts, const int32_t *ctx, int64_t R,
-                                 const int32_t *ids, int64_t n_sel, int N, const int2 *tin_tout,
+                                 int64_t E, const int32_t *ids, int64_t n_sel, int N, const int2 *tin_tout,
                                  int64_t t0, int64_t t1, int64_t *excl, int64_t *incl, void *ws,
                                  uint32_t *err, int cus, hipStream_t s) {
   zero_i64<<<grid_w((N + WT - 1) / WT, cus, 4), WT, 0, s>>>(excl, N);
@@ -113,16 +219,24 @@ hipError_t launch_window_profile(const int64_t *off, const int64_t *ts, const in
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
         attr = true;
       }
-      window_excl<true><<<grid_w(n_sel, cus, 4), WT, (size_t)N * 8, s>>>(off, ts, ctx, R, ids, n_sel,
-                                                                        N, t0, t1, excl, err);
+      window_excl<true><<<grid_w(n_sel, cus, 4), WT, (size_t)N * 8, s>>>(off, ts, ctx, R, E, ids,
+                                                                        n_sel, N, t0, t1, excl, err);
     } else {
-      window_excl<false><<<grid_w(n_sel, cus, 8), WT, 0, s>>>(off, ts, ctx, R, ids, n_sel, N, t0, t1,
-                                                             excl, err);
+      window_excl<false><<<grid_w(n_sel, cus, 8), WT, 0, s>>>(off, ts, ctx, R, E, ids, n_sel, N, t0,
+                                                             t1, excl, err);
     }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !incl) return e;
   return launch_subtree_sums(excl, N, tin_tout, incl, ws, cus, s);
+}
+
+hipError_t launch_sparse_profiles(const int64_t *off, const int64_t *ts, const int32_t *ctx, int64_t R,
+                                  int64_t E, int N, int64_t *counts, int32_t *ids, int64_t *vals, uint32_t *err,
+                                  int cus, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  sparse_profiles_kernel<<<grid_w(R, cus, 2), SPT, 0, s>>>(off, ts, ctx, R, E, N, counts, ids, vals, err);
+  return hipGetLastError();
 }
 
 }  // namespace ta

@@ -885,10 +885,31 @@ ta_status ta_window_profile(ta_handle h, const ta_traces *t, const int32_t *rank
   DeviceGuard dg(h->device);
   st = ensure_ws(h, ta::window_ws_bytes(h->N));
   if (st) return st;
-  hipError_t e = ta::launch_window_profile(t->offsets, t->ts, t->ctx, t->n_ranks, rank_ids, n, h->N,
+  hipError_t e = ta::launch_window_profile(t->offsets, t->ts, t->ctx, t->n_ranks, t->n_events, rank_ids,
+                                           n, h->N,
                                            h->d_tin_tout, t0, t1, excl, incl, h->ws, h->d_err,
                                            device_cus(h->device), (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "window profile launch");
+  return TA_OK;
+}
+
+ta_status ta_sparse_profiles(ta_handle h, const ta_traces *t, int64_t *counts, int32_t *node_ids,
+                             int64_t *excl, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  ta_status st = check_traces(h, t);
+  if (st) return st;
+  if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  if (t->n_ranks > 0 && !counts) return fail(h, TA_ERR_INVALID_ARG, "counts is required");
+  if (t->n_events > 0 && (!node_ids || !excl))
+    return fail(h, TA_ERR_INVALID_ARG, "node_ids and excl are required");
+  const void *ptrs[] = {counts, node_ids, excl};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  DeviceGuard dg(h->device);
+  hipError_t e = ta::launch_sparse_profiles(t->offsets, t->ts, t->ctx, t->n_ranks, t->n_events, h->N,
+                                            counts, node_ids,
+                                            excl, h->d_err, device_cus(h->device), (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "sparse profiles launch");
   return TA_OK;
 }
 

@@ -133,10 +133,15 @@ hipError_t launch_summary(const int64_t *excl, int64_t R, int N, const int2 *tin
 size_t subtree_sums_ws_bytes(int N);
 hipError_t launch_subtree_sums(const int64_t *vec, int N, const int2 *tin_tout, int64_t *out, void *ws,
                                int cus, hipStream_t s);
+// Sparse per-rank profiles (k_window.hip): rank r's non-zero exclusive costs
+// in ascending node id at [off[r], off[r] + counts[r]).
+hipError_t launch_sparse_profiles(const int64_t *off, const int64_t *ts, const int32_t *ctx, int64_t R,
+                                  int64_t E, int N, int64_t *counts, int32_t *ids, int64_t *vals, uint32_t *err,
+                                  int cus, hipStream_t s);
 // Time-window profile (k_window.hip).
 size_t window_ws_bytes(int N);
 hipError_t launch_window_profile(const int64_t *off, const int64_t *ts, const int32_t *ctx, int64_t R,
-                                 const int32_t *ids, int64_t n_sel, int N, const int2 *tin_tout,
+                                 int64_t E, const int32_t *ids, int64_t n_sel, int N, const int2 *tin_tout,
                                  int64_t t0, int64_t t1, int64_t *excl, int64_t *incl, void *ws,
                                  uint32_t *err, int cus, hipStream_t s);
 hipError_t launch_prune(const int64_t *sum_excl, const int64_t *sum_incl, int N, double fraction,

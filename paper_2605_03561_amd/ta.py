@@ -88,6 +88,7 @@ def _load():
         "ta_pruned_profiles": [P, P, i64, P, P, P],
         "ta_tensor_inclusive": [P, P, i64, i32, P, P],
         "ta_window_profile": [P, P, P, i64, i64, i64, P, P, P],
+        "ta_sparse_profiles": [P, P, P, P, P, P],
         "ta_kmeans": [P, P, i64, i32, i32, P, i32, P, P, P, P, P],
         "ta_dbscan1d": [P, P, i64, i64, i64, P, P, P, P],
         "ta_node_intersections": [P, P, P, i64, i32, i32, P, P, P],
@@ -339,6 +340,19 @@ class Handle:
         self._check(_lib.ta_window_profile(self.h, C.byref(t), _ptr(ranks), n, int(t0), int(t1),
                                            _ptr(e), _ptr(i), _stream(self.device)))
         return e, i
+
+    def sparse_profiles(self, tr: DeviceTraces):
+        """Per rank, the non-zero exclusive costs in ascending node id: device
+        (counts [R], node_ids [E], excl [E]); rank r's entries sit at
+        [offsets[r], offsets[r] + counts[r])."""
+        R, E = tr.n_ranks, tr.n_events
+        counts = self._empty((R,), torch.int64)
+        ids = self._empty((E,), torch.int32)
+        ex = self._empty((E,), torch.int64)
+        t = tr.struct()
+        self._check(_lib.ta_sparse_profiles(self.h, C.byref(t), _ptr(counts), _ptr(ids), _ptr(ex),
+                                            _stream(self.device)))
+        return counts, ids, ex
 
     # -- clustering of ranks ---------------------------------------------------
     def kmeans(self, X, init, max_iter=100):

@@ -259,6 +259,36 @@ def test_c3_window_profile(mods, oracle, c3):
     h.set_regions(w.marker, w.regions)
 
 
+def test_c3_sparse_profiles(mods, oracle, c3):
+    """Sparse per-rank profiles of the 100k ranks: sampled ranks against the
+    oracle, and on every rank the entries against the dense attribution row
+    of the same pass (non-zero excl in ascending node id)."""
+    torch, gpu_synth, ta = mods
+    w, h, seg, cfg = c3
+    h.set_tree(w.parent)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx)
+    print("[fullsize] sparse profiles", flush=True)
+    gc, gi, ge = h.sparse_profiles(tr)
+    h.sync_status()
+    assert torch.equal(gc, (seg["excl"] != 0).sum(1))
+    ranks = _sample(w)
+    s = gpu_synth.sample_ranks_to_host(w, ranks)
+    st, cnt, ids, ex = oracle.sparse_profiles(s.offsets, s.ts, s.ctx, len(s.parent))
+    assert st == 0
+    offs = w.offsets_host
+    for j, r in enumerate(ranks):
+        b, n = int(offs[r]), int(cnt[j])
+        sb = int(s.offsets[j])
+        assert int(gc[r].item()) == n
+        assert np.array_equal(gi[b:b + n].cpu().numpy(), ids[sb:sb + n])
+        assert np.array_equal(ge[b:b + n].cpu().numpy(), ex[sb:sb + n])
+        row = seg["excl"][r]
+        nz = torch.nonzero(row).flatten()
+        assert torch.equal(gi[b:b + n].long(), nz) and torch.equal(ge[b:b + n], row[nz])
+    h.set_tree(w.parent)
+    h.set_regions(w.marker, w.regions)
+
+
 def test_c2_shape_full_parity(mods, oracle):
     torch, gpu_synth, ta = mods
     w = gpu_synth.timeline_on_gpu(seed=4, n_ranks=3000, median_len=6000, min_len=1000,

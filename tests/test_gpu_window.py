@@ -67,3 +67,31 @@ def test_windows_match_oracle(ta, h, oracle, seed, n_nodes):
             assert np.array_equal(ge.cpu().numpy(), ex), (a, b, sel)
             assert np.array_equal(gi.cpu().numpy(), inc), (a, b, sel)
     h.sync_status()
+
+
+@pytest.mark.parametrize("seed,n_nodes,min_len", [(5, 1, 1), (6, 300, 0), (7, 8192, 2), (8, 8193, 1),
+                                                 (9, 30000, 5), (10, 100000, 1)])
+def test_sparse_profiles_match_oracle(ta, h, oracle, seed, n_nodes, min_len):
+    print(f"sparse seed={seed} N={n_nodes}", flush=True)
+    if n_nodes == 1:
+        w = synth.hand_example()
+        parent = np.array([-1], np.int32)
+        ctx = np.zeros_like(w.ctx)
+        offsets, ts = w.offsets, w.ts
+    else:
+        w = synth.timeline_workload(seed=seed, n_ranks=25, median_len=3000, min_len=min_len,
+                                    max_len=15000, n_nodes=n_nodes, depth_max=12, n_iters=30,
+                                    n_regions=6)
+        parent, ctx, offsets, ts = w.parent, w.ctx, w.offsets, w.ts
+    h.set_tree(parent)
+    tr = ta.DeviceTraces(offsets, ts, ctx)
+    st, cnt, ids, ex = oracle.sparse_profiles(offsets, ts, ctx, len(parent))
+    assert st == 0
+    gc, gi, ge = h.sparse_profiles(tr)
+    h.sync_status()
+    gc, gi, ge = gc.cpu().numpy(), gi.cpu().numpy(), ge.cpu().numpy()
+    assert np.array_equal(gc, cnt)
+    for r in range(len(offsets) - 1):
+        b = int(offsets[r])
+        assert np.array_equal(gi[b:b + cnt[r]], ids[b:b + cnt[r]])
+        assert np.array_equal(ge[b:b + cnt[r]], ex[b:b + cnt[r]])
