@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--no-clustering", action="store_true",
                     help="skip the clustering leg (K-Means on the per-rank region totals, DBSCAN "
                          "on the per-rank totals, compute nodes shared by the clusters)")
+    ap.add_argument("--no-window", action="store_true",
+                    help="skip the time-window and sparse-profile leg")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
@@ -223,7 +225,12 @@ def main():
     pruned = None
     if not args.no_pruned:
         pruned = pruned_model_summary(tr, excl, w, I, args.steps)
-    del excl, tr, w
+    del excl
+    torch.cuda.empty_cache()
+    window = None
+    if not args.no_window:
+        window = window_sparse_summary(tr, w, args.steps, args.seed)
+    del tr, w
     torch.cuda.empty_cache()
     pre = None
     if not args.no_prescreen:
@@ -269,8 +276,82 @@ def main():
         "mixed_batch": mixed,
         "pruned_model": pruned,
         "clustering": clus,
+        "window_and_sparse": window,
     }
     print(json.dumps(line))
+
+
+def window_sparse_summary(tr, w, steps, seed):
+    """Time-window profiles and sparse per-rank profiles on the batch (a window
+    over the middle tenth of the time span, the whole-trace window, and the
+    sparse profiles of every rank), then sparse profiles on 10,000 ranks of a
+    97,833-node call tree (the paper's scale).  Each call is timed with HIP
+    events on the launch stream over `steps` calls."""
+    import torch
+
+    from paper_2605_03561_amd import gpu_synth, ta
+
+    stream = torch.cuda.current_stream()
+    R = len(w["offsets_host"]) - 1
+    E = int(w["offsets_host"][-1])
+    N = len(w["parent"])
+    h = ta.Handle(0)
+    h.set_tree(w["parent"])
+
+    def timed(fn):
+        res = fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(stream)
+        for j in range(steps):
+            res = fn()
+            ev[j + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[j].elapsed_time(ev[j + 1]) for j in range(steps)])), res
+
+    offs = w["offsets"]
+    first = w["ts"][offs[:-1].clamp(max=E - 1)]
+    lo, hi = int(first.min().item()), int(w["ts"].max().item()) + 1
+    a, b = lo + (hi - lo) * 9 // 20, lo + (hi - lo) * 11 // 20
+    ms, byt = {}, {}
+    ms["window_middle_tenth"], _ = timed(lambda: h.window_profile(tr, a, b))
+    n_in = int(((w["ts"] >= a) & (w["ts"] < b)).sum().item())
+    byt["window_middle_tenth"] = 12 * n_in + 16 * N
+    ms["window_whole"], (we, wi) = timed(lambda: h.window_profile(tr, lo, hi))
+    byt["window_whole"] = 12 * E + 8 * (R + 1) + 16 * N
+    ms["sparse_profiles"], (cnt, ids, vals) = timed(lambda: h.sparse_profiles(tr))
+    nnz = int(cnt.sum().item())
+    byt["sparse_profiles"] = 12 * E + 8 * (R + 1) + 8 * R + 12 * nnz
+    h.sync_status()
+    del cnt, ids, vals, we, wi
+    h.close()
+    torch.cuda.empty_cache()
+    # the paper's scale: a 97,833-node tree (10,000 ranks, lognormal lengths)
+    big = dict(n_ranks=10_000, median_len=20_000, min_len=1_000, max_len=200_000, n_nodes=97_833,
+               depth_max=12, n_iters=500, n_regions=64)
+    wb = gpu_synth.timeline_on_gpu(seed=seed, **big)
+    hb = ta.Handle(0)
+    hb.set_tree(wb["parent"])
+    trb = ta.DeviceTraces(wb["offsets"], wb["ts"], wb["ctx"])
+    Eb = int(wb["offsets_host"][-1])
+    ms["sparse_profiles_97833_nodes"], (cb, ib, vb) = timed(lambda: hb.sparse_profiles(trb))
+    nnzb = int(cb.sum().item())
+    byt["sparse_profiles_97833_nodes"] = 12 * Eb + 16 * big["n_ranks"] + 12 * nnzb
+    hb.sync_status()
+    dense_bytes = 8 * big["n_ranks"] * big["n_nodes"]
+    hb.close()
+    del cb, ib, vb, trb, wb
+    torch.cuda.empty_cache()
+    gbs = {k: byt[k] / (ms[k] / 1e3) / 1e9 for k in byt}
+    out = {"window": [a, b], "events_in_window": n_in, "sparse_nonzeros": nnz,
+           "sparse_vs_dense_bytes": (12 * nnz + 8 * R) / (8 * R * N),
+           "big_tree": {"ranks": big["n_ranks"], "nodes": big["n_nodes"], "events": Eb,
+                        "nonzeros": nnzb, "dense_bytes": dense_bytes,
+                        "sparse_bytes": 12 * nnzb + 8 * big["n_ranks"]},
+           "ms": ms, "algorithmic_bytes": byt, "achieved_gbs": gbs,
+           "hbm_frac": {k: v / HBM_PEAK_GBS for k, v in gbs.items()}}
+    print(f"[bench] window and sparse: {ms}", file=sys.stderr, flush=True)
+    return out
 
 
 def clustering_summary(h, rank_sum, rank_node, steps, seed, k=6, max_iter=50, min_pts=100):

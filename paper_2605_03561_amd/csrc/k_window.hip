@@ -9,6 +9,48 @@ namespace {
 
 constexpr int WT = 256;
 
+typedef long long v2ll __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Visits events k in [lo, hi) of a rank whose events end at e, four
+// consecutive events per thread per step from a 4-aligned index (16-byte loads
+// of timestamps and contexts; scalar loads within 4 events of the array's end
+// E).  f(k, t_k, t_{k+1} (t_k for the rank's last event), ctx_k).
+template <int NT, class F>
+__device__ inline void visit_events(const int64_t *__restrict__ ts, const int32_t *__restrict__ ctx,
+                                    int64_t E, int64_t lo, int64_t hi, int64_t e, F &&f) {
+  for (int64_t k0 = (lo & ~(int64_t)3) + 4 * (int64_t)threadIdx.x; k0 < hi; k0 += 4 * (int64_t)NT) {
+    int64_t t[5];
+    int32_t c[4];
+    if (k0 + 4 <= E) {
+      const v2ll a = *reinterpret_cast<const v2ll *>(ts + k0);
+      const v2ll b = *reinterpret_cast<const v2ll *>(ts + k0 + 2);
+      const v4i q = *reinterpret_cast<const v4i *>(ctx + k0);
+      t[0] = a.x;
+      t[1] = a.y;
+      t[2] = b.x;
+      t[3] = b.y;
+      c[0] = q.x;
+      c[1] = q.y;
+      c[2] = q.z;
+      c[3] = q.w;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        t[u] = k0 + u < E ? ts[k0 + u] : 0;
+        c[u] = k0 + u < E ? ctx[k0 + u] : 0;
+      }
+    }
+    t[4] = k0 + 4 < e ? ts[k0 + 4] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int64_t k = k0 + u;
+      if (k < lo || k >= hi) continue;
+      f(k, t[u], k + 1 < e ? t[u + 1] : t[u], c[u]);
+    }
+  }
+}
+
 __global__ void zero_i64(int64_t *p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -67,14 +109,11 @@ __global__ __launch_bounds__(WT) void window_excl(const int64_t *__restrict__ of
     }
     __syncthreads();
     const int64_t lo = range[0], hi = range[1], e = range[2];
-    for (int64_t k = lo + threadIdx.x; k < hi; k += WT) {
-      const int64_t s = ts[k];
-      const int64_t f = k + 1 < e ? ts[k + 1] : s;
+    visit_events<WT>(ts, ctx, E, lo, hi, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
       if (f < s) atomicOr(err, ERRBIT_UNSORTED);
       const int64_t a = s > t0 ? s : t0;
       const int64_t z = f < t1 ? f : t1;
       if (z > a) {
-        const int32_t c = ctx[k];
         if (c < 0 || c >= N) {
           atomicOr(err, ERRBIT_CTX);
         } else if (LDSH) {
@@ -83,7 +122,7 @@ __global__ __launch_bounds__(WT) void window_excl(const int64_t *__restrict__ of
           atomicAdd((unsigned long long *)&excl[c], (unsigned long long)(z - a));
         }
       }
-    }
+    });
     __syncthreads();
   }
   if (LDSH) {
@@ -162,16 +201,15 @@ __global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__r
       const int lo = ch * SPC;
       for (int i = threadIdx.x; i < SPC; i += SPT) hist[i] = 0;
       __syncthreads();
-      for (int64_t k = b + threadIdx.x; k < e; k += SPT) {
-        const int32_t c = ctx[k];
-        const int64_t d = dur(k);
+      visit_events<SPT>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
+        const int64_t d = f - s;
         if (d < 0) atomicOr(err, ERRBIT_UNSORTED);
         if (c < 0 || c >= N) {
           if (ch == 0) atomicOr(err, ERRBIT_CTX);
         } else if (c >= lo && c < lo + SPC && d != 0) {
           atomicAdd((unsigned long long *)&hist[c - lo], (unsigned long long)d);
         }
-      }
+      });
       __syncthreads();
       uint64_t v[SPE];
       int nz = 0;
