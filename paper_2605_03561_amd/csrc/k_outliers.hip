@@ -50,44 +50,106 @@ constexpr int64_t SENT = INT64_MIN;
 
 __host__ __device__ inline int64_t pad_ranks(int64_t R) { return (R + 63) & ~(int64_t)63; }
 
-// 64 ranks x 64 columns per workgroup.  Reads: lane pairs of adjacent
-// columns of one row (16-byte loads when rows are 16-byte aligned, i.e. I*G
-// even); writes: lane pairs of adjacent ranks of one column (16-byte stores).
+// 64 columns x TG tiles of 64 ranks per workgroup, one tile at a time.  Reads:
+// lane pairs of adjacent columns of one row (16-byte loads when rows are
+// 16-byte aligned, i.e. I*G even); writes: lane pairs of adjacent ranks of one
+// column (16-byte stores).  STATS: each column's valid cells (not sentinels)
+// are also summed exactly over the workgroup's ranks -- count, int64 sum,
+// unsigned 128-bit sum of squares, min, max -- and written as rank chunk
+// blockIdx.x of the imbalance column partials (thread = column and quarter of
+// a tile; the four quarters are combined through LDS at the end).
+constexpr int TG = 16;
+
+int transpose_groups_of(int64_t R) { return (int)((pad_ranks(R) / TT + TG - 1) / TG); }
+
+template <bool STATS>
 __global__ __launch_bounds__(256) void transpose_kernel(const int64_t *__restrict__ T, int64_t R,
                                                         int IG, int G, const int32_t *it,
-                                                        int64_t *__restrict__ Tt) {
+                                                        int64_t *__restrict__ Tt, ColPartials ps) {
   __shared__ int64_t tile[TT][TT + 1];
-  const int64_t r0 = (int64_t)blockIdx.x * TT;
   const int c0 = blockIdx.y * TT;
   const int64_t Rp = pad_ranks(R);
   const int p2 = 2 * (threadIdx.x & 31), k0 = threadIdx.x >> 5;
   const int ca = c0 + p2;  // this thread's columns ca, ca + 1 (read phase)
   const int ia = ca / G, ib = (ca + 1) / G;
   const bool vec = (IG & 1) == 0;
-  for (int k = k0; k < TT; k += 8) {
-    const int64_t r = r0 + k;
-    int64_t v0 = SENT, v1 = SENT;
-    if (r < R) {
-      const int nit = it ? it[r] : 0x7fffffff;
-      const int64_t *row = T + r * IG;
-      if (vec && ca + 1 < IG) {
-        const v2ll q = __builtin_nontemporal_load(reinterpret_cast<const v2ll *>(row + ca));
-        v0 = ia < nit ? (int64_t)q.x : SENT;
-        v1 = ib < nit ? (int64_t)q.y : SENT;
-      } else {
-        if (ca < IG && ia < nit) v0 = __builtin_nontemporal_load(row + ca);
-        if (ca + 1 < IG && ib < nit) v1 = __builtin_nontemporal_load(row + ca + 1);
+  const int sc = threadIdx.x & 63, sq = threadIdx.x >> 6;  // stats: column, quarter of a tile
+  int64_t n = 0, s1 = 0, mn = INT64_MAX, mx = INT64_MIN;
+  u128 s2 = 0;
+  const int64_t n_tiles = Rp / TT;
+  for (int64_t tl = (int64_t)blockIdx.x * TG; tl < n_tiles && tl < (int64_t)(blockIdx.x + 1) * TG; tl++) {
+    const int64_t r0 = tl * TT;
+    for (int k = k0; k < TT; k += 8) {
+      const int64_t r = r0 + k;
+      int64_t v0 = SENT, v1 = SENT;
+      if (r < R) {
+        const int nit = it ? it[r] : 0x7fffffff;
+        const int64_t *row = T + r * IG;
+        if (vec && ca + 1 < IG) {
+          const v2ll q = __builtin_nontemporal_load(reinterpret_cast<const v2ll *>(row + ca));
+          v0 = ia < nit ? (int64_t)q.x : SENT;
+          v1 = ib < nit ? (int64_t)q.y : SENT;
+        } else {
+          if (ca < IG && ia < nit) v0 = __builtin_nontemporal_load(row + ca);
+          if (ca + 1 < IG && ib < nit) v1 = __builtin_nontemporal_load(row + ca + 1);
+        }
+      }
+      tile[k][p2] = v0;
+      tile[k][p2 + 1] = v1;
+    }
+    __syncthreads();
+    for (int k = k0; k < TT; k += 8) {
+      const int c = c0 + k;
+      if (c < IG) {
+        const v2ll q = {tile[p2][k], tile[p2 + 1][k]};
+        *reinterpret_cast<v2ll *>(Tt + (int64_t)c * Rp + r0 + p2) = q;
       }
     }
-    tile[k][p2] = v0;
-    tile[k][p2 + 1] = v1;
+    if (STATS) {
+#pragma unroll 4
+      for (int k = sq * 16; k < sq * 16 + 16; k++) {
+        const int64_t x = tile[k][sc];
+        if (x != SENT) {
+          n++;
+          s1 += x;
+          s2 += (u128)((i128)x * x);
+          mn = x < mn ? x : mn;
+          mx = x > mx ? x : mx;
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int k = k0; k < TT; k += 8) {
-    const int c = c0 + k;
-    if (c < IG) {
-      const v2ll q = {tile[p2][k], tile[p2 + 1][k]};
-      *reinterpret_cast<v2ll *>(Tt + (int64_t)c * Rp + r0 + p2) = q;
+  if (STATS) {
+    // combine the four quarters of each column (reusing the tile's LDS)
+    int64_t *red = &tile[0][0];  // [6][4][64]
+    const int b = sq * 64 + sc;
+    red[0 * 256 + b] = n;
+    red[1 * 256 + b] = s1;
+    red[2 * 256 + b] = (int64_t)(uint64_t)s2;
+    red[3 * 256 + b] = (int64_t)(uint64_t)(s2 >> 64);
+    red[4 * 256 + b] = mn;
+    red[5 * 256 + b] = mx;
+    __syncthreads();
+    if (threadIdx.x < 64 && c0 + sc < IG) {
+      int64_t tn = 0, ts1 = 0, tmn = INT64_MAX, tmx = INT64_MIN;
+      u128 ts2 = 0;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int j = q * 64 + sc;
+        tn += red[0 * 256 + j];
+        ts1 += red[1 * 256 + j];
+        ts2 += ((u128)(uint64_t)red[3 * 256 + j] << 64) | (uint64_t)red[2 * 256 + j];
+        tmn = red[4 * 256 + j] < tmn ? red[4 * 256 + j] : tmn;
+        tmx = red[5 * 256 + j] > tmx ? red[5 * 256 + j] : tmx;
+      }
+      const int64_t p = (int64_t)blockIdx.x * IG + c0 + sc;
+      ps.n[p] = tn;
+      ps.s1[p] = ts1;
+      ps.lo[p] = (uint64_t)ts2;
+      ps.hi[p] = (uint64_t)(ts2 >> 64);
+      ps.mn[p] = tmn;
+      ps.mx[p] = tmx;
     }
   }
 }
@@ -1117,8 +1179,15 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
   if (a.R > 0) {
     if (a.mode == TA_SCAN_FULL) {
       if (IG > 0) {
-        hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)(pad_ranks(a.R) / TT), (IG + TT - 1) / TT),
-                           dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, w.Tt);
+        const dim3 tg((unsigned)transpose_groups_of(a.R), (IG + TT - 1) / TT);
+        if (a.stats.rc > 0) {
+          if (a.stats.rc != transpose_groups_of(a.R)) return hipErrorInvalidValue;
+          hipLaunchKernelGGL(transpose_kernel<true>, tg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, w.Tt,
+                             a.stats);
+        } else {
+          hipLaunchKernelGGL(transpose_kernel<false>, tg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, w.Tt,
+                             a.stats);
+        }
         if (mad && pad_ranks(a.R) < SEL_BRACKET_MIN_RP) {
           hipLaunchKernelGGL(col_select_radix, dim3(IG), dim3(CS), 0, s, w.Tt, a.R, w.cs);
         } else if (mad) {
@@ -1162,5 +1231,7 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
   hipLaunchKernelGGL(count_final, dim3(1), dim3(256), 0, s, w.part, (int64_t)nr, a.n_flagged);
   return hipGetLastError();
 }
+
+int transpose_groups(int64_t R) { return transpose_groups_of(R); }
 
 }  // namespace ta

@@ -310,9 +310,9 @@ int rank_chunks(int64_t R, int IG) {
   return (int)rc;
 }
 
-ColWs carve(void *ws, int64_t R, int I, int G, bool rankst, size_t *used) {
+ColWs carve(void *ws, int64_t R, int I, int G, bool rankst, size_t *used, int rc_ext = 0) {
   const int IG = I * G;
-  const int RC = rank_chunks(R, IG);
+  const int RC = rc_ext > 0 ? rc_ext : rank_chunks(R, IG);
   WsCursor c{(char *)ws};
   ColWs w;
   w.p_n = c.take<int64_t>((size_t)RC * IG);
@@ -338,21 +338,38 @@ ColWs carve(void *ws, int64_t R, int I, int G, bool rankst, size_t *used) {
 
 }  // namespace
 
-size_t imbalance_ws_bytes(int64_t R, int32_t I, int32_t G, bool need_rank_stats) {
+size_t imbalance_ws_bytes(int64_t R, int32_t I, int32_t G, bool need_rank_stats, int rc_ext) {
   size_t used = 0;
-  carve((void *)0x100, R, I, G, need_rank_stats, &used);
+  carve((void *)0x100, R, I, G, need_rank_stats, &used, rc_ext);
   return used + 256;
 }
 
-hipError_t launch_imbalance(const ImbArgs &a, void *ws, size_t ws_bytes, hipStream_t s) {
+ColPartials imbalance_partials(void *ws, int64_t R, int32_t I, int32_t G, bool need_rank_stats,
+                               int rc_ext) {
+  size_t used = 0;
+  ColWs w = carve(ws, R, I, G, need_rank_stats, &used, rc_ext);
+  ColPartials p{};
+  p.n = w.p_n;
+  p.s1 = w.p_s1;
+  p.mn = w.p_mn;
+  p.mx = w.p_mx;
+  p.lo = w.p_lo;
+  p.hi = w.p_hi;
+  p.rc = rc_ext;
+  return p;
+}
+
+hipError_t launch_imbalance(const ImbArgs &a, void *ws, size_t ws_bytes, hipStream_t s, int rc_ext) {
   const bool rankst = a.rank_sum == nullptr || a.rank_sumsq == nullptr;
   size_t used = 0;
-  ColWs w = carve(ws, a.R, a.I, a.G, rankst, &used);
+  ColWs w = carve(ws, a.R, a.I, a.G, rankst, &used, rc_ext);
   if (used > ws_bytes) return hipErrorInvalidValue;
   const int IG = a.I * a.G;
-  const int RC = rank_chunks(a.R, IG);
+  const int RC = rc_ext > 0 ? rc_ext : rank_chunks(a.R, IG);
   const int64_t rpc = (a.R + RC - 1) / RC;
-  if (IG > 0 && a.R > 0) {
+  if (rc_ext > 0) {
+    // partials already written (by the FULL scan's transpose)
+  } else if (IG > 0 && a.R > 0) {
     hipLaunchKernelGGL(colstats_partial, dim3((IG + CT - 1) / CT, RC), dim3(CT), 0, s, a.T, a.R,
                        IG, a.G, a.it, rpc, w);
   } else if (IG > 0) {

@@ -1029,11 +1029,17 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
   }
   L.a.order = p->d_order;
   const int I = d->n_iters, G = h->G;
-  size_t ws = 0;
-  if (d->with_imbalance)
-    ws = std::max(ws, ta::imbalance_ws_bytes(R, I, G, !d->seg.rank_sum || !d->seg.rank_sumsq));
-  if (d->with_outliers)
-    ws = std::max(ws, ta::outliers_ws_bytes(R, I, G, d->outlier_mode, d->outlier_kind));
+  // With both the imbalance statistics and the FULL outlier scan, the scan's
+  // transpose also writes the imbalance column partials (one read of the
+  // tensor instead of two); the two workspaces then sit side by side.
+  const bool need_rs = !d->seg.rank_sum || !d->seg.rank_sumsq;
+  const bool fuse = d->with_imbalance && d->with_outliers && d->outlier_mode == TA_SCAN_FULL &&
+                    R > 0 && (int64_t)I * G > 0;
+  const int rc_t = fuse ? ta::transpose_groups(R) : 0;
+  const size_t ws_out =
+      d->with_outliers ? (ta::outliers_ws_bytes(R, I, G, d->outlier_mode, d->outlier_kind) + 255) / 256 * 256 : 0;
+  const size_t ws_imb = d->with_imbalance ? ta::imbalance_ws_bytes(R, I, G, need_rs, rc_t) : 0;
+  size_t ws = fuse ? ws_out + ws_imb : std::max(ws_out, ws_imb);
   if (ws && hipMalloc(&p->ws, ws) != hipSuccess) {
     p->ws = nullptr;
     plan_free(p);
@@ -1063,7 +1069,8 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
     return hipfail(h, e, "plan capture start");
   }
   hipError_t le = ta::launch_segment(L.a, L.attr, L.seg, best, grid, L.lds, p->cap);
-  if (le == hipSuccess && d->with_imbalance) {
+  void *imb_ws = fuse ? (void *)((char *)p->ws + ws_out) : p->ws;
+  if (le == hipSuccess && d->with_imbalance && !fuse) {
     ta::ImbArgs ia{};
     ia.T = d->seg.tensor;
     ia.R = R;
@@ -1076,7 +1083,7 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
     ia.ddof = d->ddof;
     ia.t_app = d->t_app_ns;
     ia.o = d->imb;
-    le = ta::launch_imbalance(ia, p->ws, ws, p->cap);
+    le = ta::launch_imbalance(ia, imb_ws, fuse ? ws_imb : ws, p->cap, rc_t);
   }
   if (le == hipSuccess && d->with_outliers) {
     ta::OutArgs oa{};
@@ -1092,7 +1099,23 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
     oa.rank_flag = d->rank_flag;
     oa.n_flagged = d->n_flagged;
     oa.region_score = d->region_score;
-    le = ta::launch_outliers(oa, p->ws, ws, p->cap);
+    if (fuse) oa.stats = ta::imbalance_partials(imb_ws, R, I, G, need_rs, rc_t);
+    le = ta::launch_outliers(oa, p->ws, fuse ? ws_out : ws, p->cap);
+  }
+  if (le == hipSuccess && d->with_imbalance && fuse) {
+    ta::ImbArgs ia{};
+    ia.T = d->seg.tensor;
+    ia.R = R;
+    ia.I = I;
+    ia.G = G;
+    ia.it = d->seg.iters_found;
+    ia.rank_sum = (d->seg.rank_sum && d->seg.rank_sumsq) ? d->seg.rank_sum : nullptr;
+    ia.rank_sumsq = (d->seg.rank_sum && d->seg.rank_sumsq) ? d->seg.rank_sumsq : nullptr;
+    ia.span = d->seg.span;
+    ia.ddof = d->ddof;
+    ia.t_app = d->t_app_ns;
+    ia.o = d->imb;
+    le = ta::launch_imbalance(ia, imb_ws, ws_imb, p->cap, rc_t);
   }
   e = hipStreamEndCapture(p->cap, &p->graph);
   if (le != hipSuccess || e != hipSuccess) {

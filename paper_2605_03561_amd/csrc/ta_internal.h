@@ -100,8 +100,23 @@ struct ImbArgs {
   double t_app;
   ta_imbalance_out o;
 };
-hipError_t launch_imbalance(const ImbArgs &a, void *ws, size_t ws_bytes, hipStream_t s);
-size_t imbalance_ws_bytes(int64_t R, int32_t I, int32_t G, bool need_rank_stats);
+// Per-column partial statistics over chunks of ranks, [rc][I*G] each: valid
+// cell count, int64 sum, unsigned 128-bit sum of squares (lo, hi), min, max.
+// Integer partials: how the ranks are split into chunks does not change the
+// combined result.
+struct ColPartials {
+  int64_t *n, *s1, *mn, *mx;
+  uint64_t *lo, *hi;
+  int rc;  // 0: none
+};
+// rc_ext > 0: the partials ([rc_ext] chunks, in the workspace as
+// imbalance_partials() places them) were written by another kernel (the FULL
+// outlier scan's transpose), so the column pass over the tensor is skipped.
+hipError_t launch_imbalance(const ImbArgs &a, void *ws, size_t ws_bytes, hipStream_t s,
+                            int rc_ext = 0);
+size_t imbalance_ws_bytes(int64_t R, int32_t I, int32_t G, bool need_rank_stats, int rc_ext = 0);
+ColPartials imbalance_partials(void *ws, int64_t R, int32_t I, int32_t G, bool need_rank_stats,
+                               int rc_ext);
 
 struct OutArgs {
   const int64_t *T;
@@ -114,7 +129,12 @@ struct OutArgs {
   uint8_t *rank_flag;
   int64_t *n_flagged;
   double *region_score;
+  // FULL scan: the transpose also writes the imbalance column partials here
+  // (stats.rc must be transpose_groups(R)).
+  ColPartials stats;
 };
+// Rank chunks of the FULL scan's transpose (TG tiles of 64 ranks each).
+int transpose_groups(int64_t R);
 // Robust z over active ranks of per-rank region values v_t[G][R] (median and
 // MAD per region, the exact scan's second stage), z_t[G][R], and FP32
 // score[r] = max_g |z|.

@@ -289,6 +289,34 @@ def test_c3_sparse_profiles(mods, oracle, c3):
     h.set_regions(w.marker, w.regions)
 
 
+def test_c3_plan_matches_eager(mods, oracle, c3):
+    """The batch plan at 100k ranks (fused pass, imbalance statistics taken by
+    the FULL scan's transpose, exact outlier scan, one graph) equals the eager
+    calls bit for bit."""
+    torch, gpu_synth, ta = mods
+    w, h, seg, cfg = c3
+    h.set_tree(w.parent)
+    h.set_regions(w.marker, w.regions)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx)
+    print("[fullsize] plan", flush=True)
+    p = h.plan(tr, cfg["n_iters"], w.offsets_host, imbalance=True, outliers=True, autotune=0)
+    p.launch()
+    h.sync_status()
+    imb = h.imbalance(seg["tensor"], seg["iters_found"], seg["rank_sum"], seg["rank_sumsq"],
+                      seg["span"])
+    ol = h.outliers(seg["tensor"], seg["iters_found"])
+    h.sync_status()
+    assert torch.equal(p.seg["tensor"], seg["tensor"])
+    for k in p.imb:
+        a, b = p.imb[k], imb[k]
+        assert torch.equal(torch.nan_to_num(a, nan=1.5), torch.nan_to_num(b, nan=1.5)), k
+    for k in ("rank_score", "rank_flag", "n_flagged"):
+        assert torch.equal(p.out[k], ol[k]), k
+    p.close()
+    del p
+    torch.cuda.empty_cache()
+
+
 def test_c2_shape_full_parity(mods, oracle):
     torch, gpu_synth, ta = mods
     w = gpu_synth.timeline_on_gpu(seed=4, n_ranks=3000, median_len=6000, min_len=1000,
