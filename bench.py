@@ -319,11 +319,14 @@ def window_sparse_summary(tr, w, steps, seed):
     byt["window_middle_tenth"] = 12 * n_in + 16 * N
     ms["window_whole"], (we, wi) = timed(lambda: h.window_profile(tr, lo, hi))
     byt["window_whole"] = 12 * E + 8 * (R + 1) + 16 * N
-    ms["sparse_profiles"], (cnt, ids, vals) = timed(lambda: h.sparse_profiles(tr))
+    sp = (torch.empty((R,), dtype=torch.int64, device=w["ts"].device),
+          torch.empty((E,), dtype=torch.int32, device=w["ts"].device),
+          torch.empty((E,), dtype=torch.int64, device=w["ts"].device))
+    ms["sparse_profiles"], (cnt, ids, vals) = timed(lambda: h.sparse_profiles(tr, out=sp))
     nnz = int(cnt.sum().item())
     byt["sparse_profiles"] = 12 * E + 8 * (R + 1) + 8 * R + 12 * nnz
     h.sync_status()
-    del cnt, ids, vals, we, wi
+    del cnt, ids, vals, we, wi, sp
     h.close()
     torch.cuda.empty_cache()
     # the paper's scale: a 97,833-node tree (10,000 ranks, lognormal lengths)
@@ -334,13 +337,16 @@ def window_sparse_summary(tr, w, steps, seed):
     hb.set_tree(wb["parent"])
     trb = ta.DeviceTraces(wb["offsets"], wb["ts"], wb["ctx"])
     Eb = int(wb["offsets_host"][-1])
-    ms["sparse_profiles_97833_nodes"], (cb, ib, vb) = timed(lambda: hb.sparse_profiles(trb))
+    spb = (torch.empty((big["n_ranks"],), dtype=torch.int64, device=w["ts"].device),
+           torch.empty((Eb,), dtype=torch.int32, device=w["ts"].device),
+           torch.empty((Eb,), dtype=torch.int64, device=w["ts"].device))
+    ms["sparse_profiles_97833_nodes"], (cb, ib, vb) = timed(lambda: hb.sparse_profiles(trb, out=spb))
     nnzb = int(cb.sum().item())
     byt["sparse_profiles_97833_nodes"] = 12 * Eb + 16 * big["n_ranks"] + 12 * nnzb
     hb.sync_status()
     dense_bytes = 8 * big["n_ranks"] * big["n_nodes"]
     hb.close()
-    del cb, ib, vb, trb, wb
+    del cb, ib, vb, trb, wb, spb
     torch.cuda.empty_cache()
     gbs = {k: byt[k] / (ms[k] / 1e3) / 1e9 for k in byt}
     out = {"window": [a, b], "events_in_window": n_in, "sparse_nonzeros": nnz,

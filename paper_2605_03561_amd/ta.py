@@ -341,14 +341,21 @@ class Handle:
                                            _ptr(e), _ptr(i), _stream(self.device)))
         return e, i
 
-    def sparse_profiles(self, tr: DeviceTraces):
+    def sparse_profiles(self, tr: DeviceTraces, out=None):
         """Per rank, the non-zero exclusive costs in ascending node id: device
         (counts [R], node_ids [E], excl [E]); rank r's entries sit at
-        [offsets[r], offsets[r] + counts[r])."""
+        [offsets[r], offsets[r] + counts[r]).  `out` may hold those three
+        preallocated tensors."""
         R, E = tr.n_ranks, tr.n_events
-        counts = self._empty((R,), torch.int64)
-        ids = self._empty((E,), torch.int32)
-        ex = self._empty((E,), torch.int64)
+        if out is None:
+            counts = self._empty((R,), torch.int64)
+            ids = self._empty((E,), torch.int32)
+            ex = self._empty((E,), torch.int64)
+        else:
+            counts, ids, ex = out
+            if (counts.numel() < R or ids.numel() < E or ex.numel() < E or counts.dtype != torch.int64
+                    or ids.dtype != torch.int32 or ex.dtype != torch.int64):
+                raise ValueError("out must be (int64[R], int32[E], int64[E]) tensors")
         t = tr.struct()
         self._check(_lib.ta_sparse_profiles(self.h, C.byref(t), _ptr(counts), _ptr(ids), _ptr(ex),
                                             _stream(self.device)))
