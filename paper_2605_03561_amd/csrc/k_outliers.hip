@@ -812,6 +812,455 @@ __global__ __launch_bounds__(256) void score_cols(const int64_t *__restrict__ Tt
   if (r < R) m_t[(int64_t)g * R + r] = ni > 0 ? acc / (double)ni : 0.0;
 }
 
+// ----------------------------------------------------------------------------
+// Row-major path for the robust FULL scan over long columns (no transpose).
+//   rm_sample    MS cells of every column at fixed ranks (MS / 2 chunks of two
+//                consecutive ranks, evenly spread), column-major Smp[IG][MS];
+//                also clears the column cursors
+//   rm_brackets  per column, the sample's order statistics around its middle
+//   rm_pass      one streaming pass over the row-major tensor in 64 x 64 tiles
+//                (LDS): per column and rank group, the counts below / equal to
+//                the bracket ends (and the imbalance partials, or the sum of
+//                deviations); the bracket interiors are appended to a scratch
+//                region per column (one cursor atomic per column and tile)
+//   rm_select    per column, exact selection over the compacted interior, or
+//                over a gathered copy of the whole column when the bracket
+//                misses the middle or the interior overflows the region; the
+//                median step also brackets the MAD from the sample's
+//                deviations
+//   score_rows   m(r,g) from the row-major tensor, a wave = SRW ranks x 64
+//                regions
+// The same MAD pass runs on the deviations |2x - med2| once the medians are
+// known.  Every count is an integer and every selection exact, so the results
+// equal the column-major path's.
+// ----------------------------------------------------------------------------
+__host__ __device__ inline int64_t sample_rank(int j, int64_t Rp) {
+  return ((((int64_t)(j >> 1)) * Rp / (MS / 2)) & ~(int64_t)1) + (j & 1);
+}
+
+__global__ __launch_bounds__(256) void rm_sample(const int64_t *__restrict__ T, int64_t R, int IG,
+                                                 int G, const int32_t *it, int64_t *__restrict__ smp) {
+  __shared__ int64_t tile[TT][TT + 1];
+  const int c0 = blockIdx.y * TT;
+  const int j0 = blockIdx.x * TT;
+  const int64_t Rp = pad_ranks(R);
+  const int p2 = 2 * (threadIdx.x & 31), k0 = threadIdx.x >> 5;
+  const int ca = c0 + p2;
+  const int ia = ca / G, ib = (ca + 1) / G;
+  const bool vec = (IG & 1) == 0;
+  for (int k = k0; k < TT; k += 8) {
+    const int64_t r = sample_rank(j0 + k, Rp);
+    int64_t v0 = SENT, v1 = SENT;
+    if (r < R) {
+      const int nit = it ? it[r] : 0x7fffffff;
+      const int64_t *row = T + r * IG;
+      if (vec && ca + 1 < IG) {
+        const v2ll q = *reinterpret_cast<const v2ll *>(row + ca);
+        v0 = ia < nit ? (int64_t)q.x : SENT;
+        v1 = ib < nit ? (int64_t)q.y : SENT;
+      } else {
+        if (ca < IG && ia < nit) v0 = row[ca];
+        if (ca + 1 < IG && ib < nit) v1 = row[ca + 1];
+      }
+    }
+    tile[k][p2] = v0;
+    tile[k][p2 + 1] = v1;
+  }
+  __syncthreads();
+  for (int k = k0; k < TT; k += 8) {
+    const int c = c0 + k;
+    if (c < IG) {
+      const v2ll q = {tile[p2][k], tile[p2 + 1][k]};
+      *reinterpret_cast<v2ll *>(smp + (int64_t)c * MS + j0 + p2) = q;
+    }
+  }
+}
+
+// The valid sample values of column c into L.samp (as deviations |2x - med2|
+// with DEV); returns their count.
+template <bool DEV>
+__device__ int load_sample(ColSelLds &L, const int64_t *__restrict__ s, int64_t med2) {
+  if (threadIdx.x == 0) L.ns = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < MS; j += CS) {
+    const int64_t x = s[j];
+    if (x != SENT) {
+      int64_t v = x;
+      if (DEV) {
+        const int64_t d = 2 * x - med2;
+        v = d < 0 ? -d : d;
+      }
+      L.samp[atomicAdd(&L.ns, 1u)] = v;
+    }
+  }
+  __syncthreads();
+  return (int)L.ns;
+}
+
+__global__ __launch_bounds__(CS) void rm_brackets(const int64_t *__restrict__ smp, int IG,
+                                                  int64_t *qa, int64_t *qb) {
+  __shared__ ColSelLds L;
+  const int c = blockIdx.x;
+  for (int j = threadIdx.x; j < NHC * NB; j += CS) (&L.hist[0][0])[j] = 0;
+  const int m = load_sample<false>(L, smp + (int64_t)c * MS, 0);
+  int64_t a, b;
+  sample_bracket(L, m, a, b);
+  if (threadIdx.x == 0) {
+    qa[c] = a;
+    qb[c] = b;
+  }
+}
+
+// Per (rank chunk, column) counts of one bracket pass.
+struct RmPart {
+  int32_t *n, *cl, *cea, *ceb, *cm;  // [chunks][IG]; cm: cells in the chunk's interior slot
+  int64_t *sd;                       // [chunks][IG] (MAD pass)
+};
+
+// Bracket per column: (qa, qb) for the median pass; (da, db) and med2 for the
+// MAD pass.
+struct RmBr {
+  const int64_t *a, *b, *med2;
+};
+
+constexpr int RCH = TG * TT;   // ranks per chunk (the imbalance partials' chunk)
+constexpr int RPU = 8;         // rows in flight per thread
+constexpr int SEG_MAX = 2048;  // chunks per column the selection can visit (LDS)
+
+// Counts and compaction of one column's cells against its bracket.
+template <bool MAD, bool STATS>
+struct RmCol {
+  int64_t a, b, m;
+  int32_t n = 0, cl = 0, cea = 0, ceb = 0, cm = 0;
+  int64_t sd = 0, s1 = 0, mn = INT64_MAX, mx = INT64_MIN;
+  u128 s2 = 0;
+  __device__ __forceinline__ void cell(int64_t x, int64_t *__restrict__ slot) {
+    int64_t key = x;
+    if (MAD) {
+      const int64_t d = 2 * x - m;
+      key = d < 0 ? -d : d;
+      sd += key;
+    }
+    n++;
+    cl += key < a ? 1 : 0;
+    cea += key == a ? 1 : 0;
+    ceb += (key == b && b != a) ? 1 : 0;
+    if (STATS) {
+      s1 += x;
+      s2 += (u128)((i128)x * x);
+      mn = x < mn ? x : mn;
+      mx = x > mx ? x : mx;
+    }
+    if (key > a && key < b) slot[cm++] = key;
+  }
+  __device__ __forceinline__ void flush(int64_t p, RmPart pp, ColPartials ps) {
+    if (!MAD) pp.n[p] = n;
+    pp.cl[p] = cl;
+    pp.cea[p] = cea;
+    pp.ceb[p] = ceb;
+    pp.cm[p] = cm;
+    if (MAD) pp.sd[p] = sd;
+    if (STATS) {
+      ps.n[p] = n;
+      ps.s1[p] = s1;
+      ps.lo[p] = (uint64_t)s2;
+      ps.hi[p] = (uint64_t)(s2 >> 64);
+      ps.mn[p] = mn;
+      ps.mx[p] = mx;
+    }
+  }
+};
+
+// One streaming pass over the row-major tensor: a thread owns two adjacent
+// columns (16-byte loads; a wave reads 1 KB of a row) and walks the RCH ranks
+// of chunk blockIdx.y, RPU rows in flight, counting in registers; the bracket
+// interior of each (chunk, column) goes to its own slot of RCH cells, so no
+// atomics and no overflow.  No LDS and no barriers.
+template <bool MAD, bool STATS>
+__global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, int64_t R, int IG, int G,
+                                               const int32_t *it, RmBr br, int64_t *__restrict__ scr,
+                                               RmPart pp, ColPartials ps) {
+  const int ca = ((int)blockIdx.x * 256 + (int)threadIdx.x) * 2;
+  if (ca >= IG) return;
+  const int64_t ng = gridDim.y, ch = blockIdx.y;
+  const bool two = ca + 1 < IG;
+  const int ia = ca / G, ib = (ca + 1) / G;
+  RmCol<MAD, STATS> c0, c1;
+  c0.a = br.a[ca];
+  c0.b = br.b[ca];
+  c0.m = MAD ? br.med2[ca] : 0;
+  c1.a = two ? br.a[ca + 1] : INT64_MAX;
+  c1.b = two ? br.b[ca + 1] : INT64_MIN;
+  c1.m = (MAD && two) ? br.med2[ca + 1] : 0;
+  int64_t *slot0 = scr + ((int64_t)ca * ng + ch) * RCH;
+  int64_t *slot1 = scr + ((int64_t)(ca + 1) * ng + ch) * RCH;
+  const bool vec = (IG & 1) == 0;
+  const int64_t rb = ch * RCH, re = rb + RCH < R ? rb + RCH : R;
+  for (int64_t r0 = rb; r0 < re; r0 += RPU) {
+    v2ll v[RPU];
+#pragma unroll
+    for (int u = 0; u < RPU; u++) {
+      const int64_t r = r0 + u;
+      v[u] = v2ll{SENT, SENT};
+      if (r < re) {
+        const int64_t *row = T + r * IG + ca;
+        if (vec) {
+          v[u] = __builtin_nontemporal_load(reinterpret_cast<const v2ll *>(row));
+        } else {
+          v[u].x = __builtin_nontemporal_load(row);
+          if (two) v[u].y = __builtin_nontemporal_load(row + 1);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RPU; u++) {
+      const int64_t r = r0 + u;
+      if (r < re) {
+        const int nit = it ? it[r] : 0x7fffffff;
+        if (ia < nit) c0.cell((int64_t)v[u].x, slot0);
+        if (two && ib < nit) c1.cell((int64_t)v[u].y, slot1);
+      }
+    }
+  }
+  c0.flush(ch * IG + ca, pp, ps);
+  if (two) c1.flush(ch * IG + ca + 1, pp, ps);
+}
+
+// Column c of the row-major tensor into slot[0..Rp) (SENT for cells of missing
+// iterations and padding); returns the column's min and max over valid cells.
+__device__ void gather_column(const int64_t *__restrict__ T, int64_t R, int IG, int G, const int32_t *it,
+                              int c, int64_t *__restrict__ slot, SelLds &L, int64_t &mn, int64_t &mx) {
+  constexpr int U = 8;
+  const int64_t Rp = pad_ranks(R);
+  const int i = c / G;
+  int64_t mnl = INT64_MAX, mxl = INT64_MIN;
+  for (int64_t r0 = 0; r0 < Rp; r0 += (int64_t)CS * U) {
+    int64_t v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t r = r0 + (int64_t)u * CS + threadIdx.x;
+      v[u] = SENT;
+      if (r < R && (it ? it[r] : 0x7fffffff) > i) v[u] = T[r * IG + c];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t r = r0 + (int64_t)u * CS + threadIdx.x;
+      if (r < Rp) slot[r] = v[u];
+      if (v[u] != SENT) {
+        mnl = v[u] < mnl ? v[u] : mnl;
+        mxl = v[u] > mxl ? v[u] : mxl;
+      }
+    }
+  }
+  int64_t none[1] = {0};
+  mn = mnl;
+  mx = mxl;
+  block_stats<1, true>(none, mn, mx, L.red);  // its barriers also order the slot writes
+}
+
+struct RmOut {
+  int64_t *da, *db;  // MAD brackets, written by the median step
+};
+
+// Per column (persistent grid, a gather slot of Rp cells per workgroup).
+constexpr int SU = 4;  // chunk slots read together by a wave
+
+template <bool MAD>
+__global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
+    const int64_t *__restrict__ T, int64_t R, int IG, int G, const int32_t *it,
+    const int64_t *__restrict__ smp, int ng, RmPart pp, RmBr br, const int64_t *__restrict__ scr,
+    int64_t *__restrict__ slots, RmOut ro, ColSel out) {
+  __shared__ ColSelLds L;
+  __shared__ int32_t segn[SEG_MAX];
+  const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
+  const int64_t Rp = pad_ranks(R);
+  int64_t *slot = slots + (int64_t)blockIdx.x * Rp;
+  for (int j = t; j < NHC * NB; j += CS) (&L.hist[0][0])[j] = 0;
+  for (int c = blockIdx.x; c < IG; c += gridDim.x) {
+    // the chunk partials, summed; the chunk slots' fill counts into LDS
+    int64_t sums[5] = {0, 0, 0, 0, 0};
+    for (int g = t; g < ng; g += CS) {
+      const int64_t p = (int64_t)g * IG + c;
+      sums[0] += MAD ? pp.sd[p] : pp.n[p];
+      sums[1] += pp.cl[p];
+      sums[2] += pp.cea[p];
+      sums[3] += pp.ceb[p];
+      const int32_t cm = pp.cm[p];
+      sums[4] += cm;
+      segn[g] = cm;
+    }
+    int64_t u0 = 0, u1 = 0;
+    block_stats<5, false>(sums, u0, u1, L.red);  // its barriers publish segn
+    const int64_t clo = sums[1], ceqa = sums[2], ceqb = sums[3], cmid = sums[4];
+    const int64_t qa = br.a[c], qb = br.b[c];
+    const int64_t n = MAD ? out.n[c] : sums[0];
+    // the interior cells: wave wv reads chunk slots wv, wv + CWV, ..., SU of
+    // them (two cells per lane each) per round trip
+    const int64_t *colscr = scr + (int64_t)c * ng * RCH;
+    auto vscr = [&](auto &&f) {
+      for (int g0 = wv; g0 < ng; g0 += CWV * SU) {
+        int64_t v0[SU], v1[SU];
+        int cn[SU];
+#pragma unroll
+        for (int u = 0; u < SU; u++) {
+          const int g = g0 + u * CWV;
+          cn[u] = g < ng ? segn[g] : 0;
+          const int64_t *sp = colscr + (int64_t)g * RCH;
+          v0[u] = ln < cn[u] ? sp[ln] : 0;
+          v1[u] = ln + 64 < cn[u] ? sp[ln + 64] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < SU; u++) {
+          if (ln < cn[u]) f(v0[u]);
+          if (ln + 64 < cn[u]) f(v1[u]);
+          if (cn[u] > 128) {
+            const int64_t *sp = colscr + (int64_t)(g0 + u * CWV) * RCH;
+            for (int e = ln + 128; e < cn[u]; e += 64) f(sp[e]);
+          }
+        }
+      }
+    };
+    auto vslot = [&](auto &&f) {
+      sweep(slot, Rp, [&](int64_t x) {
+        if (x != SENT) f(x);
+      });
+    };
+    if (n == 0) {
+      if (t == 0) {
+        if (!MAD) {
+          out.med2[c] = 0;
+          out.n[c] = 0;
+          ro.da[c] = INT64_MAX;  // empty bracket: the MAD pass compacts nothing
+          ro.db[c] = INT64_MIN;
+        } else {
+          out.mad4[c] = 0;
+          out.sumdev[c] = 0;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    const int64_t k = (n - 1) / 2;
+    const bool even = (n & 1) == 0;
+    int64_t x1, x2;
+    if (!MAD) {
+      if (!bracket_pick(vscr, clo, ceqa, cmid, ceqb, qa, qb, INT64_MAX, k, even, L, x1, x2)) {
+        int64_t mn, mx;
+        gather_column(T, R, IG, G, it, c, slot, L, mn, mx);
+        uint64_t a1, a2;
+        radix_select(vslot, k, even, nbits64((uint64_t)mx - (uint64_t)mn),
+                     [&](int64_t x) { return (uint64_t)x - (uint64_t)mn; }, L, a1, a2);
+        x1 = (int64_t)((uint64_t)mn + a1);
+        x2 = (int64_t)((uint64_t)mn + a2);
+      }
+      const int64_t med2 = x1 + x2;
+      __syncthreads();  // the sample slots are rewritten below
+      const int m = load_sample<true>(L, smp + (int64_t)c * MS, med2);
+      int64_t da, db;
+      sample_bracket(L, m, da, db);
+      if (t == 0) {
+        out.med2[c] = med2;
+        out.n[c] = n;
+        ro.da[c] = da;
+        ro.db[c] = db;
+      }
+    } else {
+      const int64_t med2 = br.med2[c];
+      if (!bracket_pick(vscr, clo, ceqa, cmid, ceqb, qa, qb, INT64_MAX, k, even, L, x1, x2)) {
+        int64_t mn, mx;
+        gather_column(T, R, IG, G, it, c, slot, L, mn, mx);
+        const uint64_t dlo = (uint64_t)(med2 - 2 * mn), dhi = (uint64_t)(2 * mx - med2);
+        const uint64_t dmax = dlo > dhi ? dlo : dhi;
+        uint64_t a1, a2;
+        radix_select(vslot, k, even, nbits64(dmax),
+                     [&](int64_t x) {
+                       const int64_t d = 2 * x - med2;
+                       return (uint64_t)(d < 0 ? -d : d);
+                     },
+                     L, a1, a2);
+        x1 = (int64_t)a1;
+        x2 = (int64_t)a2;
+      }
+      if (t == 0) {
+        out.mad4[c] = x1 + x2;
+        out.sumdev[c] = sums[0];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// m(r,g) = (1/n_r) sum_{i < n_r} z(r,i,g) (ascending i) from the row-major
+// tensor, written [G][R]; a wave = SRW consecutive ranks x 64 regions (lane =
+// region), so each row read is contiguous and the column parameters are read
+// once per SRW ranks.
+constexpr int SRW = 8;
+
+__device__ inline double robust_z(int64_t x, int64_t med2, int64_t mad4, int64_t sdv, int64_t n) {
+  if (mad4 > 0) return (double)(4 * x - 2 * med2) / (1.4826 * (double)mad4);
+  return sdv > 0 ? ((double)(2 * x - med2) * (double)n) / (1.253314 * (double)sdv) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void score_rows(const int64_t *__restrict__ T, int64_t R, int I, int G,
+                                                  const int32_t *it, ColSel cs, double *m_t) {
+  const int lane = threadIdx.x & 63;
+  const int gbn = (G + 63) / 64;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r0 = (wave / gbn) * SRW;
+  if (r0 >= R) return;
+  const int g = (int)(wave % gbn) * 64 + lane;
+  const bool gl = g < G;
+  const int64_t IG = (int64_t)I * G;
+  int ni[SRW];
+  int nmax = 0;
+#pragma unroll
+  for (int q = 0; q < SRW; q++) {
+    int v = 0;
+    if (r0 + q < R) {
+      v = it ? it[r0 + q] : I;
+      v = v > I ? I : (v < 0 ? 0 : v);
+    }
+    ni[q] = v;
+    nmax = v > nmax ? v : nmax;
+  }
+  double acc[SRW];
+#pragma unroll
+  for (int q = 0; q < SRW; q++) acc[q] = 0.0;
+  const int gg = gl ? g : 0;
+  const int64_t *base = T + r0 * IG + gg;
+  // iteration i's cells and column parameters; those of i + 1 are loaded
+  // before i is scored
+  int64_t x[SRW], med2 = 0, mad4 = 0;
+  auto load = [&](int i) {
+#pragma unroll
+    for (int q = 0; q < SRW; q++)
+      x[q] = i < ni[q] ? __builtin_nontemporal_load(base + q * IG + (int64_t)i * G) : 0;
+    med2 = cs.med2[(int64_t)i * G + gg];
+    mad4 = cs.mad4[(int64_t)i * G + gg];
+  };
+  if (nmax > 0) load(0);
+  for (int i = 0; i < nmax; i++) {
+    int64_t xc[SRW];
+#pragma unroll
+    for (int q = 0; q < SRW; q++) xc[q] = x[q];
+    const int64_t m2 = med2, m4 = mad4;
+    if (i + 1 < nmax) load(i + 1);
+    int64_t sdv = 0, nc = 0;
+    if (m4 <= 0) {
+      sdv = cs.sumdev[(int64_t)i * G + gg];
+      nc = cs.n[(int64_t)i * G + gg];
+    }
+#pragma unroll
+    for (int q = 0; q < SRW; q++)
+      if (i < ni[q]) acc[q] += robust_z(xc[q], m2, m4, sdv, nc);
+  }
+  if (gl) {
+#pragma unroll
+    for (int q = 0; q < SRW; q++)
+      if (r0 + q < R) m_t[(int64_t)g * R + r0 + q] = ni[q] > 0 ? acc[q] / (double)ni[q] : 0.0;
+  }
+}
+
 // Rank totals S(r,g), transposed [G][R].
 __global__ __launch_bounds__(256) void rank_totals_t(const int64_t *__restrict__ T, int64_t R, int I,
                                                      int G, const int32_t *it, int64_t *S_t) {
@@ -1106,8 +1555,13 @@ __global__ __launch_bounds__(256) void rank_max_f32(const double *z_t, int64_t R
 }
 
 struct OWs {
-  int64_t *Tt;      // [IG][Rp] column-major copy of the tensor (FULL)
-  int64_t *scr;     // [min(IG, SEL_GRID_MAX)][sel_cap(R)] bracket values (FULL + MAD)
+  int64_t *Tt;      // [IG][Rp] column-major copy of the tensor (FULL, short columns or z-score)
+  int64_t *scr;     // row-major path: [IG][chunks][RCH] bracket interiors per column and chunk;
+                    // column-major bracket path: [min(IG, SEL_GRID_MAX)][sel_cap(R)]
+  int64_t *smp;     // row-major path: [IG][MS] column samples
+  int64_t *slots;   // row-major path: [min(IG, SEL_GRID_MAX)][Rp] gathered columns
+  int64_t *qa, *qb, *da, *db;  // row-major path: [IG] brackets
+  RmPart rp;        // row-major path: [groups][IG] pass counts
   ColSel cs;
   ColMom cm;
   double *m_t;      // [G][R] doubles (FULL) -- also reused as z_t
@@ -1115,6 +1569,12 @@ struct OWs {
   double *z_t;      // [G][R]
   int64_t *part;    // [ceil(R/256)]
 };
+
+// The robust FULL scan over long columns runs on the row-major tensor.
+inline bool row_major_path(int64_t R, int mode, int kind) {
+  return mode == TA_SCAN_FULL && kind == TA_SCORE_MAD && pad_ranks(R) >= SEL_BRACKET_MIN_RP &&
+         transpose_groups_of(R) <= SEG_MAX;
+}
 
 OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
   size_t off = 0;
@@ -1126,9 +1586,25 @@ OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
   const size_t IG = (size_t)I * G;
   OWs w{};
   if (mode == TA_SCAN_FULL) {
-    w.Tt = (int64_t *)take((size_t)pad_ranks(R) * IG * 8);
-    if (kind == TA_SCORE_MAD && pad_ranks(R) >= SEL_BRACKET_MIN_RP) {
-      w.scr = (int64_t *)take((size_t)std::min<size_t>(IG, SEL_GRID_MAX) * sel_cap(R) * 8);
+    if (row_major_path(R, mode, kind)) {
+      const size_t ng = (size_t)transpose_groups_of(R);
+      w.scr = (int64_t *)take(IG * ng * RCH * 8);
+      w.smp = (int64_t *)take(IG * MS * 8);
+      w.slots = (int64_t *)take((size_t)std::min<size_t>(IG, SEL_GRID_MAX) * pad_ranks(R) * 8);
+      w.qa = (int64_t *)take(IG * 8);
+      w.qb = (int64_t *)take(IG * 8);
+      w.da = (int64_t *)take(IG * 8);
+      w.db = (int64_t *)take(IG * 8);
+      w.rp.n = (int32_t *)take(ng * IG * 4);
+      w.rp.cl = (int32_t *)take(ng * IG * 4);
+      w.rp.cea = (int32_t *)take(ng * IG * 4);
+      w.rp.ceb = (int32_t *)take(ng * IG * 4);
+      w.rp.cm = (int32_t *)take(ng * IG * 4);
+      w.rp.sd = (int64_t *)take(ng * IG * 8);
+    } else {
+      w.Tt = (int64_t *)take((size_t)pad_ranks(R) * IG * 8);
+      if (kind == TA_SCORE_MAD && pad_ranks(R) >= SEL_BRACKET_MIN_RP)  // more than SEG_MAX chunks
+        w.scr = (int64_t *)take((size_t)std::min<size_t>(IG, SEL_GRID_MAX) * sel_cap(R) * 8);
     }
     if (kind == TA_SCORE_MAD) {
       w.cs.med2 = (int64_t *)take(IG * 8);
@@ -1177,7 +1653,43 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
   const unsigned nb = (unsigned)((a.R * a.G + 255) / 256);
   const bool mad = a.kind == TA_SCORE_MAD;
   if (a.R > 0) {
-    if (a.mode == TA_SCAN_FULL) {
+    if (row_major_path(a.R, a.mode, a.kind)) {
+      if (IG > 0) {
+        const int ng = transpose_groups_of(a.R);
+        const unsigned strips = (unsigned)((IG + TT - 1) / TT);
+        if (a.stats.rc > 0 && a.stats.rc != ng) return hipErrorInvalidValue;
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int grid = std::min(IG, std::min(SEL_GRID_MAX, SEL_WGS_PER_CU * cus));
+        const dim3 pg((unsigned)((IG + 511) / 512), (unsigned)ng);
+        hipLaunchKernelGGL(rm_sample, dim3(MS / TT, strips), dim3(256), 0, s, a.T, a.R, IG, a.G, a.it,
+                           w.smp);
+        hipLaunchKernelGGL(rm_brackets, dim3(IG), dim3(CS), 0, s, (const int64_t *)w.smp, IG, w.qa, w.qb);
+        const RmBr bm{w.qa, w.qb, nullptr};
+        if (a.stats.rc > 0)
+          hipLaunchKernelGGL((rm_pass<false, true>), pg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, bm,
+                             w.scr, w.rp, a.stats);
+        else
+          hipLaunchKernelGGL((rm_pass<false, false>), pg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, bm,
+                             w.scr, w.rp, a.stats);
+        const RmOut ro{w.da, w.db};
+        hipLaunchKernelGGL(rm_select<false>, dim3(grid), dim3(CS), 0, s, a.T, a.R, IG, a.G, a.it,
+                           (const int64_t *)w.smp, ng, w.rp, bm, (const int64_t *)w.scr, w.slots, ro,
+                           w.cs);
+        const RmBr bd{w.da, w.db, w.cs.med2};
+        hipLaunchKernelGGL((rm_pass<true, false>), pg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, bd,
+                           w.scr, w.rp, a.stats);
+        hipLaunchKernelGGL(rm_select<true>, dim3(grid), dim3(CS), 0, s, a.T, a.R, IG, a.G, a.it,
+                           (const int64_t *)w.smp, ng, w.rp, bd, (const int64_t *)w.scr, w.slots, ro,
+                           w.cs);
+      }
+      const int64_t waves = ((a.R + SRW - 1) / SRW) * ((a.G + 63) / 64);
+      hipLaunchKernelGGL(score_rows, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a.T, a.R, a.I,
+                         a.G, a.it, w.cs, w.m_t);
+      hipLaunchKernelGGL((sel_regions<true, true>), dim3(a.G), dim3(RT), 0, s, (const void *)w.m_t, a.R,
+                         a.G, a.it, a.I, w.z_t, a.region_score);
+    } else if (a.mode == TA_SCAN_FULL) {
       if (IG > 0) {
         const dim3 tg((unsigned)transpose_groups_of(a.R), (IG + TT - 1) / TT);
         if (a.stats.rc > 0) {

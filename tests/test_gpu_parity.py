@@ -256,6 +256,35 @@ def test_outliers_ties_and_constant_columns(ta, h, oracle):
         assert np.array_equal(o["rank_flag"].cpu().numpy(), flag)
 
 
+def test_outliers_bracket_fallbacks(ta, h, oracle):
+    """Long columns whose sampled cells mislead the bracket.  The sample takes
+    pairs of consecutive ranks spread evenly over the padded ranks; with 65,536
+    ranks those are the ranks 0 and 1 modulo 64.  Column 0: the sampled cells
+    are far above the rest, so the median and MAD brackets miss the middle;
+    column 1: the sampled cells sit at two far ends, so the bracket interior
+    holds nearly every cell and overflows its region; column 2: the sampled
+    cells are equal (a zero-width bracket); the others are ordinary.  Every
+    column must still get the exact median and MAD."""
+    import torch
+    R, I, G = 65536, 2, 4
+    rng = np.random.default_rng(31)
+    T = rng.integers(0, 10**6, (R, I, G)).astype(np.int64)
+    sampled = (np.arange(R) % 64) < 2
+    T[sampled, 0, 0] = 10**12 + rng.integers(0, 1000, sampled.sum())
+    T[sampled, 0, 1] = np.where(np.arange(sampled.sum()) % 2 == 0, -10**9, 10**9)
+    T[sampled, 0, 2] = 5 * 10**5
+    T[~sampled, 0, 2] = rng.integers(0, 10, (~sampled).sum()) * 10**5
+    it = np.full(R, I, np.int32)
+    it[rng.choice(R, 1000, replace=False)] = 1
+    o = h.outliers(torch.from_numpy(T).cuda(), torch.from_numpy(it).cuda(), mode=0, kind=0,
+                   region=True)
+    st, score, flag, nf, reg = oracle.outliers(T, it, mode=0, kind=0)
+    assert st == 0
+    assert np.array_equal(o["region_score"].cpu().numpy(), reg)
+    assert np.array_equal(o["rank_score"].cpu().numpy(), score)
+    assert np.array_equal(o["rank_flag"].cpu().numpy(), flag)
+
+
 @pytest.mark.parametrize("R", [1, 2, 63, 64, 65, 1000, 4099, 32768, 70001])
 @pytest.mark.parametrize("style", ["narrow", "wide", "signed", "heavy_ties"])
 def test_outliers_column_shapes(ta, h, oracle, R, style):
