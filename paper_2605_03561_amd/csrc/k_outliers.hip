@@ -927,13 +927,17 @@ constexpr int RCH = TG * TT;   // ranks per chunk (the imbalance partials' chunk
 constexpr int RPU = 8;         // rows in flight per thread
 constexpr int SEG_MAX = 2048;  // chunks per column the selection can visit (LDS)
 
-// Counts and compaction of one column's cells against its bracket.
+constexpr int RQ = 8;          // interior cells buffered per column (one 64-byte write)
+
+// Counts and compaction of one column's cells against its bracket.  Interior
+// cells are buffered in registers (newest first) and written RQ at a time.
 template <bool MAD, bool STATS>
 struct RmCol {
   int64_t a, b, m;
   int32_t n = 0, cl = 0, cea = 0, ceb = 0, cm = 0;
   int64_t sd = 0, s1 = 0, mn = INT64_MAX, mx = INT64_MIN;
   u128 s2 = 0;
+  int64_t q[RQ];
   __device__ __forceinline__ void cell(int64_t x, int64_t *__restrict__ slot) {
     int64_t key = x;
     if (MAD) {
@@ -951,9 +955,24 @@ struct RmCol {
       mn = x < mn ? x : mn;
       mx = x > mx ? x : mx;
     }
-    if (key > a && key < b) slot[cm++] = key;
+    if (key > a && key < b) {
+#pragma unroll
+      for (int e = RQ - 1; e > 0; e--) q[e] = q[e - 1];
+      q[0] = key;
+      cm++;
+      if ((cm & (RQ - 1)) == 0) {
+        int64_t *d = slot + (cm - RQ);
+#pragma unroll
+        for (int e = 0; e < RQ; e += 2) *reinterpret_cast<v2ll *>(d + e) = v2ll{q[e], q[e + 1]};
+      }
+    }
   }
-  __device__ __forceinline__ void flush(int64_t p, RmPart pp, ColPartials ps) {
+  // the buffered remainder, then the counts
+  __device__ __forceinline__ void flush(int64_t p, RmPart pp, ColPartials ps, int64_t *__restrict__ slot) {
+    const int rem = cm & (RQ - 1);
+#pragma unroll
+    for (int e = 0; e < RQ; e++)
+      if (e < rem) slot[(cm & ~(RQ - 1)) + e] = q[e];
     if (!MAD) pp.n[p] = n;
     pp.cl[p] = cl;
     pp.cea[p] = cea;
@@ -974,8 +993,8 @@ struct RmCol {
 // One streaming pass over the row-major tensor: a thread owns two adjacent
 // columns (16-byte loads; a wave reads 1 KB of a row) and walks the RCH ranks
 // of chunk blockIdx.y, RPU rows in flight, counting in registers; the bracket
-// interior of each (chunk, column) goes to its own slot of RCH cells, so no
-// atomics and no overflow.  No LDS and no barriers.
+// interior of each (chunk, column) goes to its own slot of RCH cells (64-byte
+// writes), so no atomics and no overflow.  No LDS and no barriers.
 template <bool MAD, bool STATS>
 __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, int64_t R, int IG, int G,
                                                const int32_t *it, RmBr br, int64_t *__restrict__ scr,
@@ -1022,8 +1041,8 @@ __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, in
       }
     }
   }
-  c0.flush(ch * IG + ca, pp, ps);
-  if (two) c1.flush(ch * IG + ca + 1, pp, ps);
+  c0.flush(ch * IG + ca, pp, ps, slot0);
+  if (two) c1.flush(ch * IG + ca + 1, pp, ps, slot1);
 }
 
 // Column c of the row-major tensor into slot[0..Rp) (SENT for cells of missing

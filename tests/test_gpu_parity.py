@@ -262,7 +262,8 @@ def test_outliers_bracket_fallbacks(ta, h, oracle):
     ranks those are the ranks 0 and 1 modulo 64.  Column 0: the sampled cells
     are far above the rest, so the median and MAD brackets miss the middle;
     column 1: the sampled cells sit at two far ends, so the bracket interior
-    holds nearly every cell and overflows its region; column 2: the sampled
+    holds nearly every cell (on the column-major path it overflows the
+    scratch); column 2: the sampled
     cells are equal (a zero-width bracket); the others are ordinary.  Every
     column must still get the exact median and MAD."""
     import torch
