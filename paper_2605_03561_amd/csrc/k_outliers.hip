@@ -26,7 +26,25 @@ constexpr uint64_t SIGN = 0x8000000000000000ull;
 
 struct ColSel {
   int64_t *med2, *mad4, *sumdev, *n;  // [IG]
+  double *zc, *zd;                    // [IG] row-major path: z = ((2x - med2) * zc) / zd
 };
+
+// The robust z of a cell in one division with per-column (zc, zd): when
+// mad4 > 0, (2.0, 1.4826 * mad4) -- (2x - med2) * 2 converts to the same double
+// as 4x - 2 med2; when only the mean absolute deviation is positive,
+// (n, 1.253314 * sumdev); else (0, 1) (every cell is the median, z = 0).
+__host__ __device__ inline void z_coefs(int64_t mad4, int64_t sumdev, int64_t n, double &zc, double &zd) {
+  if (mad4 > 0) {
+    zc = 2.0;
+    zd = 1.4826 * (double)mad4;
+  } else if (sumdev > 0) {
+    zc = (double)n;
+    zd = 1.253314 * (double)sumdev;
+  } else {
+    zc = 0.0;
+    zd = 1.0;
+  }
+}
 
 __device__ inline int nbits64(uint64_t v) { return v ? 64 - __clzll((long long)v) : 0; }
 
@@ -1154,6 +1172,8 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
         } else {
           out.mad4[c] = 0;
           out.sumdev[c] = 0;
+          out.zc[c] = 0.0;
+          out.zd[c] = 1.0;
         }
       }
       __syncthreads();
@@ -1203,6 +1223,7 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
       if (t == 0) {
         out.mad4[c] = x1 + x2;
         out.sumdev[c] = sums[0];
+        z_coefs(x1 + x2, sums[0], n, out.zc[c], out.zd[c]);
       }
     }
     __syncthreads();
@@ -1214,11 +1235,6 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
 // region), so each row read is contiguous and the column parameters are read
 // once per SRW ranks.
 constexpr int SRW = 8;
-
-__device__ inline double robust_z(int64_t x, int64_t med2, int64_t mad4, int64_t sdv, int64_t n) {
-  if (mad4 > 0) return (double)(4 * x - 2 * med2) / (1.4826 * (double)mad4);
-  return sdv > 0 ? ((double)(2 * x - med2) * (double)n) / (1.253314 * (double)sdv) : 0.0;
-}
 
 __global__ __launch_bounds__(256) void score_rows(const int64_t *__restrict__ T, int64_t R, int I, int G,
                                                   const int32_t *it, ColSel cs, double *m_t) {
@@ -1249,29 +1265,28 @@ __global__ __launch_bounds__(256) void score_rows(const int64_t *__restrict__ T,
   const int64_t *base = T + r0 * IG + gg;
   // iteration i's cells and column parameters; those of i + 1 are loaded
   // before i is scored
-  int64_t x[SRW], med2 = 0, mad4 = 0;
+  int64_t x[SRW], med2 = 0;
+  double zc = 0.0, zd = 1.0;
   auto load = [&](int i) {
 #pragma unroll
     for (int q = 0; q < SRW; q++)
       x[q] = i < ni[q] ? __builtin_nontemporal_load(base + q * IG + (int64_t)i * G) : 0;
-    med2 = cs.med2[(int64_t)i * G + gg];
-    mad4 = cs.mad4[(int64_t)i * G + gg];
+    const int64_t c = (int64_t)i * G + gg;
+    med2 = cs.med2[c];
+    zc = cs.zc[c];
+    zd = cs.zd[c];
   };
   if (nmax > 0) load(0);
   for (int i = 0; i < nmax; i++) {
     int64_t xc[SRW];
 #pragma unroll
     for (int q = 0; q < SRW; q++) xc[q] = x[q];
-    const int64_t m2 = med2, m4 = mad4;
+    const int64_t m2 = med2;
+    const double a = zc, d = zd;
     if (i + 1 < nmax) load(i + 1);
-    int64_t sdv = 0, nc = 0;
-    if (m4 <= 0) {
-      sdv = cs.sumdev[(int64_t)i * G + gg];
-      nc = cs.n[(int64_t)i * G + gg];
-    }
 #pragma unroll
     for (int q = 0; q < SRW; q++)
-      if (i < ni[q]) acc[q] += robust_z(xc[q], m2, m4, sdv, nc);
+      if (i < ni[q]) acc[q] += ((double)(2 * xc[q] - m2) * a) / d;
   }
   if (gl) {
 #pragma unroll
@@ -1620,6 +1635,8 @@ OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
       w.rp.ceb = (int32_t *)take(ng * IG * 4);
       w.rp.cm = (int32_t *)take(ng * IG * 4);
       w.rp.sd = (int64_t *)take(ng * IG * 8);
+      w.cs.zc = (double *)take(IG * 8);
+      w.cs.zd = (double *)take(IG * 8);
     } else {
       w.Tt = (int64_t *)take((size_t)pad_ranks(R) * IG * 8);
       if (kind == TA_SCORE_MAD && pad_ranks(R) >= SEL_BRACKET_MIN_RP)  // more than SEG_MAX chunks

@@ -4,8 +4,8 @@
   ranks are copied back and checked bit-exact against the oracle (tensor rows,
   exclusive / inclusive rows, iteration counts, outside time, spans, rank
   totals); sampled tensor columns are checked against the oracle's
-  per-iteration statistics; statistics that hold at any size are checked on
-  the full outputs.
+  per-iteration statistics; the exact outlier scan is checked on sampled
+  regions; statistics that hold at any size are checked on the full outputs.
 * 3,000 ranks with the 10,000-rank workload's shape: everything, including the
   exact outlier scan, against the oracle on the whole batch.
 """
@@ -125,6 +125,25 @@ def test_c3_statistics(mods, oracle, c3):
     assert int(ol["n_flagged"].item()) == int(flag.sum())
     # the scan finds most of the injected slow ranks (sanity, not parity)
     assert flag[w.injected].mean() > 0.5
+
+
+def test_c3_outlier_scan_sampled_regions(mods, oracle, c3):
+    """The exact robust FULL scan at 100k ranks (the row-major path, in the
+    benchmark's launch configuration) against the oracle on sampled regions:
+    stage 2 works per region, so the oracle's scan of the one-region slice
+    T[:, :, g] yields that region's scores exactly (bit for bit)."""
+    torch, gpu_synth, ta = mods
+    w, h, seg, cfg = c3
+    ol = h.outliers(seg["tensor"], seg["iters_found"], region=True)
+    h.sync_status()
+    reg = ol["region_score"].cpu().numpy()
+    it = seg["iters_found"].cpu().numpy()
+    for g in (0, 31, cfg["n_regions"] - 1):
+        print(f"[fullsize] outlier scan, region {g}", flush=True)
+        sl = seg["tensor"][:, :, g:g + 1].contiguous().cpu().numpy()
+        st, score, flag, nf, oreg = oracle.outliers(sl, it, mode=0, kind=0)
+        assert st == 0
+        assert np.array_equal(reg[:, g], oreg[:, 0]), g
 
 
 def test_c3_pruned_model(mods, oracle, c3):
@@ -291,8 +310,8 @@ def test_c3_sparse_profiles(mods, oracle, c3):
 
 def test_c3_plan_matches_eager(mods, oracle, c3):
     """The batch plan at 100k ranks (fused pass, imbalance statistics taken by
-    the FULL scan's transpose, exact outlier scan, one graph) equals the eager
-    calls bit for bit."""
+    the FULL scan's first pass over the tensor, exact outlier scan, one graph)
+    equals the eager calls bit for bit."""
     torch, gpu_synth, ta = mods
     w, h, seg, cfg = c3
     h.set_tree(w.parent)
