@@ -1331,6 +1331,8 @@ __device__ inline bool rank_active(const int32_t *it, int I, int64_t r) {
 
 // Exact k-th smallest (k = (n-1)/2) of keys given by `keyf(r)` over active
 // ranks, and the next order statistic.  Returns both through v1/v2.
+constexpr int SU2 = 8;  // keys in flight per thread in the stage-2 selection
+
 template <class KeyF>
 __device__ void block_select(int64_t R, const int32_t *it, int I, int64_t n, KeyF keyf,
                              uint32_t (*hist)[256], uint32_t *tot, uint64_t *sh_u64,
@@ -1341,13 +1343,36 @@ __device__ void block_select(int64_t R, const int32_t *it, int I, int64_t n, Key
   for (int sh = 56; sh >= 0; sh -= 8) {
     const bool last = sh == 0;
     uint64_t mgt = ~0ull;
-    for (int64_t r = tid; r < R; r += RT) {
-      if (!rank_active(it, I, r)) continue;
-      const uint64_t key = keyf(r);
-      const uint64_t ks = key >> sh;
-      const uint64_t hk = ks >> 8;
-      if (hk == pref) atomicAdd(&hist[wid][(uint32_t)(ks & 255)], 1u);
-      else if (last && hk > pref) mgt = key < mgt ? key : mgt;
+    // SU2 keys per thread per round trip; a wave whose hits share one bin
+    // adds them with one LDS atomic (the rule in the leading passes)
+    for (int64_t r0 = tid; r0 < R; r0 += (int64_t)RT * SU2) {
+      uint64_t kv[SU2];
+      bool ok[SU2];
+#pragma unroll
+      for (int u = 0; u < SU2; u++) {
+        const int64_t r = r0 + (int64_t)u * RT;
+        ok[u] = r < R && rank_active(it, I, r);
+        kv[u] = r < R ? keyf(r) : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < SU2; u++) {
+        const uint64_t key = kv[u];
+        const uint64_t ks = key >> sh;
+        const uint64_t hk = ks >> 8;
+        const bool hit = ok[u] && hk == pref;
+        const uint32_t bin = (uint32_t)(ks & 255);
+        const uint64_t hm = __ballot(hit);
+        if (hm) {
+          const int lead = __ffsll((long long)hm) - 1;
+          const uint32_t b0 = (uint32_t)__shfl((int)bin, lead, 64);
+          if (__ballot(hit && bin == b0) == hm) {
+            if (lane == lead) atomicAdd(&hist[wid][b0], (uint32_t)__popcll(hm));
+          } else if (hit) {
+            atomicAdd(&hist[wid][bin], 1u);
+          }
+        }
+        if (ok[u] && last && hk > pref) mgt = key < mgt ? key : mgt;
+      }
     }
     // reduce the min-above-group over the block
     for (int d = 32; d >= 1; d >>= 1) {
