@@ -137,6 +137,9 @@ constexpr int SPT = 1024;               // threads per rank workgroup
 constexpr int SPC = 8192;               // node ids per chunk (64 KB LDS histogram)
 constexpr int SPE = SPC / SPT;          // bins per thread in the compaction
 constexpr int SPW = MAX_NODES / SPC / 32;  // words of the touched-chunk mask
+constexpr int SPBW = 4096;              // node-mask words: trees of up to 131,072 nodes take one pass
+constexpr int SPBT = SPBW / SPT;        // mask words per thread
+constexpr int SPACC = 4096;             // distinct nodes a rank may reach on the one-pass path
 
 // Exclusive scan of per-thread counts over the workgroup; *total = the sum.
 __device__ inline int block_excl_scan_i32(int v, int *wsum, int *total) {
@@ -161,12 +164,16 @@ __device__ inline int block_excl_scan_i32(int v, int *wsum, int *total) {
   return base + x - v;
 }
 
-// One workgroup per rank (grid-stride).  For each chunk of SPC node ids that
-// the rank's events reach with a positive duration: an LDS histogram of the
-// chunk (exact 64-bit atomics), then its non-zero bins in ascending id,
-// compacted by a workgroup scan and appended after the previous chunks' in the
-// rank's own event range.  With more than one chunk a first pass over the
-// events marks the chunks they reach.
+// One workgroup per rank (grid-stride).  Trees of more than SPC nodes and at
+// most SPBW * 32: a pass over the events marks the nodes they reach with a
+// positive duration in an LDS bit mask; a workgroup scan of the mask's word
+// counts gives each reached node its output index (ascending id); a second
+// pass adds the durations into an LDS accumulator at those indices (exact
+// 64-bit atomics).  Otherwise, or when a rank reaches more than SPACC nodes:
+// for each chunk of SPC node ids that the events reach, an LDS histogram of
+// the chunk, then its non-zero bins in ascending id, compacted by a workgroup
+// scan and appended after the previous chunks'.  Output goes to the rank's own
+// event range.
 __global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__restrict__ off,
                                                              const int64_t *__restrict__ ts,
                                                              const int32_t *__restrict__ ctx,
@@ -175,62 +182,129 @@ __global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__r
                                                              int32_t *__restrict__ ids,
                                                              int64_t *__restrict__ vals,
                                                              uint32_t *err) {
-  __shared__ uint64_t hist[SPC];
+  __shared__ uint64_t pool[SPC];  // chunk histogram, or mask | word prefixes | accumulator
   __shared__ uint32_t touched[SPW];
   __shared__ int wsum[SPT / 64];
+  uint64_t *hist = pool;
+  uint32_t *bm = reinterpret_cast<uint32_t *>(pool);
+  uint32_t *pre = bm + SPBW;
+  uint64_t *acc = pool + SPBW;
   const int n_chunks = (N + SPC - 1) / SPC;
+  const bool one_pass = n_chunks > 1 && N <= SPBW * 32;
+  const int nw = (N + 31) / 32;
+  const int t = threadIdx.x;
   for (int64_t r = blockIdx.x; r < R; r += gridDim.x) {
     // a rank's range, clamped to [0, E] (inconsistent offsets are an error)
     const int64_t o0 = off[r], o1 = off[r + 1];
     const bool bad = o0 < 0 || o1 < o0 || o1 > E;
     const int64_t b = bad ? 0 : o0, e = bad ? 0 : o1;
-    if (bad && threadIdx.x == 0) atomicOr(err, ERRBIT_OFFSETS);
+    if (bad && t == 0) atomicOr(err, ERRBIT_OFFSETS);
     auto dur = [&](int64_t k) -> int64_t { return k + 1 < e ? ts[k + 1] - ts[k] : 0; };
-    if (n_chunks > 1) {
-      for (int i = threadIdx.x; i < SPW; i += SPT) touched[i] = 0;
-      __syncthreads();
-      for (int64_t k = b + threadIdx.x; k < e; k += SPT) {
-        const int32_t c = ctx[k];
-        if (c >= 0 && c < N && dur(k) > 0) atomicOr(&touched[(c / SPC) >> 5], 1u << ((c / SPC) & 31));
-      }
-      __syncthreads();
-    }
     int64_t base = 0;
-    for (int ch = 0; ch < n_chunks; ch++) {
-      if (n_chunks > 1 && !((touched[ch >> 5] >> (ch & 31)) & 1u)) continue;  // uniform
-      const int lo = ch * SPC;
-      for (int i = threadIdx.x; i < SPC; i += SPT) hist[i] = 0;
+    bool done = false;
+    if (one_pass) {
+      for (int i = t; i < nw; i += SPT) bm[i] = 0;
       __syncthreads();
       visit_events<SPT>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
         const int64_t d = f - s;
         if (d < 0) atomicOr(err, ERRBIT_UNSORTED);
-        if (c < 0 || c >= N) {
-          if (ch == 0) atomicOr(err, ERRBIT_CTX);
-        } else if (c >= lo && c < lo + SPC && d != 0) {
-          atomicAdd((unsigned long long *)&hist[c - lo], (unsigned long long)d);
-        }
+        if (c < 0 || c >= N) atomicOr(err, ERRBIT_CTX);
+        else if (d > 0) atomicOr(&bm[c >> 5], 1u << (c & 31));
       });
       __syncthreads();
-      uint64_t v[SPE];
-      int nz = 0;
+      uint32_t wv[SPBT];
+      int own = 0;
 #pragma unroll
-      for (int u = 0; u < SPE; u++) {
-        v[u] = hist[threadIdx.x * SPE + u];
-        nz += v[u] != 0 ? 1 : 0;
+      for (int u = 0; u < SPBT; u++) {
+        const int w = t * SPBT + u;
+        wv[u] = w < nw ? bm[w] : 0u;
+        own += __popc(wv[u]);
       }
       int total;
-      int pos = block_excl_scan_i32(nz, wsum, &total);
+      int pos = block_excl_scan_i32(own, wsum, &total);
 #pragma unroll
-      for (int u = 0; u < SPE; u++)
-        if (v[u] != 0) {
-          const int64_t o = b + base + pos++;
-          ids[o] = lo + threadIdx.x * SPE + u;
-          vals[o] = (int64_t)v[u];
+      for (int u = 0; u < SPBT; u++) {
+        const int w = t * SPBT + u;
+        if (w < nw) pre[w] = (uint32_t)pos;
+        pos += __popc(wv[u]);
+      }
+      if (total <= SPACC) {  // uniform
+        for (int i = t; i < total; i += SPT) acc[i] = 0;
+        __syncthreads();
+        visit_events<SPT>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
+          const int64_t d = f - s;
+          if (c >= 0 && c < N && d > 0) {
+            const int w = c >> 5;
+            const int idx = (int)pre[w] + __popc(bm[w] & ((1u << (c & 31)) - 1u));
+            atomicAdd((unsigned long long *)&acc[idx], (unsigned long long)d);
+          }
+        });
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < SPBT; u++) {
+          const int w = t * SPBT + u;
+          if (w >= nw) continue;
+          uint32_t m = wv[u];
+          int p = (int)pre[w];
+          while (m) {
+            const int j = __ffs(m) - 1;
+            m &= m - 1u;
+            ids[b + p] = w * 32 + j;
+            vals[b + p] = (int64_t)acc[p];
+            p++;
+          }
         }
-      base += total;
+        base = total;
+        done = true;
+      }
       __syncthreads();
     }
-    if (threadIdx.x == 0) counts[r] = base;
+    if (!done) {
+      if (n_chunks > 1) {
+        for (int i = t; i < SPW; i += SPT) touched[i] = 0;
+        __syncthreads();
+        for (int64_t k = b + t; k < e; k += SPT) {
+          const int32_t c = ctx[k];
+          if (c >= 0 && c < N && dur(k) > 0) atomicOr(&touched[(c / SPC) >> 5], 1u << ((c / SPC) & 31));
+        }
+        __syncthreads();
+      }
+      for (int ch = 0; ch < n_chunks; ch++) {
+        if (n_chunks > 1 && !((touched[ch >> 5] >> (ch & 31)) & 1u)) continue;  // uniform
+        const int lo = ch * SPC;
+        for (int i = t; i < SPC; i += SPT) hist[i] = 0;
+        __syncthreads();
+        visit_events<SPT>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
+          const int64_t d = f - s;
+          if (d < 0) atomicOr(err, ERRBIT_UNSORTED);
+          if (c < 0 || c >= N) {
+            if (ch == 0) atomicOr(err, ERRBIT_CTX);
+          } else if (c >= lo && c < lo + SPC && d != 0) {
+            atomicAdd((unsigned long long *)&hist[c - lo], (unsigned long long)d);
+          }
+        });
+        __syncthreads();
+        uint64_t v[SPE];
+        int nz = 0;
+#pragma unroll
+        for (int u = 0; u < SPE; u++) {
+          v[u] = hist[t * SPE + u];
+          nz += v[u] != 0 ? 1 : 0;
+        }
+        int total;
+        int pos = block_excl_scan_i32(nz, wsum, &total);
+#pragma unroll
+        for (int u = 0; u < SPE; u++)
+          if (v[u] != 0) {
+            const int64_t o = b + base + pos++;
+            ids[o] = lo + t * SPE + u;
+            vals[o] = (int64_t)v[u];
+          }
+        base += total;
+        __syncthreads();
+      }
+    }
+    if (t == 0) counts[r] = base;
     __syncthreads();
   }
 }

@@ -70,7 +70,8 @@ def test_windows_match_oracle(ta, h, oracle, seed, n_nodes):
 
 
 @pytest.mark.parametrize("seed,n_nodes,min_len", [(5, 1, 1), (6, 300, 0), (7, 8192, 2), (8, 8193, 1),
-                                                 (9, 30000, 5), (10, 100000, 1)])
+                                                 (9, 30000, 5), (10, 100000, 1), (11, 131072, 1),
+                                                 (12, 131073, 1)])
 def test_sparse_profiles_match_oracle(ta, h, oracle, seed, n_nodes, min_len):
     print(f"sparse seed={seed} N={n_nodes}", flush=True)
     if n_nodes == 1:
