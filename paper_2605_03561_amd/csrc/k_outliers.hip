@@ -8,10 +8,13 @@
 // smallest key above the lower median's prefix group (kept during the last
 // pass), so no extra pass is needed.
 //
-// FULL scan:   transpose the tensor to column-major [I*G][ranks] so that every
-//              per-column pass streams contiguous memory
-//              stage 1  per column (i,g): median and MAD over ranks (11-bit
-//                       digits, one workgroup per column)
+// FULL scan:   stage 1  per column (i,g): median and MAD over ranks
+//                       - robust kind, long columns: on the row-major tensor,
+//                         a sampled bracket per column, one streaming pass
+//                         that counts and compacts the bracket interior, an
+//                         exact selection over it (rm_* kernels below)
+//                       - otherwise: transpose to column-major [I*G][ranks]
+//                         and select per column (11-bit digits)
 //              scoring  m(r,g) = mean over the rank's iterations of z(r,i,g),
 //                       summed in ascending i (bit-reproducible)
 //              stage 2  per region g: median / MAD over ranks of m(r,g)
