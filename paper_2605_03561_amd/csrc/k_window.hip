@@ -57,8 +57,34 @@ __global__ void zero_i64(int64_t *p, int64_t n) {
     p[i] = 0;
 }
 
-// One workgroup per selected rank (grid-stride over the selection).  Binary
-// searches on the rank's sorted timestamps bound the events that overlap the
+// First index in [a, z) whose timestamp satisfies a monotone predicate (false
+// then true), or z: a 64-way search by one wave -- each step probes 64 evenly
+// spaced positions and keeps the gap between the last false and the first
+// true probe, so about log_65(z - a) + 1 round trips.  All lanes of the wave
+// call it together and get the same result.
+template <class P>
+__device__ inline int64_t wave_search(const int64_t *__restrict__ ts, int64_t a, int64_t z, P pred) {
+  const int lane = threadIdx.x & 63;
+  while (z - a > 64) {
+    const int64_t len = z - a;
+    const int64_t p = a + ((int64_t)(lane + 1) * len) / 65;
+    const uint64_t m = __ballot(pred(ts[p]));
+    if (m == 0) {
+      a = a + (64 * len) / 65 + 1;
+    } else {
+      const int f = __ffsll((long long)m) - 1;
+      const int64_t pf = a + ((int64_t)(f + 1) * len) / 65;
+      a = f == 0 ? a : a + ((int64_t)f * len) / 65 + 1;
+      z = pf;
+    }
+  }
+  const bool t = a + lane < z && pred(ts[a + lane]);
+  const uint64_t m = __ballot(t);
+  return m ? a + __ffsll((long long)m) - 1 : z;
+}
+
+// One workgroup per selected rank (grid-stride over the selection).  Searches
+// (64-way, one wave) on the rank's sorted timestamps bound the events that overlap the
 // window: before the event preceding the first timestamp above t0 every
 // interval ends by t0; from the first timestamp at or above t1 every interval
 // starts at or after t1.  LDSH: an LDS histogram over the N nodes (N <= 8192)
@@ -79,33 +105,23 @@ __global__ __launch_bounds__(WT) void window_excl(const int64_t *__restrict__ of
   }
   __syncthreads();
   for (int64_t i = blockIdx.x; i < n_sel; i += gridDim.x) {
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {  // wave 0
       const int64_t r = ids ? (int64_t)ids[i] : i;
       int64_t lo = 0, hi = 0, e = 0;
       if (r < 0 || r >= R || off[r] < 0 || off[r + 1] < off[r] || off[r + 1] > E) {
-        atomicOr(err, ERRBIT_OFFSETS);
+        if (threadIdx.x == 0) atomicOr(err, ERRBIT_OFFSETS);
       } else {
         const int64_t b = off[r];
         e = off[r + 1];
-        int64_t a = b, z = e;  // first index with ts > t0
-        while (a < z) {
-          const int64_t m = (a + z) >> 1;
-          if (ts[m] > t0) z = m;
-          else a = m + 1;
-        }
+        const int64_t a = wave_search(ts, b, e, [&](int64_t v) { return v > t0; });
         lo = a > b ? a - 1 : b;
-        a = b;
-        z = e;  // first index with ts >= t1
-        while (a < z) {
-          const int64_t m = (a + z) >> 1;
-          if (ts[m] >= t1) z = m;
-          else a = m + 1;
-        }
-        hi = a;
+        hi = wave_search(ts, b, e, [&](int64_t v) { return v >= t1; });
       }
-      range[0] = lo;
-      range[1] = hi;
-      range[2] = e;
+      if (threadIdx.x == 0) {
+        range[0] = lo;
+        range[1] = hi;
+        range[2] = e;
+      }
     }
     __syncthreads();
     const int64_t lo = range[0], hi = range[1], e = range[2];
