@@ -286,6 +286,26 @@ def test_outliers_bracket_fallbacks(ta, h, oracle):
     assert np.array_equal(o["rank_flag"].cpu().numpy(), flag)
 
 
+def test_outliers_very_long_columns(ta, h, oracle):
+    """More than 2,048 chunks of 1,024 ranks: the robust FULL scan takes the
+    column-major bracket path (transpose, sampled brackets over the
+    contiguous columns); parity with the oracle, bit for bit."""
+    import torch
+    R, I, G = 2_100_000, 2, 2
+    print(f"[parity] outliers very long columns R={R}", flush=True)
+    rng = np.random.default_rng(41)
+    T = rng.integers(0, 10**7, (R, I, G)).astype(np.int64)
+    T[rng.choice(R, 5000, replace=False), 1, 0] = 10**12          # far cells
+    it = np.full(R, I, np.int32)
+    it[rng.choice(R, 70000, replace=False)] = 1
+    o = h.outliers(torch.from_numpy(T).cuda(), torch.from_numpy(it).cuda(), mode=0, kind=0,
+                   region=True)
+    st, score, flag, nf, reg = oracle.outliers(T, it, mode=0, kind=0)
+    assert st == 0
+    assert np.array_equal(o["region_score"].cpu().numpy(), reg)
+    assert np.array_equal(o["rank_flag"].cpu().numpy(), flag)
+
+
 @pytest.mark.parametrize("R", [1, 2, 63, 64, 65, 1000, 4099, 32768, 70001])
 @pytest.mark.parametrize("style", ["narrow", "wide", "signed", "heavy_ties"])
 def test_outliers_column_shapes(ta, h, oracle, R, style):
