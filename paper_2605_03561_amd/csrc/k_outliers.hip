@@ -1731,10 +1731,11 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
                            w.smp);
         hipLaunchKernelGGL(rm_brackets, dim3(IG), dim3(CS), 0, s, (const int64_t *)w.smp, IG, w.qa, w.qb);
         const RmBr bm{w.qa, w.qb, nullptr};
-        if (a.stats.rc > 0)
+        if (a.stats.rc > 0) {
           hipLaunchKernelGGL((rm_pass<false, true>), pg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, bm,
                              w.scr, w.rp, a.stats);
-        else
+          if (a.stats_ready) (void)hipEventRecord(a.stats_ready, s);
+        } else
           hipLaunchKernelGGL((rm_pass<false, false>), pg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, bm,
                              w.scr, w.rp, a.stats);
         const RmOut ro{w.da, w.db};
@@ -1760,6 +1761,7 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
           if (a.stats.rc != transpose_groups_of(a.R)) return hipErrorInvalidValue;
           hipLaunchKernelGGL(transpose_kernel<true>, tg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, w.Tt,
                              a.stats);
+          if (a.stats_ready) (void)hipEventRecord(a.stats_ready, s);
         } else {
           hipLaunchKernelGGL(transpose_kernel<false>, tg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, w.Tt,
                              a.stats);

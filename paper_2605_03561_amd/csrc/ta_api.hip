@@ -341,6 +341,8 @@ struct ta_plan_s {
   int64_t *d_tasks = nullptr;    // mixed batch: (request << 32) | rank, longest first
   void *ws = nullptr;
   hipStream_t cap = nullptr;
+  hipStream_t cap2 = nullptr;      // a second capture stream (imbalance epilogue beside the scan)
+  hipEvent_t ev_stats = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ta::SegShape shape;
@@ -354,6 +356,9 @@ void plan_free(ta_plan p) {
   if (p->exec) hipGraphExecDestroy(p->exec);
   if (p->graph) hipGraphDestroy(p->graph);
   if (p->cap) hipStreamDestroy(p->cap);
+  if (p->cap2) hipStreamDestroy(p->cap2);
+  if (p->ev_stats) hipEventDestroy(p->ev_stats);
+  if (p->ev_join) hipEventDestroy(p->ev_join);
   if (p->d_order) hipFree(p->d_order);
   if (p->d_reqs) hipFree(p->d_reqs);
   if (p->d_tasks) hipFree(p->d_tasks);
@@ -1063,6 +1068,9 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
   e = ta::launch_segment(L.a, L.attr, L.seg, best, grid, L.lds, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e == hipSuccess && fuse) e = hipStreamCreateWithFlags(&p->cap2, hipStreamNonBlocking);
+  if (e == hipSuccess && fuse) e = hipEventCreateWithFlags(&p->ev_stats, hipEventDisableTiming);
+  if (e == hipSuccess && fuse) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) {
     plan_free(p);
@@ -1099,9 +1107,15 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
     oa.rank_flag = d->rank_flag;
     oa.n_flagged = d->n_flagged;
     oa.region_score = d->region_score;
-    if (fuse) oa.stats = ta::imbalance_partials(imb_ws, R, I, G, need_rs, rc_t);
+    if (fuse) {
+      oa.stats = ta::imbalance_partials(imb_ws, R, I, G, need_rs, rc_t);
+      oa.stats_ready = p->ev_stats;
+    }
     le = ta::launch_outliers(oa, p->ws, fuse ? ws_out : ws, p->cap);
   }
+  // The imbalance epilogue needs only the partials: on the second capture
+  // stream it runs beside the rest of the scan, joined before the graph ends.
+  if (le == hipSuccess && d->with_imbalance && fuse) le = hipStreamWaitEvent(p->cap2, p->ev_stats, 0);
   if (le == hipSuccess && d->with_imbalance && fuse) {
     ta::ImbArgs ia{};
     ia.T = d->seg.tensor;
@@ -1115,7 +1129,9 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
     ia.ddof = d->ddof;
     ia.t_app = d->t_app_ns;
     ia.o = d->imb;
-    le = ta::launch_imbalance(ia, imb_ws, ws_imb, p->cap, rc_t);
+    le = ta::launch_imbalance(ia, imb_ws, ws_imb, p->cap2, rc_t);
+    if (le == hipSuccess) le = hipEventRecord(p->ev_join, p->cap2);
+    if (le == hipSuccess) le = hipStreamWaitEvent(p->cap, p->ev_join, 0);
   }
   e = hipStreamEndCapture(p->cap, &p->graph);
   if (le != hipSuccess || e != hipSuccess) {

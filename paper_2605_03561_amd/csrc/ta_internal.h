@@ -132,6 +132,9 @@ struct OutArgs {
   // FULL scan: the transpose also writes the imbalance column partials here
   // (stats.rc must be transpose_groups(R)).
   ColPartials stats;
+  // When set (with stats), recorded on the stream right after the pass that
+  // writes the imbalance partials, so a consumer on another stream can start.
+  hipEvent_t stats_ready = nullptr;
 };
 // Rank chunks of the FULL scan's transpose (TG tiles of 64 ranks each).
 int transpose_groups(int64_t R);
