@@ -63,8 +63,9 @@ enum {
 typedef struct ta_handle_s *ta_handle;
 
 /* Handle life cycle.  `device` is the HIP device ordinal the handle's
- * workspace and kernels use.  The handle owns its workspace, the call-path
- * tables, batch plans and captured graphs. */
+ * workspace and kernels use.  The handle owns its workspace and the call-path
+ * tables.  ta_destroy waits for the device; it returns TA_ERR_STATE (and
+ * keeps the handle) while batch plans made on the handle still exist. */
 ta_status ta_create(ta_handle *out, int device);
 ta_status ta_destroy(ta_handle h);
 const char *ta_status_string(ta_status s);
@@ -80,7 +81,8 @@ ta_status ta_sync_status(ta_handle h, void *stream);
  * Any numbering is accepted: the library renumbers nodes in depth-first
  * preorder internally.  A cycle or an id outside [-1, N) -> TA_ERR_BAD_TREE.
  * N must be at most 8192 for attribution (exclusive/inclusive cost) and at
- * most 4194304 otherwise.  Resets the regions. */
+ * most 4194304 otherwise.  Resets the regions.  Waits for the device before
+ * replacing the previous tables; TA_ERR_STATE while batch plans exist. */
 ta_status ta_set_tree(ta_handle h, int32_t n_nodes, const int32_t *parent_host);
 
 /* Iteration marker and regions (Sec. V: iterations are found by scanning the
@@ -88,7 +90,8 @@ ta_status ta_set_tree(ta_handle h, int32_t n_nodes, const int32_t *parent_host);
  * a new iteration when its context lies in the marker's subtree and the
  * previous event of the same rank does not.  An event belongs to region g when
  * region_nodes_host[g] is the nearest ancestor-or-self of its context among
- * the region nodes.  1 <= n_regions <= 256, distinct nodes. */
+ * the region nodes.  1 <= n_regions <= 256, distinct nodes.  Waits for the
+ * device before replacing the tables; TA_ERR_STATE while batch plans exist. */
 ta_status ta_set_regions(ta_handle h, int32_t marker_node, int32_t n_regions,
                          const int32_t *region_nodes_host);
 
@@ -371,7 +374,10 @@ ta_status ta_node_intersections(ta_handle h, const int32_t *labels, const int32_
  *   environment variable when it holds this batch shape (and store new ones).
  * offsets_host is a host copy of t->offsets.  The plan keeps its own
  * workspace; the traces and every output buffer must stay allocated while
- * the plan is used.  A plan must be destroyed before its handle. */
+ * the plan is used.  The graph also uses the handle's call-path and region
+ * tables, so while any plan of the handle exists ta_set_tree,
+ * ta_set_regions and ta_destroy return TA_ERR_STATE and change nothing:
+ * destroy the plans first. */
 typedef struct ta_plan_s *ta_plan;
 typedef struct {
   int32_t n_iters;

@@ -54,6 +54,8 @@ def lib():
         _lib.tao_kmeans.argtypes = [P, i64, i32, i32, P, i32, P, P, P, P]
         _lib.tao_dbscan1d.argtypes = [P, i64, i64, i64, P, P, P]
         _lib.tao_node_intersections.argtypes = [P, P, i64, i32, i32, P, P]
+        _lib.tao_fsum.argtypes = [P, i64, i64]
+        _lib.tao_fsum.restype = f64
         for f in ("tao_summary", "tao_prune", "tao_pruned", "tao_tensor_inclusive", "tao_kmeans",
                   "tao_dbscan1d", "tao_node_intersections", "tao_window_profile", "tao_sparse_profiles"):
             getattr(_lib, f).restype = C.c_int
@@ -138,6 +140,12 @@ def outliers(T, iters_found=None, mode=0, kind=0, tau=3.5, want_region=True):
     st = lib().tao_outliers(_p(T), R, I, G, _p(it), int(mode), int(kind), float(tau),
                             _p(score), _p(flag), _p(nf), _p(reg))
     return st, score, flag, int(nf[0]), reg
+
+
+def fsum(v):
+    """Exact sum of the FP64 values, rounded once to nearest (ties to even)."""
+    v = _arr(v, np.float64)
+    return float(lib().tao_fsum(_p(v), len(v), 1))
 
 
 def topology(rank_score, rank_flag, rank_node, node_rack, node_chassis, n_racks, n_chassis):

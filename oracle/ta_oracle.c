@@ -33,7 +33,10 @@
  * that change arithmetic are restated at the function that uses them.
  *
  * Precision: int64 for all times (ns), __int128 for sums of squares, FP64 for
- * every statistic, long double for FP accumulations of many FP64 terms.
+ * every statistic; FP accumulations of many FP64 terms are long double, except
+ * where the result feeds a difference that can cancel (the second-stage
+ * means and deviations of the outlier scores, the topology means): those sums
+ * are exact, rounded once (tao_fsum).
  * Build: gcc -O2 -ffp-contract=off (no FMA contraction), optional -fopenmp
  * (only the independent per-rank loop is parallel; results do not depend on it).
  */
@@ -394,6 +397,49 @@ static int64_t twice_median_sorted(const int64_t *s, int64_t n) {
   return (n & 1) ? 2 * s[n / 2] : s[n / 2 - 1] + s[n / 2];
 }
 
+/* Exact sum of n doubles (every `stride`-th of v), rounded once to nearest
+ * (ties to even); exact zero gives +0.0 and any non-finite term gives NaN.
+ * Shewchuk's algorithm (Adaptive Precision Floating-Point Arithmetic, 1997):
+ * the running sum is kept as a list of non-overlapping partials, each new term
+ * is folded in by exact two-sum steps (sum rounded + its exact error), and the
+ * partials are added from the largest down; the last step checks whether the
+ * remaining partials push an exact halfway case up or down. */
+double tao_fsum(const double *v, int64_t n, int64_t stride) {
+  double part[256];  /* non-overlapping: far fewer than 2,100 / 53 + 2 are live */
+  int np = 0;
+  for (int64_t k = 0; k < n; k++) {
+    double x = v[k * stride];
+    if (!isfinite(x)) return NAN;
+    int j = 0;
+    for (int i = 0; i < np; i++) {
+      double y = part[i];
+      if (fabs(x) < fabs(y)) { double t = x; x = y; y = t; }
+      double hi = x + y;
+      double lo = y - (hi - x);
+      if (lo != 0.0) part[j++] = lo;
+      x = hi;
+    }
+    part[j++] = x;
+    np = j;
+  }
+  if (np == 0) return 0.0;
+  double hi = part[--np], lo = 0.0;
+  while (np > 0) {
+    double x = hi, y = part[--np];
+    hi = x + y;
+    lo = y - (hi - x);
+    if (lo != 0.0) break;
+  }
+  /* hi + lo is exact and hi = round(hi + lo); if lo is exactly half an ulp of
+   * hi and the next partial has the same sign, the true sum lies beyond the
+   * halfway point, so round away from hi. */
+  if (np > 0 && ((lo < 0.0 && part[np - 1] < 0.0) || (lo > 0.0 && part[np - 1] > 0.0))) {
+    double y = lo * 2.0, x = hi + y;
+    if (y == x - hi) hi = x;
+  }
+  return hi == 0.0 ? 0.0 : hi;
+}
+
 /* Robust z of one integer column (n values, already gathered):
  *   med2 = 2*median,  dev_r = |2x_r - med2| (= 2|x - med|),
  *   mad4 = 2*median(dev) (= 4*MAD),
@@ -428,20 +474,16 @@ static void robust_z_int(const int64_t *x, int64_t n, double *z, int64_t *work) 
 
 /* The same robust z for FP64 values: med = middle value (odd n) or
  * 0.5*(a + b) (even n); MAD = median of |v - med| by the same rule;
- * z = (v - med) / (1.4826*MAD); MAD == 0 -> 1.253314 * mean|v - med|
- * (long double sum); both zero -> 0. */
+ * z = (v - med) / (1.4826*MAD); MAD == 0 -> 1.253314 * mean|v - med| (the
+ * exact sum of the |v - med|, rounded, over n); both zero -> 0. */
 static void robust_z_f64(const double *v, int64_t n, double *z, double *work) {
   memcpy(work, v, sizeof(double) * (size_t)n);
   qsort(work, (size_t)n, sizeof(double), cmp_f64);
   double med = (n & 1) ? work[n / 2] : 0.5 * (work[n / 2 - 1] + work[n / 2]);
-  long double sad = 0.0L;
-  for (int64_t r = 0; r < n; r++) {
-    work[r] = fabs(v[r] - med);
-    sad += work[r];
-  }
+  for (int64_t r = 0; r < n; r++) work[r] = fabs(v[r] - med);
+  double mean_ad = tao_fsum(work, n, 1) / (double)n;
   qsort(work, (size_t)n, sizeof(double), cmp_f64);
   double mad = (n & 1) ? work[n / 2] : 0.5 * (work[n / 2 - 1] + work[n / 2]);
-  double mean_ad = (double)(sad / (long double)n);
   for (int64_t r = 0; r < n; r++) {
     if (mad > 0.0)
       z[r] = (v[r] - med) / (1.4826 * mad);
@@ -467,13 +509,14 @@ static void plain_z_int(const int64_t *x, int64_t n, int32_t ddof, double *z) {
   for (int64_t r = 0; r < n; r++)
     z[r] = (sd > 0.0) ? d128((i128)n * x[r] - s1) / ((double)n * sd) : 0.0;
 }
-static void plain_z_f64(const double *v, int64_t n, int32_t ddof, double *z) {
-  long double s = 0.0L;
-  for (int64_t r = 0; r < n; r++) s += v[r];
-  double m = (double)(s / (long double)n);
-  long double q = 0.0L;
-  for (int64_t r = 0; r < n; r++) q += (long double)(v[r] - m) * (long double)(v[r] - m);
-  double sd = (n > ddof) ? sqrt((double)(q / (long double)(n - ddof))) : 0.0;
+/* FP64 values: mean = (exact sum, rounded) / n; the squared deviations
+ * (v - mean)^2 are rounded to FP64 and summed exactly (rounded once);
+ * std = sqrt(that / (n - ddof)).  `work` holds n doubles. */
+static void plain_z_f64(const double *v, int64_t n, int32_t ddof, double *z, double *work) {
+  double m = tao_fsum(v, n, 1) / (double)n;
+  for (int64_t r = 0; r < n; r++) work[r] = (v[r] - m) * (v[r] - m);
+  double q = tao_fsum(work, n, 1);
+  double sd = (n > ddof) ? sqrt(q / (double)(n - ddof)) : 0.0;
   for (int64_t r = 0; r < n; r++) z[r] = (sd > 0.0) ? (v[r] - m) / sd : 0.0;
 }
 
@@ -542,7 +585,7 @@ int tao_outliers(const int64_t *T, int64_t R, int32_t I, int32_t G,
       for (int64_t a = 0; a < na; a++) fcol[a] = m[who[a] * G + g];
       if (na > 0) {
         if (kind == 0) robust_z_f64(fcol, na, z, fwork);
-        else plain_z_f64(fcol, na, 1, z);
+        else plain_z_f64(fcol, na, 1, z, fwork);
       }
       for (int64_t a = 0; a < na; a++) zr[who[a] * G + g] = z[a];
     }
@@ -611,21 +654,23 @@ int tao_topology(const double *rank_score, const uint8_t *rank_flag, int64_t R,
     int64_t *fl = pass ? flagged_chassis : flagged_rack;
     double *mx = pass ? max_chassis : max_rack;
     double *mn = pass ? mean_chassis : mean_rack;
+    double *sel = (double *)malloc(sizeof(double) * (size_t)(R + 1));
+    if (!sel) return TAO_ERR_SIZE_OVERFLOW;
     for (int32_t k = 0; k < K; k++) {
       int64_t cnt = 0, nfl = 0;
-      long double s = 0.0L;
       double best = -INFINITY;
       for (int64_t r = 0; r < R; r++) {
         if (key[rank_node[r]] != k) continue;
-        cnt++;
+        sel[cnt++] = rank_score[r];
         nfl += rank_flag[r] ? 1 : 0;
-        s += rank_score[r];
         if (rank_score[r] > best) best = rank_score[r];
       }
       if (fl) fl[k] = nfl;
       if (mx) mx[k] = cnt ? best : NAN;
-      if (mn) mn[k] = cnt ? (double)(s / (long double)cnt) : NAN;
+      /* mean = (exact sum of the scores, rounded) / count */
+      if (mn) mn[k] = cnt ? tao_fsum(sel, cnt, 1) / (double)cnt : NAN;
     }
+    free(sel);
   }
   return TAO_OK;
 }

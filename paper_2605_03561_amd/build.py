@@ -10,13 +10,14 @@ import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off",
     # Keep the compiler from forming packed FP32 instructions.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -32,13 +33,26 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-def _compile(sources, out, extra=()):
-    tmp = out + ".tmp"
-    cmd = [_hipcc(), *HIPCC_FLAGS, *extra, "-o", tmp, *sources]
+def _run(cmd, what):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError(f"hipcc failed for {out}")
+        raise RuntimeError(f"hipcc failed for {what}")
+
+
+def _compile(sources, out, extra=()):
+    """Compiles each source to an object in parallel, then links the library."""
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = [os.path.join(objdir, os.path.basename(src) + ".o") for src in sources]
+    jobs = int(os.environ.get("MAX_JOBS", "0")) or min(8, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(sources)))) as ex:
+        futs = [ex.submit(_run, [_hipcc(), *HIPCC_FLAGS, *extra, "-c", "-o", o, src], src)
+                for src, o in zip(sources, objs)]
+        for f in futs:
+            f.result()
+    tmp = out + ".tmp"
+    _run([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], out)
     os.replace(tmp, out)
     return out
 

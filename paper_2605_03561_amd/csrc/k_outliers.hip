@@ -1438,8 +1438,21 @@ __global__ __launch_bounds__(RT) void sel_regions(const void *vals_t, int64_t R,
   __shared__ uint64_t sh_u64[RW + 4];
   __shared__ double fb[RT];
   __shared__ int64_t ib[RT];
+  __shared__ int64_t xacc[RW * XL];
+  __shared__ uint32_t xbad;
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
+  int64_t *xw = xacc + (tid >> 6) * XL;
+  // exact sum over the active ranks of f(r), rounded once (FP64 stage)
+  auto exact_sum = [&](auto f) {
+    xsum_clear<RT>(xacc, &xbad);
+    for (int64_t r0 = 0; r0 < R; r0 += RT) {
+      const int64_t r = r0 + tid;
+      const bool act = r < R && rank_active(it, I, r);
+      xsum_add_wave(xw, act ? f(r) : 0.0, act, &xbad);
+    }
+    return xsum_block_result<RT>(xacc, &xbad, fb);
+  };
   const double *vd = reinterpret_cast<const double *>(vals_t) + (int64_t)g * R;
   const int64_t *vi = reinterpret_cast<const int64_t *>(vals_t) + (int64_t)g * R;
   for (int k = tid; k < RW * 256; k += RT) (&hist[0][0])[k] = 0;
@@ -1465,10 +1478,7 @@ __global__ __launch_bounds__(RT) void sel_regions(const void *vals_t, int64_t R,
           mode = 1;
           scale = 1.4826 * mad;
         } else {
-          double s = 0.0;
-          for (int64_t r = tid; r < R; r += RT)
-            if (rank_active(it, I, r)) s += fabs(vd[r] - med);
-          s = block_sum_f64<RT>(s, fb);
+          const double s = exact_sum([&](int64_t r) { return fabs(vd[r] - med); });
           const double mean_ad = s / (double)n;
           if (mean_ad > 0.0) {
             mode = 2;
@@ -1505,15 +1515,13 @@ __global__ __launch_bounds__(RT) void sel_regions(const void *vals_t, int64_t R,
       }
     } else {
       if (F64) {
-        double s = 0.0;
-        for (int64_t r = tid; r < R; r += RT)
-          if (rank_active(it, I, r)) s += vd[r];
-        s = block_sum_f64<RT>(s, fb);
-        med = s / (double)n;
-        double q = 0.0;
-        for (int64_t r = tid; r < R; r += RT)
-          if (rank_active(it, I, r)) q += (vd[r] - med) * (vd[r] - med);
-        q = block_sum_f64<RT>(q, fb);
+        // mean = (exact sum, rounded) / n; std from the exact sum of the
+        // rounded squared deviations (the same operations as the oracle)
+        med = exact_sum([&](int64_t r) { return vd[r]; }) / (double)n;
+        const double q = exact_sum([&](int64_t r) {
+          const double d = vd[r] - med;
+          return d * d;
+        });
         const double sd = n > 1 ? sqrt(q / (double)(n - 1)) : 0.0;
         if (sd > 0.0) {
           mode = 2;

@@ -248,34 +248,41 @@ __global__ __launch_bounds__(RT) void imbalance_final(int64_t R, int G, const in
 __global__ __launch_bounds__(RT) void topo_kernel(TopoArgs a) {
   __shared__ double fb[RT];
   __shared__ int64_t ib[RT];
+  __shared__ int64_t xacc[(RT / 64) * XL];
+  __shared__ uint32_t xbad;
   const int k = blockIdx.x;
   const bool chassis = k >= a.n_racks;
   const int key = chassis ? k - a.n_racks : k;
   const int32_t *map = chassis ? a.node_chassis : a.node_rack;
   const int lim = chassis ? a.n_chassis : a.n_racks;
   int64_t cnt = 0, nfl = 0;
-  double s = 0.0, best = -__builtin_inf();
+  double best = -__builtin_inf();
   uint32_t bad = 0;
-  for (int64_t r = threadIdx.x; r < a.R; r += RT) {
-    const int32_t nd = a.rank_node[r];
-    if (nd < 0 || nd >= a.n_nodes) {
-      bad = 1;
-      continue;
+  xsum_clear<RT>(xacc, &xbad);
+  int64_t *xw = xacc + (threadIdx.x >> 6) * XL;
+  // uniform trip count: every lane of a wave takes part in the exact sum
+  for (int64_t r0 = 0; r0 < a.R; r0 += RT) {
+    const int64_t r = r0 + threadIdx.x;
+    bool mine = false;
+    double sc = 0.0;
+    if (r < a.R) {
+      const int32_t nd = a.rank_node[r];
+      const int32_t kk = (nd < 0 || nd >= a.n_nodes) ? -1 : map[nd];
+      if (kk < 0 || kk >= lim) {
+        bad = 1;
+      } else if (kk == key) {
+        mine = true;
+        sc = a.score[r];
+        cnt++;
+        nfl += a.flag[r] ? 1 : 0;
+        best = sc > best ? sc : best;
+      }
     }
-    const int32_t kk = map[nd];
-    if (kk < 0 || kk >= lim) {
-      bad = 1;
-      continue;
-    }
-    if (kk != key) continue;
-    cnt++;
-    nfl += a.flag[r] ? 1 : 0;
-    s += a.score[r];
-    best = a.score[r] > best ? a.score[r] : best;
+    xsum_add_wave(xw, sc, mine, &xbad);
   }
+  const double s = xsum_block_result<RT>(xacc, &xbad, fb);  // exact sum of the scores
   cnt = block_sum_i64<RT>(cnt, ib);
   nfl = block_sum_i64<RT>(nfl, ib);
-  s = block_sum_f64<RT>(s, fb);
   best = block_max_f64<RT>(best, fb);
   if (bad) atomicOr(a.err, ERRBIT_OFFSETS);
   if (threadIdx.x == 0) {

@@ -32,6 +32,9 @@ struct ta_handle_s {
   size_t ws_bytes = 0;
   int32_t *pin = nullptr;  // pinned host word (pre-screen fallback count)
   ta::AeState ae;
+  // Batch plans alive on this handle: their graphs hold the call-path tables'
+  // device addresses, so the tables cannot be replaced while any exists.
+  int32_t live_plans = 0;
 };
 
 namespace {
@@ -174,6 +177,8 @@ ta_status upload_tables(ta_handle h) {
   }
   std::vector<int2> tt(N);
   for (int32_t v = 0; v < N; v++) tt[v] = make_int2(h->tin[v], h->tout[v]);
+  // Kernels still queued may read the previous tables.
+  if (h->d_info || h->d_tin_tout || h->d_rt) TA_HIP(h, hipDeviceSynchronize());
   if (h->d_info) hipFree(h->d_info);
   if (h->d_tin_tout) hipFree(h->d_tin_tout);
   if (h->d_rt) hipFree(h->d_rt);
@@ -551,6 +556,7 @@ ta_status ta_create(ta_handle *out, int device) {
 
 ta_status ta_destroy(ta_handle h) {
   if (!h) return TA_ERR_INVALID_ARG;
+  if (h->live_plans > 0) return fail(h, TA_ERR_STATE, "destroy the handle's batch plans first");
   DeviceGuard dg(h->device);
   hipDeviceSynchronize();
   if (h->d_info) hipFree(h->d_info);
@@ -585,6 +591,8 @@ ta_status ta_set_tree(ta_handle h, int32_t n_nodes, const int32_t *parent_host) 
   if (!h) return TA_ERR_INVALID_ARG;
   if (n_nodes <= 0 || !parent_host) return fail(h, TA_ERR_INVALID_ARG, "empty tree");
   if (n_nodes > ta::MAX_NODES) return fail(h, TA_ERR_SIZE_OVERFLOW, "too many CCT nodes");
+  if (h->live_plans > 0)
+    return fail(h, TA_ERR_STATE, "batch plans use the current tree: destroy them first");
   std::vector<int32_t> tin, tout;
   ta_status st = build_tree(h, n_nodes, parent_host, tin, tout);
   if (st) return st;
@@ -604,6 +612,8 @@ ta_status ta_set_regions(ta_handle h, int32_t marker_node, int32_t n_regions,
                          const int32_t *region_nodes_host) {
   if (!h) return TA_ERR_INVALID_ARG;
   if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  if (h->live_plans > 0)
+    return fail(h, TA_ERR_STATE, "batch plans use the current regions: destroy them first");
   if (marker_node < 0 || marker_node >= h->N) return fail(h, TA_ERR_INVALID_ARG, "marker out of range");
   if (n_regions < 1 || n_regions > ta::MAX_REGIONS || !region_nodes_host)
     return fail(h, TA_ERR_INVALID_ARG, "n_regions must be in [1, 256]");
@@ -1144,6 +1154,7 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
     return hipfail(h, e, "graph instantiate");
   }
   *out = p;
+  h->live_plans++;
   return TA_OK;
 }
 
@@ -1294,6 +1305,7 @@ ta_status ta_batch_create(ta_handle h, int32_t n_requests, const ta_request *req
     return hipfail(h, e, "graph instantiate");
   }
   *out = p;
+  h->live_plans++;
   return TA_OK;
 }
 
@@ -1320,6 +1332,7 @@ ta_status ta_plan_destroy(ta_plan p) {
   if (!p) return TA_ERR_INVALID_ARG;
   DeviceGuard dg(p->h->device);
   hipStreamSynchronize(p->cap);
+  p->h->live_plans--;
   plan_free(p);
   return TA_OK;
 }

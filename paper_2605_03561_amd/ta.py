@@ -181,8 +181,10 @@ class Handle:
             raise TAError(st, msg)
 
     def close(self):
+        """Destroys the library handle; raises TAError (STATE) and keeps it while
+        batch plans made on it are open."""
         if getattr(self, "h", None) is not None:
-            _lib.ta_destroy(self.h)
+            self._check(_lib.ta_destroy(self.h))
             self.h = None
 
     def __del__(self):

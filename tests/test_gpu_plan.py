@@ -104,3 +104,29 @@ def test_graph_replays_match_eager(env):
         # unrelated eager work between replays
         h.outliers(eager["tensor"], eager["iters_found"], mode=ta.SCAN_TOTALS)
     p.close()
+
+
+def test_tables_locked_while_plans_exist(env):
+    """A plan's graph reads the handle's call-path and region tables, so the
+    handle refuses to replace them (or to go away) while a plan is open."""
+    torch, ta, w, h, tr = env
+    print("[plan] tables locked while a plan is open", flush=True)
+    h2 = ta.Handle(0)
+    h2.set_tree(w.parent)
+    h2.set_regions(w.marker, w.regions)
+    p = h2.plan(tr, w.n_iters, w.offsets, imbalance=False, outliers=False, autotune=0)
+    for call in (lambda: h2.set_tree(w.parent), lambda: h2.set_regions(w.marker, w.regions),
+                 h2.close):
+        with pytest.raises(ta.TAError) as ei:
+            call()
+        assert ei.value.status == ta.STATE
+    p.launch()                                   # the plan still runs on the old tables
+    h2.sync_status()
+    ref = p.seg["tensor"].clone()
+    p.close()
+    h2.set_tree(w.parent)                        # allowed again
+    h2.set_regions(w.marker, w.regions)
+    out = h2.attribute_segment(tr, w.n_iters)
+    h2.sync_status()
+    assert torch.equal(out["tensor"], ref)
+    h2.close()

@@ -402,6 +402,121 @@ def test_outliers_plain_z(oracle):
     assert reg == pytest.approx(z, rel=1e-12)
 
 
+def test_fsum_exact(oracle):
+    """The oracle's exact FP64 sum equals the exact rational sum rounded once
+    (Fraction -> float is correctly rounded) and Python's math.fsum, on sums
+    built to cancel, on halfway cases of both parities and on subnormals."""
+    import math
+    cases = [
+        [1e100, 1.0, -1e100],
+        [0.1] * 10,
+        [1.0, 2.0 ** -53],                       # exact tie -> even (1.0)
+        [1.0 + 2.0 ** -52, 2.0 ** -53],          # exact tie -> even (up)
+        [1.0, 2.0 ** -53, 2.0 ** -106],          # just above the tie -> up
+        [1.0, 2.0 ** -53, -(2.0 ** -106)],       # just below the tie -> 1.0
+        [-1.0, -(2.0 ** -53), -(2.0 ** -106)],
+        [5e-324, 5e-324, -1e-320, 2.2250738585072014e-308],
+        [1.7976931348623157e308, -1.7976931348623157e308, 1.0],
+        [], [0.0, -0.0], [3.0],
+    ]
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        n = int(rng.integers(1, 300))
+        mag = 10.0 ** rng.integers(-300, 300, n)
+        v = rng.standard_normal(n) * mag
+        v = np.concatenate([v, -v[: n // 2] * (1 + 2.0 ** -50)])  # heavy cancellation
+        rng.shuffle(v)
+        cases.append(list(v))
+    for c in cases:
+        want = float(sum((Fraction(x) for x in c), Fraction(0)))
+        got = oracle.fsum(np.array(c, np.float64))
+        assert got == want and got == math.fsum(c) + 0.0, c[:4]
+
+
+def _sqrt_fraction(q, digits=60):
+    from decimal import Decimal, getcontext
+    getcontext().prec = digits
+    return Fraction((Decimal(q.numerator) / Decimal(q.denominator)).sqrt())
+
+
+def test_outliers_full_plain_z_exact(oracle):
+    """FULL scan with plain z, against the definition in exact rational
+    arithmetic (square roots to 60 digits): per cell (x - mean) / std with
+    ddof 1 over the ranks valid in the iteration, m(r,g) = the mean of the
+    rank's cell scores, then per region (m - mean) / std (ddof 1) over the
+    active ranks; rank score = max_g |z2|.  The oracle rounds at every step,
+    so its values agree to a few ulps of the largest score."""
+    rng = np.random.default_rng(21)
+    R, I, G = 7, 5, 3
+    T = rng.integers(0, 10**6, (R, I, G)).astype(np.int64)
+    T[2, :, 1] = T[2, :, 1] * 3                      # a slow rank
+    T[:, 3, 2] = 777                                 # a constant column: z = 0
+    it = np.array([5, 5, 4, 5, 2, 5, 0], np.int32)   # rank 6 takes no part
+    st, score, flag, nf, reg = oracle.outliers(T, it, mode=0, kind=1, tau=1.5)
+    assert st == 0
+    m = {}
+    for i in range(I):
+        for g in range(G):
+            rows = [r for r in range(R) if it[r] > i]
+            xs = [Fraction(int(T[r, i, g])) for r in rows]
+            n = len(xs)
+            mean = sum(xs) / n
+            var = sum((x - mean) ** 2 for x in xs) / (n - 1)
+            sd = _sqrt_fraction(var) if var > 0 else Fraction(0)
+            for r, x in zip(rows, xs):
+                m[r, g] = m.get((r, g), Fraction(0)) + ((x - mean) / sd if sd > 0 else 0)
+    act = [r for r in range(R) if it[r] > 0]
+    want = np.zeros((R, G))
+    for g in range(G):
+        v = [m[r, g] / int(it[r]) for r in act]
+        mean = sum(v) / len(v)
+        sd = _sqrt_fraction(sum((x - mean) ** 2 for x in v) / (len(v) - 1))
+        for r, x in zip(act, v):
+            want[r, g] = float((x - mean) / sd)
+    tol = 1e-12 * max(1.0, np.abs(want).max())
+    assert np.abs(reg - want).max() <= tol
+    assert np.array_equal(score, np.abs(reg).max(1))
+    assert score[6] == 0.0 and np.all(reg[6] == 0.0)
+    assert np.array_equal(flag, (score > 1.5).astype(np.uint8)) and nf == int(flag.sum())
+    assert score.argmax() == 2
+
+
+def test_topology_hand_counted(oracle):
+    """Ranks placed on compute nodes, nodes on racks and chassis (Sec. VI-B),
+    counted by hand: per rack / chassis the flagged ranks, the largest score
+    and the mean score of the ranks placed there (NaN where none is)."""
+    score = np.array([1.0, 4.0, 0.5, 6.0, 2.5, 3.75, 0.25])
+    flag = np.array([0, 1, 0, 1, 0, 1, 0], np.uint8)      # flags are taken as given
+    rank_node = np.array([0, 0, 1, 2, 3, 3, 1], np.int32)
+    node_rack = np.array([0, 0, 1, 1], np.int32)
+    node_chassis = np.array([0, 1, 2, 2], np.int32)
+    st, o = oracle.topology(score, flag, rank_node, node_rack, node_chassis, 3, 4)
+    assert st == 0
+    # rack 0: ranks 0, 1, 2, 6; rack 1: ranks 3, 4, 5; rack 2: none
+    assert list(o["flagged_rack"]) == [1, 2, 0]
+    assert o["max_rack"][:2].tolist() == [4.0, 6.0] and np.isnan(o["max_rack"][2])
+    assert o["mean_rack"][0] == 5.75 / 4 and o["mean_rack"][1] == 12.25 / 3
+    assert np.isnan(o["mean_rack"][2])
+    # chassis 0: ranks 0, 1; chassis 1: ranks 2, 6; chassis 2: ranks 3, 4, 5
+    assert list(o["flagged_chassis"]) == [1, 0, 2, 0]
+    assert o["max_chassis"][:3].tolist() == [4.0, 0.5, 6.0] and np.isnan(o["max_chassis"][3])
+    assert o["mean_chassis"][:3].tolist() == [2.5, 0.375, 12.25 / 3]
+    # a rank on a node outside the map, a node outside the racks
+    bad = rank_node.copy()
+    bad[3] = 4
+    assert oracle.topology(score, flag, bad, node_rack, node_chassis, 3, 4)[0] == oracle.INVALID_ARG
+    bad_rack = node_rack.copy()
+    bad_rack[1] = 3
+    assert oracle.topology(score, flag, rank_node, bad_rack, node_chassis, 3, 4)[0] == \
+        oracle.INVALID_ARG
+    # means of many scores are the exact sums rounded once
+    sc = np.full(3000, 0.1)
+    sc[::7] = 1e-17
+    st, o = oracle.topology(sc, np.zeros(3000, np.uint8), np.zeros(3000, np.int32),
+                            np.zeros(1, np.int32), np.zeros(1, np.int32), 1, 1)
+    assert o["mean_rack"][0] == float(sum(Fraction(x) for x in sc)) / 3000
+
+
 def test_outliers_recall_injected(oracle):
     """Secondary sanity pin: the exact scan finds the ranks the generator
     slowed down (1.3x in 3 regions) in a small anchored workload."""
