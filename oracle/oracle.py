@@ -54,6 +54,10 @@ def lib():
         _lib.tao_kmeans.argtypes = [P, i64, i32, i32, P, i32, P, P, P, P]
         _lib.tao_dbscan1d.argtypes = [P, i64, i64, i64, P, P, P]
         _lib.tao_node_intersections.argtypes = [P, P, i64, i32, i32, P, P]
+        _lib.tao_node_model.argtypes = [i64, P, P, P, i32, P, i32, i32, P, P, P, P, P, P, P, P]
+        _lib.tao_node_model.restype = C.c_int
+        _lib.tao_set_threads.argtypes = [C.c_int]
+        _lib.tao_set_threads.restype = C.c_int
         _lib.tao_fsum.argtypes = [P, i64, i64]
         _lib.tao_fsum.restype = f64
         for f in ("tao_summary", "tao_prune", "tao_pruned", "tao_tensor_inclusive", "tao_kmeans",
@@ -140,6 +144,12 @@ def outliers(T, iters_found=None, mode=0, kind=0, tau=3.5, want_region=True):
     st = lib().tao_outliers(_p(T), R, I, G, _p(it), int(mode), int(kind), float(tau),
                             _p(score), _p(flag), _p(nf), _p(reg))
     return st, score, flag, int(nf[0]), reg
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads for the following oracle calls (timing only; the results
+    do not depend on it).  Returns the number in use."""
+    return int(lib().tao_set_threads(int(n)))
 
 
 def fsum(v):
@@ -262,3 +272,31 @@ def sparse_profiles(offsets, ts, ctx, n_nodes):
     st = lib().tao_sparse_profiles(R, _p(offsets), _p(ts), _p(ctx), int(n_nodes), _p(counts), _p(ids),
                                    _p(ex))
     return st, counts, ids, ex
+
+
+def node_model(offsets, ts, ctx, parent, marker, n_iters):
+    """Sparse node x rank x iteration model.  -> (status, model) where model
+    holds, for the rows q = r*I + i: nnz_x[q], row_off_x[q+1] (exclusive
+    prefix), node_x, val_x (non-zero exclusive costs in ascending node id) and
+    nnz_i, row_off_i, node_i, val_i (non-zero inclusive costs)."""
+    offsets, ts, ctx = _arr(offsets, np.int64), _arr(ts, np.int64), _arr(ctx, np.int32)
+    parent = _arr(parent, np.int32)
+    R, N, I = len(offsets) - 1, len(parent), int(n_iters)
+    nx = np.zeros(R * I, np.int64)
+    ni = np.zeros(R * I, np.int64)
+    args = (R, _p(offsets), _p(ts), _p(ctx), N, _p(parent), int(marker), I)
+    st = lib().tao_node_model(*args, _p(nx), _p(ni), None, None, None, None, None, None)
+    if st != OK:
+        return st, None
+    ox = np.zeros(R * I + 1, np.int64)
+    oi = np.zeros(R * I + 1, np.int64)
+    np.cumsum(nx, out=ox[1:])
+    np.cumsum(ni, out=oi[1:])
+    node_x = np.full(int(ox[-1]), -1, np.int32)
+    val_x = np.zeros(int(ox[-1]), np.int64)
+    node_i = np.full(int(oi[-1]), -1, np.int32)
+    val_i = np.zeros(int(oi[-1]), np.int64)
+    st = lib().tao_node_model(*args, _p(nx), _p(ni), _p(ox), _p(node_x), _p(val_x), _p(oi),
+                              _p(node_i), _p(val_i))
+    return st, {"nnz_x": nx, "row_off_x": ox, "node_x": node_x, "val_x": val_x,
+                "nnz_i": ni, "row_off_i": oi, "node_i": node_i, "val_i": val_i}

@@ -41,6 +41,9 @@
  * (only the independent per-rank loop is parallel; results do not depend on it).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -95,6 +98,19 @@ static int32_t region_of_node(const int32_t *parent, int32_t c, int32_t G,
     for (int32_t g = 0; g < G; g++)
       if (region_nodes[g] == u) return g;
   return -1;
+}
+
+/* Number of OpenMP threads for the next calls (n < 1: leave as is); returns
+ * the number in use.  Only the timing of the oracle uses it: results do not
+ * depend on the thread count. */
+int tao_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */
@@ -276,12 +292,22 @@ int tao_imbalance(const int64_t *T, int64_t R, int32_t I, int32_t G,
   if (R < 0 || I < 0 || G <= 0 || ddof < 0 || T == NULL) return TAO_ERR_INVALID_ARG;
   const double nan = NAN;
   int64_t grand = 0;
+#pragma omp parallel for reduction(+ : grand)
   for (int64_t r = 0; r < R; r++)
     for (int32_t i = 0; i < I; i++)
       if (valid(iters_found, r, i))
         for (int32_t g = 0; g < G; g++) grand += T[((int64_t)r * I + i) * G + g];
 
-  long double sum_total = 0.0L;
+  /* Regions are independent (threads take whole regions); each region's
+   * total savings is kept and the total is summed in ascending g below. */
+  double *tot_g = (double *)malloc(sizeof(double) * (size_t)G);
+  int *has_g = (int *)malloc(sizeof(int) * (size_t)G);
+  if (!tot_g || !has_g) {
+    free(tot_g);
+    free(has_g);
+    return TAO_ERR_SIZE_OVERFLOW;
+  }
+#pragma omp parallel for schedule(dynamic, 1)
   for (int32_t g = 0; g < G; g++) {
     long double acc_mean = 0.0L, acc_mm = 0.0L, acc_cv = 0.0L;
     int64_t acc_max = 0, n_iters = 0, n_cv = 0;
@@ -328,7 +354,8 @@ int tao_imbalance(const int64_t *T, int64_t R, int32_t I, int32_t G,
     if (avg_max) avg_max[g] = n_iters ? (double)acc_max / (double)n_iters : nan;
     if (savings_per_iter) savings_per_iter[g] = spi;
     if (total_savings) total_savings[g] = tot;
-    if (n_iters) sum_total += tot;
+    tot_g[g] = tot;
+    has_g[g] = n_iters > 0;
     if (cv_across) cv_across[g] = n_cv ? (double)(acc_cv / (long double)n_cv) : nan;
 
     /* Per-rank totals over the rank's valid iterations. */
@@ -362,6 +389,11 @@ int tao_imbalance(const int64_t *T, int64_t R, int32_t I, int32_t G,
     if (cv_within) cv_within[g] = n_w ? (double)(acc_w / (long double)n_w) : nan;
     if (share) share[g] = grand ? (double)gsum / (double)grand : nan;
   }
+  long double sum_total = 0.0L;
+  for (int32_t g = 0; g < G; g++)
+    if (has_g[g]) sum_total += tot_g[g];
+  free(tot_g);
+  free(has_g);
   if (potential_speedup) {
     double tapp = t_app;
     if (!(tapp > 0.0)) {
@@ -540,69 +572,82 @@ int tao_outliers(const int64_t *T, int64_t R, int32_t I, int32_t G,
   if (R < 0 || I < 0 || G <= 0 || T == NULL || rank_score == NULL ||
       rank_flag == NULL || (mode != 0 && mode != 1) || (kind != 0 && kind != 1))
     return TAO_ERR_INVALID_ARG;
-  int64_t *col = (int64_t *)malloc(sizeof(int64_t) * (size_t)(R + 1));
-  int64_t *iwork = (int64_t *)malloc(sizeof(int64_t) * (size_t)(R + 1));
   int64_t *who = (int64_t *)malloc(sizeof(int64_t) * (size_t)(R + 1));
-  double *z = (double *)malloc(sizeof(double) * (size_t)(R + 1));
-  double *fwork = (double *)malloc(sizeof(double) * (size_t)(R + 1));
-  double *fcol = (double *)malloc(sizeof(double) * (size_t)(R + 1));
   double *m = (double *)calloc((size_t)R * (size_t)G + 1, sizeof(double));
   double *zr = (double *)malloc(sizeof(double) * ((size_t)R * (size_t)G + 1));
-  if (!col || !iwork || !who || !z || !fwork || !fcol || !m || !zr) return TAO_ERR_SIZE_OVERFLOW;
+  if (!who || !m || !zr) {
+    free(who); free(m); free(zr);
+    return TAO_ERR_SIZE_OVERFLOW;
+  }
 
   /* Active ranks: at least one iteration. */
   int64_t na = 0;
   for (int64_t r = 0; r < R; r++)
     if (iters_found == NULL ? I > 0 : iters_found[r] > 0) who[na++] = r;
 
-  if (mode == 0) {
-    /* Stage 1: per-cell score, summed over i in ascending order per (r,g). */
-    for (int32_t i = 0; i < I; i++) {
-      for (int32_t g = 0; g < G; g++) {
-        int64_t n = 0;
-        for (int64_t a = 0; a < na; a++) {
-          int64_t r = who[a];
-          if (valid(iters_found, r, i)) col[n++] = T[((int64_t)r * I + i) * G + g];
-        }
-        if (n == 0) continue;
-        if (kind == 0) robust_z_int(col, n, z, iwork);
-        else plain_z_int(col, n, 1, z);
-        n = 0;
-        for (int64_t a = 0; a < na; a++) {
-          int64_t r = who[a];
-          if (valid(iters_found, r, i)) m[r * G + g] += z[n++];
-        }
-      }
-    }
-    for (int64_t a = 0; a < na; a++) {
-      int64_t r = who[a];
-      double cnt = (double)(iters_found ? iters_found[r] : I);
-      if (iters_found && iters_found[r] > I) cnt = (double)I;
-      for (int32_t g = 0; g < G; g++) m[r * G + g] = m[r * G + g] / cnt;
-    }
-    /* Stage 2: per region, score of m(r,g) over active ranks. */
+  /* Regions are independent: threads take whole regions, each with its own
+   * column buffers; within a region the iterations go in ascending order. */
+  int nomem = 0;
+#pragma omp parallel reduction(| : nomem)
+  {
+    int64_t *col = (int64_t *)malloc(sizeof(int64_t) * (size_t)(R + 1));
+    int64_t *iwork = (int64_t *)malloc(sizeof(int64_t) * (size_t)(R + 1));
+    double *z = (double *)malloc(sizeof(double) * (size_t)(R + 1));
+    double *fwork = (double *)malloc(sizeof(double) * (size_t)(R + 1));
+    double *fcol = (double *)malloc(sizeof(double) * (size_t)(R + 1));
+    int ok = col && iwork && z && fwork && fcol;
+    if (!ok) nomem = 1;
+#pragma omp for schedule(dynamic, 1)
     for (int32_t g = 0; g < G; g++) {
-      for (int64_t a = 0; a < na; a++) fcol[a] = m[who[a] * G + g];
-      if (na > 0) {
-        if (kind == 0) robust_z_f64(fcol, na, z, fwork);
-        else plain_z_f64(fcol, na, 1, z, fwork);
+      if (!ok) continue;
+      if (mode == 0) {
+        /* Stage 1: per-cell score, summed over i in ascending order per (r,g). */
+        for (int32_t i = 0; i < I; i++) {
+          int64_t n = 0;
+          for (int64_t a = 0; a < na; a++) {
+            int64_t r = who[a];
+            if (valid(iters_found, r, i)) col[n++] = T[((int64_t)r * I + i) * G + g];
+          }
+          if (n == 0) continue;
+          if (kind == 0) robust_z_int(col, n, z, iwork);
+          else plain_z_int(col, n, 1, z);
+          n = 0;
+          for (int64_t a = 0; a < na; a++) {
+            int64_t r = who[a];
+            if (valid(iters_found, r, i)) m[r * G + g] += z[n++];
+          }
+        }
+        for (int64_t a = 0; a < na; a++) {
+          int64_t r = who[a];
+          double cnt = (double)(iters_found ? iters_found[r] : I);
+          if (iters_found && iters_found[r] > I) cnt = (double)I;
+          m[r * G + g] = m[r * G + g] / cnt;
+        }
+        /* Stage 2: score of m(r,g) over active ranks. */
+        for (int64_t a = 0; a < na; a++) fcol[a] = m[who[a] * G + g];
+        if (na > 0) {
+          if (kind == 0) robust_z_f64(fcol, na, z, fwork);
+          else plain_z_f64(fcol, na, 1, z, fwork);
+        }
+      } else {
+        for (int64_t a = 0; a < na; a++) {
+          int64_t r = who[a], s = 0;
+          for (int32_t i = 0; i < I; i++)
+            if (valid(iters_found, r, i)) s += T[((int64_t)r * I + i) * G + g];
+          col[a] = s;
+        }
+        if (na > 0) {
+          if (kind == 0) robust_z_int(col, na, z, iwork);
+          else plain_z_int(col, na, 1, z);
+        }
       }
       for (int64_t a = 0; a < na; a++) zr[who[a] * G + g] = z[a];
     }
-  } else {
-    for (int32_t g = 0; g < G; g++) {
-      for (int64_t a = 0; a < na; a++) {
-        int64_t r = who[a], s = 0;
-        for (int32_t i = 0; i < I; i++)
-          if (valid(iters_found, r, i)) s += T[((int64_t)r * I + i) * G + g];
-        col[a] = s;
-      }
-      if (na > 0) {
-        if (kind == 0) robust_z_int(col, na, z, iwork);
-        else plain_z_int(col, na, 1, z);
-      }
-      for (int64_t a = 0; a < na; a++) zr[who[a] * G + g] = z[a];
-    }
+    free(col); free(iwork); free(z); free(fwork); free(fcol);
+  }
+  if (nomem) {
+    free(who); free(m); free(zr);
+    return TAO_ERR_SIZE_OVERFLOW;
   }
 
   int64_t nf = 0;
@@ -625,7 +670,7 @@ int tao_outliers(const int64_t *T, int64_t R, int32_t I, int32_t G,
     nf += rank_flag[r];
   }
   if (n_flagged) n_flagged[0] = nf;
-  free(col); free(iwork); free(who); free(z); free(fwork); free(fcol); free(m); free(zr);
+  free(who); free(m); free(zr);
   return TAO_OK;
 }
 
@@ -1048,4 +1093,105 @@ int tao_sparse_profiles(int64_t R, const int64_t *off, const int64_t *ts, const 
   }
   free(row);
   return TAO_OK;
+}
+
+/* ---- Node x rank x iteration model (Sec. V: per-iteration profiles indexed
+ * by calling-context node, trace and iteration; the Thicket model keeps
+ * inclusive and exclusive metrics per node). ---- */
+
+/* For rank r and iteration i < iters_found[r] (iterations as in tao_segment:
+ * entry into the marker's subtree opens one; events before the first boundary
+ * belong to none):
+ *   excl(r,i,v) = sum of d_k over rank r's events k of iteration i with
+ *                 context v,
+ *   incl(r,i,v) = sum of excl(r,i,u) over the subtree of v (walk from each u
+ *                 up to its root).
+ * Row (r,i) of the sparse model is stored at index q = r*I + i: the nodes with
+ * a non-zero excl, in ascending node id, at node_x[row_off_x[q] + j] /
+ * val_x[...] for j < nnz_x[q]; likewise the nodes with a non-zero incl in
+ * node_i / val_i.  Rows i >= iters_found[r] are empty.  nnz_x[R*I] and
+ * nnz_i[R*I] are always written; the rows are written when row_off_x (and
+ * node_x, val_x) and row_off_i (and node_i, val_i) are given.  More than I
+ * boundaries in a rank -> TAO_ERR_ITER_OVERFLOW (nothing of that rank past
+ * iteration I-1 is stored). */
+int tao_node_model(int64_t R, const int64_t *off, const int64_t *ts, const int32_t *ctx,
+                   int32_t N, const int32_t *parent, int32_t marker, int32_t I,
+                   int64_t *nnz_x, int64_t *nnz_i, const int64_t *row_off_x, int32_t *node_x,
+                   int64_t *val_x, const int64_t *row_off_i, int32_t *node_i, int64_t *val_i) {
+  int st = tao_check_tree(N, parent);
+  if (st) return st;
+  if (marker < 0 || marker >= N || I < 1 || !nnz_x || !nnz_i) return TAO_ERR_INVALID_ARG;
+  if (row_off_x && (!node_x || !val_x)) return TAO_ERR_INVALID_ARG;
+  if (row_off_i && (!node_i || !val_i)) return TAO_ERR_INVALID_ARG;
+  st = check_traces(R, off, ts, ctx, N);
+  if (st) return st;
+  int overflow = 0;
+#pragma omp parallel reduction(| : overflow)
+  {
+    int64_t *ex = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    int64_t *in = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t r = 0; r < R; r++) {
+      for (int32_t i = 0; i < I; i++) {
+        nnz_x[r * I + i] = 0;
+        nnz_i[r * I + i] = 0;
+      }
+      const int64_t b = off[r], e = off[r + 1];
+      int32_t it = -1;
+      int prev_in = 0;
+      int64_t k = b;
+      /* prologue: events before the first boundary */
+      while (k < e) {
+        const int in_m = is_anc_or_self(parent, marker, ctx[k]);
+        if (in_m && (k == b || !prev_in)) break;
+        prev_in = in_m;
+        k++;
+      }
+      while (k < e) {
+        /* k opens iteration it + 1; find the end of that iteration */
+        it++;
+        int64_t k_end = k + 1;
+        prev_in = 1;
+        while (k_end < e) {
+          const int in_m = is_anc_or_self(parent, marker, ctx[k_end]);
+          if (in_m && !prev_in) break;
+          prev_in = in_m;
+          k_end++;
+        }
+        if (it >= I) {
+          overflow = 1;
+          break;
+        }
+        for (int32_t v = 0; v < N; v++) ex[v] = in[v] = 0;
+        for (int64_t j = k; j < k_end; j++) ex[ctx[j]] += duration(ts, j, e);
+        for (int32_t u = 0; u < N; u++)
+          if (ex[u] != 0)
+            for (int32_t a = u; a != -1; a = parent[a]) in[a] += ex[u];
+        const int64_t q = r * I + it;
+        int64_t nx = 0, ni = 0;
+        for (int32_t v = 0; v < N; v++) {
+          if (ex[v] != 0) {
+            if (row_off_x) {
+              node_x[row_off_x[q] + nx] = v;
+              val_x[row_off_x[q] + nx] = ex[v];
+            }
+            nx++;
+          }
+          if (in[v] != 0) {
+            if (row_off_i) {
+              node_i[row_off_i[q] + ni] = v;
+              val_i[row_off_i[q] + ni] = in[v];
+            }
+            ni++;
+          }
+        }
+        nnz_x[q] = nx;
+        nnz_i[q] = ni;
+        k = k_end;
+      }
+    }
+    free(ex);
+    free(in);
+  }
+  return overflow ? TAO_ERR_ITER_OVERFLOW : TAO_OK;
 }
