@@ -187,6 +187,26 @@ ta_status ta_imbalance(ta_handle h, const int64_t *tensor, int64_t n_ranks, int3
                        const uint64_t *rank_sumsq, const int64_t *span, int32_t ddof,
                        double t_app_ns, const ta_imbalance_out *o, void *stream);
 
+/* Allocation-free variant of ta_imbalance, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, outputs, results and error
+ * behaviour as ta_imbalance; it calls no allocating routine.  Its workspace is
+ * a static device array of TA_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, which
+ * the library holds from the first ta_create on that GPU until the process
+ * ends; nothing in it needs to start at zero.  A call whose workspace would
+ * exceed it (per-column partials of about 48 B x n_iters x n_regions x rank
+ * chunks, plus 24 B x n_ranks x n_regions when rank_sum or rank_sumsq is
+ * NULL) returns TA_ERR_SIZE_OVERFLOW before anything is launched.  Every call
+ * on one GPU shares that array: calls that overlap in time on one GPU (on
+ * different streams, handles or host threads) race and give undefined
+ * results; calls ordered on one stream do not. */
+#define TA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ta_status ta_imbalance_noalloc(ta_handle h, const int64_t *tensor, int64_t n_ranks,
+                               int32_t n_iters, int32_t n_regions, const int32_t *iters_found,
+                               const int64_t *rank_sum, const uint64_t *rank_sumsq,
+                               const int64_t *span, int32_t ddof, double t_app_ns,
+                               const ta_imbalance_out *o, void *stream);
+
 /* Exact outlier scan (not in the paper, which clusters ranks, Sec. VI-B; this
  * is the textbook modified z-score).  Ranks with no iteration take no part and
  * score 0.

@@ -56,6 +56,43 @@ ta_status hipfail(ta_handle h, hipError_t e, const char *what) {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Workspace of ta_imbalance_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory, so it is never passed to a kernel or a copy:
+// its device address is looked up once per device (ta_create, with that
+// device current) and that address is used instead.
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[TA_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+hipError_t g_scratch_err[SCRATCH_MAX_DEVICES] = {};
+bool g_scratch_done[SCRATCH_MAX_DEVICES] = {};
+
+// Called with `device` current.
+void scratch_setup(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_done[device]) return;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+  g_scratch_done[device] = true;
+}
+
+ta_status scratch_address(ta_handle h, void **out) {
+  const int d = h->device;
+  if (d < 0 || d >= SCRATCH_MAX_DEVICES)
+    return fail(h, TA_ERR_INVALID_ARG, "device index above the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[d] || !g_scratch_ptr[d])
+    return fail(h, TA_ERR_HIP,
+                std::string("device address of the static scratch array unavailable: ") +
+                    hipGetErrorString(g_scratch_done[d] ? g_scratch_err[d] : hipErrorNotReady));
+  *out = g_scratch_ptr[d];
+  return TA_OK;
+}
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int d) {
@@ -550,6 +587,7 @@ ta_status ta_create(ta_handle *out, int device) {
     delete h;
     return TA_ERR_HIP;
   }
+  scratch_setup(device);
   *out = h;
   return TA_OK;
 }
@@ -668,11 +706,13 @@ ta_status ta_attribute_segment(ta_handle h, const ta_traces *t, int32_t n_iters,
   return run_segment(h, t, n_iters, out, stream, true, true);
 }
 
-ta_status ta_imbalance(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
-                       int32_t n_regions, const int32_t *iters_found, const int64_t *rank_sum,
-                       const uint64_t *rank_sumsq, const int64_t *span, int32_t ddof,
-                       double t_app_ns, const ta_imbalance_out *o, void *stream) {
-  if (!h) return TA_ERR_INVALID_ARG;
+namespace {
+
+// Argument checks shared by ta_imbalance and ta_imbalance_noalloc.
+ta_status imbalance_args(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                         int32_t n_regions, const int32_t *iters_found, const int64_t *rank_sum,
+                         const uint64_t *rank_sumsq, const int64_t *span, int32_t ddof,
+                         const ta_imbalance_out *o) {
   if (!o) return fail(h, TA_ERR_INVALID_ARG, "outputs NULL");
   if (n_ranks < 0 || n_iters < 1 || n_regions < 1 || ddof < 0)
     return fail(h, TA_ERR_INVALID_ARG, "bad sizes or ddof");
@@ -685,10 +725,15 @@ ta_status ta_imbalance(ta_handle h, const int64_t *tensor, int64_t n_ranks, int3
                         o->cv_within, o->share, o->potential_speedup};
   for (const void *p : ptrs)
     if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  return TA_OK;
+}
+
+ta_status imbalance_launch(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                           int32_t n_regions, const int32_t *iters_found, const int64_t *rank_sum,
+                           const uint64_t *rank_sumsq, const int64_t *span, int32_t ddof,
+                           double t_app_ns, const ta_imbalance_out *o, void *ws, size_t ws_bytes,
+                           void *stream) {
   const bool need_rs = !rank_sum || !rank_sumsq;
-  DeviceGuard dg(h->device);
-  ta_status st = ensure_ws(h, ta::imbalance_ws_bytes(n_ranks, n_iters, n_regions, need_rs));
-  if (st) return st;
   ta::ImbArgs a{};
   a.T = tensor;
   a.R = n_ranks;
@@ -701,9 +746,53 @@ ta_status ta_imbalance(ta_handle h, const int64_t *tensor, int64_t n_ranks, int3
   a.ddof = ddof;
   a.t_app = t_app_ns;
   a.o = *o;
-  hipError_t e = ta::launch_imbalance(a, h->ws, h->ws_bytes, (hipStream_t)stream);
+  hipError_t e = ta::launch_imbalance(a, ws, ws_bytes, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "imbalance launch");
   return TA_OK;
+}
+
+}  // namespace
+
+ta_status ta_imbalance(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
+                       int32_t n_regions, const int32_t *iters_found, const int64_t *rank_sum,
+                       const uint64_t *rank_sumsq, const int64_t *span, int32_t ddof,
+                       double t_app_ns, const ta_imbalance_out *o, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  ta_status st = imbalance_args(h, tensor, n_ranks, n_iters, n_regions, iters_found, rank_sum,
+                                rank_sumsq, span, ddof, o);
+  if (st) return st;
+  const bool need_rs = !rank_sum || !rank_sumsq;
+  DeviceGuard dg(h->device);
+  st = ensure_ws(h, ta::imbalance_ws_bytes(n_ranks, n_iters, n_regions, need_rs));
+  if (st) return st;
+  return imbalance_launch(h, tensor, n_ranks, n_iters, n_regions, iters_found, rank_sum,
+                          rank_sumsq, span, ddof, t_app_ns, o, h->ws, h->ws_bytes, stream);
+}
+
+ta_status ta_imbalance_noalloc(ta_handle h, const int64_t *tensor, int64_t n_ranks,
+                               int32_t n_iters, int32_t n_regions, const int32_t *iters_found,
+                               const int64_t *rank_sum, const uint64_t *rank_sumsq,
+                               const int64_t *span, int32_t ddof, double t_app_ns,
+                               const ta_imbalance_out *o, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  ta_status st = imbalance_args(h, tensor, n_ranks, n_iters, n_regions, iters_found, rank_sum,
+                                rank_sumsq, span, ddof, o);
+  if (st) return st;
+  const bool need_rs = !rank_sum || !rank_sumsq;
+  const size_t need = ta::imbalance_ws_bytes(n_ranks, n_iters, n_regions, need_rs);
+  if (need > (size_t)TA_NOALLOC_SCRATCH_BYTES)
+    return fail(h, TA_ERR_SIZE_OVERFLOW,
+                "ta_imbalance_noalloc needs " + std::to_string(need) +
+                    " bytes of workspace, above its static scratch of " +
+                    std::to_string((size_t)TA_NOALLOC_SCRATCH_BYTES) +
+                    " bytes (pass rank_sum and rank_sumsq, or call ta_imbalance)");
+  void *ws = nullptr;
+  st = scratch_address(h, &ws);
+  if (st) return st;
+  DeviceGuard dg(h->device);
+  return imbalance_launch(h, tensor, n_ranks, n_iters, n_regions, iters_found, rank_sum,
+                          rank_sumsq, span, ddof, t_app_ns, o, ws,
+                          (size_t)TA_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 ta_status ta_outliers(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,

@@ -80,6 +80,7 @@ def _load():
         "ta_segment": [P, P, i32, P, P, P, P],
         "ta_attribute_segment": [P, P, i32, P, P],
         "ta_imbalance": [P, P, i64, i32, i32, P, P, P, P, i32, f64, P, P],
+        "ta_imbalance_noalloc": [P, P, i64, i32, i32, P, P, P, P, i32, f64, P, P],
         "ta_outliers": [P, P, i64, i32, i32, P, i32, i32, f64, P, P, P, P, P],
         "ta_topology_aggregate": [P, P, P, i64, P, P, P, i32, i32, i32, P, P, P, P, P, P, P],
         "ta_summary": [P, P, i64, P, P, P],
@@ -404,8 +405,18 @@ class Handle:
 
     # -- statistics ----------------------------------------------------------
     def imbalance(self, tensor, iters_found=None, rank_sum=None, rank_sumsq=None, span=None,
-                  ddof=1, t_app=0.0):
+                  ddof=1, t_app=0.0, out=None, noalloc=False):
+        """ta_imbalance (or ta_imbalance_noalloc when noalloc is set: the
+        library's static scratch instead of its workspace).  `out` reuses
+        preallocated outputs (a dict as returned)."""
         R, I, G = tensor.shape
+        if out is not None:
+            io = ImbOut(*[_ptr(out[k]).value for k in IMB_FIELDS])
+            fn = _lib.ta_imbalance_noalloc if noalloc else _lib.ta_imbalance
+            self._check(fn(self.h, _ptr(tensor), R, I, G, _ptr(iters_found), _ptr(rank_sum),
+                           _ptr(rank_sumsq), _ptr(span), int(ddof), float(t_app), C.byref(io),
+                           _stream(self.device)))
+            return out
         o = {}
         for k in ("mean", "std", "max_minus_mean"):
             o[k] = self._empty((I, G), torch.float64)
@@ -415,11 +426,8 @@ class Handle:
                   "cv_across", "cv_within", "share"):
             o[k] = self._empty((G,), torch.float64)
         o["potential_speedup"] = self._empty((1,), torch.float64)
-        io = ImbOut(*[_ptr(o[k]).value for k in IMB_FIELDS])
-        self._check(_lib.ta_imbalance(self.h, _ptr(tensor), R, I, G, _ptr(iters_found),
-                                      _ptr(rank_sum), _ptr(rank_sumsq), _ptr(span), int(ddof),
-                                      float(t_app), C.byref(io), _stream(self.device)))
-        return o
+        return self.imbalance(tensor, iters_found, rank_sum, rank_sumsq, span, ddof, t_app,
+                              out=o, noalloc=noalloc)
 
     def outliers(self, tensor, iters_found=None, mode=SCAN_FULL, kind=SCORE_MAD, tau=3.5,
                  region=False):
