@@ -277,8 +277,9 @@ def sparse_profiles(offsets, ts, ctx, n_nodes):
 def node_model(offsets, ts, ctx, parent, marker, n_iters):
     """Sparse node x rank x iteration model.  -> (status, model) where model
     holds, for the rows q = r*I + i: nnz_x[q], row_off_x[q+1] (exclusive
-    prefix), node_x, val_x (non-zero exclusive costs in ascending node id) and
-    nnz_i, row_off_i, node_i, val_i (non-zero inclusive costs)."""
+    prefix), node_x, val_x (non-zero exclusive costs, nodes in the tree's
+    preorder with children and roots in ascending id) and nnz_i, row_off_i,
+    node_i, val_i (non-zero inclusive costs, same order)."""
     offsets, ts, ctx = _arr(offsets, np.int64), _arr(ts, np.int64), _arr(ctx, np.int32)
     parent = _arr(parent, np.int32)
     R, N, I = len(offsets) - 1, len(parent), int(n_iters)

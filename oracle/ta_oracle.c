@@ -1107,9 +1107,10 @@ int tao_sparse_profiles(int64_t R, const int64_t *off, const int64_t *ts, const 
  *   incl(r,i,v) = sum of excl(r,i,u) over the subtree of v (walk from each u
  *                 up to its root).
  * Row (r,i) of the sparse model is stored at index q = r*I + i: the nodes with
- * a non-zero excl, in ascending node id, at node_x[row_off_x[q] + j] /
- * val_x[...] for j < nnz_x[q]; likewise the nodes with a non-zero incl in
- * node_i / val_i.  Rows i >= iters_found[r] are empty.  nnz_x[R*I] and
+ * a non-zero excl, in the tree's preorder (every node before its descendants;
+ * the children of a node, and the roots of a forest, in ascending id), at
+ * node_x[row_off_x[q] + j] / val_x[...] for j < nnz_x[q]; likewise the nodes
+ * with a non-zero incl, in the same order, in node_i / val_i.  Rows i >= iters_found[r] are empty.  nnz_x[R*I] and
  * nnz_i[R*I] are always written; the rows are written when row_off_x (and
  * node_x, val_x) and row_off_i (and node_i, val_i) are given.  More than I
  * boundaries in a rank -> TAO_ERR_ITER_OVERFLOW (nothing of that rank past
@@ -1125,6 +1126,36 @@ int tao_node_model(int64_t R, const int64_t *off, const int64_t *ts, const int32
   if (row_off_i && (!node_i || !val_i)) return TAO_ERR_INVALID_ARG;
   st = check_traces(R, off, ts, ctx, N);
   if (st) return st;
+  /* the preorder: children grouped by parent in ascending id (counting sort),
+   * then a depth-first walk from each root in ascending id */
+  int32_t *first = (int32_t *)calloc((size_t)N + 1, sizeof(int32_t));
+  int32_t *kids = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  int32_t *stk = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  if (!first || !kids || !fill || !order || !stk) {
+    free(first); free(kids); free(fill); free(order); free(stk);
+    return TAO_ERR_INVALID_ARG;
+  }
+  for (int32_t v = 0; v < N; v++)
+    if (parent[v] >= 0) first[parent[v] + 1]++;
+  for (int32_t v = 0; v < N; v++) first[v + 1] += first[v];
+  for (int32_t v = 0; v < N; v++) fill[v] = first[v];
+  for (int32_t v = 0; v < N; v++)
+    if (parent[v] >= 0) kids[fill[parent[v]]++] = v;
+  int32_t n_ord = 0;
+  for (int32_t root = 0; root < N; root++) {
+    if (parent[root] != -1) continue;
+    int32_t top = 0;
+    stk[top++] = root;
+    while (top > 0) {
+      const int32_t v = stk[--top];
+      order[n_ord++] = v;
+      /* push the children in descending id so the smallest is visited next */
+      for (int32_t c = first[v + 1] - 1; c >= first[v]; c--) stk[top++] = kids[c];
+    }
+  }
+  free(first); free(kids); free(fill); free(stk);
   int overflow = 0;
 #pragma omp parallel reduction(| : overflow)
   {
@@ -1169,7 +1200,8 @@ int tao_node_model(int64_t R, const int64_t *off, const int64_t *ts, const int32
             for (int32_t a = u; a != -1; a = parent[a]) in[a] += ex[u];
         const int64_t q = r * I + it;
         int64_t nx = 0, ni = 0;
-        for (int32_t v = 0; v < N; v++) {
+        for (int32_t j = 0; j < N; j++) {
+          const int32_t v = order[j];
           if (ex[v] != 0) {
             if (row_off_x) {
               node_x[row_off_x[q] + nx] = v;
@@ -1193,5 +1225,6 @@ int tao_node_model(int64_t R, const int64_t *off, const int64_t *ts, const int32
     free(ex);
     free(in);
   }
+  free(order);
   return overflow ? TAO_ERR_ITER_OVERFLOW : TAO_OK;
 }

@@ -33,7 +33,7 @@ import numpy as np
 
 __all__ = [
     "make_tree", "pick_marker", "pick_regions", "subtree_members", "Workload",
-    "plain_workload", "timeline_workload", "hand_example", "topology",
+    "plain_workload", "timeline_workload", "hand_example", "topology", "relabel",
 ]
 
 # Workload ids used in the seed sequences.
@@ -286,6 +286,27 @@ def timeline_workload(seed: int = 0, n_ranks: int = 10_000, median_len: int = 50
     if keep_truth:
         w["truth"] = np.stack(truths) if truths else np.zeros((0, I, G), np.int64)
     return w
+
+
+def relabel(w: Workload, seed: int) -> Workload:
+    """The same workload with its node ids renamed by a seeded random
+    permutation (node v becomes perm[v] in the tree, the contexts, the marker
+    and the regions), so that ids no longer follow the tree's order; every
+    cost per node is unchanged under the renaming."""
+    rng = np.random.default_rng(np.random.SeedSequence([3, seed]))
+    N = len(w["parent"])
+    perm = rng.permutation(N).astype(np.int32)
+    parent = np.full(N, -1, np.int32)
+    for v in range(N):
+        p = int(w["parent"][v])
+        parent[perm[v]] = -1 if p < 0 else perm[p]
+    out = Workload(w)
+    out["parent"] = parent
+    out["ctx"] = perm[w["ctx"]].astype(np.int32)
+    out["marker"] = int(perm[w["marker"]])
+    out["regions"] = perm[np.asarray(w["regions"], np.int64)].astype(np.int32)
+    out["perm"] = perm
+    return out
 
 
 def hand_example() -> Workload:

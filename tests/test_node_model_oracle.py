@@ -12,6 +12,11 @@ exclusive and inclusive costs per node).
 * with disjoint regions, the inclusive cost of each region node equals the
   rank x iteration x region tensor;
 * no marker event: empty rows; more boundaries than n_iters: ITER_OVERFLOW.
+
+Within a row the nodes are listed in the tree's preorder (a node before its
+descendants, children and roots in ascending id), the order in which a
+calling context tree is walked from its roots; the relabelled workload has
+ids that are not in that order.
 """
 import json
 import os
@@ -28,6 +33,25 @@ def rows(m, q, which):
     o = m["row_off_" + which]
     return (m["node_" + which][o[q]:o[q + 1]].tolist(),
             m["val_" + which][o[q]:o[q + 1]].tolist())
+
+
+def preorder(parent):
+    """Depth-first order from the roots, children and roots in ascending id."""
+    kids = [[] for _ in parent]
+    for v, p in enumerate(parent):
+        if p >= 0:
+            kids[p].append(v)
+    out = []
+
+    def visit(v):
+        out.append(v)
+        for c in kids[v]:
+            visit(c)
+
+    for v, p in enumerate(parent):
+        if p == -1:
+            visit(v)
+    return out
 
 
 def boundaries(w, r, parent, marker):
@@ -72,6 +96,10 @@ WORKLOADS = {
     "timeline": lambda: synth.timeline_workload(seed=4, n_ranks=6, median_len=1500,
                                                 min_len=400, max_len=4000, n_nodes=150,
                                                 depth_max=8, n_iters=12, n_regions=10),
+    "relabelled": lambda: synth.relabel(
+        synth.timeline_workload(seed=5, n_ranks=5, median_len=1200, min_len=300,
+                                max_len=3000, n_nodes=140, depth_max=8, n_iters=10,
+                                n_regions=9), seed=6),
 }
 
 
@@ -82,6 +110,7 @@ def test_brute_force_resegmentation(oracle, name):
     st, m = oracle.node_model(w.offsets, w.ts, w.ctx, w.parent, w.marker, I)
     assert st == 0
     N = len(w.parent)
+    pre = np.array(preorder(w.parent), np.int64)
     for r in range(w.n_ranks):
         bs = boundaries(w, r, w.parent, w.marker)
         e = int(w.offsets[r + 1])
@@ -97,7 +126,7 @@ def test_brute_force_resegmentation(oracle, name):
             assert st == 0
             for which, dense in (("x", ex[0]), ("i", inc[0])):
                 ids, vals = rows(m, q, which)
-                nz = np.flatnonzero(dense)
+                nz = pre[dense[pre] != 0]       # non-zero nodes in preorder
                 assert ids == nz.tolist() and vals == dense[nz].tolist(), (r, i, which)
         # summed over iterations: the attribution of the trace from its first boundary on
         if bs:
@@ -150,3 +179,25 @@ def test_no_marker_and_overflow(oracle):
     st, m = oracle.node_model(w.offsets, w.ts, w.ctx, parent, 6, 3)
     assert st == 0
     assert m["nnz_x"].sum() == 0 and m["nnz_i"].sum() == 0 and len(m["node_x"]) == 0
+
+
+def test_relabelling_renames_entries(oracle):
+    """Renaming the node ids renames the entries of every row and keeps each
+    cost; only the order within a row follows the renamed tree's preorder."""
+    base = synth.timeline_workload(seed=7, n_ranks=4, median_len=1000, min_len=300,
+                                   max_len=2500, n_nodes=90, depth_max=7, n_iters=8,
+                                   n_regions=7)
+    w = synth.relabel(base, seed=8)
+    I = base.n_iters
+    st, a = oracle.node_model(base.offsets, base.ts, base.ctx, base.parent, base.marker, I)
+    st2, b = oracle.node_model(w.offsets, w.ts, w.ctx, w.parent, w.marker, I)
+    assert st == 0 and st2 == 0
+    pre = preorder(w.parent)
+    where = {v: j for j, v in enumerate(pre)}
+    assert np.array_equal(a["nnz_x"], b["nnz_x"]) and np.array_equal(a["nnz_i"], b["nnz_i"])
+    for q in range(base.n_ranks * I):
+        for which in ("x", "i"):
+            ia, va = rows(a, q, which)
+            ib, vb = rows(b, q, which)
+            assert dict(zip(w.perm[ia].tolist(), va)) == dict(zip(ib, vb))
+            assert [where[v] for v in ib] == sorted(where[v] for v in ib)
