@@ -235,6 +235,41 @@ ta_status ta_outliers(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32
                       double tau, double *rank_score, uint8_t *rank_flag, int64_t *n_flagged,
                       double *region_score, void *stream);
 
+/* Sparse node x rank x iteration model (Sec. V: one profile per iteration,
+ * indexed by calling-context node, trace and iteration; Thicket keeps
+ * inclusive and exclusive costs per node).  Row q = r * n_iters + i is
+ * iteration i of rank r, iterations as in ta_segment (entry into the subtree
+ * of the marker given to ta_set_regions opens one; events before the first
+ * boundary belong to no row).  Its entries:
+ *   exclusive: (v, excl) for every node v with excl(r,i,v) != 0, where
+ *     excl(r,i,v) = sum of d_k over rank r's events k of iteration i with
+ *     context v (d_k = t_{k+1} - t_k, 0 for a rank's last event);
+ *   inclusive: (v, incl) for every node with incl(r,i,v) != 0, where incl is
+ *     the sum of excl over the subtree of v;
+ * each list in the tree's preorder (a node before its descendants, children
+ * and roots in ascending id).  Rows i >= iters_found[r] are empty.  Any tree
+ * size up to 2^22 nodes.  Two calls on the same traces, n_iters and tables:
+ * ta_node_model_count writes row_start[R * n_iters] (index in ts/ctx of the
+ * event that opens row q, written for i < iters_found[r]), iters_found[R],
+ * and row_off_x, row_off_i [R * n_iters + 1]: the number of exclusive
+ * (inclusive) entries of the rows before q, so [R * n_iters] holds the
+ * total.  The caller reads the totals to size the entry arrays, then
+ * ta_node_model_fill writes row q's entries at [row_off_x[q], row_off_x[q+1])
+ * of node_x (caller ids) / val_x, and at [row_off_i[q], row_off_i[q+1]) of
+ * node_i / val_i; either pair may be NULL to skip that list.  All arrays are
+ * device pointers.  Sticky device errors: context out of range, a timestamp
+ * decreasing inside a row, inconsistent offsets, more than n_iters
+ * boundaries in a rank (TA_ERR_ITER_OVERFLOW; iters_found is then n_iters).  TA_ERR_STATE without
+ * ta_set_tree and ta_set_regions. */
+ta_status ta_node_model_count(ta_handle h, const ta_traces *t, int32_t n_iters,
+                              int64_t *row_start, int32_t *iters_found, int64_t *row_off_x,
+                              int64_t *row_off_i, void *stream);
+ta_status ta_node_model_fill(ta_handle h, const ta_traces *t, int32_t n_iters,
+                             const int64_t *row_start, const int32_t *iters_found,
+                             const int64_t *row_off_x, int32_t *node_x, int64_t *val_x,
+                             const int64_t *row_off_i, int32_t *node_i, int64_t *val_i,
+                             void *stream);
+
 /* Node-level and physical localisation (Sec. VI-B: ranks are joined with their
  * compute node, nodes are mapped to rack and chassis coordinates).  For each
  * rack and each chassis: the number of flagged ranks placed there, their max

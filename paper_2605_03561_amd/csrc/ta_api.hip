@@ -22,6 +22,8 @@ struct ta_handle_s {
   uint32_t *d_info = nullptr;
   int2 *d_tin_tout = nullptr;
   int4 *d_rt = nullptr;  // regions in preorder: see region_table()
+  // by preorder position: caller id, parent position (-1 at a root), subtree end
+  int4 *d_ptab = nullptr;
   // pruned tree (ta_set_pruned): kept nodes' preorder ranges and, for each, the
   // index of its nearest kept strict ancestor (-1 if none)
   int32_t K = 0;
@@ -214,18 +216,25 @@ ta_status upload_tables(ta_handle h) {
   }
   std::vector<int2> tt(N);
   for (int32_t v = 0; v < N; v++) tt[v] = make_int2(h->tin[v], h->tout[v]);
+  std::vector<int4> pt(N);
+  for (int32_t v = 0; v < N; v++)
+    pt[h->tin[v]] = make_int4(v, h->parent[v] >= 0 ? h->tin[h->parent[v]] : -1, h->tout[v], 0);
   // Kernels still queued may read the previous tables.
-  if (h->d_info || h->d_tin_tout || h->d_rt) TA_HIP(h, hipDeviceSynchronize());
+  if (h->d_info || h->d_tin_tout || h->d_rt || h->d_ptab) TA_HIP(h, hipDeviceSynchronize());
   if (h->d_info) hipFree(h->d_info);
   if (h->d_tin_tout) hipFree(h->d_tin_tout);
   if (h->d_rt) hipFree(h->d_rt);
+  if (h->d_ptab) hipFree(h->d_ptab);
   h->d_info = nullptr;
   h->d_tin_tout = nullptr;
   h->d_rt = nullptr;
+  h->d_ptab = nullptr;
   TA_HIP(h, hipMalloc(&h->d_info, (size_t)N * sizeof(uint32_t)));
   TA_HIP(h, hipMalloc(&h->d_tin_tout, (size_t)N * sizeof(int2)));
+  TA_HIP(h, hipMalloc(&h->d_ptab, (size_t)N * sizeof(int4)));
   TA_HIP(h, hipMemcpy(h->d_info, info.data(), (size_t)N * sizeof(uint32_t), hipMemcpyHostToDevice));
   TA_HIP(h, hipMemcpy(h->d_tin_tout, tt.data(), (size_t)N * sizeof(int2), hipMemcpyHostToDevice));
+  TA_HIP(h, hipMemcpy(h->d_ptab, pt.data(), (size_t)N * sizeof(int4), hipMemcpyHostToDevice));
   if (h->G > 0) {
     const std::vector<int4> rt = region_table(h);
     TA_HIP(h, hipMalloc(&h->d_rt, rt.size() * sizeof(int4)));
@@ -600,6 +609,7 @@ ta_status ta_destroy(ta_handle h) {
   if (h->d_info) hipFree(h->d_info);
   if (h->d_tin_tout) hipFree(h->d_tin_tout);
   if (h->d_rt) hipFree(h->d_rt);
+  if (h->d_ptab) hipFree(h->d_ptab);
   free_pruned(h);
   if (h->d_err) hipFree(h->d_err);
   if (h->ws) hipFree(h->ws);
@@ -1014,6 +1024,92 @@ ta_status ta_sparse_profiles(ta_handle h, const ta_traces *t, int64_t *counts, i
                                             counts, node_ids,
                                             excl, h->d_err, device_cus(h->device), (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(h, e, "sparse profiles launch");
+  return TA_OK;
+}
+
+namespace {
+
+ta_status node_model_args(ta_handle h, const ta_traces *t, int32_t n_iters, ta::NodeModelArgs *m) {
+  ta_status st = check_traces(h, t);
+  if (st) return st;
+  if (h->N <= 0) return fail(h, TA_ERR_STATE, "ta_set_tree has not been called");
+  if (h->marker < 0) return fail(h, TA_ERR_STATE, "ta_set_regions (the marker) has not been called");
+  if (n_iters < 1) return fail(h, TA_ERR_INVALID_ARG, "n_iters must be >= 1");
+  if ((double)t->n_ranks * (double)n_iters > 4e18)
+    return fail(h, TA_ERR_SIZE_OVERFLOW, "n_ranks * n_iters too large");
+  m->off = t->offsets;
+  m->ts = t->ts;
+  m->ctx = t->ctx;
+  m->R = t->n_ranks;
+  m->E = t->n_events;
+  m->I = n_iters;
+  m->N = h->N;
+  m->info = h->d_info;
+  m->ptab = h->d_ptab;
+  m->err = h->d_err;
+  return TA_OK;
+}
+
+}  // namespace
+
+ta_status ta_node_model_count(ta_handle h, const ta_traces *t, int32_t n_iters, int64_t *row_start,
+                              int32_t *iters_found, int64_t *row_off_x, int64_t *row_off_i,
+                              void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  ta::NodeModelArgs m{};
+  ta_status st = node_model_args(h, t, n_iters, &m);
+  if (st) return st;
+  if (!row_off_x || !row_off_i || (t->n_ranks > 0 && (!row_start || !iters_found)))
+    return fail(h, TA_ERR_INVALID_ARG, "row_start, iters_found, row_off_x and row_off_i are required");
+  const void *ptrs[] = {row_start, iters_found, row_off_x, row_off_i};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  m.row_start = row_start;
+  m.iters_found = iters_found;
+  m.row_off_x = row_off_x;
+  m.row_off_i = row_off_i;
+  DeviceGuard dg(h->device);
+  const int cus = device_cus(h->device);
+  st = ensure_ws(h, ta::node_model_ws_bytes(m.R, m.I, m.E, m.N, cus));
+  if (st) return st;
+  hipError_t e = ta::launch_node_model(m, false, h->ws, cus, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "node model count launch");
+  return TA_OK;
+}
+
+ta_status ta_node_model_fill(ta_handle h, const ta_traces *t, int32_t n_iters,
+                             const int64_t *row_start, const int32_t *iters_found,
+                             const int64_t *row_off_x, int32_t *node_x, int64_t *val_x,
+                             const int64_t *row_off_i, int32_t *node_i, int64_t *val_i,
+                             void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  ta::NodeModelArgs m{};
+  ta_status st = node_model_args(h, t, n_iters, &m);
+  if (st) return st;
+  if (t->n_ranks > 0 && (!row_start || !iters_found))
+    return fail(h, TA_ERR_INVALID_ARG, "row_start and iters_found are required");
+  if ((node_x || val_x) && (!node_x || !val_x || !row_off_x))
+    return fail(h, TA_ERR_INVALID_ARG, "node_x, val_x and row_off_x go together");
+  if ((node_i || val_i) && (!node_i || !val_i || !row_off_i))
+    return fail(h, TA_ERR_INVALID_ARG, "node_i, val_i and row_off_i go together");
+  if (!node_x && !node_i) return fail(h, TA_ERR_INVALID_ARG, "no output requested");
+  const void *ptrs[] = {row_start, iters_found, row_off_x, node_x, val_x, row_off_i, node_i, val_i};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
+  m.row_start = const_cast<int64_t *>(row_start);
+  m.iters_found = const_cast<int32_t *>(iters_found);
+  m.row_off_x = const_cast<int64_t *>(row_off_x);
+  m.row_off_i = const_cast<int64_t *>(row_off_i);
+  m.node_x = node_x;
+  m.val_x = val_x;
+  m.node_i = node_i;
+  m.val_i = val_i;
+  DeviceGuard dg(h->device);
+  const int cus = device_cus(h->device);
+  st = ensure_ws(h, ta::node_model_ws_bytes(m.R, m.I, m.E, m.N, cus));
+  if (st) return st;
+  hipError_t e = ta::launch_node_model(m, true, h->ws, cus, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(h, e, "node model fill launch");
   return TA_OK;
 }
 

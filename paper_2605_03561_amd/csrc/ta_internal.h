@@ -175,6 +175,25 @@ hipError_t launch_pruned_profiles(const int64_t *excl, int64_t R, int N, const i
 hipError_t launch_tensor_inclusive(const int64_t *T, int64_t n_rows, int G, const int4 *rt,
                                    int64_t *out, int cus, hipStream_t s);
 
+// Sparse node x rank x iteration model (k_nodemodel.hip).  ptab[p] for the
+// preorder position p: (caller id, parent position or -1, subtree end, 0).
+struct NodeModelArgs {
+  const int64_t *off, *ts;
+  const int32_t *ctx;
+  int64_t R, E;
+  int I, N;
+  const uint32_t *info;
+  const int4 *ptab;
+  int64_t *row_start;     // count: written; fill: read
+  int32_t *iters_found;   // count: written; fill: read
+  int64_t *row_off_x, *row_off_i;  // count: written ([R*I + 1]); fill: read
+  int32_t *node_x, *node_i;
+  int64_t *val_x, *val_i;
+  uint32_t *err;
+};
+size_t node_model_ws_bytes(int64_t R, int I, int64_t E, int N, int cus);
+hipError_t launch_node_model(const NodeModelArgs &m, bool fill, void *ws, int cus, hipStream_t s);
+
 // Clustering of ranks (k_cluster.hip).
 size_t kmeans_ws_bytes(int K, int D, int64_t R);
 hipError_t launch_kmeans(const int64_t *X, int64_t R, int D, int K, const double *C0, int max_iter,

@@ -90,6 +90,8 @@ def _load():
         "ta_tensor_inclusive": [P, P, i64, i32, P, P],
         "ta_window_profile": [P, P, P, i64, i64, i64, P, P, P],
         "ta_sparse_profiles": [P, P, P, P, P, P],
+        "ta_node_model_count": [P, P, i32, P, P, P, P, P],
+        "ta_node_model_fill": [P, P, i32, P, P, P, P, P, P, P, P, P],
         "ta_kmeans": [P, P, i64, i32, i32, P, i32, P, P, P, P, P],
         "ta_dbscan1d": [P, P, i64, i64, i64, P, P, P, P],
         "ta_node_intersections": [P, P, P, i64, i32, i32, P, P, P],
@@ -363,6 +365,49 @@ class Handle:
         self._check(_lib.ta_sparse_profiles(self.h, C.byref(t), _ptr(counts), _ptr(ids), _ptr(ex),
                                             _stream(self.device)))
         return counts, ids, ex
+
+    # -- node x rank x iteration model ---------------------------------------
+    def node_model_count(self, tr: DeviceTraces, n_iters: int):
+        """Row starts, iterations per rank and the CSR row offsets (device):
+        (row_start [R*I], iters_found [R], row_off_x [R*I+1], row_off_i [R*I+1])."""
+        R = tr.n_ranks
+        rs = self._empty((max(R * n_iters, 1),), torch.int64)
+        it = self._empty((max(R, 1),), torch.int32)
+        ox = self._empty((R * n_iters + 1,), torch.int64)
+        oi = self._empty((R * n_iters + 1,), torch.int64)
+        t = tr.struct()
+        self._check(_lib.ta_node_model_count(self.h, C.byref(t), int(n_iters), _ptr(rs), _ptr(it),
+                                             _ptr(ox), _ptr(oi), _stream(self.device)))
+        return rs, it, ox, oi
+
+    def node_model_fill(self, tr: DeviceTraces, n_iters: int, counted, n_x: int, n_i: int,
+                        excl=True, incl=True):
+        """Entries of every row (device): (node_x, val_x, node_i, val_i) with
+        n_x / n_i entries (None for a list not asked for)."""
+        rs, it, ox, oi = counted
+        nx = self._empty((max(n_x, 1),), torch.int32) if excl else None
+        vx = self._empty((max(n_x, 1),), torch.int64) if excl else None
+        ni = self._empty((max(n_i, 1),), torch.int32) if incl else None
+        vi = self._empty((max(n_i, 1),), torch.int64) if incl else None
+        t = tr.struct()
+        self._check(_lib.ta_node_model_fill(self.h, C.byref(t), int(n_iters), _ptr(rs), _ptr(it),
+                                            _ptr(ox), _ptr(nx), _ptr(vx), _ptr(oi), _ptr(ni),
+                                            _ptr(vi), _stream(self.device)))
+        return (nx[:n_x] if excl else None, vx[:n_x] if excl else None,
+                ni[:n_i] if incl else None, vi[:n_i] if incl else None)
+
+    def node_model(self, tr: DeviceTraces, n_iters: int):
+        """Sparse node x rank x iteration model: count, size the entry arrays
+        from the totals (one device-to-host read), fill.  Returns a dict of
+        device tensors: row_start, iters_found, row_off_x/node_x/val_x and
+        row_off_i/node_i/val_i (rows q = r * n_iters + i)."""
+        counted = self.node_model_count(tr, n_iters)
+        R = tr.n_ranks
+        n_x = int(counted[2][R * n_iters].item())
+        n_i = int(counted[3][R * n_iters].item())
+        nx, vx, ni, vi = self.node_model_fill(tr, n_iters, counted, n_x, n_i)
+        return {"row_start": counted[0], "iters_found": counted[1], "row_off_x": counted[2],
+                "node_x": nx, "val_x": vx, "row_off_i": counted[3], "node_i": ni, "val_i": vi}
 
     # -- clustering of ranks ---------------------------------------------------
     def kmeans(self, X, init, max_iter=100):
