@@ -455,6 +455,18 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
                          const ta_batch_desc *d, ta_plan *out, void *stream);
 /* Replays the captured graph on `stream`. */
 ta_status ta_plan_launch(ta_plan p, void *stream);
+/* Replays the graph like ta_plan_launch, with the event record nodes that
+ * sit right before and right after the fused pass in the graph pointed at
+ * the plan's event pair number `slot` (0 <= slot < 4096; pairs are created on
+ * first use), so each replay of a timed loop keeps its own pair and no host
+ * synchronisation is needed between replays.  TA_ERR_STATE if the graph has
+ * no timing nodes.  For the measurement of the fused pass inside the whole
+ * step (what a one-kernel graph would not show). */
+ta_status ta_plan_launch_timed(ta_plan p, int32_t slot, void *stream);
+/* Milliseconds between the two events of `slot` (the fused pass of the
+ * replay that used it, plus the record nodes' own latency); waits for that
+ * replay to reach the second event. */
+ta_status ta_plan_segment_ms(ta_plan p, int32_t slot, float *ms);
 /* The chosen launch shape (threads per workgroup, events per thread per tile,
  * streaming loads, workgroups per CU of a persistent grid or 0) and its
  * measured time (ms; 0 when not tuned).  Any pointer may be NULL. */

@@ -398,6 +398,11 @@ struct ta_plan_s {
   hipGraphExec_t exec = nullptr;
   ta::SegShape shape;
   float tuned_ms = 0.f;
+  // Event record nodes just before and just after the fused pass in the graph
+  // (null when they could not be added), and the event pairs they are pointed
+  // at by ta_plan_launch_timed, one pair per slot.
+  hipGraphNode_t rec[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> slots;
 };
 
 namespace {
@@ -410,6 +415,8 @@ void plan_free(ta_plan p) {
   if (p->cap2) hipStreamDestroy(p->cap2);
   if (p->ev_stats) hipEventDestroy(p->ev_stats);
   if (p->ev_join) hipEventDestroy(p->ev_join);
+  for (hipEvent_t ev : p->slots)
+    if (ev) hipEventDestroy(ev);
   if (p->d_order) hipFree(p->d_order);
   if (p->d_reqs) hipFree(p->d_reqs);
   if (p->d_tasks) hipFree(p->d_tasks);
@@ -1177,6 +1184,47 @@ ta_status ta_node_intersections(ta_handle h, const int32_t *labels, const int32_
   return TA_OK;
 }
 
+namespace {
+
+// Places event record nodes right before and right after the fused pass (the
+// graph's one root node): root -> fused -> record -> the fused pass's former
+// dependents, so the graph stays one chain there.  Best effort: without them
+// the plan still works and ta_plan_launch_timed reports an error.
+void add_timing_nodes(ta_plan p) {
+  size_t nr = 0;
+  if (hipGraphGetRootNodes(p->graph, nullptr, &nr) != hipSuccess || nr != 1) return;
+  hipGraphNode_t fused = nullptr;
+  if (hipGraphGetRootNodes(p->graph, &fused, &nr) != hipSuccess) return;
+  hipGraphNodeType ty;
+  if (hipGraphNodeGetType(fused, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) return;
+  size_t nd = 0;
+  if (hipGraphNodeGetDependentNodes(fused, nullptr, &nd) != hipSuccess) return;
+  std::vector<hipGraphNode_t> deps(nd);
+  if (nd && hipGraphNodeGetDependentNodes(fused, deps.data(), &nd) != hipSuccess) return;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return;
+  }
+  p->slots.push_back(e0);
+  p->slots.push_back(e1);
+  hipGraphNode_t r0 = nullptr, r1 = nullptr;
+  if (hipGraphAddEventRecordNode(&r1, p->graph, &fused, 1, e1) != hipSuccess) return;
+  // every former dependent waits on the record node first, then drops the
+  // direct edge, so no dependent ever loses its wait on the fused pass
+  for (hipGraphNode_t d : deps) {
+    if (hipGraphAddDependencies(p->graph, &r1, &d, 1) != hipSuccess) return;
+    hipGraphRemoveDependencies(p->graph, &fused, &d, 1);
+  }
+  if (hipGraphAddEventRecordNode(&r0, p->graph, nullptr, 0, e0) != hipSuccess) return;
+  if (hipGraphAddDependencies(p->graph, &r0, &fused, 1) != hipSuccess) return;
+  p->rec[0] = r0;
+  p->rec[1] = r1;
+}
+
+}  // namespace
+
 ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets_host,
                          const ta_batch_desc *d, ta_plan *out, void *stream) {
   if (!h) return TA_ERR_INVALID_ARG;
@@ -1333,6 +1381,7 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
     plan_free(p);
     return hipfail(h, le != hipSuccess ? le : e, "plan capture");
   }
+  add_timing_nodes(p);
   e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     plan_free(p);
@@ -1499,6 +1548,36 @@ ta_status ta_plan_launch(ta_plan p, void *stream) {
   DeviceGuard dg(p->h->device);
   hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(p->h, e, "graph launch");
+  return TA_OK;
+}
+
+ta_status ta_plan_launch_timed(ta_plan p, int32_t slot, void *stream) {
+  if (!p) return TA_ERR_INVALID_ARG;
+  ta_handle h = p->h;
+  if (slot < 0 || slot >= 4096) return fail(h, TA_ERR_INVALID_ARG, "slot must be in [0, 4096)");
+  if (!p->rec[0] || !p->rec[1])
+    return fail(h, TA_ERR_STATE, "this plan's graph has no timing nodes");
+  DeviceGuard dg(h->device);
+  while ((int64_t)p->slots.size() < 2 * ((int64_t)slot + 2)) {
+    hipEvent_t ev = nullptr;
+    TA_HIP(h, hipEventCreate(&ev));
+    p->slots.push_back(ev);
+  }
+  // slot k uses events 2k + 2 and 2k + 3 (the first pair belongs to the capture)
+  TA_HIP(h, hipGraphExecEventRecordNodeSetEvent(p->exec, p->rec[0], p->slots[2 * slot + 2]));
+  TA_HIP(h, hipGraphExecEventRecordNodeSetEvent(p->exec, p->rec[1], p->slots[2 * slot + 3]));
+  TA_HIP(h, hipGraphLaunch(p->exec, (hipStream_t)stream));
+  return TA_OK;
+}
+
+ta_status ta_plan_segment_ms(ta_plan p, int32_t slot, float *ms) {
+  if (!p || !ms) return TA_ERR_INVALID_ARG;
+  ta_handle h = p->h;
+  if (slot < 0 || 2 * ((int64_t)slot + 2) > (int64_t)p->slots.size())
+    return fail(h, TA_ERR_INVALID_ARG, "slot was never launched");
+  DeviceGuard dg(h->device);
+  TA_HIP(h, hipEventSynchronize(p->slots[2 * slot + 3]));
+  TA_HIP(h, hipEventElapsedTime(ms, p->slots[2 * slot + 2], p->slots[2 * slot + 3]));
   return TA_OK;
 }
 

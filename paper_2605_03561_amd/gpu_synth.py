@@ -153,6 +153,10 @@ def sample_ranks_to_host(w: GpuWorkload, ranks) -> synth.Workload:
     """Copy a subset of ranks' traces to host memory as a CSR workload."""
     ranks = np.asarray(ranks, dtype=np.int64)
     off = w["offsets_host"]
+    if len(ranks) == len(off) - 1 and np.array_equal(ranks, np.arange(len(ranks))):
+        return synth.Workload(offsets=np.asarray(off, np.int64).copy(), ts=w["ts"].cpu().numpy(),
+                              ctx=w["ctx"].cpu().numpy(), parent=w["parent"],
+                              marker=w["marker"], regions=w["regions"], n_iters=w["n_iters"])
     parts_t, parts_c = [], []
     for r in ranks:
         a, b = int(off[r]), int(off[r + 1])

@@ -97,6 +97,8 @@ def _load():
         "ta_node_intersections": [P, P, P, i64, i32, i32, P, P, P],
         "ta_plan_create": [P, P, P, P, P, P],
         "ta_plan_launch": [P, P],
+        "ta_plan_launch_timed": [P, i32, P],
+        "ta_plan_segment_ms": [P, i32, P],
         "ta_plan_info": [P, P, P, P, P, P],
         "ta_batch_create": [P, i32, P, f64, i32, P, P],
         "ta_plan_destroy": [P],
@@ -381,14 +383,21 @@ class Handle:
         return rs, it, ox, oi
 
     def node_model_fill(self, tr: DeviceTraces, n_iters: int, counted, n_x: int, n_i: int,
-                        excl=True, incl=True):
+                        excl=True, incl=True, out=None):
         """Entries of every row (device): (node_x, val_x, node_i, val_i) with
-        n_x / n_i entries (None for a list not asked for)."""
+        n_x / n_i entries (None for a list not asked for).  `out` reuses a
+        previous result's four tensors."""
         rs, it, ox, oi = counted
-        nx = self._empty((max(n_x, 1),), torch.int32) if excl else None
-        vx = self._empty((max(n_x, 1),), torch.int64) if excl else None
-        ni = self._empty((max(n_i, 1),), torch.int32) if incl else None
-        vi = self._empty((max(n_i, 1),), torch.int64) if incl else None
+        if out is not None:
+            nx, vx, ni, vi = out
+        else:
+            nx = self._empty((max(n_x, 1),), torch.int32) if excl else None
+            vx = self._empty((max(n_x, 1),), torch.int64) if excl else None
+            ni = self._empty((max(n_i, 1),), torch.int32) if incl else None
+            vi = self._empty((max(n_i, 1),), torch.int64) if incl else None
+        for t, n in ((nx, n_x), (vx, n_x), (ni, n_i), (vi, n_i)):
+            if t is not None and t.numel() < n:
+                raise ValueError("out holds fewer entries than the counts")
         t = tr.struct()
         self._check(_lib.ta_node_model_fill(self.h, C.byref(t), int(n_iters), _ptr(rs), _ptr(it),
                                             _ptr(ox), _ptr(nx), _ptr(vx), _ptr(oi), _ptr(ni),
@@ -599,6 +608,16 @@ class _PlanBase:
 
     def launch(self):
         self.h._check(_lib.ta_plan_launch(self.p, _stream(self.h.device)))
+
+    def launch_timed(self, slot: int):
+        """Replay with the fused pass's in-graph events pointed at pair `slot`."""
+        self.h._check(_lib.ta_plan_launch_timed(self.p, int(slot), _stream(self.h.device)))
+
+    def segment_ms(self, slot: int) -> float:
+        """Milliseconds of the fused pass in the replay that used `slot`."""
+        ms = C.c_float()
+        self.h._check(_lib.ta_plan_segment_ms(self.p, int(slot), C.byref(ms)))
+        return float(ms.value)
 
     def info(self):
         th, ept, nt, wgs, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()

@@ -119,3 +119,45 @@ def test_node_intersections_bad_ids(ta, h):
         h.kmeans(dev(np.zeros((3, 2), np.int64)), dev(np.zeros((33, 2))), 5)   # k > 32
     with pytest.raises(ta.TAError):
         h.dbscan1d(dev(np.zeros(3, np.int64)), -1, 2)
+
+
+def test_stability_sweep_matches_oracle(ta, h, oracle):
+    """Sec. VI-B's stability test on synthetic per-rank times: DBSCAN over all
+    ranks (a slow group on a fifth of the compute nodes), then K-Means with 2..5
+    groups on the ranks of the largest DBSCAN group and the compute nodes
+    shared by each k's groups; every step against the oracle on the same
+    inputs."""
+    from paper_2605_03561_amd import synth
+    print("[cluster] stability sweep", flush=True)
+    R = 20_000
+    rank_node, _, _ = synth.topology(5, R)
+    n_nodes = int(rank_node.max()) + 1
+    rng = np.random.default_rng(77)
+    slow_nodes = rng.random(n_nodes) < 0.2
+    t = np.where(slow_nodes[rank_node], rng.normal(5.2e9, 2e7, R), rng.normal(3.1e9, 2e7, R))
+    t = np.rint(t).astype(np.int64)
+    eps, min_pts = int(np.median(t) // 2000), 100
+    dl, dn, dc = h.dbscan1d(dev(t), eps, min_pts)
+    st, lab, n, core = oracle.dbscan1d(t, eps, min_pts)
+    assert st == 0 and int(dn.item()) == n and n >= 2
+    assert np.array_equal(dl.cpu().numpy(), lab)
+    gp, gnc = h.node_intersections(dl, dev(rank_node), n_nodes, n)
+    st, pair, nc = oracle.node_intersections(lab, rank_node, n_nodes, n)
+    assert np.array_equal(gp.cpu().numpy(), pair) and np.array_equal(gnc.cpu().numpy(), nc)
+    big = int(np.bincount(lab[lab >= 0]).argmax())
+    idx = np.flatnonzero(lab == big)
+    x, rn = t[idx].reshape(-1, 1), rank_node[idx]
+    xs = np.sort(x.ravel())
+    for k in (2, 3, 4, 5):
+        C0 = xs[((np.arange(k) + 0.5) / k * (len(xs) - 1)).round().astype(np.int64)]
+        C0 = C0.astype(np.float64).reshape(k, 1)
+        gl, gc, gn, gi = h.kmeans(dev(x), dev(C0), 100)
+        st, kl, Cc, cnt, it = oracle.kmeans(x, C0, 100)
+        assert st == 0
+        assert np.array_equal(gl.cpu().numpy(), kl) and np.array_equal(gc.cpu().numpy(), Cc)
+        assert int(gi.item()) == it
+        gp, gnc = h.node_intersections(gl, dev(rn), n_nodes, k)
+        st, pair, nc = oracle.node_intersections(kl, rn, n_nodes, k)
+        assert np.array_equal(gp.cpu().numpy(), pair), k
+        assert np.array_equal(gnc.cpu().numpy(), nc), k
+    h.sync_status()

@@ -6,8 +6,17 @@
   totals); sampled tensor columns are checked against the oracle's
   per-iteration statistics; the exact outlier scan is checked on sampled
   regions; statistics that hold at any size are checked on the full outputs.
-* 3,000 ranks with the 10,000-rank workload's shape: everything, including the
-  exact outlier scan, against the oracle on the whole batch.
+  The per-cell and per-region imbalance statistics, and the exact FULL
+  scan's region scores, rank scores and flags of all 100,000 ranks are
+  checked against the oracle on the whole tensor copied to the host.  The
+  sparse node x rank x iteration model is checked on the rows of sampled
+  ranks, and at any size through its totals.
+* 10,000 ranks exactly as the plain-method-at-scale workload is configured
+  (median 50,000 events, 1,000..400,000, 1,000 nodes, 300 iterations, 32
+  regions): every rank's tensor, exclusive and inclusive rows, every
+  statistic, and the scores and flags of both scan modes and score kinds,
+  against the oracle on the whole batch.
+* 3,000 ranks with that workload's shape: the same, on a smaller batch.
 """
 import numpy as np
 import pytest
@@ -75,7 +84,8 @@ def _sample(w, k=40):
 def test_c3_sampled_rank_parity(mods, oracle, c3):
     torch, gpu_synth, ta = mods
     w, h, seg, cfg = c3
-    ranks = _sample(w)
+    ranks = _sample(w, 1000)
+    print(f"[fullsize] {len(ranks)} sampled ranks bit-exact", flush=True)
     s = gpu_synth.sample_ranks_to_host(w, ranks)
     st, ex, inc = oracle.attribute(s.offsets, s.ts, s.ctx, s.parent)
     st2, T, it, out, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker, s.regions,
@@ -144,6 +154,119 @@ def test_c3_outlier_scan_sampled_regions(mods, oracle, c3):
         st, score, flag, nf, oreg = oracle.outliers(sl, it, mode=0, kind=0)
         assert st == 0
         assert np.array_equal(reg[:, g], oreg[:, 0]), g
+
+
+def test_c3_whole_tensor_statistics_and_flags(mods, oracle, c3):
+    """All 32,000 cells' and 64 regions' imbalance statistics, and the exact
+    robust FULL scan's region scores, rank scores and flags of all 100,000
+    ranks, against the oracle on the whole tensor copied to the host (in the
+    benchmark's launch configuration)."""
+    torch, gpu_synth, ta = mods
+    w, h, seg, cfg = c3
+    print("[fullsize] whole tensor to the host", flush=True)
+    T = seg["tensor"].cpu().numpy()
+    it = seg["iters_found"].cpu().numpy()
+    span = seg["span"].cpu().numpy()
+    o = h.imbalance(seg["tensor"], seg["iters_found"], seg["rank_sum"], seg["rank_sumsq"],
+                    seg["span"])
+    ol = h.outliers(seg["tensor"], seg["iters_found"], region=True)
+    go = {k: v.cpu().numpy() for k, v in o.items()}
+    gl = {k: v.cpu().numpy() for k, v in ol.items()}
+    h.sync_status()
+    print("[fullsize] oracle imbalance over the whole tensor", flush=True)
+    st, ref = oracle.imbalance(T, it, span=span)
+    assert st == 0
+    for k in ref:
+        a, b = np.asarray(go[k], np.float64), np.asarray(ref[k], np.float64)
+        assert np.array_equal(np.isnan(a), np.isnan(b)), k
+        m = ~np.isnan(a)
+        np.testing.assert_allclose(a[m], b[m], rtol=1e-12, atol=0.0, err_msg=k)
+    for k in ("min", "max"):
+        assert np.array_equal(go[k], ref[k]), k
+    # The second stage works per region, so the oracle's scan of a slice of
+    # regions gives those regions' scores exactly; a rank's score is the
+    # largest over the slices, and it is flagged when any slice flags it.
+    G = T.shape[2]
+    score = np.zeros(T.shape[0])
+    flag = np.zeros(T.shape[0], np.uint8)
+    for g0 in range(0, G, 16):
+        print(f"[fullsize] oracle exact FULL scan, regions {g0}..{g0 + 15}", flush=True)
+        st, sc, fl, nf, reg = oracle.outliers(np.ascontiguousarray(T[:, :, g0:g0 + 16]), it,
+                                              mode=0, kind=0)
+        assert st == 0
+        assert np.array_equal(gl["region_score"][:, g0:g0 + 16], reg), g0
+        score = np.maximum(score, sc)
+        flag |= fl
+    assert np.array_equal(gl["rank_score"], score)
+    assert np.array_equal(gl["rank_flag"], flag)
+    assert int(gl["n_flagged"][0]) == int(flag.sum())
+    del T
+
+
+def test_c3_node_model(mods, oracle, c3):
+    """The sparse node x rank x iteration model of the 100k-rank batch: row
+    counts and entries of sampled ranks against the oracle; over the whole
+    batch, the iteration counts equal the fused pass's, the exclusive entries
+    add up to the time after each rank's first boundary, and so do the root's
+    inclusive entries."""
+    torch, gpu_synth, ta = mods
+    w, h, seg, cfg = c3
+    I = cfg["n_iters"]
+    R = len(w.offsets_host) - 1
+    h.set_tree(w.parent)
+    h.set_regions(w.marker, w.regions)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx)
+    torch.cuda.empty_cache()
+    print("[fullsize] node model: count", flush=True)
+    counted = h.node_model_count(tr, I)
+    h.sync_status()
+    rs, it, ox, oi = counted
+    assert torch.equal(it[:R], seg["iters_found"])
+    n_x, n_i = int(ox[R * I].item()), int(oi[R * I].item())
+    print(f"[fullsize] node model: {n_x} exclusive, {n_i} inclusive entries", flush=True)
+    ranks = _sample(w, 40)
+    s = gpu_synth.sample_ranks_to_host(w, ranks)
+    st, m = oracle.node_model(s.offsets, s.ts, s.ctx, s.parent, s.marker, I)
+    assert st == 0
+    oxh, oih = ox.cpu().numpy(), oi.cpu().numpy()
+    for j, r in enumerate(ranks):
+        assert np.array_equal(np.diff(oxh[r * I:(r + 1) * I + 1]), m["nnz_x"][j * I:(j + 1) * I])
+        assert np.array_equal(np.diff(oih[r * I:(r + 1) * I + 1]), m["nnz_i"][j * I:(j + 1) * I])
+    # time after each rank's first boundary
+    offs = torch.from_numpy(w.offsets_host).cuda()
+    has = it[:R] > 0
+    first_row = rs[torch.arange(R, device=offs.device) * I].clamp(min=0, max=len(w.ts) - 1)
+    last = w.ts[(offs[1:] - 1).clamp(min=0)]
+    after = torch.where(has, last - w.ts[first_row], torch.zeros_like(last))
+    want = int(after.sum().item())
+    for which in ("x", "i"):
+        print(f"[fullsize] node model: fill {which}", flush=True)
+        nx, vx, ni, vi = h.node_model_fill(tr, I, counted, n_x if which == "x" else 0,
+                                           n_i if which == "i" else 0, excl=which == "x",
+                                           incl=which == "i")
+        h.sync_status()
+        node, val = (nx, vx) if which == "x" else (ni, vi)
+        off_h = oxh if which == "x" else oih
+        for j, r in enumerate(ranks):
+            a, b = int(off_h[r * I]), int(off_h[(r + 1) * I])
+            ma = m["row_off_" + which]
+            assert np.array_equal(node[a:b].cpu().numpy(),
+                                  m["node_" + which][ma[j * I]:ma[(j + 1) * I]])
+            assert np.array_equal(val[a:b].cpu().numpy(),
+                                  m["val_" + which][ma[j * I]:ma[(j + 1) * I]])
+        if which == "x":
+            assert int(val.sum().item()) == want
+        else:
+            root = int(np.flatnonzero(np.asarray(w.parent) == -1)[0])
+            tot = 0
+            for c0 in range(0, len(val), 1 << 28):   # chunks: no 10^10-entry temporaries
+                v, nd = val[c0:c0 + (1 << 28)], node[c0:c0 + (1 << 28)]
+                tot += int(torch.where(nd == root, v, torch.zeros_like(v)).sum().item())
+            assert tot == want
+        del nx, vx, ni, vi, node, val
+        torch.cuda.empty_cache()
+    del counted, rs, it, ox, oi
+    torch.cuda.empty_cache()
 
 
 def test_c3_pruned_model(mods, oracle, c3):
@@ -333,6 +456,66 @@ def test_c3_plan_matches_eager(mods, oracle, c3):
         assert torch.equal(p.out[k], ol[k]), k
     p.close()
     del p
+    torch.cuda.empty_cache()
+
+
+def test_c2_as_configured_full_parity(mods, oracle):
+    """The plain-method-at-scale workload exactly as configured: 10,000 ranks,
+    lognormal lengths median 50,000 (1,000..400,000), a 1,000-node tree, 300
+    iterations, 32 regions.  Every output against the oracle on the whole
+    batch."""
+    torch, gpu_synth, ta = mods
+    import bench
+    cfg = bench.WORKLOADS["c2"]
+    I = cfg["n_iters"]
+    print("[fullsize] c2: generating 10,000 ranks", flush=True)
+    w = gpu_synth.timeline_on_gpu(seed=2, **cfg)
+    h = ta.Handle(0)
+    h.set_tree(w.parent)
+    h.set_regions(w.marker, w.regions)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx)
+    seg = h.attribute_segment(tr, I)
+    imb = h.imbalance(seg["tensor"], seg["iters_found"], seg["rank_sum"], seg["rank_sumsq"],
+                      seg["span"])
+    scans = {(mode, kind): h.outliers(seg["tensor"], seg["iters_found"], mode=mode, kind=kind,
+                                      region=True)
+             for mode in (0, 1) for kind in (0, 1)}
+    h.sync_status()
+    R = len(w.offsets_host) - 1
+    print(f"[fullsize] c2: {len(w.ts)} events to the host", flush=True)
+    s = gpu_synth.sample_ranks_to_host(w, np.arange(R))
+    print("[fullsize] c2: oracle attribute + segment", flush=True)
+    st, ex, inc = oracle.attribute(s.offsets, s.ts, s.ctx, s.parent)
+    st2, T, it, out, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker, s.regions,
+                                           I)
+    assert st == st2 == 0
+    assert np.array_equal(seg["tensor"].cpu().numpy(), T)
+    assert np.array_equal(seg["excl"].cpu().numpy(), ex)
+    assert np.array_equal(seg["incl"].cpu().numpy(), inc)
+    assert np.array_equal(seg["iters_found"].cpu().numpy(), it)
+    assert np.array_equal(seg["outside"].cpu().numpy(), out)
+    assert np.array_equal(seg["span"].cpu().numpy(), span)
+    print("[fullsize] c2: oracle statistics", flush=True)
+    st, ref = oracle.imbalance(T, it, span=span)
+    for k in ref:
+        a, b = imb[k].cpu().numpy().astype(np.float64), np.asarray(ref[k], np.float64)
+        assert np.array_equal(np.isnan(a), np.isnan(b)), k
+        m = ~np.isnan(a)
+        np.testing.assert_allclose(a[m], b[m], rtol=1e-12, atol=0.0, err_msg=k)
+    for (mode, kind), ol in scans.items():
+        print(f"[fullsize] c2: oracle scan mode {mode} kind {kind}", flush=True)
+        st, score, flag, nf, reg = oracle.outliers(T, it, mode=mode, kind=kind)
+        assert st == 0
+        g_reg, g_sc = ol["region_score"].cpu().numpy(), ol["rank_score"].cpu().numpy()
+        if kind == 0:
+            assert np.array_equal(g_reg, reg) and np.array_equal(g_sc, score), (mode, kind)
+        else:
+            np.testing.assert_allclose(g_reg, reg, rtol=1e-12, atol=0.0)
+            np.testing.assert_allclose(g_sc, score, rtol=1e-12, atol=0.0)
+        assert np.array_equal(ol["rank_flag"].cpu().numpy(), flag), (mode, kind)
+        assert int(ol["n_flagged"].item()) == nf
+    h.close()
+    del seg, imb, scans, w, tr
     torch.cuda.empty_cache()
 
 

@@ -117,6 +117,12 @@ WORKLOADS = {
         seed=5, n_ranks=8, median_len=2000, min_len=500, max_len=5000, n_nodes=100,
         depth_max=6, n_iters=30, n_regions=1),
     "edge": edge_workload,
+    # node ids renamed by a random permutation: parents are no longer below
+    # their children, and the preorder differs from the id order
+    "relabelled_timeline": lambda: synth.relabel(synth.timeline_workload(
+        seed=6, n_ranks=20, median_len=2500, min_len=800, max_len=8000, n_nodes=400,
+        depth_max=10, n_iters=30, n_regions=12, inject_frac=0.1), 7),
+    "relabelled_plain": lambda: synth.relabel(synth.plain_workload(seed=8, n_ranks=12), 9),
 }
 
 

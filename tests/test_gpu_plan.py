@@ -130,3 +130,35 @@ def test_tables_locked_while_plans_exist(env):
     h2.sync_status()
     assert torch.equal(out["tensor"], ref)
     h2.close()
+
+
+def test_timed_replays_match_eager(env):
+    """Replays that point the in-graph events around the fused pass at their
+    own event pair give the same outputs as the eager calls, back to back with
+    no host synchronisation between them, and each pair then holds that
+    replay's fused-pass time."""
+    torch, ta, w, h, tr = env
+    print("[plan] timed replays", flush=True)
+    p = h.plan(tr, w.n_iters, w.offsets, imbalance=True, outliers=True, autotune=0)
+    eager = h.attribute_segment(tr, w.n_iters)
+    imb = h.imbalance(eager["tensor"], eager["iters_found"], eager["rank_sum"],
+                      eager["rank_sumsq"], eager["span"])
+    ol = h.outliers(eager["tensor"], eager["iters_found"])
+    h.sync_status()
+    for slot in range(6):
+        p.launch_timed(slot)
+    h.sync_status()
+    ms = [p.segment_ms(slot) for slot in range(6)]
+    assert all(0.0 < m < 1000.0 for m in ms), ms
+    for k in p.seg:
+        assert torch.equal(p.seg[k], eager[k]), k
+    for k in p.imb:
+        a, b = p.imb[k], imb[k]
+        assert torch.equal(torch.nan_to_num(a, nan=1.5), torch.nan_to_num(b, nan=1.5)), k
+    for k in ("rank_score", "rank_flag", "n_flagged"):
+        assert torch.equal(p.out[k], ol[k]), k
+    p.launch()                                 # the plain replay still works
+    h.sync_status()
+    with pytest.raises(ta.TAError):
+        p.segment_ms(100)                      # a slot never launched
+    p.close()
