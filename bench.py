@@ -89,7 +89,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample-ranks", type=int, default=6000)
+    ap.add_argument("--cpu-sample-ranks", type=int, default=6000,
+                    help="ranks timed on all host cores (one tenth of them on one thread)")
+    ap.add_argument("--cpu-runs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prescreen", action="store_true",
                     help="skip training and judging the learned pre-screen")
@@ -105,6 +107,8 @@ def main():
                          "on the per-rank totals, compute nodes shared by the clusters)")
     ap.add_argument("--no-window", action="store_true",
                     help="skip the time-window and sparse-profile leg")
+    ap.add_argument("--no-node-model", action="store_true",
+                    help="skip the sparse node x rank x iteration model leg")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
@@ -149,22 +153,28 @@ def main():
     rank_node_d, node_rack_d, node_chassis_d = dn(rank_node), dn(node_rack), dn(node_chassis)
     stream = torch.cuda.current_stream(dev)
 
-    def step():
-        plan.launch()
+    def step(slot):
+        # one graph replay; event record nodes around the fused pass inside
+        # the graph take this step's own event pair
+        plan.launch_timed(slot)
         h.topology(plan.out["rank_score"], plan.out["rank_flag"], rank_node_d, node_rack_d,
                    node_chassis_d, 22, 176)
 
-    for _ in range(args.warmup):
-        step()
+    for k in range(args.warmup):
+        step(k)
     h.sync_status()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step()
+        step(args.warmup + k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     h.sync_status()
     ms_step = (t1 - t0) * 1e3 / args.steps
+    # the fused kernel's duration inside each timed step (HIP events recorded
+    # by the graph on the launch stream)
+    instep_ms = [plan.segment_ms(args.warmup + k) for k in range(args.steps)]
+    plan.close()
     del plan
     torch.cuda.empty_cache()
 
@@ -202,14 +212,16 @@ def main():
     # Algorithmic bytes of the fused kernel (what the method must move).
     alg_bytes = (12 * E + 8 * (R + 1) + 8 * R * I * G + 16 * R * N + 8 * R * G + 16 * R * G
                  + (4 + 8 + 8) * R + 12 * N)
-    seg_s = float(np.mean(seg_ms)) / 1e3
+    seg_s = float(np.mean(instep_ms)) / 1e3
     achieved = alg_bytes / seg_s / 1e9
+    iso_s = float(np.mean(seg_ms)) / 1e3
     src_hash = kernel_source_hash()
     traffic = read_traffic(args.workload, src_hash)
+    copy = copy_peak(dev)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_sample_ranks, I, E / R)
+        cpu = cpu_baseline(w, args.cpu_sample_ranks, I, E / R, runs=args.cpu_runs)
 
     # Release the batch outputs and the handle's workspace (the exact scan's
     # column-major copy) before the pruned-tree leg, which needs the traces,
@@ -230,6 +242,10 @@ def main():
     window = None
     if not args.no_window:
         window = window_sparse_summary(tr, w, args.steps, args.seed)
+    torch.cuda.empty_cache()
+    nodemodel = None
+    if not args.no_node_model:
+        nodemodel = node_model_summary(tr, w, I, min(args.steps, 3))
     del tr, w
     torch.cuda.empty_cache()
     pre = None
@@ -270,6 +286,16 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "seg_kernel<true,true> (fused attribute+segment)",
                      "algorithmic_bytes_per_launch": alg_bytes,
+                     "duration_ms": seg_s * 1e3,
+                     "duration_source": "in-step: HIP events recorded by the step's graph right "
+                                        "before and after the fused kernel, one pair per timed "
+                                        "step, mean over the timed steps",
+                     "instep_ms_per_step": instep_ms,
+                     "isolated_ms": iso_s * 1e3,
+                     "isolated_frac": alg_bytes / iso_s / 1e9 / HBM_PEAK_GBS,
+                     "copy_peak_GBs": copy["GBs"],
+                     "frac_of_copy_peak": achieved / copy["GBs"],
+                     "copy_calibration": copy,
                      "kernel_source_sha256_12": src_hash},
         "cpu_baseline": cpu,
         "prescreen": pre,
@@ -277,8 +303,62 @@ def main():
         "pruned_model": pruned,
         "clustering": clus,
         "window_and_sparse": window,
+        "node_model": nodemodel,
     }
     print(json.dumps(line))
+
+
+def node_model_summary(tr, w, I, reps):
+    """The sparse node x rank x iteration model of the whole batch (every node
+    of the tree, exclusive and inclusive entries per rank and iteration): the
+    count pass (row boundaries, entry counts, row offsets) and the fill pass,
+    each timed with HIP events on the launch stream, mean of `reps` runs."""
+    import torch
+
+    from paper_2605_03561_amd import ta
+
+    stream = torch.cuda.current_stream()
+    R = len(w["offsets_host"]) - 1
+    E = int(w["offsets_host"][-1])
+    h = ta.Handle(0)
+    h.set_tree(w["parent"])
+    h.set_regions(w["marker"], w["regions"])
+    counted = h.node_model_count(tr, I)
+    h.sync_status()
+    n_x = int(counted[2][R * I].item())
+    n_i = int(counted[3][R * I].item())
+    out = h.node_model_fill(tr, I, counted, n_x, n_i)
+    h.sync_status()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * reps)]
+    for k in range(reps):
+        ev[3 * k].record(stream)
+        h.node_model_count(tr, I)          # its small outputs are new tensors each time
+        ev[3 * k + 1].record(stream)
+        h.node_model_fill(tr, I, counted, n_x, n_i, out=out)
+        ev[3 * k + 2].record(stream)
+    torch.cuda.synchronize()
+    h.sync_status()
+    c_ms = float(np.mean([ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(reps)]))
+    f_ms = float(np.mean([ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(reps)]))
+    rows = R * I
+    alg = 12 * E + 8 * (R + 1) + 12 * (n_x + n_i) + 16 * (rows + 1) + 8 * rows + 4 * R
+    moved = (4 * E + 8 * rows + 4 * R + 8 * (R + 1)        # count: row boundaries
+             + 12 * E + 16 * rows + 8 * rows + 4 * R        # count: rows, entry counts
+             + 2 * 3 * 8 * rows                              # count: two scans
+             + 12 * E + 8 * rows + 16 * rows + 4 * R + 12 * (n_x + n_i))  # fill
+    del out, counted
+    h.close()
+    torch.cuda.empty_cache()
+    t = (c_ms + f_ms) / 1e3
+    return {"ranks": R, "events": E, "rows": rows, "nodes": len(w["parent"]),
+            "exclusive_entries": n_x, "inclusive_entries": n_i,
+            "entry_bytes": 12 * (n_x + n_i),
+            "count_ms": c_ms, "fill_ms": f_ms, "events_per_s": E / t,
+            "algorithmic_bytes": alg, "GBs": alg / t / 1e9, "frac_of_hbm_peak": alg / t / 1e9 / HBM_PEAK_GBS,
+            "bytes_moved_by_both_passes": moved,
+            "note": "algorithmic bytes: events read once (12 B), offsets, the entries written "
+                    "(12 B each), row offsets, row starts and iteration counts; the two passes "
+                    "read the events twice and the contexts three times"}
 
 
 def window_sparse_summary(tr, w, steps, seed):
@@ -416,9 +496,47 @@ def clustering_summary(h, rank_sum, rank_node, steps, seed, k=6, max_iter=50, mi
                             "dbscan": b_db / (ms["dbscan"] / 1e3) / 1e9,
                             "node_intersections": b_ni / (ms["node_intersections"] / 1e3) / 1e9}}
     out["hbm_frac"] = {kk: v / HBM_PEAK_GBS for kk, v in out["achieved_gbs"].items()}
+    out["stability_sweep"] = stability_sweep(h, tot, dl, n_db, rank_node, n_nodes, max_iter)
     print(f"[bench] clustering: {out['ms']}, {it} K-Means iterations, {n_db} DBSCAN clusters",
           file=sys.stderr, flush=True)
     return out
+
+
+def stability_sweep(h, tot, db_labels, n_db, rank_node, n_nodes, max_iter, ks=(2, 3, 4, 5)):
+    """Sec. VI-B's stability test: the compute nodes shared by the DBSCAN
+    groups, then K-Means with 2..5 groups on the ranks of the largest DBSCAN
+    group (the same per-rank value, initial centroids at the (j + 1/2)/k
+    quantiles) and, for each k, the compute nodes holding ranks of two of its
+    groups."""
+    import torch
+
+    if n_db < 1:
+        return None
+    db_pair, db_nc = h.node_intersections(db_labels, rank_node, n_nodes, n_db)
+    sizes = torch.bincount(db_labels[db_labels >= 0].long(), minlength=n_db)
+    big = int(sizes.argmax().item())
+    idx = torch.nonzero(db_labels == big).flatten()
+    x = tot.index_select(0, idx).reshape(-1, 1).contiguous()
+    rn = rank_node.index_select(0, idx).contiguous()
+    xs = np.sort(x.flatten().cpu().numpy())
+    res = {"dbscan_groups": n_db, "dbscan_group_ranks": sizes.cpu().tolist(),
+           "dbscan_nodes_per_group": [int(((db_nc >> c) & 1).sum().item())
+                                      for c in range(min(n_db, 31))],
+           "dbscan_pair_nodes": db_pair.cpu().tolist(), "swept_group": big,
+           "swept_ranks": int(len(idx)), "kmeans": {}}
+    for k in ks:
+        q = xs[((np.arange(k) + 0.5) / k * (len(xs) - 1)).round().astype(np.int64)]
+        init = torch.from_numpy(q.astype(np.float64).reshape(k, 1)).to(x.device)
+        lab, cent, cnt, n_it = h.kmeans(x, init, max_iter)
+        pair, nc = h.node_intersections(lab, rn, n_nodes, k)
+        pm = pair.cpu().numpy()
+        res["kmeans"][str(k)] = {
+            "iterations": int(n_it.item()), "sizes": cnt.cpu().tolist(),
+            "centroids_ns": cent.flatten().cpu().tolist(),
+            "nodes_shared": {f"{a + 1}-{b + 1}": int(pm[a, b]) for a in range(k)
+                             for b in range(a + 1, k) if pm[a, b] > 0}}
+    h.sync_status()
+    return res
 
 
 def pruned_model_summary(tr, excl, w, I, steps, fraction=0.01):
@@ -573,6 +691,40 @@ def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9):
                                       "aggregation of each request; waves summed"}
 
 
+def copy_peak(dev, gib: int = 8, reps: int = 5):
+    """What a plain streaming copy reaches on this GPU: `gib` GiB copied by the
+    reference copy kernel (16-byte vectors, 4, 8 and 16 workgroups per CU) and
+    by torch's copy_, each timed with HIP events on the current stream; bytes
+    read + written per second, the best rate of each over `reps` copies."""
+    import torch
+
+    from paper_2605_03561_amd import gpu_synth
+    n = gib << 30
+    src = torch.ones(n, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream(dev)
+    variants = {f"copy_kernel_{k}_wg_per_cu": (lambda k=k: gpu_synth.copy(dst, src, k))
+                for k in (4, 8, 16)}
+    variants["torch_copy_"] = lambda: dst.copy_(src)
+    res = {}
+    for name, fn in variants.items():
+        fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for k in range(reps):
+            fn()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]
+        res[name] = {"ms": ms, "GBs": 2 * n / (min(ms) / 1e3) / 1e9}
+    assert torch.equal(dst[:1 << 20], src[:1 << 20])
+    del src, dst
+    torch.cuda.empty_cache()
+    best = max(res, key=lambda k: res[k]["GBs"])
+    return {"bytes_per_copy": 2 * n, "variants": res, "GBs": res[best]["GBs"], "best": best,
+            "what": f"{gib} GiB copied (read + write), best of {reps} per variant"}
+
+
 def copy_calibration(mib: int):
     """A plain copy of known size: each dispatch reads and writes mib MiB."""
     import torch
@@ -618,37 +770,78 @@ def prescreen_summary(h, epochs):
         "totals_scan_ms": summ["totals_scan_ms_mean"],
         "any_fallback": summ["any_fallback"],
         "k_needed_for_recall_0995_max": summ["k_needed_max"],
+        "exact_flag_rate_no_injection": rep["exact_flag_rate_no_injection"],
+        "injected_share_of_top_n_mean": summ["injected_share_of_top_n_mean"],
+        "k_needed_for_injected_recall_0995_max": summ["k_needed_for_injected_recall_max"],
+        "train_tflops": rep.get("train_tflops"),
         "recall_by_kind": [r["recall_by_kind"] for r in rows],
         "untrained_recall_by_kind": [r["untrained_recall_by_kind"] for r in rows],
         "meets_target": bool(summ["recall_min"] >= 0.99 and summ["speedup_min"] >= 5.0),
     }
 
 
-def cpu_baseline(w, n_sample, I, mean_events):
-    """Time the plain oracle (OpenMP over ranks, all host cores) on a stratified
-    sample of ranks copied back from the GPU: attribution, segmentation,
-    imbalance and the exact outlier scan over the sample."""
+def host_cpu():
+    """Model name and logical CPU count of the host, and the CPUs this process
+    may run on."""
+    model, n = "unknown", 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                n += 1
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "logical_cpus": n or (os.cpu_count() or 1), "usable_cpus": usable}
+
+
+def cpu_baseline(w, n_sample, I, mean_events, runs=5, single_ranks=None):
+    """Time the plain oracle on stratified samples of ranks copied back from
+    the GPU: attribution, segmentation, imbalance and the exact outlier scan
+    over the sample, `runs` times each, (a) with OpenMP on all usable host
+    cores (ranks, then regions, in parallel) and (b) on one thread.  The value
+    is the all-core mean."""
     from oracle import oracle
     from paper_2605_03561_amd import gpu_synth
 
     R = len(w["offsets_host"]) - 1
-    ranks = np.linspace(0, R - 1, min(n_sample, R)).round().astype(np.int64)
-    s = gpu_synth.sample_ranks_to_host(w, ranks)
+    cpu = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or cpu["usable_cpus"]
+    threads = min(threads, cpu["usable_cpus"])
     oracle.lib()
-    t = time.perf_counter()
-    st1, _, _ = oracle.attribute(s.offsets, s.ts, s.ctx, s.parent)
-    st2, T, it, _, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker, s.regions, I)
-    st3, _ = oracle.imbalance(T, it, span=span)
-    st4 = oracle.outliers(T, it)[0]
-    dt = time.perf_counter() - t
-    assert st1 == st2 == st3 == st4 == 0
-    n_ev = len(s.ts)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n_ev / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(ranks)} evenly spaced ranks ({n_ev} events, mean "
-                      f"{n_ev / len(ranks):.0f}/rank vs {mean_events:.0f} overall): attribute + "
-                      f"segment + imbalance + full outlier scan, {dt:.1f} s",
-            "seconds": dt}
+
+    def leg(n_ranks, n_threads):
+        ranks = np.linspace(0, R - 1, min(n_ranks, R)).round().astype(np.int64)
+        s = gpu_synth.sample_ranks_to_host(w, ranks)
+        used = oracle.set_threads(n_threads)
+        times = []
+        for _ in range(runs):
+            t = time.perf_counter()
+            st1, _, _ = oracle.attribute(s.offsets, s.ts, s.ctx, s.parent)
+            st2, T, it, _, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker,
+                                                 s.regions, I)
+            st3, _ = oracle.imbalance(T, it, span=span)
+            st4 = oracle.outliers(T, it)[0]
+            times.append(time.perf_counter() - t)
+            assert st1 == st2 == st3 == st4 == 0
+        n_ev = len(s.ts)
+        return {"ranks": len(ranks), "events": n_ev, "threads": used,
+                "seconds_per_run": times, "value": n_ev / float(np.mean(times)),
+                "mean_events_per_rank": n_ev / len(ranks)}
+
+    multi = leg(n_sample, threads)
+    single = leg(single_ranks or max(1, n_sample // 10), 1)
+    oracle.set_threads(threads)
+    return {"value": multi["value"], "unit": "events/s", "cores": multi["threads"],
+            "kind": "oracle",
+            "sample": f"{multi['ranks']} evenly spaced ranks ({multi['events']} events, mean "
+                      f"{multi['mean_events_per_rank']:.0f}/rank vs {mean_events:.0f} overall): "
+                      f"attribute + segment + imbalance + full outlier scan, mean of {runs} runs "
+                      f"on {multi['threads']} threads",
+            "runs": runs, "multi_thread": multi, "single_thread": single, "host": cpu}
 
 
 if __name__ == "__main__":

@@ -48,6 +48,15 @@ typedef struct {
  * an invalid argument, or 8 for a HIP launch error. */
 int32_t tas_generate(const tas_params *p, void *stream);
 
+/* A plain device-to-device copy of n_bytes (a multiple of 16, both pointers
+ * 16-byte aligned): the reference kernel whose measured rate calibrates the
+ * HBM figures (what a streaming read + write reaches on this GPU).  Each
+ * thread moves four 16-byte vectors per step, loads issued before stores;
+ * grid = workgroups_per_cu x the device's compute units (0: 8).  Asynchronous
+ * on `stream`; returns 0, 1 for an invalid argument, 8 for a launch error. */
+int32_t tas_copy(void *dst, const void *src, int64_t n_bytes, int32_t workgroups_per_cu,
+                 void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -146,3 +146,48 @@ extern "C" int32_t tas_generate(const tas_params *p, void *stream) {
   hipLaunchKernelGGL(gen_kernel, dim3((unsigned)p->n_ranks), dim3(GT), 0, (hipStream_t)stream, *p);
   return hipGetLastError() == hipSuccess ? 0 : 8;
 }
+
+namespace {
+
+typedef long long v2ll __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void copy_kernel(v2ll *__restrict__ dst,
+                                                   const v2ll *__restrict__ src, int64_t n) {
+  constexpr int U = 4;
+  const int64_t stride = (int64_t)gridDim.x * 256 * U;
+  for (int64_t b = (int64_t)blockIdx.x * 256 * U + threadIdx.x; b < n; b += stride) {
+    v2ll v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t k = b + (int64_t)u * 256;
+      if (k < n) v[u] = src[k];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t k = b + (int64_t)u * 256;
+      if (k < n) dst[k] = v[u];
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" int32_t tas_copy(void *dst, const void *src, int64_t n_bytes, int32_t workgroups_per_cu,
+                            void *stream) {
+  if (!dst || !src || n_bytes < 0 || (n_bytes & 15) || ((uintptr_t)dst & 15) ||
+      ((uintptr_t)src & 15) || workgroups_per_cu < 0)
+    return 1;
+  if (n_bytes == 0) return 0;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  }
+  const int64_t n = n_bytes / 16;
+  int64_t grid = (int64_t)cus * (workgroups_per_cu ? workgroups_per_cu : 8);
+  const int64_t need = (n + 1023) / 1024;
+  if (grid > need) grid = need;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
+                     (v2ll *)dst, (const v2ll *)src, n);
+  return hipGetLastError() == hipSuccess ? 0 : 8;
+}

@@ -47,7 +47,8 @@ struct AeState {
                              // 2: max robust z over ranks of the mean residual
 };
 
-constexpr int AE_WG = 32;   // workgroups per training step (gradient partials)
+constexpr int AE_WG = 256;  // workgroups per training step (gradient partials): one
+                            // 16-row tile each at the default batch of 4,096 rows
 
 hipError_t ae_alloc(AeState &s);
 void ae_free(AeState &s);

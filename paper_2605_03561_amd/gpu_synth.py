@@ -40,6 +40,8 @@ def _load():
         _lib = C.CDLL(LIB_PATH)
         _lib.tas_generate.argtypes = [C.c_void_p, C.c_void_p]
         _lib.tas_generate.restype = C.c_int32
+        _lib.tas_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+        _lib.tas_copy.restype = C.c_int32
     return _lib
 
 
@@ -169,3 +171,19 @@ def sample_ranks_to_host(w: GpuWorkload, ranks) -> synth.Workload:
                           ctx=np.concatenate(parts_c) if parts_c else np.zeros(0, np.int32),
                           parent=w["parent"], marker=w["marker"], regions=w["regions"],
                           n_iters=w["n_iters"])
+
+
+def copy(dst: "torch.Tensor", src: "torch.Tensor", workgroups_per_cu: int = 0) -> None:
+    """The plain reference copy kernel (bandwidth calibration) on the current
+    stream: dst[:] = src, both contiguous, the same number of bytes (a
+    multiple of 16)."""
+    import torch
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("dst and src must be contiguous and of the same size")
+    lib = _load()
+    st = lib.tas_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), n,
+                      int(workgroups_per_cu),
+                      C.c_void_p(torch.cuda.current_stream(src.device).cuda_stream))
+    if st != 0:
+        raise RuntimeError(f"tas_copy failed with {st}")

@@ -91,7 +91,11 @@ def train(h: ta.Handle, seeds=TRAIN_SEEDS, calib=CALIB, epochs=20, batch=4096, l
     train_ms = ev[0].elapsed_time(ev[1])
     log(f"[prescreen] trained {epochs} epochs in {train_ms / 1e3:.1f}s: loss "
         f"{el[0].item():.4f} -> {el[-1].item():.4f}")
-    del rows, tensors
+    # the exact scan on a run without injected anomalies: what it flags there
+    # is the noise floor of its flags (short, sampled traces)
+    T0, it0 = tensors[0]
+    base_rate = float(h.outliers(T0, it0)["rank_flag"].float().mean().item())
+    del rows, tensors, T0, it0
     torch.cuda.empty_cache()
 
     R = cfg["n_ranks"]
@@ -124,10 +128,16 @@ def train(h: ta.Handle, seeds=TRAIN_SEEDS, calib=CALIB, epochs=20, batch=4096, l
     log(f"[prescreen] calibration runs: exact flag rates {cal_rates}; k needed for recall "
         f"{target_recall} by score kind { {q: need[q] for q in KINDS} } -> kind {kind}, "
         f"k_frac {k_frac:.3f}, threshold {thr:.4g}")
+    # forward 64x128 + 128x32 + 32x128 + 128x64 = 24,576 multiply-adds per row
+    # (49,152 FLOPs), backward twice that: 147,456 FLOPs per row per epoch
+    n_rows = int(len(seeds) * R * cfg["n_iters"])
+    flops = 3.0 * 2.0 * 24576.0 * n_rows * epochs
     return {"epochs": epochs, "batch": batch, "lr": lr, "input_noise": noise,
-            "train_rows": int(len(seeds) * R * cfg["n_iters"]), "train_s": train_ms / 1e3,
+            "train_rows": n_rows, "train_s": train_ms / 1e3,
+            "train_tflops": flops / (train_ms / 1e3) / 1e12,
             "epoch_loss": el.cpu().numpy().tolist(), "calib_flag_rates": cal_rates,
             "k_needed_by_kind": {int(q): int(need[q]) for q in KINDS},
+            "exact_flag_rate_no_injection": base_rate,
             "k_frac": k_frac, "score_kind": int(kind), "threshold": thr}
 
 
@@ -192,10 +202,25 @@ def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_s
                 k_need["trained"] = _k_needed(sc.cpu().numpy(), flags, TARGET_RECALL)
                 k_need["untrained"] = _k_needed(sc_u, flags, TARGET_RECALL)
         k_need["totals_scan"] = _k_needed(tot["rank_score"].cpu().numpy(), flags, TARGET_RECALL)
+        # against the generator's injected slow ranks (ground truth): the
+        # share of them among each method's n_inj highest scores, and the k
+        # each method needs to hold 99.5 % of them
+        inj = meta["injected"]
         h.ae_set_score_kind(chosen)
+        ref.ae_set_score_kind(chosen)
+        truth_scores = {"trained": h.ae_score(T, it).cpu().numpy(),
+                        "untrained": ref.ae_score(T, it).cpu().numpy(),
+                        "totals_scan": tot["rank_score"].cpu().numpy(),
+                        "full_scan": full["rank_score"].cpu().numpy()}
+        n_inj = int(inj.sum())
+        inj_top, inj_k = {}, {}
+        for name, sc in truth_scores.items():
+            if n_inj:
+                top_n = np.lexsort((np.arange(R), -sc))[:n_inj]
+                inj_top[name] = float(inj[top_n].mean())
+                inj_k[name] = _k_needed(sc, inj, TARGET_RECALL)
         r_ae, p_ae = recall(top.cpu().numpy())
         r_tt, p_tt = recall(topk(tot["rank_score"].cpu().numpy()))
-        inj = meta["injected"]
         sel = np.zeros(R, bool)
         sel[top.cpu().numpy()] = True
         row = {"seed": seed, "inject_rate": rate, "n_flagged_exact": int(flags.sum()),
@@ -207,6 +232,8 @@ def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_s
                "recall_by_kind": by_kind, "untrained_recall_by_kind": by_kind_untrained,
                "totals_scan_recall": r_tt, "totals_scan_precision": p_tt,
                "k_needed_for_target_recall": k_need,
+               "n_injected": n_inj, "injected_share_of_top_n": inj_top,
+               "k_needed_for_injected_recall": inj_k,
                "full_scan_ms": t_full, "prescreen_ms": t_pre, "ae_score_ms_by_kind": score_ms,
                "totals_scan_ms": t_tot, "speedup_vs_full": t_full / t_pre}
         log(f"[prescreen] seed {seed} rate {rate:.3f}: exact flags {row['n_flagged_exact']}, "
@@ -231,5 +258,13 @@ def evaluate(h: ta.Handle, k_frac: float, held_out=HELD_OUT, cfg=C4, untrained_s
             "totals_scan_ms_mean": float(np.mean([r["totals_scan_ms"] for r in rows])),
             "any_fallback": any(r["used_fallback"] for r in rows),
             "k_needed_max": {q: max(r["k_needed_for_target_recall"][q] for r in rows)
-                             for q in ("trained", "untrained", "totals_scan")}}
+                             for q in ("trained", "untrained", "totals_scan")},
+            "injected_share_of_top_n_mean": {
+                q: float(np.mean([r["injected_share_of_top_n"][q] for r in rows
+                                  if r["injected_share_of_top_n"]]))
+                for q in ("trained", "untrained", "totals_scan", "full_scan")},
+            "k_needed_for_injected_recall_max": {
+                q: max(r["k_needed_for_injected_recall"][q] for r in rows
+                       if r["k_needed_for_injected_recall"])
+                for q in ("trained", "untrained", "totals_scan", "full_scan")}}
     return summ, rows
