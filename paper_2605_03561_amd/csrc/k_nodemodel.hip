@@ -10,7 +10,10 @@
 //
 // Pass 1 (`nm_rows`): one wave per rank finds the boundary events (entry into
 //   the marker's subtree) and writes the first event of every row.
-// Pass 2 (`nm_short<FILL>`): one wave per row of at most SHORT_CAP events.  The
+// Pass 2 (`nm_short<FILL, ...>`): one wave per row of at most SHORT_CAP events
+//   (one kernel for rows of up to 64 events with the tree and the position map
+//   staged in LDS, one for 65..SHORT_CAP events with the LDS radix sort and
+//   the tree read through L2); all of a row's events are loaded at once.  The
 //   events with a positive duration are sorted by the preorder position of
 //   their node (a 64-lane bitonic network in registers up to 64 events, else an
 //   LSD radix sort with 8-bit digits in the wave's LDS), equal positions are
@@ -30,6 +33,8 @@
 // The count run writes the entry counts, which an exclusive scan turns into
 // row offsets; the fill run writes the entries.  Integer sums throughout, so
 // the result does not depend on the order of any atomic.
+#include <mutex>
+
 #include "ta_internal.h"
 
 namespace ta {
@@ -41,6 +46,7 @@ constexpr int SHORT_CAP = 512;      // events per row handled by one wave
 constexpr int SLOT_BITS = 9;        // log2(SHORT_CAP): sort keys are pos << 9 | slot
 constexpr int LONG_T = 512;         // threads per workgroup of the long-row kernel
 constexpr int LONG_LDS_NODES = 4096;
+constexpr int SMALL_TAB_NODES = 8192; // the <= 64-event row kernel keeps the tree in LDS up to here
 constexpr int SCAN_T = 1024;
 constexpr int SCAN_EPT = 8;
 constexpr int SCAN_B = SCAN_T * SCAN_EPT;
@@ -204,12 +210,32 @@ __device__ inline bool row_range(const NmArgs &a, int64_t q, int64_t *s, int64_t
   return true;
 }
 
+template <int CAP>
 struct WaveLds {
-  uint32_t ka[SHORT_CAP];      // sort keys (pos << SLOT_BITS | slot), then positions of the unique nodes
-  uint32_t kb[SHORT_CAP];
-  int64_t d[SHORT_CAP];        // duration by slot
-  int64_t q[SHORT_CAP + 1];    // running sum of the sorted durations before each unique node
-  uint32_t hist[256];
+  uint32_t ka[CAP];      // sort keys (pos << SLOT_BITS | slot), then positions of the unique nodes
+  uint32_t kb[CAP];
+  int64_t d[CAP];        // duration by slot
+  int64_t q[CAP + 1];    // running sum of the sorted durations before each unique node
+  uint32_t hist[CAP > 64 ? 256 : 1];
+};
+
+// The tree by preorder position for the walks: (parent position + 1, subtree
+// end) from an LDS copy (small trees) or from the global table.
+template <bool LDS_TAB>
+struct TreeTab {
+  const uint2 *lds;
+  const int4 *glb;
+  __device__ __forceinline__ void at(int32_t x, int32_t &parent, int32_t &tout) const {
+    if (LDS_TAB) {
+      const uint2 t = lds[x];
+      parent = (int32_t)t.x - 1;
+      tout = (int32_t)t.y;
+    } else {
+      const int4 t = glb[x];
+      parent = t.y;
+      tout = t.z;
+    }
+  }
 };
 
 // Sorts keys[0 .. n) (distinct) ascending by bits [SLOT_BITS, SLOT_BITS + nbits)
@@ -301,46 +327,82 @@ __device__ inline int lower_bound_u32(const uint32_t *pos, int lo, int hi, uint3
   return lo;
 }
 
-template <bool FILL>
-__global__ __launch_bounds__(NMT) void nm_short(NmArgs a) {
-  __shared__ WaveLds lds_all[NMW];
-  WaveLds &L = lds_all[threadIdx.x >> 6];
+// One wave per row of LO < n <= CAP events (n = the row's event count); with
+// CAP = SHORT_CAP the rows above it are listed for the long-row kernel, and
+// with LO = 0 the empty rows' counts are written.  NT threads per workgroup;
+// LDS_TAB: the walks read the tree from an LDS copy (dynamic LDS, 8 B a node).
+template <bool FILL, int CAP, int LO, int NT, bool LDS_TAB, bool POS_LDS>
+__global__ __launch_bounds__(NT) void nm_short(NmArgs a) {
+  constexpr int NW = NT / 64;
+  __shared__ WaveLds<CAP> lds_all[NW];
+  extern __shared__ uint2 tab_lds[];
+  WaveLds<CAP> &L = lds_all[threadIdx.x >> 6];
+  TreeTab<LDS_TAB> tree{tab_lds, a.ptab};
+  // POS_LDS: the preorder position of every caller id, after the tree table
+  uint32_t *pos_lds = reinterpret_cast<uint32_t *>(tab_lds + (LDS_TAB ? a.N : 0));
+  if (LDS_TAB) {
+    for (int p = threadIdx.x; p < a.N; p += NT) {
+      const int4 t = a.ptab[p];
+      tab_lds[p] = make_uint2((uint32_t)(t.y + 1), (uint32_t)t.z);
+    }
+  }
+  if (POS_LDS)
+    for (int v = threadIdx.x; v < a.N; v += NT) pos_lds[v] = a.info[v] >> INFO_TIN_SHIFT;
+  if (LDS_TAB || POS_LDS) __syncthreads();
   const int lane = lane_id();
   const int64_t rows = a.R * (int64_t)a.I;
-  const int64_t nwaves = (int64_t)gridDim.x * NMW;
+  const int64_t nwaves = (int64_t)gridDim.x * NW;
   uint32_t errb = 0;
-  for (int64_t q = (int64_t)blockIdx.x * NMW + (threadIdx.x >> 6); q < rows; q += nwaves) {
+  for (int64_t q = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6); q < rows; q += nwaves) {
     int64_t s = 0, e = 0, re = 0;
     if (!row_range(a, q, &s, &e, &re)) {
-      if (!FILL && lane == 0) {
+      if (LO == 0 && !FILL && lane == 0) {
         a.cnt_x[q] = 0;
         a.cnt_i[q] = 0;
       }
       continue;
     }
     const int64_t n = e - s;
-    if (n > SHORT_CAP) {
-      if (lane == 0) {
+    if (n <= LO) continue;
+    if (n > CAP) {
+      if (CAP == SHORT_CAP && lane == 0) {
         const int64_t j = (int64_t)atomicAdd((unsigned long long *)a.n_long, 1ull);
         if (j < a.long_cap) a.long_rows[j] = q;
       }
       continue;
     }
-    // events with a positive duration -> (key, duration by slot)
+    // events with a positive duration -> (key, duration by slot).  All of the
+    // row's timestamps and contexts are loaded first (CAP / 64 chunks, one
+    // event per lane each); an event's next timestamp comes from the next
+    // lane (or chunk), the row's last event takes the next row's first
+    // timestamp, and a rank's last event lasts 0.
+    constexpr int NCH = CAP / 64;
+    int64_t tv[NCH];
+    int32_t cv[NCH];
+#pragma unroll
+    for (int j = 0; j < NCH; j++) {
+      const bool in = 64 * j + lane < n;
+      tv[j] = in ? a.ts[s + 64 * j + lane] : 0;
+      cv[j] = in ? a.ctx[s + 64 * j + lane] : 0;
+    }
+    const int64_t tail = e < re ? a.ts[e] : 0;
     int m = 0;
-    for (int c0 = 0; c0 < n; c0 += 64) {
-      const int64_t k = s + c0 + lane;
+#pragma unroll
+    for (int j = 0; j < NCH; j++) {
+      if (64 * j >= n) break;
+      const int i = 64 * j + lane;
+      int64_t nx = __shfl_down(tv[j], 1, 64);
+      const int64_t nc = j + 1 < NCH ? __shfl(tv[j + 1 < NCH ? j + 1 : j], 0, 64) : 0;
+      if (lane == 63) nx = nc;
       bool keep = false;
       uint32_t pos = 0;
       int64_t d = 0;
-      if (c0 + lane < n) {
-        const int64_t t0 = a.ts[k];
-        const int64_t t1 = k + 1 < re ? a.ts[k + 1] : t0;
-        d = t1 - t0;
+      if (i < n) {
+        d = i + 1 < n ? nx - tv[j] : (e < re ? tail - tv[j] : 0);
         if (d < 0) errb |= ERRBIT_UNSORTED;
-        const int32_t c = a.ctx[k];
+        const int32_t c = cv[j];
         if ((uint32_t)c < (uint32_t)a.N) {
-          pos = a.info[c] >> INFO_TIN_SHIFT;
+          pos = POS_LDS ? pos_lds[c] : a.info[c] >> INFO_TIN_SHIFT;
           keep = d > 0;
         } else {
           errb |= ERRBIT_CTX;
@@ -356,7 +418,7 @@ __global__ __launch_bounds__(NMT) void nm_short(NmArgs a) {
       m += __popcll(km);
     }
     int nu = 0;          // unique nodes
-    const uint32_t *ups; // their positions
+    const uint32_t *ups = L.kb;  // their positions
     if (m <= 64) {
       // the compacted keys, one per lane: sort in registers, merge equal
       // positions by ballot
@@ -364,7 +426,7 @@ __global__ __launch_bounds__(NMT) void nm_short(NmArgs a) {
       const uint32_t key = wave_bitonic_sort(lane < m ? L.ka[lane] : 0xffffffffu);
       const bool act = lane < m;
       const uint32_t pos = key >> SLOT_BITS;
-      const int64_t d = act ? L.d[key & (SHORT_CAP - 1)] : 0;
+      const int64_t d = act ? L.d[key & ((1u << SLOT_BITS) - 1)] : 0;
       const int64_t run = wave_incl_scan_i64(d);
       const uint32_t ppos = (uint32_t)__shfl_up((int)pos, 1, 64);
       const bool head = act && (lane == 0 || ppos != pos);
@@ -379,7 +441,7 @@ __global__ __launch_bounds__(NMT) void nm_short(NmArgs a) {
       const int64_t total = __shfl(run, 63, 64);
       if (lane == 0) L.q[nu] = total;
       ups = L.kb;
-    } else {
+    } else if constexpr (CAP > 64) {
       uint32_t *sorted = wave_radix_sort(L.ka, L.kb, L.hist, m, a.pos_bits);
       uint32_t *upos = sorted == L.ka ? L.kb : L.ka;
       int64_t carry = 0;
@@ -388,7 +450,7 @@ __global__ __launch_bounds__(NMT) void nm_short(NmArgs a) {
         const bool act = c0 + lane < m;
         const uint32_t key = act ? sorted[c0 + lane] : 0xffffffffu;
         const uint32_t pos = key >> SLOT_BITS;
-        const int64_t d = act ? L.d[key & (SHORT_CAP - 1)] : 0;
+        const int64_t d = act ? L.d[key & ((1u << SLOT_BITS) - 1)] : 0;
         const int64_t run = carry + wave_incl_scan_i64(d);
         uint32_t ppos = (uint32_t)__shfl_up((int)pos, 1, 64);
         if (lane == 0) ppos = cpos;
@@ -421,10 +483,11 @@ __global__ __launch_bounds__(NMT) void nm_short(NmArgs a) {
         const int32_t prev = u > 0 ? (int32_t)ups[u - 1] : -1;
         int32_t x = pu;
         while (x >= 0) {
-          const int4 t = a.ptab[x];
-          if (prev >= 0 && x <= prev && prev < t.z) break;  // x is an ancestor of prev
+          int32_t par, tz;
+          tree.at(x, par, tz);
+          if (prev >= 0 && x <= prev && prev < tz) break;  // x is an ancestor of prev
           len++;
-          x = t.y;
+          x = par;
         }
       }
       int tot;
@@ -438,12 +501,13 @@ __global__ __launch_bounds__(NMT) void nm_short(NmArgs a) {
         if (a.node_i) {
           int32_t x = pu;
           for (int t = 0; t < len; t++) {
-            const int4 tx = a.ptab[x];
-            const int j = lower_bound_u32(ups, u, nu, (uint32_t)tx.z);
+            int32_t par, tz;
+            tree.at(x, par, tz);
+            const int j = lower_bound_u32(ups, u, nu, (uint32_t)tz);
             const int64_t at = oi + n_incl + before + (len - 1 - t);
-            a.node_i[at] = tx.x;
+            a.node_i[at] = a.ptab[x].x;
             a.val_i[at] = L.q[j] - qu;
-            x = tx.y;
+            x = par;
           }
         }
       }
@@ -688,6 +752,15 @@ __global__ __launch_bounds__(SCAN_T) void scan_apply(const int64_t *x, int64_t n
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bs[nb];
 }
 
+// Raises a kernel's dynamic LDS limit to what the CU holds beside its static
+// LDS (needed above 64 KB).
+template <class K>
+void allow_dynamic_lds(K k, size_t static_bytes) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(160 * 1024 - static_bytes));
+}
+
 int grid_for(int64_t units, int cus, int per_cu) {
   int64_t g = units < (int64_t)cus * per_cu ? units : (int64_t)cus * per_cu;
   return g < 1 ? 1 : (int)g;
@@ -783,10 +856,30 @@ hipError_t launch_node_model(const NodeModelArgs &m, bool fill, void *ws, int cu
     hipLaunchKernelGGL(nm_zero, dim3(grid_for(1 << 20, cus, 4)), dim3(256), 0, s, w.long_ws,
                        (int64_t)(2 * (int64_t)m.N + (m.N + 31) / 32 + 1) * w.long_grid);
   if (rows > 0) {
-    // three workgroups of four waves fit a CU's LDS
-    const int g = grid_for((rows + NMW - 1) / NMW, cus, 3);
-    if (fill) hipLaunchKernelGGL(nm_short<true>, dim3(g), dim3(NMT), 0, s, a);
-    else hipLaunchKernelGGL(nm_short<false>, dim3(g), dim3(NMT), 0, s, a);
+    // rows of up to 64 events: small per-wave buffers, the tree and the
+    // position map in LDS when they fit (two workgroups of eight waves per CU);
+    // 65..SHORT_CAP events: the LDS radix sort, the tree from L2 (three
+    // workgroups of four waves per CU: more waves in flight beat LDS walks)
+    static std::once_flag lds_once;
+    std::call_once(lds_once, [] {
+      allow_dynamic_lds(&nm_short<true, 64, 0, 512, true, true>, 8 * sizeof(WaveLds<64>));
+      allow_dynamic_lds(&nm_short<false, 64, 0, 512, true, true>, 8 * sizeof(WaveLds<64>));
+      allow_dynamic_lds(&nm_long<true, true>, 64);
+      allow_dynamic_lds(&nm_long<false, true>, 64);
+    });
+    const bool tab1 = m.N <= SMALL_TAB_NODES;
+    const size_t lds1 = tab1 ? (size_t)m.N * (sizeof(uint2) + sizeof(uint32_t)) : 0;
+    const int g1 = grid_for((rows + 7) / 8, cus, 2);
+    if (fill) {
+      if (tab1) hipLaunchKernelGGL((nm_short<true, 64, 0, 512, true, true>), dim3(g1), dim3(512), lds1, s, a);
+      else hipLaunchKernelGGL((nm_short<true, 64, 0, 512, false, false>), dim3(g1), dim3(512), 0, s, a);
+    } else {
+      if (tab1) hipLaunchKernelGGL((nm_short<false, 64, 0, 512, true, true>), dim3(g1), dim3(512), lds1, s, a);
+      else hipLaunchKernelGGL((nm_short<false, 64, 0, 512, false, false>), dim3(g1), dim3(512), 0, s, a);
+    }
+    const int g2 = grid_for((rows + NMW - 1) / NMW, cus, 3);
+    if (fill) hipLaunchKernelGGL((nm_short<true, SHORT_CAP, 64, NMT, false, false>), dim3(g2), dim3(NMT), 0, s, a);
+    else hipLaunchKernelGGL((nm_short<false, SHORT_CAP, 64, NMT, false, false>), dim3(g2), dim3(NMT), 0, s, a);
     const size_t lds = w.long_in_lds ? (size_t)(2 * m.N) * 8 + (size_t)((m.N + 31) / 32) * 8 : 0;
     if (w.long_in_lds) {
       if (fill) hipLaunchKernelGGL((nm_long<true, true>), dim3(w.long_grid), dim3(LONG_T), lds, s, a);

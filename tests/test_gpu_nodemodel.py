@@ -88,6 +88,16 @@ CASES = {
     # 100,000 nodes: 17-bit positions (three radix passes), rows of about 300 events
     "big_tree": lambda: (synth.plain_workload(seed=8, n_ranks=6, events=6_000,
                                               n_nodes=100_000, depth_max=12, n_iters=20), 20),
+    # trees around the LDS-table limits of the row kernels (6,144 and 8,192
+    # nodes), rows of 40..90 events so both row kernels take part
+    "tree_6144": lambda: (synth.plain_workload(seed=13, n_ranks=6, events=6_000, n_nodes=6_144,
+                                               n_iters=100), 100),
+    "tree_7000": lambda: (synth.plain_workload(seed=14, n_ranks=6, events=6_000, n_nodes=7_000,
+                                               n_iters=100), 100),
+    "tree_8192": lambda: (synth.plain_workload(seed=15, n_ranks=6, events=6_000, n_nodes=8_192,
+                                               n_iters=100), 100),
+    "tree_8193": lambda: (synth.plain_workload(seed=16, n_ranks=6, events=6_000, n_nodes=8_193,
+                                               n_iters=100), 100),
     # rows of 60..70 events around the register/LDS boundary
     "boundary_64": lambda: (synth.plain_workload(seed=9, n_ranks=8, events=6_500,
                                                  n_nodes=2_000, n_iters=100), 100),
