@@ -601,7 +601,7 @@ def pruned_model_summary(tr, excl, w, I, steps, fraction=0.01):
             "traffic": read_pruned_traffic()}
 
 
-def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9):
+def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9, prescreen_epochs: int = 10):
     """Mixed-size batch: n_req requests with rank counts log-uniform in
     1,000..100,000 and 100..500 iterations each, lengths lognormal around 40
     events per iteration (2..400 per iteration), one application (5,000-node
@@ -610,10 +610,18 @@ def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9):
     each wave is generated on the GPU (not timed), then reduced by one mixed
     batch graph (persistent fused pass over every rank of the wave + each
     request's exact FULL outlier scan), timed with HIP events over 2 launches;
-    rack/chassis aggregation of each request's scores is timed after it."""
+    rack/chassis aggregation of each request's scores is timed after it.
+
+    The learned pre-screen with exact-scan fallback: a network trained on runs
+    of the same application without injected slow ranks (operating point set
+    on labelled calibration runs) is applied to every request's tensor (k =
+    k_frac x the request's ranks; ta_prescreen falls back to the exact scan by
+    itself), timed per wave against the requests' exact FULL scans run one by
+    one, and judged by the recall of the exact scan's flags (computed in the
+    wave's graph) among its k ranks."""
     import torch
 
-    from paper_2605_03561_amd import gpu_synth, synth, ta
+    from paper_2605_03561_amd import gpu_synth, prescreen, synth, ta
     log = lambda m: print(m, file=sys.stderr, flush=True)
     rng = np.random.default_rng([seed, 5])
     Rq = np.round(np.exp(rng.uniform(np.log(1e3), np.log(1e5), n_req))).astype(np.int64)
@@ -631,6 +639,18 @@ def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9):
     h = ta.Handle(0)
     app = dict(n_nodes=5_000, depth_max=12, n_regions=64, app_seed=seed + 77)
     stream = torch.cuda.current_stream()
+    # the pre-screen for this application: 20,000-rank runs of 300 iterations
+    pcfg = dict(n_ranks=20_000, median_len=40 * 300, min_len=2 * 300, max_len=400 * 300,
+                n_iters=300, **app)
+    rep = prescreen.train(h, seeds=(seed * 1000 + 901, seed * 1000 + 902, seed * 1000 + 903),
+                          calib=((seed * 1000 + 911, 0.01), (seed * 1000 + 912, 0.03),
+                                 (seed * 1000 + 913, 0.05)),
+                          epochs=prescreen_epochs, cfg=pcfg, log=lambda m: None)
+    log(f"[mixed] pre-screen trained in {rep['train_s']:.1f}s: kind {rep['score_kind']}, "
+        f"k_frac {rep['k_frac']:.3f}")
+    pre_ms = exact_ms = 0.0
+    n_fb = 0
+    recalls = []
     tot_ms = topo_ms = 0.0
     tot_E = tot_R = flagged = 0
     shape = None
@@ -672,9 +692,30 @@ def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9):
         tot_ms += ms
         topo_ms += ev[1].elapsed_time(ev[2])
         flagged += sum(int(o["n_flagged"][0]) for o in mb.outs)
+        # the pre-screen of every request of the wave, then their exact scans
+        ks = [max(1, int(round(rep["k_frac"] * tr.n_ranks))) for tr, _, _ in reqs]
+        ep = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ep[0].record(stream)
+        pres = [h.prescreen(o["tensor"], o["iters_found"], k) for o, k in zip(mb.outs, ks)]
+        ep[1].record(stream)
+        for o in mb.outs:
+            h.outliers(o["tensor"], o["iters_found"])
+        ep[2].record(stream)
+        torch.cuda.synchronize()
+        h.sync_status()
+        pre_ms += ep[0].elapsed_time(ep[1])
+        exact_ms += ep[1].elapsed_time(ep[2])
+        for o, (top, _, fb) in zip(mb.outs, pres):
+            n_fb += int(fb)
+            fl = o["rank_flag"].bool()
+            nf = int(fl.sum().item())
+            if nf:
+                recalls.append(int(fl[top.long()].sum().item()) / nf)
+        del pres
         log(f"[mixed] wave {wv + 1}/{len(waves)}: {len(qs)} requests, "
             f"{sum(t.n_ranks for t, _, _ in reqs)} ranks, {sum(w.n_events for w in keep)} events, "
-            f"{ms:.1f} ms")
+            f"{ms:.1f} ms; pre-screen {ep[0].elapsed_time(ep[1]):.1f} ms vs exact scans "
+            f"{ep[1].elapsed_time(ep[2]):.1f} ms")
         mb.close()
         del mb, reqs, keep, topo_in
         w = None
@@ -686,6 +727,16 @@ def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9):
             "waves": len(waves), "n_ranks": tot_R, "n_events": int(tot_E),
             "graph_ms": tot_ms, "topology_ms": topo_ms,
             "events_per_s": tot_E / ((tot_ms + topo_ms) / 1e3), "n_flagged": flagged,
+            "prescreen": {"trained_on": "3 runs of the same application (20,000 ranks, 300 "
+                                        "iterations, no injection); operating point on 3 runs "
+                                        "with 1/3/5% injected",
+                          "train_s": rep["train_s"], "epochs": rep["epochs"],
+                          "score_kind": rep["score_kind"], "k_frac": rep["k_frac"],
+                          "requests": n_req, "fallbacks": n_fb,
+                          "recall_of_exact_flags_min": min(recalls) if recalls else None,
+                          "recall_of_exact_flags_mean": float(np.mean(recalls)) if recalls else None,
+                          "prescreen_ms": pre_ms, "exact_scans_ms": exact_ms,
+                          "speedup": exact_ms / pre_ms if pre_ms > 0 else None},
             "shape": shape, "timed": "per wave: one graph (fused pass over every rank of the wave + "
                                       "each request's exact FULL outlier scan), then rack/chassis "
                                       "aggregation of each request; waves summed"}
