@@ -533,6 +533,11 @@ ta_status ta_ae_rows(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_
  * SplitMix64 finaliser of the initialiser. */
 ta_status ta_ae_grad(ta_handle h, const float *rows, int64_t n_rows, float input_noise,
                      uint64_t noise_key, float *grad, float *loss, void *stream);
+/* The same gradient and loss as ta_ae_grad with every operation in FP32 (no
+ * bfloat16 rounding of the matrix-product operands): a debug reference for
+ * the matrix-core training path (single threads per dot product; slow). */
+ta_status ta_ae_grad_f32(ta_handle h, const float *rows, int64_t n_rows, float input_noise,
+                         uint64_t noise_key, float *grad, float *loss, void *stream);
 /* `epochs` passes over the rows in batches of `batch` (a fresh permutation of
  * the rows per epoch, drawn from shuffle_seed), one Adam step (learning rate
  * lr) per batch; with input_noise > 0 every step is a denoising step with its

@@ -333,6 +333,93 @@ __global__ __launch_bounds__(AT) void ae_fwdbwd(const float *__restrict__ rows, 
   if (tid == 0) P[AE_NP] = (float)ls;
 }
 
+// ---------------------------------------------------------------------------
+// FP32 debug gradient: the same network, loss and input noise with every
+// operation in FP32 (no bfloat16 operand rounding), for checking the gradient
+// code against an FP64 reference.  A workgroup takes rows blockIdx.x,
+// blockIdx.x + gridDim.x, ...; each layer's outputs are dot products in
+// ascending k by single threads; thread t owns the partial entries p = t mod
+// 256 (so the read-modify-writes of a row need no atomics).  Not a fast path.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ae_grad_f32_kernel(const float *__restrict__ rows, int64_t n,
+                                                          float scale, float noise_sd,
+                                                          uint64_t noise_key,
+                                                          const float *__restrict__ w, float *part) {
+  __shared__ float x[AE_IN], xin[AE_IN], h1[AE_H1], h2[AE_H2], h3[AE_H3];
+  __shared__ float d4[AE_IN], d3[AE_H3], d2[AE_H2], d1[AE_H1];
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  float *P = part + (int64_t)blockIdx.x * (AE_NP + 1);
+  for (int p = t; p < AE_NP; p += 256) P[p] = 0.f;
+  double loss = 0.0;
+  for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+    if (t < AE_IN) {
+      x[t] = rows[r * AE_IN + t];
+      xin[t] = noise_sd > 0.f ? x[t] + noise_sd * gauss_draw(noise_key, (uint64_t)r, t) : x[t];
+    }
+    __syncthreads();
+    if (t < AE_H1) {
+      float a = w[AE_B1 + t];
+      for (int k = 0; k < AE_IN; k++) a = fmaf(w[AE_W1 + t * AE_IN + k], xin[k], a);
+      h1[t] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    if (t < AE_H2) {
+      float a = w[AE_B2 + t];
+      for (int k = 0; k < AE_H1; k++) a = fmaf(w[AE_W2 + t * AE_H1 + k], h1[k], a);
+      h2[t] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    if (t < AE_H3) {
+      float a = w[AE_B3 + t];
+      for (int k = 0; k < AE_H2; k++) a = fmaf(w[AE_W3 + t * AE_H2 + k], h2[k], a);
+      h3[t] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    if (t < AE_IN) {
+      float a = w[AE_B4 + t];
+      for (int k = 0; k < AE_H3; k++) a = fmaf(w[AE_W4 + t * AE_H3 + k], h3[k], a);
+      const float e = a - x[t];
+      loss += (double)e * e;
+      d4[t] = scale * e;
+    }
+    __syncthreads();
+    if (t < AE_H3) {
+      float a = 0.f;
+      for (int o = 0; o < AE_IN; o++) a = fmaf(w[AE_W4 + o * AE_H3 + t], d4[o], a);
+      d3[t] = h3[t] > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    if (t < AE_H2) {
+      float a = 0.f;
+      for (int o = 0; o < AE_H3; o++) a = fmaf(w[AE_W3 + o * AE_H2 + t], d3[o], a);
+      d2[t] = h2[t] > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    if (t < AE_H1) {
+      float a = 0.f;
+      for (int o = 0; o < AE_H2; o++) a = fmaf(w[AE_W2 + o * AE_H1 + t], d2[o], a);
+      d1[t] = h1[t] > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    for (int p = t; p < AE_NP; p += 256) {
+      float g;
+      if (p < AE_W2) g = d1[p / AE_IN] * xin[p % AE_IN];
+      else if (p < AE_W3) g = d2[(p - AE_W2) / AE_H1] * h1[(p - AE_W2) % AE_H1];
+      else if (p < AE_W4) g = d3[(p - AE_W3) / AE_H2] * h2[(p - AE_W3) % AE_H2];
+      else if (p < AE_NW) g = d4[(p - AE_W4) / AE_H3] * h3[(p - AE_W4) % AE_H3];
+      else if (p < AE_B2) g = d1[p - AE_B1];
+      else if (p < AE_B3) g = d2[p - AE_B2];
+      else if (p < AE_B4) g = d3[p - AE_B3];
+      else g = d4[p - AE_B4];
+      P[p] += g;
+    }
+    __syncthreads();
+  }
+  const double ls = block_sum_f64<256>(loss, red);
+  if (t == 0) P[AE_NP] = (float)ls;
+}
+
 // Sum the workgroup partials in workgroup order; optionally take one Adam step.
 __global__ __launch_bounds__(256) void ae_adam(const float *part, int nwg, float *w, uint16_t *wb,
                                                float *m, float *v, float lr, float bc1, float bc2,
@@ -1149,6 +1236,18 @@ hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, 
   hipLaunchKernelGGL(ae_adam, dim3((AE_NP + 255) / 256), dim3(256), 0, st, s.part, AE_WG, s.w, s.wb,
                      s.m, s.v, lr, bc1, bc2, update ? 1 : 0, grad_out, loss_out ? loss_out : s.loss,
                      1.0f / (float)(bv * AE_IN));
+  return hipGetLastError();
+}
+
+hipError_t launch_ae_grad_f32(AeState &s, const float *rows, int64_t n, float noise_sd,
+                              uint64_t noise_key, hipStream_t st, float *grad_out, float *loss_out) {
+  if (n <= 0) return hipErrorInvalidValue;
+  const float scale = 2.0f / (float)(n * AE_IN);
+  hipLaunchKernelGGL(ae_grad_f32_kernel, dim3(AE_WG), dim3(256), 0, st, rows, n, scale, noise_sd,
+                     noise_key, s.w, s.part);
+  hipLaunchKernelGGL(ae_adam, dim3((AE_NP + 255) / 256), dim3(256), 0, st, s.part, AE_WG, s.w, s.wb,
+                     s.m, s.v, 0.f, 1.f, 1.f, 0, grad_out, loss_out ? loss_out : s.loss,
+                     1.0f / (float)(n * AE_IN));
   return hipGetLastError();
 }
 

@@ -64,6 +64,10 @@ size_t ae_rows_ws_bytes(int64_t R);
 hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, int batch,
                           uint64_t a, uint64_t c, float lr, bool update, float noise_sd,
                           uint64_t noise_key, hipStream_t st, float *grad_out, float *loss_out);
+// The same gradient and mean loss over rows[0..n) in FP32 throughout (a debug
+// reference for the matrix-core path; no update).
+hipError_t launch_ae_grad_f32(AeState &s, const float *rows, int64_t n, float noise_sd,
+                              uint64_t noise_key, hipStream_t st, float *grad_out, float *loss_out);
 // Workspace of launch_ae_score (score kind 2 keeps per-region residual means
 // and their z-scores, [64][R] FP64 each).
 size_t ae_score_ws_bytes(int64_t R);

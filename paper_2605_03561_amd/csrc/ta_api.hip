@@ -1731,6 +1731,22 @@ ta_status ta_ae_grad(ta_handle h, const float *rows, int64_t n_rows, float input
   return TA_OK;
 }
 
+ta_status ta_ae_grad_f32(ta_handle h, const float *rows, int64_t n_rows, float input_noise,
+                         uint64_t noise_key, float *grad, float *loss, void *stream) {
+  if (!h) return TA_ERR_INVALID_ARG;
+  if (!rows || n_rows < 1 || !grad || !aligned16(rows) || !aligned16(grad) || !aligned16(loss))
+    return fail(h, TA_ERR_INVALID_ARG, "bad rows or outputs");
+  if (!(input_noise >= 0.f) || input_noise > 1e6f)
+    return fail(h, TA_ERR_INVALID_ARG, "input_noise must be in [0, 1e6]");
+  if (!h->ae.ready) return fail(h, TA_ERR_STATE, "ta_ae_init has not been called");
+  if (n_rows > ((int64_t)1 << 31)) return fail(h, TA_ERR_SIZE_OVERFLOW, "too many rows");
+  DeviceGuard dg(h->device);
+  hipError_t e = ta::launch_ae_grad_f32(h->ae, rows, n_rows, input_noise, noise_key,
+                                        (hipStream_t)stream, grad, loss);
+  if (e != hipSuccess) return hipfail(h, e, "ae grad f32");
+  return TA_OK;
+}
+
 ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t epochs, int32_t batch,
                       float lr, float input_noise, uint64_t shuffle_seed, float *epoch_loss,
                       void *stream) {

@@ -106,6 +106,7 @@ def _load():
         "ta_ae_fit_norm": [P, P, i64, i32, i32, P, i32, P],
         "ta_ae_rows": [P, P, i64, i32, i32, P, P, P, P],
         "ta_ae_grad": [P, P, i64, C.c_float, C.c_uint64, P, P, P],
+        "ta_ae_grad_f32": [P, P, i64, C.c_float, C.c_uint64, P, P, P],
         "ta_ae_train": [P, P, i64, i32, i32, C.c_float, C.c_float, C.c_uint64, P, P],
         "ta_ae_score": [P, P, i64, i32, i32, P, P, P],
         "ta_ae_set_score_kind": [P, i32],
@@ -531,12 +532,14 @@ class Handle:
                                     C.byref(n), _stream(self.device)))
         return rows[:n.value]
 
-    def ae_grad(self, rows, noise=0.0, noise_key=0):
+    def ae_grad(self, rows, noise=0.0, noise_key=0, fp32=False):
+        """Gradient and mean loss (ta_ae_grad; ta_ae_grad_f32 with fp32, the
+        FP32 debug reference of the matrix-core path)."""
         g = self._empty((self.AE_NP,), torch.float32)
         loss = self._empty((1,), torch.float32)
-        self._check(_lib.ta_ae_grad(self.h, _ptr(rows), rows.shape[0], C.c_float(noise),
-                                    C.c_uint64(noise_key), _ptr(g), _ptr(loss),
-                                    _stream(self.device)))
+        fn = _lib.ta_ae_grad_f32 if fp32 else _lib.ta_ae_grad
+        self._check(fn(self.h, _ptr(rows), rows.shape[0], C.c_float(noise), C.c_uint64(noise_key),
+                       _ptr(g), _ptr(loss), _stream(self.device)))
         return g, loss
 
     def ae_train(self, rows, epochs, batch=4096, lr=1e-3, seed=0, noise=0.0):

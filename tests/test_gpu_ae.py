@@ -114,6 +114,37 @@ def test_gradient_matches_oracle(env):
     assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-2
 
 
+@pytest.mark.parametrize("noise", [0.0, 0.7])
+def test_fp32_gradient_matches_oracle(env, noise):
+    """The FP32 debug gradient (no bfloat16 operand rounding) against the FP64
+    oracle without bfloat16 rounding: every weight matrix and the biases to
+    1e-4 relative L2 (FP32 sums of at most 128 products, then over 300 rows),
+    with and without input noise."""
+    torch, ta, h = env
+    rng = np.random.default_rng(5)
+    h.ae_init(79)
+    X = rng.normal(0, 1, (300, 64)).astype(np.float32)
+    key = 0x2468ACE013579BDF
+    g, loss = h.ae_grad(torch.from_numpy(X).cuda(), noise=noise, noise_key=key, fp32=True)
+    g = g.cpu().numpy().astype(np.float64)
+    p = ae.init_params(79)
+    X_in = None
+    if noise > 0:
+        X_in = (X + np.float32(noise) * ae.gaussian_noise(key, np.arange(300)).astype(np.float32))
+        X_in = X_in.astype(np.float32).astype(np.float64)
+    l_ref, g_ref = ae.loss_and_grads(p, X.astype(np.float64), bf16=False, X_in=X_in)
+    assert abs(loss.item() - l_ref) / l_ref < 1e-5
+    rg = flat(g_ref)
+    o = 0
+    for l in range(4):
+        n = ae.DIMS[l] * ae.DIMS[l + 1]
+        a, b = g[o:o + n], rg[o:o + n]
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-4, f"W{l + 1}"
+        o += n
+    a, b = g[o:], rg[o:]
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-4
+
+
 def test_denoising_gradient_matches_oracle(env):
     """Denoising gradient: the GPU draws the input noise itself (counter-based
     normal draws per row and feature); the oracle draws the same values from
