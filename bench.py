@@ -601,6 +601,31 @@ def pruned_model_summary(tr, excl, w, I, steps, fraction=0.01):
             "traffic": read_pruned_traffic()}
 
 
+def mixed_batch_plan(n_req: int, seed: int, wave_bytes: float = 120e9):
+    """The mixed batch's requests and waves: rank counts log-uniform in
+    1,000..100,000, iterations uniform in 100..500, one application (5,000-node
+    tree, 64 regions); requests grouped in order into waves of about
+    `wave_bytes` of traces and tensors.  Request q's traces come from
+    gpu_synth.timeline_on_gpu(seed=seed * 1000 + q, n_ranks=Rq[q],
+    n_iters=Iq[q], median_len=40 * Iq[q], min_len=2 * Iq[q],
+    max_len=400 * Iq[q], inject_frac=0.02, **app)."""
+    rng = np.random.default_rng([seed, 5])
+    Rq = np.round(np.exp(rng.uniform(np.log(1e3), np.log(1e5), n_req))).astype(np.int64)
+    Iq = rng.integers(100, 501, n_req)
+    est = Rq * Iq * (66 * 12 + 64 * 8)          # mean events x 12 B + tensor
+    waves, cur, acc = [], [], 0.0
+    for q in range(n_req):
+        if cur and acc + est[q] > wave_bytes:
+            waves.append(cur)
+            cur, acc = [], 0.0
+        cur.append(q)
+        acc += est[q]
+    if cur:
+        waves.append(cur)
+    app = dict(n_nodes=5_000, depth_max=12, n_regions=64, app_seed=seed + 77)
+    return Rq, Iq, waves, app
+
+
 def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9, prescreen_epochs: int = 10):
     """Mixed-size batch: n_req requests with rank counts log-uniform in
     1,000..100,000 and 100..500 iterations each, lengths lognormal around 40
@@ -623,21 +648,8 @@ def mixed_batch_summary(n_req: int, seed: int, wave_bytes: float = 120e9, prescr
 
     from paper_2605_03561_amd import gpu_synth, prescreen, synth, ta
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    rng = np.random.default_rng([seed, 5])
-    Rq = np.round(np.exp(rng.uniform(np.log(1e3), np.log(1e5), n_req))).astype(np.int64)
-    Iq = rng.integers(100, 501, n_req)
-    est = Rq * Iq * (66 * 12 + 64 * 8)          # mean events x 12 B + tensor
-    waves, cur, acc = [], [], 0.0
-    for q in range(n_req):
-        if cur and acc + est[q] > wave_bytes:
-            waves.append(cur)
-            cur, acc = [], 0.0
-        cur.append(q)
-        acc += est[q]
-    if cur:
-        waves.append(cur)
+    Rq, Iq, waves, app = mixed_batch_plan(n_req, seed, wave_bytes)
     h = ta.Handle(0)
-    app = dict(n_nodes=5_000, depth_max=12, n_regions=64, app_seed=seed + 77)
     stream = torch.cuda.current_stream()
     # the pre-screen for this application: 20,000-rank runs of 300 iterations
     pcfg = dict(n_ranks=20_000, median_len=40 * 300, min_len=2 * 300, max_len=400 * 300,

@@ -123,3 +123,80 @@ def test_mixed_batch_topology_and_prescreen_fallback(env, oracle):
         want = np.sort(np.lexsort((np.arange(R), -xs))[:k])
         assert np.array_equal(top.cpu().numpy(), want)
     mb.close()
+
+
+def test_mixed_batch_first_wave_as_configured(oracle):
+    """The first wave of the mixed batch as benchmarked (256 requests, rank
+    counts log-uniform in 1,000..100,000, 100..500 iterations, 5,000-node tree,
+    64 regions, 2 % injected; waves of about 120 GB): one graph of the fused
+    pass and every request's exact FULL scan.  Against the oracle: the
+    smallest request and the two next-smallest on every output (tensor,
+    iterations, outside time, spans, region scores, rank scores, flags); the
+    largest request on 200 sampled ranks bit-exact and on two regions' scores
+    (the scan's second stage works per region, so the oracle's scan of the
+    one-region slice gives that region's scores)."""
+    import torch
+
+    import bench
+    from paper_2605_03561_amd import gpu_synth, ta
+    Rq, Iq, waves, app = bench.mixed_batch_plan(256, 0)
+    qs = waves[0]
+    print(f"[batch] first wave: {len(qs)} requests, {int(Rq[qs].sum())} ranks", flush=True)
+    h = ta.Handle(0)
+    ws, reqs = [], []
+    for q in qs:
+        I = int(Iq[q])
+        w = gpu_synth.timeline_on_gpu(seed=q, n_ranks=int(Rq[q]), n_iters=I, median_len=40 * I,
+                                      min_len=2 * I, max_len=400 * I, inject_frac=0.02, **app)
+        ws.append(w)
+        reqs.append((ta.DeviceTraces(w.offsets, w.ts, w.ctx), w.offsets_host, I))
+    h.set_tree(ws[0].parent)
+    h.set_regions(ws[0].marker, ws[0].regions)
+    mb = h.mixed_batch(reqs, outliers=True, attribution=False, autotune=0)
+    mb.launch()
+    h.sync_status()
+    order = np.argsort(Rq[qs], kind="stable")
+    for j in order[:3]:
+        q, I, w = qs[j], int(Iq[qs[j]]), ws[j]
+        R = int(Rq[q])
+        print(f"[batch] request {q}: {R} ranks, {I} iterations, whole request", flush=True)
+        s = gpu_synth.sample_ranks_to_host(w, np.arange(R))
+        st, T, it, out, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker,
+                                              s.regions, I)
+        assert st == 0
+        o = mb.outs[j]
+        assert np.array_equal(o["tensor"].cpu().numpy(), T)
+        assert np.array_equal(o["iters_found"].cpu().numpy(), it)
+        assert np.array_equal(o["outside"].cpu().numpy(), out)
+        assert np.array_equal(o["span"].cpu().numpy(), span)
+        st, score, flag, nf, reg = oracle.outliers(T, it, mode=0, kind=0, tau=3.5)
+        assert st == 0
+        assert np.array_equal(o["rank_score"].cpu().numpy(), score)
+        assert np.array_equal(o["rank_flag"].cpu().numpy(), flag)
+        assert int(o["n_flagged"][0]) == nf
+    j = int(order[-1])
+    q, I, w = qs[j], int(Iq[qs[j]]), ws[j]
+    R = int(Rq[q])
+    print(f"[batch] request {q}: {R} ranks, {I} iterations, sampled", flush=True)
+    ranks = np.unique(np.linspace(0, R - 1, 200).round().astype(np.int64))
+    s = gpu_synth.sample_ranks_to_host(w, ranks)
+    st, T, it, out, span = oracle.segment(s.offsets, s.ts, s.ctx, s.parent, s.marker, s.regions, I)
+    assert st == 0
+    idx = torch.from_numpy(ranks).cuda()
+    o = mb.outs[j]
+    assert np.array_equal(o["tensor"].index_select(0, idx).cpu().numpy(), T)
+    assert np.array_equal(o["iters_found"].index_select(0, idx).cpu().numpy(), it)
+    assert np.array_equal(o["span"].index_select(0, idx).cpu().numpy(), span)
+    single = h.outliers(o["tensor"], o["iters_found"], region=True)
+    h.sync_status()
+    assert torch.equal(single["rank_score"], o["rank_score"])
+    itf = o["iters_found"].cpu().numpy()
+    for g in (0, 37):
+        sl = o["tensor"][:, :, g:g + 1].contiguous().cpu().numpy()
+        st, sc, fl, nf, rg = oracle.outliers(sl, itf, mode=0, kind=0)
+        assert st == 0
+        assert np.array_equal(single["region_score"][:, g].cpu().numpy(), rg[:, 0]), g
+    mb.close()
+    h.close()
+    del ws, reqs, mb
+    torch.cuda.empty_cache()
