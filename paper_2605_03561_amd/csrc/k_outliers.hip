@@ -953,14 +953,18 @@ constexpr int RCH = TG * TT;   // ranks per chunk (the imbalance partials' chunk
 constexpr int RPU = 8;         // rows in flight per thread
 constexpr int SEG_MAX = 2048;  // chunks per column the selection can visit (LDS)
 
-constexpr int RQ = 8;          // interior cells buffered per column (one 64-byte write)
+constexpr int RQ = 6;          // interior cells buffered per column
 
 // Counts and compaction of one column's cells against its bracket.  Interior
-// cells are buffered in registers (newest first) and written RQ at a time.
+// cells are buffered in registers (newest first, qn of them) and written out
+// when the wave flushes: after any row in which some lane's buffer filled up,
+// every lane writes what it holds (so a store instruction carries many lanes,
+// not the one lane whose buffer happened to fill).  The order of the cells in
+// a slot does not matter to the selection.
 template <bool MAD, bool STATS>
 struct RmCol {
   int64_t a, b, m;
-  int32_t n = 0, cl = 0, cea = 0, ceb = 0, cm = 0;
+  int32_t n = 0, cl = 0, cea = 0, ceb = 0, cm = 0, qn = 0;
   int64_t sd = 0, s1 = 0, mn = INT64_MAX, mx = INT64_MIN;
   u128 s2 = 0;
   int64_t q[RQ];
@@ -985,20 +989,21 @@ struct RmCol {
 #pragma unroll
       for (int e = RQ - 1; e > 0; e--) q[e] = q[e - 1];
       q[0] = key;
-      cm++;
-      if ((cm & (RQ - 1)) == 0) {
-        int64_t *d = slot + (cm - RQ);
-#pragma unroll
-        for (int e = 0; e < RQ; e += 2) *reinterpret_cast<v2ll *>(d + e) = v2ll{q[e], q[e + 1]};
-      }
+      qn++;
     }
+  }
+  // Writes the buffered cells at slot[cm ..); every lane of the wave calls it
+  // together.
+  __device__ __forceinline__ void drain(int64_t *__restrict__ slot) {
+#pragma unroll
+    for (int e = 0; e < RQ; e++)
+      if (e < qn) slot[cm + e] = q[e];
+    cm += qn;
+    qn = 0;
   }
   // the buffered remainder, then the counts
   __device__ __forceinline__ void flush(int64_t p, RmPart pp, ColPartials ps, int64_t *__restrict__ slot) {
-    const int rem = cm & (RQ - 1);
-#pragma unroll
-    for (int e = 0; e < RQ; e++)
-      if (e < rem) slot[(cm & ~(RQ - 1)) + e] = q[e];
+    drain(slot);
     if (!MAD) pp.n[p] = n;
     pp.cl[p] = cl;
     pp.cea[p] = cea;
@@ -1064,6 +1069,12 @@ __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, in
         const int nit = it ? it[r] : 0x7fffffff;
         if (ia < nit) c0.cell((int64_t)v[u].x, slot0);
         if (two && ib < nit) c1.cell((int64_t)v[u].y, slot1);
+      }
+      // a row adds at most one cell per column: drain the whole wave as soon
+      // as one buffer is full
+      if (__ballot(c0.qn == RQ || c1.qn == RQ)) {
+        c0.drain(slot0);
+        c1.drain(slot1);
       }
     }
   }
@@ -1434,6 +1445,293 @@ __device__ void block_select(int64_t R, const int32_t *it, int I, int64_t n, Key
   __syncthreads();
 }
 
+// Stage-2 selection by bracket, for regions of at least S2_MIN_N active ranks:
+// the keys of S2S evenly spaced ranks give a bracket [lo, hi] of +-BRACKET_SE
+// standard errors around the sample median (as in the first stage); one pass
+// over the region counts the keys below lo and equal to either end and
+// compacts those strictly inside into LDS, where the selection finishes.  A
+// wanted rank outside the bracket, or an interior larger than the LDS buffer,
+// returns false and the caller runs the whole-region radix passes instead, so
+// the result is the same exact order statistic either way (two passes over
+// the region instead of eight).
+constexpr int S2S = 4096;              // sample keys
+constexpr int S2CAP = 14336;           // interior keys held in LDS (112 KB)
+constexpr int64_t S2_MIN_N = 16384;    // fewer active ranks: radix passes only
+constexpr size_t S2_LDS_BYTES = (size_t)S2CAP * sizeof(uint64_t);
+
+// Appends v to buf (LDS) when `in`; all lanes of the wave call it together.
+// The counter keeps counting past cap (the caller detects the overflow).
+__device__ inline void wave_push(bool in, uint64_t v, uint32_t *counter, uint64_t *buf, int cap) {
+  const uint64_t m = __ballot(in);
+  if (m == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = (uint32_t)__shfl((int)base, leader, 64);
+  const uint32_t pos = base + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+  if (in && pos < (uint32_t)cap) buf[pos] = v;
+}
+
+// Block-wide (RT threads) sums of three counters, returned to every thread.
+__device__ inline void block_sum3(int64_t &a, int64_t &b, int64_t &c, int64_t *slots) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    a += __shfl_xor(a, d, 64);
+    b += __shfl_xor(b, d, 64);
+    c += __shfl_xor(c, d, 64);
+  }
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    slots[3 * wid] = a;
+    slots[3 * wid + 1] = b;
+    slots[3 * wid + 2] = c;
+  }
+  __syncthreads();
+  a = b = c = 0;
+  for (int w = 0; w < RW; w++) {
+    a += slots[3 * w];
+    b += slots[3 * w + 1];
+    c += slots[3 * w + 2];
+  }
+  __syncthreads();
+}
+
+// Block-wide minimum and maximum, returned to every thread.
+__device__ inline void block_minmax_u64(uint64_t &mn, uint64_t &mx, uint64_t *slots) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t a = __shfl_xor(mn, d, 64), b = __shfl_xor(mx, d, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    slots[2 * wid] = mn;
+    slots[2 * wid + 1] = mx;
+  }
+  __syncthreads();
+  for (int w = 0; w < RW; w++) {
+    mn = slots[2 * w] < mn ? slots[2 * w] : mn;
+    mx = slots[2 * w + 1] > mx ? slots[2 * w + 1] : mx;
+  }
+  __syncthreads();
+}
+
+// The k-th smallest (k from 0) of the cnt keys buf[0 .. cnt) in LDS, all in
+// [base, base + 2^bits), and with want_next also the (k+1)-th, which must
+// exist.  8-bit digits, a histogram per wave; st holds at least 4 + RW words.
+// hist is zero on entry and on return.
+__device__ void lds_select(const uint64_t *buf, int cnt, uint64_t base, int bits, int64_t k,
+                           bool want_next, uint32_t (*hist)[256], uint32_t *tot, uint64_t *st,
+                           uint64_t &v1, uint64_t &v2) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  uint64_t pref = 0, r1 = 0, r2 = 0;
+  int hi = bits;
+  while (hi > 0) {
+    const int w = hi < 8 ? hi : 8;
+    const int lo = hi - w;
+    const bool last = lo == 0;
+    const uint32_t mask = (1u << w) - 1;
+    uint64_t mgt = ~0ull;  // smallest key above the prefix group (last digit)
+    for (int i = tid; i < cnt; i += RT) {
+      const uint64_t rel = buf[i] - base;
+      const uint64_t top = shr64(rel, hi);
+      if (top == pref)
+        atomicAdd(&hist[wid][(uint32_t)(rel >> lo) & mask], 1u);
+      else if (last && top > pref && rel < mgt)
+        mgt = rel;
+    }
+    if (last && want_next) {
+      for (int d = 32; d >= 1; d >>= 1) {
+        const uint64_t o = __shfl_xor(mgt, d, 64);
+        mgt = o < mgt ? o : mgt;
+      }
+      if (lane == 0) st[4 + wid] = mgt;
+    }
+    __syncthreads();
+    if (tid < 256) {
+      uint32_t c = 0;
+      for (int q = 0; q < RW; q++) {
+        c += hist[q][tid];
+        hist[q][tid] = 0;
+      }
+      tot[tid] = c;
+    }
+    __syncthreads();
+    if (wid == 0) {
+      // lane owns bins 4 lane .. 4 lane + 3
+      uint32_t c[4];
+      int64_t own = 0;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        c[j] = tot[4 * lane + j];
+        own += c[j];
+      }
+      int64_t incl = own;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int64_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+      }
+      const int64_t excl = incl - own;
+      const bool mine = excl <= k && k < excl + own;
+      int b = 0, same = 0;
+      int64_t kk = 0;
+      if (mine) {
+        int64_t cum = excl;
+        int j = 0;
+        for (; j < 3; j++) {
+          if (cum + (int64_t)c[j] > k) break;
+          cum += c[j];
+        }
+        b = 4 * lane + j;
+        kk = k - cum;
+        same = kk + 1 < (int64_t)c[j] ? 1 : 0;
+      }
+      const int owner = __ffsll((long long)__ballot(mine)) - 1;
+      b = __shfl(b, owner, 64);
+      kk = __shfl(kk, owner, 64);
+      same = __shfl(same, owner, 64);
+      uint32_t nxt = 0xffffffffu;  // smallest non-empty bin above b
+      if (last && want_next && !same) {
+#pragma unroll
+        for (int j = 3; j >= 0; j--)
+          if (4 * lane + j > b && c[j] > 0) nxt = (uint32_t)(4 * lane + j);
+        for (int d = 32; d >= 1; d >>= 1) {
+          const uint32_t o = (uint32_t)__shfl_xor((int)nxt, d, 64);
+          nxt = o < nxt ? o : nxt;
+        }
+      }
+      if (lane == 0) {
+        st[0] = (pref << w) | (uint64_t)b;
+        st[1] = (uint64_t)kk;
+        st[2] = (uint64_t)same;
+        st[3] = nxt;
+      }
+    }
+    __syncthreads();
+    const uint64_t np = st[0];
+    const int64_t kn = (int64_t)st[1];
+    if (last) {
+      r1 = np;
+      if (!want_next || st[2]) {
+        r2 = np;
+      } else if (st[3] != 0xffffffffu) {
+        r2 = (pref << w) | st[3];
+      } else {
+        uint64_t mg = ~0ull;
+        for (int q = 0; q < RW; q++) mg = st[4 + q] < mg ? st[4 + q] : mg;
+        r2 = mg;
+      }
+    }
+    pref = np;
+    k = kn;
+    hi = lo;
+    __syncthreads();  // st is rewritten by the next digit
+  }
+  v1 = base + r1;
+  v2 = base + (want_next ? r2 : r1);
+}
+
+// Order statistics (n-1)/2 and, for even n, n/2 of the keys keyf(r) over the
+// active ranks (block_select's contract) through a bracket; false when the
+// bracket misses or overflows (nothing written to v1, v2).
+template <class KeyF>
+__device__ bool bracket_select(int64_t R, const int32_t *it, int I, int64_t n, KeyF keyf,
+                               uint64_t *buf, uint32_t (*hist)[256], uint32_t *tot, uint64_t *st,
+                               int64_t *slots, uint32_t *counter, uint64_t &v1, uint64_t &v2) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *counter = 0;
+  __syncthreads();
+  {
+    constexpr int U = S2S / RT;
+    uint64_t kv[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t j = (int64_t)u * RT + tid;
+      const int64_t r = ((2 * j + 1) * R) / (2 * S2S);
+      ok[u] = rank_active(it, I, r);
+      kv[u] = keyf(r);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) wave_push(ok[u], kv[u], counter, buf, S2S);
+  }
+  __syncthreads();
+  const int m = (int)*counter;
+  if (m < 256) return false;
+  uint64_t mn = ~0ull, mx = 0;
+  for (int j = tid; j < m; j += RT) {
+    mn = buf[j] < mn ? buf[j] : mn;
+    mx = buf[j] > mx ? buf[j] : mx;
+  }
+  block_minmax_u64(mn, mx, reinterpret_cast<uint64_t *>(slots));
+  const int sbits = nbits64(mx - mn);
+  const double dl = 0.5 * BRACKET_SE / sqrt((double)m);
+  const double ca = (0.5 - dl) * (double)(m - 1), cb = (0.5 + dl) * (double)(m - 1);
+  const int ia = ca <= 0.0 ? 0 : (int)floor(ca);
+  const int ib = cb >= (double)(m - 1) ? m - 1 : (int)ceil(cb);
+  uint64_t lo, hi;
+  lds_select(buf, m, mn, sbits, ia, ib == ia + 1, hist, tot, st, lo, hi);
+  if (ib > ia + 1) lds_select(buf, m, mn, sbits, ib, false, hist, tot, st, hi, hi);
+  else if (ib == ia) hi = lo;
+  // buf now takes the interior
+  if (tid == 0) *counter = 0;
+  __syncthreads();
+  int64_t clo = 0, ceqa = 0, ceqb = 0;
+  for (int64_t r0 = tid; r0 < R; r0 += (int64_t)RT * SU2) {
+    uint64_t kv[SU2];
+    bool ok[SU2];
+#pragma unroll
+    for (int u = 0; u < SU2; u++) {
+      const int64_t r = r0 + (int64_t)u * RT;
+      ok[u] = r < R && rank_active(it, I, r);
+      kv[u] = r < R ? keyf(r) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < SU2; u++) {
+      const uint64_t key = kv[u];
+      clo += (ok[u] && key < lo) ? 1 : 0;
+      ceqa += (ok[u] && key == lo) ? 1 : 0;
+      ceqb += (ok[u] && key == hi && hi != lo) ? 1 : 0;
+      wave_push(ok[u] && key > lo && key < hi, key, counter, buf, S2CAP);
+    }
+  }
+  block_sum3(clo, ceqa, ceqb, slots);
+  const int64_t cmid = (int64_t)*counter;
+  __syncthreads();  // every thread has read the counter
+  const int64_t k = (n - 1) / 2;
+  const bool even = (n & 1) == 0;
+  auto where = [&](int64_t j) -> int {
+    if (j < clo) return 0;
+    j -= clo;
+    if (j < ceqa) return 1;
+    j -= ceqa;
+    if (j < cmid) return 2;
+    j -= cmid;
+    return j < ceqb ? 3 : 0;
+  };
+  const int w1 = where(k), w2 = even ? where(k + 1) : w1;
+  if (w1 == 0 || w2 == 0) return false;
+  if ((w1 == 2 || w2 == 2) && cmid > S2CAP) return false;
+  const int64_t base = clo + ceqa;
+  const int ibits = nbits64(hi - lo);
+  uint64_t a1 = 0, a2 = 0;
+  if (w1 == 2 && w2 == 2) {
+    lds_select(buf, (int)cmid, lo, ibits, k - base, even, hist, tot, st, a1, a2);
+    v1 = a1;
+    v2 = even ? a2 : a1;
+    return true;
+  }
+  if (w1 == 2) lds_select(buf, (int)cmid, lo, ibits, k - base, false, hist, tot, st, a1, a1);
+  v1 = w1 == 2 ? a1 : (w1 == 1 ? lo : hi);
+  if (!even) {
+    v2 = v1;
+    return true;
+  }
+  if (w2 == 2) lds_select(buf, (int)cmid, lo, ibits, k + 1 - base, false, hist, tot, st, a2, a2);
+  v2 = w2 == 2 ? a2 : (w2 == 1 ? lo : hi);
+  return true;
+}
+
 template <bool F64, bool MAD>
 __global__ __launch_bounds__(RT) void sel_regions(const void *vals_t, int64_t R, int G,
                                                   const int32_t *it, int I, double *z_t,
@@ -1445,6 +1743,9 @@ __global__ __launch_bounds__(RT) void sel_regions(const void *vals_t, int64_t R,
   __shared__ int64_t ib[RT];
   __shared__ int64_t xacc[RW * XL];
   __shared__ uint32_t xbad;
+  __shared__ uint64_t st2[4 + RW];
+  __shared__ uint32_t s2cnt;
+  extern __shared__ uint64_t s2buf[];  // S2_LDS_BYTES, launched with MAD only
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
   int64_t *xw = xacc + (tid >> 6) * XL;
@@ -1465,6 +1766,14 @@ __global__ __launch_bounds__(RT) void sel_regions(const void *vals_t, int64_t R,
   int64_t n = 0;
   for (int64_t r = tid; r < R; r += RT) n += rank_active(it, I, r) ? 1 : 0;
   n = block_sum_i64<RT>(n, ib);
+  // the middle order statistics: by bracket when the region is large enough,
+  // else (or when the bracket misses) by radix passes over the region
+  auto select = [&](auto keyf, uint64_t &a, uint64_t &b) {
+    if (n >= S2_MIN_N &&
+        bracket_select(R, it, I, n, keyf, s2buf, hist, tot, st2, ib, &s2cnt, a, b))
+      return;
+    block_select(R, it, I, n, keyf, hist, tot, sh_u64, a, b);
+  };
 
   // Centre and scale.
   double med = 0.0, scale = 0.0;
@@ -1474,10 +1783,9 @@ __global__ __launch_bounds__(RT) void sel_regions(const void *vals_t, int64_t R,
     if (MAD) {
       uint64_t a, b;
       if (F64) {
-        block_select(R, it, I, n, [&](int64_t r) { return key_f64(vd[r]); }, hist, tot, sh_u64, a, b);
+        select([&](int64_t r) { return key_f64(vd[r]); }, a, b);
         med = (n & 1) ? dec_f64(a) : 0.5 * (dec_f64(a) + dec_f64(b));
-        block_select(R, it, I, n, [&](int64_t r) { return key_f64(fabs(vd[r] - med)); }, hist, tot,
-                     sh_u64, a, b);
+        select([&](int64_t r) { return key_f64(fabs(vd[r] - med)); }, a, b);
         const double mad = (n & 1) ? dec_f64(a) : 0.5 * (dec_f64(a) + dec_f64(b));
         if (mad > 0.0) {
           mode = 1;
@@ -1491,15 +1799,14 @@ __global__ __launch_bounds__(RT) void sel_regions(const void *vals_t, int64_t R,
           }
         }
       } else {
-        block_select(R, it, I, n, [&](int64_t r) { return (uint64_t)vi[r] ^ SIGN; }, hist, tot,
-                     sh_u64, a, b);
+        select([&](int64_t r) { return (uint64_t)vi[r] ^ SIGN; }, a, b);
         med2 = (int64_t)(a ^ SIGN) + (int64_t)(b ^ SIGN);
-        block_select(R, it, I, n,
-                     [&](int64_t r) {
-                       const int64_t d = 2 * vi[r] - med2;
-                       return (uint64_t)(d < 0 ? -d : d);
-                     },
-                     hist, tot, sh_u64, a, b);
+        select(
+            [&](int64_t r) {
+              const int64_t d = 2 * vi[r] - med2;
+              return (uint64_t)(d < 0 ? -d : d);
+            },
+            a, b);
         const int64_t mad4 = (int64_t)(a + b);
         if (mad4 > 0) {
           mode = 1;
@@ -1703,6 +2010,25 @@ OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
   return w;
 }
 
+// sel_regions with the dynamic LDS its instantiation uses (the bracket buffer
+// of the robust kind; the limit is raised by outliers_init).
+template <bool F64, bool MAD>
+void launch_sel_regions(const void *vals_t, int64_t R, int G, const int32_t *it, int I, double *z_t,
+                        double *region_score, hipStream_t s) {
+  hipLaunchKernelGGL((sel_regions<F64, MAD>), dim3(G), dim3(RT), MAD ? S2_LDS_BYTES : 0, s, vals_t, R,
+                     G, it, I, z_t, region_score);
+}
+
+}  // namespace
+
+void outliers_init() {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&sel_regions<true, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)S2_LDS_BYTES);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&sel_regions<false, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)S2_LDS_BYTES);
+}
+
+namespace {
 }  // namespace
 
 size_t outliers_ws_bytes(int64_t R, int32_t I, int32_t G, int32_t mode, int32_t kind) {
@@ -1714,8 +2040,7 @@ size_t outliers_ws_bytes(int64_t R, int32_t I, int32_t G, int32_t mode, int32_t 
 hipError_t launch_region_robust(const double *v_t, int64_t R, int G, const int32_t *it, int I,
                                 double *z_t, float *score, hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL((sel_regions<true, true>), dim3(G), dim3(RT), 0, s, (const void *)v_t, R, G, it,
-                     I, z_t, (double *)nullptr);
+  launch_sel_regions<true, true>((const void *)v_t, R, G, it, I, z_t, (double *)nullptr, s);
   hipLaunchKernelGGL(rank_max_f32, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, z_t, R, G, it, I,
                      score);
   return hipGetLastError();
@@ -1765,8 +2090,8 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
       const int64_t waves = ((a.R + SRW - 1) / SRW) * ((a.G + 63) / 64);
       hipLaunchKernelGGL(score_rows, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a.T, a.R, a.I,
                          a.G, a.it, w.cs, w.m_t);
-      hipLaunchKernelGGL((sel_regions<true, true>), dim3(a.G), dim3(RT), 0, s, (const void *)w.m_t, a.R,
-                         a.G, a.it, a.I, w.z_t, a.region_score);
+      launch_sel_regions<true, true>((const void *)w.m_t, a.R, a.G, a.it, a.I, w.z_t, a.region_score,
+                                     s);
     } else if (a.mode == TA_SCAN_FULL) {
       if (IG > 0) {
         const dim3 tg((unsigned)transpose_groups_of(a.R), (IG + TT - 1) / TT);
@@ -1800,19 +2125,19 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
         hipLaunchKernelGGL((score_cols<false>), dim3(nw), dim3(256), 0, s, w.Tt, a.R, a.I, a.G, a.it,
                            w.cs, w.cm, w.m_t);
       if (mad)
-        hipLaunchKernelGGL((sel_regions<true, true>), dim3(a.G), dim3(RT), 0, s, (const void *)w.m_t,
-                           a.R, a.G, a.it, a.I, w.z_t, a.region_score);
+        launch_sel_regions<true, true>((const void *)w.m_t, a.R, a.G, a.it, a.I, w.z_t, a.region_score,
+                                       s);
       else
-        hipLaunchKernelGGL((sel_regions<true, false>), dim3(a.G), dim3(RT), 0, s,
-                           (const void *)w.m_t, a.R, a.G, a.it, a.I, w.z_t, a.region_score);
+        launch_sel_regions<true, false>((const void *)w.m_t, a.R, a.G, a.it, a.I, w.z_t,
+                                         a.region_score, s);
     } else {
       hipLaunchKernelGGL(rank_totals_t, dim3(nb), dim3(256), 0, s, a.T, a.R, a.I, a.G, a.it, w.S_t);
       if (mad)
-        hipLaunchKernelGGL((sel_regions<false, true>), dim3(a.G), dim3(RT), 0, s,
-                           (const void *)w.S_t, a.R, a.G, a.it, a.I, w.z_t, a.region_score);
+        launch_sel_regions<false, true>((const void *)w.S_t, a.R, a.G, a.it, a.I, w.z_t,
+                                         a.region_score, s);
       else
-        hipLaunchKernelGGL((sel_regions<false, false>), dim3(a.G), dim3(RT), 0, s,
-                           (const void *)w.S_t, a.R, a.G, a.it, a.I, w.z_t, a.region_score);
+        launch_sel_regions<false, false>((const void *)w.S_t, a.R, a.G, a.it, a.I, w.z_t,
+                                         a.region_score, s);
     }
   }
   const unsigned nr = (unsigned)((a.R + 255) / 256);

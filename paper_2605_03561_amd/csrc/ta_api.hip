@@ -604,6 +604,7 @@ ta_status ta_create(ta_handle *out, int device) {
     return TA_ERR_HIP;
   }
   scratch_setup(device);
+  ta::outliers_init();
   *out = h;
   return TA_OK;
 }

@@ -143,6 +143,9 @@ int transpose_groups(int64_t R);
 // score[r] = max_g |z|.
 hipError_t launch_region_robust(const double *v_t, int64_t R, int G, const int32_t *it, int I,
                                 double *z_t, float *score, hipStream_t s);
+// Raises the dynamic LDS limit of the outlier kernels that use more than
+// 64 KB; called once per handle, before any launch or capture.
+void outliers_init();
 hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStream_t s);
 size_t outliers_ws_bytes(int64_t R, int32_t I, int32_t G, int32_t mode, int32_t kind);
 

@@ -354,6 +354,46 @@ def test_outliers_column_shapes(ta, h, oracle, R, style):
                 assert np.array_equal(go["rank_flag"], flag), (mode, kind)
 
 
+@pytest.mark.parametrize("case", ["miss", "overflow", "ties"])
+def test_outliers_region_bracket_fallbacks(ta, h, oracle, case):
+    """The per-region selection over ranks brackets the middle from the keys of
+    4,096 evenly spaced ranks (when at least 16,384 ranks are active).  Inputs
+    built against those sample ranks make the bracket miss the median (sample
+    ranks far above the rest), overflow its interior buffer (the other ranks
+    packed inside the sample's central bracket), or put the middle on a tie at
+    a bracket end; the result must equal the oracle's either way.  With one
+    iteration the per-rank region means keep the order of the cells, so the
+    construction carries over to the second stage, in both scan modes."""
+    import torch
+    R, I, G = (20000, 1, 2) if case == "miss" else (100000, 1, 2)
+    print(f"[parity] outliers region bracket {case} R={R}", flush=True)
+    rng = np.random.default_rng(len(case))
+    j = np.arange(4096, dtype=np.int64)
+    samp = ((2 * j + 1) * R) // (2 * 4096)            # the sample's ranks
+    is_s = np.zeros(R, bool)
+    is_s[samp] = True
+    r = np.arange(R, dtype=np.int64)
+    if case == "miss":
+        x = np.where(is_s, 10**9 + r, r)
+    elif case == "overflow":
+        x = np.where(is_s, 0, 2_048_000 + r % 5000)
+        x[samp] = j * 1000
+    else:                                                 # the middle ties at the low end
+        x = np.full(R, 10**6, np.int64)
+        x[samp] = np.where(j < 2000, 10**6, 10**6 + j)
+    T = np.stack([x, x[::-1] + rng.integers(0, 3, R)], axis=1).reshape(R, I, G).astype(np.int64)
+    it = np.full(R, I, np.int32)
+    dT, dit = torch.from_numpy(T).cuda(), torch.from_numpy(it).cuda()
+    for mode in (0, 1):
+        o = h.outliers(dT, dit, mode=mode, kind=0, tau=3.5, region=True)
+        st, score, flag, nf, reg = oracle.outliers(T, it, mode=mode, kind=0, tau=3.5)
+        assert st == 0
+        go = {k: v.cpu().numpy() for k, v in o.items()}
+        assert np.array_equal(go["region_score"], reg), mode
+        assert np.array_equal(go["rank_score"], score), mode
+        assert np.array_equal(go["rank_flag"], flag), mode
+
+
 def test_topology_parity(ta, h, oracle):
     import torch
     rng = np.random.default_rng(3)
