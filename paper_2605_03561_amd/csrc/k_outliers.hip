@@ -960,7 +960,8 @@ constexpr int RQ = 6;          // interior cells buffered per column
 // when the wave flushes: after any row in which some lane's buffer filled up,
 // every lane writes what it holds (so a store instruction carries many lanes,
 // not the one lane whose buffer happened to fill).  The order of the cells in
-// a slot does not matter to the selection.
+// a slot does not matter to the selection.  A cell is counted when `ok`, with
+// selects rather than branches, so the row loads around it stay in one block.
 template <bool MAD, bool STATS>
 struct RmCol {
   int64_t a, b, m;
@@ -968,29 +969,34 @@ struct RmCol {
   int64_t sd = 0, s1 = 0, mn = INT64_MAX, mx = INT64_MIN;
   u128 s2 = 0;
   int64_t q[RQ];
-  __device__ __forceinline__ void cell(int64_t x, int64_t *__restrict__ slot) {
+  __device__ __forceinline__ void cell(int64_t x, bool ok) {
     int64_t key = x;
     if (MAD) {
       const int64_t d = 2 * x - m;
       key = d < 0 ? -d : d;
-      sd += key;
+      sd += ok ? key : 0;
     }
-    n++;
-    cl += key < a ? 1 : 0;
-    cea += key == a ? 1 : 0;
-    ceb += (key == b && b != a) ? 1 : 0;
-    if (STATS) {
+    n += ok ? 1 : 0;
+    cl += (ok && key < a) ? 1 : 0;
+    cea += (ok && key == a) ? 1 : 0;
+    ceb += (ok && key == b && b != a) ? 1 : 0;
+    if (STATS && ok) {
       s1 += x;
-      s2 += (u128)((i128)x * x);
+      // the square: one 32 x 32 -> 64-bit product when |x| < 2^32 (times
+      // below 4.3 s), the full 128-bit one otherwise
+      const uint64_t ax = (uint64_t)(x < 0 ? -x : x);
+      if ((ax >> 32) == 0)
+        s2 += (u128)((uint64_t)(uint32_t)ax * (uint64_t)(uint32_t)ax);
+      else
+        s2 += (u128)((i128)x * x);
       mn = x < mn ? x : mn;
       mx = x > mx ? x : mx;
     }
-    if (key > a && key < b) {
+    const bool in = ok && key > a && key < b;
 #pragma unroll
-      for (int e = RQ - 1; e > 0; e--) q[e] = q[e - 1];
-      q[0] = key;
-      qn++;
-    }
+    for (int e = RQ - 1; e > 0; e--) q[e] = in ? q[e - 1] : q[e];
+    q[0] = in ? key : q[0];
+    qn += in ? 1 : 0;
   }
   // Writes the buffered cells at slot[cm ..); every lane of the wave calls it
   // together.
@@ -1021,19 +1027,21 @@ struct RmCol {
   }
 };
 
-// One streaming pass over the row-major tensor: a thread owns two adjacent
-// columns (16-byte loads; a wave reads 1 KB of a row) and walks the RCH ranks
-// of chunk blockIdx.y, RPU rows in flight, counting in registers; the bracket
-// interior of each (chunk, column) goes to its own slot of RCH cells (64-byte
-// writes), so no atomics and no overflow.  No LDS and no barriers.
-template <bool MAD, bool STATS>
+// One streaming pass over the row-major tensor: a thread owns CPL adjacent
+// columns (two: 16-byte loads when the row length is even, a wave reads 1 KB
+// of a row; one: half the registers, so more waves) and walks the RCH ranks of
+// chunk blockIdx.y, RPU rows in flight, counting in registers; the bracket
+// interior of each (chunk, column) goes to its own slot of RCH cells, so no
+// atomics and no overflow.  No LDS and no barriers.  Rows past the chunk's end
+// load its last row (in bounds) and are not counted.
+template <bool MAD, bool STATS, bool VEC, int CPL>
 __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, int64_t R, int IG, int G,
                                                const int32_t *it, RmBr br, int64_t *__restrict__ scr,
                                                RmPart pp, ColPartials ps) {
-  const int ca = ((int)blockIdx.x * 256 + (int)threadIdx.x) * 2;
+  const int ca = ((int)blockIdx.x * 256 + (int)threadIdx.x) * CPL;
   if (ca >= IG) return;
   const int64_t ng = gridDim.y, ch = blockIdx.y;
-  const bool two = ca + 1 < IG;
+  const bool two = CPL == 2 && ca + 1 < IG;
   const int ia = ca / G, ib = (ca + 1) / G;
   RmCol<MAD, STATS> c0, c1;
   c0.a = br.a[ca];
@@ -1044,32 +1052,29 @@ __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, in
   c1.m = (MAD && two) ? br.med2[ca + 1] : 0;
   int64_t *slot0 = scr + ((int64_t)ca * ng + ch) * RCH;
   int64_t *slot1 = scr + ((int64_t)(ca + 1) * ng + ch) * RCH;
-  const bool vec = (IG & 1) == 0;
-  const int64_t rb = ch * RCH, re = rb + RCH < R ? rb + RCH : R;
+  const int64_t rb = ch * RCH, re = rb + RCH < R ? rb + RCH : R, last = re - 1;
+  const int cb = two ? ca + 1 : ca;
+  auto load_row = [&](int64_t r) {
+    const int64_t *row = T + (r < re ? r : last) * IG;
+    if (CPL == 1) return v2ll{__builtin_nontemporal_load(row + ca), SENT};
+    if (VEC) return __builtin_nontemporal_load(reinterpret_cast<const v2ll *>(row + ca));
+    return v2ll{__builtin_nontemporal_load(row + ca), __builtin_nontemporal_load(row + cb)};
+  };
+  // RPU rows in flight: the register of a row, once counted, loads the row
+  // RPU further on (so the loads stay in flight while the counting runs)
+  v2ll v[RPU];
+#pragma unroll
+  for (int u = 0; u < RPU; u++) v[u] = load_row(rb + u);
   for (int64_t r0 = rb; r0 < re; r0 += RPU) {
-    v2ll v[RPU];
+    int nit[RPU];
+#pragma unroll
+    for (int u = 0; u < RPU; u++) nit[u] = it ? it[r0 + u < re ? r0 + u : last] : 0x7fffffff;
 #pragma unroll
     for (int u = 0; u < RPU; u++) {
-      const int64_t r = r0 + u;
-      v[u] = v2ll{SENT, SENT};
-      if (r < re) {
-        const int64_t *row = T + r * IG + ca;
-        if (vec) {
-          v[u] = __builtin_nontemporal_load(reinterpret_cast<const v2ll *>(row));
-        } else {
-          v[u].x = __builtin_nontemporal_load(row);
-          if (two) v[u].y = __builtin_nontemporal_load(row + 1);
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < RPU; u++) {
-      const int64_t r = r0 + u;
-      if (r < re) {
-        const int nit = it ? it[r] : 0x7fffffff;
-        if (ia < nit) c0.cell((int64_t)v[u].x, slot0);
-        if (two && ib < nit) c1.cell((int64_t)v[u].y, slot1);
-      }
+      const bool rv = r0 + u < re;
+      c0.cell((int64_t)v[u].x, rv && ia < nit[u]);
+      c1.cell((int64_t)v[u].y, rv && two && ib < nit[u]);
+      v[u] = load_row(r0 + u + RPU);
       // a row adds at most one cell per column: drain the whole wave as soon
       // as one buffer is full
       if (__ballot(c0.qn == RQ || c1.qn == RQ)) {
@@ -2010,6 +2015,22 @@ OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
   return w;
 }
 
+// rm_pass with CPL columns per lane (16-byte row loads for two columns when
+// the row length is even).
+constexpr int RM_CPL_STATS = 1, RM_CPL_MAD = 2, RM_CPL_COUNT = 2;
+template <bool MAD, bool STATS>
+void launch_rm_pass(int ng, const OutArgs &a, int IG, RmBr br, int64_t *scr, RmPart rp,
+                    hipStream_t s) {
+  constexpr int CPL = STATS ? RM_CPL_STATS : (MAD ? RM_CPL_MAD : RM_CPL_COUNT);
+  const dim3 grid((unsigned)((IG + 256 * CPL - 1) / (256 * CPL)), (unsigned)ng);
+  if (CPL == 2 && (IG & 1) == 0)
+    hipLaunchKernelGGL((rm_pass<MAD, STATS, true, CPL>), grid, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it,
+                       br, scr, rp, a.stats);
+  else
+    hipLaunchKernelGGL((rm_pass<MAD, STATS, false, CPL>), grid, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it,
+                       br, scr, rp, a.stats);
+}
+
 // sel_regions with the dynamic LDS its instantiation uses (the bracket buffer
 // of the robust kind; the limit is raised by outliers_init).
 template <bool F64, bool MAD>
@@ -2064,25 +2085,22 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         const int grid = std::min(IG, std::min(SEL_GRID_MAX, SEL_WGS_PER_CU * cus));
-        const dim3 pg((unsigned)((IG + 511) / 512), (unsigned)ng);
         hipLaunchKernelGGL(rm_sample, dim3(MS / TT, strips), dim3(256), 0, s, a.T, a.R, IG, a.G, a.it,
                            w.smp);
         hipLaunchKernelGGL(rm_brackets, dim3(IG), dim3(CS), 0, s, (const int64_t *)w.smp, IG, w.qa, w.qb);
         const RmBr bm{w.qa, w.qb, nullptr};
         if (a.stats.rc > 0) {
-          hipLaunchKernelGGL((rm_pass<false, true>), pg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, bm,
-                             w.scr, w.rp, a.stats);
+          launch_rm_pass<false, true>(ng, a, IG, bm, w.scr, w.rp, s);
           if (a.stats_ready) (void)hipEventRecord(a.stats_ready, s);
-        } else
-          hipLaunchKernelGGL((rm_pass<false, false>), pg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, bm,
-                             w.scr, w.rp, a.stats);
+        } else {
+          launch_rm_pass<false, false>(ng, a, IG, bm, w.scr, w.rp, s);
+        }
         const RmOut ro{w.da, w.db};
         hipLaunchKernelGGL(rm_select<false>, dim3(grid), dim3(CS), 0, s, a.T, a.R, IG, a.G, a.it,
                            (const int64_t *)w.smp, ng, w.rp, bm, (const int64_t *)w.scr, w.slots, ro,
                            w.cs);
         const RmBr bd{w.da, w.db, w.cs.med2};
-        hipLaunchKernelGGL((rm_pass<true, false>), pg, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, bd,
-                           w.scr, w.rp, a.stats);
+        launch_rm_pass<true, false>(ng, a, IG, bd, w.scr, w.rp, s);
         hipLaunchKernelGGL(rm_select<true>, dim3(grid), dim3(CS), 0, s, a.T, a.R, IG, a.G, a.it,
                            (const int64_t *)w.smp, ng, w.rp, bd, (const int64_t *)w.scr, w.slots, ro,
                            w.cs);
