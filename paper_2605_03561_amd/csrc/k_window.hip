@@ -7,7 +7,8 @@
 namespace ta {
 namespace {
 
-constexpr int WT = 256;
+constexpr int WT = 256;   // threads of the small kernels
+constexpr int WWT = 512;  // threads of a window workgroup
 
 typedef long long v2ll __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -15,39 +16,59 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 // Visits events k in [lo, hi) of a rank whose events end at e, four
 // consecutive events per thread per step from a 4-aligned index (16-byte loads
 // of timestamps and contexts; scalar loads within 4 events of the array's end
-// E).  f(k, t_k, t_{k+1} (t_k for the rank's last event), ctx_k).
-template <int NT, class F>
+// E), DEPTH steps' loads in flight before any is visited.  f(k, t_k, t_{k+1}
+// (t_k for the rank's last event), ctx_k).
+struct EvQuad {
+  int64_t t[5];
+  int32_t c[4];
+};
+
+__device__ inline EvQuad load_quad(const int64_t *__restrict__ ts, const int32_t *__restrict__ ctx,
+                                   int64_t E, int64_t k0, int64_t e) {
+  EvQuad q;
+  if (k0 + 4 <= E) {
+    const v2ll a = *reinterpret_cast<const v2ll *>(ts + k0);
+    const v2ll b = *reinterpret_cast<const v2ll *>(ts + k0 + 2);
+    const v4i c = *reinterpret_cast<const v4i *>(ctx + k0);
+    q.t[0] = a.x;
+    q.t[1] = a.y;
+    q.t[2] = b.x;
+    q.t[3] = b.y;
+    q.c[0] = c.x;
+    q.c[1] = c.y;
+    q.c[2] = c.z;
+    q.c[3] = c.w;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      q.t[u] = k0 + u < E ? ts[k0 + u] : 0;
+      q.c[u] = k0 + u < E ? ctx[k0 + u] : 0;
+    }
+  }
+  q.t[4] = k0 + 4 < e ? ts[k0 + 4] : 0;
+  return q;
+}
+
+template <int NT, int DEPTH, class F>
 __device__ inline void visit_events(const int64_t *__restrict__ ts, const int32_t *__restrict__ ctx,
                                     int64_t E, int64_t lo, int64_t hi, int64_t e, F &&f) {
-  for (int64_t k0 = (lo & ~(int64_t)3) + 4 * (int64_t)threadIdx.x; k0 < hi; k0 += 4 * (int64_t)NT) {
-    int64_t t[5];
-    int32_t c[4];
-    if (k0 + 4 <= E) {
-      const v2ll a = *reinterpret_cast<const v2ll *>(ts + k0);
-      const v2ll b = *reinterpret_cast<const v2ll *>(ts + k0 + 2);
-      const v4i q = *reinterpret_cast<const v4i *>(ctx + k0);
-      t[0] = a.x;
-      t[1] = a.y;
-      t[2] = b.x;
-      t[3] = b.y;
-      c[0] = q.x;
-      c[1] = q.y;
-      c[2] = q.z;
-      c[3] = q.w;
-    } else {
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        t[u] = k0 + u < E ? ts[k0 + u] : 0;
-        c[u] = k0 + u < E ? ctx[k0 + u] : 0;
-      }
-    }
-    t[4] = k0 + 4 < e ? ts[k0 + 4] : 0;
+  auto visit = [&](const EvQuad &q, int64_t k0) {
 #pragma unroll
     for (int u = 0; u < 4; u++) {
       const int64_t k = k0 + u;
       if (k < lo || k >= hi) continue;
-      f(k, t[u], k + 1 < e ? t[u + 1] : t[u], c[u]);
+      f(k, q.t[u], k + 1 < e ? q.t[u + 1] : q.t[u], q.c[u]);
     }
+  };
+  constexpr int64_t STEP = 4 * (int64_t)NT;
+  for (int64_t k0 = (lo & ~(int64_t)3) + 4 * (int64_t)threadIdx.x; k0 < hi; k0 += DEPTH * STEP) {
+    // every load is in bounds of the arrays (load_quad guards E); the later
+    // steps' events may lie past hi, where visit skips them
+    EvQuad q[DEPTH];
+#pragma unroll
+    for (int d = 0; d < DEPTH; d++) q[d] = load_quad(ts, ctx, E, k0 + d * STEP, e);
+#pragma unroll
+    for (int d = 0; d < DEPTH; d++) visit(q[d], k0 + d * STEP);
   }
 }
 
@@ -58,74 +79,64 @@ __global__ void zero_i64(int64_t *p, int64_t n) {
 }
 
 // First index in [a, z) whose timestamp satisfies a monotone predicate (false
-// then true), or z: a 64-way search by one wave -- each step probes 64 evenly
-// spaced positions and keeps the gap between the last false and the first
-// true probe, so about log_65(z - a) + 1 round trips.  All lanes of the wave
-// call it together and get the same result.
+// then true), or z: binary search by one thread.
 template <class P>
-__device__ inline int64_t wave_search(const int64_t *__restrict__ ts, int64_t a, int64_t z, P pred) {
-  const int lane = threadIdx.x & 63;
-  while (z - a > 64) {
-    const int64_t len = z - a;
-    const int64_t p = a + ((int64_t)(lane + 1) * len) / 65;
-    const uint64_t m = __ballot(pred(ts[p]));
-    if (m == 0) {
-      a = a + (64 * len) / 65 + 1;
-    } else {
-      const int f = __ffsll((long long)m) - 1;
-      const int64_t pf = a + ((int64_t)(f + 1) * len) / 65;
-      a = f == 0 ? a : a + ((int64_t)f * len) / 65 + 1;
-      z = pf;
-    }
+__device__ inline int64_t first_true(const int64_t *__restrict__ ts, int64_t a, int64_t z, P pred) {
+  while (a < z) {
+    const int64_t m = a + ((z - a) >> 1);
+    if (pred(ts[m])) z = m;
+    else a = m + 1;
   }
-  const bool t = a + lane < z && pred(ts[a + lane]);
-  const uint64_t m = __ballot(t);
-  return m ? a + __ffsll((long long)m) - 1 : z;
+  return a;
 }
 
-// One workgroup per selected rank (grid-stride over the selection).  Searches
-// (64-way, one wave) on the rank's sorted timestamps bound the events that overlap the
-// window: before the event preceding the first timestamp above t0 every
-// interval ends by t0; from the first timestamp at or above t1 every interval
-// starts at or after t1.  LDSH: an LDS histogram over the N nodes (N <= 8192)
-// flushed once; otherwise 64-bit atomics on the output.  Integer sums: the
-// order of the atomics does not matter.
+// The events of each selected rank that overlap the window, one thread per
+// rank (so the searches' round trips overlap one another): before the event
+// preceding the first timestamp above t0 every interval ends by t0; from the
+// first timestamp at or above t1 every interval starts at or after t1.
+// bounds[i] = {lo, hi, e (the rank's end), 0}; an invalid rank gets an empty
+// range and sets the offsets error bit.
+__global__ __launch_bounds__(WT) void window_bounds(const int64_t *__restrict__ off,
+                                                   const int64_t *__restrict__ ts, int64_t R, int64_t E,
+                                                   const int32_t *__restrict__ ids, int64_t n_sel,
+                                                   int64_t t0, int64_t t1, v2ll *__restrict__ bounds,
+                                                   uint32_t *err) {
+  const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
+  if (i >= n_sel) return;
+  const int64_t r = ids ? (int64_t)ids[i] : i;
+  int64_t lo = 0, hi = 0, e = 0;
+  if (r < 0 || r >= R || off[r] < 0 || off[r + 1] < off[r] || off[r + 1] > E) {
+    atomicOr(err, ERRBIT_OFFSETS);
+  } else {
+    const int64_t b = off[r];
+    e = off[r + 1];
+    const int64_t a = first_true(ts, b, e, [&](int64_t v) { return v > t0; });
+    lo = a > b ? a - 1 : b;
+    hi = first_true(ts, b, e, [&](int64_t v) { return v >= t1; });
+  }
+  bounds[2 * i] = v2ll{lo, hi};
+  bounds[2 * i + 1] = v2ll{e, 0};
+}
+
+// One workgroup per selected rank (grid-stride over the selection) over the
+// events window_bounds found.  LDSH: an LDS histogram over the N nodes
+// (N <= 8192) flushed once; otherwise 64-bit atomics on the output.  Integer
+// sums: the order of the atomics does not matter.
 template <bool LDSH>
-__global__ __launch_bounds__(WT) void window_excl(const int64_t *__restrict__ off,
-                                                 const int64_t *__restrict__ ts,
-                                                 const int32_t *__restrict__ ctx, int64_t R,
-                                                 int64_t E, const int32_t *__restrict__ ids,
-                                                 int64_t n_sel,
-                                                 int N, int64_t t0, int64_t t1,
-                                                 int64_t *__restrict__ excl, uint32_t *err) {
+__global__ __launch_bounds__(WWT) void window_excl(const int64_t *__restrict__ ts,
+                                                 const int32_t *__restrict__ ctx, int64_t E,
+                                                 const v2ll *__restrict__ bounds, int64_t n_sel, int N,
+                                                 int64_t t0, int64_t t1, int64_t *__restrict__ excl,
+                                                 uint32_t *err) {
   extern __shared__ uint64_t hist[];  // [N] when LDSH
-  __shared__ int64_t range[3];
   if (LDSH) {
-    for (int v = threadIdx.x; v < N; v += WT) hist[v] = 0;
+    for (int v = threadIdx.x; v < N; v += WWT) hist[v] = 0;
   }
   __syncthreads();
   for (int64_t i = blockIdx.x; i < n_sel; i += gridDim.x) {
-    if (threadIdx.x < 64) {  // wave 0
-      const int64_t r = ids ? (int64_t)ids[i] : i;
-      int64_t lo = 0, hi = 0, e = 0;
-      if (r < 0 || r >= R || off[r] < 0 || off[r + 1] < off[r] || off[r + 1] > E) {
-        if (threadIdx.x == 0) atomicOr(err, ERRBIT_OFFSETS);
-      } else {
-        const int64_t b = off[r];
-        e = off[r + 1];
-        const int64_t a = wave_search(ts, b, e, [&](int64_t v) { return v > t0; });
-        lo = a > b ? a - 1 : b;
-        hi = wave_search(ts, b, e, [&](int64_t v) { return v >= t1; });
-      }
-      if (threadIdx.x == 0) {
-        range[0] = lo;
-        range[1] = hi;
-        range[2] = e;
-      }
-    }
-    __syncthreads();
-    const int64_t lo = range[0], hi = range[1], e = range[2];
-    visit_events<WT>(ts, ctx, E, lo, hi, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
+    const v2ll b0 = bounds[2 * i], b1 = bounds[2 * i + 1];
+    const int64_t lo = b0.x, hi = b0.y, e = b1.x;
+    visit_events<WWT, 2>(ts, ctx, E, lo, hi, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
       if (f < s) atomicOr(err, ERRBIT_UNSORTED);
       const int64_t a = s > t0 ? s : t0;
       const int64_t z = f < t1 ? f : t1;
@@ -139,10 +150,10 @@ __global__ __launch_bounds__(WT) void window_excl(const int64_t *__restrict__ of
         }
       }
     });
-    __syncthreads();
   }
   if (LDSH) {
-    for (int v = threadIdx.x; v < N; v += WT)
+    __syncthreads();
+    for (int v = threadIdx.x; v < N; v += WWT)
       if (hist[v]) atomicAdd((unsigned long long *)&excl[v], (unsigned long long)hist[v]);
   }
 }
@@ -221,7 +232,7 @@ __global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__r
     if (one_pass) {
       for (int i = t; i < nw; i += SPT) bm[i] = 0;
       __syncthreads();
-      visit_events<SPT>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
+      visit_events<SPT, 1>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
         const int64_t d = f - s;
         if (d < 0) atomicOr(err, ERRBIT_UNSORTED);
         if (c < 0 || c >= N) atomicOr(err, ERRBIT_CTX);
@@ -247,7 +258,7 @@ __global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__r
       if (total <= SPACC) {  // uniform
         for (int i = t; i < total; i += SPT) acc[i] = 0;
         __syncthreads();
-        visit_events<SPT>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
+        visit_events<SPT, 1>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
           const int64_t d = f - s;
           if (c >= 0 && c < N && d > 0) {
             const int w = c >> 5;
@@ -290,7 +301,7 @@ __global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__r
         const int lo = ch * SPC;
         for (int i = t; i < SPC; i += SPT) hist[i] = 0;
         __syncthreads();
-        visit_events<SPT>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
+        visit_events<SPT, 1>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
           const int64_t d = f - s;
           if (d < 0) atomicOr(err, ERRBIT_UNSORTED);
           if (c < 0 || c >= N) {
@@ -332,7 +343,10 @@ int grid_w(int64_t n, int cus, int per_cu) {
 
 }  // namespace
 
-size_t window_ws_bytes(int N) { return subtree_sums_ws_bytes(N); }
+// The subtree-sum workspace, then 32 bytes of event bounds per selected rank.
+size_t window_ws_bytes(int N, int64_t n_sel) {
+  return ((subtree_sums_ws_bytes(N) + 255) & ~(size_t)255) + (size_t)(n_sel > 0 ? n_sel : 0) * 32;
+}
 
 hipError_t launch_window_profile(const int64_t *off, const int64_t *ts, const int32_t *ctx, int64_t R,
                                  int64_t E, const int32_t *ids, int64_t n_sel, int N, const int2 *tin_tout,
@@ -340,6 +354,10 @@ hipError_t launch_window_profile(const int64_t *off, const int64_t *ts, const in
                                  uint32_t *err, int cus, hipStream_t s) {
   zero_i64<<<grid_w((N + WT - 1) / WT, cus, 4), WT, 0, s>>>(excl, N);
   if (n_sel > 0) {
+    v2ll *bounds = reinterpret_cast<v2ll *>(static_cast<char *>(ws) +
+                                            ((subtree_sums_ws_bytes(N) + 255) & ~(size_t)255));
+    window_bounds<<<(unsigned)((n_sel + WT - 1) / WT), WT, 0, s>>>(off, ts, R, E, ids, n_sel, t0, t1,
+                                                                   bounds, err);
     if (N <= MAX_NODES_ATTR) {
       static bool attr = false;
       if (!attr) {
@@ -347,11 +365,11 @@ hipError_t launch_window_profile(const int64_t *off, const int64_t *ts, const in
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
         attr = true;
       }
-      window_excl<true><<<grid_w(n_sel, cus, 4), WT, (size_t)N * 8, s>>>(off, ts, ctx, R, E, ids,
-                                                                        n_sel, N, t0, t1, excl, err);
+      window_excl<true><<<grid_w(n_sel, cus, 4), WWT, (size_t)N * 8, s>>>(ts, ctx, E, bounds, n_sel, N,
+                                                                         t0, t1, excl, err);
     } else {
-      window_excl<false><<<grid_w(n_sel, cus, 8), WT, 0, s>>>(off, ts, ctx, R, E, ids, n_sel, N, t0,
-                                                             t1, excl, err);
+      window_excl<false><<<grid_w(n_sel, cus, 4), WWT, 0, s>>>(ts, ctx, E, bounds, n_sel, N, t0, t1,
+                                                              excl, err);
     }
   }
   hipError_t e = hipGetLastError();

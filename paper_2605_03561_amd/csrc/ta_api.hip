@@ -1005,7 +1005,7 @@ ta_status ta_window_profile(ta_handle h, const ta_traces *t, const int32_t *rank
     if (p && !aligned16(p)) return fail(h, TA_ERR_INVALID_ARG, "array not 16-byte aligned");
   const int64_t n = rank_ids ? n_sel : t->n_ranks;
   DeviceGuard dg(h->device);
-  st = ensure_ws(h, ta::window_ws_bytes(h->N));
+  st = ensure_ws(h, ta::window_ws_bytes(h->N, n));
   if (st) return st;
   hipError_t e = ta::launch_window_profile(t->offsets, t->ts, t->ctx, t->n_ranks, t->n_events, rank_ids,
                                            n, h->N,

@@ -165,7 +165,7 @@ hipError_t launch_sparse_profiles(const int64_t *off, const int64_t *ts, const i
                                   int64_t E, int N, int64_t *counts, int32_t *ids, int64_t *vals, uint32_t *err,
                                   int cus, hipStream_t s);
 // Time-window profile (k_window.hip).
-size_t window_ws_bytes(int N);
+size_t window_ws_bytes(int N, int64_t n_sel);
 hipError_t launch_window_profile(const int64_t *off, const int64_t *ts, const int32_t *ctx, int64_t R,
                                  int64_t E, const int32_t *ids, int64_t n_sel, int N, const int2 *tin_tout,
                                  int64_t t0, int64_t t1, int64_t *excl, int64_t *incl, void *ws,
