@@ -75,11 +75,28 @@ struct AeLds {
   int valid[TR];
 };
 
+// The bf16 weights (16-byte loads, all of a thread's loads issued before its
+// first LDS store: one round trip, not one per word) and the FP32 biases.
 __device__ void stage_weights(AeLds &L, const uint16_t *wb, const float *w) {
-  const uint32_t *src = reinterpret_cast<const uint32_t *>(wb);
-  uint32_t *dst = reinterpret_cast<uint32_t *>(L.W);
-  for (int k = threadIdx.x; k < AE_NW / 2; k += AT) dst[k] = src[k];
-  for (int k = threadIdx.x; k < AE_NP - AE_NW; k += AT) L.b[k] = w[AE_NW + k];
+  constexpr int NV = AE_NW * 2 / 16;     // 16-byte words of bf16 weights
+  constexpr int PER = NV / AT;
+  constexpr int NB = AE_NP - AE_NW;      // biases
+  constexpr int PB = (NB + AT - 1) / AT;
+  static_assert(NV % AT == 0, "the weights are staged in whole steps of the workgroup");
+  const int t = threadIdx.x;
+  const uint4 *src = reinterpret_cast<const uint4 *>(wb);
+  uint4 *dst = reinterpret_cast<uint4 *>(L.W);
+  uint4 v[PER];
+  float bv[PB];
+#pragma unroll
+  for (int u = 0; u < PER; u++) v[u] = src[u * AT + t];
+#pragma unroll
+  for (int u = 0; u < PB; u++) bv[u] = u * AT + t < NB ? w[AE_NW + u * AT + t] : 0.f;
+#pragma unroll
+  for (int u = 0; u < PER; u++) dst[u * AT + t] = v[u];
+#pragma unroll
+  for (int u = 0; u < PB; u++)
+    if (u * AT + t < NB) L.b[u * AT + t] = bv[u];
 }
 
 // Forward through the four layers for the tile in L.Xb.  Hidden activations
@@ -420,33 +437,59 @@ __global__ __launch_bounds__(256) void ae_grad_f32_kernel(const float *__restric
   if (t == 0) P[AE_NP] = (float)ls;
 }
 
+// Entry p of the workgroup partials summed in workgroup order; the loads go
+// out 16 at a time (one round trip per 16 partials instead of one each), the
+// additions stay in order.
+__device__ inline float sum_partials(const float *part, int nwg, int p) {
+  constexpr int U = 16;
+  float g = 0.f;
+  for (int k0 = 0; k0 < nwg; k0 += U) {
+    float pv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) pv[u] = k0 + u < nwg ? part[(int64_t)(k0 + u) * (AE_NP + 1) + p] : 0.f;
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (k0 + u < nwg) g += pv[u];
+  }
+  return g;
+}
+
+// Parameter p: the sum of the workgroup partials in workgroup order, then
+// optionally one Adam step.
+__device__ inline void adam_param(int p, const float *part, int nwg, float *w, uint16_t *wb, float *m,
+                                  float *v, float lr, float bc1, float bc2, int update,
+                                  float *grad_out) {
+  const float g = sum_partials(part, nwg, p);
+  if (grad_out) grad_out[p] = g;
+  if (update) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float mm = b1 * m[p] + (1.f - b1) * g;
+    const float vv = b2 * v[p] + (1.f - b2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float wn = w[p] - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+    w[p] = wn;
+    if (p < AE_NW) wb[p] = f2bf(wn);
+  }
+}
+
+__device__ inline float loss_sum(const float *part, int nwg) { return sum_partials(part, nwg, AE_NP); }
+
 // Sum the workgroup partials in workgroup order; optionally take one Adam step.
+// With epoch_loss, also epoch_loss[0] += loss * lfrac (the step's share of the
+// epoch's rows), in the kernel rather than a launch of its own.
 __global__ __launch_bounds__(256) void ae_adam(const float *part, int nwg, float *w, uint16_t *wb,
                                                float *m, float *v, float lr, float bc1, float bc2,
                                                int update, float *grad_out, float *loss_out,
-                                               float loss_scale) {
+                                               float loss_scale, float *epoch_loss, float lfrac) {
   const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p < AE_NP) {
-    float g = 0.f;
-    for (int k = 0; k < nwg; k++) g += part[(int64_t)k * (AE_NP + 1) + p];
-    if (grad_out) grad_out[p] = g;
-    if (update) {
-      const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-      const float mm = b1 * m[p] + (1.f - b1) * g;
-      const float vv = b2 * v[p] + (1.f - b2) * g * g;
-      m[p] = mm;
-      v[p] = vv;
-      const float wn = w[p] - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
-      w[p] = wn;
-      if (p < AE_NW) wb[p] = f2bf(wn);
-    }
-  }
+  if (p < AE_NP) adam_param(p, part, nwg, w, wb, m, v, lr, bc1, bc2, update, grad_out);
   if (p == 0 && loss_out) {
-    float s = 0.f;
-    for (int k = 0; k < nwg; k++) s += part[(int64_t)k * (AE_NP + 1) + AE_NP];
-    loss_out[0] = s * loss_scale;
+    loss_out[0] = loss_sum(part, nwg) * loss_scale;
+    if (epoch_loss) epoch_loss[0] += loss_out[0] * lfrac;
   }
 }
+
 
 // ---------------------------------------------------------------------------
 // Initialisation: Xavier-uniform weights from SplitMix64 counter draws.
@@ -1219,7 +1262,8 @@ void allow_lds(K k) {
 
 hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, int batch,
                           uint64_t a, uint64_t c, float lr, bool update, float noise_sd,
-                          uint64_t noise_key, hipStream_t st, float *grad_out, float *loss_out) {
+                          uint64_t noise_key, hipStream_t st, float *grad_out, float *loss_out,
+                          float *epoch_loss, float lfrac) {
   const int64_t k_end = k0 + batch < n ? k0 + batch : n;
   const int64_t bv = k_end - k0;
   if (bv <= 0) return hipErrorInvalidValue;
@@ -1235,7 +1279,7 @@ hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, 
   }
   hipLaunchKernelGGL(ae_adam, dim3((AE_NP + 255) / 256), dim3(256), 0, st, s.part, AE_WG, s.w, s.wb,
                      s.m, s.v, lr, bc1, bc2, update ? 1 : 0, grad_out, loss_out ? loss_out : s.loss,
-                     1.0f / (float)(bv * AE_IN));
+                     1.0f / (float)(bv * AE_IN), epoch_loss, lfrac);
   return hipGetLastError();
 }
 
@@ -1247,7 +1291,7 @@ hipError_t launch_ae_grad_f32(AeState &s, const float *rows, int64_t n, float no
                      noise_key, s.w, s.part);
   hipLaunchKernelGGL(ae_adam, dim3((AE_NP + 255) / 256), dim3(256), 0, st, s.part, AE_WG, s.w, s.wb,
                      s.m, s.v, 0.f, 1.f, 1.f, 0, grad_out, loss_out ? loss_out : s.loss,
-                     1.0f / (float)(n * AE_IN));
+                     1.0f / (float)(n * AE_IN), (float *)nullptr, 0.f);
   return hipGetLastError();
 }
 

@@ -61,9 +61,11 @@ hipError_t launch_ae_rows(const AeState &s, const int64_t *T, int64_t R, int I, 
 size_t ae_rows_ws_bytes(int64_t R);
 // One optimiser step on rows perm(k), k in [k0, k0 + batch), perm(k) = (a*k + c) mod n;
 // noise_sd > 0: denoising step (inputs x + noise_sd * N(0,1) drawn under noise_key).
+// With epoch_loss, also epoch_loss[0] += (the step's loss) * lfrac.
 hipError_t launch_ae_step(AeState &s, const float *rows, int64_t n, int64_t k0, int batch,
                           uint64_t a, uint64_t c, float lr, bool update, float noise_sd,
-                          uint64_t noise_key, hipStream_t st, float *grad_out, float *loss_out);
+                          uint64_t noise_key, hipStream_t st, float *grad_out, float *loss_out,
+                          float *epoch_loss = nullptr, float lfrac = 0.f);
 // The same gradient and mean loss over rows[0..n) in FP32 throughout (a debug
 // reference for the matrix-core path; no update).
 hipError_t launch_ae_grad_f32(AeState &s, const float *rows, int64_t n, float noise_sd,

@@ -1648,8 +1648,6 @@ __global__ void fill_f32(float *p, int n, float v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void add_loss(float *dst, const float *src, float w) { dst[0] += src[0] * w; }
-
 __global__ void f64_to_f32(const double *a, float *b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (float)a[i];
@@ -1775,14 +1773,13 @@ ta_status ta_ae_train(ta_handle h, const float *rows, int64_t n_rows, int32_t ep
     }
     for (int64_t k0 = 0; k0 < n_rows; k0 += batch) {
       const uint64_t nkey = splitmix(ns);
+      const int64_t bv = std::min<int64_t>(batch, n_rows - k0);
+      // two launches per step: the gradient partials, then their sum, the
+      // Adam step and the epoch-loss add
       hipError_t e = ta::launch_ae_step(h->ae, rows, n_rows, k0, batch, a, c, lr, true, input_noise,
-                                        nkey, s, nullptr, nullptr);
+                                        nkey, s, nullptr, nullptr, epoch_loss ? epoch_loss + ep : nullptr,
+                                        (float)((double)bv / (double)n_rows));
       if (e != hipSuccess) return hipfail(h, e, "ae step");
-      if (epoch_loss) {
-        const int64_t bv = std::min<int64_t>(batch, n_rows - k0);
-        hipLaunchKernelGGL(add_loss, dim3(1), dim3(1), 0, s, epoch_loss + ep, h->ae.loss,
-                           (float)((double)bv / (double)n_rows));
-      }
     }
   }
   const hipError_t le = hipGetLastError();
