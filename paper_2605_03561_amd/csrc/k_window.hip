@@ -62,11 +62,14 @@ __device__ inline void visit_events(const int64_t *__restrict__ ts, const int32_
   };
   constexpr int64_t STEP = 4 * (int64_t)NT;
   for (int64_t k0 = (lo & ~(int64_t)3) + 4 * (int64_t)threadIdx.x; k0 < hi; k0 += DEPTH * STEP) {
-    // every load is in bounds of the arrays (load_quad guards E); the later
-    // steps' events may lie past hi, where visit skips them
+    // every load is in bounds of the arrays (load_quad guards E); a later
+    // step that starts at or past hi loads nothing (visit skips its events)
     EvQuad q[DEPTH];
 #pragma unroll
-    for (int d = 0; d < DEPTH; d++) q[d] = load_quad(ts, ctx, E, k0 + d * STEP, e);
+    for (int d = 0; d < DEPTH; d++) {
+      q[d] = EvQuad{};
+      if (d == 0 || k0 + d * STEP < hi) q[d] = load_quad(ts, ctx, E, k0 + d * STEP, e);
+    }
 #pragma unroll
     for (int d = 0; d < DEPTH; d++) visit(q[d], k0 + d * STEP);
   }
