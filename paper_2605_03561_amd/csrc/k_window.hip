@@ -195,11 +195,13 @@ __device__ inline int block_excl_scan_i32(int v, int *wsum, int *total) {
 }
 
 // One workgroup per rank (grid-stride).  Trees of more than SPC nodes and at
-// most SPBW * 32: a pass over the events marks the nodes they reach with a
-// positive duration in an LDS bit mask; a workgroup scan of the mask's word
-// counts gives each reached node its output index (ascending id); a second
-// pass adds the durations into an LDS accumulator at those indices (exact
-// 64-bit atomics).  Otherwise, or when a rank reaches more than SPACC nodes:
+// most SPBW * 32: a pass over the events' contexts (4 bytes per event) marks
+// the nodes they reach in an LDS bit mask; a workgroup scan of the mask's word
+// counts gives each reached node an accumulator index (ascending id); a
+// second pass adds the durations into the LDS accumulator at those indices
+// (exact 64-bit atomics), and the nodes with a positive total are written in
+// ascending id (a second scan of the per-thread counts of those).  Otherwise,
+// or when a rank reaches more than SPACC nodes:
 // for each chunk of SPC node ids that the events reach, an LDS histogram of
 // the chunk, then its non-zero bins in ascending id, compacted by a workgroup
 // scan and appended after the previous chunks'.  Output goes to the rank's own
@@ -235,12 +237,28 @@ __global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__r
     if (one_pass) {
       for (int i = t; i < nw; i += SPT) bm[i] = 0;
       __syncthreads();
-      visit_events<SPT, 1>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
-        const int64_t d = f - s;
-        if (d < 0) atomicOr(err, ERRBIT_UNSORTED);
-        if (c < 0 || c >= N) atomicOr(err, ERRBIT_CTX);
-        else if (d > 0) atomicOr(&bm[c >> 5], 1u << (c & 31));
-      });
+      // the nodes the rank's events reach, from the contexts alone (4 bytes
+      // per event; the durations are read once, by the accumulating pass)
+      for (int64_t k0 = (b & ~(int64_t)3) + 4 * (int64_t)t; k0 < e; k0 += 4 * (int64_t)SPT) {
+        int32_t c4[4];
+        if (k0 + 4 <= E) {
+          const v4i q = *reinterpret_cast<const v4i *>(ctx + k0);
+          c4[0] = q.x;
+          c4[1] = q.y;
+          c4[2] = q.z;
+          c4[3] = q.w;
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; u++) c4[u] = k0 + u < E ? ctx[k0 + u] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          if (k0 + u < b || k0 + u >= e) continue;
+          const int32_t c = c4[u];
+          if (c < 0 || c >= N) atomicOr(err, ERRBIT_CTX);
+          else atomicOr(&bm[c >> 5], 1u << (c & 31));
+        }
+      }
       __syncthreads();
       uint32_t wv[SPBT];
       int own = 0;
@@ -263,6 +281,7 @@ __global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__r
         __syncthreads();
         visit_events<SPT, 1>(ts, ctx, E, b, e, e, [&](int64_t, int64_t s, int64_t f, int32_t c) {
           const int64_t d = f - s;
+          if (d < 0) atomicOr(err, ERRBIT_UNSORTED);
           if (c >= 0 && c < N && d > 0) {
             const int w = c >> 5;
             const int idx = (int)pre[w] + __popc(bm[w] & ((1u << (c & 31)) - 1u));
@@ -270,6 +289,18 @@ __global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__r
           }
         });
         __syncthreads();
+        // the reached nodes with a positive total, in ascending id: a node
+        // reached only by zero durations is marked but not written
+        int nz = 0;
+#pragma unroll
+        for (int u = 0; u < SPBT; u++) {
+          const int w = t * SPBT + u;
+          if (w >= nw) continue;
+          const int p0 = (int)pre[w];
+          for (int q = 0; q < __popc(wv[u]); q++) nz += acc[p0 + q] != 0 ? 1 : 0;
+        }
+        int nz_total;
+        int o = block_excl_scan_i32(nz, wsum, &nz_total);
 #pragma unroll
         for (int u = 0; u < SPBT; u++) {
           const int w = t * SPBT + u;
@@ -279,12 +310,15 @@ __global__ __launch_bounds__(SPT) void sparse_profiles_kernel(const int64_t *__r
           while (m) {
             const int j = __ffs(m) - 1;
             m &= m - 1u;
-            ids[b + p] = w * 32 + j;
-            vals[b + p] = (int64_t)acc[p];
+            if (acc[p] != 0) {
+              ids[b + o] = w * 32 + j;
+              vals[b + o] = (int64_t)acc[p];
+              o++;
+            }
             p++;
           }
         }
-        base = total;
+        base = nz_total;
         done = true;
       }
       __syncthreads();

@@ -96,3 +96,40 @@ def test_sparse_profiles_match_oracle(ta, h, oracle, seed, n_nodes, min_len):
         b = int(offsets[r])
         assert np.array_equal(gi[b:b + cnt[r]], ids[b:b + cnt[r]])
         assert np.array_equal(ge[b:b + cnt[r]], ex[b:b + cnt[r]])
+
+
+@pytest.mark.parametrize("n_nodes", [20000, 131072])
+def test_sparse_profiles_zero_durations(ta, h, oracle, n_nodes):
+    """Ranks whose events repeat timestamps, so some nodes are reached only by
+    zero durations: the one-pass path (trees of 8,193..131,072 nodes) marks
+    every node a context reaches but writes only those with a positive total,
+    in ascending id, exactly as the oracle lists them."""
+    print(f"sparse zero durations N={n_nodes}", flush=True)
+    rng = np.random.default_rng(n_nodes)
+    parent = np.concatenate([[-1], rng.integers(0, np.arange(1, n_nodes))]).astype(np.int32)
+    lens = np.array([0, 1, 2, 3000, 7777, 40], np.int64)
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    E = int(offsets[-1])
+    steps = rng.integers(0, 3, E) * rng.integers(1, 50, E)     # about a third are zero
+    ts = np.zeros(E, np.int64)
+    for r in range(len(lens)):
+        a, b = int(offsets[r]), int(offsets[r + 1])
+        ts[a:b] = 1000 + np.cumsum(steps[a:b])
+    ctx = rng.integers(0, n_nodes, E).astype(np.int32)
+    ctx[offsets[4]:offsets[4] + 500] = 17                       # a node hit many times
+    h.set_tree(parent)
+    tr = ta.DeviceTraces(offsets, ts, ctx)
+    st, cnt, ids, ex = oracle.sparse_profiles(offsets, ts, ctx, n_nodes)
+    assert st == 0
+    gc, gi, ge = h.sparse_profiles(tr)
+    h.sync_status()
+    gc, gi, ge = gc.cpu().numpy(), gi.cpu().numpy(), ge.cpu().numpy()
+    assert np.array_equal(gc, cnt)
+    for r in range(len(lens)):
+        b = int(offsets[r])
+        assert np.array_equal(gi[b:b + cnt[r]], ids[b:b + cnt[r]])
+        assert np.array_equal(ge[b:b + cnt[r]], ex[b:b + cnt[r]])
+    # some reached nodes have a zero total, so the one-pass path skipped them
+    reached = sum(len(set(ctx[offsets[r]:offsets[r + 1]].tolist())) for r in range(len(lens)))
+    assert reached > cnt.sum()
+
