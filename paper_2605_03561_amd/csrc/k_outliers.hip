@@ -841,14 +841,13 @@ __global__ __launch_bounds__(256) void score_cols(const int64_t *__restrict__ Tt
 // ----------------------------------------------------------------------------
 // Row-major path for the robust FULL scan over long columns (no transpose).
 //   rm_sample    MS cells of every column at fixed ranks (MS / 2 chunks of two
-//                consecutive ranks, evenly spread), column-major Smp[IG][MS];
-//                also clears the column cursors
+//                consecutive ranks, evenly spread), column-major Smp[IG][MS]
 //   rm_brackets  per column, the sample's order statistics around its middle
-//   rm_pass      one streaming pass over the row-major tensor in 64 x 64 tiles
-//                (LDS): per column and rank group, the counts below / equal to
-//                the bracket ends (and the imbalance partials, or the sum of
-//                deviations); the bracket interiors are appended to a scratch
-//                region per column (one cursor atomic per column and tile)
+//   rm_pass      one streaming pass over the row-major tensor: per column and
+//                chunk of RCH ranks, the counts below / equal to the bracket
+//                ends (and the imbalance partials, or the sum of deviations);
+//                the bracket interior of each (chunk, column) goes to its own
+//                scratch slot
 //   rm_select    per column, exact selection over the compacted interior, or
 //                over a gathered copy of the whole column when the bracket
 //                misses the middle or the interior overflows the region; the
@@ -923,10 +922,10 @@ __device__ int load_sample(ColSelLds &L, const int64_t *__restrict__ s, int64_t 
   return (int)L.ns;
 }
 
-__global__ __launch_bounds__(CS) void rm_brackets(const int64_t *__restrict__ smp, int IG,
+__global__ __launch_bounds__(CS) void rm_brackets(const int64_t *__restrict__ smp, int c_lo,
                                                   int64_t *qa, int64_t *qb) {
   __shared__ ColSelLds L;
-  const int c = blockIdx.x;
+  const int c = c_lo + (int)blockIdx.x;
   for (int j = threadIdx.x; j < NHC * NB; j += CS) (&L.hist[0][0])[j] = 0;
   const int m = load_sample<false>(L, smp + (int64_t)c * MS, 0);
   int64_t a, b;
@@ -1036,12 +1035,12 @@ struct RmCol {
 // load its last row (in bounds) and are not counted.
 template <bool MAD, bool STATS, bool VEC, int CPL>
 __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, int64_t R, int IG, int G,
-                                               const int32_t *it, RmBr br, int64_t *__restrict__ scr,
-                                               RmPart pp, ColPartials ps) {
-  const int ca = ((int)blockIdx.x * 256 + (int)threadIdx.x) * CPL;
-  if (ca >= IG) return;
+                                               const int32_t *it, int c_lo, int c_hi, RmBr br,
+                                               int64_t *__restrict__ scr, RmPart pp, ColPartials ps) {
+  const int ca = c_lo + ((int)blockIdx.x * 256 + (int)threadIdx.x) * CPL;
+  if (ca >= c_hi) return;
   const int64_t ng = gridDim.y, ch = blockIdx.y;
-  const bool two = CPL == 2 && ca + 1 < IG;
+  const bool two = CPL == 2 && ca + 1 < c_hi;
   const int ia = ca / G, ib = (ca + 1) / G;
   RmCol<MAD, STATS> c0, c1;
   c0.a = br.a[ca];
@@ -1129,15 +1128,15 @@ constexpr int SU = 4;  // chunk slots read together by a wave
 template <bool MAD>
 __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
     const int64_t *__restrict__ T, int64_t R, int IG, int G, const int32_t *it,
-    const int64_t *__restrict__ smp, int ng, RmPart pp, RmBr br, const int64_t *__restrict__ scr,
-    int64_t *__restrict__ slots, RmOut ro, ColSel out) {
+    const int64_t *__restrict__ smp, int ng, int c_lo, int c_hi, RmPart pp, RmBr br,
+    const int64_t *__restrict__ scr, int64_t *__restrict__ slots, RmOut ro, ColSel out) {
   __shared__ ColSelLds L;
   __shared__ int32_t segn[SEG_MAX];
   const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
   const int64_t Rp = pad_ranks(R);
   int64_t *slot = slots + (int64_t)blockIdx.x * Rp;
   for (int j = t; j < NHC * NB; j += CS) (&L.hist[0][0])[j] = 0;
-  for (int c = blockIdx.x; c < IG; c += gridDim.x) {
+  for (int c = c_lo + (int)blockIdx.x; c < c_hi; c += gridDim.x) {
     // the chunk partials, summed; the chunk slots' fill counts into LDS
     int64_t sums[5] = {0, 0, 0, 0, 0};
     for (int g = t; g < ng; g += CS) {
@@ -1257,11 +1256,15 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
 // m(r,g) = (1/n_r) sum_{i < n_r} z(r,i,g) (ascending i) from the row-major
 // tensor, written [G][R]; a wave = SRW consecutive ranks x 64 regions (lane =
 // region), so each row read is contiguous and the column parameters are read
-// once per SRW ranks.
+// once per SRW ranks.  One launch adds the iterations [i_lo, i_hi): a launch
+// with i_lo > 0 continues the running sums that the previous one left in m_t
+// (the same additions in the same order), and the launch that reaches I
+// divides by n_r.
 constexpr int SRW = 8;
 
 __global__ __launch_bounds__(256) void score_rows(const int64_t *__restrict__ T, int64_t R, int I, int G,
-                                                  const int32_t *it, ColSel cs, double *m_t) {
+                                                  const int32_t *it, int i_lo, int i_hi, ColSel cs,
+                                                  double *m_t) {
   const int lane = threadIdx.x & 63;
   const int gbn = (G + 63) / 64;
   const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1284,8 +1287,9 @@ __global__ __launch_bounds__(256) void score_rows(const int64_t *__restrict__ T,
   }
   double acc[SRW];
 #pragma unroll
-  for (int q = 0; q < SRW; q++) acc[q] = 0.0;
+  for (int q = 0; q < SRW; q++) acc[q] = (i_lo > 0 && gl && r0 + q < R) ? m_t[(int64_t)g * R + r0 + q] : 0.0;
   const int gg = gl ? g : 0;
+  const int ie = nmax < i_hi ? nmax : i_hi;
   const int64_t *base = T + r0 * IG + gg;
   // iteration i's cells and column parameters; those of i + 1 are loaded
   // before i is scored
@@ -1300,22 +1304,23 @@ __global__ __launch_bounds__(256) void score_rows(const int64_t *__restrict__ T,
     zc = cs.zc[c];
     zd = cs.zd[c];
   };
-  if (nmax > 0) load(0);
-  for (int i = 0; i < nmax; i++) {
+  if (i_lo < ie) load(i_lo);
+  for (int i = i_lo; i < ie; i++) {
     int64_t xc[SRW];
 #pragma unroll
     for (int q = 0; q < SRW; q++) xc[q] = x[q];
     const int64_t m2 = med2;
     const double a = zc, d = zd;
-    if (i + 1 < nmax) load(i + 1);
+    if (i + 1 < ie) load(i + 1);
 #pragma unroll
     for (int q = 0; q < SRW; q++)
       if (i < ni[q]) acc[q] += ((double)(2 * xc[q] - m2) * a) / d;
   }
   if (gl) {
+    const bool fin = i_hi >= I;
 #pragma unroll
     for (int q = 0; q < SRW; q++)
-      if (r0 + q < R) m_t[(int64_t)g * R + r0 + q] = ni[q] > 0 ? acc[q] / (double)ni[q] : 0.0;
+      if (r0 + q < R) m_t[(int64_t)g * R + r0 + q] = !fin ? acc[q] : (ni[q] > 0 ? acc[q] / (double)ni[q] : 0.0);
   }
 }
 
@@ -2015,20 +2020,131 @@ OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
   return w;
 }
 
-// rm_pass with CPL columns per lane (16-byte row loads for two columns when
-// the row length is even).
+// rm_pass over the columns [c_lo, c_hi) with CPL columns per lane (16-byte
+// row loads for two columns when the row length and c_lo are even).
 constexpr int RM_CPL_STATS = 1, RM_CPL_MAD = 2, RM_CPL_COUNT = 2;
 template <bool MAD, bool STATS>
-void launch_rm_pass(int ng, const OutArgs &a, int IG, RmBr br, int64_t *scr, RmPart rp,
-                    hipStream_t s) {
+void launch_rm_pass(int ng, const OutArgs &a, int IG, int c_lo, int c_hi, RmBr br, int64_t *scr,
+                    RmPart rp, hipStream_t s) {
   constexpr int CPL = STATS ? RM_CPL_STATS : (MAD ? RM_CPL_MAD : RM_CPL_COUNT);
-  const dim3 grid((unsigned)((IG + 256 * CPL - 1) / (256 * CPL)), (unsigned)ng);
-  if (CPL == 2 && (IG & 1) == 0)
+  const dim3 grid((unsigned)((c_hi - c_lo + 256 * CPL - 1) / (256 * CPL)), (unsigned)ng);
+  if (CPL == 2 && (IG & 1) == 0 && (c_lo & 1) == 0)
     hipLaunchKernelGGL((rm_pass<MAD, STATS, true, CPL>), grid, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it,
-                       br, scr, rp, a.stats);
+                       c_lo, c_hi, br, scr, rp, a.stats);
   else
     hipLaunchKernelGGL((rm_pass<MAD, STATS, false, CPL>), grid, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it,
-                       br, scr, rp, a.stats);
+                       c_lo, c_hi, br, scr, rp, a.stats);
+}
+
+// The row-major robust FULL scan.  Serially: sample, brackets, median pass,
+// median selection, MAD pass, MAD selection, row scores.  With a side stream
+// the columns are split at iteration ih (halves A = [0, ih*G) and B =
+// [ih*G, IG)): the passes stay in order on the launch stream and the
+// latency-bound selections (and B's brackets) run on the side stream, each
+// beside the next pass:
+//   launch: sample | br A | pass med A | pass med B | pass MAD A | pass MAD B | score A | score B
+//   side:                 | br B       | select A   | select B   | select A   | select B
+// Every half reads and writes only its own columns' entries of the shared
+// buffers (partials, interior slots, brackets, results); the selections are
+// serialised on the side stream, so its gather slots are never shared.  The
+// row scores run as two launches over the iterations of A and of B (the second
+// continues the first's running sums), so score A overlaps B's MAD selection.
+hipError_t scan_row_major(const OutArgs &a, const OWs &w, int IG, hipStream_t s) {
+  const int ng = transpose_groups_of(a.R);
+  const unsigned strips = (unsigned)((IG + TT - 1) / TT);
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int sel_max = std::min(SEL_GRID_MAX, SEL_WGS_PER_CU * cus);
+  const RmBr bm{w.qa, w.qb, nullptr};
+  const RmBr bd{w.da, w.db, w.cs.med2};
+  const RmOut ro{w.da, w.db};
+  auto brackets = [&](int lo, int hi, hipStream_t q) {
+    hipLaunchKernelGGL(rm_brackets, dim3((unsigned)(hi - lo)), dim3(CS), 0, q, (const int64_t *)w.smp, lo,
+                       w.qa, w.qb);
+  };
+  auto select = [&](bool mad, int lo, int hi, hipStream_t q) {
+    const int grid = std::min(hi - lo, sel_max);
+    if (mad)
+      hipLaunchKernelGGL(rm_select<true>, dim3(grid), dim3(CS), 0, q, a.T, a.R, IG, a.G, a.it,
+                         (const int64_t *)w.smp, ng, lo, hi, w.rp, bd, (const int64_t *)w.scr, w.slots, ro,
+                         w.cs);
+    else
+      hipLaunchKernelGGL(rm_select<false>, dim3(grid), dim3(CS), 0, q, a.T, a.R, IG, a.G, a.it,
+                         (const int64_t *)w.smp, ng, lo, hi, w.rp, bm, (const int64_t *)w.scr, w.slots, ro,
+                         w.cs);
+  };
+  auto med_pass = [&](int lo, int hi) {
+    if (a.stats.rc > 0)
+      launch_rm_pass<false, true>(ng, a, IG, lo, hi, bm, w.scr, w.rp, s);
+    else
+      launch_rm_pass<false, false>(ng, a, IG, lo, hi, bm, w.scr, w.rp, s);
+  };
+  const int64_t waves = ((a.R + SRW - 1) / SRW) * ((a.G + 63) / 64);
+  const dim3 sgrid((unsigned)((waves + 3) / 4));
+  auto score = [&](int i_lo, int i_hi) {
+    hipLaunchKernelGGL(score_rows, sgrid, dim3(256), 0, s, a.T, a.R, a.I, a.G, a.it, i_lo, i_hi, w.cs, w.m_t);
+  };
+  hipLaunchKernelGGL(rm_sample, dim3(MS / TT, strips), dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, w.smp);
+  // the split: even column counts on both sides when the rows are even, so
+  // both halves keep the 16-byte loads
+  int ih = a.I / 2;
+  if ((IG & 1) == 0 && ((ih * a.G) & 1)) ih--;
+  if (!a.side || ih <= 0) {
+    brackets(0, IG, s);
+    med_pass(0, IG);
+    if (a.stats.rc > 0 && a.stats_ready) (void)hipEventRecord(a.stats_ready, s);
+    select(false, 0, IG, s);
+    launch_rm_pass<true, false>(ng, a, IG, 0, IG, bd, w.scr, w.rp, s);
+    select(true, 0, IG, s);
+    score(0, a.I);
+    return hipGetLastError();
+  }
+  const int cm = ih * a.G;
+  hipStream_t q = a.side;
+  const hipEvent_t *ev = a.ev;
+  hipError_t e = hipSuccess;
+  auto rec = [&](int k, hipStream_t on) {  // k < 0: the imbalance partials' event
+    if (e == hipSuccess) e = hipEventRecord(k < 0 ? a.stats_ready : ev[k], on);
+  };
+  auto wait = [&](hipStream_t on, int k) {
+    if (e == hipSuccess) e = hipStreamWaitEvent(on, ev[k], 0);
+  };
+  brackets(0, cm, s);
+  rec(0, s);  // fork
+  wait(q, 0);
+  if (e != hipSuccess) return e;
+  brackets(cm, IG, q);  // beside the median pass of A
+  rec(1, q);
+  med_pass(0, cm);
+  rec(2, s);
+  wait(q, 2);
+  select(false, 0, cm, q);  // beside the median pass of B
+  rec(3, q);
+  wait(s, 1);
+  med_pass(cm, IG);
+  if (a.stats.rc > 0 && a.stats_ready) rec(-1, s);
+  rec(4, s);
+  wait(q, 4);
+  select(false, cm, IG, q);  // beside the MAD pass of A
+  rec(5, q);
+  wait(s, 3);
+  launch_rm_pass<true, false>(ng, a, IG, 0, cm, bd, w.scr, w.rp, s);
+  rec(6, s);
+  wait(q, 6);
+  select(true, 0, cm, q);  // beside the MAD pass of B
+  rec(7, q);
+  wait(s, 5);
+  launch_rm_pass<true, false>(ng, a, IG, cm, IG, bd, w.scr, w.rp, s);
+  rec(8, s);
+  wait(q, 8);
+  select(true, cm, IG, q);  // beside score A
+  rec(9, q);
+  wait(s, 7);
+  score(0, ih);
+  wait(s, 9);  // joins the side stream
+  score(ih, a.I);
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 // sel_regions with the dynamic LDS its instantiation uses (the bracket buffer
@@ -2078,36 +2194,14 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
   if (a.R > 0) {
     if (row_major_path(a.R, a.mode, a.kind)) {
       if (IG > 0) {
-        const int ng = transpose_groups_of(a.R);
-        const unsigned strips = (unsigned)((IG + TT - 1) / TT);
-        if (a.stats.rc > 0 && a.stats.rc != ng) return hipErrorInvalidValue;
-        int dev = 0, cus = 256;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        const int grid = std::min(IG, std::min(SEL_GRID_MAX, SEL_WGS_PER_CU * cus));
-        hipLaunchKernelGGL(rm_sample, dim3(MS / TT, strips), dim3(256), 0, s, a.T, a.R, IG, a.G, a.it,
-                           w.smp);
-        hipLaunchKernelGGL(rm_brackets, dim3(IG), dim3(CS), 0, s, (const int64_t *)w.smp, IG, w.qa, w.qb);
-        const RmBr bm{w.qa, w.qb, nullptr};
-        if (a.stats.rc > 0) {
-          launch_rm_pass<false, true>(ng, a, IG, bm, w.scr, w.rp, s);
-          if (a.stats_ready) (void)hipEventRecord(a.stats_ready, s);
-        } else {
-          launch_rm_pass<false, false>(ng, a, IG, bm, w.scr, w.rp, s);
-        }
-        const RmOut ro{w.da, w.db};
-        hipLaunchKernelGGL(rm_select<false>, dim3(grid), dim3(CS), 0, s, a.T, a.R, IG, a.G, a.it,
-                           (const int64_t *)w.smp, ng, w.rp, bm, (const int64_t *)w.scr, w.slots, ro,
-                           w.cs);
-        const RmBr bd{w.da, w.db, w.cs.med2};
-        launch_rm_pass<true, false>(ng, a, IG, bd, w.scr, w.rp, s);
-        hipLaunchKernelGGL(rm_select<true>, dim3(grid), dim3(CS), 0, s, a.T, a.R, IG, a.G, a.it,
-                           (const int64_t *)w.smp, ng, w.rp, bd, (const int64_t *)w.scr, w.slots, ro,
-                           w.cs);
+        if (a.stats.rc > 0 && a.stats.rc != transpose_groups_of(a.R)) return hipErrorInvalidValue;
+        const hipError_t e = scan_row_major(a, w, IG, s);
+        if (e != hipSuccess) return e;
+      } else {
+        const int64_t waves = ((a.R + SRW - 1) / SRW) * ((a.G + 63) / 64);
+        hipLaunchKernelGGL(score_rows, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a.T, a.R, a.I,
+                           a.G, a.it, 0, a.I, w.cs, w.m_t);
       }
-      const int64_t waves = ((a.R + SRW - 1) / SRW) * ((a.G + 63) / 64);
-      hipLaunchKernelGGL(score_rows, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a.T, a.R, a.I,
-                         a.G, a.it, w.cs, w.m_t);
       launch_sel_regions<true, true>((const void *)w.m_t, a.R, a.G, a.it, a.I, w.z_t, a.region_score,
                                      s);
     } else if (a.mode == TA_SCAN_FULL) {

@@ -394,6 +394,8 @@ struct ta_plan_s {
   hipStream_t cap = nullptr;
   hipStream_t cap2 = nullptr;      // a second capture stream (imbalance epilogue beside the scan)
   hipEvent_t ev_stats = nullptr, ev_join = nullptr;
+  hipStream_t cap3 = nullptr;      // the exact scan's selections beside its passes
+  hipEvent_t ev_scan[10] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ta::SegShape shape;
@@ -415,6 +417,9 @@ void plan_free(ta_plan p) {
   if (p->cap2) hipStreamDestroy(p->cap2);
   if (p->ev_stats) hipEventDestroy(p->ev_stats);
   if (p->ev_join) hipEventDestroy(p->ev_join);
+  if (p->cap3) hipStreamDestroy(p->cap3);
+  for (hipEvent_t ev : p->ev_scan)
+    if (ev) hipEventDestroy(ev);
   for (hipEvent_t ev : p->slots)
     if (ev) hipEventDestroy(ev);
   if (p->d_order) hipFree(p->d_order);
@@ -1315,6 +1320,10 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
   if (e == hipSuccess && fuse) e = hipStreamCreateWithFlags(&p->cap2, hipStreamNonBlocking);
   if (e == hipSuccess && fuse) e = hipEventCreateWithFlags(&p->ev_stats, hipEventDisableTiming);
   if (e == hipSuccess && fuse) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+  const bool split = d->with_outliers && d->outlier_mode == TA_SCAN_FULL && R > 0 && (int64_t)I * G > 0;
+  if (e == hipSuccess && split) e = hipStreamCreateWithFlags(&p->cap3, hipStreamNonBlocking);
+  for (int k = 0; k < 10 && split; k++)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_scan[k], hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) {
     plan_free(p);
@@ -1354,6 +1363,10 @@ ta_status ta_plan_create(ta_handle h, const ta_traces *t, const int64_t *offsets
     if (fuse) {
       oa.stats = ta::imbalance_partials(imb_ws, R, I, G, need_rs, rc_t);
       oa.stats_ready = p->ev_stats;
+    }
+    if (split) {
+      oa.side = p->cap3;
+      for (int k = 0; k < 10; k++) oa.ev[k] = p->ev_scan[k];
     }
     le = ta::launch_outliers(oa, p->ws, fuse ? ws_out : ws, p->cap);
   }

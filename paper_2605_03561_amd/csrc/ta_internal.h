@@ -135,6 +135,13 @@ struct OutArgs {
   // When set (with stats), recorded on the stream right after the pass that
   // writes the imbalance partials, so a consumer on another stream can start.
   hipEvent_t stats_ready = nullptr;
+  // When set, the row-major robust FULL scan runs as two column halves
+  // (iterations [0, I/2) and [I/2, I)) in a pipeline: the streaming passes on
+  // the launch stream, each half's per-column selection on `side` beside the
+  // other half's pass; ev[] are the fork and join events (all ten distinct).
+  // `side` is joined back into the launch stream before the call returns.
+  hipStream_t side = nullptr;
+  hipEvent_t ev[10] = {};
 };
 // Rank chunks of the FULL scan's transpose (TG tiles of 64 ranks each).
 int transpose_groups(int64_t R);

@@ -162,3 +162,76 @@ def test_timed_replays_match_eager(env):
     with pytest.raises(ta.TAError):
         p.segment_ms(100)                      # a slot never launched
     p.close()
+
+
+@pytest.fixture(scope="module", params=[10, 7])
+def long_columns(request):
+    """33,000 ranks (more than 32,768 padded: the exact scan's row-major path
+    with sampled brackets), short traces over 5 regions and 10 or 7
+    iterations, every third rank's trace cut short so that ranks end at
+    different iterations."""
+    import torch
+
+    from paper_2605_03561_amd import ta
+    n_iters = request.param
+    w = synth.timeline_workload(seed=5, n_ranks=33000, median_len=160, min_len=40, max_len=2000,
+                                n_nodes=60, depth_max=5, n_iters=n_iters, n_regions=5,
+                                inject_frac=0.02)
+    rng = np.random.default_rng(6)
+    off = np.asarray(w.offsets, np.int64)
+    lens = np.diff(off)
+    cut = np.arange(0, len(lens), 3)
+    lens[cut] = (lens[cut] * rng.random(len(cut))).astype(np.int64)
+    keep = np.concatenate([np.arange(off[r], off[r] + lens[r]) for r in range(len(lens))])
+    w["offsets"] = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    w["ts"] = np.asarray(w.ts)[keep]
+    w["ctx"] = np.asarray(w.ctx)[keep]
+    h = ta.Handle(0)
+    h.set_tree(w.parent)
+    h.set_regions(w.marker, w.regions)
+    tr = ta.DeviceTraces(w.offsets, w.ts, w.ctx)
+    yield torch, ta, w, h, tr
+    h.close()
+
+
+def test_split_scan_plan(long_columns, oracle):
+    """In a plan the row-major exact scan runs as two column halves, the
+    per-column selections of one half beside the streaming pass of the other
+    on a second stream, and the row scores in two launches (the second
+    continuing the first's running sums).  Its outputs equal the oracle's and
+    the eager serial scan's on every replay.  With 5 regions, 10 iterations
+    split at 4 (so both halves keep even column counts) and 7 at 3 (odd row
+    length)."""
+    torch, ta, w, h, tr = long_columns
+    n_iters = w.n_iters
+    print(f"[plan] split scan I={n_iters}", flush=True)
+    st, T, it, out, span = oracle.segment(w.offsets, w.ts, w.ctx, w.parent, w.marker, w.regions,
+                                          n_iters)
+    assert st == 0 and len(np.unique(it)) > 2
+    st, score, flag, nf, reg = oracle.outliers(T, it, mode=0, kind=0, tau=3.5)
+    assert st == 0
+    p = h.plan(tr, n_iters, w.offsets, imbalance=True, outliers=True, autotune=0, region=True)
+    eager = h.attribute_segment(tr, n_iters)
+    imb = h.imbalance(eager["tensor"], eager["iters_found"], eager["rank_sum"],
+                      eager["rank_sumsq"], eager["span"])
+    ol = h.outliers(eager["tensor"], eager["iters_found"], region=True)
+    h.sync_status()
+    for rep in range(3):
+        p.out["rank_score"].fill_(-7)
+        p.out["region_score"].fill_(-7)
+        for k in p.imb:
+            p.imb[k].fill_(-7)
+        torch.cuda.synchronize()
+        p.launch()
+        h.sync_status()
+        assert np.array_equal(p.seg["tensor"].cpu().numpy(), T)
+        assert np.array_equal(p.out["region_score"].cpu().numpy(), reg), rep
+        assert np.array_equal(p.out["rank_score"].cpu().numpy(), score), rep
+        assert np.array_equal(p.out["rank_flag"].cpu().numpy(), flag), rep
+        assert int(p.out["n_flagged"][0]) == nf
+        for k in ("rank_score", "rank_flag", "n_flagged", "region_score"):
+            assert torch.equal(p.out[k], ol[k]), (rep, k)
+        for k in p.imb:
+            a, b = p.imb[k], imb[k]
+            assert torch.equal(torch.nan_to_num(a, nan=1.5), torch.nan_to_num(b, nan=1.5)), (rep, k)
+    p.close()
