@@ -43,6 +43,12 @@ __global__ void km_init(const double *C0, double *C, int KD, int32_t *labels, in
 }
 
 constexpr int KW = 256;  // threads of the K-Means assignment
+// Copies of the workgroup's cluster sums in LDS for the register-resident
+// row: lane l adds to copy l mod KNC, so the lanes of a wave that chose the
+// same cluster hit KNC different addresses (in different banks: a copy is
+// K*D + 1 words long) instead of one.
+constexpr int KNC = 16;
+__host__ __device__ inline int km_copies(bool reg) { return reg ? KNC : 1; }
 constexpr int FB = 16;   // features loaded per batch
 constexpr int DREG = 64; // features a row keeps in registers
 
@@ -88,15 +94,20 @@ __global__ __launch_bounds__(KW) void km_assign(const int64_t *__restrict__ Xt, 
   // centroids as [D][KMAX], so that feature d, centroid k sits at a fixed
   // offset from d's row (an immediate when d is unrolled)
   double *Cs = reinterpret_cast<double *>(lds);  // [D][KMAX]
-  uint64_t *Ss = lds + (size_t)D * KMAX;         // [K][D]
-  uint64_t *Ns = Ss + (size_t)K * D;             // [K]
+  constexpr int NC = REG ? KNC : 1;
+  const int KDP = K * D + 1, KP = K + 1;         // padded copy lengths
+  uint64_t *Ss = lds + (size_t)D * KMAX;         // [NC][K*D + 1]
+  uint64_t *Ns = Ss + (size_t)NC * KDP;          // [NC][K + 1]
   __shared__ uint32_t nchg;
   for (int i = threadIdx.x; i < D * KMAX; i += KW) {
     const int d = i / KMAX, k = i % KMAX;
     Cs[i] = k < K ? C[k * D + d] : 0.0;
   }
-  for (int i = threadIdx.x; i < K * D; i += KW) Ss[i] = 0;
-  for (int i = threadIdx.x; i < K; i += KW) Ns[i] = 0;
+  for (int i = threadIdx.x; i < NC * KDP; i += KW) Ss[i] = 0;
+  for (int i = threadIdx.x; i < NC * KP; i += KW) Ns[i] = 0;
+  const int cp = (threadIdx.x & 63) % NC;
+  uint64_t *Sc = Ss + (size_t)cp * KDP;
+  uint64_t *Nc = Ns + (size_t)cp * KP;
   if (threadIdx.x == 0) nchg = 0;
   __syncthreads();
   uint32_t my_chg = 0;
@@ -144,18 +155,18 @@ __global__ __launch_bounds__(KW) void km_assign(const int64_t *__restrict__ Xt, 
       }
     if (labels[r] != best) my_chg++;
     labels[r] = best;
-    atomicAdd((unsigned long long *)&Ns[best], 1ull);
+    atomicAdd((unsigned long long *)&Nc[best], 1ull);
     if (REG) {
 #pragma unroll
       for (int d = 0; d < DREG; d++)
-        atomicAdd((unsigned long long *)&Ss[best * DREG + d], (unsigned long long)v[d]);
+        atomicAdd((unsigned long long *)&Sc[best * DREG + d], (unsigned long long)v[d]);
     } else {
       for (int d0 = 0; d0 < D; d0 += FB) {
 #pragma unroll
         for (int u = 0; u < FB; u++) v[u] = d0 + u < D ? Xt[(int64_t)(d0 + u) * R + r] : 0;
 #pragma unroll
         for (int u = 0; u < FB; u++)
-          if (d0 + u < D) atomicAdd((unsigned long long *)&Ss[best * D + d0 + u], (unsigned long long)v[u]);
+          if (d0 + u < D) atomicAdd((unsigned long long *)&Sc[best * D + d0 + u], (unsigned long long)v[u]);
       }
     }
   }
@@ -164,10 +175,18 @@ __global__ __launch_bounds__(KW) void km_assign(const int64_t *__restrict__ Xt, 
   const int slot = blockIdx.x % KS;
   int64_t *sum_s = sum + (size_t)slot * K * D;
   int64_t *cnt_s = cnt + (size_t)slot * K;
-  for (int i = threadIdx.x; i < K * D; i += KW)
-    if (Ss[i]) atomicAdd((unsigned long long *)&sum_s[i], (unsigned long long)Ss[i]);
-  for (int i = threadIdx.x; i < K; i += KW)
-    if (Ns[i]) atomicAdd((unsigned long long *)&cnt_s[i], (unsigned long long)Ns[i]);
+  for (int i = threadIdx.x; i < K * D; i += KW) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int c = 0; c < NC; c++) t += Ss[(size_t)c * KDP + i];
+    if (t) atomicAdd((unsigned long long *)&sum_s[i], (unsigned long long)t);
+  }
+  for (int i = threadIdx.x; i < K; i += KW) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int c = 0; c < NC; c++) t += Ns[(size_t)c * KP + i];
+    if (t) atomicAdd((unsigned long long *)&cnt_s[i], (unsigned long long)t);
+  }
   if (threadIdx.x == 0 && nchg) atomicAdd((unsigned long long *)&chg[slot], (unsigned long long)nchg);
 }
 
@@ -217,169 +236,37 @@ __global__ __launch_bounds__(KT) void km_update(int K, int D, int max_iter, doub
 }
 
 // ---- DBSCAN on one int64 feature --------------------------------------------
+//
+// Rows are sorted by value with a device-wide stable LSD radix sort (8-bit
+// digits of the key minus the smallest key, only the digits that vary), in
+// tiles of WG1 rows, one workgroup per tile:
+//   db_keys     order-preserving keys x ^ SIGN, row ids, min and max key
+//   per digit:  db_hist (the tile's digit counts, digit-major [256][tiles]),
+//               db_xscan (exclusive sum over that array: each tile's start
+//               for each digit), db_scatter (a row's place among the equal
+//               digits of its tile from wave ballots and per-wave counts)
+// then, on the sorted rows, core flags (two binary searches per row) and the
+// labels from block scans with carries across tiles (db_xscan over the tiles'
+// maxima, minima and start counts).  The number of passes is known only on the
+// device, so all eight digit passes are queued and those past the last varying
+// digit return at once; nothing waits on the host.
 
 struct SortState {
-  uint64_t kmin;
-  int32_t which;  // buffer holding the sorted result (0 = A, 1 = B)
+  uint64_t kmin, kmax;
 };
+
+__device__ inline int sort_passes(const SortState *ss) {
+  const uint64_t span = ss->kmax - ss->kmin;
+  const int bits = span == 0 ? 0 : 64 - __clzll((long long)span);
+  return (bits + 7) / 8;
+}
 
 __device__ inline uint64_t lane_lt_mask() {
   const int lane = threadIdx.x & 63;
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Stable LSD radix sort of the keys x[r] ^ SIGN (order-preserving) with their
-// row index, in one workgroup: the range [kmin, kmax] fixes how many 8-bit
-// digits vary; each pass counts the digits, then scatters tiles of WG1 rows in
-// order, a row's place among equal digits of its tile coming from wave ballots
-// (lanes with the same digit) and the per-wave digit counts.
-__global__ __launch_bounds__(WG1) void radix_sort_1wg(const int64_t *__restrict__ x, int64_t R,
-                                                     uint64_t *kA, int32_t *iA, uint64_t *kB,
-                                                     int32_t *iB, SortState *ss) {
-  constexpr int NWV = WG1 / 64;
-  __shared__ uint64_t red_min[NWV], red_max[NWV];
-  __shared__ uint32_t hist[256];
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[NWV][256];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint64_t mn = ~0ull, mx = 0;
-  for (int64_t i = threadIdx.x; i < R; i += WG1) {
-    const uint64_t k = (uint64_t)x[i] ^ SIGN;
-    mn = k < mn ? k : mn;
-    mx = k > mx ? k : mx;
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint64_t a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
-  }
-  if (lane == 0) {
-    red_min[w] = mn;
-    red_max[w] = mx;
-  }
-  __syncthreads();
-  mn = red_min[0];
-  mx = red_max[0];
-  for (int i = 1; i < NWV; i++) {
-    mn = red_min[i] < mn ? red_min[i] : mn;
-    mx = red_max[i] > mx ? red_max[i] : mx;
-  }
-  const uint64_t span = R > 0 ? mx - mn : 0;
-  const int bits = span == 0 ? 0 : 64 - __clzll((long long)span);
-  const int passes = (bits + 7) / 8;
-  // keys relative to the minimum, in row order
-  for (int64_t i = threadIdx.x; i < R; i += WG1) {
-    kA[i] = ((uint64_t)x[i] ^ SIGN) - mn;
-    iA[i] = (int32_t)i;
-  }
-  __syncthreads();
-  uint64_t *ks = kA, *kd = kB;
-  int32_t *is = iA, *id = iB;
-  for (int p = 0; p < passes; p++) {
-    const int sh = 8 * p;
-    for (int i = threadIdx.x; i < 256; i += WG1) hist[i] = 0;
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < R; i += WG1) atomicAdd(&hist[(ks[i] >> sh) & 255], 1u);
-    __syncthreads();
-    if (threadIdx.x < 64) {  // exclusive scan of 256 counts by one wave
-      uint32_t c[4], s = 0;
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        c[u] = hist[4 * lane + u];
-        s += c[u];
-      }
-      uint32_t incl = s;
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += y;
-      }
-      uint32_t acc = incl - s;
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        base[4 * lane + u] = acc;
-        acc += c[u];
-      }
-    }
-    __syncthreads();
-    for (int64_t t0 = 0; t0 < R; t0 += WG1) {
-      for (int i = threadIdx.x; i < NWV * 256; i += WG1) (&wcnt[0][0])[i] = 0;
-      __syncthreads();
-      const int64_t i = t0 + threadIdx.x;
-      const bool on = i < R;
-      const uint64_t key = on ? ks[i] : 0;
-      const int32_t val = on ? is[i] : 0;
-      const uint32_t dg = (uint32_t)(key >> sh) & 255u;
-      uint64_t peers = __ballot(on);
-#pragma unroll
-      for (int b = 0; b < 8; b++) {
-        const uint64_t bb = __ballot((dg >> b) & 1u);
-        peers &= ((dg >> b) & 1u) ? bb : ~bb;
-      }
-      const uint32_t rank = (uint32_t)__popcll(peers & lane_lt_mask());
-      if (on && rank == 0) wcnt[w][dg] = (uint32_t)__popcll(peers);
-      __syncthreads();
-      for (int d = threadIdx.x; d < 256; d += WG1) {
-        uint32_t off = base[d];
-        for (int v = 0; v < NWV; v++) {
-          const uint32_t c = wcnt[v][d];
-          wcnt[v][d] = off;
-          off += c;
-        }
-        base[d] = off;
-      }
-      __syncthreads();
-      if (on) {
-        const uint32_t dst = wcnt[w][dg] + rank;
-        kd[dst] = key;
-        id[dst] = val;
-      }
-      __syncthreads();
-    }
-    uint64_t *tk = ks;
-    ks = kd;
-    kd = tk;
-    int32_t *ti = is;
-    is = id;
-    id = ti;
-  }
-  if (threadIdx.x == 0) {
-    ss->kmin = mn;
-    ss->which = (passes & 1) ? 1 : 0;
-  }
-}
-
-__device__ inline int64_t sorted_value(const uint64_t *k, int64_t j, uint64_t kmin) {
-  return (int64_t)((k[j] + kmin) ^ SIGN);
-}
-
-// Core rows: the neighbours of sorted row j are the rows with values in
-// [v_j - eps, v_j + eps], a contiguous range found by two binary searches.
-__global__ __launch_bounds__(KT) void db_core(const uint64_t *kA, const uint64_t *kB, int64_t R,
-                                             int64_t eps, int64_t min_pts, const SortState *ss,
-                                             uint8_t *core_s) {
-  const uint64_t *k = ss->which ? kB : kA;
-  const uint64_t kmin = ss->kmin;
-  for (int64_t j = (int64_t)blockIdx.x * KT + threadIdx.x; j < R; j += (int64_t)gridDim.x * KT) {
-    const int64_t v = sorted_value(k, j, kmin);
-    const int64_t lo_v = v < INT64_MIN + eps ? INT64_MIN : v - eps;
-    const int64_t hi_v = v > INT64_MAX - eps ? INT64_MAX : v + eps;
-    int64_t a = 0, b = j;  // first index with value >= lo_v (in [0, j])
-    while (a < b) {
-      const int64_t m = (a + b) >> 1;
-      if (sorted_value(k, m, kmin) < lo_v) a = m + 1;
-      else b = m;
-    }
-    const int64_t lo = a;
-    a = j + 1;
-    b = R;  // first index with value > hi_v (in [j+1, R])
-    while (a < b) {
-      const int64_t m = (a + b) >> 1;
-      if (sorted_value(k, m, kmin) <= hi_v) a = m + 1;
-      else b = m;
-    }
-    core_s[j] = (a - lo) >= min_pts ? 1 : 0;
-  }
-}
+__device__ inline int64_t key_value(uint64_t k) { return (int64_t)(k ^ SIGN); }
 
 // Inclusive scan over the workgroup with a binary operation (wave shuffles,
 // then the wave totals).  `wtot` holds NWV slots.
@@ -401,84 +288,294 @@ __device__ inline T block_incl_scan(T v, T *wtot, T ident, Op op) {
   return op(pre, x);
 }
 
-// Cluster numbers (one workgroup, chunks of WG1 sorted rows with carries):
-// forward, a core row starts a new cluster when the previous core row is more
-// than eps below it, and every row learns the previous core row; backward,
-// every row learns the next core row; a border row joins the nearer of the two
-// (the previous one on a tie) when it is within eps.  Labels and core flags go
-// back to row order.
-__global__ __launch_bounds__(WG1) void db_label(const uint64_t *kA, const int32_t *iA,
-                                               const uint64_t *kB, const int32_t *iB, int64_t R,
-                                               int64_t eps, const SortState *ss,
-                                               const uint8_t *core_s, int32_t *cl_s,
-                                               int32_t *prev_s, int32_t *labels, uint8_t *core,
-                                               int32_t *n_clusters) {
+struct OpMax {
+  __device__ int64_t operator()(int64_t a, int64_t b) const { return a > b ? a : b; }
+};
+struct OpMin {
+  __device__ int64_t operator()(int64_t a, int64_t b) const { return a < b ? a : b; }
+};
+struct OpSum {
+  __device__ int64_t operator()(int64_t a, int64_t b) const { return a + b; }
+};
+
+// The inclusive scan's value of the previous thread (ident for thread 0).
+template <typename Op>
+__device__ inline int64_t block_excl_scan(int64_t v, int64_t ident, Op op, int64_t *wtot,
+                                          int64_t *shift, int64_t *total) {
+  const int64_t incl = block_incl_scan<int64_t>(v, wtot, ident, op);
+  shift[threadIdx.x] = incl;
+  __syncthreads();
+  const int64_t ex = threadIdx.x == 0 ? ident : shift[threadIdx.x - 1];
+  if (total) *total = shift[WG1 - 1];
+  __syncthreads();
+  return ex;
+}
+
+__global__ void db_init(SortState *ss, int32_t *n_clusters, int64_t R) {
+  ss->kmin = ~0ull;
+  ss->kmax = 0;
+  if (R == 0) *n_clusters = 0;
+}
+
+__global__ __launch_bounds__(WG1) void db_keys(const int64_t *__restrict__ x, int64_t R, uint64_t *kA,
+                                              int32_t *iA, SortState *ss) {
   constexpr int NWV = WG1 / 64;
-  __shared__ int64_t wt64[NWV];
-  __shared__ int32_t wt32[NWV];
-  __shared__ int64_t idx_lds[WG1];
-  __shared__ int32_t num_last;
-  const uint64_t *k = ss->which ? kB : kA;
-  const int32_t *perm = ss->which ? iB : iA;
+  __shared__ uint64_t rmin[NWV], rmax[NWV];
+  const int64_t i = (int64_t)blockIdx.x * WG1 + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t mn = ~0ull, mx = 0;
+  if (i < R) {
+    const uint64_t k = (uint64_t)x[i] ^ SIGN;
+    kA[i] = k;
+    iA[i] = (int32_t)i;
+    mn = mx = k;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if (lane == 0) {
+    rmin[w] = mn;
+    rmax[w] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 1; v < NWV; v++) {
+      mn = rmin[v] < mn ? rmin[v] : mn;
+      mx = rmax[v] > mx ? rmax[v] : mx;
+    }
+    atomicMin((unsigned long long *)&ss->kmin, (unsigned long long)mn);
+    atomicMax((unsigned long long *)&ss->kmax, (unsigned long long)mx);
+  }
+}
+
+// Digit pass p reads the keys from A when p is even, from B when odd.
+__global__ __launch_bounds__(WG1) void db_hist(const uint64_t *kA, const uint64_t *kB, int64_t R,
+                                              int p, const SortState *ss, int64_t *hist) {
+  __shared__ uint32_t h[256];
+  if (p >= sort_passes(ss)) return;
+  const uint64_t *ks = (p & 1) ? kB : kA;
   const uint64_t kmin = ss->kmin;
-  auto imax = [](int64_t a, int64_t b) { return a > b ? a : b; };
-  auto imin = [](int64_t a, int64_t b) { return a < b ? a : b; };
-  auto iadd = [](int32_t a, int32_t b) { return a + b; };
-  int64_t last_core = -1;  // carry: last core row before the chunk
-  int32_t clusters = 0;    // carry: clusters started before the chunk
-  for (int64_t t0 = 0; t0 < R; t0 += WG1) {
-    const int64_t j = t0 + threadIdx.x;
-    const bool on = j < R;
-    const bool c = on && core_s[j];
-    const int64_t pc = imax(last_core, block_incl_scan<int64_t>(c ? j : -1, wt64, (int64_t)-1, imax));
-    idx_lds[threadIdx.x] = pc;  // last core row at or before j
-    __syncthreads();
-    const int64_t prev = threadIdx.x == 0 ? last_core : idx_lds[threadIdx.x - 1];
-    int32_t start = 0;
-    if (c) start = (prev < 0 || sorted_value(k, j, kmin) - sorted_value(k, prev, kmin) > eps) ? 1 : 0;
-    const int32_t num = clusters + block_incl_scan<int32_t>(start, wt32, 0, iadd);
-    if (on) {
-      cl_s[j] = c ? num - 1 : -1;
-      prev_s[j] = (int32_t)prev;
-    }
-    if (threadIdx.x == WG1 - 1) num_last = num;
-    __syncthreads();
-    last_core = idx_lds[WG1 - 1];
-    clusters = num_last;
-    __syncthreads();
+  const int64_t tiles = gridDim.x;
+  for (int d = threadIdx.x; d < 256; d += WG1) h[d] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * WG1 + threadIdx.x;
+  if (i < R) atomicAdd(&h[(uint32_t)((ks[i] - kmin) >> (8 * p)) & 255u], 1u);
+  __syncthreads();
+  for (int d = threadIdx.x; d < 256; d += WG1) hist[(int64_t)d * tiles + blockIdx.x] = h[d];
+}
+
+__global__ __launch_bounds__(WG1) void db_scatter(uint64_t *kA, int32_t *iA, uint64_t *kB, int32_t *iB,
+                                                 int64_t R, int p, const SortState *ss,
+                                                 const int64_t *__restrict__ start) {
+  constexpr int NWV = WG1 / 64;
+  __shared__ uint32_t wcnt[NWV][256];
+  if (p >= sort_passes(ss)) return;
+  const bool odd = p & 1;
+  const uint64_t *ks = odd ? kB : kA;
+  const int32_t *is = odd ? iB : iA;
+  uint64_t *kd = odd ? kA : kB;
+  int32_t *id = odd ? iA : iB;
+  const uint64_t kmin = ss->kmin;
+  const int64_t tiles = gridDim.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < NWV * 256; d += WG1) (&wcnt[0][0])[d] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * WG1 + threadIdx.x;
+  const bool on = i < R;
+  const uint64_t key = on ? ks[i] : 0;
+  const int32_t val = on ? is[i] : 0;
+  const uint32_t dg = (uint32_t)((key - kmin) >> (8 * p)) & 255u;
+  // lanes of this wave with the same digit
+  uint64_t peers = __ballot(on);
+#pragma unroll
+  for (int b = 0; b < 8; b++) {
+    const uint64_t bb = __ballot((dg >> b) & 1u);
+    peers &= ((dg >> b) & 1u) ? bb : ~bb;
   }
-  if (threadIdx.x == 0) *n_clusters = clusters;
-  // backward: thread t takes row t0 + (WG1 - 1 - t), so a scan over threads
-  // runs from the chunk's last row down
-  int64_t next_core = INT64_MAX;  // carry: first core row after the chunk
-  const int64_t n_chunks = (R + WG1 - 1) / WG1;
-  for (int64_t ci = n_chunks - 1; ci >= 0; ci--) {
-    const int64_t j = ci * WG1 + (WG1 - 1 - threadIdx.x);
-    const bool on = j < R;
-    const bool c = on && core_s[j];
-    const int64_t nc =
-        imin(next_core, block_incl_scan<int64_t>(c ? j : INT64_MAX, wt64, INT64_MAX, imin));
-    idx_lds[threadIdx.x] = nc;  // first core row at or after j
-    __syncthreads();
-    const int64_t next = threadIdx.x == 0 ? next_core : idx_lds[threadIdx.x - 1];
-    if (on) {
-      int32_t lab = cl_s[j];
-      if (!c) {
-        const int64_t v = sorted_value(k, j, kmin);
-        const int64_t prev = prev_s[j];
-        const int64_t dl = prev >= 0 ? v - sorted_value(k, prev, kmin) : INT64_MAX;
-        const int64_t dr = next != INT64_MAX ? sorted_value(k, next, kmin) - v : INT64_MAX;
-        if (dl <= eps && dl <= dr) lab = cl_s[prev];
-        else if (dr <= eps) lab = cl_s[next];
-      }
-      const int32_t r = perm[j];
-      labels[r] = lab;
-      if (core) core[r] = c ? 1 : 0;
+  const uint32_t rank = (uint32_t)__popcll(peers & lane_lt_mask());
+  if (on && rank == 0) wcnt[w][dg] = (uint32_t)__popcll(peers);
+  __syncthreads();
+  // per digit: the tile's start, then the waves in order
+  for (int d = threadIdx.x; d < 256; d += WG1) {
+    uint32_t off = (uint32_t)start[(int64_t)d * tiles + blockIdx.x];
+    for (int v = 0; v < NWV; v++) {
+      const uint32_t c = wcnt[v][d];
+      wcnt[v][d] = off;
+      off += c;
     }
-    __syncthreads();
-    next_core = idx_lds[WG1 - 1];
-    __syncthreads();
   }
+  __syncthreads();
+  if (on) {
+    const uint32_t dst = wcnt[w][dg] + rank;
+    kd[dst] = key;
+    id[dst] = val;
+  }
+}
+
+// Exclusive scan of n values in one workgroup (thread t owns a contiguous run;
+// `rev` scans from the last value down), in place allowed; total (optional)
+// is the whole reduction.  With p >= 0 it belongs to digit pass p and returns
+// when that pass does not run.
+template <typename Op>
+__global__ __launch_bounds__(WG1) void db_xscan(const int64_t *in, int64_t n, int rev, int64_t ident,
+                                               int64_t *out, int32_t *total, int p,
+                                               const SortState *ss) {
+  __shared__ int64_t wtot[WG1 / 64];
+  __shared__ int64_t shift[WG1];
+  __shared__ int64_t all;
+  if (p >= 0 && p >= sort_passes(ss)) return;
+  constexpr int XB = 8;  // loads in flight per thread
+  const Op op;
+  const int64_t ch = (n + WG1 - 1) / WG1;
+  const int64_t s = (int64_t)threadIdx.x * ch;
+  const int64_t e = s + ch < n ? s + ch : n;
+  auto at = [&](int64_t q) { return rev ? n - 1 - q : q; };
+  // loads at clamped positions (unconditional, so all XB stay in flight),
+  // values past the run replaced by the identity
+  auto batch = [&](int64_t q0, int64_t *v) {
+#pragma unroll
+    for (int u = 0; u < XB; u++) v[u] = in[at(q0 + u < e ? q0 + u : e - 1)];
+#pragma unroll
+    for (int u = 0; u < XB; u++) v[u] = q0 + u < e ? v[u] : ident;
+  };
+  int64_t acc = ident;
+  for (int64_t q0 = s; q0 < e; q0 += XB) {
+    int64_t v[XB];
+    batch(q0, v);
+#pragma unroll
+    for (int u = 0; u < XB; u++) acc = op(acc, v[u]);
+  }
+  int64_t run = block_excl_scan(acc, ident, op, wtot, shift, &all);
+  for (int64_t q0 = s; q0 < e; q0 += XB) {
+    int64_t v[XB];
+    batch(q0, v);
+#pragma unroll
+    for (int u = 0; u < XB; u++) {
+      if (q0 + u < e) out[at(q0 + u)] = run;
+      run = op(run, v[u]);
+    }
+  }
+  if (total && threadIdx.x == 0) *total = (int32_t)all;
+}
+
+__device__ inline const uint64_t *sorted_keys(const uint64_t *kA, const uint64_t *kB,
+                                              const SortState *ss) {
+  return (sort_passes(ss) & 1) ? kB : kA;
+}
+
+// Core rows: the neighbours of sorted row j are the rows with values in
+// [v_j - eps, v_j + eps], a contiguous range found by two binary searches.
+// Per tile: the last and the first core row (-1 / INT64_MAX when none).
+__global__ __launch_bounds__(WG1) void db_core(const uint64_t *kA, const uint64_t *kB, int64_t R,
+                                              int64_t eps, int64_t min_pts, const SortState *ss,
+                                              uint8_t *core_s, int64_t *tmax, int64_t *tmin) {
+  __shared__ int64_t wtot[WG1 / 64];
+  const uint64_t *k = sorted_keys(kA, kB, ss);
+  const int64_t j = (int64_t)blockIdx.x * WG1 + threadIdx.x;
+  bool c = false;
+  if (j < R) {
+    const int64_t v = key_value(k[j]);
+    const int64_t lo_v = v < INT64_MIN + eps ? INT64_MIN : v - eps;
+    const int64_t hi_v = v > INT64_MAX - eps ? INT64_MAX : v + eps;
+    int64_t a = 0, b = j;  // first index with value >= lo_v (in [0, j])
+    while (a < b) {
+      const int64_t m = (a + b) >> 1;
+      if (key_value(k[m]) < lo_v) a = m + 1;
+      else b = m;
+    }
+    const int64_t lo = a;
+    a = j + 1;
+    b = R;  // first index with value > hi_v (in [j+1, R])
+    while (a < b) {
+      const int64_t m = (a + b) >> 1;
+      if (key_value(k[m]) <= hi_v) a = m + 1;
+      else b = m;
+    }
+    c = (a - lo) >= min_pts;
+    core_s[j] = c ? 1 : 0;
+  }
+  const int64_t mx = block_incl_scan<int64_t>(c ? j : -1, wtot, (int64_t)-1, OpMax());
+  const int64_t mn = block_incl_scan<int64_t>(c ? j : INT64_MAX, wtot, INT64_MAX, OpMin());
+  if (threadIdx.x == WG1 - 1) {
+    tmax[blockIdx.x] = mx;
+    tmin[blockIdx.x] = mn;
+  }
+}
+
+// Per sorted row: the last core row before it (prev_s), and for a core row
+// whether it starts a new cluster (the previous core row is more than eps
+// below it), written to cl_s; per tile the count of starts.
+__global__ __launch_bounds__(WG1) void db_start(const uint64_t *kA, const uint64_t *kB, int64_t R,
+                                               int64_t eps, const SortState *ss,
+                                               const uint8_t *core_s, const int64_t *cprev,
+                                               int32_t *prev_s, int32_t *cl_s, int64_t *tstart) {
+  __shared__ int64_t wtot[WG1 / 64];
+  __shared__ int64_t shift[WG1];
+  __shared__ int64_t all;
+  const uint64_t *k = sorted_keys(kA, kB, ss);
+  const int64_t j = (int64_t)blockIdx.x * WG1 + threadIdx.x;
+  const bool on = j < R;
+  const bool c = on && core_s[j];
+  const int64_t ex = block_excl_scan(c ? j : (int64_t)-1, (int64_t)-1, OpMax(), wtot, shift, nullptr);
+  const int64_t cp = cprev[blockIdx.x];
+  const int64_t prev = ex > cp ? ex : cp;
+  int64_t st = 0;
+  if (c) st = (prev < 0 || key_value(k[j]) - key_value(k[prev]) > eps) ? 1 : 0;
+  if (on) {
+    prev_s[j] = (int32_t)prev;
+    cl_s[j] = (int32_t)st;
+  }
+  (void)block_excl_scan(st, (int64_t)0, OpSum(), wtot, shift, &all);
+  if (threadIdx.x == 0) tstart[blockIdx.x] = all;
+}
+
+// Cluster numbers of the core rows: the starts up to and including the row,
+// after the tile's base, minus one (-1 for the other rows).
+__global__ __launch_bounds__(WG1) void db_number(int64_t R, const uint8_t *core_s, const int64_t *cbase,
+                                                int32_t *cl_s) {
+  __shared__ int64_t wtot[WG1 / 64];
+  const int64_t j = (int64_t)blockIdx.x * WG1 + threadIdx.x;
+  const bool on = j < R;
+  const int64_t st = on ? cl_s[j] : 0;
+  const int64_t incl = block_incl_scan<int64_t>(st, wtot, (int64_t)0, OpSum());
+  if (on) cl_s[j] = core_s[j] ? (int32_t)(cbase[blockIdx.x] + incl - 1) : -1;
+}
+
+// Labels in row order: a border row joins the nearer of the previous and the
+// next core row (the previous one on a tie) when it is within eps.  Thread t
+// takes the tile's row WG1 - 1 - t, so a scan over threads runs from the
+// tile's last row down and gives the first core row at or after each row.
+__global__ __launch_bounds__(WG1) void db_out(const uint64_t *kA, const int32_t *iA, const uint64_t *kB,
+                                             const int32_t *iB, int64_t R, int64_t eps,
+                                             const SortState *ss, const uint8_t *core_s,
+                                             const int64_t *cnext, const int32_t *prev_s,
+                                             const int32_t *cl_s, int32_t *labels, uint8_t *core) {
+  __shared__ int64_t wtot[WG1 / 64];
+  const bool inB = sort_passes(ss) & 1;
+  const uint64_t *k = inB ? kB : kA;
+  const int32_t *perm = inB ? iB : iA;
+  const int64_t j = (int64_t)blockIdx.x * WG1 + (WG1 - 1 - threadIdx.x);
+  const bool on = j < R;
+  const bool c = on && core_s[j];
+  const int64_t sm = block_incl_scan<int64_t>(c ? j : INT64_MAX, wtot, INT64_MAX, OpMin());
+  const int64_t cn = cnext[blockIdx.x];
+  const int64_t next = sm < cn ? sm : cn;
+  if (!on) return;
+  int32_t lab = cl_s[j];
+  if (!c) {
+    const int64_t v = key_value(k[j]);
+    const int64_t prev = prev_s[j];
+    const int64_t dl = prev >= 0 ? v - key_value(k[prev]) : INT64_MAX;
+    const int64_t dr = next != INT64_MAX ? key_value(k[next]) - v : INT64_MAX;
+    if (dl <= eps && dl <= dr) lab = cl_s[prev];
+    else if (dr <= eps) lab = cl_s[next];
+    else lab = -1;
+  }
+  const int32_t r = perm[j];
+  labels[r] = lab;
+  if (core) core[r] = c ? 1 : 0;
 }
 
 // ---- compute nodes shared by clusters ---------------------------------------
@@ -545,7 +642,11 @@ hipError_t launch_kmeans(const int64_t *X, int64_t R, int D, int K, const double
   km_init<<<grid_of(R > KS * K * D ? R : KS * K * D, cus), KT, 0, s>>>(C0, C, K * D, labels, R, sum,
                                                                        cnt, chg, K, st);
   if (R > 0) km_transpose<<<dim3((unsigned)((R + 63) / 64), (unsigned)((D + 63) / 64)), KT, 0, s>>>(X, R, D, Xt);
-  const size_t lds = ((size_t)D * (K <= 8 ? 8 : 32) + (size_t)K * D + K) * sizeof(uint64_t);
+  // the register-resident row for the usual width (64 region totals, K <= 8)
+  const bool reg = D == DREG && K <= 8;
+  const size_t nc = (size_t)km_copies(reg);
+  const size_t lds =
+      ((size_t)D * (K <= 8 ? 8 : 32) + nc * ((size_t)K * D + 1) + nc * ((size_t)K + 1)) * sizeof(uint64_t);
   static bool attr = false;
   if (!attr) {
     const void *fns[] = {reinterpret_cast<const void *>(&km_assign<8, true>),
@@ -559,8 +660,6 @@ hipError_t launch_kmeans(const int64_t *X, int64_t R, int D, int K, const double
   int64_t grid = (R + KW - 1) / KW;
   if (grid > (int64_t)cus * 8) grid = (int64_t)cus * 8;
   if (grid < 1) grid = 1;
-  // the register-resident row for the usual width (64 region totals, K <= 8)
-  const bool reg = D == DREG && K <= 8;
   for (int it = 0; it < max_iter; it++) {
     if (reg)
       km_assign<8, true><<<(int)grid, KW, lds, s>>>(Xt, R, D, K, C, labels, sum, cnt, chg, st);
@@ -573,32 +672,77 @@ hipError_t launch_kmeans(const int64_t *X, int64_t R, int D, int K, const double
   return hipGetLastError();
 }
 
+namespace {
+
+struct DbWs {
+  uint64_t *kA, *kB;
+  int32_t *iA, *iB, *cl_s, *prev_s;
+  uint8_t *core_s;
+  SortState *ss;
+  int64_t *hist;                // [256][tiles] digit counts, then each tile's start
+  int64_t *tmax, *tmin, *tst;   // per tile: last / first core row, cluster starts
+  int64_t *cprev, *cnext, *cbase;
+};
+
+DbWs db_carve(void *ws, int64_t R, size_t *used) {
+  const size_t tiles = (size_t)((R + WG1 - 1) / WG1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *p = (char *)ws + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return (void *)p;
+  };
+  DbWs w;
+  w.kA = (uint64_t *)take((size_t)R * 8);
+  w.kB = (uint64_t *)take((size_t)R * 8);
+  w.iA = (int32_t *)take((size_t)R * 4);
+  w.iB = (int32_t *)take((size_t)R * 4);
+  w.cl_s = (int32_t *)take((size_t)R * 4);
+  w.prev_s = (int32_t *)take((size_t)R * 4);
+  w.core_s = (uint8_t *)take((size_t)R);
+  w.ss = (SortState *)take(sizeof(SortState));
+  w.hist = (int64_t *)take(256 * tiles * 8);
+  w.tmax = (int64_t *)take(tiles * 8);
+  w.tmin = (int64_t *)take(tiles * 8);
+  w.tst = (int64_t *)take(tiles * 8);
+  w.cprev = (int64_t *)take(tiles * 8);
+  w.cnext = (int64_t *)take(tiles * 8);
+  w.cbase = (int64_t *)take(tiles * 8);
+  *used = off;
+  return w;
+}
+
+}  // namespace
+
 size_t dbscan_ws_bytes(int64_t R) {
-  return (size_t)R * (8 + 4) * 2 + (size_t)R * (1 + 4 + 4) + 256;
+  size_t used = 0;
+  db_carve(nullptr, R, &used);
+  return used;
 }
 
 hipError_t launch_dbscan1d(const int64_t *x, int64_t R, int64_t eps, int64_t min_pts,
                            int32_t *labels, int32_t *n_clusters, uint8_t *core, void *ws, int cus,
                            hipStream_t s) {
-  char *p = (char *)ws;
-  uint64_t *kA = (uint64_t *)p;
-  p += (size_t)R * 8;
-  uint64_t *kB = (uint64_t *)p;
-  p += (size_t)R * 8;
-  int32_t *iA = (int32_t *)p;
-  p += (size_t)R * 4;
-  int32_t *iB = (int32_t *)p;
-  p += (size_t)R * 4;
-  int32_t *cl_s = (int32_t *)p;
-  p += (size_t)R * 4;
-  int32_t *prev_s = (int32_t *)p;
-  p += (size_t)R * 4;
-  SortState *ss = (SortState *)p;
-  p += 64;
-  uint8_t *core_s = (uint8_t *)p;
-  radix_sort_1wg<<<1, WG1, 0, s>>>(x, R, kA, iA, kB, iB, ss);
-  db_core<<<grid_of(R, cus), KT, 0, s>>>(kA, kB, R, eps, min_pts, ss, core_s);
-  db_label<<<1, WG1, 0, s>>>(kA, iA, kB, iB, R, eps, ss, core_s, cl_s, prev_s, labels, core, n_clusters);
+  (void)cus;
+  size_t used = 0;
+  const DbWs w = db_carve(ws, R, &used);
+  db_init<<<1, 1, 0, s>>>(w.ss, n_clusters, R);
+  if (R == 0) return hipGetLastError();
+  const unsigned tiles = (unsigned)((R + WG1 - 1) / WG1);
+  db_keys<<<tiles, WG1, 0, s>>>(x, R, w.kA, w.iA, w.ss);
+  for (int p = 0; p < 8; p++) {  // passes past the last varying digit return at once
+    db_hist<<<tiles, WG1, 0, s>>>(w.kA, w.kB, R, p, w.ss, w.hist);
+    db_xscan<OpSum><<<1, WG1, 0, s>>>(w.hist, 256 * (int64_t)tiles, 0, 0, w.hist, nullptr, p, w.ss);
+    db_scatter<<<tiles, WG1, 0, s>>>(w.kA, w.iA, w.kB, w.iB, R, p, w.ss, w.hist);
+  }
+  db_core<<<tiles, WG1, 0, s>>>(w.kA, w.kB, R, eps, min_pts, w.ss, w.core_s, w.tmax, w.tmin);
+  db_xscan<OpMax><<<1, WG1, 0, s>>>(w.tmax, tiles, 0, -1, w.cprev, nullptr, -1, w.ss);
+  db_xscan<OpMin><<<1, WG1, 0, s>>>(w.tmin, tiles, 1, INT64_MAX, w.cnext, nullptr, -1, w.ss);
+  db_start<<<tiles, WG1, 0, s>>>(w.kA, w.kB, R, eps, w.ss, w.core_s, w.cprev, w.prev_s, w.cl_s, w.tst);
+  db_xscan<OpSum><<<1, WG1, 0, s>>>(w.tst, tiles, 0, 0, w.cbase, n_clusters, -1, w.ss);
+  db_number<<<tiles, WG1, 0, s>>>(R, w.core_s, w.cbase, w.cl_s);
+  db_out<<<tiles, WG1, 0, s>>>(w.kA, w.iA, w.kB, w.iB, R, eps, w.ss, w.core_s, w.cnext, w.prev_s, w.cl_s,
+                               labels, core);
   return hipGetLastError();
 }
 
