@@ -200,30 +200,28 @@ __global__ __launch_bounds__(KT) void km_update(int K, int D, int max_iter, doub
   if (st->done) return;
   __shared__ int64_t n_k[32];
   __shared__ uint64_t changed;
+  // the KS slots of one entry: all loads in flight, then the sum, then the
+  // slots cleared for the next iteration
+  auto take = [](uint64_t *p, size_t stride) {
+    uint64_t v[KS];
+#pragma unroll
+    for (int s = 0; s < KS; s++) v[s] = p[(size_t)s * stride];
+    uint64_t t = 0;
+#pragma unroll
+    for (int s = 0; s < KS; s++) t += v[s];
+#pragma unroll
+    for (int s = 0; s < KS; s++) p[(size_t)s * stride] = 0;
+    return t;
+  };
   for (int k = threadIdx.x; k < K; k += KT) {
-    int64_t n = 0;
-    for (int s = 0; s < KS; s++) {
-      n += cnt[(size_t)s * K + k];
-      cnt[(size_t)s * K + k] = 0;
-    }
+    const int64_t n = (int64_t)take((uint64_t *)cnt + k, (size_t)K);
     n_k[k] = n;
     if (counts) counts[k] = n;
   }
-  if (threadIdx.x == 0) {
-    uint64_t c = 0;
-    for (int s = 0; s < KS; s++) {
-      c += chg[s];
-      chg[s] = 0;
-    }
-    changed = c;
-  }
+  if (threadIdx.x == 0) changed = take(chg, 1);
   __syncthreads();
   for (int i = threadIdx.x; i < K * D; i += KT) {
-    uint64_t sm = 0;
-    for (int s = 0; s < KS; s++) {
-      sm += (uint64_t)sum[(size_t)s * K * D + i];
-      sum[(size_t)s * K * D + i] = 0;
-    }
+    const uint64_t sm = take((uint64_t *)sum + i, (size_t)K * D);
     const int64_t n = n_k[i / D];
     if (n > 0) C[i] = (double)(int64_t)sm / (double)n;
   }
@@ -414,50 +412,56 @@ __global__ __launch_bounds__(WG1) void db_scatter(uint64_t *kA, int32_t *iA, uin
   }
 }
 
-// Exclusive scan of n values in one workgroup (thread t owns a contiguous run;
-// `rev` scans from the last value down), in place allowed; total (optional)
-// is the whole reduction.  With p >= 0 it belongs to digit pass p and returns
-// when that pass does not run.
+// Exclusive scan of n values in one workgroup, in chunks of XC values: each
+// chunk is loaded coalesced into LDS, thread t scans its XP consecutive values
+// there after the block's exclusive scan of the per-thread sums, and the chunk
+// is stored coalesced; the running total carries to the next chunk.  `rev`
+// scans from the last value down; in place allowed; total (optional) is the
+// whole reduction.  With p >= 0 it belongs to digit pass p and returns when
+// that pass does not run.
+constexpr int XP = 4, XC = XP * WG1;
 template <typename Op>
 __global__ __launch_bounds__(WG1) void db_xscan(const int64_t *in, int64_t n, int rev, int64_t ident,
                                                int64_t *out, int32_t *total, int p,
                                                const SortState *ss) {
+  __shared__ int64_t buf[XC];
   __shared__ int64_t wtot[WG1 / 64];
   __shared__ int64_t shift[WG1];
   __shared__ int64_t all;
   if (p >= 0 && p >= sort_passes(ss)) return;
-  constexpr int XB = 8;  // loads in flight per thread
   const Op op;
-  const int64_t ch = (n + WG1 - 1) / WG1;
-  const int64_t s = (int64_t)threadIdx.x * ch;
-  const int64_t e = s + ch < n ? s + ch : n;
+  const int t = threadIdx.x;
   auto at = [&](int64_t q) { return rev ? n - 1 - q : q; };
-  // loads at clamped positions (unconditional, so all XB stay in flight),
-  // values past the run replaced by the identity
-  auto batch = [&](int64_t q0, int64_t *v) {
+  int64_t carry = ident;
+  for (int64_t c0 = 0; c0 < n; c0 += XC) {
 #pragma unroll
-    for (int u = 0; u < XB; u++) v[u] = in[at(q0 + u < e ? q0 + u : e - 1)];
+    for (int u = 0; u < XP; u++) {
+      const int64_t q = c0 + (int64_t)u * WG1 + t;
+      buf[u * WG1 + t] = q < n ? in[at(q)] : ident;
+    }
+    __syncthreads();
+    int64_t v[XP], acc = ident;
 #pragma unroll
-    for (int u = 0; u < XB; u++) v[u] = q0 + u < e ? v[u] : ident;
-  };
-  int64_t acc = ident;
-  for (int64_t q0 = s; q0 < e; q0 += XB) {
-    int64_t v[XB];
-    batch(q0, v);
+    for (int u = 0; u < XP; u++) {
+      v[u] = buf[XP * t + u];
+      acc = op(acc, v[u]);
+    }
+    int64_t run = op(carry, block_excl_scan(acc, ident, op, wtot, shift, &all));
 #pragma unroll
-    for (int u = 0; u < XB; u++) acc = op(acc, v[u]);
-  }
-  int64_t run = block_excl_scan(acc, ident, op, wtot, shift, &all);
-  for (int64_t q0 = s; q0 < e; q0 += XB) {
-    int64_t v[XB];
-    batch(q0, v);
-#pragma unroll
-    for (int u = 0; u < XB; u++) {
-      if (q0 + u < e) out[at(q0 + u)] = run;
+    for (int u = 0; u < XP; u++) {
+      buf[XP * t + u] = run;
       run = op(run, v[u]);
     }
+    carry = op(carry, all);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < XP; u++) {
+      const int64_t q = c0 + (int64_t)u * WG1 + t;
+      if (q < n) out[at(q)] = buf[u * WG1 + t];
+    }
+    __syncthreads();
   }
-  if (total && threadIdx.x == 0) *total = (int32_t)all;
+  if (total && t == 0) *total = (int32_t)carry;
 }
 
 __device__ inline const uint64_t *sorted_keys(const uint64_t *kA, const uint64_t *kB,
