@@ -67,6 +67,7 @@ __device__ inline int nbits64(uint64_t v) { return v ? 64 - __clzll((long long)v
 // ----------------------------------------------------------------------------
 constexpr int TT = 64;
 typedef long long v2ll __attribute__((ext_vector_type(2)));
+typedef int v2i __attribute__((ext_vector_type(2)));
 constexpr int64_t SENT = INT64_MIN;
 
 __host__ __device__ inline int64_t pad_ranks(int64_t R) { return (R + 63) & ~(int64_t)63; }
@@ -864,7 +865,9 @@ __host__ __device__ inline int64_t sample_rank(int j, int64_t Rp) {
 }
 
 __global__ __launch_bounds__(256) void rm_sample(const int64_t *__restrict__ T, int64_t R, int IG,
-                                                 int G, const int32_t *it, int64_t *__restrict__ smp) {
+                                                 int G, const int32_t *it, int64_t *__restrict__ smp,
+                                                 int32_t *esc) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *esc = 0;  // before the median pass
   __shared__ int64_t tile[TT][TT + 1];
   const int c0 = blockIdx.y * TT;
   const int j0 = blockIdx.x * TT;
@@ -953,6 +956,25 @@ constexpr int RPU = 8;         // rows in flight per thread
 constexpr int SEG_MAX = 2048;  // chunks per column the selection can visit (LDS)
 
 constexpr int RQ = 6;          // interior cells buffered per column
+// Interior cells kept per (chunk, column) slot; a column with a fuller slot
+// is selected over its gathered copy instead.  The bracket holds about a tenth
+// of a column (60-110 cells of a chunk), so only skewed or tied columns reach it.
+constexpr int SCAP = 256;
+
+// The 32-bit copy of the tensor that the median pass writes for the later
+// passes: a cell as its offset from the column's median-bracket low end when
+// that fits in (INT32_MIN, INT32_MAX], else CSENT (the reader then takes the
+// int64 cell).
+constexpr int32_t CSENT = INT32_MIN;
+struct CxRange {
+  int64_t lo, hi;  // the cells that fit
+  __device__ explicit CxRange(int64_t base)
+      : lo(base > INT64_MIN + 0x7fffffff ? base - 0x7fffffff : INT64_MIN),
+        hi(base < INT64_MAX - 0x7fffffff ? base + 0x7fffffff : INT64_MAX) {}
+  __device__ int32_t put(int64_t x, int64_t base) const {
+    return (x >= lo && x <= hi) ? (int32_t)(x - base) : CSENT;
+  }
+};
 
 // Counts and compaction of one column's cells against its bracket.  Interior
 // cells are buffered in registers (newest first, qn of them) and written out
@@ -1002,7 +1024,7 @@ struct RmCol {
   __device__ __forceinline__ void drain(int64_t *__restrict__ slot) {
 #pragma unroll
     for (int e = 0; e < RQ; e++)
-      if (e < qn) slot[cm + e] = q[e];
+      if (e < qn && cm + e < SCAP) slot[cm + e] = q[e];
     cm += qn;
     qn = 0;
   }
@@ -1026,17 +1048,48 @@ struct RmCol {
   }
 };
 
+template <bool S32>
+struct RmRow {
+  typedef v2ll T;  // two int64 cells
+};
+template <>
+struct RmRow<true> {
+  typedef v2i T;  // two cells of the 32-bit copy
+};
+template <bool B>
+struct Flag {
+  static constexpr bool value = B;
+};
+template <bool S32>
+struct RmCell {
+  typedef long long T;
+};
+template <>
+struct RmCell<true> {
+  typedef int T;
+};
+
 // One streaming pass over the row-major tensor: a thread owns CPL adjacent
 // columns (two: 16-byte loads when the row length is even, a wave reads 1 KB
 // of a row; one: half the registers, so more waves) and walks the RCH ranks of
 // chunk blockIdx.y, RPU rows in flight, counting in registers; the bracket
-// interior of each (chunk, column) goes to its own slot of RCH cells, so no
-// atomics and no overflow.  No LDS and no barriers.  Rows past the chunk's end
-// load its last row (in bounds) and are not counted.
-template <bool MAD, bool STATS, bool VEC, int CPL>
+// interior of each (chunk, column) goes to its own slot of SCAP cells (no
+// atomics; cells past SCAP are counted, not stored).  The median pass also
+// writes the 32-bit copy of every cell it reads (cx, offsets from its bracket's
+// low end) and sets *esc when a valid cell did not fit; the MAD pass then reads
+// the copy (S32, half the bytes), or the int64 tensor when *esc is set: both
+// forms are launched and the one that does not apply returns at once (one
+// loop per kernel, so no load sits in a branch inside it).  No LDS and no
+// barriers.  Rows past the chunk's end load its last row (in bounds) and are
+// not counted.
+template <bool MAD, bool STATS, bool VEC, int CPL, bool S32>
 __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, int64_t R, int IG, int G,
                                                const int32_t *it, int c_lo, int c_hi, RmBr br,
-                                               int64_t *__restrict__ scr, RmPart pp, ColPartials ps) {
+                                               int64_t *__restrict__ scr, RmPart pp, ColPartials ps,
+                                               int32_t *__restrict__ cx, const int64_t *__restrict__ cbase,
+                                               int32_t *esc) {
+  static_assert(MAD || !S32, "the median pass reads the int64 tensor");
+  if (MAD && (*esc == 0) != S32) return;
   const int ca = c_lo + ((int)blockIdx.x * 256 + (int)threadIdx.x) * CPL;
   if (ca >= c_hi) return;
   const int64_t ng = gridDim.y, ch = blockIdx.y;
@@ -1049,39 +1102,84 @@ __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, in
   c1.a = two ? br.a[ca + 1] : INT64_MAX;
   c1.b = two ? br.b[ca + 1] : INT64_MIN;
   c1.m = (MAD && two) ? br.med2[ca + 1] : 0;
-  int64_t *slot0 = scr + ((int64_t)ca * ng + ch) * RCH;
-  int64_t *slot1 = scr + ((int64_t)(ca + 1) * ng + ch) * RCH;
+  int64_t *slot0 = scr + ((int64_t)ca * ng + ch) * SCAP;
+  int64_t *slot1 = scr + ((int64_t)(ca + 1) * ng + ch) * SCAP;
   const int64_t rb = ch * RCH, re = rb + RCH < R ? rb + RCH : R, last = re - 1;
   const int cb = two ? ca + 1 : ca;
-  auto load_row = [&](int64_t r) {
-    const int64_t *row = T + (r < re ? r : last) * IG;
-    if (CPL == 1) return v2ll{__builtin_nontemporal_load(row + ca), SENT};
-    if (VEC) return __builtin_nontemporal_load(reinterpret_cast<const v2ll *>(row + ca));
-    return v2ll{__builtin_nontemporal_load(row + ca), __builtin_nontemporal_load(row + cb)};
-  };
-  // RPU rows in flight: the register of a row, once counted, loads the row
-  // RPU further on (so the loads stay in flight while the counting runs)
-  v2ll v[RPU];
+  // the copy's base per column (column cb is column ca again without a second)
+  const int64_t b0 = MAD ? cbase[ca] : c0.a;
+  const int64_t b1 = MAD ? cbase[cb] : (two ? c1.a : c0.a);
+  bool escaped = false;
+  {
+    typedef typename RmRow<S32>::T Row;
+    const CxRange f0(b0), f1(b1);
+    auto load_row = [&](int64_t r) -> Row {
+      const int64_t rr = r < re ? r : last;
+      if constexpr (S32) {
+        const int32_t *row = cx + rr * IG;
+        if (CPL == 1) return v2i{__builtin_nontemporal_load(row + ca), 0};
+        if (VEC) return __builtin_nontemporal_load(reinterpret_cast<const v2i *>(row + ca));
+        return v2i{__builtin_nontemporal_load(row + ca), __builtin_nontemporal_load(row + cb)};
+      } else {
+        const int64_t *row = T + rr * IG;
+        if (CPL == 1) return v2ll{__builtin_nontemporal_load(row + ca), SENT};
+        if (VEC) return __builtin_nontemporal_load(reinterpret_cast<const v2ll *>(row + ca));
+        return v2ll{__builtin_nontemporal_load(row + ca), __builtin_nontemporal_load(row + cb)};
+      }
+    };
+    // RPU rows in flight: the register of a row, once counted, loads the row
+    // RPU further on (so the loads stay in flight while the counting runs)
+    Row v[RPU];
 #pragma unroll
-  for (int u = 0; u < RPU; u++) v[u] = load_row(rb + u);
-  for (int64_t r0 = rb; r0 < re; r0 += RPU) {
-    int nit[RPU];
+    for (int u = 0; u < RPU; u++) v[u] = load_row(rb + u);
+    for (int64_t r0 = rb; r0 < re; r0 += RPU) {
+      int nit[RPU];
 #pragma unroll
-    for (int u = 0; u < RPU; u++) nit[u] = it ? it[r0 + u < re ? r0 + u : last] : 0x7fffffff;
+      for (int u = 0; u < RPU; u++) nit[u] = it ? it[r0 + u < re ? r0 + u : last] : 0x7fffffff;
 #pragma unroll
-    for (int u = 0; u < RPU; u++) {
-      const bool rv = r0 + u < re;
-      c0.cell((int64_t)v[u].x, rv && ia < nit[u]);
-      c1.cell((int64_t)v[u].y, rv && two && ib < nit[u]);
-      v[u] = load_row(r0 + u + RPU);
-      // a row adds at most one cell per column: drain the whole wave as soon
-      // as one buffer is full
-      if (__ballot(c0.qn == RQ || c1.qn == RQ)) {
-        c0.drain(slot0);
-        c1.drain(slot1);
+      for (int u = 0; u < RPU; u++) {
+        const bool rv = r0 + u < re;
+        const bool ok0 = rv && ia < nit[u], ok1 = rv && two && ib < nit[u];
+        int64_t x0, x1;
+        if constexpr (S32) {
+          x0 = b0 + (int64_t)v[u].x;
+          x1 = b1 + (int64_t)v[u].y;
+        } else {
+          x0 = (int64_t)v[u].x;
+          x1 = (int64_t)v[u].y;
+        }
+        if constexpr (!MAD) {
+          // a row past the chunk's end rewrites the last row's copy with its
+          // own values (no branch around the store)
+          int32_t *crow = cx + (rv ? r0 + u : last) * IG;
+          const int32_t y0 = f0.put(x0, b0);
+          escaped |= ok0 && y0 == CSENT;
+          if (CPL == 1) {
+            __builtin_nontemporal_store(y0, crow + ca);
+          } else {
+            const int32_t y1 = f1.put(x1, b1);
+            escaped |= ok1 && y1 == CSENT;
+            if (VEC)
+              __builtin_nontemporal_store(v2i{y0, y1}, reinterpret_cast<v2i *>(crow + ca));
+            else {
+              __builtin_nontemporal_store(y0, crow + ca);
+              __builtin_nontemporal_store(y1, crow + cb);
+            }
+          }
+        }
+        c0.cell(x0, ok0);
+        c1.cell(x1, ok1);
+        v[u] = load_row(r0 + u + RPU);
+        // a row adds at most one cell per column: drain the whole wave as
+        // soon as one buffer is full
+        if (__ballot(c0.qn == RQ || c1.qn == RQ)) {
+          c0.drain(slot0);
+          c1.drain(slot1);
+        }
       }
     }
   }
+  if (!MAD && escaped) *esc = 1;
   c0.flush(ch * IG + ca, pp, ps, slot0);
   if (two) c1.flush(ch * IG + ca + 1, pp, ps, slot1);
 }
@@ -1138,7 +1236,7 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
   for (int j = t; j < NHC * NB; j += CS) (&L.hist[0][0])[j] = 0;
   for (int c = c_lo + (int)blockIdx.x; c < c_hi; c += gridDim.x) {
     // the chunk partials, summed; the chunk slots' fill counts into LDS
-    int64_t sums[5] = {0, 0, 0, 0, 0};
+    int64_t sums[6] = {0, 0, 0, 0, 0, 0};
     for (int g = t; g < ng; g += CS) {
       const int64_t p = (int64_t)g * IG + c;
       sums[0] += MAD ? pp.sd[p] : pp.n[p];
@@ -1147,16 +1245,18 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
       sums[3] += pp.ceb[p];
       const int32_t cm = pp.cm[p];
       sums[4] += cm;
+      sums[5] += cm > SCAP ? 1 : 0;  // a slot that could not hold its chunk's interior
       segn[g] = cm;
     }
     int64_t u0 = 0, u1 = 0;
-    block_stats<5, false>(sums, u0, u1, L.red);  // its barriers publish segn
+    block_stats<6, false>(sums, u0, u1, L.red);  // its barriers publish segn
     const int64_t clo = sums[1], ceqa = sums[2], ceqb = sums[3], cmid = sums[4];
+    const bool full = sums[5] > 0;
     const int64_t qa = br.a[c], qb = br.b[c];
     const int64_t n = MAD ? out.n[c] : sums[0];
     // the interior cells: wave wv reads chunk slots wv, wv + CWV, ..., SU of
     // them (two cells per lane each) per round trip
-    const int64_t *colscr = scr + (int64_t)c * ng * RCH;
+    const int64_t *colscr = scr + (int64_t)c * ng * SCAP;
     auto vscr = [&](auto &&f) {
       for (int g0 = wv; g0 < ng; g0 += CWV * SU) {
         int64_t v0[SU], v1[SU];
@@ -1165,7 +1265,7 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
         for (int u = 0; u < SU; u++) {
           const int g = g0 + u * CWV;
           cn[u] = g < ng ? segn[g] : 0;
-          const int64_t *sp = colscr + (int64_t)g * RCH;
+          const int64_t *sp = colscr + (int64_t)g * SCAP;
           v0[u] = ln < cn[u] ? sp[ln] : 0;
           v1[u] = ln + 64 < cn[u] ? sp[ln + 64] : 0;
         }
@@ -1174,7 +1274,7 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
           if (ln < cn[u]) f(v0[u]);
           if (ln + 64 < cn[u]) f(v1[u]);
           if (cn[u] > 128) {
-            const int64_t *sp = colscr + (int64_t)(g0 + u * CWV) * RCH;
+            const int64_t *sp = colscr + (int64_t)(g0 + u * CWV) * SCAP;
             for (int e = ln + 128; e < cn[u]; e += 64) f(sp[e]);
           }
         }
@@ -1206,7 +1306,7 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
     const bool even = (n & 1) == 0;
     int64_t x1, x2;
     if (!MAD) {
-      if (!bracket_pick(vscr, clo, ceqa, cmid, ceqb, qa, qb, INT64_MAX, k, even, L, x1, x2)) {
+      if (full || !bracket_pick(vscr, clo, ceqa, cmid, ceqb, qa, qb, INT64_MAX, k, even, L, x1, x2)) {
         int64_t mn, mx;
         gather_column(T, R, IG, G, it, c, slot, L, mn, mx);
         uint64_t a1, a2;
@@ -1228,7 +1328,7 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
       }
     } else {
       const int64_t med2 = br.med2[c];
-      if (!bracket_pick(vscr, clo, ceqa, cmid, ceqb, qa, qb, INT64_MAX, k, even, L, x1, x2)) {
+      if (full || !bracket_pick(vscr, clo, ceqa, cmid, ceqb, qa, qb, INT64_MAX, k, even, L, x1, x2)) {
         int64_t mn, mx;
         gather_column(T, R, IG, G, it, c, slot, L, mn, mx);
         const uint64_t dlo = (uint64_t)(med2 - 2 * mn), dhi = (uint64_t)(2 * mx - med2);
@@ -1253,18 +1353,24 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
   }
 }
 
-// m(r,g) = (1/n_r) sum_{i < n_r} z(r,i,g) (ascending i) from the row-major
-// tensor, written [G][R]; a wave = SRW consecutive ranks x 64 regions (lane =
-// region), so each row read is contiguous and the column parameters are read
-// once per SRW ranks.  One launch adds the iterations [i_lo, i_hi): a launch
+// m(r,g) = (1/n_r) sum_{i < n_r} z(r,i,g) (ascending i) from the median
+// pass's 32-bit copy of the row-major tensor (the int64 cell where the copy
+// holds CSENT), written [G][R]; a wave = SRW consecutive ranks x 64 regions
+// (lane = region), so each row read is contiguous and the column parameters
+// are read once per SRW ranks.  One launch adds the iterations [i_lo, i_hi): a launch
 // with i_lo > 0 continues the running sums that the previous one left in m_t
 // (the same additions in the same order), and the launch that reaches I
 // divides by n_r.
 constexpr int SRW = 8;
 
-__global__ __launch_bounds__(256) void score_rows(const int64_t *__restrict__ T, int64_t R, int I, int G,
-                                                  const int32_t *it, int i_lo, int i_hi, ColSel cs,
-                                                  double *m_t) {
+template <bool S32>
+__global__ __launch_bounds__(256) void score_rows(const int64_t *__restrict__ T,
+                                                  const int32_t *__restrict__ cx,
+                                                  const int64_t *__restrict__ cxb, const int32_t *esc,
+                                                  int64_t R, int I, int G, const int32_t *it, int i_lo,
+                                                  int i_hi, ColSel cs, double *m_t) {
+  // both forms are launched and one applies (without the flag: the int64 form)
+  if (esc ? (*esc == 0) != S32 : S32) return;
   const int lane = threadIdx.x & 63;
   const int gbn = (G + 63) / 64;
   const int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1290,31 +1396,38 @@ __global__ __launch_bounds__(256) void score_rows(const int64_t *__restrict__ T,
   for (int q = 0; q < SRW; q++) acc[q] = (i_lo > 0 && gl && r0 + q < R) ? m_t[(int64_t)g * R + r0 + q] : 0.0;
   const int gg = gl ? g : 0;
   const int ie = nmax < i_hi ? nmax : i_hi;
-  const int64_t *base = T + r0 * IG + gg;
   // iteration i's cells and column parameters; those of i + 1 are loaded
-  // before i is scored
-  int64_t x[SRW], med2 = 0;
-  double zc = 0.0, zd = 1.0;
-  auto load = [&](int i) {
+  // before i is scored.  The cells come from the 32-bit copy (S32) unless
+  // some valid cell did not fit in it (then from the int64 tensor).
+  {
+    typedef typename RmCell<S32>::T Cell;
+    const Cell *base = S32 ? (const Cell *)(const void *)(cx + r0 * IG + gg)
+                           : (const Cell *)(const void *)(T + r0 * IG + gg);
+    Cell x[SRW];
+    int64_t med2 = 0, cb = 0;
+    double zc = 0.0, zd = 1.0;
+    auto load = [&](int i) {
 #pragma unroll
-    for (int q = 0; q < SRW; q++)
-      x[q] = i < ni[q] ? __builtin_nontemporal_load(base + q * IG + (int64_t)i * G) : 0;
-    const int64_t c = (int64_t)i * G + gg;
-    med2 = cs.med2[c];
-    zc = cs.zc[c];
-    zd = cs.zd[c];
-  };
-  if (i_lo < ie) load(i_lo);
-  for (int i = i_lo; i < ie; i++) {
-    int64_t xc[SRW];
+      for (int q = 0; q < SRW; q++)
+        x[q] = i < ni[q] ? __builtin_nontemporal_load(base + q * IG + (int64_t)i * G) : 0;
+      const int64_t c = (int64_t)i * G + gg;
+      med2 = cs.med2[c];
+      if (S32) cb = cxb[c];
+      zc = cs.zc[c];
+      zd = cs.zd[c];
+    };
+    if (i_lo < ie) load(i_lo);
+    for (int i = i_lo; i < ie; i++) {
+      Cell xc[SRW];
 #pragma unroll
-    for (int q = 0; q < SRW; q++) xc[q] = x[q];
-    const int64_t m2 = med2;
-    const double a = zc, d = zd;
-    if (i + 1 < ie) load(i + 1);
+      for (int q = 0; q < SRW; q++) xc[q] = x[q];
+      const int64_t m2 = med2, b = cb;
+      const double a = zc, d = zd;
+      if (i + 1 < ie) load(i + 1);
 #pragma unroll
-    for (int q = 0; q < SRW; q++)
-      if (i < ni[q]) acc[q] += ((double)(2 * xc[q] - m2) * a) / d;
+      for (int q = 0; q < SRW; q++)
+        if (i < ni[q]) acc[q] += ((double)(2 * (b + (int64_t)xc[q]) - m2) * a) / d;
+    }
   }
   if (gl) {
     const bool fin = i_hi >= I;
@@ -1948,10 +2061,12 @@ __global__ __launch_bounds__(256) void rank_max_f32(const double *z_t, int64_t R
 
 struct OWs {
   int64_t *Tt;      // [IG][Rp] column-major copy of the tensor (FULL, short columns or z-score)
-  int64_t *scr;     // row-major path: [IG][chunks][RCH] bracket interiors per column and chunk;
+  int64_t *scr;     // row-major path: [IG][chunks][SCAP] bracket interiors per column and chunk;
                     // column-major bracket path: [min(IG, SEL_GRID_MAX)][sel_cap(R)]
   int64_t *smp;     // row-major path: [IG][MS] column samples
   int64_t *slots;   // row-major path: [min(IG, SEL_GRID_MAX)][Rp] gathered columns
+  int32_t *cx;      // row-major path: [R][IG] the median pass's 32-bit copy of the tensor
+  int32_t *esc;     // row-major path: set when a valid cell did not fit in the copy
   int64_t *qa, *qb, *da, *db;  // row-major path: [IG] brackets
   RmPart rp;        // row-major path: [groups][IG] pass counts
   ColSel cs;
@@ -1980,7 +2095,9 @@ OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
   if (mode == TA_SCAN_FULL) {
     if (row_major_path(R, mode, kind)) {
       const size_t ng = (size_t)transpose_groups_of(R);
-      w.scr = (int64_t *)take(IG * ng * RCH * 8);
+      w.scr = (int64_t *)take(IG * ng * SCAP * 8);
+      w.cx = (int32_t *)take((size_t)R * IG * 4);
+      w.esc = (int32_t *)take(4);
       w.smp = (int64_t *)take(IG * MS * 8);
       w.slots = (int64_t *)take((size_t)std::min<size_t>(IG, SEL_GRID_MAX) * pad_ranks(R) * 8);
       w.qa = (int64_t *)take(IG * 8);
@@ -2024,16 +2141,23 @@ OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
 // row loads for two columns when the row length and c_lo are even).
 constexpr int RM_CPL_STATS = 1, RM_CPL_MAD = 2, RM_CPL_COUNT = 2;
 template <bool MAD, bool STATS>
-void launch_rm_pass(int ng, const OutArgs &a, int IG, int c_lo, int c_hi, RmBr br, int64_t *scr,
-                    RmPart rp, hipStream_t s) {
+void launch_rm_pass(int ng, const OutArgs &a, int IG, int c_lo, int c_hi, RmBr br, const OWs &w,
+                    hipStream_t s) {
   constexpr int CPL = STATS ? RM_CPL_STATS : (MAD ? RM_CPL_MAD : RM_CPL_COUNT);
   const dim3 grid((unsigned)((c_hi - c_lo + 256 * CPL - 1) / (256 * CPL)), (unsigned)ng);
-  if (CPL == 2 && (IG & 1) == 0 && (c_lo & 1) == 0)
-    hipLaunchKernelGGL((rm_pass<MAD, STATS, true, CPL>), grid, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it,
-                       c_lo, c_hi, br, scr, rp, a.stats);
-  else
-    hipLaunchKernelGGL((rm_pass<MAD, STATS, false, CPL>), grid, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it,
-                       c_lo, c_hi, br, scr, rp, a.stats);
+  const bool vec = CPL == 2 && (IG & 1) == 0 && (c_lo & 1) == 0;
+  // the MAD pass in both forms (32-bit copy, int64 tensor): one returns at once
+  for (int f = 0; f < (MAD ? 2 : 1); f++) {
+    const bool s32 = MAD && f == 0;
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, c_lo, c_hi, br, w.scr, w.rp,
+                         a.stats, w.cx, (const int64_t *)w.qa, w.esc);
+    };
+    if (vec && s32) go(rm_pass<MAD, STATS, true, CPL, MAD>);
+    else if (vec) go(rm_pass<MAD, STATS, true, CPL, false>);
+    else if (s32) go(rm_pass<MAD, STATS, false, CPL, MAD>);
+    else go(rm_pass<MAD, STATS, false, CPL, false>);
+  }
 }
 
 // The row-major robust FULL scan.  Serially: sample, brackets, median pass,
@@ -2076,16 +2200,22 @@ hipError_t scan_row_major(const OutArgs &a, const OWs &w, int IG, hipStream_t s)
   };
   auto med_pass = [&](int lo, int hi) {
     if (a.stats.rc > 0)
-      launch_rm_pass<false, true>(ng, a, IG, lo, hi, bm, w.scr, w.rp, s);
+      launch_rm_pass<false, true>(ng, a, IG, lo, hi, bm, w, s);
     else
-      launch_rm_pass<false, false>(ng, a, IG, lo, hi, bm, w.scr, w.rp, s);
+      launch_rm_pass<false, false>(ng, a, IG, lo, hi, bm, w, s);
   };
   const int64_t waves = ((a.R + SRW - 1) / SRW) * ((a.G + 63) / 64);
   const dim3 sgrid((unsigned)((waves + 3) / 4));
   auto score = [&](int i_lo, int i_hi) {
-    hipLaunchKernelGGL(score_rows, sgrid, dim3(256), 0, s, a.T, a.R, a.I, a.G, a.it, i_lo, i_hi, w.cs, w.m_t);
+    hipLaunchKernelGGL(score_rows<true>, sgrid, dim3(256), 0, s, a.T, (const int32_t *)w.cx,
+                       (const int64_t *)w.qa, (const int32_t *)w.esc, a.R, a.I, a.G, a.it, i_lo, i_hi, w.cs,
+                       w.m_t);
+    hipLaunchKernelGGL(score_rows<false>, sgrid, dim3(256), 0, s, a.T, (const int32_t *)w.cx,
+                       (const int64_t *)w.qa, (const int32_t *)w.esc, a.R, a.I, a.G, a.it, i_lo, i_hi, w.cs,
+                       w.m_t);
   };
-  hipLaunchKernelGGL(rm_sample, dim3(MS / TT, strips), dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, w.smp);
+  hipLaunchKernelGGL(rm_sample, dim3(MS / TT, strips), dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, w.smp,
+                     w.esc);
   // the split: even column counts on both sides when the rows are even, so
   // both halves keep the 16-byte loads
   int ih = a.I / 2;
@@ -2095,7 +2225,7 @@ hipError_t scan_row_major(const OutArgs &a, const OWs &w, int IG, hipStream_t s)
     med_pass(0, IG);
     if (a.stats.rc > 0 && a.stats_ready) (void)hipEventRecord(a.stats_ready, s);
     select(false, 0, IG, s);
-    launch_rm_pass<true, false>(ng, a, IG, 0, IG, bd, w.scr, w.rp, s);
+    launch_rm_pass<true, false>(ng, a, IG, 0, IG, bd, w, s);
     select(true, 0, IG, s);
     score(0, a.I);
     return hipGetLastError();
@@ -2129,13 +2259,13 @@ hipError_t scan_row_major(const OutArgs &a, const OWs &w, int IG, hipStream_t s)
   select(false, cm, IG, q);  // beside the MAD pass of A
   rec(5, q);
   wait(s, 3);
-  launch_rm_pass<true, false>(ng, a, IG, 0, cm, bd, w.scr, w.rp, s);
+  launch_rm_pass<true, false>(ng, a, IG, 0, cm, bd, w, s);
   rec(6, s);
   wait(q, 6);
   select(true, 0, cm, q);  // beside the MAD pass of B
   rec(7, q);
   wait(s, 5);
-  launch_rm_pass<true, false>(ng, a, IG, cm, IG, bd, w.scr, w.rp, s);
+  launch_rm_pass<true, false>(ng, a, IG, cm, IG, bd, w, s);
   rec(8, s);
   wait(q, 8);
   select(true, cm, IG, q);  // beside score A
@@ -2199,7 +2329,8 @@ hipError_t launch_outliers(const OutArgs &a, void *ws, size_t ws_bytes, hipStrea
         if (e != hipSuccess) return e;
       } else {
         const int64_t waves = ((a.R + SRW - 1) / SRW) * ((a.G + 63) / 64);
-        hipLaunchKernelGGL(score_rows, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a.T, a.R, a.I,
+        hipLaunchKernelGGL(score_rows<false>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a.T,
+                           (const int32_t *)w.cx, (const int64_t *)w.qa, (const int32_t *)nullptr, a.R, a.I,
                            a.G, a.it, 0, a.I, w.cs, w.m_t);
       }
       launch_sel_regions<true, true>((const void *)w.m_t, a.R, a.G, a.it, a.I, w.z_t, a.region_score,

@@ -394,6 +394,48 @@ def test_outliers_region_bracket_fallbacks(ta, h, oracle, case):
         assert np.array_equal(go["rank_flag"], flag), mode
 
 
+@pytest.mark.parametrize("wide", [False, True])
+def test_outliers_column_slot_overflow(ta, h, oracle, wide):
+    """The robust scan over long row-major columns keeps at most 256 bracket
+    cells per chunk of 1,024 ranks and selects over a gathered column when a
+    chunk holds more.  Built against the 2,048 sample ranks of a column (pairs
+    of consecutive ranks, evenly spaced): the sample spread over [0, 1e6) and
+    the other ranks packed inside its central bracket (region 0: the median's
+    interior overflows), or packed at the sample's typical deviation on both
+    sides of the middle (region 1: the MAD's interior overflows).  Region 2
+    holds plain cells; with `wide` they span 2^40, so they do not fit the
+    scan's 32-bit copy and the later passes read the int64 tensor.  Against the
+    oracle, both scan modes."""
+    import torch
+    R, I, G = 40000, 2, 3
+    print(f"[parity] outliers column slot overflow wide={wide}", flush=True)
+    rng = np.random.default_rng(40 + int(wide))
+    Rp = (R + 63) // 64 * 64
+    j = np.arange(2048, dtype=np.int64)
+    samp = (((j >> 1) * Rp // 1024) & ~1) + (j & 1)      # the column sample's ranks
+    is_s = np.zeros(R, bool)
+    is_s[samp[samp < R]] = True
+    T = np.empty((R, I, G), np.int64)
+    for i in range(I):
+        spread = rng.integers(0, 10**6, R)
+        band = 499_000 + rng.integers(0, 2_000, R)
+        T[:, i, 0] = np.where(is_s, spread, band)
+        two = np.where(rng.random(R) < 0.5, 250_000, 750_000) + rng.integers(-10_000, 10_000, R)
+        T[:, i, 1] = np.where(is_s, spread, two)
+        T[:, i, 2] = rng.integers(0, 1 << 40, R) if wide else rng.integers(0, 10**7, R)
+    it = np.full(R, I, np.int32)
+    it[rng.choice(R, 3000, replace=False)] = 1
+    dT, dit = torch.from_numpy(T).cuda(), torch.from_numpy(it).cuda()
+    for mode in (0, 1):
+        o = h.outliers(dT, dit, mode=mode, kind=0, tau=3.5, region=True)
+        st, score, flag, nf, reg = oracle.outliers(T, it, mode=mode, kind=0, tau=3.5)
+        assert st == 0
+        go = {k: v.cpu().numpy() for k, v in o.items()}
+        assert np.array_equal(go["region_score"], reg), mode
+        assert np.array_equal(go["rank_score"], score), mode
+        assert np.array_equal(go["rank_flag"], flag), mode
+
+
 def test_topology_parity(ta, h, oracle):
     import torch
     rng = np.random.default_rng(3)
