@@ -867,7 +867,7 @@ __host__ __device__ inline int64_t sample_rank(int j, int64_t Rp) {
 __global__ __launch_bounds__(256) void rm_sample(const int64_t *__restrict__ T, int64_t R, int IG,
                                                  int G, const int32_t *it, int64_t *__restrict__ smp,
                                                  int32_t *esc) {
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *esc = 0;  // before the median pass
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) esc[threadIdx.x] = 0;  // before the median pass
   __shared__ int64_t tile[TT][TT + 1];
   const int c0 = blockIdx.y * TT;
   const int j0 = blockIdx.x * TT;
@@ -962,17 +962,68 @@ constexpr int RQ = 6;          // interior cells buffered per column
 constexpr int SCAP = 256;
 
 // The 32-bit copy of the tensor that the median pass writes for the later
-// passes: a cell as its offset from the column's median-bracket low end when
-// that fits in (INT32_MIN, INT32_MAX], else CSENT (the reader then takes the
-// int64 cell).
+// passes: a cell as its offset v from the column's median-bracket low end
+// when |v| < 2^29, else CSENT, and then the half's flag is set and the later
+// passes of that half read the int64 tensor.  The range leaves the MAD pass
+// 32-bit keys: with |med2 - 2 * base| < 2^30 (checked when the median is
+// known), |2x - med2| = |2v - (med2 - 2 * base)| < 2^31 - 2.
 constexpr int32_t CSENT = INT32_MIN;
+constexpr int64_t CX_LIM = (int64_t(1) << 29) - 1;  // largest |v| kept
+constexpr int64_t CK_LIM = (int64_t(1) << 30) - 1;  // largest |med2 - 2 * base|
 struct CxRange {
   int64_t lo, hi;  // the cells that fit
   __device__ explicit CxRange(int64_t base)
-      : lo(base > INT64_MIN + 0x7fffffff ? base - 0x7fffffff : INT64_MIN),
-        hi(base < INT64_MAX - 0x7fffffff ? base + 0x7fffffff : INT64_MAX) {}
+      : lo(base > INT64_MIN + CX_LIM ? base - CX_LIM : INT64_MIN),
+        hi(base < INT64_MAX - CX_LIM ? base + CX_LIM : INT64_MAX) {}
   __device__ int32_t put(int64_t x, int64_t base) const {
     return (x >= lo && x <= hi) ? (int32_t)(x - base) : CSENT;
+  }
+};
+
+// The MAD pass's counts on the 32-bit copy (the half's flag clear): key =
+// |2v - K| with K = med2 - 2 * base, in [0, 2^31 - 3]; the bracket ends are
+// clamped to [-1, INT32_MAX], which changes no comparison with such keys.
+// Same counts, sums and interior cells as RmCol<true, false>.
+struct RmMad32 {
+  int32_t K = 0, a = 0, b = 0;
+  bool bneq = false;
+  int32_t n = 0, cl = 0, cea = 0, ceb = 0, cm = 0, qn = 0;
+  int64_t sd = 0;
+  uint32_t q[RQ];
+  __device__ void set(int64_t a64, int64_t b64, int64_t k64) {
+    auto clamp = [](int64_t x) { return (int32_t)(x < -1 ? -1 : (x > INT32_MAX ? INT32_MAX : x)); };
+    a = clamp(a64);
+    b = clamp(b64);
+    bneq = a64 != b64;
+    K = (int32_t)k64;
+  }
+  __device__ __forceinline__ void cell(int32_t v, bool ok) {
+    const int32_t d = 2 * v - K;
+    const int32_t key = d < 0 ? -d : d;
+    sd += ok ? key : 0;
+    cl += (ok && key < a) ? 1 : 0;
+    cea += (ok && key == a) ? 1 : 0;
+    ceb += (ok && key == b && bneq) ? 1 : 0;
+    const bool in = ok && key > a && key < b;
+#pragma unroll
+    for (int e = RQ - 1; e > 0; e--) q[e] = in ? q[e - 1] : q[e];
+    q[0] = in ? (uint32_t)key : q[0];
+    qn += in ? 1 : 0;
+  }
+  __device__ __forceinline__ void drain(int64_t *__restrict__ slot) {
+#pragma unroll
+    for (int e = 0; e < RQ; e++)
+      if (e < qn && cm + e < SCAP) slot[cm + e] = (int64_t)q[e];
+    cm += qn;
+    qn = 0;
+  }
+  __device__ __forceinline__ void flush(int64_t p, RmPart pp, ColPartials, int64_t *__restrict__ slot) {
+    drain(slot);
+    pp.cl[p] = cl;
+    pp.cea[p] = cea;
+    pp.ceb[p] = ceb;
+    pp.cm[p] = cm;
+    pp.sd[p] = sd;
   }
 };
 
@@ -1060,6 +1111,14 @@ template <bool B>
 struct Flag {
   static constexpr bool value = B;
 };
+template <bool MAD, bool STATS, bool S32>
+struct RmColOf {
+  typedef RmCol<MAD, STATS> T;
+};
+template <>
+struct RmColOf<true, false, true> {
+  typedef RmMad32 T;
+};
 template <bool S32>
 struct RmCell {
   typedef long long T;
@@ -1089,19 +1148,30 @@ __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, in
                                                int32_t *__restrict__ cx, const int64_t *__restrict__ cbase,
                                                int32_t *esc) {
   static_assert(MAD || !S32, "the median pass reads the int64 tensor");
+  static_assert(!(S32 && STATS), "the MAD pass takes no imbalance partials");
   if (MAD && (*esc == 0) != S32) return;
   const int ca = c_lo + ((int)blockIdx.x * 256 + (int)threadIdx.x) * CPL;
   if (ca >= c_hi) return;
   const int64_t ng = gridDim.y, ch = blockIdx.y;
   const bool two = CPL == 2 && ca + 1 < c_hi;
   const int ia = ca / G, ib = (ca + 1) / G;
-  RmCol<MAD, STATS> c0, c1;
-  c0.a = br.a[ca];
-  c0.b = br.b[ca];
-  c0.m = MAD ? br.med2[ca] : 0;
-  c1.a = two ? br.a[ca + 1] : INT64_MAX;
-  c1.b = two ? br.b[ca + 1] : INT64_MIN;
-  c1.m = (MAD && two) ? br.med2[ca + 1] : 0;
+  typename RmColOf<MAD, STATS, S32>::T c0, c1;
+  if constexpr (MAD && S32) {
+    // K = med2 - 2 * base (in range: the half's flag is clear)
+    auto kof = [&](int c) { return (int64_t)((uint64_t)br.med2[c] - 2 * (uint64_t)cbase[c]); };
+    c0.set(br.a[ca], br.b[ca], kof(ca));
+    if (two)
+      c1.set(br.a[ca + 1], br.b[ca + 1], kof(ca + 1));
+    else
+      c1.set(INT64_MAX, INT64_MIN, 0);
+  } else {
+    c0.a = br.a[ca];
+    c0.b = br.b[ca];
+    c0.m = MAD ? br.med2[ca] : 0;
+    c1.a = two ? br.a[ca + 1] : INT64_MAX;
+    c1.b = two ? br.b[ca + 1] : INT64_MIN;
+    c1.m = (MAD && two) ? br.med2[ca + 1] : 0;
+  }
   int64_t *slot0 = scr + ((int64_t)ca * ng + ch) * SCAP;
   int64_t *slot1 = scr + ((int64_t)(ca + 1) * ng + ch) * SCAP;
   const int64_t rb = ch * RCH, re = rb + RCH < R ? rb + RCH : R, last = re - 1;
@@ -1140,11 +1210,8 @@ __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, in
       for (int u = 0; u < RPU; u++) {
         const bool rv = r0 + u < re;
         const bool ok0 = rv && ia < nit[u], ok1 = rv && two && ib < nit[u];
-        int64_t x0, x1;
-        if constexpr (S32) {
-          x0 = b0 + (int64_t)v[u].x;
-          x1 = b1 + (int64_t)v[u].y;
-        } else {
+        int64_t x0 = 0, x1 = 0;
+        if constexpr (!S32) {
           x0 = (int64_t)v[u].x;
           x1 = (int64_t)v[u].y;
         }
@@ -1167,8 +1234,13 @@ __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, in
             }
           }
         }
-        c0.cell(x0, ok0);
-        c1.cell(x1, ok1);
+        if constexpr (S32) {
+          c0.cell(v[u].x, ok0);
+          c1.cell(v[u].y, ok1);
+        } else {
+          c0.cell(x0, ok0);
+          c1.cell(x1, ok1);
+        }
         v[u] = load_row(r0 + u + RPU);
         // a row adds at most one cell per column: drain the whole wave as
         // soon as one buffer is full
@@ -1227,7 +1299,7 @@ template <bool MAD>
 __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
     const int64_t *__restrict__ T, int64_t R, int IG, int G, const int32_t *it,
     const int64_t *__restrict__ smp, int ng, int c_lo, int c_hi, RmPart pp, RmBr br,
-    const int64_t *__restrict__ scr, int64_t *__restrict__ slots, RmOut ro, ColSel out) {
+    const int64_t *__restrict__ scr, int64_t *__restrict__ slots, RmOut ro, ColSel out, int32_t *esc) {
   __shared__ ColSelLds L;
   __shared__ int32_t segn[SEG_MAX];
   const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
@@ -1325,6 +1397,10 @@ __global__ __launch_bounds__(CS, SEL_WGS_PER_CU) void rm_select(
         out.n[c] = n;
         ro.da[c] = da;
         ro.db[c] = db;
+        // the MAD pass's 32-bit keys need |med2 - 2 * base| <= CK_LIM (base:
+        // the copy's base, the median bracket's low end)
+        const i128 k = (i128)med2 - 2 * (i128)qa;
+        if (k > CK_LIM || k < -CK_LIM) *esc = 1;
       }
     } else {
       const int64_t med2 = br.med2[c];
@@ -2066,7 +2142,7 @@ struct OWs {
   int64_t *smp;     // row-major path: [IG][MS] column samples
   int64_t *slots;   // row-major path: [min(IG, SEL_GRID_MAX)][Rp] gathered columns
   int32_t *cx;      // row-major path: [R][IG] the median pass's 32-bit copy of the tensor
-  int32_t *esc;     // row-major path: set when a valid cell did not fit in the copy
+  int32_t *esc;     // row-major path: [2] per column half, set when the copy does not serve
   int64_t *qa, *qb, *da, *db;  // row-major path: [IG] brackets
   RmPart rp;        // row-major path: [groups][IG] pass counts
   ColSel cs;
@@ -2097,7 +2173,7 @@ OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
       const size_t ng = (size_t)transpose_groups_of(R);
       w.scr = (int64_t *)take(IG * ng * SCAP * 8);
       w.cx = (int32_t *)take((size_t)R * IG * 4);
-      w.esc = (int32_t *)take(4);
+      w.esc = (int32_t *)take(8);
       w.smp = (int64_t *)take(IG * MS * 8);
       w.slots = (int64_t *)take((size_t)std::min<size_t>(IG, SEL_GRID_MAX) * pad_ranks(R) * 8);
       w.qa = (int64_t *)take(IG * 8);
@@ -2142,7 +2218,7 @@ OWs carve(void *ws, int64_t R, int I, int G, int mode, int kind, size_t *used) {
 constexpr int RM_CPL_STATS = 1, RM_CPL_MAD = 2, RM_CPL_COUNT = 2;
 template <bool MAD, bool STATS>
 void launch_rm_pass(int ng, const OutArgs &a, int IG, int c_lo, int c_hi, RmBr br, const OWs &w,
-                    hipStream_t s) {
+                    int h, hipStream_t s) {
   constexpr int CPL = STATS ? RM_CPL_STATS : (MAD ? RM_CPL_MAD : RM_CPL_COUNT);
   const dim3 grid((unsigned)((c_hi - c_lo + 256 * CPL - 1) / (256 * CPL)), (unsigned)ng);
   const bool vec = CPL == 2 && (IG & 1) == 0 && (c_lo & 1) == 0;
@@ -2151,7 +2227,7 @@ void launch_rm_pass(int ng, const OutArgs &a, int IG, int c_lo, int c_hi, RmBr b
     const bool s32 = MAD && f == 0;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, c_lo, c_hi, br, w.scr, w.rp,
-                         a.stats, w.cx, (const int64_t *)w.qa, w.esc);
+                         a.stats, w.cx, (const int64_t *)w.qa, w.esc + h);
     };
     if (vec && s32) go(rm_pass<MAD, STATS, true, CPL, MAD>);
     else if (vec) go(rm_pass<MAD, STATS, true, CPL, false>);
@@ -2187,32 +2263,33 @@ hipError_t scan_row_major(const OutArgs &a, const OWs &w, int IG, hipStream_t s)
     hipLaunchKernelGGL(rm_brackets, dim3((unsigned)(hi - lo)), dim3(CS), 0, q, (const int64_t *)w.smp, lo,
                        w.qa, w.qb);
   };
-  auto select = [&](bool mad, int lo, int hi, hipStream_t q) {
+  // h: the column half (0 or 1) whose copy flag a kernel sets or reads
+  auto select = [&](bool mad, int lo, int hi, int h, hipStream_t q) {
     const int grid = std::min(hi - lo, sel_max);
     if (mad)
       hipLaunchKernelGGL(rm_select<true>, dim3(grid), dim3(CS), 0, q, a.T, a.R, IG, a.G, a.it,
                          (const int64_t *)w.smp, ng, lo, hi, w.rp, bd, (const int64_t *)w.scr, w.slots, ro,
-                         w.cs);
+                         w.cs, w.esc + h);
     else
       hipLaunchKernelGGL(rm_select<false>, dim3(grid), dim3(CS), 0, q, a.T, a.R, IG, a.G, a.it,
                          (const int64_t *)w.smp, ng, lo, hi, w.rp, bm, (const int64_t *)w.scr, w.slots, ro,
-                         w.cs);
+                         w.cs, w.esc + h);
   };
-  auto med_pass = [&](int lo, int hi) {
+  auto med_pass = [&](int lo, int hi, int h) {
     if (a.stats.rc > 0)
-      launch_rm_pass<false, true>(ng, a, IG, lo, hi, bm, w, s);
+      launch_rm_pass<false, true>(ng, a, IG, lo, hi, bm, w, h, s);
     else
-      launch_rm_pass<false, false>(ng, a, IG, lo, hi, bm, w, s);
+      launch_rm_pass<false, false>(ng, a, IG, lo, hi, bm, w, h, s);
   };
   const int64_t waves = ((a.R + SRW - 1) / SRW) * ((a.G + 63) / 64);
   const dim3 sgrid((unsigned)((waves + 3) / 4));
-  auto score = [&](int i_lo, int i_hi) {
+  auto score = [&](int i_lo, int i_hi, int h) {
     hipLaunchKernelGGL(score_rows<true>, sgrid, dim3(256), 0, s, a.T, (const int32_t *)w.cx,
-                       (const int64_t *)w.qa, (const int32_t *)w.esc, a.R, a.I, a.G, a.it, i_lo, i_hi, w.cs,
-                       w.m_t);
+                       (const int64_t *)w.qa, (const int32_t *)(w.esc + h), a.R, a.I, a.G, a.it, i_lo, i_hi,
+                       w.cs, w.m_t);
     hipLaunchKernelGGL(score_rows<false>, sgrid, dim3(256), 0, s, a.T, (const int32_t *)w.cx,
-                       (const int64_t *)w.qa, (const int32_t *)w.esc, a.R, a.I, a.G, a.it, i_lo, i_hi, w.cs,
-                       w.m_t);
+                       (const int64_t *)w.qa, (const int32_t *)(w.esc + h), a.R, a.I, a.G, a.it, i_lo, i_hi,
+                       w.cs, w.m_t);
   };
   hipLaunchKernelGGL(rm_sample, dim3(MS / TT, strips), dim3(256), 0, s, a.T, a.R, IG, a.G, a.it, w.smp,
                      w.esc);
@@ -2222,12 +2299,12 @@ hipError_t scan_row_major(const OutArgs &a, const OWs &w, int IG, hipStream_t s)
   if ((IG & 1) == 0 && ((ih * a.G) & 1)) ih--;
   if (!a.side || ih <= 0) {
     brackets(0, IG, s);
-    med_pass(0, IG);
+    med_pass(0, IG, 0);
     if (a.stats.rc > 0 && a.stats_ready) (void)hipEventRecord(a.stats_ready, s);
-    select(false, 0, IG, s);
-    launch_rm_pass<true, false>(ng, a, IG, 0, IG, bd, w, s);
-    select(true, 0, IG, s);
-    score(0, a.I);
+    select(false, 0, IG, 0, s);
+    launch_rm_pass<true, false>(ng, a, IG, 0, IG, bd, w, 0, s);
+    select(true, 0, IG, 0, s);
+    score(0, a.I, 0);
     return hipGetLastError();
   }
   const int cm = ih * a.G;
@@ -2246,34 +2323,34 @@ hipError_t scan_row_major(const OutArgs &a, const OWs &w, int IG, hipStream_t s)
   if (e != hipSuccess) return e;
   brackets(cm, IG, q);  // beside the median pass of A
   rec(1, q);
-  med_pass(0, cm);
+  med_pass(0, cm, 0);
   rec(2, s);
   wait(q, 2);
-  select(false, 0, cm, q);  // beside the median pass of B
+  select(false, 0, cm, 0, q);  // beside the median pass of B
   rec(3, q);
   wait(s, 1);
-  med_pass(cm, IG);
+  med_pass(cm, IG, 1);
   if (a.stats.rc > 0 && a.stats_ready) rec(-1, s);
   rec(4, s);
   wait(q, 4);
-  select(false, cm, IG, q);  // beside the MAD pass of A
+  select(false, cm, IG, 1, q);  // beside the MAD pass of A
   rec(5, q);
   wait(s, 3);
-  launch_rm_pass<true, false>(ng, a, IG, 0, cm, bd, w, s);
+  launch_rm_pass<true, false>(ng, a, IG, 0, cm, bd, w, 0, s);
   rec(6, s);
   wait(q, 6);
-  select(true, 0, cm, q);  // beside the MAD pass of B
+  select(true, 0, cm, 0, q);  // beside the MAD pass of B
   rec(7, q);
   wait(s, 5);
-  launch_rm_pass<true, false>(ng, a, IG, cm, IG, bd, w, s);
+  launch_rm_pass<true, false>(ng, a, IG, cm, IG, bd, w, 1, s);
   rec(8, s);
   wait(q, 8);
-  select(true, cm, IG, q);  // beside score A
+  select(true, cm, IG, 1, q);  // beside score A
   rec(9, q);
   wait(s, 7);
-  score(0, ih);
+  score(0, ih, 0);
   wait(s, 9);  // joins the side stream
-  score(ih, a.I);
+  score(ih, a.I, 1);
   return e != hipSuccess ? e : hipGetLastError();
 }
 
