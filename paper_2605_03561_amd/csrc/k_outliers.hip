@@ -1107,10 +1107,6 @@ template <>
 struct RmRow<true> {
   typedef v2i T;  // two cells of the 32-bit copy
 };
-template <bool B>
-struct Flag {
-  static constexpr bool value = B;
-};
 template <bool MAD, bool STATS, bool S32>
 struct RmColOf {
   typedef RmCol<MAD, STATS> T;
@@ -1135,12 +1131,13 @@ struct RmCell<true> {
 // interior of each (chunk, column) goes to its own slot of SCAP cells (no
 // atomics; cells past SCAP are counted, not stored).  The median pass also
 // writes the 32-bit copy of every cell it reads (cx, offsets from its bracket's
-// low end) and sets *esc when a valid cell did not fit; the MAD pass then reads
-// the copy (S32, half the bytes), or the int64 tensor when *esc is set: both
-// forms are launched and the one that does not apply returns at once (one
-// loop per kernel, so no load sits in a branch inside it).  No LDS and no
-// barriers.  Rows past the chunk's end load its last row (in bounds) and are
-// not counted.
+// low end) and sets its column half's flag *esc when a valid cell did not fit
+// (the median selection sets it too when a column's MAD keys would not fit 32
+// bits); the MAD pass then reads the copy with 32-bit keys (S32, half the
+// bytes), or the int64 tensor when *esc is set: both forms are launched and
+// the one that does not apply returns at once (one loop per kernel, so no load
+// sits in a branch inside it).  No LDS and no barriers.  Rows past the chunk's
+// end load its last row (in bounds) and are not counted.
 template <bool MAD, bool STATS, bool VEC, int CPL, bool S32>
 __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, int64_t R, int IG, int G,
                                                const int32_t *it, int c_lo, int c_hi, RmBr br,
@@ -1176,9 +1173,10 @@ __global__ __launch_bounds__(256) void rm_pass(const int64_t *__restrict__ T, in
   int64_t *slot1 = scr + ((int64_t)(ca + 1) * ng + ch) * SCAP;
   const int64_t rb = ch * RCH, re = rb + RCH < R ? rb + RCH : R, last = re - 1;
   const int cb = two ? ca + 1 : ca;
-  // the copy's base per column (column cb is column ca again without a second)
-  const int64_t b0 = MAD ? cbase[ca] : c0.a;
-  const int64_t b1 = MAD ? cbase[cb] : (two ? c1.a : c0.a);
+  // the median pass: the copy's base per column (column cb is column ca again
+  // without a second)
+  const int64_t b0 = MAD ? 0 : (int64_t)c0.a;
+  const int64_t b1 = MAD ? 0 : (two ? (int64_t)c1.a : (int64_t)c0.a);
   bool escaped = false;
   {
     typedef typename RmRow<S32>::T Row;
