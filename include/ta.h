@@ -224,10 +224,11 @@ ta_status ta_imbalance_noalloc(ta_handle h, const int64_t *tensor, int64_t n_ran
  * Cell values must lie in (-2^61, 2^61); n_iters * n_regions <= 4,194,240
  * (TA_ERR_SIZE_OVERFLOW otherwise).  The FULL scan's workspace is about as
  * large as the tensor: for the robust kind over columns of at least 32,768
- * padded ranks it holds a slot of 1,024 cells per column and chunk of 1,024
- * ranks for the bracket interiors (plus the column samples and one gathered
- * column per selection workgroup); otherwise a column-major copy of the
- * tensor. */
+ * padded ranks it holds a 32-bit copy of the tensor (half its size) and a
+ * slot of 256 cells per column and chunk of 1,024 ranks for the bracket
+ * interiors (a quarter of the tensor), plus the column samples and one
+ * gathered column per selection workgroup; otherwise a column-major copy of
+ * the tensor. */
 enum { TA_SCAN_FULL = 0, TA_SCAN_TOTALS = 1 };
 enum { TA_SCORE_MAD = 0, TA_SCORE_Z = 1 };
 ta_status ta_outliers(ta_handle h, const int64_t *tensor, int64_t n_ranks, int32_t n_iters,
